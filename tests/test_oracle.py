@@ -1,0 +1,426 @@
+"""Pins for the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks a closed form, an
+exact integral, an invariant, a textbook special case, a value printed in the
+paper (Listing 1, section 3.5) or a brute-force/independent computation, chosen
+so that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.assembly import MaskedOperator, pcg, jacobi_diagonal, direct_solve
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ GLL
+
+@pytest.mark.parametrize("Q", [3, 4, 6, 8, 10, 12])
+def test_gll_exactness_degree(Q):
+    """GLL with Q points integrates x^k exactly for k <= 2Q-3 and not 2Q-2."""
+    x, w = oracle.gll(Q)
+    assert abs(w.sum() - 2.0) < 1e-14
+    for k in range(0, 2 * Q - 2):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(w @ x ** k - exact) < 1e-13, k
+    k = 2 * Q - 2
+    assert abs(w @ x ** k - 2.0 / (k + 1)) > 1e-7
+
+
+def test_gll_textbook_small_cases():
+    """Closed forms: Q=3 -> (-1,0,1), (1/3,4/3,1/3); Q=4 -> +-1, +-1/sqrt(5),
+    weights 1/6, 5/6."""
+    x, w = oracle.gll(3)
+    np.testing.assert_allclose(x, [-1, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    x, w = oracle.gll(4)
+    s = 1 / math.sqrt(5)
+    np.testing.assert_allclose(x, [-1, -s, s, 1], atol=1e-15)
+    np.testing.assert_allclose(w, [1 / 6, 5 / 6, 5 / 6, 1 / 6], atol=1e-15)
+
+
+@pytest.mark.parametrize("Q", [5, 8, 11])
+def test_gll_symmetry(Q):
+    x, w = oracle.gll(Q)
+    np.testing.assert_allclose(x, -x[::-1], atol=1e-15)
+    np.testing.assert_allclose(w, w[::-1], atol=1e-15)
+    assert np.all(np.diff(x) > 0)
+
+
+# ---------------------------------------------------------- modified basis
+
+@pytest.mark.parametrize("P", [1, 2, 4, 6, 8, 10])
+def test_basis_partition_and_bubbles(P):
+    """phi_0 + phi_P = 1; bubbles vanish at both ends (section 2.1 display)."""
+    x = np.linspace(-1, 1, 37)
+    B, _ = oracle.modified_basis(P, x)
+    np.testing.assert_allclose(B[:, 0] + B[:, P], 1.0, atol=1e-15)
+    Bend, _ = oracle.modified_basis(P, np.array([-1.0, 1.0]))
+    np.testing.assert_allclose(Bend[:, 1:P], 0.0, atol=1e-15)
+    np.testing.assert_allclose(Bend[0, [0, P]], [1, 0], atol=1e-15)
+    np.testing.assert_allclose(Bend[1, [0, P]], [0, 1], atol=1e-15)
+
+
+def test_basis_low_bubbles_closed_form():
+    """P^{1,1}_0 = 1 and P^{1,1}_1(x) = 2x give phi_1 = (1-x^2)/4 and
+    phi_2 = (1-x^2) x / 2 at P >= 3."""
+    x = np.linspace(-1, 1, 11)
+    B, DB = oracle.modified_basis(4, x)
+    np.testing.assert_allclose(B[:, 1], (1 - x * x) / 4, atol=1e-15)
+    np.testing.assert_allclose(B[:, 2], (1 - x * x) * x / 2, atol=1e-15)
+    np.testing.assert_allclose(DB[:, 1], -x / 2, atol=1e-15)
+    np.testing.assert_allclose(DB[:, 2], (1 - 3 * x * x) / 2, atol=1e-14)
+
+
+@pytest.mark.parametrize("P", [2, 4, 6, 8, 10])
+def test_basis_derivative_against_finite_differences(P):
+    x = np.linspace(-0.97, 0.97, 23)
+    h = 1e-6
+    _, DB = oracle.modified_basis(P, x)
+    Bp, _ = oracle.modified_basis(P, x + h)
+    Bm, _ = oracle.modified_basis(P, x - h)
+    np.testing.assert_allclose(DB, (Bp - Bm) / (2 * h), atol=1e-7)
+
+
+@pytest.mark.parametrize("P", [2, 4, 6, 8, 10])
+def test_basis_derivative_equals_collocation(P):
+    """phi_p has degree <= P <= Q-1, so the GLL collocation derivative of its
+    point values equals its analytic derivative."""
+    x, _ = oracle.gll(P + 2)
+    B, DB = oracle.modified_basis(P, x)
+    D = oracle.lagrange_derivative(x)
+    np.testing.assert_allclose(D @ B, DB, atol=1e-12)
+
+
+@pytest.mark.parametrize("P", [2, 4, 6, 8, 10])
+def test_1d_stiffness_closed_form(P):
+    """phi_p' = -(p/2) L_p for bubbles (L_p Legendre), which fixes the Jacobi
+    normalisation: S1 = [[1/2, ..., -1/2], diag(p^2/(2(2p+1))), ...]."""
+    x, w = oracle.gll(P + 2)
+    _, DB = oracle.modified_basis(P, x)
+    S1 = DB.T @ (w[:, None] * DB)
+    ref = np.zeros((P + 1, P + 1))
+    ref[0, 0] = ref[P, P] = 0.5
+    ref[0, P] = ref[P, 0] = -0.5
+    for p in range(1, P):
+        ref[p, p] = p * p / (2.0 * (2 * p + 1))
+    np.testing.assert_allclose(S1, ref, atol=5e-14)
+
+
+@pytest.mark.parametrize("P", [4, 6, 8])
+def test_1d_mass_sparsity_and_spd(P):
+    """Bubble-bubble entries vanish unless |p-q| in {0,2}; vertex-bubble
+    entries vanish unless the bubble is p in {1, 2}; M1 is SPD."""
+    x, w = oracle.gll(P + 2)
+    B, _ = oracle.modified_basis(P, x)
+    M1 = B.T @ (w[:, None] * B)
+    for p in range(1, P):
+        for q in range(1, P):
+            if abs(p - q) not in (0, 2):
+                assert abs(M1[p, q]) < 1e-15
+        for v in (0, P):
+            if p not in (1, 2):
+                assert abs(M1[v, p]) < 1e-15
+    assert np.linalg.eigvalsh(M1).min() > 1e-4
+
+
+# ------------------------------------------------- tensor-product elements
+
+def _affine_box_J(h, Q, dim):
+    nq = Q ** dim
+    J = np.zeros((1, dim, dim, nq))
+    for a in range(dim):
+        J[0, a, a, :] = h[a] / 2
+    return J
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_kronecker_identities_affine_box(P):
+    """Box of sides (hx, hy, hz) all distinct: M_e = (hx hy hz / 8) Mz(x)My(x)Mx and
+    L_e = detJ (4/hx^2 M(x)M(x)S1 + 4/hy^2 M(x)S1(x)M + 4/hz^2 S1(x)M(x)M),
+    direction 1 in the rightmost factor.  Catches swapped directions."""
+    Q = P + 2
+    h = np.array([0.3, 0.7, 1.9])
+    ops = oracle.ElementOps(3, P, Q, _affine_box_J(h, Q, 3), lam=0.0)
+    x, w = oracle.gll(Q)
+    B, DB = oracle.modified_basis(P, x)
+    M1 = B.T @ (w[:, None] * B)
+    S1 = DB.T @ (w[:, None] * DB)
+    det = h.prod() / 8
+    Mref = det * np.kron(M1, np.kron(M1, M1))
+    Lref = det * (4 / h[0] ** 2 * np.kron(M1, np.kron(M1, S1))
+                  + 4 / h[1] ** 2 * np.kron(M1, np.kron(S1, M1))
+                  + 4 / h[2] ** 2 * np.kron(S1, np.kron(M1, M1)))
+    np.testing.assert_allclose(ops.mass_matrix(0), Mref, atol=1e-15)
+    np.testing.assert_allclose(ops.laplacian_matrix(0), Lref, atol=1e-13)
+
+
+def test_2d_laplacian_independent_of_h():
+    """On an affine square the 2-D Laplacian S1(x)M1 + M1(x)S1 does not depend on h."""
+    P, Q = 4, 6
+    L = [oracle.ElementOps(2, P, Q, _affine_box_J([hh, hh], Q, 2), lam=0.0).laplacian_matrix(0)
+         for hh in (0.125, 1.0, 3.0)]
+    x, w = oracle.gll(Q)
+    B, DB = oracle.modified_basis(P, x)
+    M1 = B.T @ (w[:, None] * B)
+    S1 = DB.T @ (w[:, None] * DB)
+    for Li in L:
+        np.testing.assert_allclose(Li, np.kron(M1, S1) + np.kron(S1, M1), atol=1e-14)
+
+
+def _warped_ops(shape, P, lam=1.0, kappa=None, amp=0.05):
+    Q = P + 2
+    lat = W.lattice(shape)
+    x, _ = oracle.gll(Q)
+    J = W.element_jacobians(x, lat, amp)
+    return oracle.ElementOps(len(shape), P, Q, J, kappa=kappa, lam=lam), lat
+
+
+def _vertex_constant(P, dim):
+    c1 = np.zeros(P + 1)
+    c1[0] = c1[P] = 1.0
+    c = c1
+    for _ in range(dim - 1):
+        c = np.kron(c1, c)
+    return c
+
+
+@pytest.mark.parametrize("P", [2, 5])
+def test_constants_volume_symmetry_spd_curved(P):
+    """On curved elements: L_e 1 = 0, 1^T M_e 1 = element volume (sum w detJ),
+    H_e symmetric, M_e Cholesky succeeds."""
+    ops, _ = _warped_ops((2, 2, 2), P)
+    c = _vertex_constant(P, 3)
+    for e in range(ops.nelem):
+        L = ops.laplacian_matrix(e)
+        M = ops.mass_matrix(e)
+        np.testing.assert_allclose(L @ c, 0.0, atol=1e-12)
+        assert abs(c @ M @ c - ops.wJ[e].sum()) < 1e-14
+        H = ops.helmholtz_matrix(e)
+        np.testing.assert_allclose(H, H.T, atol=1e-13)
+        np.linalg.cholesky(M)
+
+
+def test_warped_unit_cube_volume_is_one():
+    """Every off-diagonal product of the cyclic warp integrates to zero over a
+    period, so the warped unit cube keeps volume 1."""
+    for shape, P in (((8, 8, 8), 6), ((3, 5, 4), 4)):
+        ops, lat = _warped_ops(shape, P)
+        assert abs(ops.wJ.sum() - 1.0) < 1e-13
+        dwarp = ops.detJ / np.prod(lat.h / 2)          # det of the curving map alone
+        assert dwarp.min() > 0.89 and dwarp.max() < 1.11
+
+
+@pytest.mark.parametrize("P", [3, 6])
+def test_fwd_bwd_roundtrip_curved(P):
+    """FwdTrans o BwdTrans = I on curved elements: M_e^{-1} I_e (B u^) = u^."""
+    ops, _ = _warped_ops((2, 1, 2), P)
+    rng = np.random.default_rng(5)
+    c = rng.uniform(-1, 1, (ops.nelem, (P + 1) ** 3))
+    u = ops.bwd(c)
+    f = ops.iprod(u)
+    for e in range(ops.nelem):
+        # M_e has condition number ~1e7 at P=6, so the round trip holds to ~1e-9
+        np.testing.assert_allclose(np.linalg.solve(ops.mass_matrix(e), f[e]), c[e], atol=1e-8)
+
+
+def test_projection_reproduces_polynomials():
+    """A polynomial of degree <= P per reference direction lies in the space:
+    BwdTrans(FwdTrans f) = f at the quadrature points, on a curved element."""
+    P = 4
+    ops, _ = _warped_ops((1, 1, 1), P)
+    x = ops.x
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    f = (X ** 4 - 2 * X * Y ** 3 + Z ** 2 * Y * X + 0.5).transpose(2, 1, 0).reshape(1, -1)
+    c = np.linalg.solve(ops.mass_matrix(0), ops.iprod(f)[0])
+    np.testing.assert_allclose(ops.bwd(c[None]), f, atol=1e-12)
+
+
+def test_listing1_integral_and_projection():
+    """Listing 1 (section 3.5): 8 modes (P=7), nModes+1 = 9 GLL points; the
+    integral of cos(x)cos(y) over [-1,1]^2 is 4 sin^2(1) (value in the text)."""
+    with open(os.path.join(GOLDEN, "listing1_integral.txt")) as fh:
+        nm, npts, exact = [l for l in fh if not l.startswith("#")][0].split()
+    P, Q, exact = int(nm) - 1, int(npts), float(exact)
+    assert abs(exact - 4 * math.sin(1.0) ** 2) < 1e-15
+    ops = oracle.ElementOps(2, P, Q, _affine_box_J([2.0, 2.0], Q, 2), lam=0.0)
+    x = ops.x
+    Xg, Yg = np.meshgrid(x, x, indexing="ij")
+    f = (np.cos(Xg) * np.cos(Yg)).T.reshape(1, -1)
+    assert abs(ops.integral(f)[0] - exact) < 1e-14
+    # Galerkin orthogonality of the projection (FwdTrans): I(f - B u^) = 0
+    c = np.linalg.solve(ops.mass_matrix(0), ops.iprod(f)[0])
+    np.testing.assert_allclose(ops.iprod(f - ops.bwd(c[None]))[0], 0.0, atol=1e-15)
+
+
+def test_listing1_point_count_reading():
+    """Reading of Listing 1: nine points (Q = P+2) integrate the P=7 mass matrix
+    exactly; eight (P+1) do not, so the text's 'P+1 points' is read as the
+    code's nModes+1."""
+    P = 7
+    xg, wg = np.polynomial.legendre.leggauss(20)
+    Bg, _ = oracle.modified_basis(P, xg)
+    M_exact = Bg.T @ (wg[:, None] * Bg)
+    for Q, ok in ((9, True), (8, False)):
+        x, w = oracle.gll(Q)
+        B, _ = oracle.modified_basis(P, x)
+        err = np.abs(B.T @ (w[:, None] * B) - M_exact).max()
+        assert (err < 1e-14) == ok, (Q, err)
+
+
+def test_sheared_affine_energy_of_physical_polynomials():
+    """On an affine element x = A xi + x0 with non-normal A, the stiffness
+    quadratic form of u = x1*x2 + 3 x3 equals int |grad_x u|^2 dx computed
+    in physical terms (gradient (x2, x1, 3)) by tensor Gauss quadrature.
+    Catches G = J^{-T} J^{-1} instead of J^{-1} J^{-T}."""
+    P, Q = 3, 5
+    A = np.array([[0.7, 0.4, -0.1], [0.05, 0.9, 0.3], [0.2, -0.25, 1.1]])
+    x0 = np.array([0.1, -0.2, 0.3])
+    J = np.broadcast_to(A[None, :, :, None], (1, 3, 3, Q ** 3)).copy()
+    ops = oracle.ElementOps(3, P, Q, J, lam=0.0)
+    xq = ops.x
+    XI = np.stack([g.transpose(2, 1, 0).reshape(-1) for g in np.meshgrid(xq, xq, xq, indexing="ij")])
+    Xp = A @ XI + x0[:, None]
+    u = Xp[0] * Xp[1] + 3 * Xp[2]
+    c = np.linalg.solve(ops.mass_matrix(0), ops.iprod(u[None])[0])
+    np.testing.assert_allclose(ops.bwd(c[None])[0], u, atol=1e-12)    # u in the space
+    xg, wg = np.polynomial.legendre.leggauss(6)
+    XG = np.stack([g.transpose(2, 1, 0).reshape(-1) for g in np.meshgrid(xg, xg, xg, indexing="ij")])
+    WG = np.kron(wg, np.kron(wg, wg))
+    Xg = A @ XG + x0[:, None]
+    grad2 = Xg[1] ** 2 + Xg[0] ** 2 + 9.0
+    exact = abs(np.linalg.det(A)) * WG @ grad2
+    assert abs(c @ ops.laplacian_matrix(0) @ c - exact) < 1e-12 * exact
+    # mass quadratic form: int u^2 dx
+    ug = Xg[0] * Xg[1] + 3 * Xg[2]
+    assert abs(c @ ops.mass_matrix(0) @ c - abs(np.linalg.det(A)) * WG @ ug ** 2) < 1e-12
+
+
+def test_variable_kappa_laplacian_single_point():
+    """dH_e/dkappa_q summed over all points with weights kappa_q rebuilds L_e."""
+    P = 2
+    rng = np.random.default_rng(3)
+    ops, _ = _warped_ops((1, 1, 1), P, kappa=rng.uniform(0.5, 2, (1, 64)))
+    L = sum(ops.kappa[0, q] * ops.dkappa_matrix(0, q) for q in range(64))
+    np.testing.assert_allclose(L, ops.laplacian_matrix(0), atol=1e-13)
+
+
+# ----------------------------------------------------------- assembly/solve
+
+def test_lattice_assembly_volume_and_constants():
+    """Assembled with the lattice map: the global constant (ones on global
+    vertex DOFs) has 1^T M 1 = 1 on the warped unit cube and L 1 = 0."""
+    P, shape = 3, (3, 2, 2)
+    ops, _ = _warped_ops(shape, P, lam=0.0)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    G = [s * P + 1 for s in shape]
+    gidx = np.indices(G[::-1]).reshape(3, -1)[::-1]
+    one = np.all(gidx % P == 0, axis=0).astype(float)
+    Mg = oracle.assembled_matrix(oracle.mass_matrices(ops), l2g, ng)
+    Lg = oracle.assembled_matrix([ops.laplacian_matrix(e) for e in range(ops.nelem)], l2g, ng)
+    assert abs(one @ (Mg @ one) - 1.0) < 1e-13
+    np.testing.assert_allclose(Lg @ one, 0.0, atol=1e-12)
+    np.testing.assert_allclose((Lg - Lg.T).toarray(), 0.0, atol=1e-13)
+    # gathered constant is the local vertex-constant on every element
+    np.testing.assert_array_equal(oracle.gather(one, l2g), np.tile(_vertex_constant(P, 3), (ops.nelem, 1)))
+
+
+def test_polynomial_manufactured_solution_is_exact():
+    """U = X(1-X) Y(1-Y) Z(1-Z) lies in the C0 space at P >= 2 on the affine
+    lattice and vanishes on the boundary: the discrete solution of the weak
+    problem with l(v) = a(U, v) reproduces U exactly.  Pins the weak RHS, the
+    assembly, the Dirichlet restriction and the solve together."""
+    P, shape = 2, (2, 3, 2)
+    ops, lat = _warped_ops(shape, P, lam=1.5, amp=0.0)
+    Xp = W.lattice_points(ops.x, lat)
+    f = Xp * (1 - Xp)
+    U = f.prod(axis=1)
+    dfX = 1 - 2 * Xp
+    dU = np.stack([dfX[:, 0] * f[:, 1] * f[:, 2], f[:, 0] * dfX[:, 1] * f[:, 2],
+                   f[:, 0] * f[:, 1] * dfX[:, 2]], axis=1) * (lat.h[None, :, None] / 2)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    b = oracle.assemble_vector(ops.weak_rhs(U, dU), l2g, ng)
+    b[dm.astype(bool)] = 0
+    u = direct_solve(oracle.helmholtz_matrices(ops), l2g, ng, dm, b)
+    np.testing.assert_allclose(ops.bwd(oracle.gather(u, l2g)), U, atol=1e-14)
+
+
+def test_manufactured_sine_converges_exponentially():
+    """Curved 3^3 lattice, U = sin(pi X) sin(pi Y) sin(pi Z): the max error at
+    the quadrature points falls by > 5x per two orders (exponential
+    convergence of the spectral/hp discretisation)."""
+    errs = []
+    for P in (2, 4, 6):
+        ops, lat = _warped_ops((3, 3, 3), P)
+        l2g, ng, dm = W.lattice_l2g((3, 3, 3), P)
+        U, dU = W.manufactured_ref_gradient(ops.x, lat)
+        b = oracle.assemble_vector(ops.weak_rhs(U, dU), l2g, ng)
+        b[dm.astype(bool)] = 0
+        u = direct_solve(oracle.helmholtz_matrices(ops), l2g, ng, dm, b)
+        errs.append(np.abs(ops.bwd(oracle.gather(u, l2g)) - U).max())
+    assert errs[0] < 2e-2 and errs[1] < errs[0] / 100 and errs[2] < errs[1] / 100, errs
+
+
+def test_pcg_matches_direct_solve():
+    P, shape = 3, (3, 3, 2)
+    ops, lat = _warped_ops(shape, P)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    mats = oracle.helmholtz_matrices(ops)
+    b = oracle.assemble_vector(ops.iprod(np.ones((ops.nelem, ops.Q ** 3))), l2g, ng)
+    b[dm.astype(bool)] = 0
+    xd = direct_solve(mats, l2g, ng, dm, b)
+    A = MaskedOperator(mats, l2g, ng, dm)
+    xc, it, res = pcg(A, b, jacobi_diagonal(mats, l2g, ng, dm), rtol=1e-13)
+    assert res < 1e-13 and it > 5
+    np.testing.assert_allclose(xc, xd, atol=1e-12 * np.abs(xd).max())
+
+
+# ----------------------------------------------------------------- gradient
+
+def _grad_problem(shape, P, seed):
+    Q = P + 2
+    lat = W.lattice(shape)
+    x, _ = oracle.gll(Q)
+    J = W.element_jacobians(x, lat, 0.05)
+    E, nq = lat.nelem, Q ** 3
+    kap = W.uniform(seed, (E, nq), 0.5, 2.0)
+    lam = W.uniform(seed + 1, (E,), 0.5, 2.0)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    ref = oracle.ElementOps(3, P, Q, J, lam=1.0)
+    U, dU = W.manufactured_ref_gradient(x, lat)
+    b = oracle.assemble_vector(ref.weak_rhs(U, dU), l2g, ng)
+    b[dm.astype(bool)] = 0
+    _, u_t = oracle.loss_and_solution(oracle.helmholtz_matrices(ref), l2g, ng, dm, b, np.zeros(ng))
+    return J, kap, lam, l2g, ng, dm, b, u_t
+
+
+def test_adjoint_gradient_matches_finite_differences():
+    """Central differences of the loss along random directions agree with
+    -z^T dA u for both lambda (per element) and kappa (per point)."""
+    P, shape = 2, (2, 2, 1)
+    J, kap, lam, l2g, ng, dm, b, u_t = _grad_problem(shape, P, 77)
+
+    def loss(k, l):
+        ops = oracle.ElementOps(3, P, P + 2, J, kappa=k, lam=l)
+        return oracle.loss_and_solution(oracle.helmholtz_matrices(ops), l2g, ng, dm, b, u_t)
+
+    ops = oracle.ElementOps(3, P, P + 2, J, kappa=kap, lam=lam)
+    mats = oracle.helmholtz_matrices(ops)
+    L0, u = loss(kap, lam)
+    assert L0 > 1e-8
+    z = direct_solve(mats, l2g, ng, dm, u - u_t)
+    dkap, dlam = oracle.param_grad(ops, l2g, u, z)
+    rng = np.random.default_rng(6)
+    for _ in range(2):
+        vk = rng.standard_normal(kap.shape)
+        vl = rng.standard_normal(lam.shape)
+        eps = 1e-5
+        fd = (loss(kap + eps * vk, lam + eps * vl)[0] - loss(kap - eps * vk, lam - eps * vl)[0]) / (2 * eps)
+        an = np.sum(dkap * vk) + np.sum(dlam * vl)
+        assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)

@@ -1,0 +1,237 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This module holds input generation only: structured element lattices, the
+analytic curving map and its derivative, a manufactured field, the lattice
+local-to-global numbering, and seeded random draws.  It contains no
+quadrature, basis or operator arithmetic: every caller passes in the 1-D
+reference points at which the map is to be evaluated, so the oracle and the
+GPU path each use their own quadrature tables.
+
+Conventions (shared data formats, not method arithmetic):
+  * element index e = ex + Nx*(ey + Ny*ez)  (x fastest);
+  * 1-D reference points xi in [-1, 1]; tensor point index
+    q = i + Q*(j + Q*l)  (direction 1 fastest);
+  * local mode index m = p + n*(q + n*r), n = P + 1 (direction 1 fastest),
+    with mode 0 the left vertex mode and mode P the right vertex mode of the
+    1-D modified basis (the order in which the paper's modified basis
+    display in section 2.1 lists them);
+  * Jacobian array J[e, c, a, q] = d x_c / d xi_a at point q.
+
+Seeds follow seed = 1000 * config_index + k with k = 0 coefficients,
+1 point values, 2 lambda, 3 kappa, 4 polynomial-order draws, 5 solve sizes,
+6 finite-difference directions.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+WARP_AMPLITUDE = 0.05
+
+# The five workloads: sizes and shapes of the paper's tensor-product element
+# groupings (section 3.3) at the scales this library is measured on.
+CONFIGS = {
+    0: dict(name="quad2d_8x8_P4", dim=2, shape=(8, 8), P=4, Q=6, warp=0.0, lam=1.0),
+    1: dict(name="hex3d_32c_P6_curved", dim=3, shape=(32, 32, 32), P=6, Q=8,
+            warp=WARP_AMPLITUDE, lam=1.0),
+    2: dict(name="hex3d_24c_cg", dim=3, shape=(24, 24, 24), P=(4, 6, 8),
+            warp=WARP_AMPLITUDE, lam=1.0),
+    3: dict(name="batch_varp20000_and_256solves", dim=3, varp_shape=(20, 20, 50),
+            varp_P=(2, 10), nsolves=256, solve_P=5, solve_sizes=(64, 4096),
+            warp=WARP_AMPLITUDE, lam=1.0),
+    4: dict(name="grad_16c_P6", dim=3, shape=(16, 16, 16), P=6, Q=8,
+            warp=WARP_AMPLITUDE, coef_range=(0.5, 2.0)),
+}
+
+
+def seed(config_index: int, k: int) -> int:
+    return 1000 * int(config_index) + int(k)
+
+
+def uniform(seed_: int, shape, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """i.i.d. U[lo, hi] FP64 draws from numpy's PCG64 with the given seed."""
+    return np.random.default_rng(seed_).uniform(lo, hi, size=shape)
+
+
+# ---------------------------------------------------------------- lattices
+
+@dataclass(frozen=True)
+class Lattice:
+    shape: tuple          # elements per direction (Nx, Ny[, Nz])
+    h: np.ndarray         # element edge lengths per direction
+    origins: np.ndarray   # (E, d) lower corner of each element
+
+    @property
+    def dim(self) -> int:
+        return len(self.shape)
+
+    @property
+    def nelem(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def lattice(shape, lengths=None) -> Lattice:
+    """Structured lattice of shape[0] x shape[1] (x shape[2]) boxes on
+    [0, L_0] x [0, L_1] (x [0, L_2]), element index x-fastest."""
+    shape = tuple(int(s) for s in shape)
+    d = len(shape)
+    lengths = np.ones(d) if lengths is None else np.asarray(lengths, float)
+    h = lengths / np.asarray(shape, float)
+    idx = np.indices(shape[::-1]).reshape(d, -1)[::-1]   # idx[0] fastest
+    origins = (idx.T * h).astype(np.float64)
+    return Lattice(shape, h, origins)
+
+
+def lattice_points(xi: np.ndarray, lat: Lattice) -> np.ndarray:
+    """Undeformed lattice coordinates X[e, c, q] of the tensor points built
+    from the 1-D reference points xi (affine map X = X_e0 + (xi+1)/2 * h)."""
+    xi = np.asarray(xi, np.float64)
+    Q = xi.size
+    d = lat.dim
+    t = (xi + 1.0) / 2.0
+    grids = np.meshgrid(*([t] * d), indexing="ij")        # grids[a][i0, i1, ...]
+    # point index q = i + Q*(j + Q*l): direction 1 fastest -> reverse axes
+    local = np.stack([g.transpose(tuple(range(d))[::-1]).reshape(-1) for g in grids])
+    X = lat.origins[:, :, None] + lat.h[None, :, None] * local[None, :, :]
+    return X
+
+
+# ---------------------------------------------------------- curving map
+
+def _s(t):
+    return np.sin(2.0 * math.pi * t)
+
+
+def _ds(t):
+    return 2.0 * math.pi * np.cos(2.0 * math.pi * t)
+
+
+def warp(X: np.ndarray, amp: float = WARP_AMPLITUDE) -> np.ndarray:
+    """Cyclic curving map of the unit cube (3-D) or square (2-D):
+    x = X + a s(Y) s(Z), y = Y + a s(Z) s(X), z = Z + a s(X) s(Y),
+    s(t) = sin(2 pi t).  X has the coordinate on axis -2: (..., d, npts)."""
+    X = np.asarray(X, np.float64)
+    d = X.shape[-2]
+    if d == 2:
+        x, y = X[..., 0, :], X[..., 1, :]
+        return np.stack([x + amp * _s(y), y + amp * _s(x)], axis=-2)
+    x, y, z = X[..., 0, :], X[..., 1, :], X[..., 2, :]
+    return np.stack([x + amp * _s(y) * _s(z),
+                     y + amp * _s(z) * _s(x),
+                     z + amp * _s(x) * _s(y)], axis=-2)
+
+
+def warp_jacobian(X: np.ndarray, amp: float = WARP_AMPLITUDE) -> np.ndarray:
+    """d x_c / d X_a of `warp`, shape (..., d, d, npts) indexed [c, a]."""
+    X = np.asarray(X, np.float64)
+    d = X.shape[-2]
+    one = np.ones_like(X[..., 0, :])
+    if d == 2:
+        x, y = X[..., 0, :], X[..., 1, :]
+        rows = [[one, amp * _ds(y)], [amp * _ds(x), one]]
+    else:
+        x, y, z = X[..., 0, :], X[..., 1, :], X[..., 2, :]
+        rows = [[one, amp * _ds(y) * _s(z), amp * _s(y) * _ds(z)],
+                [amp * _s(z) * _ds(x), one, amp * _ds(z) * _s(x)],
+                [amp * _ds(x) * _s(y), amp * _s(x) * _ds(y), one]]
+    return np.stack([np.stack(r, axis=-2) for r in rows], axis=-3)
+
+
+def element_jacobians(xi: np.ndarray, lat: Lattice, amp: float) -> np.ndarray:
+    """J[e, c, a, q] = d x_c / d xi_a at the tensor points of xi for the
+    composition (reference -> lattice box -> curving map).  The lattice step
+    is affine, d X_a / d xi_a = h_a / 2, so J = (d x / d X) diag(h / 2)."""
+    X = lattice_points(xi, lat)
+    if amp == 0.0:
+        d = lat.dim
+        J = np.zeros((lat.nelem, d, d, X.shape[-1]))
+        for a in range(d):
+            J[:, a, a, :] = lat.h[a] / 2.0
+        return J
+    dxdX = warp_jacobian(X, amp)
+    return dxdX * (lat.h[None, None, :, None] / 2.0)
+
+
+# ---------------------------------------------------- manufactured field
+
+def manufactured_sine(X: np.ndarray):
+    """U = prod_c sin(pi X_c) on the undeformed lattice coordinates and its
+    gradient dU/dX_c; X is (..., d, npts).  U vanishes on the boundary of the
+    unit box."""
+    X = np.asarray(X, np.float64)
+    d = X.shape[-2]
+    s = np.sin(math.pi * X)
+    c = math.pi * np.cos(math.pi * X)
+    U = np.prod(s, axis=-2)
+    grads = []
+    for a in range(d):
+        g = c[..., a, :].copy()
+        for b in range(d):
+            if b != a:
+                g = g * s[..., b, :]
+        grads.append(g)
+    return U, np.stack(grads, axis=-2)
+
+
+def manufactured_ref_gradient(xi: np.ndarray, lat: Lattice):
+    """U and its reference-coordinate gradient dU/dxi_a = (h_a/2) dU/dX_a at
+    the tensor points of xi in every element: (E, Q^d) and (E, d, Q^d)."""
+    X = lattice_points(xi, lat)
+    U, dU = manufactured_sine(X)
+    return U, dU * (lat.h[None, :, None] / 2.0)
+
+
+# ------------------------------------------------ lattice C0 numbering
+
+def lattice_l2g(shape, P: int):
+    """Local-to-global map of a conforming structured lattice at uniform
+    order P with the modified-basis mode order (vertex modes at 0 and P).
+
+    Global index of local mode (p, q, r) of element (ex, ey, ez):
+      gx = ex*P + p, gy = ey*P + q, gz = ez*P + r,
+      g = gx + Gx*(gy + Gy*gz),  G_c = N_c*P + 1.
+    Right vertex mode P of element e coincides with left vertex mode 0 of
+    element e+1; bubble modes interior to an element edge are shared along
+    that edge in the other directions.  Returns (l2g[E, n^d] int32, nglobal,
+    dirichlet[nglobal] uint8) with Dirichlet DOFs on the lattice boundary.
+    """
+    shape = tuple(int(s) for s in shape)
+    d = len(shape)
+    n = P + 1
+    G = [s * P + 1 for s in shape]
+    eidx = np.indices(shape[::-1]).reshape(d, -1)[::-1]           # (d, E)
+    midx = np.indices((n,) * d).reshape(d, -1)[::-1]             # (d, n^d)
+    gc = eidx[:, :, None] * P + midx[:, None, :]                 # (d, E, n^d)
+    g = gc[d - 1]
+    for c in range(d - 2, -1, -1):
+        g = gc[c] + G[c] * g
+    nglobal = int(np.prod(G))
+    gall = np.indices(G[::-1]).reshape(d, -1)[::-1]
+    dir_mask = np.zeros(nglobal, np.uint8)
+    for c in range(d):
+        dir_mask |= ((gall[c] == 0) | (gall[c] == G[c] - 1)).astype(np.uint8)
+    return g.astype(np.int32), nglobal, dir_mask
+
+
+# ----------------------------------------------------------- draws
+
+def varp_orders(seed_: int, nelem: int, lo: int = 2, hi: int = 10) -> np.ndarray:
+    """Per-element polynomial order drawn uniformly from {lo..hi}."""
+    return np.random.default_rng(seed_).integers(lo, hi + 1, size=nelem)
+
+
+def solve_boxes(seed_: int, nsolves: int, smin: int = 64, smax: int = 4096):
+    """Independent solve sizes s ~ log-uniform[smin, smax] mapped to box
+    lattices a x b x c with a = round(s^(1/3)), b = round(sqrt(s/a)),
+    c = ceil(s/(a b)).  Returns a list of (a, b, c)."""
+    rng = np.random.default_rng(seed_)
+    s = np.exp(rng.uniform(math.log(smin), math.log(smax), size=nsolves))
+    boxes = []
+    for si in s:
+        a = max(1, int(round(si ** (1.0 / 3.0))))
+        b = max(1, int(round(math.sqrt(si / a))))
+        c = max(1, int(math.ceil(si / (a * b))))
+        boxes.append((a, b, c))
+    return boxes
