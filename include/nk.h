@@ -1,0 +1,236 @@
+/*
+ * nk.h -- C ABI of the matrix-free spectral/hp operator library for MI355X
+ * (gfx950).
+ *
+ * The library evaluates, for many same-shape tensor-product elements at once,
+ * the operators that section 3.3 ("Collective linear algebra operations") of
+ * Moxey et al., "Nektar++: enhancing the capability and application of
+ * high-fidelity spectral/hp element methods" (arXiv 1906.03489) groups into
+ * collections: the backward transform (elemental expansion evaluated at the
+ * quadrature points), the inner product with respect to the basis, and the
+ * Helmholtz operator of the weak problem a(u, v) = l(v) of Eqs. (1)-(2), all
+ * by sum-factorisation (the display in section 3.3).  On top of these it
+ * assembles the C0 system (section 2.1, assembly operator) and solves it with
+ * Jacobi-preconditioned conjugate gradients.
+ *
+ * Discretisation (section 2.1):
+ *   - 1-D modified hierarchical C0 basis phi_p, 0 <= p <= P (P = polynomial
+ *     order, n = P + 1 modes per direction): phi_0 = (1-x)/2 and
+ *     phi_P = (1+x)/2 are the vertex modes, phi_p = (1-x)/2 (1+x)/2
+ *     P^{1,1}_{p-1}(x) the bubbles; tensor products on quads and hexes;
+ *   - Q Gauss-Lobatto-Legendre points per direction (currently Q = P + 2);
+ *   - the map chi_e of each element enters through its Jacobian
+ *     J = dx/dxi at every quadrature point.
+ * The Helmholtz operator is  y_e = (L_e + lambda_e M_e) x_e  with
+ *   M_e = B^T diag(w detJ) B,
+ *   L_e = sum_{a,b} (D_a B)^T diag(w detJ kappa (J^{-1} J^{-T})_{ab}) (D_b B),
+ * i.e. the weak form of -div(kappa grad u) + lambda u (symmetric positive
+ * definite for lambda >= 0).
+ *
+ * Layouts (all arrays row-major, element index slowest):
+ *   coefficients  [E][n^d]  mode m = p + n*(q + n*r), direction 1 fastest;
+ *   point values  [E][Q^d]  point k = i + Q*(j + Q*l), direction 1 fastest;
+ *   Jacobians     [E][d][d][Q^d], entry [e][c][a][k] = d x_c / d xi_a;
+ *   kappa         [E][Q^d];  lambda  [E].
+ * For a variable-order space the groups' arrays are concatenated in group
+ * order.
+ *
+ * Ownership: every buffer argument is owned by the caller; "device" means
+ * GPU memory of the current HIP device, "host" means CPU memory.  Create
+ * calls copy or derive what they need; no call keeps a caller pointer after
+ * it returns.  Handles own their GPU memory and free it on destroy.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Operator
+ * calls are asynchronous on it.  Create calls and solves synchronise it.
+ *
+ * Errors: every call returns an nk_status; nothing throws across the ABI.
+ * Arguments are validated before any device work; on a non-OK status
+ * nk_last_error() returns a thread-local message.  NK_EDEVICE means no usable
+ * HIP device is present.
+ */
+#ifndef NK_H
+#define NK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NK_OK = 0,
+  NK_EINVAL = 1,        /* bad argument (null pointer, bad size, bad enum) */
+  NK_ENOMEM = 2,        /* device allocation failed                        */
+  NK_EDEVICE = 3,       /* no usable HIP device                            */
+  NK_EHIP = 4,          /* a HIP runtime call failed                       */
+  NK_ENOCONV = 5,       /* CG hit maxit; x holds the last iterate          */
+  NK_EBREAKDOWN = 6,    /* CG breakdown (p.Ap <= 0 or non-finite)          */
+  NK_EUNSUPPORTED = 7   /* (dim, P, Q) combination not compiled in         */
+} nk_status;
+
+typedef enum { NK_F64 = 0, NK_F32 = 1 } nk_dtype;
+
+typedef enum { NK_SOLVE_F64 = 0, NK_SOLVE_F32_REFINED = 1 } nk_solve_mode;
+
+typedef struct nk_space_s* nk_space;
+typedef struct nk_system_s* nk_system;
+
+typedef struct {
+  int iters;             /* CG iterations (FP64 mode) or inner FP32 iterations summed */
+  int outer_iters;       /* refinement steps (FP32-refined mode), 0 otherwise          */
+  double rel_resid;      /* true ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit    */
+  double solve_ms;       /* wall time of the solve on the host clock                   */
+  int status;            /* nk_status of this system                                   */
+} nk_solve_info;
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char* nk_last_error(void);
+
+/* Library version, as 10000*major + 100*minor + patch. */
+int nk_version(void);
+
+/* Number of usable HIP devices (0 if none); never fails. */
+int nk_device_count(void);
+
+/* Host-side 1-D tables (section 2.1): Q GLL points x[Q] and weights w[Q],
+ * B[Q][P+1] = phi_p(x_i) and DB[Q][P+1] = phi_p'(x_i).  Any output may be
+ * NULL.  Host memory.  1 <= P, P + 1 <= Q <= 32.  Useful to evaluate a
+ * mesh's Jacobians at the library's quadrature points. */
+nk_status nk_basis_tables(int P, int Q, double* x, double* w, double* B, double* DB);
+
+/* Create a space of `nelem` elements of one shape (dim = 2: quads, 3: hexes)
+ * at order P with Q points per direction -- one collection in the sense of
+ * section 3.3.  jac: device [E][d][d][Q^d]; kappa: device [E][Q^d] or NULL
+ * (kappa = 1).  Computes and stores the per-point geometric factors
+ * w detJ and w detJ kappa (J^{-1} J^{-T})_{ab} in FP64 and FP32.  Returns
+ * NK_EINVAL if any detJ <= 0, NK_EUNSUPPORTED if (dim, P, Q) is not built. */
+nk_status nk_space_create(nk_space* out, int dim, int64_t nelem, int P, int Q,
+                          const double* jac, const double* kappa, void* stream);
+
+/* Variable polynomial order (section 4.2): `ngroups` groups, group g holding
+ * nelem[g] elements at order P[g] with Q[g] points (host arrays); jac[g] and
+ * kappa[g] (kappa may be NULL) are device pointers laid out as for
+ * nk_space_create.  Operators on such a space take the groups' arrays
+ * concatenated in group order and run as ONE persistent launch. */
+nk_status nk_space_create_varp(nk_space* out, int dim, int ngroups, const int* P,
+                               const int* Q, const int64_t* nelem,
+                               const double* const* jac, const double* const* kappa,
+                               void* stream);
+
+nk_status nk_space_destroy(nk_space s);
+
+/* Sizes of a space: total elements, coefficients (sum n^d) and points
+ * (sum Q^d).  Any output may be NULL. */
+nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints);
+
+/* BwdTrans (section 2.1 elemental expansion; section 3.3 sum-factorisation):
+ * phys_e = (B (x) B (x) B) coeffs_e.  coeffs: device [E][n^d], phys: device
+ * [E][Q^d], both of type t. */
+nk_status nk_bwd_trans(nk_space s, nk_dtype t, const void* coeffs, void* phys, void* stream);
+
+/* IProductWRTBase: coeffs_e = B^T diag(w detJ) phys_e (section 3.3 operator
+ * set).  phys: device [E][Q^d], coeffs: device [E][n^d], type t. */
+nk_status nk_iprod_wrt_base(nk_space s, nk_dtype t, const void* phys, void* coeffs, void* stream);
+
+/* Local Helmholtz operator y_e = (L_e + lambda_e M_e) x_e, matrix-free.
+ * lambda: device [E] FP64 per-element coefficients, or NULL to use lambda0
+ * for every element.  x, y: device [E][n^d] of type t (x and y must not
+ * overlap). */
+nk_status nk_helmholtz(nk_space s, nk_dtype t, const double* lambda, double lambda0,
+                       const void* x, void* y, void* stream);
+
+/* Weak form of the Helmholtz operator of a field given at the quadrature
+ * points: y_e[m] = a_e(U, phi_m) = sum_a (D_a B)^T (w detJ kappa sum_b G_ab dU_b)
+ * + lambda_e B^T (w detJ U), the right-hand side l(v) = a(U, v) of Eq. (1)
+ * for a manufactured U.  u: device [E][Q^d] values; du: device [E][d][Q^d]
+ * reference-coordinate gradient dU/dxi_a; y: device [E][n^d].  FP64. */
+nk_status nk_helmholtz_weak_rhs(nk_space s, const double* lambda, double lambda0,
+                                const double* u, const double* du, double* y,
+                                void* stream);
+
+/* Assembled C0 system (section 2.1, assembly operator) over a space with a
+ * single group: nglobal global coefficients, l2g device int32 [E][n^d]
+ * mapping local to global modes (no sign flips), dirichlet device uint8
+ * [nglobal] (1 = homogeneous Dirichlet DOF, fixed at zero), lambda device
+ * [E] or NULL (lambda0).  Builds the Jacobi diagonal on the GPU. */
+nk_status nk_system_create(nk_system* out, nk_space s, int64_t nglobal, const int32_t* l2g,
+                           const uint8_t* dirichlet, const double* lambda, double lambda0,
+                           void* stream);
+
+/* Many independent systems solved together (the union is block diagonal):
+ * system k owns elements [elem_off[k], elem_off[k+1]) of the space and global
+ * DOFs [dof_off[k], dof_off[k+1]) (host int64 arrays of nsys+1 entries); l2g
+ * holds indices into the union numbering.  Each system keeps its own CG
+ * scalars and convergence test. */
+nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys,
+                                   const int64_t* elem_off, const int64_t* dof_off,
+                                   const int32_t* l2g, const uint8_t* dirichlet,
+                                   const double* lambda, double lambda0, void* stream);
+
+nk_status nk_system_destroy(nk_system sys);
+
+/* y = R A R x for the assembled operator (R zeroes Dirichlet entries) in the
+ * given precision.  x, y: device [nglobal] of type t. */
+nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* y, void* stream);
+
+/* b = R (sum_e A_e^T y_loc_e): scatter-add of local vectors into the global
+ * numbering with Dirichlet entries zeroed.  FP64 device arrays. */
+nk_status nk_assemble(nk_system sys, const double* y_loc, double* b, void* stream);
+
+/* x_loc_e = A_e x: gather of global coefficients to local ones.  FP64. */
+nk_status nk_gather(nk_system sys, const double* x, double* x_loc, void* stream);
+
+/* Jacobi diagonal of the assembled operator (Dirichlet rows = 1).  FP64
+ * device [nglobal]. */
+nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
+
+/* Solve R A R x = b by Jacobi-preconditioned CG.  b, x: device FP64
+ * [nglobal] (x: initial guess in, solution out; Dirichlet entries of x are
+ * forced to zero).  Stops when the residual ||r||_2 <= rtol ||b||_2 or after
+ * maxit iterations.  NK_SOLVE_F64: FP64 throughout.  NK_SOLVE_F32_REFINED:
+ * the operator and CG vectors run in FP32 (dot products accumulated in FP64)
+ * inside an FP64 iterative-refinement loop whose residual, dot products and
+ * solution update are FP64.  Iterations run as captured HIP graphs.  info
+ * (host, may be NULL) receives one entry per system (nsys entries for a
+ * batched system).  Returns NK_ENOCONV / NK_EBREAKDOWN if any system did
+ * not converge. */
+nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double* x,
+                      double rtol, int maxit, nk_solve_info* info, void* stream);
+
+/* Adjoint-gradient kernel for a loss of a Helmholtz solve: with u_loc and
+ * z_loc the local (gathered) forward and adjoint solutions, writes
+ *   dkappa[e][k] = -w_k detJ_k (grad_xi z)^T G (grad_xi u) at point k,
+ *   dlambda[e]   = -z_e^T M_e u_e,
+ * i.e. -z^T (dA/dtheta) u for theta = kappa (per point) and lambda (per
+ * element).  Device FP64: z_loc, u_loc [E][n^d], dkappa [E][Q^d] (may be
+ * NULL), dlambda [E] (may be NULL).  Requires a single-group 3-D or 2-D
+ * space created with kappa (NULL kappa means kappa = 1). */
+nk_status nk_helmholtz_param_grad(nk_space s, const double* z_loc, const double* u_loc,
+                                  double* dkappa, double* dlambda, void* stream);
+
+/* Time every compiled tile configuration of the operators in op_mask
+ * (bit 0 BwdTrans, 1 IProductWRTBase, 2 Helmholtz, 3 assembled operator)
+ * for this space's orders with HIP events and keep the fastest; results are
+ * cached per (op, dim, P, Q, dtype, device name) in the file named by
+ * NK_AUTOTUNE_CACHE (default: no file). */
+nk_status nk_autotune(nk_space s, int op_mask, void* stream);
+
+/* Name of the tile configuration currently selected for (op, dim, P, dtype)
+ * ("" if none).  Host string owned by the library (thread-local buffer). */
+const char* nk_tile_config(int op, int dim, int P, nk_dtype t);
+
+/* Number of compiled tile configurations of (op, dim, P) (0 for a bad op). */
+int nk_tile_count(int op, int dim, int P);
+
+/* Force tile configuration `tile` (0 <= tile < nk_tile_count) for (op, dim,
+ * P, dtype), op in {0 BwdTrans, 1 IProductWRTBase, 2 Helmholtz}; the
+ * assembled operator follows the Helmholtz choice for systems created
+ * afterwards.  NK_EINVAL for out-of-range arguments. */
+nk_status nk_set_tile_config(int op, int dim, int P, nk_dtype t, int tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NK_H */

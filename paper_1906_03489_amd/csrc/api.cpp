@@ -1,0 +1,1136 @@
+// C ABI of the library: argument validation, handle management and dispatch.
+// Every entry point validates before touching the device and converts every
+// failure into an nk_status with a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "nk_internal.h"
+#include "system.h"
+#include "tiles.h"
+
+namespace nk {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+nk_status fail(nk_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+nk_status hip_fail(hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  g_err = m;
+  return e == hipErrorOutOfMemory ? NK_ENOMEM : NK_EHIP;
+}
+
+bool op_supported(int dim, int P, int Q) {
+  return (dim == 2 || dim == 3) && P >= kMinP && P <= kMaxP && Q == P + 2;
+}
+
+hipError_t launch_op3(nk_dtype t, const OpArgs& a) {
+  if (a.nelem == 0) return hipSuccess;
+  switch (a.P) {
+    case 1: case 2: case 3: case 4: return launch_op3_set0(t, a);
+    case 5: return launch_op3_set1(t, a);
+    case 6: return launch_op3_set2(t, a);
+    case 7: return launch_op3_set3(t, a);
+    case 8: return launch_op3_set4(t, a);
+    case 9: return launch_op3_set5(t, a);
+    case 10: return launch_op3_set6(t, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_op(int dim, nk_dtype t, const OpArgs& a) {
+  if (a.nelem == 0) return hipSuccess;
+  return dim == 3 ? launch_op3(t, a) : launch_op2(t, a);
+}
+
+// ------------------------------------------------------------- tile choice
+static std::atomic<int> g_tile[OP_COUNT][2][kMaxP + 1][2];
+
+int tile_count(int op, int dim, int P) {
+  if (P < kMinP || P > kMaxP || !op_has_tiles(op)) return 1;
+  int c = 0;
+  for (int k = 0; k < kMaxTiles; ++k)
+    c += (dim == 3 ? kTileEPB3[P][k] : kTileEPB2[P][k]) > 0 ? 1 : 0;
+  return c;
+}
+
+const char* tile_name(int op, int dim, int P, int tile) {
+  static thread_local char buf[64];
+  if (P < kMinP || P > kMaxP) return "";
+  const int epb = dim == 3 ? kTileEPB3[P][tile] : kTileEPB2[P][tile];
+  const int q = P + 2;
+  std::snprintf(buf, sizeof buf, "epb%d_thr%d", epb, epb * (dim == 3 ? q * q : q));
+  (void)op;
+  return buf;
+}
+
+static int cur_tile(int op, int dim, int P, nk_dtype t) {
+  if (op == OP_HELM_ASM) op = OP_HELM;
+  if (!op_has_tiles(op) || P < kMinP || P > kMaxP) return 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    // NK_TILE forces one candidate index for every operator (testing aid)
+    const char* f = std::getenv("NK_TILE");
+    const int v = f ? std::atoi(f) : 0;
+    for (auto& a : g_tile)
+      for (auto& b : a)
+        for (auto& c : b)
+          for (auto& d : c) d.store(v);
+  });
+  int k = g_tile[op][dim - 2][P][t].load();
+  if (k < 0 || k >= tile_count(op, dim, P)) k = 0;
+  return k;
+}
+
+// ------------------------------------------------------------- validation
+static nk_status check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(NK_EDEVICE, "no usable HIP device");
+  return NK_OK;
+}
+
+// A device buffer argument must be GPU-accessible memory with at least
+// `bytes` bytes from p to the end of its allocation.
+static nk_status check_buf(const void* p, size_t bytes, const char* name) {
+  if (bytes == 0) return NK_OK;
+  if (p == nullptr) return fail(NK_EINVAL, std::string(name) + " is NULL");
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(NK_EINVAL, std::string(name) + " is not device memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged &&
+      attr.type != hipMemoryTypeUnified) {
+    return fail(NK_EINVAL, std::string(name) + " is not device memory");
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) == hipSuccess && base != nullptr) {
+    const size_t off = (const char*)p - (const char*)base;
+    if (off + bytes > size)
+      return fail(NK_EINVAL, std::string(name) + " is smaller than required (" +
+                                 std::to_string(bytes) + " bytes)");
+  } else {
+    (void)hipGetLastError();
+  }
+  return NK_OK;
+}
+
+#define NK_CHECK(expr)               \
+  do {                               \
+    nk_status st_ = (expr);          \
+    if (st_ != NK_OK) return st_;    \
+  } while (0)
+
+static size_t dsize(nk_dtype t) { return t == NK_F64 ? 8 : 4; }
+
+static int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+template <typename T>
+static hipError_t dmalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <typename T>
+static void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace nk
+
+using namespace nk;
+
+// =================================================================== ABI
+// The entry points below were declared extern "C" in nk.h, so their
+// definitions have C linkage.
+
+const char* nk_last_error(void) { return g_err.c_str(); }
+
+int nk_version(void) { return 10000; }
+
+int nk_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+nk_status nk_basis_tables(int P, int Q, double* x, double* w, double* B, double* DB) {
+  if (P < 1 || Q < P + 1 || Q > 32) return fail(NK_EINVAL, "need 1 <= P, P+1 <= Q <= 32");
+  std::vector<double> xx(Q), ww(Q), bb(Q * (P + 1)), dd(Q * (P + 1));
+  gll_points(Q, xx.data(), ww.data());
+  modified_basis(P, Q, xx.data(), bb.data(), dd.data());
+  if (x) std::memcpy(x, xx.data(), Q * sizeof(double));
+  if (w) std::memcpy(w, ww.data(), Q * sizeof(double));
+  if (B) std::memcpy(B, bb.data(), bb.size() * sizeof(double));
+  if (DB) std::memcpy(DB, dd.data(), dd.size() * sizeof(double));
+  return NK_OK;
+}
+
+static void space_free(nk_space s) {
+  if (!s) return;
+  dfree(s->fac64);
+  dfree(s->fac32);
+  dfree(s->kappa);
+  dfree(s->varp_groups);
+  dfree(s->varp_item_start);
+  dfree(s->varp_lam_off);
+  delete s;
+}
+
+nk_status nk_space_create_varp(nk_space* out, int dim, int ngroups, const int* P, const int* Q,
+                               const int64_t* nelem, const double* const* jac,
+                               const double* const* kappa, void* stream) {
+  if (!out) return fail(NK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(NK_EINVAL, "dim must be 2 or 3");
+  if (ngroups < 1 || ngroups > 64) return fail(NK_EINVAL, "ngroups must be in [1, 64]");
+  if (!P || !Q || !nelem || !jac) return fail(NK_EINVAL, "P, Q, nelem and jac must be non-NULL");
+  for (int g = 0; g < ngroups; ++g) {
+    if (nelem[g] < 0) return fail(NK_EINVAL, "nelem must be >= 0");
+    if (nelem[g] > 0 && jac[g] == nullptr) return fail(NK_EINVAL, "jac is NULL");
+    if (P[g] < 1 || Q[g] < P[g] + 1) return fail(NK_EINVAL, "need P >= 1 and Q >= P+1");
+    if (!op_supported(dim, P[g], Q[g]))
+      return fail(NK_EUNSUPPORTED, "compiled orders: 1 <= P <= 10 with Q = P + 2");
+  }
+  NK_CHECK(check_device());
+  hipStream_t st = (hipStream_t)stream;
+  nk_space s = new nk_space_s();
+  s->dim = dim;
+  (void)hipGetDevice(&s->device);
+  bool has_kappa = false;
+  for (int g = 0; g < ngroups; ++g) {
+    Group G;
+    G.P = P[g];
+    G.Q = Q[g];
+    G.n = P[g] + 1;
+    G.nelem = nelem[g];
+    G.e0 = s->nelem;
+    G.c0 = s->ncoeff;
+    G.q0 = s->npoint;
+    G.f0 = s->nfac;
+    s->nelem += G.nelem;
+    s->ncoeff += G.nelem * ipow(G.n, dim);
+    s->npoint += G.nelem * ipow(G.Q, dim);
+    s->nfac += G.nelem * ipow(G.Q, dim) * (dim == 3 ? kNF3 : kNF2);
+    s->groups.push_back(G);
+    if (kappa && kappa[g]) has_kappa = true;
+  }
+  for (int g = 0; g < ngroups; ++g) {
+    const Group& G = s->groups[g];
+    const int64_t nq = ipow(G.Q, dim);
+    nk_status cs = check_buf(jac[g], (size_t)G.nelem * dim * dim * nq * 8, "jac");
+    if (cs == NK_OK && kappa && kappa[g]) cs = check_buf(kappa[g], (size_t)G.nelem * nq * 8, "kappa");
+    if (cs != NK_OK) {
+      space_free(s);
+      return cs;
+    }
+  }
+  auto cleanup = [&](nk_status stt) {
+    space_free(s);
+    return stt;
+  };
+  hipError_t e;
+  if ((e = dmalloc(&s->fac64, s->nfac)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = dmalloc(&s->fac32, s->nfac)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if (has_kappa) {
+    if ((e = dmalloc(&s->kappa, s->npoint)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  }
+  int* d_bad = nullptr;
+  double* d_w = nullptr;
+  if ((e = dmalloc(&d_bad, 1)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = dmalloc(&d_w, 32)) != hipSuccess) {
+    dfree(d_bad);
+    return cleanup(hip_fail(e, "hipMalloc"));
+  }
+  e = hipMemsetAsync(d_bad, 0, sizeof(int), st);
+  for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
+    const Group& G = s->groups[g];
+    std::vector<double> x(G.Q), w(G.Q);
+    gll_points(G.Q, x.data(), w.data());
+    e = hipMemcpyAsync(d_w, w.data(), G.Q * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    const double* kg = (kappa && kappa[g]) ? kappa[g] : nullptr;
+    if (has_kappa) {
+      const int64_t nq = ipow(G.Q, dim);
+      if (kg)
+        e = hipMemcpyAsync(s->kappa + G.q0, kg, G.nelem * nq * sizeof(double),
+                           hipMemcpyDeviceToDevice, st);
+      else
+        e = vec_fill<double>(s->kappa + G.q0, G.nelem * nq, 1.0, st);
+      if (e != hipSuccess) break;
+    }
+    e = launch_geom(dim, G.Q, G.nelem, jac[g], kg, d_w, s->fac64 + G.f0, s->fac32 + G.f0, d_bad, st);
+    // the weights buffer is reused by the next group: wait for this launch
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
+  dfree(d_bad);
+  dfree(d_w);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "space setup"));
+  if (bad) return cleanup(fail(NK_EINVAL, "non-positive Jacobian determinant or kappa"));
+  if (ngroups > 1) {
+    // persistent mixed-order launch tables: items of larger orders first
+    std::vector<int> order(ngroups);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return s->groups[a].P > s->groups[b].P; });
+    std::vector<VarpGroup> vg;
+    std::vector<int64_t> start(1, 0), lamoff;
+    for (int k : order) {
+      const Group& G = s->groups[k];
+      VarpGroup v;
+      v.P = G.P;
+      v.nelem = G.nelem;
+      v.c0 = G.c0;
+      v.f0 = G.f0;
+      vg.push_back(v);
+      lamoff.push_back(G.e0);
+      start.push_back(start.back() + varp_items_per_group(G.P, G.nelem));
+    }
+    s->varp_nitems = start.back();
+    if ((e = dmalloc(&s->varp_groups, vg.size())) != hipSuccess ||
+        (e = dmalloc(&s->varp_item_start, start.size())) != hipSuccess ||
+        (e = dmalloc(&s->varp_lam_off, lamoff.size())) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc"));
+    e = hipMemcpy(s->varp_groups, vg.data(), vg.size() * sizeof(VarpGroup), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(s->varp_item_start, start.data(), start.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(s->varp_lam_off, lamoff.data(), lamoff.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy"));
+  }
+  *out = s;
+  return NK_OK;
+}
+
+nk_status nk_space_create(nk_space* out, int dim, int64_t nelem, int P, int Q, const double* jac,
+                          const double* kappa, void* stream) {
+  const double* j[1] = {jac};
+  const double* k[1] = {kappa};
+  return nk_space_create_varp(out, dim, 1, &P, &Q, &nelem, j, kappa ? k : nullptr, stream);
+}
+
+nk_status nk_space_destroy(nk_space s) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  (void)hipDeviceSynchronize();
+  space_free(s);
+  return NK_OK;
+}
+
+nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (nelem) *nelem = s->nelem;
+  if (ncoeffs) *ncoeffs = s->ncoeff;
+  if (npoints) *npoints = s->npoint;
+  return NK_OK;
+}
+
+// Run one elemental operator over every group of the space.
+static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* out,
+                          const double* lam, double lam0, const double* in2, void* stream) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
+  const size_t sz = dsize(t);
+  const int d = s->dim;
+  const bool pts_in = (op == OP_IPROD || op == OP_RHS);
+  const bool pts_out = (op == OP_BWD);
+  NK_CHECK(check_buf(in, (pts_in ? s->npoint : s->ncoeff) * sz, "input"));
+  NK_CHECK(check_buf(out, (pts_out ? s->npoint : s->ncoeff) * sz, "output"));
+  if (lam) NK_CHECK(check_buf(lam, s->nelem * 8, "lambda"));
+  if (op == OP_RHS) NK_CHECK(check_buf(in2, s->npoint * d * 8, "du"));
+  if (in == out) return fail(NK_EINVAL, "input and output must not alias");
+  hipStream_t st = (hipStream_t)stream;
+  const char* fac = t == NK_F64 ? (const char*)s->fac64 : (const char*)s->fac32;
+  if (op == OP_HELM && s->groups.size() > 1) {
+    VarpArgs v;
+    v.t = t;
+    v.ngroups = (int)s->groups.size();
+    v.groups_dev = s->varp_groups;
+    v.item_start_dev = s->varp_item_start;
+    v.nitems = s->varp_nitems;
+    v.x = in;
+    v.y = out;
+    v.fac = fac;
+    v.lam = lam;
+    v.lam_off_dev = s->varp_lam_off;
+    v.lam0 = lam0;
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device);
+    const int64_t grid = std::min<int64_t>((int64_t)std::max(ncu, 1) * varp_blocks_per_cu(t),
+                                           s->varp_nitems);
+    v.grid = (int)std::max<int64_t>(grid, 1);
+    v.stream = st;
+    hipError_t e = launch_helm_varp(v);
+    if (e != hipSuccess) return hip_fail(e, "mixed-order Helmholtz launch");
+    return NK_OK;
+  }
+  for (const Group& G : s->groups) {
+    OpArgs a;
+    a.op = op;
+    a.dim = d;
+    a.P = G.P;
+    a.Q = G.Q;
+    a.nelem = G.nelem;
+    a.in = (const char*)in + (pts_in ? G.q0 : G.c0) * sz;
+    a.out = (char*)out + (pts_out ? G.q0 : G.c0) * sz;
+    a.fac = fac + G.f0 * sz;
+    a.lam = lam ? lam + G.e0 : nullptr;
+    a.lam0 = lam0;
+    a.in2 = in2 ? in2 + G.q0 * d : nullptr;
+    a.tile = cur_tile(op, d, G.P, t);
+    a.stream = st;
+    hipError_t e = launch_op(d, t, a);
+    if (e != hipSuccess) return hip_fail(e, "operator launch");
+  }
+  return NK_OK;
+}
+
+nk_status nk_bwd_trans(nk_space s, nk_dtype t, const void* coeffs, void* phys, void* stream) {
+  return space_op(s, OP_BWD, t, coeffs, phys, nullptr, 0.0, nullptr, stream);
+}
+
+nk_status nk_iprod_wrt_base(nk_space s, nk_dtype t, const void* phys, void* coeffs, void* stream) {
+  return space_op(s, OP_IPROD, t, phys, coeffs, nullptr, 0.0, nullptr, stream);
+}
+
+nk_status nk_helmholtz(nk_space s, nk_dtype t, const double* lambda, double lambda0, const void* x,
+                       void* y, void* stream) {
+  return space_op(s, OP_HELM, t, x, y, lambda, lambda0, nullptr, stream);
+}
+
+nk_status nk_helmholtz_weak_rhs(nk_space s, const double* lambda, double lambda0, const double* u,
+                                const double* du, double* y, void* stream) {
+  return space_op(s, OP_RHS, NK_F64, u, y, lambda, lambda0, du, stream);
+}
+
+nk_status nk_helmholtz_param_grad(nk_space s, const double* z_loc, const double* u_loc,
+                                  double* dkappa, double* dlambda, void* stream) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (s->groups.size() != 1) return fail(NK_EINVAL, "gradient needs a single-order space");
+  NK_CHECK(check_buf(z_loc, s->ncoeff * 8, "z_loc"));
+  NK_CHECK(check_buf(u_loc, s->ncoeff * 8, "u_loc"));
+  if (dkappa) NK_CHECK(check_buf(dkappa, s->npoint * 8, "dkappa"));
+  if (dlambda) NK_CHECK(check_buf(dlambda, s->nelem * 8, "dlambda"));
+  const Group& G = s->groups[0];
+  OpArgs a;
+  a.op = OP_GRAD;
+  a.dim = s->dim;
+  a.P = G.P;
+  a.Q = G.Q;
+  a.nelem = G.nelem;
+  a.in = z_loc;
+  a.in2 = u_loc;
+  a.out = dkappa;
+  a.out2 = dlambda;
+  a.fac = s->fac64;
+  a.kappa = s->kappa;
+  a.stream = (hipStream_t)stream;
+  hipError_t e = launch_op(s->dim, NK_F64, a);
+  if (e != hipSuccess) return hip_fail(e, "gradient launch");
+  return NK_OK;
+}
+
+// ================================================================ systems
+static void system_free(nk_system y) {
+  if (!y) return;
+  if (y->cs) (void)hipStreamSynchronize(y->cs);
+  if (y->g64) (void)hipGraphExecDestroy(y->g64);
+  if (y->g32) (void)hipGraphExecDestroy(y->g32);
+  dfree(y->d_dof_off);
+  dfree(y->d_pdof_off);
+  dfree(y->d_elem_off);
+  dfree(y->d_blk_first);
+  dfree(y->d_blk_seg);
+  dfree(y->elem_seg);
+  dfree(y->l2g);
+  dfree(y->lam);
+  dfree(y->diag);
+  dfree(y->dinv64);
+  dfree(y->dinv32);
+  dfree(y->b);
+  dfree(y->x);
+  dfree(y->r);
+  dfree(y->p);
+  dfree(y->y);
+  dfree(y->r32);
+  dfree(y->p32);
+  dfree(y->y32);
+  dfree(y->d32);
+  dfree(y->dots);
+  dfree(y->part);
+  for (CgState* c : {&y->st64, &y->st32}) {
+    dfree(c->rz);
+    dfree(c->rr);
+    dfree(c->tol2);
+    dfree(c->alpha);
+    dfree(c->beta);
+    dfree(c->done);
+    dfree(c->iters);
+    dfree(c->status);
+    dfree(c->cnt);
+  }
+  dfree(y->bb);
+  dfree(y->rr_true);
+  dfree(y->cnt_aux);
+  dfree(y->outer_done);
+  dfree(y->outer_tol2);
+  dfree(y->outer_rr);
+  dfree(y->outer_cnt);
+  dfree(y->outer_status);
+  if (y->h_flags) (void)hipHostFree(y->h_flags);
+  if (y->h_d) (void)hipHostFree(y->h_d);
+  if (y->ev) (void)hipEventDestroy(y->ev);
+  if (y->cs) (void)hipStreamDestroy(y->cs);
+  delete y;
+}
+
+static hipError_t alloc_state(CgState& c, int n) {
+  hipError_t e;
+  if ((e = dmalloc(&c.rz, n)) || (e = dmalloc(&c.rr, n)) || (e = dmalloc(&c.tol2, n)) ||
+      (e = dmalloc(&c.alpha, n)) || (e = dmalloc(&c.beta, n)) || (e = dmalloc(&c.done, n)) ||
+      (e = dmalloc(&c.iters, n)) || (e = dmalloc(&c.status, n)) || (e = dmalloc(&c.cnt, n)))
+    return e;
+  return hipMemset(c.cnt, 0, n * sizeof(int32_t));
+}
+
+nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
+                                   const int64_t* dof_off, const int32_t* l2g,
+                                   const uint8_t* dirichlet, const double* lambda, double lambda0,
+                                   void* stream) {
+  if (!out) return fail(NK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (s->groups.size() != 1) return fail(NK_EINVAL, "systems need a single-order space");
+  if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
+  if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
+  if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
+    return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");
+  if (dof_off[0] != 0) return fail(NK_EINVAL, "dof_off must start at 0");
+  for (int k = 0; k < nsys; ++k) {
+    if (elem_off[k + 1] < elem_off[k] || dof_off[k + 1] < dof_off[k])
+      return fail(NK_EINVAL, "offsets must be non-decreasing");
+  }
+  if (dof_off[nsys] >= ((int64_t)1 << 30)) return fail(NK_EINVAL, "too many global DOFs");
+  const Group& G = s->groups[0];
+  const int nloc = (int)ipow(G.n, s->dim);
+  NK_CHECK(check_buf(l2g, (size_t)s->nelem * nloc * 4, "l2g"));
+  NK_CHECK(check_buf(dirichlet, (size_t)dof_off[nsys], "dirichlet"));
+  if (lambda) NK_CHECK(check_buf(lambda, s->nelem * 8, "lambda"));
+  NK_CHECK(check_device());
+  hipStream_t st = (hipStream_t)stream;
+  nk_system y = new nk_system_s();
+  y->space = s;
+  y->nsys = nsys;
+  y->lam0 = lambda0;
+  (void)hipGetDevice(&y->device);
+  y->dof_off.assign(dof_off, dof_off + nsys + 1);
+  y->elem_off.assign(elem_off, elem_off + nsys + 1);
+  y->nuser = dof_off[nsys];
+  y->pdof_off.assign(nsys + 1, 0);
+  y->blk_first.assign(nsys + 1, 0);
+  for (int k = 0; k < nsys; ++k) {
+    const int64_t nd = std::max<int64_t>(dof_off[k + 1] - dof_off[k], 1);
+    const int64_t padded = (nd + kSegAlign - 1) / kSegAlign * kSegAlign;
+    y->pdof_off[k + 1] = y->pdof_off[k] + padded;
+    y->blk_first[k + 1] = y->pdof_off[k + 1] / kSegAlign;
+  }
+  y->L.npad = y->pdof_off[nsys];
+  y->L.nblk = y->L.npad / kSegAlign;
+  if (y->L.npad >= ((int64_t)1 << 31) - 1) {
+    system_free(y);
+    return fail(NK_EINVAL, "padded system too large");
+  }
+  std::vector<int32_t> blk_seg(y->L.nblk), eseg(s->nelem);
+  for (int k = 0; k < nsys; ++k) {
+    for (int64_t b = y->blk_first[k]; b < y->blk_first[k + 1]; ++b) blk_seg[b] = k;
+    for (int64_t e = elem_off[k]; e < elem_off[k + 1]; ++e) eseg[e] = k;
+  }
+  auto cleanup = [&](nk_status stt) {
+    system_free(y);
+    return stt;
+  };
+  hipError_t e = hipSuccess;
+  const int64_t np = y->L.npad;
+#define NK_ALLOC(ptr, n) \
+  if ((e = dmalloc(&(ptr), (n))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"))
+  NK_ALLOC(y->d_dof_off, nsys + 1);
+  NK_ALLOC(y->d_pdof_off, nsys + 1);
+  NK_ALLOC(y->d_elem_off, nsys + 1);
+  NK_ALLOC(y->d_blk_first, nsys + 1);
+  NK_ALLOC(y->d_blk_seg, y->L.nblk);
+  NK_ALLOC(y->elem_seg, std::max<int64_t>(s->nelem, 1));
+  NK_ALLOC(y->l2g, std::max<int64_t>(s->nelem * nloc, 1));
+  if (lambda) NK_ALLOC(y->lam, s->nelem);
+  NK_ALLOC(y->diag, np);
+  NK_ALLOC(y->dinv64, np);
+  NK_ALLOC(y->dinv32, np);
+  NK_ALLOC(y->b, np);
+  NK_ALLOC(y->x, np);
+  NK_ALLOC(y->r, np);
+  NK_ALLOC(y->p, np);
+  NK_ALLOC(y->y, np);
+  NK_ALLOC(y->r32, np);
+  NK_ALLOC(y->p32, np);
+  NK_ALLOC(y->y32, np);
+  NK_ALLOC(y->d32, np);
+  NK_ALLOC(y->dots, std::max<int64_t>(s->nelem, 1));
+  NK_ALLOC(y->part, 2 * y->L.nblk);
+  NK_ALLOC(y->bb, nsys);
+  NK_ALLOC(y->rr_true, nsys);
+  NK_ALLOC(y->cnt_aux, nsys);
+  NK_ALLOC(y->outer_done, nsys);
+  NK_ALLOC(y->outer_tol2, nsys);
+  NK_ALLOC(y->outer_rr, nsys);
+  NK_ALLOC(y->outer_cnt, nsys);
+  NK_ALLOC(y->outer_status, nsys);
+#undef NK_ALLOC
+  if ((e = alloc_state(y->st64, nsys)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = alloc_state(y->st32, nsys)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipHostMalloc((void**)&y->h_flags, nsys * sizeof(int32_t), 0)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostMalloc"));
+  if ((e = hipHostMalloc((void**)&y->h_d, nsys * sizeof(double), 0)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostMalloc"));
+  if ((e = hipStreamCreateWithFlags(&y->cs, hipStreamNonBlocking)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipStreamCreate"));
+  if ((e = hipEventCreateWithFlags(&y->ev, hipEventDisableTiming)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipEventCreate"));
+  y->L.blk_seg = y->d_blk_seg;
+  y->L.blk_first = y->d_blk_first;
+  // setup runs on the caller's stream, then synchronises it
+  int* d_bad = nullptr;
+  double *d_B = nullptr, *d_D = nullptr;
+  const int QN = G.Q * G.n;
+  if ((e = dmalloc(&d_bad, 1)) || (e = dmalloc(&d_B, QN)) || (e = dmalloc(&d_D, QN))) {
+    dfree(d_bad);
+    dfree(d_B);
+    dfree(d_D);
+    return cleanup(hip_fail(e, "hipMalloc"));
+  }
+  std::vector<double> xq(G.Q), wq(G.Q), hB(QN), hD(QN);
+  gll_points(G.Q, xq.data(), wq.data());
+  modified_basis(G.P, G.Q, xq.data(), hB.data(), hD.data());
+  do {
+    if ((e = hipMemcpyAsync(y->d_dof_off, dof_off, (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(y->d_pdof_off, y->pdof_off.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(y->d_elem_off, elem_off, (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(y->d_blk_first, y->blk_first.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(y->d_blk_seg, blk_seg.data(), y->L.nblk * 4, hipMemcpyHostToDevice, st))) break;
+    if (s->nelem > 0 &&
+        (e = hipMemcpyAsync(y->elem_seg, eseg.data(), s->nelem * 4, hipMemcpyHostToDevice, st))) break;
+    if (lambda && (e = hipMemcpyAsync(y->lam, lambda, s->nelem * 8, hipMemcpyDeviceToDevice, st))) break;
+    if ((e = hipMemcpyAsync(d_B, hB.data(), QN * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(d_D, hD.data(), QN * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemsetAsync(d_bad, 0, 4, st))) break;
+    if ((e = build_l2g(s->nelem, nloc, y->elem_seg, y->d_dof_off, y->d_pdof_off, l2g, dirichlet,
+                       y->l2g, d_bad, st)))
+      break;
+    if ((e = vec_fill<double>(y->diag, np, 0.0, st))) break;
+    if ((e = launch_diag(s->dim, G.P, G.Q, s->nelem, d_B, d_D, s->fac64, y->lam, y->lam0, y->l2g,
+                         y->diag, st)))
+      break;
+    if ((e = diag_finish(y->L, y->diag, y->dinv64, y->dinv32, y->diag, st))) break;
+    for (double* v : {y->b, y->x, y->r, y->p, y->y})
+      if ((e = vec_fill<double>(v, np, 0.0, st))) break;
+    for (float* v : {y->r32, y->p32, y->y32, y->d32})
+      if ((e = vec_fill<float>(v, np, 0.f, st))) break;
+    if ((e = vec_fill<int32_t>(y->outer_cnt, nsys, 0, st))) break;
+    if ((e = vec_fill<int32_t>(y->cnt_aux, nsys, 0, st))) break;
+    e = hipStreamSynchronize(st);
+  } while (0);
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, 4, hipMemcpyDeviceToHost);
+  dfree(d_bad);
+  dfree(d_B);
+  dfree(d_D);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "system setup"));
+  if (bad) return cleanup(fail(NK_EINVAL, "l2g index outside its system's DOF range"));
+  y->tile64 = cur_tile(OP_HELM_ASM, s->dim, G.P, NK_F64);
+  y->tile32 = cur_tile(OP_HELM_ASM, s->dim, G.P, NK_F32);
+  *out = y;
+  return NK_OK;
+}
+
+nk_status nk_system_create(nk_system* out, nk_space s, int64_t nglobal, const int32_t* l2g,
+                           const uint8_t* dirichlet, const double* lambda, double lambda0,
+                           void* stream) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (nglobal < 1) return fail(NK_EINVAL, "nglobal must be >= 1");
+  const int64_t eo[2] = {0, s->nelem};
+  const int64_t dofo[2] = {0, nglobal};
+  return nk_system_create_batched(out, s, 1, eo, dofo, l2g, dirichlet, lambda, lambda0, stream);
+}
+
+nk_status nk_system_destroy(nk_system sys) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  system_free(sys);
+  return NK_OK;
+}
+
+// y (padded) += A x (padded) over all elements; dots per element if requested.
+static hipError_t sys_op(nk_system y, nk_dtype t, const void* x, void* out, double* dots,
+                         const int32_t* seg_done, int tile, hipStream_t st) {
+  nk_space s = y->space;
+  const Group& G = s->groups[0];
+  OpArgs a;
+  a.op = OP_HELM_ASM;
+  a.dim = s->dim;
+  a.P = G.P;
+  a.Q = G.Q;
+  a.nelem = G.nelem;
+  a.in = x;
+  a.out = out;
+  a.fac = t == NK_F64 ? (const void*)s->fac64 : (const void*)s->fac32;
+  a.lam = y->lam;
+  a.lam0 = y->lam0;
+  a.l2g = y->l2g;
+  a.dots = dots;
+  a.elem_seg = seg_done ? y->elem_seg : nullptr;
+  a.seg_done = seg_done;
+  a.tile = tile;
+  a.stream = st;
+  return launch_op(s->dim, t, a);
+}
+
+nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* yv, void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
+  NK_CHECK(check_buf(x, sys->nuser * dsize(t), "x"));
+  NK_CHECK(check_buf(yv, sys->nuser * dsize(t), "y"));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = sys->L.npad;
+  hipError_t e;
+  if (t == NK_F64) {
+    if ((e = pad_in<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, (const double*)x,
+                            sys->dinv64, sys->p, st)) ||
+        (e = vec_fill<double>(sys->y, np, 0.0, st)) ||
+        (e = sys_op(sys, t, sys->p, sys->y, nullptr, nullptr, sys->tile64, st)) ||
+        (e = pad_out<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->y,
+                             (double*)yv, st)))
+      return hip_fail(e, "system apply");
+  } else {
+    if ((e = pad_in<float>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, (const float*)x,
+                           sys->dinv64, sys->p32, st)) ||
+        (e = vec_fill<float>(sys->y32, np, 0.f, st)) ||
+        (e = sys_op(sys, t, sys->p32, sys->y32, nullptr, nullptr, sys->tile32, st)) ||
+        (e = pad_out<float>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->y32,
+                            (float*)yv, st)))
+      return hip_fail(e, "system apply");
+  }
+  // the padded work vectors are shared with solves on the system's own stream
+  if ((e = hipStreamSynchronize(st))) return hip_fail(e, "system apply");
+  return NK_OK;
+}
+
+nk_status nk_assemble(nk_system sys, const double* y_loc, double* b, void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  nk_space s = sys->space;
+  const int nloc = (int)ipow(s->groups[0].n, s->dim);
+  NK_CHECK(check_buf(y_loc, (size_t)s->nelem * nloc * 8, "y_loc"));
+  NK_CHECK(check_buf(b, sys->nuser * 8, "b"));
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = vec_fill<double>(sys->y, sys->L.npad, 0.0, st)) ||
+      (e = scatter_add(s->nelem, nloc, sys->l2g, y_loc, sys->y, st)) ||
+      (e = pad_out<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->y, b, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "assemble");
+  return NK_OK;
+}
+
+nk_status nk_gather(nk_system sys, const double* x, double* x_loc, void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  nk_space s = sys->space;
+  const int nloc = (int)ipow(s->groups[0].n, s->dim);
+  NK_CHECK(check_buf(x, sys->nuser * 8, "x"));
+  NK_CHECK(check_buf(x_loc, (size_t)s->nelem * nloc * 8, "x_loc"));
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  // Dirichlet entries are gathered as they are (not masked): the reported
+  // diagonal is positive on every row, so it serves as an all-pass mask.
+  if ((e = pad_in<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, x, sys->diag,
+                          sys->p, st)) ||
+      (e = gather_user(s->nelem, nloc, sys->l2g, sys->p, x_loc, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "gather");
+  return NK_OK;
+}
+
+nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  NK_CHECK(check_buf(diag, sys->nuser * 8, "diag"));
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = pad_out<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->diag, diag,
+                           st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "diagonal");
+  return NK_OK;
+}
+
+// ------------------------------------------------------------------ solve
+static int graph_iters() {
+  const char* v = std::getenv("NK_GRAPH_ITERS");
+  const int k = v ? std::atoi(v) : 16;
+  return std::min(std::max(k, 1), 256);
+}
+
+static double inner_tol() {
+  const char* v = std::getenv("NK_INNER_TOL");
+  const double t = v ? std::atof(v) : 1e-4;
+  return (t > 0.0 && t < 1.0) ? t : 1e-4;
+}
+
+// One CG iteration of precision T on the system's stream.
+template <typename T>
+static hipError_t cg_iteration(nk_system y, int maxit) {
+  const bool f64 = std::is_same<T, double>::value;
+  CgState& st = f64 ? y->st64 : y->st32;
+  T* r = f64 ? (T*)y->r : (T*)y->r32;
+  T* p = f64 ? (T*)y->p : (T*)y->p32;
+  T* yy = f64 ? (T*)y->y : (T*)y->y32;
+  T* x = f64 ? (T*)y->x : (T*)y->d32;
+  const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
+  hipError_t e;
+  if ((e = cg_p_update<T>(y->L, st, r, dinv, p, y->cs))) return e;
+  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, p, yy, y->dots, st.done, f64 ? y->tile64 : y->tile32,
+                  y->cs)))
+    return e;
+  if ((e = cg_alpha<T>(y->nsys, y->d_elem_off, y->dots, st, f64, y->cs))) return e;
+  return cg_update<T>(y->L, st, maxit, x, r, p, yy, dinv, y->part, y->cs);
+}
+
+template <typename T>
+static hipError_t ensure_graph(nk_system y, int maxit) {
+  const bool f64 = std::is_same<T, double>::value;
+  hipGraphExec_t& ge = f64 ? y->g64 : y->g32;
+  int& gi = f64 ? y->g64_iters : y->g32_iters;
+  int& gm = f64 ? y->g_maxit64 : y->g_maxit32;
+  const int k = graph_iters();
+  if (ge && gi == k && gm == maxit) return hipSuccess;
+  if (ge) {
+    (void)hipGraphExecDestroy(ge);
+    ge = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(y->cs, hipStreamCaptureModeThreadLocal);
+  if (e) return e;
+  hipError_t e2 = hipSuccess;
+  for (int i = 0; i < k && e2 == hipSuccess; ++i) e2 = cg_iteration<T>(y, maxit);
+  e = hipStreamEndCapture(y->cs, &g);
+  if (e2) {
+    if (g) (void)hipGraphDestroy(g);
+    return e2;
+  }
+  if (e) return e;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e) return e;
+  gi = k;
+  gm = maxit;
+  return hipSuccess;
+}
+
+// Run graph launches of CG iterations until every system reports done.
+template <typename T>
+static hipError_t cg_loop(nk_system y, int maxit, const int32_t* done_dev) {
+  hipError_t e = ensure_graph<T>(y, maxit);
+  if (e) return e;
+  const hipGraphExec_t ge = std::is_same<T, double>::value ? y->g64 : y->g32;
+  const int k = std::is_same<T, double>::value ? y->g64_iters : y->g32_iters;
+  const int64_t max_launch = (int64_t)maxit / k + 2;
+  for (int64_t l = 0; l < max_launch; ++l) {
+    if ((e = hipGraphLaunch(ge, y->cs))) return e;
+    if ((e = hipMemcpyAsync(y->h_flags, done_dev, y->nsys * 4, hipMemcpyDeviceToHost, y->cs)))
+      return e;
+    if ((e = hipStreamSynchronize(y->cs))) return e;
+    bool all = true;
+    for (int i = 0; i < y->nsys; ++i) all = all && y->h_flags[i] != 0;
+    if (all) break;
+  }
+  return hipSuccess;
+}
+
+nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* x, double rtol,
+                      int maxit, nk_solve_info* info, void* stream) {
+  if (!y) return fail(NK_EINVAL, "system is NULL");
+  if (mode != NK_SOLVE_F64 && mode != NK_SOLVE_F32_REFINED) return fail(NK_EINVAL, "bad mode");
+  if (!(rtol > 0.0) || rtol >= 1.0) return fail(NK_EINVAL, "rtol must be in (0, 1)");
+  if (maxit < 1) return fail(NK_EINVAL, "maxit must be >= 1");
+  NK_CHECK(check_buf(b, y->nuser * 8, "b"));
+  NK_CHECK(check_buf(x, y->nuser * 8, "x"));
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t us = (hipStream_t)stream;
+  hipStream_t cs = y->cs;
+  const int ns = y->nsys;
+  const int64_t np = y->L.npad;
+  std::vector<int> iters(ns, 0), outer(ns, 0);
+  hipError_t e = hipSuccess;
+  // order the private stream after the caller's work
+  if ((e = hipEventRecord(y->ev, us)) || (e = hipStreamWaitEvent(cs, y->ev, 0)))
+    return hip_fail(e, "stream ordering");
+  CgState outer_st;
+  outer_st.rr = y->outer_rr;
+  outer_st.tol2 = y->outer_tol2;
+  outer_st.done = y->outer_done;
+  outer_st.status = y->outer_status;
+  outer_st.cnt = y->outer_cnt;
+  do {
+    if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, b, y->dinv64, y->b, cs))) break;
+    if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, x, y->dinv64, y->x, cs))) break;
+    if (mode == NK_SOLVE_F64) {
+      if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->st64.tol2, cs))) break;
+      if ((e = vec_fill<int32_t>(y->st64.status, ns, 0, cs))) break;
+      if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
+      if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
+      if ((e = cg_residual(y->L, y->st64, y->b, y->y, y->dinv64, y->r, y->p, y->part, cs))) break;
+      if ((e = cg_loop<double>(y, maxit, y->st64.done))) break;
+      if ((e = hipMemcpyAsync(y->h_flags, y->st64.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
+      if ((e = hipStreamSynchronize(cs))) break;
+      for (int i = 0; i < ns; ++i) iters[i] = y->h_flags[i];
+    } else {
+      // FP64 outer refinement around an FP32 inner CG
+      if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->outer_tol2, cs))) break;
+      if ((e = vec_fill<int32_t>(y->outer_status, ns, 0, cs))) break;
+      if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
+      const double tau = inner_tol();
+      const int max_outer = 60;
+      int k = 0;
+      for (; k < max_outer; ++k) {
+        if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
+        if ((e = cg_residual(y->L, outer_st, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs)))
+          break;
+        if ((e = hipMemcpyAsync(y->h_flags, y->outer_done, ns * 4, hipMemcpyDeviceToHost, cs))) break;
+        if ((e = hipStreamSynchronize(cs))) break;
+        bool all = true;
+        for (int i = 0; i < ns; ++i) {
+          all = all && y->h_flags[i] != 0;
+          if (!y->h_flags[i]) outer[i] += 1;
+        }
+        if (all) break;
+        if ((e = cg_inner_init(y->L, y->st32, y->outer_done, tau, y->r, y->dinv32, y->r32, y->d32,
+                               y->p32, y->y32, y->part, cs)))
+          break;
+        if ((e = cg_loop<float>(y, maxit, y->st32.done))) break;
+        if ((e = hipMemcpyAsync(y->h_flags, y->st32.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
+        if ((e = hipStreamSynchronize(cs))) break;
+        for (int i = 0; i < ns; ++i) iters[i] += y->h_flags[i];
+        if ((e = cg_correct(y->L, y->outer_done, y->d32, y->x, cs))) break;
+      }
+      if (e) break;
+      if (k == max_outer) {
+        // mark systems that never reached the tolerance
+        if ((e = hipMemcpyAsync(y->h_flags, y->outer_done, ns * 4, hipMemcpyDeviceToHost, cs))) break;
+        if ((e = hipStreamSynchronize(cs))) break;
+      }
+    }
+    // true residual in FP64
+    CgState chk;
+    chk.rr = y->rr_true;
+    chk.tol2 = y->outer_tol2;
+    chk.cnt = y->cnt_aux;
+    if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
+    if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
+    if ((e = cg_residual(y->L, chk, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs))) break;
+    if ((e = pad_out<double>(ns, y->d_dof_off, y->d_pdof_off, y->nuser, y->x, x, cs))) break;
+    if ((e = hipEventRecord(y->ev, cs)) || (e = hipStreamWaitEvent(us, y->ev, 0))) break;
+    e = hipStreamSynchronize(cs);
+  } while (0);
+  if (e != hipSuccess) return hip_fail(e, "cg solve");
+  // collect per-system results
+  std::vector<double> rr(ns), bbv(ns);
+  std::vector<int32_t> stat(ns);
+  if ((e = hipMemcpy(rr.data(), y->rr_true, ns * 8, hipMemcpyDeviceToHost)) ||
+      (e = hipMemcpy(bbv.data(), y->bb, ns * 8, hipMemcpyDeviceToHost)) ||
+      (e = hipMemcpy(stat.data(), mode == NK_SOLVE_F64 ? y->st64.status : y->outer_status, ns * 4,
+                     hipMemcpyDeviceToHost)))
+    return hip_fail(e, "cg solve");
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  nk_status worst = NK_OK;
+  for (int i = 0; i < ns; ++i) {
+    const double rel = bbv[i] > 0.0 ? std::sqrt(rr[i] / bbv[i]) : std::sqrt(rr[i]);
+    int sti = stat[i];
+    if (sti == NK_OK && mode == NK_SOLVE_F32_REFINED && !(rel <= rtol * 1.0000001)) sti = NK_ENOCONV;
+    if (sti == NK_OK && mode == NK_SOLVE_F64 && iters[i] >= maxit && !(rel <= rtol)) sti = NK_ENOCONV;
+    if (info) {
+      info[i].iters = iters[i];
+      info[i].outer_iters = mode == NK_SOLVE_F32_REFINED ? outer[i] : 0;
+      info[i].rel_resid = rel;
+      info[i].solve_ms = ms;
+      info[i].status = sti;
+    }
+    if (sti != NK_OK && worst == NK_OK) worst = (nk_status)sti;
+  }
+  if (worst != NK_OK)
+    return fail(worst, worst == NK_EBREAKDOWN ? "CG breakdown" : "CG did not converge");
+  return NK_OK;
+}
+
+// --------------------------------------------------------------- autotune
+static std::mutex g_tune_mu;
+
+static std::string device_name() {
+  hipDeviceProp_t p;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string n = p.gcnArchName;
+  for (char& c : n)
+    if (c == ' ' || c == ':') c = '_';
+  return n;
+}
+
+static bool cache_lookup(const std::string& key, int* tile) {
+  const char* path = std::getenv("NK_AUTOTUNE_CACHE");
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line, k;
+  int t = -1;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    if (is >> k >> t && k == key) {
+      *tile = t;
+      found = true;
+    }
+  }
+  return found;
+}
+
+static void cache_store(const std::string& key, int tile, double us) {
+  const char* path = std::getenv("NK_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << tile << " " << us << "\n";
+}
+
+nk_status nk_autotune(nk_space s, int op_mask, void* stream) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  NK_CHECK(check_device());
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  hipStream_t st = (hipStream_t)stream;
+  const std::string dev = device_name();
+  // scratch operands large enough for every op of the space
+  const int64_t big = std::max(s->ncoeff, s->npoint);
+  double *a = nullptr, *b = nullptr;
+  hipError_t e;
+  if ((e = dmalloc(&a, std::max<int64_t>(big, 1))) || (e = dmalloc(&b, std::max<int64_t>(big, 1)))) {
+    dfree(a);
+    dfree(b);
+    return hip_fail(e, "hipMalloc");
+  }
+  (void)vec_fill<double>(a, big, 0.5, st);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  nk_status result = NK_OK;
+  for (const Group& G : s->groups) {
+    if (G.nelem == 0) continue;
+    for (int op = 0; op <= OP_HELM && result == NK_OK; ++op) {
+      if (!(op_mask >> op & 1)) continue;
+      for (nk_dtype t : {NK_F64, NK_F32}) {
+        const int nt = tile_count(op, s->dim, G.P);
+        std::string key = "op" + std::to_string(op) + "_d" + std::to_string(s->dim) + "_P" +
+                          std::to_string(G.P) + "_Q" + std::to_string(G.Q) + "_" +
+                          (t == NK_F64 ? "f64" : "f32") + "_" + dev;
+        int best = 0;
+        if (nt > 1 && !cache_lookup(key, &best)) {
+          double best_us = 1e30;
+          for (int k = 0; k < nt; ++k) {
+            OpArgs o;
+            o.op = op;
+            o.dim = s->dim;
+            o.P = G.P;
+            o.Q = G.Q;
+            o.nelem = G.nelem;
+            o.in = a;
+            o.out = b;
+            o.fac = t == NK_F64 ? (const void*)(s->fac64 + G.f0) : (const void*)(s->fac32 + G.f0);
+            o.lam0 = 1.0;
+            o.tile = k;
+            o.stream = st;
+            for (int w = 0; w < 2; ++w) e = launch_op(s->dim, t, o);
+            const int reps = 5;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_op(s->dim, t, o);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            if (e != hipSuccess) {
+              result = hip_fail(e, "autotune launch");
+              break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1000.0 * ms / reps;
+            if (us < best_us) {
+              best_us = us;
+              best = k;
+            }
+          }
+          if (result == NK_OK) cache_store(key, best, best_us);
+        }
+        if (result == NK_OK) {
+          (void)cur_tile(op, s->dim, G.P, t);  // runs the one-time default initialisation
+          g_tile[op][s->dim - 2][G.P][t].store(best);
+        }
+      }
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dfree(a);
+  dfree(b);
+  return result;
+}
+
+nk_status nk_set_tile_config(int op, int dim, int P, nk_dtype t, int tile) {
+  if (op < 0 || op > OP_HELM || (dim != 2 && dim != 3) || P < kMinP || P > kMaxP ||
+      (t != NK_F64 && t != NK_F32))
+    return fail(NK_EINVAL, "bad operator, dimension, order or dtype");
+  if (tile < 0 || tile >= tile_count(op, dim, P)) return fail(NK_EINVAL, "tile index out of range");
+  (void)cur_tile(op, dim, P, t);
+  g_tile[op][dim - 2][P][t].store(tile);
+  return NK_OK;
+}
+
+int nk_tile_count(int op, int dim, int P) {
+  if (op < 0 || op >= OP_COUNT || (dim != 2 && dim != 3)) return 0;
+  return tile_count(op, dim, P);
+}
+
+const char* nk_tile_config(int op, int dim, int P, nk_dtype t) {
+  if (op < 0 || op >= OP_COUNT || (dim != 2 && dim != 3) || P < kMinP || P > kMaxP) return "";
+  return tile_name(op, dim, P, cur_tile(op, dim, P, t));
+}

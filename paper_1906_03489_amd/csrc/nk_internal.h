@@ -1,0 +1,143 @@
+// Internal declarations shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nk.h"
+
+namespace nk {
+
+// ------------------------------------------------------------------ limits
+constexpr int kMinP = 1;
+constexpr int kMaxP = 10;          // n = P+1 <= 11, Q = P+2 <= 12
+constexpr int kNF3 = 7;            // per-point factors in 3-D
+constexpr int kNF2 = 4;            // per-point factors in 2-D
+constexpr int kVecBlock = 256;     // threads per block of the CG vector kernels
+constexpr int64_t kSegAlign = 1024;  // batched systems: DOF ranges padded to this
+
+// ------------------------------------------------------------ host tables
+void gll_points(int Q, double* x, double* w);
+void modified_basis(int P, int Q, const double* x, double* B, double* DB);
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+nk_status fail(nk_status st, const std::string& msg);
+nk_status hip_fail(hipError_t e, const char* what);
+
+#define NK_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return ::nk::hip_fail(e_, #call); \
+  } while (0)
+
+// ------------------------------------------------------------- operators
+enum OpKind : int {
+  OP_BWD = 0,        // coeffs -> point values
+  OP_IPROD = 1,      // point values -> coeffs (w detJ weighted)
+  OP_HELM = 2,       // local Helmholtz
+  OP_HELM_ASM = 3,   // gather -> Helmholtz -> scatter-add, per-element p.Ap
+  OP_RHS = 4,        // weak Helmholtz form of a point field (FP64)
+  OP_GRAD = 5,       // adjoint parameter gradient (FP64)
+  OP_DIAG = 6,       // elemental Helmholtz diagonal scattered to global (FP64)
+  OP_COUNT = 7
+};
+
+// Everything one operator launch needs; pointers are device pointers of the
+// element group being processed (already offset to the group's start).
+struct OpArgs {
+  int op = 0;
+  int dim = 3, P = 0, Q = 0;
+  int64_t nelem = 0;
+  const void* in = nullptr;     // coefficients or point values (dtype)
+  void* out = nullptr;          // point values, coefficients, or global y (dtype)
+  const void* fac = nullptr;    // geometric factors (dtype)
+  const double* lam = nullptr;  // per-element lambda or null
+  double lam0 = 0.0;
+  const int32_t* l2g = nullptr; // signed local-to-global (assembled ops): -1-g marks Dirichlet
+  double* dots = nullptr;       // per-element p_e . (H_e p_e) (assembled ops)
+  const double* in2 = nullptr;  // RHS: reference gradient; GRAD: u_loc
+  double* out2 = nullptr;       // GRAD: dlambda; DIAG: unused
+  const double* kappa = nullptr;  // GRAD: kappa per point (null = 1)
+  const int32_t* elem_seg = nullptr;  // batched: segment of each element
+  const int32_t* seg_done = nullptr;  // batched: converged flag per segment
+  int tile = 0;                 // tile configuration index
+  hipStream_t stream = nullptr;
+};
+
+// Number of compiled tile configurations for an operator and its names.
+int tile_count(int op, int dim, int P);
+const char* tile_name(int op, int dim, int P, int tile);
+
+// Launch one operator on one element group.  Returns hipErrorInvalidValue
+// for (dim, P) combinations that are not compiled.
+hipError_t launch_op3(nk_dtype t, const OpArgs& a);
+hipError_t launch_op2(nk_dtype t, const OpArgs& a);
+bool op_supported(int dim, int P, int Q);
+
+// Mixed-order Helmholtz: all groups in one persistent launch.
+struct VarpGroup {
+  int P = 0;
+  int64_t nelem = 0, c0 = 0, f0 = 0;   // coefficient / factor offsets (elements of scalars)
+};
+struct VarpArgs {
+  nk_dtype t = NK_F64;
+  int ngroups = 0;
+  const VarpGroup* groups_dev = nullptr;   // device array of groups
+  const int64_t* item_start_dev = nullptr; // device prefix sum of work items per group
+  int64_t nitems = 0;
+  const void* x = nullptr;
+  void* y = nullptr;
+  const void* fac = nullptr;
+  const double* lam = nullptr;  // per element over the concatenated elements, or null
+  const int64_t* lam_off_dev = nullptr;    // element offset of each group
+  double lam0 = 0.0;
+  int grid = 0;
+  hipStream_t stream = nullptr;
+};
+hipError_t launch_helm_varp(const VarpArgs& a);
+int varp_items_per_group(int P, int64_t nelem);   // work items of one group
+int varp_blocks_per_cu(nk_dtype t);
+
+// One entry point per compiled order set (objects built from ops3d_inst.hip).
+hipError_t launch_op3_set0(nk_dtype t, const OpArgs& a);
+hipError_t launch_op3_set1(nk_dtype t, const OpArgs& a);
+hipError_t launch_op3_set2(nk_dtype t, const OpArgs& a);
+hipError_t launch_op3_set3(nk_dtype t, const OpArgs& a);
+hipError_t launch_op3_set4(nk_dtype t, const OpArgs& a);
+hipError_t launch_op3_set5(nk_dtype t, const OpArgs& a);
+hipError_t launch_op3_set6(nk_dtype t, const OpArgs& a);
+
+// Geometry: per-point factors from Jacobians.
+hipError_t launch_geom(int dim, int Q, int64_t nelem, const double* jac, const double* kappa,
+                       const double* wq, double* fac64, float* fac32, int* bad, hipStream_t s);
+
+// ------------------------------------------------------------------- space
+struct Group {
+  int P = 0, Q = 0, n = 0;
+  int64_t nelem = 0;
+  int64_t e0 = 0;   // first element (global element index)
+  int64_t c0 = 0;   // first coefficient
+  int64_t q0 = 0;   // first point value
+  int64_t f0 = 0;   // first factor entry
+};
+
+}  // namespace nk
+
+struct nk_space_s {
+  int dim = 3;
+  int device = 0;
+  std::vector<nk::Group> groups;
+  int64_t nelem = 0, ncoeff = 0, npoint = 0, nfac = 0;
+  double* fac64 = nullptr;
+  float* fac32 = nullptr;
+  double* kappa = nullptr;   // copy of kappa per point (null = 1)
+  // variable-order persistent launch tables
+  nk::VarpGroup* varp_groups = nullptr;
+  int64_t* varp_item_start = nullptr;
+  int64_t* varp_lam_off = nullptr;
+  int64_t varp_nitems = 0;
+};

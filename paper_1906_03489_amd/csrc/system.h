@@ -1,0 +1,128 @@
+// Assembled C0 system state and CG solver internals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "nk_internal.h"
+
+namespace nk {
+
+// Per-system CG scalars, structure of arrays over the nsys systems.
+struct CgState {
+  double* rz = nullptr;     // r . z
+  double* rr = nullptr;     // r . r
+  double* tol2 = nullptr;   // stop when rr <= tol2
+  double* alpha = nullptr;
+  double* beta = nullptr;
+  int32_t* done = nullptr;
+  int32_t* iters = nullptr;
+  int32_t* status = nullptr;
+  int32_t* cnt = nullptr;   // finished-block counter of the fused reduction
+};
+
+// Vector-kernel geometry: DOF ranges of every system are padded to multiples
+// of kSegAlign so that each block of a vector kernel belongs to one system.
+struct VecLayout {
+  int64_t npad = 0;          // padded length
+  int64_t nblk = 0;          // npad / kSegAlign
+  const int32_t* blk_seg = nullptr;    // system of each block
+  const int64_t* blk_first = nullptr;  // first block of each system (nsys+1)
+};
+
+// Kernel launchers (cg.hip).
+template <typename T>
+hipError_t cg_p_update(const VecLayout& L, CgState st, const T* r, const T* dinv, T* p,
+                       hipStream_t s);
+template <typename T>
+hipError_t cg_alpha(int nsys, const int64_t* elem_off, const double* dots, CgState st,
+                    bool fatal_breakdown, hipStream_t s);
+template <typename T>
+hipError_t cg_update(const VecLayout& L, CgState st, int maxit, T* x, T* r, const T* p, T* y,
+                     const T* dinv, double* part, hipStream_t s);
+
+// r = (b - y) on free DOFs (dinv > 0), 0 elsewhere; y is reset to 0; optionally
+// p = 0; per system rz = r.dinv.r, rr = r.r; done = rr <= tol2.
+hipError_t cg_residual(const VecLayout& L, CgState st, const double* b, double* y,
+                       const double* dinv, double* r, double* p, double* part, hipStream_t s);
+// per-system squared norm of v into out[s] (and tol2 = rtol^2 * out when tol2 != null)
+hipError_t vec_norm2(const VecLayout& L, const double* v, double* part, int32_t* cnt, double* out,
+                     double rtol, double* tol2, hipStream_t s);
+// inner FP32 start: r32 = r64, d = p = y = 0, rz/rr, tol2 = tau^2 rr, done = outer_done || rr == 0
+hipError_t cg_inner_init(const VecLayout& L, CgState st, const int32_t* outer_done, double tau,
+                         const double* r64, const float* dinv32, float* r32, float* d32,
+                         float* p32, float* y32, double* part, hipStream_t s);
+// x += d on systems not yet converged
+hipError_t cg_correct(const VecLayout& L, const int32_t* outer_done, const float* d32, double* x,
+                      hipStream_t s);
+template <typename T>
+hipError_t vec_fill(T* v, int64_t n, T val, hipStream_t s);
+// padded <-> user layouts (per system contiguous ranges)
+template <typename T>
+hipError_t pad_in(int nsys, const int64_t* dof_off, const int64_t* pdof_off, const VecLayout& L,
+                  const T* user, const double* dinv, T* padded, hipStream_t s);
+template <typename T>
+hipError_t pad_out(int nsys, const int64_t* dof_off, const int64_t* pdof_off, int64_t nuser,
+                   const T* padded, T* user, hipStream_t s);
+hipError_t build_l2g(int64_t nelem, int nloc, const int32_t* elem_seg, const int64_t* dof_off,
+                     const int64_t* pdof_off, const int32_t* l2g_user, const uint8_t* dirichlet,
+                     int32_t* l2g_int, int* bad, hipStream_t s);
+hipError_t diag_finish(const VecLayout& L, const double* diag, double* dinv64, float* dinv32,
+                       double* diag_out, hipStream_t s);
+hipError_t gather_user(int64_t nelem, int nloc, const int32_t* l2g_int, const double* xpad,
+                       double* xloc, hipStream_t s);
+hipError_t scatter_add(int64_t nelem, int nloc, const int32_t* l2g_int, const double* yloc,
+                       double* ypad, hipStream_t s);
+hipError_t cast_copy(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t cast_copy(const float* src, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_diag(int dim, int P, int Q, int64_t nelem, const double* Bt, const double* Dt,
+                       const double* fac, const double* lam, double lam0, const int32_t* l2g,
+                       double* diag, hipStream_t s);
+
+}  // namespace nk
+
+struct nk_system_s {
+  nk_space space = nullptr;
+  int device = 0;
+  int nsys = 1;
+  int64_t nuser = 0;                      // user global length (sum of system DOFs)
+  std::vector<int64_t> dof_off, pdof_off, elem_off, blk_first;
+  nk::VecLayout L;
+  int64_t* d_dof_off = nullptr;
+  int64_t* d_pdof_off = nullptr;
+  int64_t* d_elem_off = nullptr;
+  int64_t* d_blk_first = nullptr;
+  int32_t* d_blk_seg = nullptr;
+  int32_t* elem_seg = nullptr;
+  int32_t* l2g = nullptr;                 // internal signed l2g into the padded numbering
+  double* lam = nullptr;                  // per-element lambda copy (or null)
+  double lam0 = 0.0;
+  double* diag = nullptr;                 // padded, Dirichlet/padding rows = 1
+  double* dinv64 = nullptr;               // 1/diag on free DOFs, 0 elsewhere (doubles as mask)
+  float* dinv32 = nullptr;
+  // work vectors (padded)
+  double *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *y = nullptr;
+  float *r32 = nullptr, *p32 = nullptr, *y32 = nullptr, *d32 = nullptr;
+  double* dots = nullptr;                 // per element
+  double* part = nullptr;                 // per vector block x 2
+  // per-system scalars
+  nk::CgState st64, st32;
+  double* bb = nullptr;                   // ||b||^2
+  double* rr_true = nullptr;
+  int32_t* cnt_aux = nullptr;
+  int32_t* outer_done = nullptr;
+  double* outer_tol2 = nullptr;
+  double* outer_rr = nullptr;
+  int32_t* outer_cnt = nullptr;
+  int32_t* outer_status = nullptr;
+  // host staging (pinned)
+  int32_t* h_flags = nullptr;             // nsys
+  double* h_d = nullptr;                  // nsys
+  hipStream_t cs = nullptr;               // private stream (graphs are captured here)
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t g64 = nullptr, g32 = nullptr;
+  int g64_iters = 0, g32_iters = 0, g_maxit64 = -1, g_maxit32 = -1;
+  int tile64 = 0, tile32 = 0;
+};

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, validates arguments before touching a device, and its host
+basis tables agree with the oracle's.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nk.h")
+
+
+def _lib():
+    from paper_1906_03489_amd import nk
+    return nk, nk.lib()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_and_library_exports_everything():
+    nk, L = _lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(nk.EXPORTS) == names
+
+
+def test_version_and_device_count_never_fail():
+    _, L = _lib()
+    assert L.nk_version() == 10000
+    assert L.nk_device_count() >= 0
+
+
+@pytest.mark.parametrize("P", [1, 2, 4, 6, 8, 10])
+def test_library_basis_tables_match_oracle(P):
+    nk, _ = _lib()
+    Q = P + 2
+    x, w, B, D = nk.basis_tables(P, Q)
+    xo, wo = oracle.gll(Q)
+    Bo, Do = oracle.modified_basis(P, xo)
+    np.testing.assert_allclose(x, xo, atol=5e-15)
+    np.testing.assert_allclose(w, wo, atol=5e-15)
+    np.testing.assert_allclose(B, Bo, atol=5e-15)
+    np.testing.assert_allclose(D, Do, atol=1e-13)
+
+
+def test_invalid_arguments_rejected_before_device_work():
+    nk, L = _lib()
+    h = ctypes.c_void_p()
+    assert L.nk_basis_tables(0, 2, None, None, None, None) == nk.NK_EINVAL
+    assert L.nk_basis_tables(3, 3, None, None, None, None) == nk.NK_EINVAL
+    assert L.nk_space_create(None, 3, 1, 2, 4, None, None, None) == nk.NK_EINVAL
+    assert L.nk_space_create(ctypes.byref(h), 4, 1, 2, 4, None, None, None) == nk.NK_EINVAL
+    assert L.nk_space_create(ctypes.byref(h), 3, -1, 2, 4, None, None, None) == nk.NK_EINVAL
+    assert L.nk_space_create(ctypes.byref(h), 3, 1, 2, 4, None, None, None) == nk.NK_EINVAL
+    assert b"jac" in L.nk_last_error()
+    assert L.nk_space_create(ctypes.byref(h), 3, 1, 11, 13, ctypes.c_void_p(8), None, None) == nk.NK_EUNSUPPORTED
+    assert L.nk_space_create(ctypes.byref(h), 3, 1, 6, 9, ctypes.c_void_p(8), None, None) == nk.NK_EUNSUPPORTED
+    for f in ("nk_bwd_trans", "nk_iprod_wrt_base"):
+        assert getattr(L, f)(None, 0, None, None, None) == nk.NK_EINVAL
+    assert L.nk_helmholtz(None, 0, None, 1.0, None, None, None) == nk.NK_EINVAL
+    assert L.nk_system_create(ctypes.byref(h), None, 5, None, None, None, 1.0, None) == nk.NK_EINVAL
+    assert L.nk_cg_solve(None, 0, None, None, 1e-10, 10, None, None) == nk.NK_EINVAL
+    assert L.nk_space_destroy(None) == nk.NK_EINVAL
+    assert L.nk_system_destroy(None) == nk.NK_EINVAL
+    assert L.nk_set_tile_config(2, 3, 6, 0, 99) == nk.NK_EINVAL
+    assert L.nk_set_tile_config(9, 3, 6, 0, 0) == nk.NK_EINVAL
+    assert L.nk_tile_count(2, 3, 6) == 3
+
+
+def test_no_device_reports_edevice():
+    nk, L = _lib()
+    if L.nk_device_count() > 0:
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    assert L.nk_space_create(ctypes.byref(h), 3, 1, 2, 4, ctypes.c_void_p(8), None, None) == nk.NK_EDEVICE
+    assert b"device" in L.nk_last_error()
