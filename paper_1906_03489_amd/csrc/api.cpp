@@ -656,10 +656,12 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
                        y->l2g, d_bad, st)))
       break;
     if ((e = vec_fill<double>(y->diag, np, 0.0, st))) break;
+    if ((e = vec_fill<double>(y->y, np, 0.0, st))) break;
+    if ((e = mark_free(s->nelem, nloc, y->l2g, y->y, st))) break;
     if ((e = launch_diag(s->dim, G.P, G.Q, s->nelem, d_B, d_D, s->fac64, y->lam, y->lam0, y->l2g,
                          y->diag, st)))
       break;
-    if ((e = diag_finish(y->L, y->diag, y->dinv64, y->dinv32, y->diag, st))) break;
+    if ((e = diag_finish(y->L, y->diag, y->y, y->dinv64, y->dinv32, y->diag, st))) break;
     for (double* v : {y->b, y->x, y->r, y->p, y->y})
       if ((e = vec_fill<double>(v, np, 0.0, st))) break;
     for (float* v : {y->r32, y->p32, y->y32, y->d32})
@@ -777,7 +779,8 @@ nk_status nk_gather(nk_system sys, const double* x, double* x_loc, void* stream)
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   // Dirichlet entries are gathered as they are (not masked): the reported
-  // diagonal is positive on every row, so it serves as an all-pass mask.
+  // diagonal is nonzero on every row of a definite system, so it serves as an
+  // all-pass mask.
   if ((e = pad_in<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, x, sys->diag,
                           sys->p, st)) ||
       (e = gather_user(s->nelem, nloc, sys->l2g, sys->p, x_loc, st)) ||

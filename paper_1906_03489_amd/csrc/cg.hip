@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kVecBlock)
   for (int c = 0; c < kPer; ++c) {
     const int64_t i = base + c * kVecBlock;
     const double di = dinv[i];
-    const double ri = di > 0.0 ? b[i] - y[i] : 0.0;
+    const double ri = di != 0.0 ? b[i] - y[i] : 0.0;
     r[i] = ri;
     y[i] = 0.0;
     if (p) p[i] = 0.0;
@@ -324,7 +324,7 @@ __global__ void k_pad_in(const int32_t* __restrict__ blk_seg, const int64_t* __r
   for (int c = 0; c < kPer; ++c) {
     const int64_t i = base + c * kVecBlock;
     const int64_t li = i - pdof_off[s];
-    padded[i] = (li < n_s && dinv[i] > 0.0) ? user[dof_off[s] + li] : T(0);
+    padded[i] = (li < n_s && dinv[i] != 0.0) ? user[dof_off[s] + li] : T(0);
   }
 }
 
@@ -400,26 +400,46 @@ hipError_t build_l2g(int64_t nelem, int nloc, const int32_t* elem_seg, const int
   return hipGetLastError();
 }
 
-// diag holds accumulated free-DOF diagonals (zero elsewhere): dinv = 1/diag on
-// free DOFs and 0 on Dirichlet/padding rows, whose diagonal is reported as 1.
-__global__ void k_diag_finish(int64_t n, const double* diag, double* __restrict__ dinv64,
-                              float* __restrict__ dinv32, double* diag_out) {
+// diag holds accumulated free-DOF diagonals, mark is nonzero on free DOFs:
+// dinv = 1/diag on free DOFs and exactly 0 on Dirichlet/padding rows (so
+// dinv != 0 is the free-DOF mask everywhere), whose diagonal is reported as 1.
+__global__ void k_diag_finish(int64_t n, const double* diag, const double* __restrict__ mark,
+                              double* __restrict__ dinv64, float* __restrict__ dinv32,
+                              double* diag_out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double d = diag[i];
-    const bool free_ = d > 0.0;
+    const bool free_ = mark[i] != 0.0;
     dinv64[i] = free_ ? 1.0 / d : 0.0;
     dinv32[i] = free_ ? (float)(1.0 / d) : 0.f;
     diag_out[i] = free_ ? d : 1.0;
   }
 }
 
-hipError_t diag_finish(const VecLayout& L, const double* diag, double* dinv64, float* dinv32,
-                       double* diag_out, hipStream_t s) {
+hipError_t diag_finish(const VecLayout& L, const double* diag, const double* mark,
+                       double* dinv64, float* dinv32, double* diag_out, hipStream_t s) {
   int64_t nb = (L.npad + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_diag_finish, dim3((unsigned)nb), dim3(256), 0, s, L.npad, diag, dinv64,
-                     dinv32, diag_out);
+  hipLaunchKernelGGL(k_diag_finish, dim3((unsigned)nb), dim3(256), 0, s, L.npad, diag, mark,
+                     dinv64, dinv32, diag_out);
+  return hipGetLastError();
+}
+
+// mark[g] = 1 for every free global DOF referenced by an element
+__global__ void k_mark(int64_t tot, const int32_t* __restrict__ l2g, double* __restrict__ mark) {
+  for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < tot;
+       id += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = l2g[id];
+    if (g >= 0) mark[g] = 1.0;
+  }
+}
+
+hipError_t mark_free(int64_t nelem, int nloc, const int32_t* l2g_int, double* mark, hipStream_t s) {
+  const int64_t tot = nelem * nloc;
+  if (tot == 0) return hipSuccess;
+  int64_t nb = (tot + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_mark, dim3((unsigned)nb), dim3(256), 0, s, tot, l2g_int, mark);
   return hipGetLastError();
 }
 

@@ -69,8 +69,9 @@ hipError_t pad_out(int nsys, const int64_t* dof_off, const int64_t* pdof_off, in
 hipError_t build_l2g(int64_t nelem, int nloc, const int32_t* elem_seg, const int64_t* dof_off,
                      const int64_t* pdof_off, const int32_t* l2g_user, const uint8_t* dirichlet,
                      int32_t* l2g_int, int* bad, hipStream_t s);
-hipError_t diag_finish(const VecLayout& L, const double* diag, double* dinv64, float* dinv32,
-                       double* diag_out, hipStream_t s);
+hipError_t diag_finish(const VecLayout& L, const double* diag, const double* mark,
+                       double* dinv64, float* dinv32, double* diag_out, hipStream_t s);
+hipError_t mark_free(int64_t nelem, int nloc, const int32_t* l2g_int, double* mark, hipStream_t s);
 hipError_t gather_user(int64_t nelem, int nloc, const int32_t* l2g_int, const double* xpad,
                        double* xloc, hipStream_t s);
 hipError_t scatter_add(int64_t nelem, int nloc, const int32_t* l2g_int, const double* yloc,
@@ -100,7 +101,7 @@ struct nk_system_s {
   double* lam = nullptr;                  // per-element lambda copy (or null)
   double lam0 = 0.0;
   double* diag = nullptr;                 // padded, Dirichlet/padding rows = 1
-  double* dinv64 = nullptr;               // 1/diag on free DOFs, 0 elsewhere (doubles as mask)
+  double* dinv64 = nullptr;               // 1/diag on free DOFs, exactly 0 elsewhere (the mask)
   float* dinv32 = nullptr;
   // work vectors (padded)
   double *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *y = nullptr;

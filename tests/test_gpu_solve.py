@@ -1,0 +1,180 @@
+"""GPU parity of the assembled operator, assembly helpers and CG solves.
+
+Assembled operator R A R x (FP64 <= 1e-12, FP32 <= 2e-6), Jacobi diagonal,
+gather and scatter against the oracle; FP64 PCG against the oracle's sparse
+direct solve; FP32-refined PCG to a true FP64 residual <= 1e-10 recomputed by
+the oracle; many independent systems solved as one batch against individual
+oracle solves; error paths (maxit, breakdown)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.assembly import MaskedOperator, jacobi_diagonal, direct_solve
+from gpu_common import (FP32_RTOL, FP64_RTOL, assert_close, jacobians, nk, rel_err, to_dev,
+                        torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(shape, P, amp=W.WARP_AMPLITUDE, lam_seed=None):
+    Q = P + 2
+    Jg, Jo, lat = jacobians(shape, P, amp)
+    E = lat.nelem
+    lam = None if lam_seed is None else np.random.default_rng(lam_seed).uniform(0.5, 2.0, E)
+    ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0 if lam is None else lam)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    return dict(P=P, Q=Q, Jg=Jg, ops=ops, lat=lat, l2g=l2g, ng=ng, dm=dm, lam=lam)
+
+
+def _gpu_system(pb):
+    m = nk()
+    space = m.Space.create(3, pb["P"], pb["Q"], to_dev(pb["Jg"]))
+    lam = to_dev(pb["lam"]) if pb["lam"] is not None else None
+    sysm = m.System.create(space, pb["ng"], to_dev(pb["l2g"]), to_dev(pb["dm"]), lam=lam, lam0=1.0)
+    return space, sysm
+
+
+def _rhs(pb):
+    """Weak right-hand side of the manufactured sine (oracle side)."""
+    ops, lat = pb["ops"], pb["lat"]
+    U, dU = W.manufactured_ref_gradient(ops.x, lat)
+    b = oracle.assemble_vector(ops.weak_rhs(U, dU), pb["l2g"], pb["ng"])
+    b[pb["dm"].astype(bool)] = 0.0
+    return b
+
+
+@pytest.mark.parametrize("P,shape", [(2, (3, 2, 2)), (4, (3, 3, 2)), (6, (2, 2, 2))])
+def test_assembled_operator_diag_gather_scatter(P, shape):
+    torch = torch_cuda()
+    m = nk()
+    pb = _problem(shape, P, lam_seed=3)
+    mats = oracle.helmholtz_matrices(pb["ops"])
+    A = MaskedOperator(mats, pb["l2g"], pb["ng"], pb["dm"])
+    space, sysm = _gpu_system(pb)
+    x = np.random.default_rng(1).uniform(-1, 1, pb["ng"])
+    ref = A(x)
+    y = sysm.apply(to_dev(x)).cpu().numpy()
+    assert_close(y, ref, FP64_RTOL, f"apply P={P}")
+    y32 = sysm.apply(to_dev(x, torch.float32), dtype=m.F32).double().cpu().numpy()
+    assert_close(y32, ref, FP32_RTOL, f"apply32 P={P}")
+    d = sysm.diagonal().cpu().numpy()
+    assert_close(d, jacobi_diagonal(mats, pb["l2g"], pb["ng"], pb["dm"]), FP64_RTOL, "diag")
+    xl = sysm.gather(to_dev(x)).cpu().numpy()
+    np.testing.assert_array_equal(xl, oracle.gather(x, pb["l2g"]).ravel())
+    yl = np.random.default_rng(2).uniform(-1, 1, xl.size)
+    bref = oracle.assemble_vector(yl.reshape(pb["lat"].nelem, -1), pb["l2g"], pb["ng"])
+    bref[pb["dm"].astype(bool)] = 0.0
+    assert_close(sysm.assemble(to_dev(yl)).cpu().numpy(), bref, 1e-14, "assemble")
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_cg_f64_matches_direct_solve(P):
+    torch_cuda()
+    pb = _problem((3, 3, 3) if P < 6 else (2, 2, 3), P)
+    b = _rhs(pb)
+    mats = oracle.helmholtz_matrices(pb["ops"])
+    xref = direct_solve(mats, pb["l2g"], pb["ng"], pb["dm"], b)
+    _, sysm = _gpu_system(pb)
+    x, info = sysm.solve(to_dev(b), rtol=1e-12, maxit=20000)
+    assert info[0]["status"] == 0 and info[0]["rel_resid"] <= 1e-12
+    assert info[0]["iters"] > 5
+    xs = x.cpu().numpy()
+    # the oracle's own residual of the GPU solution, and the solution error,
+    # which is bounded by cond(A) * rtol (cond ~ 1e3 at P = 6)
+    A = MaskedOperator(mats, pb["l2g"], pb["ng"], pb["dm"])
+    assert np.linalg.norm(b - A(xs)) / np.linalg.norm(b) <= 1.05e-12
+    assert rel_err(xs, xref) < 1e-8
+
+
+@pytest.mark.parametrize("P", [4, 6])
+def test_cg_f32_refined_true_residual(P):
+    """FP32 operator and vectors inside FP64 refinement: the FP64 residual of
+    the returned x, recomputed by the oracle, is <= 1e-10."""
+    m = nk()
+    torch_cuda()
+    pb = _problem((3, 3, 2), P, lam_seed=9)
+    b = _rhs(pb)
+    mats = oracle.helmholtz_matrices(pb["ops"])
+    A = MaskedOperator(mats, pb["l2g"], pb["ng"], pb["dm"])
+    _, sysm = _gpu_system(pb)
+    x, info = sysm.solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_F32_REFINED)
+    xs = x.cpu().numpy()
+    res = np.linalg.norm(b - A(xs)) / np.linalg.norm(b)
+    assert res <= 1.2e-10, res
+    assert info[0]["outer_iters"] >= 2 and info[0]["status"] == 0
+    xref = direct_solve(mats, pb["l2g"], pb["ng"], pb["dm"], b)
+    assert rel_err(xs, xref) < 1e-7
+
+
+def test_cg_initial_guess_and_zero_rhs():
+    torch = torch_cuda()
+    pb = _problem((2, 2, 2), 3)
+    b = _rhs(pb)
+    xref = direct_solve(oracle.helmholtz_matrices(pb["ops"]), pb["l2g"], pb["ng"], pb["dm"], b)
+    _, sysm = _gpu_system(pb)
+    x0 = to_dev(xref + 1e-3 * np.random.default_rng(0).standard_normal(pb["ng"]))
+    x, info = sysm.solve(to_dev(b), x=x0, rtol=1e-12)
+    assert rel_err(x.cpu().numpy(), xref) < 1e-8      # cond(A) * rtol
+    # Dirichlet entries of the initial guess are forced to zero
+    assert np.all(x.cpu().numpy()[pb["dm"].astype(bool)] == 0.0)
+    z, info = sysm.solve(torch.zeros(pb["ng"], dtype=torch.float64, device="cuda"), rtol=1e-10)
+    assert info[0]["iters"] == 0 and np.all(z.cpu().numpy() == 0.0)
+
+
+def test_cg_maxit_reports_noconv():
+    m = nk()
+    torch_cuda()
+    pb = _problem((3, 3, 3), 4)
+    b = _rhs(pb)
+    _, sysm = _gpu_system(pb)
+    x, info = sysm.solve(to_dev(b), rtol=1e-14, maxit=7, raise_on_fail=False)
+    assert info[0]["status"] == m.NK_ENOCONV
+    assert info[0]["iters"] == 7
+
+
+def test_cg_breakdown_on_indefinite_operator():
+    """lambda = -1e4 makes A indefinite: breakdown or no convergence is
+    reported, and the call returns normally."""
+    m = nk()
+    torch_cuda()
+    pb = _problem((2, 2, 2), 3)
+    b = _rhs(pb)
+    space = m.Space.create(3, pb["P"], pb["Q"], to_dev(pb["Jg"]))
+    sysm = m.System.create(space, pb["ng"], to_dev(pb["l2g"]), to_dev(pb["dm"]), lam0=-1e4)
+    with pytest.raises(m.NkError) as ei:
+        sysm.solve(to_dev(b), rtol=1e-12, maxit=500)
+    assert ei.value.status in (5, 6)
+
+
+def test_batched_independent_systems():
+    """Systems of different sizes in one batched solve (one persistent
+    operator launch per iteration, per-system CG scalars) equal the oracle's
+    individual direct solves."""
+    m = nk()
+    torch = torch_cuda()
+    P, Q = 3, 5
+    boxes = [(1, 1, 1), (2, 3, 1), (3, 3, 3), (2, 2, 2), (4, 1, 2)]
+    jg, l2gs, dms, bs, refs = [], [], [], [], []
+    eoff, doff = [0], [0]
+    for bx in boxes:
+        pb = _problem(bx, P)
+        b = _rhs(pb)
+        refs.append(direct_solve(oracle.helmholtz_matrices(pb["ops"]), pb["l2g"], pb["ng"], pb["dm"], b))
+        jg.append(pb["Jg"])
+        l2gs.append(pb["l2g"] + doff[-1])
+        dms.append(pb["dm"])
+        bs.append(b)
+        eoff.append(eoff[-1] + pb["lat"].nelem)
+        doff.append(doff[-1] + pb["ng"])
+    space = m.Space.create(3, P, Q, to_dev(np.concatenate(jg)))
+    sysm = m.System.create_batched(space, eoff, doff, to_dev(np.concatenate(l2gs).astype(np.int32)),
+                                   to_dev(np.concatenate(dms)), lam0=1.0)
+    for mode, tol in ((m.SOLVE_F64, 1e-12), (m.SOLVE_F32_REFINED, 1e-10)):
+        x, info = sysm.solve(to_dev(np.concatenate(bs)), rtol=tol, mode=mode)
+        xs = x.cpu().numpy()
+        assert len(info) == len(boxes)
+        for k, ref in enumerate(refs):
+            assert info[k]["status"] == 0 and info[k]["rel_resid"] <= tol * 1.0001
+            err = rel_err(xs[doff[k]:doff[k + 1]], ref)
+            assert err < (1e-9 if mode == m.SOLVE_F64 else 1e-6), (k, mode, err)
