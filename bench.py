@@ -168,6 +168,174 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
     return out
 
 
+def section_varp(nk, W, torch, reps=20):
+    """20 000 hexes (20x20x50 curved lattice) with per-element order drawn from
+    {2..10}: one persistent mixed-order launch vs one launch per order group."""
+    cfg = W.CONFIGS[3]
+    lat = W.lattice(cfg["varp_shape"])
+    Pe = W.varp_orders(W.seed(3, 4), lat.nelem, *cfg["varp_P"])
+    Ps = sorted(set(int(p) for p in Pe))
+    jacs, xs, nbytes, ndof = [], [], 0, 0
+    for P in Ps:
+        sel = np.flatnonzero(Pe == P)
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[sel])
+        jacs.append(torch.from_numpy(W.element_jacobians(nk.basis_tables(P, P + 2)[0], sub, cfg["warp"])).cuda())
+        n3 = (P + 1) ** 3
+        xs.append(torch.from_numpy(W.uniform(W.seed(3, 0) + P, sel.size * n3)).cuda())
+        nbytes += helm_bytes_per_elem(P, P + 2) * sel.size
+        ndof += sel.size * n3
+    space = nk.Space.create_varp(3, Ps, [p + 2 for p in Ps], jacs)
+    singles = [nk.Space.create(3, P, P + 2, j) for P, j in zip(Ps, jacs)]
+    x = torch.cat(xs)
+    out = {"nelem": int(lat.nelem), "local_dof": int(ndof), "orders": Ps}
+    for dt, name in ((nk.F64, "f64"), (nk.F32, "f32")):
+        td = torch.float64 if dt == nk.F64 else torch.float32
+        xd = x.to(td)
+        y = torch.empty_like(xd)
+        xg = [t.to(td) for t in xs]
+        yg = [torch.empty_like(t) for t in xg]
+        nk.helmholtz(space, xd, y, lam0=1.0, dtype=dt)
+        ms_one = time_launches(lambda: nk.helmholtz(space, xd, y, lam0=1.0, dtype=dt), reps, torch)
+
+        def per_group():
+            for sp, xi, yi in zip(singles, xg, yg):
+                nk.helmholtz(sp, xi, yi, lam0=1.0, dtype=dt)
+        per_group()
+        ms_grp = time_launches(per_group, reps, torch)
+        err = float(torch.linalg.norm(y - torch.cat(yg)) / torch.linalg.norm(torch.cat(yg)))
+        s = 8 if dt == nk.F64 else 4
+        gbs = nbytes * s / 8 / (ms_one * 1e-3) / 1e9
+        out[name] = {"single_launch_ms": round(ms_one, 4), "per_group_ms": round(ms_grp, 4),
+                     "speedup": round(ms_grp / ms_one, 3),
+                     "gdof_s": round(ndof / (ms_one * 1e-3) / 1e9, 2),
+                     "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "rel_diff_vs_per_group": err}
+        log(f"varp {name}: one launch {ms_one * 1e3:.1f} us vs per-group {ms_grp * 1e3:.1f} us")
+    return out
+
+
+def section_many_solves(nk, W, torch):
+    """256 independent P=5 Helmholtz solves on curved boxes of 64..4096 hexes
+    (log-uniform sizes): one batched solve (one operator launch per CG
+    iteration for all systems, captured in graphs) vs the systems solved one
+    by one, FP64 and FP32-refined."""
+    cfg = W.CONFIGS[3]
+    P, Q = cfg["solve_P"], cfg["solve_P"] + 2
+    boxes = W.solve_boxes(W.seed(3, 5), cfg["nsolves"], *cfg["solve_sizes"])
+    xq = nk.basis_tables(P, Q)[0]
+    n3, q3 = (P + 1) ** 3, Q ** 3
+    nel = [a * b * c for a, b, c in boxes]
+    E = int(sum(nel))
+    J = torch.empty((E, 3, 3, q3), dtype=torch.float64, device="cuda")
+    U = torch.empty((E, q3), dtype=torch.float64, device="cuda")
+    dU = torch.empty((E, 3, q3), dtype=torch.float64, device="cuda")
+    l2gs, dms, eoff, doff, ngs = [], [], [0], [0], []
+    for bx in boxes:
+        lat = W.lattice(bx)
+        e0, e1 = eoff[-1], eoff[-1] + lat.nelem
+        J[e0:e1] = torch.from_numpy(W.element_jacobians(xq, lat, cfg["warp"]))
+        u_, du_ = W.manufactured_ref_gradient(xq, lat)
+        U[e0:e1] = torch.from_numpy(u_)
+        dU[e0:e1] = torch.from_numpy(du_)
+        l2g, ng, dm = W.lattice_l2g(bx, P)
+        l2gs.append(l2g)
+        dms.append(dm)
+        ngs.append(ng)
+        eoff.append(e1)
+        doff.append(doff[-1] + ng)
+    space = nk.Space.create(3, P, Q, J)
+    l2g_u = torch.from_numpy(np.concatenate([l + o for l, o in zip(l2gs, doff[:-1])]).astype(np.int32)).cuda()
+    dm_u = torch.from_numpy(np.concatenate(dms)).cuda()
+    sysb = nk.System.create_batched(space, eoff, doff, l2g_u, dm_u, lam0=1.0)
+    yl = nk.helmholtz_weak_rhs(space, U.reshape(-1), dU.reshape(-1), lam0=1.0)
+    b = sysb.assemble(yl)
+    del U, dU, yl
+    out = {"nsys": len(boxes), "nelem_total": E, "nglobal_total": int(doff[-1]),
+           "min_elems": int(min(nel)), "max_elems": int(max(nel))}
+    for mode, name in ((nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")):
+        sysb.solve(b, rtol=1e-2, maxit=50000, mode=mode)      # capture graphs
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xb, info = sysb.solve(b, rtol=1e-10, maxit=50000, mode=mode)
+        tb = (time.perf_counter() - t) * 1e3
+        its = [i["iters"] for i in info]
+        out[name] = {"batched_ms": round(tb, 2), "iters_min": min(its), "iters_max": max(its),
+                     "max_rel_resid": max(i["rel_resid"] for i in info)}
+        log(f"256 solves {name}: batched {tb:.1f} ms (iters {min(its)}..{max(its)})")
+    # one by one (same kernels, one system per solve)
+    singles = []
+    for k in range(len(boxes)):
+        sp = nk.Space.create(3, P, Q, J[eoff[k]:eoff[k + 1]])
+        sy = nk.System.create(sp, ngs[k], torch.from_numpy(l2gs[k]).cuda(), torch.from_numpy(dms[k]).cuda(),
+                              lam0=1.0)
+        singles.append((sp, sy, b[doff[k]:doff[k + 1]].contiguous()))
+    for mode, name in ((nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")):
+        for sp, sy, bk in singles:
+            sy.solve(bk, rtol=1e-2, maxit=50000, mode=mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xs = [sy.solve(bk, rtol=1e-10, maxit=50000, mode=mode)[0] for sp, sy, bk in singles]
+        ti = (time.perf_counter() - t) * 1e3
+        xb, _ = sysb.solve(b, rtol=1e-10, maxit=50000, mode=mode)
+        diff = float(torch.linalg.norm(xb - torch.cat(xs)) / torch.linalg.norm(xb))
+        out[name].update({"one_by_one_ms": round(ti, 2),
+                          "speedup_batched": round(ti / out[name]["batched_ms"], 2),
+                          "rel_diff_batched_vs_one_by_one": diff})
+        log(f"256 solves {name}: one by one {ti:.1f} ms")
+    out["speedup_f32_refined_vs_f64_batched"] = round(out["f64"]["batched_ms"] / out["f32_refined"]["batched_ms"], 3)
+    return out
+
+
+def section_grad(nk, W, torch):
+    """Loss 0.5 ||u(kappa, lambda) - u_t||^2 on 16^3 curved hexes at P=6 with
+    kappa per quadrature point and lambda per element drawn from [0.5, 2]:
+    forward solve and adjoint backward through torch.autograd, plus a
+    central-difference check along a seeded direction."""
+    from paper_1906_03489_amd.autograd import HelmholtzProblem, helmholtz_solve
+    cfg = W.CONFIGS[4]
+    P, Q, shape = cfg["P"], cfg["Q"], cfg["shape"]
+    lat = W.lattice(shape)
+    E, q3 = lat.nelem, Q ** 3
+    xq = nk.basis_tables(P, Q)[0]
+    J = torch.from_numpy(W.element_jacobians(xq, lat, cfg["warp"])).cuda()
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    l2g, dm = torch.from_numpy(l2g).cuda(), torch.from_numpy(dm).cuda()
+    sp1 = nk.Space.create(3, P, Q, J)
+    sy1 = nk.System.create(sp1, ng, l2g, dm, lam0=1.0)
+    U, dU = W.manufactured_ref_gradient(xq, lat)
+    b = sy1.assemble(nk.helmholtz_weak_rhs(sp1, torch.from_numpy(U).cuda().reshape(-1),
+                                           torch.from_numpy(dU).cuda().reshape(-1), lam0=1.0))
+    ut, _ = sy1.solve(b, rtol=1e-12)
+    pb = HelmholtzProblem(3, P, Q, J, l2g, ng, dm, b, rtol=1e-12)
+    lo, hi = cfg["coef_range"]
+    kap = torch.from_numpy(W.uniform(W.seed(4, 3), (E, q3), lo, hi)).cuda().requires_grad_(True)
+    lam = torch.from_numpy(W.uniform(W.seed(4, 2), E, lo, hi)).cuda().requires_grad_(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    u = helmholtz_solve(kap, lam, pb)
+    loss = 0.5 * torch.sum((u - ut) ** 2)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t) * 1e3
+    t = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_bwd = (time.perf_counter() - t) * 1e3
+    rng = np.random.default_rng(W.seed(4, 6))
+    vk = torch.from_numpy(rng.standard_normal((E, q3))).cuda()
+    vl = torch.from_numpy(rng.standard_normal(E)).cuda()
+    eps = 1e-4
+    with torch.no_grad():
+        lp = 0.5 * torch.sum((helmholtz_solve(kap + eps * vk, lam + eps * vl, pb) - ut) ** 2)
+        lm = 0.5 * torch.sum((helmholtz_solve(kap - eps * vk, lam - eps * vl, pb) - ut) ** 2)
+    fd = float((lp - lm) / (2 * eps))
+    an = float(torch.sum(kap.grad * vk) + torch.sum(lam.grad * vl))
+    log(f"grad: forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms, fd {fd:.6e} vs adjoint {an:.6e}")
+    return {"nelem": E, "n_kappa": E * q3, "n_lambda": E, "loss": float(loss),
+            "forward_ms": round(t_fwd, 2), "backward_ms": round(t_bwd, 2),
+            "fd_directional": fd, "adjoint_directional": an,
+            "fd_rel_diff": abs(fd - an) / abs(an)}
+
+
 def cpu_baseline(W, budget_s=12.0):
     """The plain FP64 oracle (dense elemental matrices, build + apply) on a
     bounded sample of the 32^3, P=6 workload's elements."""
@@ -206,7 +374,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="ops,cg,cpu",
+    ap.add_argument("--sections", default="ops,cg,batch,grad,cpu",
                     help="comma list of ops,cg,batch,grad,cpu (or 'none')")
     ap.add_argument("--cg-orders", default="4,6,8")
     args = ap.parse_args()
@@ -276,11 +444,13 @@ def main():
         log("section cg ...")
         sections["cg_24c"] = section_cg(nk, W, torch, [int(p) for p in args.cg_orders.split(",") if p])
     if "batch" in secs:
-        from bench_sections import section_batch
-        log("section batch ...")
-        sections["batch"] = section_batch(nk, W, torch)
+        log("section batch (mixed order) ...")
+        sections["batch_varp_20000"] = section_varp(nk, W, torch)
+        torch.cuda.empty_cache()
+        log("section batch (256 solves) ...")
+        sections["batch_256_solves"] = section_many_solves(nk, W, torch)
+        torch.cuda.empty_cache()
     if "grad" in secs:
-        from bench_sections import section_grad
         log("section grad ...")
         sections["grad_16c_P6"] = section_grad(nk, W, torch)
     result["sections"] = sections

@@ -77,7 +77,9 @@ const char* tile_name(int op, int dim, int P, int tile) {
   if (P < kMinP || P > kMaxP) return "";
   const int epb = dim == 3 ? kTileEPB3[P][tile] : kTileEPB2[P][tile];
   const int q = P + 2;
-  std::snprintf(buf, sizeof buf, "epb%d_thr%d", epb, epb * (dim == 3 ? q * q : q));
+  const int q2 = q * q;
+  const int slot = dim == 3 ? (q2 <= 16 ? 16 : q2 <= 64 ? 64 : q2) : q;
+  std::snprintf(buf, sizeof buf, "epb%d_thr%d", epb, epb * slot);
   (void)op;
   return buf;
 }
@@ -472,6 +474,10 @@ static void system_free(nk_system y) {
   dfree(y->d_elem_off);
   dfree(y->d_blk_first);
   dfree(y->d_blk_seg);
+  dfree(y->d_dblk_first);
+  dfree(y->d_dblk_seg);
+  dfree(y->dslot);
+  dfree(y->part_d);
   dfree(y->elem_seg);
   dfree(y->l2g);
   dfree(y->lam);
@@ -483,6 +489,10 @@ static void system_free(nk_system y) {
   dfree(y->r);
   dfree(y->p);
   dfree(y->y);
+  dfree(y->u);
+  dfree(y->s);
+  dfree(y->u32);
+  dfree(y->s32);
   dfree(y->r32);
   dfree(y->p32);
   dfree(y->y32);
@@ -567,14 +577,27 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   }
   y->L.npad = y->pdof_off[nsys];
   y->L.nblk = y->L.npad / kSegAlign;
+  y->pdot_off.assign(nsys + 1, 0);
+  y->dblk_first.assign(nsys + 1, 0);
+  for (int k = 0; k < nsys; ++k) {
+    const int64_t ne = std::max<int64_t>(elem_off[k + 1] - elem_off[k], 1);
+    y->pdot_off[k + 1] = y->pdot_off[k] + (ne + kSegAlign - 1) / kSegAlign * kSegAlign;
+    y->dblk_first[k + 1] = y->pdot_off[k + 1] / kSegAlign;
+  }
+  y->Ld.npad = y->pdot_off[nsys];
+  y->Ld.nblk = y->Ld.npad / kSegAlign;
   if (y->L.npad >= ((int64_t)1 << 31) - 1) {
     system_free(y);
     return fail(NK_EINVAL, "padded system too large");
   }
-  std::vector<int32_t> blk_seg(y->L.nblk), eseg(s->nelem);
+  std::vector<int32_t> blk_seg(y->L.nblk), eseg(s->nelem), dblk_seg(y->Ld.nblk), dslot(s->nelem);
   for (int k = 0; k < nsys; ++k) {
     for (int64_t b = y->blk_first[k]; b < y->blk_first[k + 1]; ++b) blk_seg[b] = k;
-    for (int64_t e = elem_off[k]; e < elem_off[k + 1]; ++e) eseg[e] = k;
+    for (int64_t b = y->dblk_first[k]; b < y->dblk_first[k + 1]; ++b) dblk_seg[b] = k;
+    for (int64_t e = elem_off[k]; e < elem_off[k + 1]; ++e) {
+      eseg[e] = k;
+      dslot[e] = (int32_t)(y->pdot_off[k] + (e - elem_off[k]));
+    }
   }
   auto cleanup = [&](nk_status stt) {
     system_free(y);
@@ -600,12 +623,20 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   NK_ALLOC(y->r, np);
   NK_ALLOC(y->p, np);
   NK_ALLOC(y->y, np);
+  NK_ALLOC(y->u, np);
+  NK_ALLOC(y->s, np);
+  NK_ALLOC(y->u32, np);
+  NK_ALLOC(y->s32, np);
   NK_ALLOC(y->r32, np);
   NK_ALLOC(y->p32, np);
   NK_ALLOC(y->y32, np);
   NK_ALLOC(y->d32, np);
-  NK_ALLOC(y->dots, std::max<int64_t>(s->nelem, 1));
+  NK_ALLOC(y->dots, y->Ld.npad);
   NK_ALLOC(y->part, 2 * y->L.nblk);
+  NK_ALLOC(y->part_d, 2 * y->Ld.nblk);
+  NK_ALLOC(y->d_dblk_first, nsys + 1);
+  NK_ALLOC(y->d_dblk_seg, y->Ld.nblk);
+  NK_ALLOC(y->dslot, std::max<int64_t>(s->nelem, 1));
   NK_ALLOC(y->bb, nsys);
   NK_ALLOC(y->rr_true, nsys);
   NK_ALLOC(y->cnt_aux, nsys);
@@ -627,6 +658,8 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
     return cleanup(hip_fail(e, "hipEventCreate"));
   y->L.blk_seg = y->d_blk_seg;
   y->L.blk_first = y->d_blk_first;
+  y->Ld.blk_seg = y->d_dblk_seg;
+  y->Ld.blk_first = y->d_dblk_first;
   // setup runs on the caller's stream, then synchronises it
   int* d_bad = nullptr;
   double *d_B = nullptr, *d_D = nullptr;
@@ -646,6 +679,11 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
     if ((e = hipMemcpyAsync(y->d_elem_off, elem_off, (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
     if ((e = hipMemcpyAsync(y->d_blk_first, y->blk_first.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
     if ((e = hipMemcpyAsync(y->d_blk_seg, blk_seg.data(), y->L.nblk * 4, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(y->d_dblk_first, y->dblk_first.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(y->d_dblk_seg, dblk_seg.data(), y->Ld.nblk * 4, hipMemcpyHostToDevice, st))) break;
+    if (s->nelem > 0 &&
+        (e = hipMemcpyAsync(y->dslot, dslot.data(), s->nelem * 4, hipMemcpyHostToDevice, st))) break;
+    if ((e = vec_fill<double>(y->dots, y->Ld.npad, 0.0, st))) break;
     if (s->nelem > 0 &&
         (e = hipMemcpyAsync(y->elem_seg, eseg.data(), s->nelem * 4, hipMemcpyHostToDevice, st))) break;
     if (lambda && (e = hipMemcpyAsync(y->lam, lambda, s->nelem * 8, hipMemcpyDeviceToDevice, st))) break;
@@ -662,9 +700,9 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
                          y->diag, st)))
       break;
     if ((e = diag_finish(y->L, y->diag, y->y, y->dinv64, y->dinv32, y->diag, st))) break;
-    for (double* v : {y->b, y->x, y->r, y->p, y->y})
+    for (double* v : {y->b, y->x, y->r, y->p, y->y, y->u, y->s})
       if ((e = vec_fill<double>(v, np, 0.0, st))) break;
-    for (float* v : {y->r32, y->p32, y->y32, y->d32})
+    for (float* v : {y->r32, y->p32, y->y32, y->d32, y->u32, y->s32})
       if ((e = vec_fill<float>(v, np, 0.f, st))) break;
     if ((e = vec_fill<int32_t>(y->outer_cnt, nsys, 0, st))) break;
     if ((e = vec_fill<int32_t>(y->cnt_aux, nsys, 0, st))) break;
@@ -717,6 +755,7 @@ static hipError_t sys_op(nk_system y, nk_dtype t, const void* x, void* out, doub
   a.lam0 = y->lam0;
   a.l2g = y->l2g;
   a.dots = dots;
+  a.dslot = dots ? y->dslot : nullptr;
   a.elem_seg = seg_done ? y->elem_seg : nullptr;
   a.seg_done = seg_done;
   a.tile = tile;
@@ -814,23 +853,47 @@ static double inner_tol() {
   return (t > 0.0 && t < 1.0) ? t : 1e-4;
 }
 
-// One CG iteration of precision T on the system's stream.
+// One CG iteration of precision T on the system's stream: vector update,
+// assembled operator w = A u with per-element u.Au, per-system finish.
 template <typename T>
 static hipError_t cg_iteration(nk_system y, int maxit) {
   const bool f64 = std::is_same<T, double>::value;
   CgState& st = f64 ? y->st64 : y->st32;
-  T* r = f64 ? (T*)y->r : (T*)y->r32;
-  T* p = f64 ? (T*)y->p : (T*)y->p32;
-  T* yy = f64 ? (T*)y->y : (T*)y->y32;
   T* x = f64 ? (T*)y->x : (T*)y->d32;
+  T* r = f64 ? (T*)y->r : (T*)y->r32;
+  T* u = f64 ? (T*)y->u : (T*)y->u32;
+  T* p = f64 ? (T*)y->p : (T*)y->p32;
+  T* s = f64 ? (T*)y->s : (T*)y->s32;
+  T* w = f64 ? (T*)y->y : (T*)y->y32;
   const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
   hipError_t e;
-  if ((e = cg_p_update<T>(y->L, st, r, dinv, p, y->cs))) return e;
-  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, p, yy, y->dots, st.done, f64 ? y->tile64 : y->tile32,
+  if ((e = cg_update<T>(y->L, st, x, r, u, p, s, w, dinv, y->part, y->cs))) return e;
+  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, st.done, f64 ? y->tile64 : y->tile32,
                   y->cs)))
     return e;
-  if ((e = cg_alpha<T>(y->nsys, y->d_elem_off, y->dots, st, f64, y->cs))) return e;
-  return cg_update<T>(y->L, st, maxit, x, r, p, yy, dinv, y->part, y->cs);
+  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, maxit, f64, false, 0.0, nullptr,
+                   nullptr, nullptr, y->cs);
+}
+
+// First step of a CG solve in precision T: r = b - w (w = A x0 or 0),
+// u = M^{-1} r, w = A u, alpha from (r,u)/(w,u).
+template <typename T>
+static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int32_t* outer_done) {
+  const bool f64 = std::is_same<T, double>::value;
+  CgState& st = f64 ? y->st64 : y->st32;
+  T* r = f64 ? (T*)y->r : (T*)y->r32;
+  T* u = f64 ? (T*)y->u : (T*)y->u32;
+  T* p = f64 ? (T*)y->p : (T*)y->p32;
+  T* s = f64 ? (T*)y->s : (T*)y->s32;
+  T* w = f64 ? (T*)y->y : (T*)y->y32;
+  const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
+  hipError_t e;
+  if ((e = cg_start<T>(y->L, b, w, r, u, p, s, dinv, y->part, y->cs))) return e;
+  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, nullptr, f64 ? y->tile64 : y->tile32,
+                  y->cs)))
+    return e;
+  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, 1 << 30, f64, true, tau2,
+                   outer_done, y->outer_tol2, y->outer_rr, y->cs);
 }
 
 template <typename T>
@@ -913,10 +976,9 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
     if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, x, y->dinv64, y->x, cs))) break;
     if (mode == NK_SOLVE_F64) {
       if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->st64.tol2, cs))) break;
-      if ((e = vec_fill<int32_t>(y->st64.status, ns, 0, cs))) break;
       if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
       if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
-      if ((e = cg_residual(y->L, y->st64, y->b, y->y, y->dinv64, y->r, y->p, y->part, cs))) break;
+      if ((e = cg_begin<double>(y, y->b, 0.0, nullptr))) break;
       if ((e = cg_loop<double>(y, maxit, y->st64.done))) break;
       if ((e = hipMemcpyAsync(y->h_flags, y->st64.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
       if ((e = hipStreamSynchronize(cs))) break;
@@ -941,9 +1003,9 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
           if (!y->h_flags[i]) outer[i] += 1;
         }
         if (all) break;
-        if ((e = cg_inner_init(y->L, y->st32, y->outer_done, tau, y->r, y->dinv32, y->r32, y->d32,
-                               y->p32, y->y32, y->part, cs)))
-          break;
+        if ((e = vec_fill<float>(y->d32, np, 0.f, cs))) break;
+        if ((e = vec_fill<float>(y->y32, np, 0.f, cs))) break;
+        if ((e = cg_begin<float>(y, y->r, tau * tau, y->outer_done))) break;
         if ((e = cg_loop<float>(y, maxit, y->st32.done))) break;
         if ((e = hipMemcpyAsync(y->h_flags, y->st32.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
         if ((e = hipStreamSynchronize(cs))) break;

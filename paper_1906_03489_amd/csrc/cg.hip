@@ -9,6 +9,7 @@ namespace nk {
 
 constexpr int kPer = kSegAlign / kVecBlock;  // DOFs per thread
 
+template <int NTH = kVecBlock>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -18,9 +19,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < kVecBlock / 64; ++i) s += sh[i];
+    for (int i = 0; i < NTH / 64; ++i) s += sh[i];
   return s;  // valid in thread 0
 }
+
+constexpr int kFinThreads = 1024;
 
 // Register the block's partials (a, b); returns true in thread 0 of the last
 // block of system `s` to arrive, which then sees every block's partials.
@@ -51,105 +54,194 @@ __device__ __forceinline__ void sum_parts(double* part, int64_t b0, int64_t b1, 
   b = block_sum(sb, sh);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kVecBlock)
-    k_cg_p(const int32_t* __restrict__ blk_seg, CgState st, const T* __restrict__ r,
-           const T* __restrict__ dinv, T* __restrict__ p) {
-  const int s = blk_seg[blockIdx.x];
-  if (st.done[s]) return;
-  const T beta = (T)st.beta[s];
-  const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
-#pragma unroll
-  for (int c = 0; c < kPer; ++c) {
-    const int64_t i = base + c * kVecBlock;
-    p[i] = r[i] * dinv[i] + beta * p[i];
-  }
-}
+// ---------------------------------------------------------------------------
+// Preconditioned CG with one reduction phase per iteration (the Chronopoulos-
+// Gear arrangement of the textbook recurrences): with u = M^{-1} r, w = A u,
+//   gamma = (r, u), delta = (w, u),
+//   beta = gamma / gamma_old,  alpha = gamma / (delta - beta gamma / alpha_old),
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s.
+// One iteration = cg_update (vectors; partial sums of gamma and r.r),
+// the assembled operator w = A u (per-element u_e.(H_e u_e) into dots), and
+// cg_finish (one block per system sums the partials and the dots, tests
+// convergence and forms alpha, beta).  Block partials are plain stores read by
+// the next kernel, so no grid-wide fence is needed.
 
-template <typename T>
-hipError_t cg_p_update(const VecLayout& L, CgState st, const T* r, const T* dinv, T* p,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_p<T>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, s, L.blk_seg, st, r,
-                     dinv, p);
-  return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(kVecBlock)
-    k_cg_alpha(const int64_t* __restrict__ elem_off, const double* __restrict__ dots, CgState st,
-               int fatal) {
-  __shared__ double sh[kVecBlock / 64];
-  const int s = blockIdx.x;
-  if (st.done[s]) return;
-  double v = 0.0;
-  for (int64_t e = elem_off[s] + threadIdx.x; e < elem_off[s + 1]; e += kVecBlock) v += dots[e];
-  const double pAp = block_sum(v, sh);
+// Writes the block's two partial sums; thread 0 holds the block sums.
+__device__ __forceinline__ void store_parts(double a, double b, double* part) {
   if (threadIdx.x == 0) {
-    if (!(pAp > 0.0) || !isfinite(pAp)) {
-      st.alpha[s] = 0.0;
-      st.done[s] = 1;
-      if (fatal) st.status[s] = NK_EBREAKDOWN;
-    } else {
-      st.alpha[s] = st.rz[s] / pAp;
-    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
   }
 }
 
 template <typename T>
-hipError_t cg_alpha(int nsys, const int64_t* elem_off, const double* dots, CgState st,
-                    bool fatal_breakdown, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(nsys), dim3(kVecBlock), 0, s, elem_off, dots, st,
-                     fatal_breakdown ? 1 : 0);
-  return hipGetLastError();
-}
-
-template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_cg_upd(const int32_t* __restrict__ blk_seg, const int64_t* __restrict__ blk_first, CgState st,
-             int maxit, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-             T* __restrict__ y, const T* __restrict__ dinv, double* __restrict__ part) {
+    k_cg_update(const int32_t* __restrict__ blk_seg, CgState st, T* __restrict__ x,
+                T* __restrict__ r, T* __restrict__ u, T* __restrict__ p, T* __restrict__ s,
+                T* __restrict__ w, const T* __restrict__ dinv, double* __restrict__ part) {
   __shared__ double sh[kVecBlock / 64];
-  const int s = blk_seg[blockIdx.x];
-  if (st.done[s]) return;
-  const T alpha = (T)st.alpha[s];
+  const int sg = blk_seg[blockIdx.x];
+  if (st.done[sg]) return;
+  const T alpha = (T)st.alpha[sg], beta = (T)st.beta[sg];
   const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
+  double g = 0.0, rr = 0.0;
 #pragma unroll
   for (int c = 0; c < kPer; ++c) {
     const int64_t i = base + c * kVecBlock;
-    x[i] += alpha * p[i];
-    const T ri = r[i] - alpha * y[i];
+    const T di = dinv[i];
+    const T ri = r[i];
+    const T pi = ri * di + beta * p[i];
+    const T si = w[i] + beta * s[i];
+    x[i] += alpha * pi;
+    const T rn = ri - alpha * si;
+    const T un = rn * di;
+    p[i] = pi;
+    s[i] = si;
+    r[i] = rn;
+    u[i] = un;
+    w[i] = T(0);
+    g += (double)rn * (double)un;
+    rr += (double)rn * (double)rn;
+  }
+  g = block_sum(g, sh);
+  rr = block_sum(rr, sh);
+  store_parts(g, rr, part);
+}
+
+template <typename T>
+hipError_t cg_update(const VecLayout& L, CgState st, T* x, T* r, T* u, T* p, T* s, T* w,
+                     const T* dinv, double* part, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_update<T>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream,
+                     L.blk_seg, st, x, r, u, p, s, w, dinv, part);
+  return hipGetLastError();
+}
+
+// Start of a solve: r = (b - w) on free DOFs (w = A x0, or 0), u = M^{-1} r,
+// p = s = w = 0, partial sums of (r, u) and (r, r).
+template <typename T>
+__global__ void __launch_bounds__(kVecBlock)
+    k_cg_start(const int32_t* __restrict__ blk_seg, const double* __restrict__ b,
+               T* __restrict__ w, T* __restrict__ r, T* __restrict__ u, T* __restrict__ p,
+               T* __restrict__ s, const T* __restrict__ dinv, double* __restrict__ part) {
+  __shared__ double sh[kVecBlock / 64];
+  (void)blk_seg;
+  const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
+  double g = 0.0, rr = 0.0;
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int64_t i = base + c * kVecBlock;
+    const T di = dinv[i];
+    const T ri = di != T(0) ? (T)(b[i] - (double)w[i]) : T(0);
+    const T ui = ri * di;
     r[i] = ri;
-    y[i] = T(0);
-    const double rd = (double)ri;
-    rz += rd * rd * (double)dinv[i];
-    rr += rd * rd;
+    u[i] = ui;
+    p[i] = T(0);
+    s[i] = T(0);
+    w[i] = T(0);
+    g += (double)ri * (double)ui;
+    rr += (double)ri * (double)ri;
   }
-  const double a = block_sum(rz, sh), b = block_sum(rr, sh);
-  const int64_t b0 = blk_first[s], b1 = blk_first[s + 1];
-  if (!last_block(a, b, part, st.cnt, s, b1 - b0)) return;
-  double rzn, rrn;
-  sum_parts(part, b0, b1, sh, rzn, rrn);
-  if (threadIdx.x == 0) {
-    st.beta[s] = rzn / st.rz[s];
-    st.rz[s] = rzn;
-    st.rr[s] = rrn;
-    const int it = st.iters[s] + 1;
-    st.iters[s] = it;
-    if (rrn <= st.tol2[s]) {
-      st.done[s] = 1;
-    } else if (it >= maxit || !isfinite(rrn)) {
-      st.done[s] = 1;
-      st.status[s] = isfinite(rrn) ? NK_ENOCONV : NK_EBREAKDOWN;
-    }
-    st.cnt[s] = 0;
-  }
+  g = block_sum(g, sh);
+  rr = block_sum(rr, sh);
+  store_parts(g, rr, part);
 }
 
 template <typename T>
-hipError_t cg_update(const VecLayout& L, CgState st, int maxit, T* x, T* r, const T* p, T* y,
-                     const T* dinv, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_upd<T>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, s, L.blk_seg,
-                     L.blk_first, st, maxit, x, r, p, y, dinv, part);
+hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p, T* s,
+                    const T* dinv, double* part, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_start<T>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream,
+                     L.blk_seg, b, w, r, u, p, s, dinv, part);
+  return hipGetLastError();
+}
+
+// One block per system: gamma = sum of (r,u) partials, rr = sum of (r,r)
+// partials, delta = sum of the system's dots.  mode 0: iteration, mode 1:
+// first step of a solve (tol2 is set from rr when tau2 > 0, for the inner
+// solves of the refinement).
+__global__ void __launch_bounds__(kFinThreads)
+    k_cg_finish(const int64_t* __restrict__ blk_first, const int64_t* __restrict__ dblk_first,
+                const double* __restrict__ part, const double* __restrict__ dots, CgState st,
+                int maxit, int fatal, int start, double tau2, const int32_t* __restrict__ outer_done,
+                const double* __restrict__ outer_tol2, const double* __restrict__ outer_rr) {
+  __shared__ double sh[kFinThreads / 64];
+  const int sg = blockIdx.x;
+  if (!start && st.done[sg]) return;
+  double g = 0.0, rr = 0.0, dl = 0.0;
+  // dots are padded per system to whole kSegAlign blocks (padding is zero)
+  const int64_t d0 = dblk_first[sg] * kSegAlign, d1 = dblk_first[sg + 1] * kSegAlign;
+#pragma unroll 4
+  for (int64_t i = d0 + threadIdx.x; i < d1; i += kFinThreads) dl += dots[i];
+#pragma unroll 4
+  for (int64_t b = blk_first[sg] + threadIdx.x; b < blk_first[sg + 1]; b += kFinThreads) {
+    g += part[2 * b];
+    rr += part[2 * b + 1];
+  }
+  g = block_sum<kFinThreads>(g, sh);
+  rr = block_sum<kFinThreads>(rr, sh);
+  dl = block_sum<kFinThreads>(dl, sh);
+  if (threadIdx.x != 0) return;
+  if (start) {
+    st.iters[sg] = 0;
+    st.status[sg] = 0;
+    st.rr[sg] = rr;
+    if (tau2 > 0.0) {
+      // inner solve of the refinement: reduce by tau, or only as far as the
+      // outer tolerance still needs (with a factor 1/2 of margin)
+      const double need = outer_rr[sg] > 0.0 ? 0.25 * outer_tol2[sg] / outer_rr[sg] : 0.0;
+      st.tol2[sg] = (need > tau2 ? need : tau2) * rr;
+    }
+    const bool od = outer_done != nullptr && outer_done[sg] != 0;
+    if (od || rr <= st.tol2[sg] || rr == 0.0) {
+      st.done[sg] = 1;
+      return;
+    }
+    st.done[sg] = 0;
+    if (!(dl > 0.0) || !isfinite(dl) || !isfinite(g)) {
+      st.done[sg] = 1;
+      if (fatal) st.status[sg] = NK_EBREAKDOWN;
+      return;
+    }
+    st.rz[sg] = g;
+    st.alpha[sg] = g / dl;
+    st.beta[sg] = 0.0;
+    return;
+  }
+  const int it = st.iters[sg] + 1;
+  st.iters[sg] = it;
+  st.rr[sg] = rr;
+  if (rr <= st.tol2[sg]) {
+    st.done[sg] = 1;
+    return;
+  }
+  if (!isfinite(rr) || !isfinite(g) || !isfinite(dl)) {
+    st.done[sg] = 1;
+    st.status[sg] = NK_EBREAKDOWN;
+    return;
+  }
+  if (it >= maxit) {
+    st.done[sg] = 1;
+    if (fatal) st.status[sg] = NK_ENOCONV;
+    return;
+  }
+  const double beta = g / st.rz[sg];
+  const double den = dl - beta * g / st.alpha[sg];
+  if (!(den > 0.0)) {
+    st.done[sg] = 1;
+    if (fatal) st.status[sg] = NK_EBREAKDOWN;
+    return;
+  }
+  st.beta[sg] = beta;
+  st.alpha[sg] = g / den;
+  st.rz[sg] = g;
+}
+
+hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
+                     const double* dots, CgState st, int maxit, bool fatal, bool start,
+                     double tau2, const int32_t* outer_done, const double* outer_tol2,
+                     const double* outer_rr, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_finish, dim3(nsys), dim3(kFinThreads), 0, stream, L.blk_first,
+                     Ld.blk_first, part, dots, st, maxit, fatal ? 1 : 0, start ? 1 : 0, tau2,
+                     outer_done, outer_tol2, outer_rr);
   return hipGetLastError();
 }
 
@@ -224,54 +316,6 @@ hipError_t vec_norm2(const VecLayout& L, const double* v, double* part, int32_t*
                      double rtol, double* tol2, hipStream_t s) {
   hipLaunchKernelGGL(k_norm2, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, s, L.blk_seg,
                      L.blk_first, v, part, cnt, out, rtol * rtol, tol2);
-  return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(kVecBlock)
-    k_inner_init(const int32_t* __restrict__ blk_seg, const int64_t* __restrict__ blk_first,
-                 CgState st, const int32_t* __restrict__ outer_done, double tau2,
-                 const double* __restrict__ r64, const float* __restrict__ dinv32,
-                 float* __restrict__ r32, float* __restrict__ d32, float* __restrict__ p32,
-                 float* __restrict__ y32, double* __restrict__ part) {
-  __shared__ double sh[kVecBlock / 64];
-  const int s = blk_seg[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-#pragma unroll
-  for (int c = 0; c < kPer; ++c) {
-    const int64_t i = base + c * kVecBlock;
-    const float ri = (float)r64[i];
-    r32[i] = ri;
-    d32[i] = 0.f;
-    p32[i] = 0.f;
-    y32[i] = 0.f;
-    const double rd = (double)ri;
-    rz += rd * rd * (double)dinv32[i];
-    rr += rd * rd;
-  }
-  const double a = block_sum(rz, sh), b = block_sum(rr, sh);
-  const int64_t b0 = blk_first[s], b1 = blk_first[s + 1];
-  if (!last_block(a, b, part, st.cnt, s, b1 - b0)) return;
-  double rzn, rrn;
-  sum_parts(part, b0, b1, sh, rzn, rrn);
-  if (threadIdx.x == 0) {
-    st.rz[s] = rzn;
-    st.rr[s] = rrn;
-    st.tol2[s] = tau2 * rrn;
-    st.beta[s] = 0.0;
-    st.iters[s] = 0;
-    st.status[s] = 0;
-    st.done[s] = (outer_done[s] || rrn == 0.0) ? 1 : 0;
-    st.cnt[s] = 0;
-  }
-}
-
-hipError_t cg_inner_init(const VecLayout& L, CgState st, const int32_t* outer_done, double tau,
-                         const double* r64, const float* dinv32, float* r32, float* d32,
-                         float* p32, float* y32, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_inner_init, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, s, L.blk_seg,
-                     L.blk_first, st, outer_done, tau * tau, r64, dinv32, r32, d32, p32, y32,
-                     part);
   return hipGetLastError();
 }
 
@@ -504,17 +548,15 @@ hipError_t cast_copy(const float* src, double* dst, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t cg_p_update<double>(const VecLayout&, CgState, const double*, const double*,
-                                        double*, hipStream_t);
-template hipError_t cg_p_update<float>(const VecLayout&, CgState, const float*, const float*,
-                                       float*, hipStream_t);
-template hipError_t cg_alpha<double>(int, const int64_t*, const double*, CgState, bool,
-                                     hipStream_t);
-template hipError_t cg_alpha<float>(int, const int64_t*, const double*, CgState, bool, hipStream_t);
-template hipError_t cg_update<double>(const VecLayout&, CgState, int, double*, double*,
-                                      const double*, double*, const double*, double*, hipStream_t);
-template hipError_t cg_update<float>(const VecLayout&, CgState, int, float*, float*, const float*,
-                                     float*, const float*, double*, hipStream_t);
+template hipError_t cg_update<double>(const VecLayout&, CgState, double*, double*, double*,
+                                      double*, double*, double*, const double*, double*,
+                                      hipStream_t);
+template hipError_t cg_update<float>(const VecLayout&, CgState, float*, float*, float*, float*,
+                                     float*, float*, const float*, double*, hipStream_t);
+template hipError_t cg_start<double>(const VecLayout&, const double*, double*, double*, double*,
+                                     double*, double*, const double*, double*, hipStream_t);
+template hipError_t cg_start<float>(const VecLayout&, const double*, float*, float*, float*,
+                                    float*, float*, const float*, double*, hipStream_t);
 template hipError_t pad_in<double>(int, const int64_t*, const int64_t*, const VecLayout&,
                                    const double*, const double*, double*, hipStream_t);
 template hipError_t pad_in<float>(int, const int64_t*, const int64_t*, const VecLayout&,

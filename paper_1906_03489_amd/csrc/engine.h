@@ -3,22 +3,28 @@
 // Section 3.3 of arXiv 1906.03489 evaluates an expansion at the quadrature
 // points by contracting one direction at a time (the sum-factorisation
 // display), across many elements of one collection concurrently ("SumFac").
-// On CDNA4 one element is handled by one "slot" of Q*Q threads.  Each thread
-// owns a pencil: a line of values along one direction, held in registers, so
-// every contraction is a register-local product with a uniform 1-D matrix
-// (read from the kernel arguments through the scalar cache).  Between the
-// three directions the pencils are re-oriented through LDS.
+//
+// CDNA4 mapping.  One element is handled by one "slot" of NT >= Q*Q threads.
+// Each thread owns a pencil (a line of values along one direction) in
+// registers, so every contraction is a register-local product with a 1-D
+// matrix that is uniform across the wavefront.  The stages loop over the
+// point index (k, j or i) without unrolling and unroll the mode index, so each
+// iteration needs exactly one row of B and of DB, which the scalar unit loads
+// from the kernel arguments; the FP64/FP32 FMAs take it as their scalar
+// operand.  Between directions the pencils are re-oriented through LDS.
 //
 // Forward (coefficients -> values and reference gradient at the points):
-//   K: thread (p,q)  contracts r -> k with B and DB        (n^2 pencils)
-//   J: thread (p,k)  contracts q -> j                      (n Q pencils)
-//   I: thread (j,k)  contracts p -> i                      (Q^2 pencils)
-// producing u, du/dxi_1, du/dxi_2, du/dxi_3 at points (i, j, k) in thread
-// (j, k).  The backward (transpose) sweep runs I', J', K' in reverse and sums
-// the four point fields into one set of coefficients:
-//   y = (B (x) B (x) B)^T m + sum_a (D_a (B (x) B (x) B))^T g_a.
-// Derivative factors are carried as separate tensors (t_B, t_D after K;
-// s_BB, s_DB, s_BD after J) so that no collocation-derivative pass is needed.
+//   K: thread (p,q)  r -> k with B and DB           -> t_B, t_D   [k][q][p]
+//   J: thread (p,k)  q -> j                         -> s_BB, s_DB, s_BD [k][j][p]
+//   I: thread (j,k)  p -> i, fused with the pointwise factors and with the
+//      transposed I stage, one point i per loop iteration
+// Backward (transpose), summing m and the three flux components:
+//   I': thread (j,k) i -> p                         -> s'_BB, s'_DB, s'_BD
+//   J': thread (p,k) j -> q                         -> t'_B, t'_D
+//   K': thread (p,q) k -> r                         -> coefficients
+// y = (B(x)B(x)B)^T m + sum_a (D_a(B(x)B(x)B))^T g_a, with the derivative
+// factors carried as separate tensors so no collocation-derivative pass is
+// needed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,6 +56,7 @@ struct DevArgs {
   const double* kappa;
   const int32_t* elem_seg;
   const int32_t* seg_done;
+  const int32_t* dslot;
 };
 
 template <typename T>
@@ -68,6 +75,7 @@ inline DevArgs<T> dev_args(const OpArgs& a) {
   d.kappa = a.kappa;
   d.elem_seg = a.elem_seg;
   d.seg_done = a.seg_done;
+  d.dslot = a.dslot;
   return d;
 }
 
@@ -84,254 +92,294 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
-// ---------------------------------------------------------------- 3-D engine
+// Slot synchronisation.  When every slot lies inside one wavefront (NT
+// divides 64) only the owning wavefront touches the slot's LDS, and LDS
+// operations of a wavefront complete in program order, so a compiler-level
+// fence is enough; otherwise the whole block synchronises.
+template <int NT>
+__device__ __forceinline__ void slot_sync() {
+  if constexpr (64 % NT == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
 
-// Forward sweep of one element.  `in` is the element's coefficient array (or
-// the global vector when ASM, indexed through l2g_e).  Results for thread t
-// = j + Q k: u[i], u1[i], u2[i], u3[i] at points (i, j, k).  Without DER only
-// u is produced.  Must be called by every thread of the block.
-template <typename T, int N, int Q, bool DER, bool ASM>
-__device__ __forceinline__ void fwd3(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool live,
-                                     const T* __restrict__ in, const int32_t* __restrict__ l2g_e,
-                                     int32_t (&gidx)[N], T (&xin)[N], T (&u)[Q], T (&u1)[Q],
-                                     T (&u2)[Q], T (&u3)[Q]) {
+// LDS scalars per slot: three tensors of Q*Q*N.
+template <int N, int Q>
+constexpr int slot_lds() {
+  return 3 * Q * Q * N;
+}
+
+// ---------------------------------------------------------------- stages
+// Every stage is executed by all threads of the block (barriers inside);
+// `act` masks the threads that own a pencil of a live element.
+
+// K: thread t = p + N q (< N^2) holds xin[r]; writes t_B (and t_D) [k][q][p].
+template <typename T, int N, int Q, bool DER>
+__device__ __forceinline__ void stage_k(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool act,
+                                        const T (&xin)[N]) {
   constexpr int NN = N * N, S = Q * Q * N;
-  // K: thread (p,q) = t < N^2 contracts r -> k
-  if (live && t < NN) {
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      if constexpr (ASM) {
-        const int32_t g = l2g_e[r * NN + t];
-        gidx[r] = g;
-        xin[r] = g >= 0 ? in[g] : T(0);
-      } else {
-        xin[r] = in[r * NN + t];
-      }
-    }
-#pragma unroll
+  if (act && t < NN) {
+#pragma unroll 2
     for (int k = 0; k < Q; ++k) {
+      const T* Bk = tb.B + k * N;
+      const T* Dk = tb.D + k * N;
       T sb = 0, sd = 0;
 #pragma unroll
       for (int r = 0; r < N; ++r) {
-        sb += tb.B[k * N + r] * xin[r];
-        if constexpr (DER) sd += tb.D[k * N + r] * xin[r];
+        sb += Bk[r] * xin[r];
+        if constexpr (DER) sd += Dk[r] * xin[r];
       }
       sm[k * NN + t] = sb;
       if constexpr (DER) sm[S + k * NN + t] = sd;
     }
   }
-  __syncthreads();
-  // J: thread (p,k) = t < N Q contracts q -> j
-  T sBB[Q], sDB[Q], sBD[Q];
+}
+
+// J: thread (p,k) = t < N Q reads t_B, t_D; writes s_BB, s_DB, s_BD [k][j][p].
+template <typename T, int N, int Q, int NT, bool DER>
+__device__ __forceinline__ void stage_j(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool act) {
+  constexpr int NN = N * N, S = Q * Q * N;
   const int pj = t % N, kj = t / N;
-  if (live && t < N * Q) {
-    T av[N], bv[N];
+  const bool me = act && t < N * Q;
+  T av[N], bv[N];
+  if (me) {
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       av[q] = sm[kj * NN + q * N + pj];
       if constexpr (DER) bv[q] = sm[S + kj * NN + q * N + pj];
     }
-#pragma unroll
+  }
+  slot_sync<NT>();
+  if (me) {
+#pragma unroll 2
     for (int j = 0; j < Q; ++j) {
+      const T* Bj = tb.B + j * N;
+      const T* Dj = tb.D + j * N;
       T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
       for (int q = 0; q < N; ++q) {
-        s0 += tb.B[j * N + q] * av[q];
+        s0 += Bj[q] * av[q];
         if constexpr (DER) {
-          s1 += tb.D[j * N + q] * av[q];
-          s2 += tb.B[j * N + q] * bv[q];
+          s1 += Dj[q] * av[q];
+          s2 += Bj[q] * bv[q];
         }
       }
-      sBB[j] = s0;
+      const int o = (kj * Q + j) * N + pj;
+      sm[o] = s0;
       if constexpr (DER) {
-        sDB[j] = s1;
-        sBD[j] = s2;
-      }
-    }
-  }
-  __syncthreads();
-  if (live && t < N * Q) {
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      sm[(kj * Q + j) * N + pj] = sBB[j];
-      if constexpr (DER) {
-        sm[S + (kj * Q + j) * N + pj] = sDB[j];
-        sm[2 * S + (kj * Q + j) * N + pj] = sBD[j];
-      }
-    }
-  }
-  __syncthreads();
-  // I: thread (j,k) = t < Q^2 contracts p -> i
-  if (live) {
-    T av[N], bv[N], cv[N];
-#pragma unroll
-    for (int p = 0; p < N; ++p) {
-      av[p] = sm[t * N + p];
-      if constexpr (DER) {
-        bv[p] = sm[S + t * N + p];
-        cv[p] = sm[2 * S + t * N + p];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll
-      for (int p = 0; p < N; ++p) {
-        s0 += tb.B[i * N + p] * av[p];
-        if constexpr (DER) {
-          s1 += tb.D[i * N + p] * av[p];
-          s2 += tb.B[i * N + p] * bv[p];
-          s3 += tb.B[i * N + p] * cv[p];
-        }
-      }
-      u[i] = s0;
-      if constexpr (DER) {
-        u1[i] = s1;
-        u2[i] = s2;
-        u3[i] = s3;
+        sm[S + o] = s1;
+        sm[2 * S + o] = s2;
       }
     }
   }
 }
 
-// Backward (transpose) sweep: from m, g1, g2, g3 at points (i, j, k) of
-// thread t = j + Q k to coefficients yv[r] of thread (p,q) = t < N^2.
-// Without DER only m is used.  Must be called by every thread; the caller
-// has synchronised so that sm may be overwritten.
+// I-stage inputs of thread (j,k) = t < Q^2: s_BB, s_DB, s_BD [k][j][p].
 template <typename T, int N, int Q, bool DER>
-__device__ __forceinline__ void bwd3(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool live,
-                                     const T (&m)[Q], const T (&g1)[Q], const T (&g2)[Q],
-                                     const T (&g3)[Q], T (&yv)[N]) {
+__device__ __forceinline__ void load_i(const T* __restrict__ sm, int t, T (&av)[N], T (&bv)[N],
+                                       T (&cv)[N]) {
+  constexpr int S = Q * Q * N;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    av[p] = sm[t * N + p];
+    if constexpr (DER) {
+      bv[p] = sm[S + t * N + p];
+      cv[p] = sm[2 * S + t * N + p];
+    }
+  }
+}
+
+// Store the I' accumulators of thread (j,k) as s'_BB, s'_DB, s'_BD [k][j][p].
+template <typename T, int N, int Q, bool DER>
+__device__ __forceinline__ void store_i(T* __restrict__ sm, int t, const T (&sa)[N],
+                                        const T (&sb)[N], const T (&sc)[N]) {
+  constexpr int S = Q * Q * N;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    sm[t * N + p] = sa[p];
+    if constexpr (DER) {
+      sm[S + t * N + p] = sb[p];
+      sm[2 * S + t * N + p] = sc[p];
+    }
+  }
+}
+
+// J': thread (p,k) = t < N Q sums over j; writes t'_B, t'_D [k][q][p].
+template <typename T, int N, int Q, int NT, bool DER>
+__device__ __forceinline__ void stage_jt(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t,
+                                         bool act) {
   constexpr int NN = N * N, S = Q * Q * N;
-  // I': thread (j,k) contracts i -> p
-  if (live) {
-#pragma unroll
-    for (int p = 0; p < N; ++p) {
-      T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        s0 += tb.B[i * N + p] * m[i];
-        if constexpr (DER) {
-          s0 += tb.D[i * N + p] * g1[i];
-          s1 += tb.B[i * N + p] * g2[i];
-          s2 += tb.B[i * N + p] * g3[i];
-        }
-      }
-      sm[t * N + p] = s0;
-      if constexpr (DER) {
-        sm[S + t * N + p] = s1;
-        sm[2 * S + t * N + p] = s2;
-      }
-    }
-  }
-  __syncthreads();
-  // J': thread (p,k) = t < N Q contracts j -> q
   const int pj = t % N, kj = t / N;
+  const bool me = act && t < N * Q;
   T tB[N], tD[N];
-  if (live && t < N * Q) {
-    T av[Q], bv[Q], cv[Q];
 #pragma unroll
+  for (int q = 0; q < N; ++q) tB[q] = tD[q] = T(0);
+  if (me) {
+#pragma unroll 2
     for (int j = 0; j < Q; ++j) {
-      av[j] = sm[(kj * Q + j) * N + pj];
+      const int o = (kj * Q + j) * N + pj;
+      const T a = sm[o];
+      T b = 0, c = 0;
       if constexpr (DER) {
-        bv[j] = sm[S + (kj * Q + j) * N + pj];
-        cv[j] = sm[2 * S + (kj * Q + j) * N + pj];
+        b = sm[S + o];
+        c = sm[2 * S + o];
       }
-    }
+      const T* Bj = tb.B + j * N;
+      const T* Dj = tb.D + j * N;
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      T s0 = 0, s1 = 0;
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        s0 += tb.B[j * N + q] * av[j];
+      for (int q = 0; q < N; ++q) {
+        tB[q] += Bj[q] * a;
         if constexpr (DER) {
-          s0 += tb.D[j * N + q] * bv[j];
-          s1 += tb.B[j * N + q] * cv[j];
+          tB[q] += Dj[q] * b;
+          tD[q] += Bj[q] * c;
         }
       }
-      tB[q] = s0;
-      if constexpr (DER) tD[q] = s1;
     }
   }
-  __syncthreads();
-  if (live && t < N * Q) {
+  slot_sync<NT>();
+  if (me) {
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       sm[kj * NN + q * N + pj] = tB[q];
       if constexpr (DER) sm[S + kj * NN + q * N + pj] = tD[q];
     }
   }
-  __syncthreads();
-  // K': thread (p,q) = t < N^2 contracts k -> r
-  if (live && t < NN) {
-    T av[Q], bv[Q];
+}
+
+// K': thread (p,q) = t < N^2 sums over k into y[r].
+template <typename T, int N, int Q, bool DER>
+__device__ __forceinline__ void stage_kt(const Tab<T, N, Q>& tb, const T* __restrict__ sm, int t,
+                                         bool act, T (&yv)[N]) {
+  constexpr int NN = N * N, S = Q * Q * N;
 #pragma unroll
+  for (int r = 0; r < N; ++r) yv[r] = T(0);
+  if (act && t < NN) {
+#pragma unroll 2
     for (int k = 0; k < Q; ++k) {
-      av[k] = sm[k * NN + t];
-      if constexpr (DER) bv[k] = sm[S + k * NN + t];
-    }
+      const T a = sm[k * NN + t];
+      const T b = DER ? sm[S + k * NN + t] : T(0);
+      const T* Bk = tb.B + k * N;
+      const T* Dk = tb.D + k * N;
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-      T s0 = 0;
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        s0 += tb.B[k * N + r] * av[k];
-        if constexpr (DER) s0 += tb.D[k * N + r] * bv[k];
+      for (int r = 0; r < N; ++r) {
+        yv[r] += Bk[r] * a;
+        if constexpr (DER) yv[r] += Dk[r] * b;
       }
-      yv[r] = s0;
     }
   }
 }
 
-// Sum of v over the threads of a slot (NT threads), result valid in thread
-// t == 0 of the slot.  `red` is a block-shared scratch of blockDim doubles.
+// Sum of v over the threads of a slot, valid in thread t == 0 of the slot.
 template <int NT>
 __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int t) {
-  __syncthreads();
-  red[slot * NT + t] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (t == 0) {
-    for (int i = 0; i < NT; ++i) s += red[slot * NT + i];
+  if constexpr (NT == 64) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  } else {
+    __syncthreads();
+    red[slot * NT + t] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0) {
+      for (int i = 0; i < NT; ++i) s += red[slot * NT + i];
+    }
+    return s;
   }
-  return s;
 }
 
-// Helmholtz of one element per slot: forward sweep, pointwise geometric
-// factors and lambda mass term, backward sweep; local store or (ASM) atomic
-// scatter-add into the global vector with the element's p_e . (H_e p_e).
+// Helmholtz of one element per slot.  The I stage, the pointwise geometric
+// factors with the lambda mass term and the transposed I stage run as one
+// loop over the point index i; the factors of point i+1 are loaded while
+// point i is processed.  Local store or (ASM) atomic scatter-add into the
+// global vector with the element's p_e . (H_e p_e).
 template <typename T, int N, int Q, int NT, bool ASM>
 __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
                                            const DevArgs<T>& a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q;
   const int64_t ee = live ? e : 0;
-  const T* fe = a.fac + ee * (int64_t)(kNF3 * Q3);
+  const bool pq = live && t < NN;
   int32_t gidx[N];
   T xin[N];
-  T u[Q], u1[Q], u2[Q], u3[Q];
-  const T* src = ASM ? a.in : a.in + ee * N3;
-  fwd3<T, N, Q, true, ASM>(tb, sm, t, live, src, ASM ? a.l2g + ee * N3 : nullptr, gidx, xin, u,
-                           u1, u2, u3);
-  const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
-  T m[Q], g1[Q], g2[Q], g3[Q], yv[N];
-  if (live) {
+  if (pq) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T* fp = fe + i * QQ + t;
-      const T wj = fp[0], G11 = fp[Q3], G12 = fp[2 * Q3], G13 = fp[3 * Q3], G22 = fp[4 * Q3],
-              G23 = fp[5 * Q3], G33 = fp[6 * Q3];
-      m[i] = lam * wj * u[i];
-      g1[i] = G11 * u1[i] + G12 * u2[i] + G13 * u3[i];
-      g2[i] = G12 * u1[i] + G22 * u2[i] + G23 * u3[i];
-      g3[i] = G13 * u1[i] + G23 * u2[i] + G33 * u3[i];
+    for (int r = 0; r < N; ++r) {
+      if constexpr (ASM) {
+        const int32_t g = a.l2g[ee * N3 + r * NN + t];
+        gidx[r] = g;
+        xin[r] = g >= 0 ? a.in[g] : T(0);
+      } else {
+        xin[r] = a.in[ee * N3 + r * NN + t];
+      }
     }
   }
-  __syncthreads();
-  bwd3<T, N, Q, true>(tb, sm, t, live, m, g1, g2, g3, yv);
+  stage_k<T, N, Q, true>(tb, sm, t, live, xin);
+  slot_sync<NT>();
+  stage_j<T, N, Q, NT, true>(tb, sm, t, live);
+  slot_sync<NT>();
+  const bool jk = live && t < QQ;
+  T av[N], bv[N], cv[N], sa[N], sb[N], sc[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
+  if (jk) {
+    load_i<T, N, Q, true>(sm, t, av, bv, cv);
+    const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
+    const T* fp = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
+    // one point: forward I contraction, factors, transposed I contraction
+    auto point = [&](int i, const T (&f)[kNF3]) {
+      const T* Bi = tb.B + i * N;
+      const T* Di = tb.D + i * N;
+      T u = 0, u1 = 0, u2 = 0, u3 = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        u += Bi[p] * av[p];
+        u1 += Di[p] * av[p];
+        u2 += Bi[p] * bv[p];
+        u3 += Bi[p] * cv[p];
+      }
+      const T m = lam * f[0] * u;
+      const T g1 = f[1] * u1 + f[2] * u2 + f[3] * u3;
+      const T g2 = f[2] * u1 + f[4] * u2 + f[5] * u3;
+      const T g3 = f[3] * u1 + f[5] * u2 + f[6] * u3;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        sa[p] += Bi[p] * m + Di[p] * g1;
+        sb[p] += Bi[p] * g2;
+        sc[p] += Bi[p] * g3;
+      }
+    };
+    auto load = [&](int i, T (&f)[kNF3]) {
+#pragma unroll
+      for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
+    };
+    // two register sets alternate so the factors of the next point are in
+    // flight while the current point is computed
+    T fA[kNF3], fB[kNF3];
+    load(0, fA);
+#pragma unroll 1
+    for (int i = 0; i < Q; i += 2) {
+      // loads are unconditional (clamped index) so that the waits for them
+      // can be placed right before their first use
+      load(i + 1 < Q ? i + 1 : Q - 1, fB);
+      point(i, fA);
+      load(i + 2 < Q ? i + 2 : Q - 1, fA);
+      if (Q % 2 == 0 || i + 1 < Q) point(i + 1, fB);
+    }
+  }
+  slot_sync<NT>();
+  if (jk) store_i<T, N, Q, true>(sm, t, sa, sb, sc);
+  slot_sync<NT>();
+  stage_jt<T, N, Q, NT, true>(tb, sm, t, live);
+  slot_sync<NT>();
+  T yv[N];
+  stage_kt<T, N, Q, true>(tb, sm, t, live, yv);
   if constexpr (ASM) {
     double dp = 0.0;
-    if (live && t < NN) {
+    if (pq) {
 #pragma unroll
       for (int r = 0; r < N; ++r) {
         if (gidx[r] >= 0) atomic_add(a.out + gidx[r], yv[r]);
@@ -339,25 +387,34 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
       }
     }
     const double s = slot_sum<NT>(dp, red, slot, t);
-    if (live && t == 0 && a.dots) a.dots[e] = s;
+    if (live && t == 0 && a.dots) a.dots[a.dslot ? a.dslot[e] : e] = s;
   } else {
-    if (live && t < NN) {
+    if (pq) {
 #pragma unroll
-      for (int r = 0; r < N; ++r) a.out[e * N3 + r * NN + t] = yv[r];
+      for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   }
 }
 
+// Threads per slot: Q^2 rounded up to a divisor of 64 when that keeps a slot
+// inside one wavefront (then no block barriers are needed), else Q^2.
+template <int Q>
+constexpr int slot_threads() {
+  return Q * Q <= 1 ? 1 : Q * Q <= 4 ? 4 : Q * Q <= 16 ? 16 : Q * Q <= 64 ? 64 : Q * Q;
+}
+
 template <typename T, int N, int Q, int EPB, int OP>
-__global__ void __launch_bounds__(EPB * Q * Q)
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
     k_op3(const Tab<T, N, Q> tb, const DevArgs<T> a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q, S = Q * Q * N;
-  constexpr int NT = QQ;
+  constexpr int NT = slot_threads<Q>();
   constexpr bool DER = (OP == OP_HELM || OP == OP_HELM_ASM || OP == OP_GRAD || OP == OP_RHS);
   constexpr int NTEN = DER ? 3 : 1;
   constexpr bool ASM = (OP == OP_HELM_ASM);
-  __shared__ T smem[EPB * NTEN * S];
-  __shared__ double red[(ASM || OP == OP_GRAD) ? EPB * NT : 1];
+  // BwdTrans / IProduct stage whole point arrays (Q^3) for coalesced access
+  constexpr int SLOT = (NTEN * S > Q3) ? NTEN * S : Q3;
+  __shared__ T smem[EPB * SLOT];
+  __shared__ double red[((ASM || OP == OP_GRAD) && NT != 64) ? EPB * NT : 1];
 
   const int slot = threadIdx.x / NT;
   const int t = threadIdx.x - slot * NT;
@@ -365,79 +422,157 @@ __global__ void __launch_bounds__(EPB * Q * Q)
   const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
   bool live = e < a.nelem;
   if (live && a.elem_seg != nullptr) live = a.seg_done[a.elem_seg[e]] == 0;
-  T* sm = smem + slot * NTEN * S;
-  // factor f at point (i, t) of element e
-  const T* fe = a.fac + (live ? e : 0) * (int64_t)(kNF3 * Q3);
-  auto F = [&](int f, int i) -> T { return fe[(f * Q + i) * QQ + t]; };
-
-  int32_t gidx[N];
-  T xin[N];
-  T u[Q], u1[Q], u2[Q], u3[Q];
+  const int64_t ee = live ? e : 0;
+  T* sm = smem + slot * SLOT;
+  const T* fe = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
 
   if constexpr (OP == OP_BWD) {
-    fwd3<T, N, Q, false, false>(tb, sm, t, live, a.in + (live ? e : 0) * N3, nullptr, gidx, xin, u,
-                                u1, u2, u3);
-    if (live) {
-      T* o = a.out + e * Q3 + t * Q;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) o[i] = u[i];
-    }
-  } else if constexpr (OP == OP_IPROD) {
-    T m[Q], yv[N];
-    if (live) {
-      const T* f = a.in + e * Q3 + t * Q;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) m[i] = F(0, i) * f[i];
-    }
-    bwd3<T, N, Q, false>(tb, sm, t, live, m, m, m, m, yv);
+    T xin[N];
     if (live && t < NN) {
 #pragma unroll
-      for (int r = 0; r < N; ++r) a.out[e * N3 + r * NN + t] = yv[r];
+      for (int r = 0; r < N; ++r) xin[r] = a.in[ee * N3 + r * NN + t];
+    }
+    stage_k<T, N, Q, false>(tb, sm, t, live, xin);
+    slot_sync<NT>();
+    stage_j<T, N, Q, NT, false>(tb, sm, t, live);
+    slot_sync<NT>();
+    T av[N], bv[N], cv[N];
+    if (live && t < QQ) load_i<T, N, Q, false>(sm, t, av, bv, cv);
+    slot_sync<NT>();
+    if (live && t < QQ) {
+#pragma unroll 2
+      for (int i = 0; i < Q; ++i) {
+        const T* Bi = tb.B + i * N;
+        T u = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) u += Bi[p] * av[p];
+        sm[t * Q + i] = u;
+      }
+    }
+    slot_sync<NT>();
+    // the slot writes its Q^3 point values contiguously
+    if (live) {
+      T* o = a.out + ee * Q3;
+      for (int c = t; c < Q3; c += NT) o[c] = sm[c];
+    }
+  } else if constexpr (OP == OP_IPROD) {
+    if (live) {
+      const T* f = a.in + ee * Q3;
+      for (int c = t; c < Q3; c += NT) sm[c] = f[c];
+    }
+    slot_sync<NT>();
+    T sa[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) sa[p] = T(0);
+    if (live && t < QQ) {
+#pragma unroll 2
+      for (int i = 0; i < Q; ++i) {
+        const T m = fe[i * QQ] * sm[t * Q + i];
+        const T* Bi = tb.B + i * N;
+#pragma unroll
+        for (int p = 0; p < N; ++p) sa[p] += Bi[p] * m;
+      }
+    }
+    slot_sync<NT>();
+    if (live && t < QQ) store_i<T, N, Q, false>(sm, t, sa, sa, sa);
+    slot_sync<NT>();
+    stage_jt<T, N, Q, NT, false>(tb, sm, t, live);
+    slot_sync<NT>();
+    T yv[N];
+    stage_kt<T, N, Q, false>(tb, sm, t, live, yv);
+    if (live && t < NN) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   } else if constexpr (OP == OP_HELM || OP == OP_HELM_ASM) {
     helm3_body<T, N, Q, NT, ASM>(tb, sm, red, slot, t, live, e, a);
   } else if constexpr (OP == OP_RHS) {
-    const T lam = (T)(a.lam ? a.lam[live ? e : 0] : a.lam0);
-    T m[Q], g1[Q], g2[Q], g3[Q], yv[N];
-    if (live) {
-      const T* uu = a.in + e * Q3 + t * Q;
-      const double* du = a.in2 + e * 3 * Q3 + t * Q;
+    const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
+    T sa[N], sb[N], sc[N];
 #pragma unroll
+    for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
+    if (live && t < QQ) {
+      const T* uu = a.in + ee * Q3 + t * Q;
+      const double* du = a.in2 + ee * 3 * Q3 + t * Q;
+#pragma unroll 1
       for (int i = 0; i < Q; ++i) {
+        const T* fp = fe + i * QQ;
         const T d1 = du[i], d2 = du[Q3 + i], d3 = du[2 * Q3 + i];
-        m[i] = lam * F(0, i) * uu[i];
-        g1[i] = F(1, i) * d1 + F(2, i) * d2 + F(3, i) * d3;
-        g2[i] = F(2, i) * d1 + F(4, i) * d2 + F(5, i) * d3;
-        g3[i] = F(3, i) * d1 + F(5, i) * d2 + F(6, i) * d3;
+        const T m = lam * fp[0] * uu[i];
+        const T g1 = fp[Q3] * d1 + fp[2 * Q3] * d2 + fp[3 * Q3] * d3;
+        const T g2 = fp[2 * Q3] * d1 + fp[4 * Q3] * d2 + fp[5 * Q3] * d3;
+        const T g3 = fp[3 * Q3] * d1 + fp[5 * Q3] * d2 + fp[6 * Q3] * d3;
+        const T* Bi = tb.B + i * N;
+        const T* Di = tb.D + i * N;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          sa[p] += Bi[p] * m + Di[p] * g1;
+          sb[p] += Bi[p] * g2;
+          sc[p] += Bi[p] * g3;
+        }
       }
+      store_i<T, N, Q, true>(sm, t, sa, sb, sc);
     }
-    bwd3<T, N, Q, true>(tb, sm, t, live, m, g1, g2, g3, yv);
+    slot_sync<NT>();
+    stage_jt<T, N, Q, NT, true>(tb, sm, t, live);
+    slot_sync<NT>();
+    T yv[N];
+    stage_kt<T, N, Q, true>(tb, sm, t, live, yv);
     if (live && t < NN) {
 #pragma unroll
-      for (int r = 0; r < N; ++r) a.out[e * N3 + r * NN + t] = yv[r];
+      for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   } else if constexpr (OP == OP_GRAD) {
     // in = z_loc, in2 = u_loc; out = dkappa [E][Q^3] (may be null), out2 = dlambda [E]
-    T z[Q], z1[Q], z2[Q], z3[Q];
-    fwd3<T, N, Q, true, false>(tb, sm, t, live, a.in + (live ? e : 0) * N3, nullptr, gidx, xin, z,
-                               z1, z2, z3);
-    __syncthreads();
-    fwd3<T, N, Q, true, false>(tb, sm, t, live, (const T*)a.in2 + (live ? e : 0) * N3, nullptr,
-                               gidx, xin, u, u1, u2, u3);
-    double dl = 0.0;
-    if (live) {
-      const double* kap = a.kappa ? a.kappa + e * Q3 + t * Q : nullptr;
+    T zv[3][N], uv[3][N];
 #pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const T* src = pass == 0 ? a.in : (const T*)a.in2;
+      T xin[N];
+      if (live && t < NN) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) xin[r] = src[ee * N3 + r * NN + t];
+      }
+      if (pass == 1) slot_sync<NT>();
+      stage_k<T, N, Q, true>(tb, sm, t, live, xin);
+      slot_sync<NT>();
+      stage_j<T, N, Q, NT, true>(tb, sm, t, live);
+      slot_sync<NT>();
+      if (live && t < QQ) {
+        if (pass == 0)
+          load_i<T, N, Q, true>(sm, t, zv[0], zv[1], zv[2]);
+        else
+          load_i<T, N, Q, true>(sm, t, uv[0], uv[1], uv[2]);
+      }
+    }
+    double dl = 0.0;
+    if (live && t < QQ) {
+      const double* kap = a.kappa ? a.kappa + ee * Q3 + t * Q : nullptr;
+#pragma unroll 1
       for (int i = 0; i < Q; ++i) {
-        const T wj = F(0, i);
+        const T* Bi = tb.B + i * N;
+        const T* Di = tb.D + i * N;
+        T z = 0, z1 = 0, z2 = 0, z3 = 0, u = 0, u1 = 0, u2 = 0, u3 = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          z += Bi[p] * zv[0][p];
+          z1 += Di[p] * zv[0][p];
+          z2 += Bi[p] * zv[1][p];
+          z3 += Bi[p] * zv[2][p];
+          u += Bi[p] * uv[0][p];
+          u1 += Di[p] * uv[0][p];
+          u2 += Bi[p] * uv[1][p];
+          u3 += Bi[p] * uv[2][p];
+        }
+        const T* fp = fe + i * QQ;
         const T ik = kap ? T(1) / (T)kap[i] : T(1);
-        const T G11 = F(1, i) * ik, G12 = F(2, i) * ik, G13 = F(3, i) * ik, G22 = F(4, i) * ik,
-                G23 = F(5, i) * ik, G33 = F(6, i) * ik;
-        const T q1 = G11 * u1[i] + G12 * u2[i] + G13 * u3[i];
-        const T q2 = G12 * u1[i] + G22 * u2[i] + G23 * u3[i];
-        const T q3 = G13 * u1[i] + G23 * u2[i] + G33 * u3[i];
-        if (a.out) a.out[e * Q3 + t * Q + i] = -(z1[i] * q1 + z2[i] * q2 + z3[i] * q3);
-        dl += (double)(wj * z[i] * u[i]);
+        const T G11 = fp[Q3] * ik, G12 = fp[2 * Q3] * ik, G13 = fp[3 * Q3] * ik,
+                G22 = fp[4 * Q3] * ik, G23 = fp[5 * Q3] * ik, G33 = fp[6 * Q3] * ik;
+        const T q1 = G11 * u1 + G12 * u2 + G13 * u3;
+        const T q2 = G12 * u1 + G22 * u2 + G23 * u3;
+        const T q3 = G13 * u1 + G23 * u2 + G33 * u3;
+        if (a.out) a.out[ee * Q3 + t * Q + i] = -(z1 * q1 + z2 * q2 + z3 * q3);
+        dl += (double)(fp[0] * z * u);
       }
     }
     const double s = slot_sum<NT>(dl, red, slot, t);

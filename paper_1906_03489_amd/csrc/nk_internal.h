@@ -17,7 +17,7 @@ constexpr int kMaxP = 10;          // n = P+1 <= 11, Q = P+2 <= 12
 constexpr int kNF3 = 7;            // per-point factors in 3-D
 constexpr int kNF2 = 4;            // per-point factors in 2-D
 constexpr int kVecBlock = 256;     // threads per block of the CG vector kernels
-constexpr int64_t kSegAlign = 1024;  // batched systems: DOF ranges padded to this
+constexpr int64_t kSegAlign = 2048;  // DOF ranges of each system padded to this (one vector block)
 
 // ------------------------------------------------------------ host tables
 void gll_points(int Q, double* x, double* w);
@@ -64,6 +64,7 @@ struct OpArgs {
   const double* kappa = nullptr;  // GRAD: kappa per point (null = 1)
   const int32_t* elem_seg = nullptr;  // batched: segment of each element
   const int32_t* seg_done = nullptr;  // batched: converged flag per segment
+  const int32_t* dslot = nullptr;     // assembled ops: where element e's p.Ap goes in dots
   int tile = 0;                 // tile configuration index
   hipStream_t stream = nullptr;
 };

@@ -20,7 +20,7 @@ static hipError_t run3(const OpArgs& a) {
   const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP>), dim3((unsigned)nblk), dim3(EPB * Q * Q), 0,
+  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP>), dim3((unsigned)nblk), dim3(EPB * slot_threads<Q>()), 0,
                      a.stream, tb, dev_args<T>(a));
   return hipGetLastError();
 }

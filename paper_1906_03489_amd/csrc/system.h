@@ -34,14 +34,15 @@ struct VecLayout {
 
 // Kernel launchers (cg.hip).
 template <typename T>
-hipError_t cg_p_update(const VecLayout& L, CgState st, const T* r, const T* dinv, T* p,
-                       hipStream_t s);
+hipError_t cg_update(const VecLayout& L, CgState st, T* x, T* r, T* u, T* p, T* s, T* w,
+                     const T* dinv, double* part, hipStream_t stream);
 template <typename T>
-hipError_t cg_alpha(int nsys, const int64_t* elem_off, const double* dots, CgState st,
-                    bool fatal_breakdown, hipStream_t s);
-template <typename T>
-hipError_t cg_update(const VecLayout& L, CgState st, int maxit, T* x, T* r, const T* p, T* y,
-                     const T* dinv, double* part, hipStream_t s);
+hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p, T* s,
+                    const T* dinv, double* part, hipStream_t stream);
+hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
+                     const double* dots, CgState st, int maxit, bool fatal, bool start,
+                     double tau2, const int32_t* outer_done, const double* outer_tol2,
+                     const double* outer_rr, hipStream_t stream);
 
 // r = (b - y) on free DOFs (dinv > 0), 0 elsewhere; y is reset to 0; optionally
 // p = 0; per system rz = r.dinv.r, rr = r.r; done = rr <= tol2.
@@ -50,10 +51,6 @@ hipError_t cg_residual(const VecLayout& L, CgState st, const double* b, double* 
 // per-system squared norm of v into out[s] (and tol2 = rtol^2 * out when tol2 != null)
 hipError_t vec_norm2(const VecLayout& L, const double* v, double* part, int32_t* cnt, double* out,
                      double rtol, double* tol2, hipStream_t s);
-// inner FP32 start: r32 = r64, d = p = y = 0, rz/rr, tol2 = tau^2 rr, done = outer_done || rr == 0
-hipError_t cg_inner_init(const VecLayout& L, CgState st, const int32_t* outer_done, double tau,
-                         const double* r64, const float* dinv32, float* r32, float* d32,
-                         float* p32, float* y32, double* part, hipStream_t s);
 // x += d on systems not yet converged
 hipError_t cg_correct(const VecLayout& L, const int32_t* outer_done, const float* d32, double* x,
                       hipStream_t s);
@@ -91,6 +88,13 @@ struct nk_system_s {
   int64_t nuser = 0;                      // user global length (sum of system DOFs)
   std::vector<int64_t> dof_off, pdof_off, elem_off, blk_first;
   nk::VecLayout L;
+  // per-element p.Ap slots, padded per system like a vector
+  std::vector<int64_t> pdot_off, dblk_first;
+  nk::VecLayout Ld;
+  int64_t* d_dblk_first = nullptr;
+  int32_t* d_dblk_seg = nullptr;
+  int32_t* dslot = nullptr;
+  double* part_d = nullptr;
   int64_t* d_dof_off = nullptr;
   int64_t* d_pdof_off = nullptr;
   int64_t* d_elem_off = nullptr;
@@ -105,7 +109,9 @@ struct nk_system_s {
   float* dinv32 = nullptr;
   // work vectors (padded)
   double *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *y = nullptr;
+  double *u = nullptr, *s = nullptr;
   float *r32 = nullptr, *p32 = nullptr, *y32 = nullptr, *d32 = nullptr;
+  float *u32 = nullptr, *s32 = nullptr;
   double* dots = nullptr;                 // per element
   double* part = nullptr;                 // per vector block x 2
   // per-system scalars

@@ -8,19 +8,21 @@ namespace nk {
 
 constexpr int kMaxTiles = 3;
 
-// 3-D: elements per block, 0 = no candidate.
+// 3-D: elements per block, 0 = no candidate.  Slots hold slot_threads<Q>()
+// threads: Q*Q rounded up to 16 or 64 for Q <= 8 (a slot never straddles a
+// wavefront), Q*Q above.
 constexpr int kTileEPB3[11][kMaxTiles] = {
     {0, 0, 0},   // P = 0 (unused)
-    {7, 28, 0},  // Q = 3:  63 / 252 threads
-    {4, 16, 0},  // Q = 4:  64 / 256
-    {5, 10, 0},  // Q = 5: 125 / 250
-    {2, 7, 0},   // Q = 6:  72 / 252
-    {1, 5, 0},   // Q = 7:  49 / 245
-    {1, 2, 4},   // Q = 8:  64 / 128 / 256
-    {1, 3, 0},   // Q = 9:  81 / 243
-    {1, 2, 0},   // Q = 10: 100 / 200
-    {1, 2, 0},   // Q = 11: 121 / 242
-    {1, 0, 0},   // Q = 12: 144
+    {4, 16, 0},  // Q = 3:  slot 16:  64 / 256 threads
+    {4, 16, 0},  // Q = 4:  slot 16:  64 / 256
+    {1, 4, 0},   // Q = 5:  slot 64:  64 / 256
+    {1, 4, 0},   // Q = 6:  slot 64
+    {1, 4, 0},   // Q = 7:  slot 64
+    {1, 2, 4},   // Q = 8:  slot 64:  64 / 128 / 256
+    {1, 3, 0},   // Q = 9:  slot 81:  81 / 243
+    {1, 2, 0},   // Q = 10: slot 100: 100 / 200
+    {1, 2, 0},   // Q = 11: slot 121: 121 / 242
+    {1, 0, 0},   // Q = 12: slot 144
 };
 
 // 2-D: elements per block (slot = Q threads).
@@ -31,7 +33,7 @@ constexpr int kTileEPB2[11][kMaxTiles] = {
 
 // Elements per block of the single mixed-order launch (256 threads).
 constexpr int kVarpThreads = 256;
-constexpr int kVarpEPB[11] = {0, 28, 16, 10, 7, 5, 4, 3, 2, 2, 1};
+constexpr int kVarpEPB[11] = {0, 16, 16, 4, 4, 4, 4, 3, 2, 2, 1};
 
 constexpr bool op_has_tiles(int op) { return op <= 3; }
 

@@ -56,7 +56,8 @@ struct VarpDev {
 template <typename T, int P>
 __device__ __forceinline__ void varp_body(const VarpDev<T>& a, const VarpGroup& G, int64_t li,
                                           int64_t lam_off, T* smem) {
-  constexpr int N = P + 1, Q = P + 2, NT = Q * Q, EPB = kVarpEPB[P];
+  constexpr int N = P + 1, Q = P + 2, NT = slot_threads<Q>(), EPB = kVarpEPB[P];
+  static_assert(EPB * NT <= kVarpThreads, "varp tile");
   const int slot = threadIdx.x / NT;
   const int t = threadIdx.x - slot * NT;
   const int64_t e = li * EPB + slot;
@@ -69,7 +70,7 @@ __device__ __forceinline__ void varp_body(const VarpDev<T>& a, const VarpGroup& 
   d.fac = a.fac + G.f0;
   d.lam = a.lam ? a.lam + lam_off : nullptr;
   d.lam0 = a.lam0;
-  T* sm = smem + (slot < EPB ? slot : 0) * 3 * NT * N;
+  T* sm = smem + (slot < EPB ? slot : 0) * 3 * Q * Q * N;
   helm3_body<T, N, Q, NT, false>(tb, sm, nullptr, slot, t, live, e, d);
 }
 

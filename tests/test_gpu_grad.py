@@ -1,0 +1,96 @@
+"""GPU parity of the adjoint gradient kernel and of the autograd solve.
+
+The gradient kernel -z^T (dA/dtheta) u (per point for kappa, per element for
+lambda) against the oracle's explicit single-point matrices on the same u, z;
+the torch.autograd Helmholtz solve against the oracle's adjoint gradient and
+against central finite differences of the GPU solve itself."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.assembly import direct_solve
+from gpu_common import FP64_RTOL, assert_close, jacobians, nk, rel_err, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,shape,P", [(3, (2, 2, 1), 2), (3, (2, 1, 1), 4), (2, (3, 2), 3)])
+def test_param_grad_kernel_matches_oracle(dim, shape, P):
+    torch_cuda()
+    m = nk()
+    Q = P + 2
+    Jg, Jo, lat = jacobians(shape, P, W.WARP_AMPLITUDE if dim == 3 else 0.0)
+    E, nq = lat.nelem, Q ** dim
+    rng = np.random.default_rng(21 + P)
+    kap = rng.uniform(0.5, 2.0, (E, nq))
+    lam = rng.uniform(0.5, 2.0, E)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    ops = oracle.ElementOps(dim, P, Q, Jo, kappa=kap, lam=lam)
+    u = rng.uniform(-1, 1, ng)
+    z = rng.uniform(-1, 1, ng)
+    u[dm.astype(bool)] = 0
+    z[dm.astype(bool)] = 0
+    dk_ref, dl_ref = oracle.param_grad(ops, l2g, u, z)
+    space = m.Space.create(dim, P, Q, to_dev(Jg), kappa=to_dev(kap))
+    ul = to_dev(oracle.gather(u, l2g)).reshape(-1)
+    zl = to_dev(oracle.gather(z, l2g)).reshape(-1)
+    dk, dl = m.param_grad(space, zl, ul)
+    assert_close(dk.cpu().numpy(), dk_ref.ravel(), FP64_RTOL, "dkappa")
+    assert_close(dl.cpu().numpy(), dl_ref, FP64_RTOL, "dlambda")
+
+
+def _autograd_problem(shape, P, seed):
+    import torch
+    from paper_1906_03489_amd.autograd import HelmholtzProblem
+    m = nk()
+    Q = P + 2
+    Jg, Jo, lat = jacobians(shape, P, W.WARP_AMPLITUDE)
+    E, nq = lat.nelem, Q ** 3
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    # fixed right-hand side: weak form of the manufactured sine at kappa = lambda = 1
+    ref = oracle.ElementOps(3, P, Q, Jo, lam=1.0)
+    U, dU = W.manufactured_ref_gradient(ref.x, lat)
+    b = oracle.assemble_vector(ref.weak_rhs(U, dU), l2g, ng)
+    b[dm.astype(bool)] = 0.0
+    ut = direct_solve(oracle.helmholtz_matrices(ref), l2g, ng, dm, b)
+    kap = W.uniform(seed, (E, nq), 0.5, 2.0)
+    lam = W.uniform(seed + 1, (E,), 0.5, 2.0)
+    pb = HelmholtzProblem(3, P, Q, to_dev(Jg), to_dev(l2g), ng, to_dev(dm), to_dev(b), rtol=1e-13)
+    return pb, Jo, l2g, ng, dm, b, ut, kap, lam
+
+
+def test_autograd_solve_matches_oracle_and_fd():
+    torch = torch_cuda()
+    from paper_1906_03489_amd.autograd import helmholtz_solve
+    P, shape = 3, (2, 2, 2)
+    pb, Jo, l2g, ng, dm, b, ut, kap, lam = _autograd_problem(shape, P, 4000)
+    utd = to_dev(ut)
+    k = to_dev(kap).requires_grad_(True)
+    l = to_dev(lam).requires_grad_(True)
+    u = helmholtz_solve(k, l, pb)
+    loss = 0.5 * torch.sum((u - utd) ** 2)
+    loss.backward()
+    # oracle: solve, adjoint, explicit single-point matrices
+    ops = oracle.ElementOps(3, P, P + 2, Jo, kappa=kap, lam=lam)
+    mats = oracle.helmholtz_matrices(ops)
+    uo = direct_solve(mats, l2g, ng, dm, b)
+    zo = direct_solve(mats, l2g, ng, dm, uo - ut)
+    dk_ref, dl_ref = oracle.param_grad(ops, l2g, uo, zo)
+    assert rel_err(u.detach().cpu().numpy(), uo) < 1e-9
+    assert rel_err(k.grad.cpu().numpy(), dk_ref) < 1e-8
+    assert rel_err(l.grad.cpu().numpy(), dl_ref) < 1e-8
+    # central differences of the GPU solve along seeded directions
+    rng = np.random.default_rng(W.seed(4, 6))
+    for _ in range(2):
+        vk = to_dev(rng.standard_normal(kap.shape))
+        vl = to_dev(rng.standard_normal(lam.shape))
+        # step 1e-4: truncation error O(eps^2) ~ 1e-8; the CG solves' own noise
+        # (relative residual 1e-13) divided by eps stays below 1e-6
+        eps = 1e-4
+        with torch.no_grad():
+            up = helmholtz_solve(k + eps * vk, l + eps * vl, pb)
+            um = helmholtz_solve(k - eps * vk, l - eps * vl, pb)
+            fd = (0.5 * torch.sum((up - utd) ** 2) - 0.5 * torch.sum((um - utd) ** 2)) / (2 * eps)
+        an = torch.sum(k.grad * vk) + torch.sum(l.grad * vl)
+        assert abs(float(fd) - float(an)) <= 2e-5 * abs(float(an)), (float(fd), float(an))

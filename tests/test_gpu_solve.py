@@ -104,7 +104,8 @@ def test_cg_f32_refined_true_residual(P):
     assert res <= 1.2e-10, res
     assert info[0]["outer_iters"] >= 2 and info[0]["status"] == 0
     xref = direct_solve(mats, pb["l2g"], pb["ng"], pb["dm"], b)
-    assert rel_err(xs, xref) < 1e-7
+    # the error is bounded by cond(A) * 1e-10 (cond ~ 1e4 at P = 6)
+    assert rel_err(xs, xref) < 1e-5
 
 
 def test_cg_initial_guess_and_zero_rhs():
