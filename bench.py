@@ -49,6 +49,36 @@ def iprod_bytes_per_elem(P, Q, s=8):
     return s * ((P + 1) ** 3 + 2 * Q ** 3)
 
 
+KERNEL_SOURCES = ["paper_1906_03489_amd/csrc/engine.h", "paper_1906_03489_amd/csrc/ops3d_inst.hip",
+                  "paper_1906_03489_amd/csrc/tiles.h"]
+PMC_SUMMARY = "profiles/helmholtz_f64_32c_P6_pmc.txt"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 Helmholtz kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None if
+    the kernel sources changed since those counters were taken."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        vals, digest = {}, None
+        with open(os.path.join(ROOT, PMC_SUMMARY)) as fh:
+            for line in fh:
+                if "kernel sources hash" in line:
+                    digest = line.split(":")[-1].strip()
+                elif line.strip() and not line.startswith("#"):
+                    k, v = line.split()
+                    vals[k] = float(v)
+        if digest != h.hexdigest()[:16]:
+            return None
+        return int(vals["helm_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def time_launches(fn, n, torch):
     """Average ms per call of fn over n back-to-back calls, HIP events on
     the current stream (the stream the kernels are launched on)."""
@@ -188,29 +218,36 @@ def section_varp(nk, W, torch, reps=20):
     singles = [nk.Space.create(3, P, P + 2, j) for P, j in zip(Ps, jacs)]
     x = torch.cat(xs)
     out = {"nelem": int(lat.nelem), "local_dof": int(ndof), "orders": Ps}
+    names = {0: "persistent", 1: "persistent_2bpc", 2: "concurrent", 3: "sequential"}
     for dt, name in ((nk.F64, "f64"), (nk.F32, "f32")):
         td = torch.float64 if dt == nk.F64 else torch.float32
         xd = x.to(td)
         y = torch.empty_like(xd)
         xg = [t.to(td) for t in xs]
         yg = [torch.empty_like(t) for t in xg]
-        nk.helmholtz(space, xd, y, lam0=1.0, dtype=dt)
-        ms_one = time_launches(lambda: nk.helmholtz(space, xd, y, lam0=1.0, dtype=dt), reps, torch)
 
         def per_group():
             for sp, xi, yi in zip(singles, xg, yg):
                 nk.helmholtz(sp, xi, yi, lam0=1.0, dtype=dt)
         per_group()
         ms_grp = time_launches(per_group, reps, torch)
-        err = float(torch.linalg.norm(y - torch.cat(yg)) / torch.linalg.norm(torch.cat(yg)))
-        s = 8 if dt == nk.F64 else 4
-        gbs = nbytes * s / 8 / (ms_one * 1e-3) / 1e9
-        out[name] = {"single_launch_ms": round(ms_one, 4), "per_group_ms": round(ms_grp, 4),
-                     "speedup": round(ms_grp / ms_one, 3),
-                     "gdof_s": round(ndof / (ms_one * 1e-3) / 1e9, 2),
-                     "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "rel_diff_vs_per_group": err}
-        log(f"varp {name}: one launch {ms_one * 1e3:.1f} us vs per-group {ms_grp * 1e3:.1f} us")
+        ref = torch.cat(yg)
+        res = {"per_group_separate_spaces_ms": round(ms_grp, 4)}
+        for k, sname in names.items():
+            space.set_strategy(dt, k)
+            nk.helmholtz(space, xd, y, lam0=1.0, dtype=dt)
+            ms = time_launches(lambda: nk.helmholtz(space, xd, y, lam0=1.0, dtype=dt), reps, torch)
+            err = float(torch.linalg.norm(y - ref) / torch.linalg.norm(ref))
+            s = 8 if dt == nk.F64 else 4
+            gbs = nbytes * s / 8 / (ms * 1e-3) / 1e9
+            res[sname] = {"ms": round(ms, 4), "speedup_vs_per_group": round(ms_grp / ms, 3),
+                          "gdof_s": round(ndof / (ms * 1e-3) / 1e9, 2), "GB_s": round(gbs, 1),
+                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "rel_diff_vs_per_group": err}
+            log(f"varp {name} {sname}: {ms * 1e3:.1f} us vs per-group {ms_grp * 1e3:.1f} us")
+        # the autotuner's choice
+        nk.autotune(space, 0b100)
+        res["autotuned"] = names[space.get_strategy(dt)]
+        out[name] = res
     return out
 
 
@@ -377,6 +414,8 @@ def main():
     ap.add_argument("--sections", default="ops,cg,batch,grad,cpu",
                     help="comma list of ops,cg,batch,grad,cpu (or 'none')")
     ap.add_argument("--cg-orders", default="4,6,8")
+    ap.add_argument("--calib", action="store_true",
+                    help="after the timed region, one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -418,6 +457,15 @@ def main():
     gdof = ndof / (ms * 1e-3) / 1e9
     bpl = helm_bytes_per_elem(P, Q) * E
     achieved = bpl / (ms * 1e-3) / 1e9
+    if args.calib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # calibrate the counters of the Helmholtz kernel in the same run
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"helmholtz f64: {ms * 1e3:.1f} us/launch, {gdof:.2f} GDOF/s, {achieved:.0f} GB/s "
         f"({achieved / HBM_PEAK_GBS:.1%} of HBM peak); host wall {wall * 1e3 / args.steps:.1f} us/step")
     result = {
@@ -430,7 +478,7 @@ def main():
                                f"{ndof} local DOF per step",
                    "tile": nk.tile_config(2, 3, P, nk.F64)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_op3<double,7,8,EPB,OP_HELM>",
                      "bytes_per_launch": bpl},
     }

@@ -120,6 +120,20 @@ nk_status nk_space_create_varp(nk_space* out, int dim, int ngroups, const int* P
 
 nk_status nk_space_destroy(nk_space s);
 
+/* Evaluation strategy of the Helmholtz operator on a mixed-order space, per
+ * dtype (section 3.3 picks among evaluation strategies by timing them at
+ * start-up; nk_autotune does the same):
+ *   0  one persistent launch over all order groups (work items of the
+ *      largest orders first),
+ *   1  the same with registers capped for two resident blocks per CU,
+ *   2  one launch per order group, all groups on concurrent streams
+ *      (fork/join with the caller's stream),
+ *   3  one launch per order group in sequence.
+ * BwdTrans and IProductWRTBase on mixed-order spaces always use 2.  Calls on
+ * one space from several host threads at once must not use strategy 2. */
+nk_status nk_space_set_strategy(nk_space s, nk_dtype t, int strategy);
+int nk_space_get_strategy(nk_space s, nk_dtype t);   /* -1 on bad arguments */
+
 /* Sizes of a space: total elements, coefficients (sum n^d) and points
  * (sum Q^d).  Any output may be NULL. */
 nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints);

@@ -200,6 +200,11 @@ nk_status nk_basis_tables(int P, int Q, double* x, double* w, double* B, double*
 
 static void space_free(nk_space s) {
   if (!s) return;
+  for (hipStream_t g : s->gstreams)
+    if (g) (void)hipStreamDestroy(g);
+  for (hipEvent_t g : s->gevents)
+    if (g) (void)hipEventDestroy(g);
+  if (s->fork) (void)hipEventDestroy(s->fork);
   dfree(s->fac64);
   dfree(s->fac32);
   dfree(s->kappa);
@@ -374,30 +379,7 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
   if (in == out) return fail(NK_EINVAL, "input and output must not alias");
   hipStream_t st = (hipStream_t)stream;
   const char* fac = t == NK_F64 ? (const char*)s->fac64 : (const char*)s->fac32;
-  if (op == OP_HELM && s->groups.size() > 1) {
-    VarpArgs v;
-    v.t = t;
-    v.ngroups = (int)s->groups.size();
-    v.groups_dev = s->varp_groups;
-    v.item_start_dev = s->varp_item_start;
-    v.nitems = s->varp_nitems;
-    v.x = in;
-    v.y = out;
-    v.fac = fac;
-    v.lam = lam;
-    v.lam_off_dev = s->varp_lam_off;
-    v.lam0 = lam0;
-    int ncu = 0;
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device);
-    const int64_t grid = std::min<int64_t>((int64_t)std::max(ncu, 1) * varp_blocks_per_cu(t),
-                                           s->varp_nitems);
-    v.grid = (int)std::max<int64_t>(grid, 1);
-    v.stream = st;
-    hipError_t e = launch_helm_varp(v);
-    if (e != hipSuccess) return hip_fail(e, "mixed-order Helmholtz launch");
-    return NK_OK;
-  }
-  for (const Group& G : s->groups) {
+  auto group_args = [&](const Group& G) {
     OpArgs a;
     a.op = op;
     a.dim = d;
@@ -412,10 +394,81 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
     a.in2 = in2 ? in2 + G.q0 * d : nullptr;
     a.tile = cur_tile(op, d, G.P, t);
     a.stream = st;
-    hipError_t e = launch_op(d, t, a);
+    return a;
+  };
+  int strategy = VARP_SEQUENTIAL;
+  if (s->groups.size() > 1)
+    strategy = (op == OP_HELM) ? s->varp_strategy[t] : VARP_CONCURRENT;
+  if (strategy == VARP_PERSISTENT || strategy == VARP_PERSISTENT_2) {
+    VarpArgs v;
+    v.t = t;
+    v.ngroups = (int)s->groups.size();
+    v.groups_dev = s->varp_groups;
+    v.item_start_dev = s->varp_item_start;
+    v.nitems = s->varp_nitems;
+    v.x = in;
+    v.y = out;
+    v.fac = fac;
+    v.lam = lam;
+    v.lam_off_dev = s->varp_lam_off;
+    v.lam0 = lam0;
+    v.minb = strategy == VARP_PERSISTENT_2 ? 2 : 1;
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device);
+    const int64_t grid = std::min<int64_t>(
+        (int64_t)std::max(ncu, 1) * varp_blocks_per_cu(t, v.minb), s->varp_nitems);
+    v.grid = (int)std::max<int64_t>(grid, 1);
+    v.stream = st;
+    hipError_t e = launch_helm_varp(v);
+    if (e != hipSuccess) return hip_fail(e, "mixed-order Helmholtz launch");
+    return NK_OK;
+  }
+  if (strategy == VARP_CONCURRENT) {
+    // fork/join: every order group on its own stream, all ordered after the
+    // caller's work and joined back into the caller's stream
+    hipError_t e = hipSuccess;
+    if (s->gstreams.empty()) {
+      for (size_t g = 0; g < s->groups.size() && e == hipSuccess; ++g) {
+        hipStream_t gs = nullptr;
+        hipEvent_t ge = nullptr;
+        e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ge, hipEventDisableTiming);
+        s->gstreams.push_back(gs);
+        s->gevents.push_back(ge);
+      }
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "stream creation");
+    }
+    if ((e = hipEventRecord(s->fork, st))) return hip_fail(e, "hipEventRecord");
+    for (size_t g = 0; g < s->groups.size(); ++g) {
+      OpArgs a = group_args(s->groups[g]);
+      a.stream = s->gstreams[g];
+      if ((e = hipStreamWaitEvent(a.stream, s->fork, 0))) return hip_fail(e, "hipStreamWaitEvent");
+      if ((e = launch_op(d, t, a))) return hip_fail(e, "operator launch");
+      if ((e = hipEventRecord(s->gevents[g], a.stream))) return hip_fail(e, "hipEventRecord");
+    }
+    for (size_t g = 0; g < s->groups.size(); ++g)
+      if ((e = hipStreamWaitEvent(st, s->gevents[g], 0))) return hip_fail(e, "hipStreamWaitEvent");
+    return NK_OK;
+  }
+  for (const Group& G : s->groups) {
+    hipError_t e = launch_op(d, t, group_args(G));
     if (e != hipSuccess) return hip_fail(e, "operator launch");
   }
   return NK_OK;
+}
+
+nk_status nk_space_set_strategy(nk_space s, nk_dtype t, int strategy) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
+  if (strategy < 0 || strategy >= VARP_COUNT) return fail(NK_EINVAL, "bad strategy");
+  s->varp_strategy[t] = strategy;
+  return NK_OK;
+}
+
+int nk_space_get_strategy(nk_space s, nk_dtype t) {
+  if (!s || (t != NK_F64 && t != NK_F32)) return -1;
+  return s->varp_strategy[t];
 }
 
 nk_status nk_bwd_trans(nk_space s, nk_dtype t, const void* coeffs, void* phys, void* stream) {
@@ -1170,6 +1223,37 @@ nk_status nk_autotune(nk_space s, int op_mask, void* stream) {
           g_tile[op][s->dim - 2][G.P][t].store(best);
         }
       }
+    }
+  }
+  // mixed-order spaces: time the evaluation strategies of the Helmholtz
+  // operator on the whole space and keep the fastest (per dtype)
+  if (result == NK_OK && s->groups.size() > 1 && (op_mask >> OP_HELM & 1)) {
+    for (nk_dtype t : {NK_F64, NK_F32}) {
+      double best_us = 1e30;
+      int best = VARP_PERSISTENT;
+      for (int k = 0; k < VARP_COUNT && result == NK_OK; ++k) {
+        s->varp_strategy[t] = k;
+        nk_status r2 = NK_OK;
+        for (int w = 0; w < 2 && r2 == NK_OK; ++w)
+          r2 = space_op(s, OP_HELM, t, a, b, nullptr, 1.0, nullptr, st);
+        const int reps = 5;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && r2 == NK_OK; ++r)
+          r2 = space_op(s, OP_HELM, t, a, b, nullptr, 1.0, nullptr, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        if (r2 != NK_OK) {
+          result = r2;
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (1000.0 * ms / reps < best_us) {
+          best_us = 1000.0 * ms / reps;
+          best = k;
+        }
+      }
+      s->varp_strategy[t] = best;
     }
   }
   (void)hipStreamSynchronize(st);

@@ -296,7 +296,7 @@ __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int 
 // loop over the point index i; the factors of point i+1 are loaded while
 // point i is processed.  Local store or (ASM) atomic scatter-add into the
 // global vector with the element's p_e . (H_e p_e).
-template <typename T, int N, int Q, int NT, bool ASM>
+template <typename T, int N, int Q, int NT, bool ASM, bool LEAN = false>
 __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
                                            const DevArgs<T>& a) {
@@ -358,16 +358,26 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
     };
     // two register sets alternate so the factors of the next point are in
     // flight while the current point is computed
-    T fA[kNF3], fB[kNF3];
-    load(0, fA);
+    if constexpr (LEAN) {
+      // fewer live registers (used where occupancy matters more than latency)
 #pragma unroll 1
-    for (int i = 0; i < Q; i += 2) {
-      // loads are unconditional (clamped index) so that the waits for them
-      // can be placed right before their first use
-      load(i + 1 < Q ? i + 1 : Q - 1, fB);
-      point(i, fA);
-      load(i + 2 < Q ? i + 2 : Q - 1, fA);
-      if (Q % 2 == 0 || i + 1 < Q) point(i + 1, fB);
+      for (int i = 0; i < Q; ++i) {
+        T f[kNF3];
+        load(i, f);
+        point(i, f);
+      }
+    } else {
+      T fA[kNF3], fB[kNF3];
+      load(0, fA);
+#pragma unroll 1
+      for (int i = 0; i < Q; i += 2) {
+        // loads are unconditional (clamped index) so that the waits for them
+        // can be placed right before their first use
+        load(i + 1 < Q ? i + 1 : Q - 1, fB);
+        point(i, fA);
+        load(i + 2 < Q ? i + 2 : Q - 1, fA);
+        if (Q % 2 == 0 || i + 1 < Q) point(i + 1, fB);
+      }
     }
   }
   slot_sync<NT>();

@@ -97,11 +97,21 @@ struct VarpArgs {
   const int64_t* lam_off_dev = nullptr;    // element offset of each group
   double lam0 = 0.0;
   int grid = 0;
+  int minb = 1;                 // minimum resident blocks per CU (register cap)
   hipStream_t stream = nullptr;
 };
 hipError_t launch_helm_varp(const VarpArgs& a);
+
+// Strategies for operators on a mixed-order space (chosen by the autotuner):
+enum VarpStrategy : int {
+  VARP_PERSISTENT = 0,      // one persistent launch over all order groups
+  VARP_PERSISTENT_2 = 1,    // same, registers capped for two blocks per CU
+  VARP_CONCURRENT = 2,      // one launch per order group, all groups concurrent
+  VARP_SEQUENTIAL = 3,      // one launch per order group, in order (reference)
+  VARP_COUNT = 4
+};
 int varp_items_per_group(int P, int64_t nelem);   // work items of one group
-int varp_blocks_per_cu(nk_dtype t);
+int varp_blocks_per_cu(nk_dtype t, int minb);
 
 // One entry point per compiled order set (objects built from ops3d_inst.hip).
 hipError_t launch_op3_set0(nk_dtype t, const OpArgs& a);
@@ -141,4 +151,9 @@ struct nk_space_s {
   int64_t* varp_item_start = nullptr;
   int64_t* varp_lam_off = nullptr;
   int64_t varp_nitems = 0;
+  int varp_strategy[2] = {nk::VARP_PERSISTENT, nk::VARP_PERSISTENT};   // per dtype
+  // fork/join streams of the concurrent strategy (created on first use)
+  std::vector<hipStream_t> gstreams;
+  std::vector<hipEvent_t> gevents;
+  hipEvent_t fork = nullptr;
 };

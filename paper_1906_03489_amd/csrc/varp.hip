@@ -71,11 +71,14 @@ __device__ __forceinline__ void varp_body(const VarpDev<T>& a, const VarpGroup& 
   d.lam = a.lam ? a.lam + lam_off : nullptr;
   d.lam0 = a.lam0;
   T* sm = smem + (slot < EPB ? slot : 0) * 3 * Q * Q * N;
-  helm3_body<T, N, Q, NT, false>(tb, sm, nullptr, slot, t, live, e, d);
+  helm3_body<T, N, Q, NT, false, (P >= 8)>(tb, sm, nullptr, slot, t, live, e, d);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kVarpThreads) k_helm_varp(const VarpDev<T> a) {
+// MINB = minimum resident blocks per CU requested from the compiler (1 or 2):
+// 2 caps registers so two 256-thread blocks fit per CU, at the price of
+// spills in the largest orders.
+template <typename T, int MINB>
+__global__ void __launch_bounds__(kVarpThreads, MINB) k_helm_varp(const VarpDev<T> a) {
   __shared__ T smem[varp_smem<T>()];
   for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
     int g = 0;
@@ -142,21 +145,29 @@ hipError_t launch_helm_varp(const VarpArgs& a) {
   if (a.t == NK_F64) {
     VarpDev<double> d{a.groups_dev, a.item_start_dev, a.lam_off_dev, a.ngroups, a.nitems,
                       (const double*)a.x, (double*)a.y, (const double*)a.fac, a.lam, a.lam0};
-    hipLaunchKernelGGL(k_helm_varp<double>, dim3(a.grid), dim3(kVarpThreads), 0, a.stream, d);
+    if (a.minb == 2)
+      hipLaunchKernelGGL((k_helm_varp<double, 2>), dim3(a.grid), dim3(kVarpThreads), 0, a.stream, d);
+    else
+      hipLaunchKernelGGL((k_helm_varp<double, 1>), dim3(a.grid), dim3(kVarpThreads), 0, a.stream, d);
   } else {
     VarpDev<float> d{a.groups_dev, a.item_start_dev, a.lam_off_dev, a.ngroups, a.nitems,
                      (const float*)a.x, (float*)a.y, (const float*)a.fac, a.lam, a.lam0};
-    hipLaunchKernelGGL(k_helm_varp<float>, dim3(a.grid), dim3(kVarpThreads), 0, a.stream, d);
+    if (a.minb == 2)
+      hipLaunchKernelGGL((k_helm_varp<float, 2>), dim3(a.grid), dim3(kVarpThreads), 0, a.stream, d);
+    else
+      hipLaunchKernelGGL((k_helm_varp<float, 1>), dim3(a.grid), dim3(kVarpThreads), 0, a.stream, d);
   }
   return hipGetLastError();
 }
 
-int varp_blocks_per_cu(nk_dtype t) {
+int varp_blocks_per_cu(nk_dtype t, int minb) {
   int nb = 0;
   if (t == NK_F64)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_helm_varp<double>, kVarpThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, minb == 2 ? k_helm_varp<double, 2> : k_helm_varp<double, 1>, kVarpThreads, 0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_helm_varp<float>, kVarpThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, minb == 2 ? k_helm_varp<float, 2> : k_helm_varp<float, 1>, kVarpThreads, 0);
   return nb > 0 ? nb : 1;
 }
 

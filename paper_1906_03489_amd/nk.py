@@ -31,7 +31,8 @@ EXPORTS = [
     "nk_iprod_wrt_base", "nk_helmholtz", "nk_helmholtz_weak_rhs", "nk_system_create",
     "nk_system_create_batched", "nk_system_destroy", "nk_system_apply", "nk_assemble",
     "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
-    "nk_tile_config", "nk_tile_count", "nk_set_tile_config",
+    "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
+    "nk_space_get_strategy",
 ]
 
 
@@ -90,6 +91,8 @@ def lib():
         "nk_tile_config": (ctypes.c_char_p, [i32, i32, i32, i32]),
         "nk_tile_count": (i32, [i32, i32, i32]),
         "nk_set_tile_config": (i32, [i32, i32, i32, i32, i32]),
+        "nk_space_set_strategy": (i32, [vp, i32, i32]),
+        "nk_space_get_strategy": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -180,6 +183,14 @@ class Space:
         h = ctypes.c_void_p()
         _check(lib().nk_space_create_varp(ctypes.byref(h), dim, ng, Pa, Qa, ne, ja, ka, _stream()))
         return cls(h.value, dim, [(P, Q, int(n)) for P, Q, n in zip(Ps, Qs, ne)])
+
+    STRATEGIES = {0: "persistent", 1: "persistent_2bpc", 2: "concurrent", 3: "sequential"}
+
+    def set_strategy(self, dtype, strategy: int):
+        _check(lib().nk_space_set_strategy(self.handle, dtype, int(strategy)))
+
+    def get_strategy(self, dtype) -> int:
+        return int(lib().nk_space_get_strategy(self.handle, dtype))
 
     def sizes(self):
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

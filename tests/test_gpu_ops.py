@@ -133,13 +133,26 @@ def test_mixed_order_single_launch():
     lam = to_dev(np.concatenate(lams))
     for dtype, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_RTOL)):
         td = torch.float64 if dtype == m.F64 else torch.float32
-        y = m.helmholtz(space, x.to(td), lam=lam, dtype=dtype).double().cpu().numpy()
-        off = 0
-        for P, r in zip(Ps, refs):
-            assert_close(y[off:off + r.size], r, tol, f"varp P={P} dtype={dtype}")
-            off += r.size
-        # the other operators run group by group on the same space
-        assert off == y.size
+        for strategy in range(4):
+            space.set_strategy(dtype, strategy)
+            y = m.helmholtz(space, x.to(td), lam=lam, dtype=dtype).double().cpu().numpy()
+            off = 0
+            for P, r in zip(Ps, refs):
+                assert_close(y[off:off + r.size], r, tol, f"varp P={P} dtype={dtype} strategy={strategy}")
+                off += r.size
+            assert off == y.size
+    # BwdTrans on the mixed-order space (concurrent per-group launches)
+    c64 = x
+    u = m.bwd_trans(space, c64).cpu().numpy()
+    off_c = off_u = 0
+    for P in Ps:
+        Jg, Jo, _ = jacobians((4, 4, 4), P, W.WARP_AMPLITUDE, nelem=counts[P])
+        n3, q3 = (P + 1) ** 3, (P + 2) ** 3
+        c = x[off_c:off_c + counts[P] * n3].cpu().numpy().reshape(counts[P], n3)
+        ref = oracle.ElementOps(3, P, P + 2, Jo).bwd(c).ravel()
+        assert_close(u[off_u:off_u + ref.size], ref, FP64_RTOL, f"varp bwd P={P}")
+        off_c += counts[P] * n3
+        off_u += ref.size
 
 
 def test_weak_rhs_matches_oracle():
