@@ -139,6 +139,24 @@ def section_ops(nk, W, torch, space, lat, P, Q, reps):
                                    "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                                    "tile": nk.tile_config({"bwd_trans": 0, "iprod_wrt_base": 1,
                                                            "helmholtz": 2}[op], 3, P, dt)}
+        # every compiled Helmholtz candidate (vector tiles and the matrix-core variant)
+        chosen = None
+        nt = nk.tile_count(2, 3, P)
+        per_tile = {}
+        for k in range(nt):
+            nk.set_tile_config(2, 3, P, dt, k)
+            name_k = nk.tile_config(2, 3, P, dt)
+            nk.helmholtz(space, cs[0], ys[0], lam0=1.0, dtype=dt)
+            cnt = [0]
+
+            def step_t():
+                nk.helmholtz(space, cs[cnt[0] % nset], ys[cnt[0] % nset], lam0=1.0, dtype=dt)
+                cnt[0] += 1
+            ms = time_launches(step_t, reps, torch)
+            gbs = helm_bytes_per_elem(P, Q, s) * E / (ms * 1e-3) / 1e9
+            per_tile[name_k] = {"ms": round(ms, 5), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        out[f"helmholtz_all_tiles_{name}"] = per_tile
+        nk.autotune(space, 0b100)
         del cs, fs, us, ys
         torch.cuda.empty_cache()
     return out

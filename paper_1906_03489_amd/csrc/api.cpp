@@ -56,15 +56,21 @@ hipError_t launch_op3(nk_dtype t, const OpArgs& a) {
   return hipErrorInvalidValue;
 }
 
+static int vector_tile_count(int op, int dim, int P);
+
 static hipError_t launch_op(int dim, nk_dtype t, const OpArgs& a) {
   if (a.nelem == 0) return hipSuccess;
+  if ((a.op == OP_HELM || a.op == OP_HELM_ASM) && mfma_supported(dim, a.P) &&
+      a.tile == vector_tile_count(OP_HELM, dim, a.P))
+    return launch_helm_mfma(t, a);
   return dim == 3 ? launch_op3(t, a) : launch_op2(t, a);
 }
 
 // ------------------------------------------------------------- tile choice
 static std::atomic<int> g_tile[OP_COUNT][2][kMaxP + 1][2];
 
-int tile_count(int op, int dim, int P) {
+// vector-ALU tile candidates (elements per block)
+static int vector_tile_count(int op, int dim, int P) {
   if (P < kMinP || P > kMaxP || !op_has_tiles(op)) return 1;
   int c = 0;
   for (int k = 0; k < kMaxTiles; ++k)
@@ -72,9 +78,22 @@ int tile_count(int op, int dim, int P) {
   return c;
 }
 
+// all candidates: the vector tiles, plus the matrix-core variant of the
+// Helmholtz operator where it exists (always the last index)
+int tile_count(int op, int dim, int P) {
+  const int v = vector_tile_count(op, dim, P);
+  if ((op == OP_HELM || op == OP_HELM_ASM) && mfma_supported(dim, P)) return v + 1;
+  return v;
+}
+
 const char* tile_name(int op, int dim, int P, int tile) {
   static thread_local char buf[64];
   if (P < kMinP || P > kMaxP) return "";
+  if ((op == OP_HELM || op == OP_HELM_ASM) && mfma_supported(dim, P) &&
+      tile == vector_tile_count(op, dim, P)) {
+    std::snprintf(buf, sizeof buf, "mfma_epb2_thr128");
+    return buf;
+  }
   const int epb = dim == 3 ? kTileEPB3[P][tile] : kTileEPB2[P][tile];
   const int q = P + 2;
   const int q2 = q * q;

@@ -69,6 +69,11 @@ struct OpArgs {
   hipStream_t stream = nullptr;
 };
 
+// Matrix-core variant of the Helmholtz operator (local and assembled) for
+// 3-D orders with Q <= 8; selected as the last tile candidate of OP_HELM.
+bool mfma_supported(int dim, int P);
+hipError_t launch_helm_mfma(nk_dtype t, const OpArgs& a);
+
 // Number of compiled tile configurations for an operator and its names.
 int tile_count(int op, int dim, int P);
 const char* tile_name(int op, int dim, int P, int tile);

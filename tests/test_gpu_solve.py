@@ -179,3 +179,34 @@ def test_batched_independent_systems():
             assert info[k]["status"] == 0 and info[k]["rel_resid"] <= tol * 1.0001
             err = rel_err(xs[doff[k]:doff[k + 1]], ref)
             assert err < (1e-9 if mode == m.SOLVE_F64 else 1e-6), (k, mode, err)
+
+
+@pytest.mark.parametrize("P", [4, 6])
+def test_assembled_operator_and_cg_matrix_core_variant(P):
+    """The matrix-core (MFMA) variant of the assembled operator, selected as
+    the last Helmholtz tile, against the oracle; and a CG solve with it."""
+    torch = torch_cuda()
+    m = nk()
+    nt = m.tile_count(m.OP_HELM, 3, P)
+    assert m.tile_config(m.OP_HELM, 3, P, m.F64) != ""
+    try:
+        for dt in (m.F64, m.F32):
+            m.set_tile_config(m.OP_HELM, 3, P, dt, nt - 1)
+        assert m.tile_config(m.OP_HELM, 3, P, m.F64).startswith("mfma")
+        pb = _problem((3, 2, 2), P, lam_seed=5)
+        mats = oracle.helmholtz_matrices(pb["ops"])
+        A = MaskedOperator(mats, pb["l2g"], pb["ng"], pb["dm"])
+        _, sysm = _gpu_system(pb)
+        x = np.random.default_rng(3).uniform(-1, 1, pb["ng"])
+        ref = A(x)
+        assert_close(sysm.apply(to_dev(x)).cpu().numpy(), ref, FP64_RTOL, f"mfma apply P={P}")
+        y32 = sysm.apply(to_dev(x, torch.float32), dtype=m.F32).double().cpu().numpy()
+        assert_close(y32, ref, FP32_RTOL, f"mfma apply32 P={P}")
+        b = _rhs(pb)
+        xs, info = sysm.solve(to_dev(b), rtol=1e-12)
+        assert np.linalg.norm(b - A(xs.cpu().numpy())) / np.linalg.norm(b) <= 1.05e-12
+        xr, info = sysm.solve(to_dev(b), rtol=1e-10, mode=m.SOLVE_F32_REFINED)
+        assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
+    finally:
+        for dt in (m.F64, m.F32):
+            m.set_tile_config(m.OP_HELM, 3, P, dt, 0)
