@@ -280,7 +280,6 @@ __global__ void __launch_bounds__(EPB * 64)
   // ---- I: X[p][(j,k)] = s[k][j][p]; pointwise; I' from registers ----
   const T lam = (T)(a.lam ? a.lam[e] : a.lam0);
   const T* fe = a.fac + e * (int64_t)(kNF3 * Q3);
-  vec pa[4], pb[4];
   {
     const T fia0 = F(FIA), fia1 = F(FIA + 1);
     const T fib0 = F(FIB), fib1 = F(FIB + 1), fib2 = F(FIB + 2), fib3 = F(FIB + 3);
@@ -336,34 +335,30 @@ __global__ void __launch_bounds__(EPB * 64)
       vec acc = zero;
 #pragma unroll
       for (int s = 0; s < 6; ++s) acc = mfma(fp[s], q[s / 2][s % 2], acc);
-      pa[c] = acc;
-      pb[c] = mfma(fp[7], q[3][1], mfma(fp[6], q[3][0], zero));
+      const vec accb = mfma(fp[7], q[3][1], mfma(fp[6], q[3][0], zero));
+      // column (j,k) was read above by this wavefront only, so its results
+      // can overwrite it in place (LDS operations of one wave stay in order)
+      if (ok) {
+        const int p0 = 4 * (g % 2);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = p0 + v;
+          if (p < N) {
+            const int o = base + p;
+            if (g < 2) {
+              sA[o] = acc[v];   // s'_BB
+              sC[o] = accb[v];  // s'_BD
+            } else {
+              sB[o] = acc[v];   // s'_DB
+            }
+          }
+        }
+      }
       if (c + 1 < 4) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int f = 0; f < kNF3; ++f) fcur[h][f] = fnxt[h][f];
-      }
-    }
-  }
-  wsync();
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int col = 16 * c + cl;
-    if (col < QQ) {
-      const int p0 = 4 * (g % 2);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int p = p0 + v;
-        if (p < N) {
-          const int o = col * N + p;
-          if (g < 2) {
-            sA[o] = pa[c][v];  // s'_BB
-            sC[o] = pb[c][v];  // s'_BD
-          } else {
-            sB[o] = pa[c][v];  // s'_DB
-          }
-        }
       }
     }
   }
