@@ -15,7 +15,10 @@ methods" (arXiv 1906.03489):
   element    tensor-product bases (section 2.1 and the sum-factorisation
              display of section 3.3), geometric factors of the map chi_e
              (section 2.1), and the dense elemental matrices of BwdTrans,
-             IProductWRTBase, mass, Laplacian and Helmholtz.  Each operator is
+             IProductWRTBase, mass, Laplacian and Helmholtz; PhysDeriv
+             (collocation derivative and chain rule), IProductWRTDerivBase
+             (the volume term of section 2.2) and FwdTrans (the projection of
+             the listing in section 3.5, a dense solve with M_e).  Each operator is
              applied as a dense matrix-vector product: this is the "StdMat"
              strategy of section 3.3, the plain definition that
              sum-factorisation reorders exactly.
@@ -29,7 +32,8 @@ Every function's docstring names the passage it follows or the reading taken
 where the paper is silent.
 """
 from .basis import gll, modified_basis, lagrange_derivative, jacobi_p
-from .element import (tensor_bases, geometry, ElementOps, bwd_trans, iprod_wrt_base,
+from .element import (tensor_bases, geometry, inverse_jacobian, collocation_derivatives,
+                      ElementOps, bwd_trans, iprod_wrt_base, phys_deriv, iprod_deriv, fwd_trans,
                       helmholtz_apply, helmholtz_matrices, mass_matrices, weak_rhs)
 from .assembly import (assemble_vector, gather, assembled_matrix, pcg, direct_solve,
                        jacobi_diagonal)
@@ -37,7 +41,8 @@ from .grad import param_grad, loss_and_solution
 
 __all__ = [
     "gll", "modified_basis", "lagrange_derivative", "jacobi_p",
-    "tensor_bases", "geometry", "ElementOps", "bwd_trans", "iprod_wrt_base",
+    "tensor_bases", "geometry", "inverse_jacobian", "collocation_derivatives",
+    "ElementOps", "bwd_trans", "iprod_wrt_base", "phys_deriv", "iprod_deriv", "fwd_trans",
     "helmholtz_apply", "helmholtz_matrices", "mass_matrices", "weak_rhs",
     "assemble_vector", "gather", "assembled_matrix", "pcg", "direct_solve",
     "jacobi_diagonal", "param_grad", "loss_and_solution",

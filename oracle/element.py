@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .basis import gll, modified_basis
+from .basis import gll, lagrange_derivative, modified_basis
 
 
 def tensor_bases(B, DB, w, dim):
@@ -46,6 +46,27 @@ def tensor_bases(B, DB, w, dim):
     else:
         raise ValueError("dim must be 2 or 3")
     return Bt, Dt, Wt
+
+
+def collocation_derivatives(x, dim):
+    """Tensor collocation derivatives on the GLL grid x (per direction):
+    (D_a u)[q] is the xi_a-derivative at point q of the interpolant of the
+    point values u, built from the 1-D Lagrange derivative matrix; direction 1
+    is the rightmost Kronecker factor."""
+    D = lagrange_derivative(x)
+    I = np.eye(len(x))
+    if dim == 2:
+        return [np.kron(I, D), np.kron(D, I)]
+    if dim == 3:
+        return [np.kron(I, np.kron(I, D)), np.kron(I, np.kron(D, I)), np.kron(D, np.kron(I, I))]
+    raise ValueError("dim must be 2 or 3")
+
+
+def inverse_jacobian(J):
+    """Jinv[e, q, a, c] = d xi_a / d x_c, the matrix inverse of
+    J[e, :, :, q] = d x_c / d xi_a."""
+    Jm = np.moveaxis(np.asarray(J, np.float64), -1, 1)     # (E, nq, c, a)
+    return np.linalg.inv(Jm)                               # (E, nq, a, c)
 
 
 def geometry(J):
@@ -76,6 +97,8 @@ class ElementOps:
         lam = np.asarray(lam, np.float64)
         self.lam = np.broadcast_to(lam, (E,)).copy() if lam.ndim == 0 else lam.reshape(E).copy()
         self.wJ = self.Wt[None, :] * self.detJ                 # (E, nq)
+        self.Jinv = inverse_jacobian(J)                        # (E, nq, a, c)
+        self.Dcol = collocation_derivatives(self.x, self.dim)
 
     # -- elemental matrices ------------------------------------------------
     def mass_matrix(self, e):
@@ -135,6 +158,32 @@ class ElementOps:
             out[e] = acc
         return out
 
+    def phys_deriv(self, u):
+        """PhysDeriv (differentiation, one of the core elemental operations
+        listed in section 2.3): du[e, c, q] = d u / d x_c at the quadrature
+        points, for u given by its values there.  Reference derivatives come
+        from the collocation derivative of the interpolant; the chain rule
+        gives d u / d x_c = sum_a (d xi_a / d x_c) d u / d xi_a."""
+        u = np.asarray(u, np.float64)
+        dref = np.stack([u @ Da.T for Da in self.Dcol], axis=1)      # (E, a, nq)
+        return np.einsum("eqac,eaq->ecq", self.Jinv, dref)
+
+    def iprod_deriv(self, f):
+        """IProductWRTDerivBase (the volume term of the weak form in section
+        2.2): I_e[m] = sum_q w_q detJ_q sum_c (d phi_m / d x_c)(x_q) f_c(x_q)
+        = sum_a (D_a B)^T [w detJ sum_c (d xi_a / d x_c) f_c], for a vector
+        field f[e, c, q] given at the quadrature points."""
+        f = np.asarray(f, np.float64)
+        g = np.einsum("eqac,ecq->eaq", self.Jinv, f) * self.wJ[:, None, :]
+        return sum(g[:, a, :] @ self.Dt[a] for a in range(self.dim))
+
+    def fwd(self, f):
+        """FwdTrans (the projection called in the listing of section 3.5):
+        the coefficients of the elemental L2 projection of the point values
+        f, u^_e = M_e^{-1} I_e(f), solved densely per element."""
+        rhs = self.iprod(f)
+        return np.stack([np.linalg.solve(self.mass_matrix(e), rhs[e]) for e in range(self.nelem)])
+
     def integral(self, f):
         """Integral of a field given at the quadrature points over each
         element: sum_q w_q detJ_q f_q."""
@@ -149,6 +198,18 @@ def bwd_trans(ops: ElementOps, coeffs):
 
 def iprod_wrt_base(ops: ElementOps, f):
     return ops.iprod(f)
+
+
+def phys_deriv(ops: ElementOps, u):
+    return ops.phys_deriv(u)
+
+
+def iprod_deriv(ops: ElementOps, f):
+    return ops.iprod_deriv(f)
+
+
+def fwd_trans(ops: ElementOps, f):
+    return ops.fwd(f)
 
 
 def helmholtz_apply(ops: ElementOps, x, elems=None):

@@ -424,3 +424,112 @@ def test_adjoint_gradient_matches_finite_differences():
         fd = (loss(kap + eps * vk, lam + eps * vl)[0] - loss(kap - eps * vk, lam - eps * vl)[0]) / (2 * eps)
         an = np.sum(dkap * vk) + np.sum(dlam * vl)
         assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)
+
+
+# ---------------------------------------------------------------- PhysDeriv,
+# IProductWRTDerivBase and FwdTrans (the explicit-type building blocks of
+# section 2.2 and the projection of the listing in section 3.5)
+
+def _points(x, dim):
+    """Reference coordinates of the tensor points, q = i + Q(j + Q l)."""
+    g = np.meshgrid(*([x] * dim), indexing="ij")
+    return np.stack([gg.transpose(*range(dim)[::-1]).reshape(-1) for gg in g])
+
+
+def test_phys_deriv_exact_on_sheared_affine_element():
+    """u = x1^2 + x1 x2 + 3 x3 (degree <= 2 per reference direction, so its
+    interpolant is exact) on x = A xi + x0 with a non-normal A: the physical
+    gradient (2 x1 + x2, x1, 3) is reproduced at every point.  A transposed
+    inverse Jacobian or a swapped direction fails."""
+    P, Q = 3, 5
+    A = np.array([[0.7, 0.4, -0.1], [0.05, 0.9, 0.3], [0.2, -0.25, 1.1]])
+    x0 = np.array([0.1, -0.2, 0.3])
+    J = np.broadcast_to(A[None, :, :, None], (1, 3, 3, Q ** 3)).copy()
+    ops = oracle.ElementOps(3, P, Q, J)
+    X = A @ _points(ops.x, 3) + x0[:, None]
+    u = X[0] ** 2 + X[0] * X[1] + 3 * X[2]
+    du = ops.phys_deriv(u[None])[0]
+    np.testing.assert_allclose(du[0], 2 * X[0] + X[1], atol=1e-12)
+    np.testing.assert_allclose(du[1], X[0], atol=1e-12)
+    np.testing.assert_allclose(du[2], 3.0, atol=1e-12)
+
+
+def test_phys_deriv_2d_affine_exact():
+    """2-D: u = x^3 - 2 x y on a sheared parallelogram, gradient (3x^2 - 2y, -2x)."""
+    P, Q = 4, 6
+    A = np.array([[0.8, 0.3], [-0.2, 1.1]])
+    J = np.broadcast_to(A[None, :, :, None], (1, 2, 2, Q ** 2)).copy()
+    ops = oracle.ElementOps(2, P, Q, J)
+    X = A @ _points(ops.x, 2)
+    du = ops.phys_deriv((X[0] ** 3 - 2 * X[0] * X[1])[None])[0]
+    np.testing.assert_allclose(du[0], 3 * X[0] ** 2 - 2 * X[1], atol=1e-12)
+    np.testing.assert_allclose(du[1], -2 * X[0], atol=1e-12)
+
+
+def test_phys_deriv_chain_rule_on_curved_elements():
+    """On warped elements, for u a polynomial of the reference coordinates of
+    degree <= Q-1 per direction, J^T grad_x u equals the analytic reference
+    gradient: checks the inverse Jacobian against J itself."""
+    P = 4
+    ops, _ = _warped_ops((2, 2, 1), P)
+    xi = _points(ops.x, 3)
+    u = xi[0] ** 5 - xi[0] * xi[1] ** 2 * xi[2] + 2 * xi[2] ** 3
+    dref = np.stack([5 * xi[0] ** 4 - xi[1] ** 2 * xi[2],
+                     -2 * xi[0] * xi[1] * xi[2],
+                     -xi[0] * xi[1] ** 2 + 6 * xi[2] ** 2])
+    lat = W.lattice((2, 2, 1))
+    J = W.element_jacobians(ops.x, lat, 0.05)                   # (E, c, a, q)
+    du = ops.phys_deriv(np.broadcast_to(u, (ops.nelem, u.size)))
+    back = np.einsum("ecaq,ecq->eaq", J, du)
+    np.testing.assert_allclose(back, np.broadcast_to(dref, back.shape), atol=1e-11)
+
+
+@pytest.mark.parametrize("dim,P", [(3, 3), (3, 5), (2, 4)])
+def test_iprod_deriv_of_gradient_is_the_laplacian(dim, P):
+    """IProductWRTDerivBase of the physical gradient of a discrete field is its
+    Laplacian matrix-vector product (kappa = 1) on curved elements: the
+    gradient of B u^ is exact at the points, so sum_q w detJ grad phi_m . grad u
+    = (L_e u^)_m.  Three independent constructions meet: G (Laplacian), the
+    collocation derivative with J^{-1} (PhysDeriv) and D_a B with J^{-1}."""
+    shape = (2, 1, 2) if dim == 3 else (2, 3)
+    ops, _ = _warped_ops(shape, P, lam=0.0, amp=0.05 if dim == 3 else 0.0)
+    rng = np.random.default_rng(31 + P)
+    c = rng.uniform(-1, 1, (ops.nelem, (P + 1) ** dim))
+    got = ops.iprod_deriv(ops.phys_deriv(ops.bwd(c)))
+    want = np.stack([ops.laplacian_matrix(e) @ c[e] for e in range(ops.nelem)])
+    np.testing.assert_allclose(got, want, atol=1e-11 * np.abs(want).max())
+
+
+def test_iprod_deriv_divergence_theorem_affine():
+    """For the constant field f = e_1 on an affine box [0,hx]x[0,hy]x[0,hz],
+    sum_m I[m] c_m = int d(u)/dx1 dx = int over the two x1-faces of u, with u
+    the vertex-constant 1 of the box (all derivatives vanish): 0; and for u = x1
+    (coefficients of the linear vertex modes) the result is the volume."""
+    P, Q = 3, 5
+    h = np.array([0.5, 0.25, 0.75])
+    ops = oracle.ElementOps(3, P, Q, _affine_box_J(h, Q, 3))
+    f = np.zeros((1, 3, Q ** 3))
+    f[0, 0] = 1.0
+    I = ops.iprod_deriv(f)[0]
+    one = _vertex_constant(P, 3)
+    assert abs(I @ one) < 1e-14
+    # x1 on [0, hx]: vertex modes p=0 -> 0, p=P -> hx in direction 1
+    c1 = np.zeros(P + 1)
+    c1[P] = h[0]
+    e1 = np.zeros(P + 1)
+    e1[0] = e1[P] = 1.0
+    cx = np.kron(e1, np.kron(e1, c1))
+    assert abs(I @ cx - h.prod()) < 1e-14
+
+
+@pytest.mark.parametrize("P", [3, 5])
+def test_fwd_trans_inverts_bwd_and_is_galerkin(P):
+    """FwdTrans o BwdTrans = I on curved elements, and the projection of an
+    arbitrary point field is Galerkin-orthogonal: I_e(f - B FwdTrans(f)) = 0."""
+    ops, _ = _warped_ops((2, 1, 1), P)
+    rng = np.random.default_rng(41 + P)
+    c = rng.uniform(-1, 1, (ops.nelem, (P + 1) ** 3))
+    np.testing.assert_allclose(ops.fwd(ops.bwd(c)), c, atol=1e-9)
+    f = rng.uniform(-1, 1, (ops.nelem, (P + 2) ** 3))
+    r = ops.iprod(f - ops.bwd(ops.fwd(f)))
+    assert np.abs(r).max() < 1e-13 * np.abs(ops.iprod(f)).max()
