@@ -154,6 +154,32 @@ nk_status nk_iprod_wrt_base(nk_space s, nk_dtype t, const void* phys, void* coef
 nk_status nk_helmholtz(nk_space s, nk_dtype t, const double* lambda, double lambda0,
                        const void* x, void* y, void* stream);
 
+/* PhysDeriv (differentiation, one of the core elemental operations listed in
+ * section 2.3): deriv[e][c][q] = d u / d x_c at quadrature point q of the
+ * interpolant of element e's point values, i.e. the collocation derivative
+ * along each reference direction followed by the chain rule with J^{-1}.
+ * phys: device [E][Q^d], deriv: device [E][d][Q^d], both of type t (must not
+ * overlap).  Exact for fields of degree <= Q-1 per reference direction. */
+nk_status nk_phys_deriv(nk_space s, nk_dtype t, const void* phys, void* deriv, void* stream);
+
+/* IProductWRTDerivBase (the volume term of the weak form in section 2.2):
+ * coeffs[e][m] = sum_q w_q detJ_q sum_c (d phi_m / d x_c)(x_q) f[e][c][q] for a
+ * vector field f given at the quadrature points.  f: device [E][d][Q^d],
+ * coeffs: device [E][n^d], type t. */
+nk_status nk_iprod_wrt_deriv_base(nk_space s, nk_dtype t, const void* f, void* coeffs,
+                                  void* stream);
+
+/* FwdTrans (the projection called in the listing of section 3.5): the
+ * coefficients of each element's L2 projection of its point values,
+ * coeffs_e = M_e^{-1} IProductWRTBase(phys)_e.  Each element's mass system
+ * is solved on chip by conjugate gradients preconditioned with the exact
+ * inverse of the tensor-product mass at the element's mean Jacobian
+ * determinant, from a zero start, until the residual falls below 1e-13 (FP64)
+ * or 2e-6 (FP32) of the right-hand side or after 100 iterations.  phys:
+ * device [E][Q^3], coeffs: device [E][n^3], type t.  3-D spaces only
+ * (NK_EUNSUPPORTED otherwise). */
+nk_status nk_fwd_trans(nk_space s, nk_dtype t, const void* phys, void* coeffs, void* stream);
+
 /* Weak form of the Helmholtz operator of a field given at the quadrature
  * points: y_e[m] = a_e(U, phi_m) = sum_a (D_a B)^T (w detJ kappa sum_b G_ab dU_b)
  * + lambda_e B^T (w detJ U), the right-hand side l(v) = a(U, v) of Eq. (1)

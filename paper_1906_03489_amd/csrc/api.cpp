@@ -226,6 +226,8 @@ static void space_free(nk_space s) {
   if (s->fork) (void)hipEventDestroy(s->fork);
   dfree(s->fac64);
   dfree(s->fac32);
+  dfree(s->dfac64);
+  dfree(s->dfac32);
   dfree(s->kappa);
   dfree(s->varp_groups);
   dfree(s->varp_item_start);
@@ -264,10 +266,12 @@ nk_status nk_space_create_varp(nk_space* out, int dim, int ngroups, const int* P
     G.c0 = s->ncoeff;
     G.q0 = s->npoint;
     G.f0 = s->nfac;
+    G.d0 = s->ndfac;
     s->nelem += G.nelem;
     s->ncoeff += G.nelem * ipow(G.n, dim);
     s->npoint += G.nelem * ipow(G.Q, dim);
     s->nfac += G.nelem * ipow(G.Q, dim) * (dim == 3 ? kNF3 : kNF2);
+    s->ndfac += G.nelem * ipow(G.Q, dim) * (dim * dim + 1);
     s->groups.push_back(G);
     if (kappa && kappa[g]) has_kappa = true;
   }
@@ -288,6 +292,8 @@ nk_status nk_space_create_varp(nk_space* out, int dim, int ngroups, const int* P
   hipError_t e;
   if ((e = dmalloc(&s->fac64, s->nfac)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = dmalloc(&s->fac32, s->nfac)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = dmalloc(&s->dfac64, s->ndfac)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = dmalloc(&s->dfac32, s->ndfac)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if (has_kappa) {
     if ((e = dmalloc(&s->kappa, s->npoint)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   }
@@ -315,7 +321,8 @@ nk_status nk_space_create_varp(nk_space* out, int dim, int ngroups, const int* P
         e = vec_fill<double>(s->kappa + G.q0, G.nelem * nq, 1.0, st);
       if (e != hipSuccess) break;
     }
-    e = launch_geom(dim, G.Q, G.nelem, jac[g], kg, d_w, s->fac64 + G.f0, s->fac32 + G.f0, d_bad, st);
+    e = launch_geom(dim, G.Q, G.nelem, jac[g], kg, d_w, s->fac64 + G.f0, s->fac32 + G.f0,
+                    s->dfac64 + G.d0, s->dfac32 + G.d0, d_bad, st);
     // the weights buffer is reused by the next group: wait for this launch
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
@@ -395,7 +402,7 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
   NK_CHECK(check_buf(out, (pts_out ? s->npoint : s->ncoeff) * sz, "output"));
   if (lam) NK_CHECK(check_buf(lam, s->nelem * 8, "lambda"));
   if (op == OP_RHS) NK_CHECK(check_buf(in2, s->npoint * d * 8, "du"));
-  if (in == out) return fail(NK_EINVAL, "input and output must not alias");
+  if (in == out && in != nullptr) return fail(NK_EINVAL, "input and output must not alias");
   hipStream_t st = (hipStream_t)stream;
   const char* fac = t == NK_F64 ? (const char*)s->fac64 : (const char*)s->fac32;
   auto group_args = [&](const Group& G) {
@@ -506,6 +513,47 @@ nk_status nk_helmholtz(nk_space s, nk_dtype t, const double* lambda, double lamb
 nk_status nk_helmholtz_weak_rhs(nk_space s, const double* lambda, double lambda0, const double* u,
                                 const double* du, double* y, void* stream) {
   return space_op(s, OP_RHS, NK_F64, u, y, lambda, lambda0, du, stream);
+}
+
+// PhysDeriv, IProductWRTDerivBase and FwdTrans: one launch per order group.
+static nk_status deriv_op(nk_space s, int which, nk_dtype t, const void* in, void* out,
+                          void* stream) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
+  const size_t sz = dsize(t);
+  const int d = s->dim;
+  if (which == DERIV_FWD && d != 3) return fail(NK_EUNSUPPORTED, "FwdTrans is built for 3-D spaces");
+  // element-major blocks: points [Q^d], vector fields [d][Q^d], coefficients [n^d]
+  const int64_t vin = which == DERIV_IPROD ? d : 1, vout = which == DERIV_PHYS ? d : 1;
+  const bool coeff_out = which != DERIV_PHYS;
+  NK_CHECK(check_buf(in, s->npoint * vin * sz, "input"));
+  NK_CHECK(check_buf(out, (coeff_out ? s->ncoeff : s->npoint * vout) * sz, "output"));
+  if (in == out && in != nullptr) return fail(NK_EINVAL, "input and output must not alias");
+  const char* df = t == NK_F64 ? (const char*)s->dfac64 : (const char*)s->dfac32;
+  for (const Group& G : s->groups) {
+    DerivArgs a;
+    a.nelem = G.nelem;
+    a.in = (const char*)in + G.q0 * vin * sz;
+    a.out = (char*)out + (coeff_out ? G.c0 : G.q0 * vout) * sz;
+    a.dfac = df + G.d0 * sz;
+    a.stream = (hipStream_t)stream;
+    const hipError_t e = launch_deriv(t, which, d, G.P, a);
+    if (e != hipSuccess) return hip_fail(e, "derivative operator launch");
+  }
+  return NK_OK;
+}
+
+nk_status nk_phys_deriv(nk_space s, nk_dtype t, const void* phys, void* deriv, void* stream) {
+  return deriv_op(s, DERIV_PHYS, t, phys, deriv, stream);
+}
+
+nk_status nk_iprod_wrt_deriv_base(nk_space s, nk_dtype t, const void* f, void* coeffs,
+                                  void* stream) {
+  return deriv_op(s, DERIV_IPROD, t, f, coeffs, stream);
+}
+
+nk_status nk_fwd_trans(nk_space s, nk_dtype t, const void* phys, void* coeffs, void* stream) {
+  return deriv_op(s, DERIV_FWD, t, phys, coeffs, stream);
 }
 
 nk_status nk_helmholtz_param_grad(nk_space s, const double* z_loc, const double* u_loc,

@@ -91,4 +91,68 @@ void modified_basis(int P, int Q, const double* x, double* B, double* DB) {
   }
 }
 
+// Derivative matrix of the Lagrange interpolant through the Q nodes x:
+// Dc[i*Q + j] = l_j'(x_i), from the barycentric weights b_j = 1 / prod_{k != j}
+// (x_j - x_k): l_j'(x_i) = (b_j / b_i) / (x_i - x_j) off the diagonal, and each
+// row sums to zero (constants have zero derivative).
+void collocation_derivative(int Q, const double* x, double* Dc) {
+  std::vector<double> b(Q, 1.0);
+  for (int j = 0; j < Q; ++j)
+    for (int k = 0; k < Q; ++k)
+      if (k != j) b[j] *= x[j] - x[k];
+  for (int j = 0; j < Q; ++j) b[j] = 1.0 / b[j];
+  for (int i = 0; i < Q; ++i) {
+    double diag = 0.0;
+    for (int j = 0; j < Q; ++j) {
+      if (j == i) continue;
+      const double v = (b[j] / b[i]) / (x[i] - x[j]);
+      Dc[i * Q + j] = v;
+      diag -= v;
+    }
+    Dc[i * Q + i] = diag;
+  }
+}
+
+// Eigen-decomposition of the symmetric n x n matrix A (row-major) by cyclic
+// Jacobi rotations: A = V diag(lam) V^T, eigenvectors in the columns of V.
+void symmetric_eigen(int n, const double* A, double* V, double* lam) {
+  std::vector<double> a(A, A + n * n);
+  for (int i = 0; i < n * n; ++i) V[i] = 0.0;
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a[i * n + j] * a[i * n + j];
+        if (i != j) off += a[i * n + j] * a[i * n + j];
+      }
+    if (off <= 1e-34 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        // rotation angle that annihilates a[p][q]
+        const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(tt * tt + 1.0), s = tt * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) lam[i] = a[i * n + i];
+}
+
 }  // namespace nk

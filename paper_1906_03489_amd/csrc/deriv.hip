@@ -1,0 +1,623 @@
+// Derivative and projection operators around the Helmholtz path (the
+// explicit-type building blocks of section 2.2 and the projection of the
+// listing in section 3.5):
+//
+//   PhysDeriv             du/dx_c at the quadrature points: collocation
+//                         derivative of the point values along each reference
+//                         direction, then the chain rule with J^{-1}.
+//   IProductWRTDerivBase  sum_q w detJ grad phi_m . f: the per-point
+//                         transform g_a = w detJ sum_c (J^{-1})_{ac} f_c, then
+//                         the transposed sum-factorisation sweeps (D along
+//                         direction a, B along the others).
+//   FwdTrans              u^_e = M_e^{-1} IProductWRTBase(f): per element,
+//                         conjugate gradients on the sum-factorised mass
+//                         operator, preconditioned with the exact inverse of
+//                         the tensor-product mass at the element's mean
+//                         Jacobian determinant (fast diagonalisation: the 1-D
+//                         reference mass M1 = V diag(lam) V^T gives
+//                         (M1 x M1 x M1)^{-1} = (V x V x V) diag(1/(lam lam lam))
+//                         (V x V x V)^T).  The whole iteration stays on chip;
+//                         HBM sees the point values, w detJ and the result.
+//
+// Element data layouts as for the other operators: points [E][Q^d] with
+// q = i + Q(j + Q k), coefficients [E][n^d] with m = p + n(q + n r); vector
+// fields [E][d][Q^d].  Derivative factors [E][d*d+1][Q^d] (J^{-1} entry
+// (a,c) at a*d + c, then w detJ) in point order.
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "engine.h"
+#include "tables.h"
+
+namespace nk {
+
+// ----------------------------------------------------------- device tables
+
+// Device copy of a host-built table, built once per (device, key).
+template <typename T, typename Build>
+static const T* cached_table(long key, Build build) {
+  static std::mutex mu;
+  static std::unordered_map<long, T*> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  const long k = key * 64 + dev;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(k);
+  if (it != cache.end()) return it->second;
+  std::vector<double> h = build();
+  std::vector<T> ht(h.begin(), h.end());
+  T* d = nullptr;
+  if (hipMalloc((void**)&d, ht.size() * sizeof(T)) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, ht.data(), ht.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  cache[k] = d;
+  return d;
+}
+
+// Collocation derivative matrix on the Q GLL points, row-major [Q][Q].
+template <typename T>
+static const T* colloc_table(int Q) {
+  return cached_table<T>(Q, [Q] {
+    std::vector<double> x(Q), w(Q), Dc(Q * Q);
+    gll_points(Q, x.data(), w.data());
+    collocation_derivative(Q, x.data(), Dc.data());
+    return Dc;
+  });
+}
+
+// Fast-diagonalisation tables of order P: VT [N][N] (VT[o][m] = V[m][o]),
+// V [N][N], then S [N^3] with S[p + N(q + N r)] = 1 / (lam_p lam_q lam_r)
+// (3-D) or S[p + N q] = 1 / (lam_p lam_q) (2-D).
+template <typename T>
+static const T* fastdiag_table(int P, int Q, int dim) {
+  return cached_table<T>(1000L * dim + 32L * P + Q, [P, Q, dim] {
+    const int N = P + 1;
+    std::vector<double> x(Q), w(Q), B(Q * N), D(Q * N), M(N * N, 0.0), V(N * N), lam(N);
+    gll_points(Q, x.data(), w.data());
+    modified_basis(P, Q, x.data(), B.data(), D.data());
+    for (int p = 0; p < N; ++p)
+      for (int pp = 0; pp < N; ++pp)
+        for (int i = 0; i < Q; ++i) M[p * N + pp] += w[i] * B[i * N + p] * B[i * N + pp];
+    symmetric_eigen(N, M.data(), V.data(), lam.data());
+    const int nd = dim == 3 ? N * N * N : N * N;
+    std::vector<double> t(2 * N * N + nd);
+    for (int o = 0; o < N; ++o)
+      for (int m = 0; m < N; ++m) {
+        t[o * N + m] = V[m * N + o];
+        t[N * N + o * N + m] = V[o * N + m];
+      }
+    for (int id = 0; id < nd; ++id) {
+      const int p = id % N, q = (id / N) % N, r = id / (N * N);
+      t[2 * N * N + id] = 1.0 / (lam[p] * lam[q] * (dim == 3 ? lam[r] : 1.0));
+    }
+    return t;
+  });
+}
+
+// Slot-wide sum visible to every thread of the slot.  Slots that fit in a
+// wavefront reduce with lane shuffles inside their lane group; larger slots
+// (one per block) combine per-wavefront partials through LDS.
+template <int NT>
+__device__ __forceinline__ double slot_allsum(double v, double* red) {
+  if constexpr (NT <= 64) {
+#pragma unroll
+    for (int o = NT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  } else {
+    constexpr int NW = (NT + 63) / 64;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[k];
+    return s;
+  }
+}
+
+template <int Q>
+constexpr int deriv_epb() {
+  return slot_threads<Q>() >= 64 ? (slot_threads<Q>() > 64 ? 1 : 4) : 256 / slot_threads<Q>();
+}
+
+// --------------------------------------------------------------- PhysDeriv
+
+// 3-D: thread t = i + Q j of a slot owns the column (i, j) over k.
+template <typename T, int Q, int EPB>
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+    k_phys_deriv3(const T* __restrict__ dc, int64_t nelem, const T* __restrict__ in,
+                  T* __restrict__ out, const T* __restrict__ dfac) {
+  constexpr int QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
+  __shared__ T smem[EPB * Q3];
+  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
+  const int64_t nblk = (nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  const bool act = e < nelem && t < QQ;
+  T* sm = smem + slot * Q3;
+  const int i = t % Q, j = t / Q;
+  T col[Q];
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      col[k] = in[e * Q3 + t + QQ * k];
+      sm[t + QQ * k] = col[k];
+    }
+  }
+  slot_sync<NT>();
+  if (!act) return;
+  T di[Q], dj[Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    di[m] = dc[i * Q + m];
+    dj[m] = dc[j * Q + m];
+  }
+  const T* fe = dfac + e * (int64_t)(10 * Q3) + t;
+  T* oe = out + e * (int64_t)(3 * Q3) + t;
+#pragma unroll 2
+  for (int k = 0; k < Q; ++k) {
+    const T* row = sm + QQ * k;
+    const T* dk = dc + k * Q;
+    T d1 = 0, d2 = 0, d3 = 0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      d1 += di[m] * row[m + Q * j];
+      d2 += dj[m] * row[i + Q * m];
+      d3 += dk[m] * col[m];
+    }
+    const T* f = fe + QQ * k;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      oe[c * Q3 + QQ * k] = f[c * Q3] * d1 + f[(3 + c) * Q3] * d2 + f[(6 + c) * Q3] * d3;
+  }
+}
+
+// 2-D: thread t = i + Q j of a slot owns point (i, j).
+template <typename T, int Q, int EPB>
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+    k_phys_deriv2(const T* __restrict__ dc, int64_t nelem, const T* __restrict__ in,
+                  T* __restrict__ out, const T* __restrict__ dfac) {
+  constexpr int QQ = Q * Q, NT = slot_threads<Q>();
+  __shared__ T smem[EPB * QQ];
+  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
+  const int64_t nblk = (nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  const bool act = e < nelem && t < QQ;
+  T* sm = smem + slot * QQ;
+  if (act) sm[t] = in[e * QQ + t];
+  slot_sync<NT>();
+  if (!act) return;
+  const int i = t % Q, j = t / Q;
+  T d1 = 0, d2 = 0;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    d1 += dc[i * Q + m] * sm[m + Q * j];
+    d2 += dc[j * Q + m] * sm[i + Q * m];
+  }
+  const T* f = dfac + e * (int64_t)(5 * QQ) + t;
+  T* o = out + e * (int64_t)(2 * QQ) + t;
+  o[0] = f[0] * d1 + f[2 * QQ] * d2;
+  o[QQ] = f[QQ] * d1 + f[3 * QQ] * d2;
+}
+
+// ---------------------------------------------------- IProductWRTDerivBase
+
+// 3-D.  Pass 1, thread t = i + Q j over k: g_a = w detJ sum_c (J^{-1})_{ac}
+// f_c into LDS [a][Q^3].  Pass 2, thread t = j + Q k along i: the transposed
+// I stage with D for g_1 and B for g_2, g_3, then the engine's J' and K'.
+template <typename T, int N, int Q, int EPB>
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+    k_iprod_deriv3(const Tab<T, N, Q> tb, int64_t nelem, const T* __restrict__ in,
+                   T* __restrict__ out, const T* __restrict__ dfac) {
+  constexpr int NN = N * N, N3 = NN * N, QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
+  static_assert(3 * Q3 >= slot_lds<N, Q>(), "LDS slot");
+  __shared__ T smem[EPB * 3 * Q3];
+  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
+  const int64_t nblk = (nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  const bool live = e < nelem;
+  const bool act = live && t < QQ;
+  const int64_t ee = live ? e : 0;
+  T* sm = smem + slot * 3 * Q3;
+  if (act) {
+    const T* fe = dfac + ee * (int64_t)(10 * Q3) + t;
+    const T* xe = in + ee * (int64_t)(3 * Q3) + t;
+#pragma unroll 2
+    for (int k = 0; k < Q; ++k) {
+      const int o = QQ * k;
+      const T f1 = xe[o], f2 = xe[Q3 + o], f3 = xe[2 * Q3 + o];
+      const T* f = fe + o;
+      const T wj = f[9 * Q3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        sm[a * Q3 + t + o] = wj * (f[(3 * a) * Q3] * f1 + f[(3 * a + 1) * Q3] * f2 +
+                                   f[(3 * a + 2) * Q3] * f3);
+    }
+  }
+  slot_sync<NT>();
+  T sa[N], sb[N], sc[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
+  if (act) {
+#pragma unroll 2
+    for (int i = 0; i < Q; ++i) {
+      const T g1 = sm[i + Q * t], g2 = sm[Q3 + i + Q * t], g3 = sm[2 * Q3 + i + Q * t];
+      const T* Bi = tb.B + i * N;
+      const T* Di = tb.D + i * N;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        sa[p] += Di[p] * g1;
+        sb[p] += Bi[p] * g2;
+        sc[p] += Bi[p] * g3;
+      }
+    }
+  }
+  slot_sync<NT>();
+  if (act) store_i<T, N, Q, true>(sm, t, sa, sb, sc);
+  slot_sync<NT>();
+  stage_jt<T, N, Q, NT, true>(tb, sm, t, live);
+  slot_sync<NT>();
+  T yv[N];
+  stage_kt<T, N, Q, true>(tb, sm, t, live, yv);
+  if (live && t < NN) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) out[e * N3 + r * NN + t] = yv[r];
+  }
+}
+
+// 2-D: thread t = i + Q j computes g_a at its point; then thread j sums
+// over i (D for g_1, B for g_2) into h_a[p][j], and thread p sums over j
+// (B for h_1, D for h_2).  Table rows are indexed by the loop counter only.
+template <typename T, int N, int Q, int EPB>
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+    k_iprod_deriv2(const Tab<T, N, Q> tb, int64_t nelem, const T* __restrict__ in,
+                   T* __restrict__ out, const T* __restrict__ dfac) {
+  constexpr int QQ = Q * Q, NT = slot_threads<Q>();
+  __shared__ T smem[EPB * 2 * QQ];
+  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
+  const int64_t nblk = (nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  const bool live = e < nelem;
+  T* sm = smem + slot * 2 * QQ;
+  if (live && t < QQ) {
+    const T* f = dfac + e * (int64_t)(5 * QQ) + t;
+    const T* x = in + e * (int64_t)(2 * QQ) + t;
+    const T f1 = x[0], f2 = x[QQ], wj = f[4 * QQ];
+    sm[t] = wj * (f[0] * f1 + f[QQ] * f2);                // g_1
+    sm[QQ + t] = wj * (f[2 * QQ] * f1 + f[3 * QQ] * f2);  // g_2
+  }
+  slot_sync<NT>();
+  T h1[N], h2[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) h1[p] = h2[p] = T(0);
+  if (live && t < Q) {
+#pragma unroll 2
+    for (int i = 0; i < Q; ++i) {
+      const T g1 = sm[i + Q * t], g2 = sm[QQ + i + Q * t];
+      const T* Bi = tb.B + i * N;
+      const T* Di = tb.D + i * N;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        h1[p] += Di[p] * g1;
+        h2[p] += Bi[p] * g2;
+      }
+    }
+  }
+  slot_sync<NT>();
+  if (live && t < Q) {
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      sm[p * Q + t] = h1[p];
+      sm[QQ + p * Q + t] = h2[p];
+    }
+  }
+  slot_sync<NT>();
+  if (live && t < N) {
+    T y[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) y[q] = T(0);
+#pragma unroll 2
+    for (int j = 0; j < Q; ++j) {
+      const T a = sm[t * Q + j], b = sm[QQ + t * Q + j];
+      const T* Bj = tb.B + j * N;
+      const T* Dj = tb.D + j * N;
+#pragma unroll
+      for (int q = 0; q < N; ++q) y[q] += Bj[q] * a + Dj[q] * b;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[e * (N * N) + q * N + t] = y[q];
+  }
+}
+
+// ----------------------------------------------------------------- FwdTrans
+
+// Contract direction DIR (0: p, 1: q, 2: r) of the n^3 array X in LDS
+// (layout [r][q][p]) with the N x N table A (row o at A + o*N):
+// X'[.., o, ..] = sum_m A[o][m] X[.., m, ..].  Thread t < N^2 owns the pencil
+// along DIR indexed by the other two directions.
+template <typename T, int N, int NT, int DIR>
+__device__ __forceinline__ void fd_contract(T* __restrict__ X, const T* __restrict__ A, int t,
+                                            bool act) {
+  constexpr int NN = N * N;
+  constexpr int stride = DIR == 0 ? 1 : DIR == 1 ? N : NN;
+  const int a = t % N, b = t / N;
+  const int base = DIR == 0 ? a * N + b * NN : DIR == 1 ? a + b * NN : a + b * N;
+  const bool me = act && t < NN;
+  T x[N];
+  if (me) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = X[base + m * stride];
+  }
+  slot_sync<NT>();
+  if (me) {
+#pragma unroll 2
+    for (int o = 0; o < N; ++o) {
+      const T* Ao = A + o * N;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) s += Ao[m] * x[m];
+      X[base + o * stride] = s;
+    }
+  }
+  slot_sync<NT>();
+}
+
+// y = M_e x for the slot's element: BwdTrans stages, w detJ at the points,
+// IProductWRTBase stages.  Vectors are columns over r of thread t = p + N q.
+template <typename T, int N, int Q, int NT>
+__device__ __forceinline__ void fd_mass(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t,
+                                        bool live, const T (&x)[N], const T (&wj)[Q], T (&y)[N]) {
+  stage_k<T, N, Q, false>(tb, sm, t, live, x);
+  slot_sync<NT>();
+  stage_j<T, N, Q, NT, false>(tb, sm, t, live);
+  slot_sync<NT>();
+  T sa[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) sa[p] = T(0);
+  if (live && t < Q * Q) {
+    T av[N], dum[N];
+    load_i<T, N, Q, false>(sm, t, av, dum, dum);
+#pragma unroll 2
+    for (int i = 0; i < Q; ++i) {
+      const T* Bi = tb.B + i * N;
+      T u = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) u += Bi[p] * av[p];
+      const T m = wj[i] * u;
+#pragma unroll
+      for (int p = 0; p < N; ++p) sa[p] += Bi[p] * m;
+    }
+  }
+  slot_sync<NT>();
+  if (live && t < Q * Q) store_i<T, N, Q, false>(sm, t, sa, sa, sa);
+  slot_sync<NT>();
+  stage_jt<T, N, Q, NT, false>(tb, sm, t, live);
+  slot_sync<NT>();
+  stage_kt<T, N, Q, false>(tb, sm, t, live, y);
+  slot_sync<NT>();
+}
+
+// z = P^{-1} r = (1/c) (V x V x V) S (V x V x V)^T r.
+template <typename T, int N, int NT>
+__device__ __forceinline__ void fd_precond(const T* __restrict__ tab, T* __restrict__ X, int t,
+                                           bool live, T inv_c, const T (&r)[N], T (&z)[N]) {
+  constexpr int NN = N * N;
+  const bool me = live && t < NN;
+  const T* VT = tab;
+  const T* V = tab + NN;
+  const T* S = tab + 2 * NN;
+  if (me) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) X[k * NN + t] = r[k];
+  }
+  slot_sync<NT>();
+  fd_contract<T, N, NT, 2>(X, VT, t, live);
+  fd_contract<T, N, NT, 1>(X, VT, t, live);
+  fd_contract<T, N, NT, 0>(X, VT, t, live);
+  if (me) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) X[k * NN + t] *= inv_c * S[k * NN + t];
+  }
+  slot_sync<NT>();
+  fd_contract<T, N, NT, 0>(X, V, t, live);
+  fd_contract<T, N, NT, 1>(X, V, t, live);
+  fd_contract<T, N, NT, 2>(X, V, t, live);
+  if (me) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) z[k] = X[k * NN + t];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) z[k] = T(0);
+  }
+  slot_sync<NT>();
+}
+
+template <typename T, int N>
+__device__ __forceinline__ double col_dot(const T (&a)[N], const T (&b)[N]) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) s += (double)a[k] * (double)b[k];
+  return s;
+}
+
+// 3-D FwdTrans, one element per slot; all slots of a block are either one
+// wavefront's lane groups (no block barriers) or the block itself.
+template <typename T, int N, int Q, int EPB>
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+    k_fwd_trans3(const Tab<T, N, Q> tb, const T* __restrict__ tab, int64_t nelem,
+                 const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ dfac,
+                 double rtol2, int maxit) {
+  constexpr int NN = N * N, N3 = NN * N, QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
+  static_assert(NT <= 64 ? (64 % NT == 0 && EPB * NT <= 64) : EPB == 1, "slot layout");
+  static_assert(Q3 >= slot_lds<N, Q>() / 3, "LDS slot");
+  __shared__ T smem[EPB * Q3];
+  __shared__ double red[(NT + 63) / 64];
+  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
+  const int64_t nblk = (nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  const bool live = e < nelem;
+  const int64_t ee = live ? e : 0;
+  T* sm = smem + slot * Q3;
+  // w detJ along this thread's pencil (j,k) = t over i, and the element's
+  // mean Jacobian determinant c = sum(w detJ) / 2^3
+  T wj[Q];
+  {
+    const T* we = dfac + ee * (int64_t)(10 * Q3) + 9 * Q3;
+    if (live && t < QQ) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) sm[t + QQ * k] = we[t + QQ * k];
+    }
+    slot_sync<NT>();
+    double ws = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      wj[i] = (live && t < QQ) ? sm[i + Q * t] : T(0);
+      ws += (double)wj[i];
+    }
+    slot_sync<NT>();
+    ws = slot_allsum<NT>(ws, red);
+    // b = I_e(f): stage f through LDS for coalesced loads, then I', J', K'
+    const T* fe = in + ee * (int64_t)Q3;
+    if (live && t < QQ) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) sm[t + QQ * k] = fe[t + QQ * k];
+    }
+    slot_sync<NT>();
+    T sa[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) sa[p] = T(0);
+    if (live && t < QQ) {
+#pragma unroll 2
+      for (int i = 0; i < Q; ++i) {
+        const T* Bi = tb.B + i * N;
+        const T m = wj[i] * sm[i + Q * t];
+#pragma unroll
+        for (int p = 0; p < N; ++p) sa[p] += Bi[p] * m;
+      }
+    }
+    slot_sync<NT>();
+    if (live && t < QQ) store_i<T, N, Q, false>(sm, t, sa, sa, sa);
+    slot_sync<NT>();
+    stage_jt<T, N, Q, NT, false>(tb, sm, t, live);
+    slot_sync<NT>();
+    T b[N];
+    stage_kt<T, N, Q, false>(tb, sm, t, live, b);
+    slot_sync<NT>();
+    const T inv_c = (T)(8.0 / ws);
+    // preconditioned CG on M_e x = b, x0 = 0
+    T x[N], r[N], p[N], q[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      x[k] = T(0);
+      r[k] = b[k];
+    }
+    const double bb = slot_allsum<NT>(col_dot(b, b), red);
+    fd_precond<T, N, NT>(tab, sm, t, live, inv_c, r, p);
+    double rz = slot_allsum<NT>(col_dot(r, p), red);
+    bool done = !(bb > 0.0);
+    // every thread of a slot holds the same sums, so the slot leaves the
+    // loop as a whole (a slot of more than 64 threads is its whole block)
+    for (int it = 0; it < maxit && !done; ++it) {
+      fd_mass<T, N, Q, NT>(tb, sm, t, live, p, wj, q);
+      const double pq = slot_allsum<NT>(col_dot(p, q), red);
+      if (!(pq > 0.0)) break;
+      const T alpha = (T)(rz / pq);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        x[k] += alpha * p[k];
+        r[k] -= alpha * q[k];
+      }
+      const double rr = slot_allsum<NT>(col_dot(r, r), red);
+      if (rr <= rtol2 * bb) {
+        done = true;
+        continue;
+      }
+      fd_precond<T, N, NT>(tab, sm, t, live, inv_c, r, q);   // q <- z
+      const double rzn = slot_allsum<NT>(col_dot(r, q), red);
+      const T beta = (T)(rzn / rz);
+      rz = rzn;
+#pragma unroll
+      for (int k = 0; k < N; ++k) p[k] = q[k] + beta * p[k];
+    }
+    if (live && t < NN) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) out[e * N3 + k * NN + t] = x[k];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+
+template <typename T, int P>
+static hipError_t run_deriv(int which, int dim, const DerivArgs& a) {
+  constexpr int N = P + 1, Q = P + 2;
+  constexpr int EPB = deriv_epb<Q>();
+  constexpr int NT = slot_threads<Q>();
+  const int64_t nblk = (a.nelem + EPB - 1) / EPB;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const T* in = static_cast<const T*>(a.in);
+  T* out = static_cast<T*>(a.out);
+  const T* df = static_cast<const T*>(a.dfac);
+  hipStream_t s = a.stream;
+  if (which == DERIV_PHYS) {
+    const T* dc = colloc_table<T>(Q);
+    if (!dc) return hipErrorOutOfMemory;
+    if (dim == 3)
+      hipLaunchKernelGGL((k_phys_deriv3<T, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s, dc,
+                         a.nelem, in, out, df);
+    else
+      hipLaunchKernelGGL((k_phys_deriv2<T, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s, dc,
+                         a.nelem, in, out, df);
+    return hipGetLastError();
+  }
+  const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
+  if (which == DERIV_IPROD) {
+    if (dim == 3)
+      hipLaunchKernelGGL((k_iprod_deriv3<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
+                         tb, a.nelem, in, out, df);
+    else
+      hipLaunchKernelGGL((k_iprod_deriv2<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
+                         tb, a.nelem, in, out, df);
+    return hipGetLastError();
+  }
+  if (which == DERIV_FWD && dim == 3) {
+    constexpr int EPBF = NT <= 64 ? 64 / NT : 1;
+    const int64_t nbf = (a.nelem + EPBF - 1) / EPBF;
+    if (nbf > 0x7fffffff) return hipErrorInvalidValue;
+    const T* tab = fastdiag_table<T>(P, Q, 3);
+    if (!tab) return hipErrorOutOfMemory;
+    const double rtol = sizeof(T) == 8 ? 1e-13 : 2e-6;
+    hipLaunchKernelGGL((k_fwd_trans3<T, N, Q, EPBF>), dim3((unsigned)nbf), dim3(EPBF * NT), 0, s,
+                       tb, tab, a.nelem, in, out, df, rtol * rtol, kFwdMaxIt);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t run_deriv_p(nk_dtype t, int which, int dim, const DerivArgs& a) {
+  return t == NK_F64 ? run_deriv<double, P>(which, dim, a) : run_deriv<float, P>(which, dim, a);
+}
+
+hipError_t launch_deriv(nk_dtype t, int which, int dim, int P, const DerivArgs& a) {
+  if (a.nelem == 0) return hipSuccess;
+  switch (P) {
+    case 1: return run_deriv_p<1>(t, which, dim, a);
+    case 2: return run_deriv_p<2>(t, which, dim, a);
+    case 3: return run_deriv_p<3>(t, which, dim, a);
+    case 4: return run_deriv_p<4>(t, which, dim, a);
+    case 5: return run_deriv_p<5>(t, which, dim, a);
+    case 6: return run_deriv_p<6>(t, which, dim, a);
+    case 7: return run_deriv_p<7>(t, which, dim, a);
+    case 8: return run_deriv_p<8>(t, which, dim, a);
+    case 9: return run_deriv_p<9>(t, which, dim, a);
+    case 10: return run_deriv_p<10>(t, which, dim, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nk

@@ -7,12 +7,14 @@ namespace nk {
 // One thread per (element, point).  J[e][c][a][q] = d x_c / d xi_a.  Writes
 // factor f of point q = i + Q t (t = j + Q k in 3-D, t = j in 2-D) at
 // ((e*NF + f)*Q + i)*Q^(d-1) + t, with f = 0: w detJ, then the upper triangle
-// of w detJ kappa J^{-1} J^{-T} row by row.
+// of w detJ kappa J^{-1} J^{-T} row by row.  The derivative factors go to
+// dfac[(e*(d*d+1) + g)*Q^d + q]: g = a*d + c for (J^{-1})_{ac} = d xi_a / d x_c,
+// g = d*d for w detJ.
 template <int D>
 __global__ void __launch_bounds__(256)
     k_geom(int Q, int64_t nelem, const double* __restrict__ jac, const double* __restrict__ kappa,
            const double* __restrict__ wq, double* __restrict__ fac64, float* __restrict__ fac32,
-           int* __restrict__ bad) {
+           double* __restrict__ dfac64, float* __restrict__ dfac32, int* __restrict__ bad) {
   const int QD = D == 3 ? Q * Q * Q : Q * Q;
   const int QT = QD / Q;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,6 +57,14 @@ __global__ void __launch_bounds__(256)
     Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id_;
     Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id_;
     Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id_;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t o = (e * 10 + a * 3 + c) * QD + q;
+        dfac64[o] = Ji[a][c];
+        dfac32[o] = (float)Ji[a][c];
+      }
     const double s = w * det * kap;
     int k = 1;
 #pragma unroll
@@ -67,12 +77,25 @@ __global__ void __launch_bounds__(256)
     det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double id_ = 1.0 / det;
     const double Ji[2][2] = {{J[1][1] * id_, -J[0][1] * id_}, {-J[1][0] * id_, J[0][0] * id_}};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int64_t o = (e * 5 + a * 2 + c) * QD + q;
+        dfac64[o] = Ji[a][c];
+        dfac32[o] = (float)Ji[a][c];
+      }
     const double s = w * det * kap;
     f[1] = s * (Ji[0][0] * Ji[0][0] + Ji[0][1] * Ji[0][1]);
     f[2] = s * (Ji[0][0] * Ji[1][0] + Ji[0][1] * Ji[1][1]);
     f[3] = s * (Ji[1][0] * Ji[1][0] + Ji[1][1] * Ji[1][1]);
   }
   f[0] = w * det;
+  {
+    const int64_t o = (e * (D * D + 1) + D * D) * QD + q;
+    dfac64[o] = w * det;
+    dfac32[o] = (float)(w * det);
+  }
   if (!(det > 0.0) || !(kap > 0.0)) atomicOr(bad, 1);
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
@@ -83,17 +106,18 @@ __global__ void __launch_bounds__(256)
 }
 
 hipError_t launch_geom(int dim, int Q, int64_t nelem, const double* jac, const double* kappa,
-                       const double* wq, double* fac64, float* fac32, int* bad, hipStream_t s) {
+                       const double* wq, double* fac64, float* fac32, double* dfac64,
+                       float* dfac32, int* bad, hipStream_t s) {
   const int64_t QD = dim == 3 ? (int64_t)Q * Q * Q : (int64_t)Q * Q;
   const int64_t n = nelem * QD;
   if (n == 0) return hipSuccess;
   const int64_t nb = (n + 255) / 256;
   if (dim == 3)
     hipLaunchKernelGGL(k_geom<3>, dim3((unsigned)nb), dim3(256), 0, s, Q, nelem, jac, kappa, wq,
-                       fac64, fac32, bad);
+                       fac64, fac32, dfac64, dfac32, bad);
   else
     hipLaunchKernelGGL(k_geom<2>, dim3((unsigned)nb), dim3(256), 0, s, Q, nelem, jac, kappa, wq,
-                       fac64, fac32, bad);
+                       fac64, fac32, dfac64, dfac32, bad);
   return hipGetLastError();
 }
 

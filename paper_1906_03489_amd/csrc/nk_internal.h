@@ -22,6 +22,8 @@ constexpr int64_t kSegAlign = 2048;  // DOF ranges of each system padded to this
 // ------------------------------------------------------------ host tables
 void gll_points(int Q, double* x, double* w);
 void modified_basis(int P, int Q, const double* x, double* B, double* DB);
+void collocation_derivative(int Q, const double* x, double* Dc);
+void symmetric_eigen(int n, const double* A, double* V, double* lam);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -127,9 +129,22 @@ hipError_t launch_op3_set4(nk_dtype t, const OpArgs& a);
 hipError_t launch_op3_set5(nk_dtype t, const OpArgs& a);
 hipError_t launch_op3_set6(nk_dtype t, const OpArgs& a);
 
+// PhysDeriv / IProductWRTDerivBase / FwdTrans (deriv.hip).
+enum DerivKind : int { DERIV_PHYS = 0, DERIV_IPROD = 1, DERIV_FWD = 2 };
+constexpr int kFwdMaxIt = 100;   // CG iterations per element in FwdTrans
+struct DerivArgs {
+  int64_t nelem = 0;
+  const void* in = nullptr;
+  void* out = nullptr;
+  const void* dfac = nullptr;   // derivative factors of the group, dtype of the call
+  hipStream_t stream = nullptr;
+};
+hipError_t launch_deriv(nk_dtype t, int which, int dim, int P, const DerivArgs& a);
+
 // Geometry: per-point factors from Jacobians.
 hipError_t launch_geom(int dim, int Q, int64_t nelem, const double* jac, const double* kappa,
-                       const double* wq, double* fac64, float* fac32, int* bad, hipStream_t s);
+                       const double* wq, double* fac64, float* fac32, double* dfac64,
+                       float* dfac32, int* bad, hipStream_t s);
 
 // ------------------------------------------------------------------- space
 struct Group {
@@ -139,6 +154,7 @@ struct Group {
   int64_t c0 = 0;   // first coefficient
   int64_t q0 = 0;   // first point value
   int64_t f0 = 0;   // first factor entry
+  int64_t d0 = 0;   // first derivative-factor entry
 };
 
 }  // namespace nk
@@ -150,6 +166,11 @@ struct nk_space_s {
   int64_t nelem = 0, ncoeff = 0, npoint = 0, nfac = 0;
   double* fac64 = nullptr;
   float* fac32 = nullptr;
+  // derivative factors [E][d*d + 1][Q^d], standard point order: J^{-1}
+  // (d xi_a / d x_c at index a*d + c), then w detJ
+  int64_t ndfac = 0;
+  double* dfac64 = nullptr;
+  float* dfac32 = nullptr;
   double* kappa = nullptr;   // copy of kappa per point (null = 1)
   // variable-order persistent launch tables
   nk::VarpGroup* varp_groups = nullptr;

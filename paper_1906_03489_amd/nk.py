@@ -32,7 +32,7 @@ EXPORTS = [
     "nk_system_create_batched", "nk_system_destroy", "nk_system_apply", "nk_assemble",
     "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
-    "nk_space_get_strategy",
+    "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
 ]
 
 
@@ -93,6 +93,9 @@ def lib():
         "nk_set_tile_config": (i32, [i32, i32, i32, i32, i32]),
         "nk_space_set_strategy": (i32, [vp, i32, i32]),
         "nk_space_get_strategy": (i32, [vp, i32]),
+        "nk_phys_deriv": (i32, [vp, i32, vp, vp, vp]),
+        "nk_iprod_wrt_deriv_base": (i32, [vp, i32, vp, vp, vp]),
+        "nk_fwd_trans": (i32, [vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -232,6 +235,36 @@ def iprod_wrt_base(space: Space, phys, coeffs=None, dtype=F64):
     coeffs = _out(coeffs, nc, td, phys.device)
     _check(lib().nk_iprod_wrt_base(space.handle, dtype, _ptr(phys, td, "phys"),
                                    _ptr(coeffs, td, "coeffs"), _stream()))
+    return coeffs
+
+
+def phys_deriv(space: Space, phys, deriv=None, dtype=F64):
+    """deriv[e, c, q] = d u / d x_c at the quadrature points (flat [E*d*Q^d])."""
+    _, _, npnt = space.sizes()
+    td = _tdtype(dtype)
+    deriv = _out(deriv, npnt * space.dim, td, phys.device)
+    _check(lib().nk_phys_deriv(space.handle, dtype, _ptr(phys, td, "phys"),
+                               _ptr(deriv, td, "deriv"), _stream()))
+    return deriv
+
+
+def iprod_wrt_deriv_base(space: Space, f, coeffs=None, dtype=F64):
+    """coeffs = IProductWRTDerivBase(f) for a vector field f [E][d][Q^d]."""
+    _, nc, _ = space.sizes()
+    td = _tdtype(dtype)
+    coeffs = _out(coeffs, nc, td, f.device)
+    _check(lib().nk_iprod_wrt_deriv_base(space.handle, dtype, _ptr(f, td, "f"),
+                                         _ptr(coeffs, td, "coeffs"), _stream()))
+    return coeffs
+
+
+def fwd_trans(space: Space, phys, coeffs=None, dtype=F64):
+    """coeffs = FwdTrans(phys): per-element L2 projection (3-D spaces)."""
+    _, nc, _ = space.sizes()
+    td = _tdtype(dtype)
+    coeffs = _out(coeffs, nc, td, phys.device)
+    _check(lib().nk_fwd_trans(space.handle, dtype, _ptr(phys, td, "phys"),
+                              _ptr(coeffs, td, "coeffs"), _stream()))
     return coeffs
 
 

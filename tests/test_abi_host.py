@@ -65,7 +65,8 @@ def test_invalid_arguments_rejected_before_device_work():
     assert b"jac" in L.nk_last_error()
     assert L.nk_space_create(ctypes.byref(h), 3, 1, 11, 13, ctypes.c_void_p(8), None, None) == nk.NK_EUNSUPPORTED
     assert L.nk_space_create(ctypes.byref(h), 3, 1, 6, 9, ctypes.c_void_p(8), None, None) == nk.NK_EUNSUPPORTED
-    for f in ("nk_bwd_trans", "nk_iprod_wrt_base"):
+    for f in ("nk_bwd_trans", "nk_iprod_wrt_base", "nk_phys_deriv", "nk_iprod_wrt_deriv_base",
+              "nk_fwd_trans"):
         assert getattr(L, f)(None, 0, None, None, None) == nk.NK_EINVAL
     assert L.nk_helmholtz(None, 0, None, 1.0, None, None, None) == nk.NK_EINVAL
     assert L.nk_system_create(ctypes.byref(h), None, 5, None, None, None, 1.0, None) == nk.NK_EINVAL

@@ -1,0 +1,124 @@
+"""GPU parity of PhysDeriv, IProductWRTDerivBase and FwdTrans against the
+oracle (dense collocation derivative with the chain rule, dense D_a B
+products, dense elemental mass solves), on warped hexes and affine quads.
+
+Tolerances.  FP64 operators: 1e-12 relative 2-norm, as for the other
+operators.  FP32 PhysDeriv and IProductWRTDerivBase: 1e-5; each output is a
+sum of Q products of the collocation (or D_a B) entries, which alternate in
+sign and exceed the result by up to ~Q^2/2 at Q <= 12, so the FP32 rounding
+of 6e-8 per term grows to a few 1e-6 normwise.  FwdTrans solves with M_e,
+whose condition number reaches ~1e7 at P=6 in the modified basis: the result
+is checked by its FP64 residual as the oracle recomputes it (<= 1e-12 of the
+right-hand side), by the mass-norm distance to the oracle's dense solution
+(the physical-space error, bounded by residual x sqrt(cond) ~ 1e-13 x 3e3),
+and by coefficients within cond x 1e-16 ~ 1e-8 (looser: both solves round).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_common import FP64_RTOL, assert_close, jacobians, nk, rel_err, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+FP32_DERIV_RTOL = 1e-5
+
+
+def _mesh(dim, P, shape=None, amp=None):
+    shape = shape or ((2, 2, 1) if dim == 3 else (3, 2))
+    amp = (W.WARP_AMPLITUDE if dim == 3 else 0.0) if amp is None else amp
+    Jg, Jo, lat = jacobians(shape, P, amp)
+    return Jg, Jo, lat
+
+
+@pytest.mark.parametrize("dim,P", [(3, 1), (3, 2), (3, 3), (3, 5), (3, 6), (3, 7), (3, 8), (3, 10),
+                                   (2, 2), (2, 4), (2, 7), (2, 10)])
+def test_phys_deriv_and_iprod_deriv_match_oracle(dim, P):
+    torch = torch_cuda()
+    m = nk()
+    Q = P + 2
+    Jg, Jo, lat = _mesh(dim, P)
+    E, nq = lat.nelem, Q ** dim
+    ops = oracle.ElementOps(dim, P, Q, Jo)
+    u = W.uniform(W.seed(0, 1) + P, (E, nq))
+    f = W.uniform(W.seed(0, 1) + 50 + P, (E, dim, nq))
+    space = m.Space.create(dim, P, Q, to_dev(Jg))
+    du_ref = ops.phys_deriv(u)
+    ip_ref = ops.iprod_deriv(f)
+    for dt, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_DERIV_RTOL)):
+        td = torch.float64 if dt == m.F64 else torch.float32
+        du = m.phys_deriv(space, to_dev(u.ravel(), td), dtype=dt)
+        assert_close(du.double().cpu().numpy(), du_ref.ravel(), tol, f"phys_deriv P={P} dt={dt}")
+        ip = m.iprod_wrt_deriv_base(space, to_dev(f.ravel(), td), dtype=dt)
+        assert_close(ip.double().cpu().numpy(), ip_ref.ravel(), tol, f"iprod_deriv P={P} dt={dt}")
+
+
+def test_iprod_deriv_of_phys_deriv_is_the_laplacian_on_gpu():
+    """Composed on the GPU: IProductWRTDerivBase(PhysDeriv(BwdTrans c)) equals
+    the local Helmholtz operator with lambda = 0 (kappa = 1) applied to c."""
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 5, 7
+    Jg, _, lat = _mesh(3, P, shape=(2, 2, 2))
+    c = to_dev(W.uniform(W.seed(0, 0) + 7, (lat.nelem, (P + 1) ** 3)).ravel())
+    space = m.Space.create(3, P, Q, to_dev(Jg))
+    lap = m.helmholtz(space, c, lam0=0.0)
+    got = m.iprod_wrt_deriv_base(space, m.phys_deriv(space, m.bwd_trans(space, c)))
+    assert_close(got.cpu().numpy(), lap.cpu().numpy(), 1e-11, "div grad")
+
+
+def _mass_norm(ops, d):
+    return np.sqrt(sum(d[e] @ ops.mass_matrix(e) @ d[e] for e in range(ops.nelem)))
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 6, 7, 8, 10])
+def test_fwd_trans_matches_oracle(P):
+    torch = torch_cuda()
+    m = nk()
+    Q = P + 2
+    Jg, Jo, lat = _mesh(3, P, shape=(2, 1, 2))
+    E = lat.nelem
+    ops = oracle.ElementOps(3, P, Q, Jo)
+    f = W.uniform(W.seed(0, 1) + 100 + P, (E, Q ** 3))
+    ref = ops.fwd(f)
+    rhs = ops.iprod(f)
+    space = m.Space.create(3, P, Q, to_dev(Jg))
+    x = m.fwd_trans(space, to_dev(f.ravel())).cpu().numpy().reshape(E, -1)
+    res = np.stack([rhs[e] - ops.mass_matrix(e) @ x[e] for e in range(E)])
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(rhs)
+    assert _mass_norm(ops, x - ref) <= 1e-10 * _mass_norm(ops, ref)
+    assert rel_err(x, ref) <= 1e-7
+    # FP32: the projection in physical space (mass norm) to FP32 accuracy
+    x32 = m.fwd_trans(space, to_dev(f.ravel(), torch.float32), dtype=m.F32)
+    x32 = x32.double().cpu().numpy().reshape(E, -1)
+    assert _mass_norm(ops, x32 - ref) <= 2e-5 * _mass_norm(ops, ref)
+
+
+def test_fwd_trans_inverts_bwd_trans_on_gpu():
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 6, 8
+    Jg, _, lat = _mesh(3, P, shape=(3, 2, 2))
+    c = W.uniform(W.seed(0, 0) + 9, (lat.nelem, (P + 1) ** 3))
+    space = m.Space.create(3, P, Q, to_dev(Jg))
+    got = m.fwd_trans(space, m.bwd_trans(space, to_dev(c.ravel()))).cpu().numpy()
+    assert rel_err(got, c) <= 1e-8
+
+
+def test_fwd_trans_2d_unsupported_and_empty_space():
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 3, 5
+    Jg, _, lat = _mesh(2, P)
+    space = m.Space.create(2, P, Q, to_dev(Jg))
+    with pytest.raises(m.NkError) as ei:
+        m.fwd_trans(space, torch.zeros(lat.nelem * Q * Q, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    # zero elements: every operator is a no-op
+    J0 = np.zeros((0, 3, 3, (P + 2) ** 3))
+    s0 = m.Space.create(3, P, P + 2, to_dev(J0))
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    assert m.phys_deriv(s0, e).numel() == 0
+    assert m.iprod_wrt_deriv_base(s0, e).numel() == 0
+    assert m.fwd_trans(s0, e).numel() == 0
