@@ -162,6 +162,50 @@ def section_ops(nk, W, torch, space, lat, P, Q, reps):
     return out
 
 
+def section_deriv(nk, W, torch, space, lat, P, Q, reps):
+    """PhysDeriv, IProductWRTDerivBase and FwdTrans on the 32^3 workload,
+    FP64 and FP32, inputs rotating over buffer sets larger than the 256 MB
+    cache.  Algorithmic bytes per element: PhysDeriv s(Q^3 + 3Q^3 + 9Q^3)
+    (values, gradient, J^{-1}); IProductWRTDerivBase s(3Q^3 + 10Q^3 + n^3)
+    (field, J^{-1} and w detJ, coefficients); FwdTrans s(2Q^3 + n^3) (values,
+    w detJ, coefficients): its CG iterations run on chip, so it is bound by
+    arithmetic, not HBM, and hbm_frac only says how far.  gdof_s counts the
+    element's n^3 modes per second for all three."""
+    E = lat.nelem
+    n3, q3 = (P + 1) ** 3, Q ** 3
+    out = {}
+    for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
+        td = torch.float64 if dt == nk.F64 else torch.float32
+        nset = 3
+        us = [torch.from_numpy(W.uniform(W.seed(1, 1) + k, E * q3)).to(td).cuda() for k in range(nset)]
+        fs = [torch.from_numpy(W.uniform(W.seed(1, 1) + 10 + k, 3 * E * q3)).to(td).cuda()
+              for k in range(nset)]
+        dus = [torch.empty(3 * E * q3, dtype=td, device="cuda") for _ in range(nset)]
+        cs = [torch.empty(E * n3, dtype=td, device="cuda") for _ in range(nset)]
+        for op, bpe, bound, fn in (
+            ("phys_deriv", s * 13 * q3, "hbm", lambda k: nk.phys_deriv(space, us[k], dus[k], dtype=dt)),
+            ("iprod_wrt_deriv_base", s * (13 * q3 + n3), "hbm",
+             lambda k: nk.iprod_wrt_deriv_base(space, fs[k], cs[k], dtype=dt)),
+            ("fwd_trans", s * (2 * q3 + n3), "alu", lambda k: nk.fwd_trans(space, us[k], cs[k], dtype=dt)),
+        ):
+            for k in range(nset):
+                fn(k)
+            cnt = [0]
+
+            def step():
+                fn(cnt[0] % nset)
+                cnt[0] += 1
+            r = reps if bound == "hbm" else max(4, reps // 4)
+            ms = time_launches(step, r, torch)
+            gbs = bpe * E / (ms * 1e-3) / 1e9
+            out[f"{op}_{name}"] = {"ms": round(ms, 5), "gdof_s": round(E * n3 / (ms * 1e-3) / 1e9, 3),
+                                   "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "bound": bound}
+        del us, fs, dus, cs
+        torch.cuda.empty_cache()
+    return out
+
+
 def build_cg_problem(nk, W, torch, shape, P, amp):
     """Curved lattice, assembled system, weak RHS of the manufactured sine
     (built on the GPU with the library's own operators)."""
@@ -429,8 +473,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="ops,cg,batch,grad,cpu",
-                    help="comma list of ops,cg,batch,grad,cpu (or 'none')")
+    ap.add_argument("--sections", default="ops,deriv,cg,batch,grad,cpu",
+                    help="comma list of ops,deriv,cg,batch,grad,cpu (or 'none')")
     ap.add_argument("--cg-orders", default="4,6,8")
     ap.add_argument("--calib", action="store_true",
                     help="after the timed region, one 1 GiB device-to-device copy (counter calibration)")
@@ -504,6 +548,9 @@ def main():
     if "ops" in secs:
         log("section ops ...")
         sections["ops_32c_P6"] = section_ops(nk, W, torch, space, lat, P, Q, 40)
+    if "deriv" in secs:
+        log("section deriv ...")
+        sections["deriv_32c_P6"] = section_deriv(nk, W, torch, space, lat, P, Q, 40)
     del space, x, y
     torch.cuda.empty_cache()
     if "cg" in secs:

@@ -122,3 +122,28 @@ def test_fwd_trans_2d_unsupported_and_empty_space():
     assert m.phys_deriv(s0, e).numel() == 0
     assert m.iprod_wrt_deriv_base(s0, e).numel() == 0
     assert m.fwd_trans(s0, e).numel() == 0
+
+
+def test_full_size_32cube_p6_sampled():
+    """The 32^3, P=6 curved workload at full size in the launch configuration
+    the benchmark times; the oracle checks a seeded sample of elements (first,
+    last and 10 random) for all three operators."""
+    torch = torch_cuda()
+    m = nk()
+    cfg = W.CONFIGS[1]
+    P, Q = cfg["P"], cfg["Q"]
+    lat = W.lattice(cfg["shape"])
+    E = lat.nelem
+    space = m.Space.create(3, P, Q, to_dev(W.element_jacobians(m.basis_tables(P, Q)[0], lat, cfg["warp"])))
+    u = W.uniform(W.seed(1, 1), (E, Q ** 3))
+    f = W.uniform(W.seed(1, 1) + 10, (E, 3, Q ** 3))
+    du = m.phys_deriv(space, to_dev(u.ravel())).cpu().numpy().reshape(E, 3, -1)
+    ip = m.iprod_wrt_deriv_base(space, to_dev(f.ravel())).cpu().numpy().reshape(E, -1)
+    fw = m.fwd_trans(space, to_dev(u.ravel())).cpu().numpy().reshape(E, -1)
+    sample = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(6).choice(E, 10, replace=False)]))
+    Jo = W.element_jacobians(oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[sample]), cfg["warp"])
+    ops = oracle.ElementOps(3, P, Q, Jo)
+    assert_close(du[sample], ops.phys_deriv(u[sample]), FP64_RTOL, "full-size phys_deriv")
+    assert_close(ip[sample], ops.iprod_deriv(f[sample]), FP64_RTOL, "full-size iprod_deriv")
+    ref = ops.fwd(u[sample])
+    assert _mass_norm(ops, fw[sample] - ref) <= 1e-10 * _mass_norm(ops, ref)
