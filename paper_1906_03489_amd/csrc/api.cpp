@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <sstream>
@@ -68,6 +69,9 @@ static hipError_t launch_op(int dim, nk_dtype t, const OpArgs& a) {
 
 // ------------------------------------------------------------- tile choice
 static std::atomic<int> g_tile[OP_COUNT][2][kMaxP + 1][2];
+// set once a caller chose the Helmholtz tile explicitly (or NK_TILE is set):
+// systems then use that choice instead of timing their own operator
+static std::atomic<bool> g_tile_forced[2][kMaxP + 1][2];
 
 // vector-ALU tile candidates (elements per block)
 static int vector_tile_count(int op, int dim, int P) {
@@ -115,6 +119,9 @@ static int cur_tile(int op, int dim, int P, nk_dtype t) {
       for (auto& b : a)
         for (auto& c : b)
           for (auto& d : c) d.store(v);
+    for (auto& a : g_tile_forced)
+      for (auto& b : a)
+        for (auto& c : b) c.store(f != nullptr);
   });
   int k = g_tile[op][dim - 2][P][t].load();
   if (k < 0 || k >= tile_count(op, dim, P)) k = 0;
@@ -654,6 +661,8 @@ static hipError_t alloc_state(CgState& c, int n) {
   return hipMemset(c.cnt, 0, n * sizeof(int32_t));
 }
 
+static int tune_asm_tile(nk_system y, nk_dtype t, hipStream_t st);
+
 nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
                                    const int64_t* dof_off, const int32_t* l2g,
                                    const uint8_t* dirichlet, const double* lambda, double lambda0,
@@ -835,8 +844,12 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   dfree(d_D);
   if (e != hipSuccess) return cleanup(hip_fail(e, "system setup"));
   if (bad) return cleanup(fail(NK_EINVAL, "l2g index outside its system's DOF range"));
-  y->tile64 = cur_tile(OP_HELM_ASM, s->dim, G.P, NK_F64);
-  y->tile32 = cur_tile(OP_HELM_ASM, s->dim, G.P, NK_F32);
+  y->tile64 = tune_asm_tile(y, NK_F64, st);
+  y->tile32 = tune_asm_tile(y, NK_F32, st);
+  // the timing runs wrote into the work vectors: clear them again
+  if ((e = vec_fill<double>(y->y, np, 0.0, st)) || (e = vec_fill<float>(y->y32, np, 0.f, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return cleanup(hip_fail(e, "system setup"));
   *out = y;
   return NK_OK;
 }
@@ -1220,6 +1233,61 @@ static void cache_store(const std::string& key, int tile, double us) {
   f << key << " " << tile << " " << us << "\n";
 }
 
+// Tile of a system's assembled operator: the caller's explicit Helmholtz
+// choice if there is one, else the fastest candidate timed on this system's
+// own operator (2 warm-up + 4 timed applications each), remembered per
+// process (and in NK_AUTOTUNE_CACHE) by order and dtype.
+static int tune_asm_tile(nk_system y, nk_dtype t, hipStream_t st) {
+  nk_space s = y->space;
+  const Group& G = s->groups[0];
+  const int fallback = cur_tile(OP_HELM_ASM, s->dim, G.P, t);
+  const int nt = tile_count(OP_HELM_ASM, s->dim, G.P);
+  if (nt <= 1 || G.nelem == 0 || g_tile_forced[s->dim - 2][G.P][t].load()) return fallback;
+  static std::map<std::string, int> memo;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string key = "asm_d" + std::to_string(s->dim) + "_P" + std::to_string(G.P) + "_Q" +
+                          std::to_string(G.Q) + "_" + (t == NK_F64 ? "f64" : "f32") + "_E2^" +
+                          std::to_string((int)std::log2((double)G.nelem)) + "_" + device_name();
+  auto it = memo.find(key);
+  if (it != memo.end()) return it->second;
+  int best = fallback;
+  if (!cache_lookup(key, &best)) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fallback;
+    }
+    const void* x = t == NK_F64 ? (const void*)y->p : (const void*)y->p32;
+    void* o = t == NK_F64 ? (void*)y->y : (void*)y->y32;
+    double best_us = 1e30;
+    for (int k = 0; k < nt; ++k) {
+      hipError_t e = hipSuccess;
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = sys_op(y, t, x, o, nullptr, nullptr, k, st);
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 4 && e == hipSuccess; ++r) e = sys_op(y, t, x, o, nullptr, nullptr, k, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      if (e != hipSuccess) {
+        best = fallback;
+        best_us = -1.0;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (250.0 * ms < best_us) {
+        best_us = 250.0 * ms;
+        best = k;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_us < 0) return fallback;
+    cache_store(key, best, best_us);
+  }
+  memo[key] = best;
+  return best;
+}
+
 nk_status nk_autotune(nk_space s, int op_mask, void* stream) {
   if (!s) return fail(NK_EINVAL, "space is NULL");
   NK_CHECK(check_device());
@@ -1338,6 +1406,7 @@ nk_status nk_set_tile_config(int op, int dim, int P, nk_dtype t, int tile) {
   if (tile < 0 || tile >= tile_count(op, dim, P)) return fail(NK_EINVAL, "tile index out of range");
   (void)cur_tile(op, dim, P, t);
   g_tile[op][dim - 2][P][t].store(tile);
+  if (op == OP_HELM) g_tile_forced[dim - 2][P][t].store(true);
   return NK_OK;
 }
 
