@@ -176,8 +176,7 @@ nk_status nk_iprod_wrt_deriv_base(nk_space s, nk_dtype t, const void* f, void* c
  * inverse of the tensor-product mass at the element's mean Jacobian
  * determinant, from a zero start, until the residual falls below 1e-13 (FP64)
  * or 2e-6 (FP32) of the right-hand side or after 100 iterations.  phys:
- * device [E][Q^3], coeffs: device [E][n^3], type t.  3-D spaces only
- * (NK_EUNSUPPORTED otherwise). */
+ * device [E][Q^d], coeffs: device [E][n^d], type t. */
 nk_status nk_fwd_trans(nk_space s, nk_dtype t, const void* phys, void* coeffs, void* stream);
 
 /* Weak form of the Helmholtz operator of a field given at the quadrature

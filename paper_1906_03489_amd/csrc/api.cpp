@@ -529,7 +529,6 @@ static nk_status deriv_op(nk_space s, int which, nk_dtype t, const void* in, voi
   if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
   const size_t sz = dsize(t);
   const int d = s->dim;
-  if (which == DERIV_FWD && d != 3) return fail(NK_EUNSUPPORTED, "FwdTrans is built for 3-D spaces");
   // element-major blocks: points [Q^d], vector fields [d][Q^d], coefficients [n^d]
   const int64_t vin = which == DERIV_IPROD ? d : 1, vout = which == DERIV_PHYS ? d : 1;
   const bool coeff_out = which != DERIV_PHYS;

@@ -550,6 +550,206 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
   }
 }
 
+// 2-D FwdTrans.  A slot is the smallest power of two >= Q threads (so the
+// slot-wide sums are lane-group shuffles); modal vectors are columns over q
+// held by thread p < N (mode m = p + N q); point arrays by thread j < Q as
+// columns over i.  Tables are read only at loop-uniform rows.
+template <int Q>
+constexpr int slot2_threads() {
+  return Q <= 4 ? 4 : Q <= 8 ? 8 : 16;
+}
+
+// Contract direction DIR (0: p, 1: q) of the N x N array X (layout [q][p])
+// with the table A: thread t < N owns the pencil along DIR.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void fd2_contract(T* __restrict__ X, const T* __restrict__ A, int t,
+                                             bool act) {
+  constexpr int stride = DIR == 0 ? 1 : N;
+  const int base = DIR == 0 ? t * N : t;
+  const bool me = act && t < N;
+  T x[N];
+  if (me) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = X[base + m * stride];
+  }
+  slot_sync<64>();
+  if (me) {
+#pragma unroll 2
+    for (int o = 0; o < N; ++o) {
+      const T* Ao = A + o * N;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) s += Ao[m] * x[m];
+      X[base + o * stride] = s;
+    }
+  }
+  slot_sync<64>();
+}
+
+template <typename T, int N, int Q, int EPB>
+__global__ void __launch_bounds__(EPB * slot2_threads<Q>())
+    k_fwd_trans2(const Tab<T, N, Q> tb, const T* __restrict__ tab, int64_t nelem,
+                 const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ dfac,
+                 double rtol2, int maxit) {
+  constexpr int NN = N * N, QQ = Q * Q, NT = slot2_threads<Q>();
+  static_assert(EPB * NT == 64, "one wavefront per block");
+  __shared__ T smem[EPB * QQ];
+  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
+  const int64_t nblk = (nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  const bool live = e < nelem;
+  const int64_t ee = live ? e : 0;
+  T* sm = smem + slot * QQ;
+  const bool pj = live && t < Q;   // point column j = t
+  const bool pm = live && t < N;   // modal column p = t
+  // w detJ along column j = t, and the mean Jacobian determinant c = sum / 2^2
+  T wj[Q];
+  const T* we = dfac + ee * (int64_t)(5 * QQ) + 4 * QQ;
+  if (live) {
+    for (int k = t; k < QQ; k += NT) sm[k] = we[k];
+  }
+  slot_sync<64>();
+  double ws = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    wj[i] = pj ? sm[i + Q * t] : T(0);
+    ws += (double)wj[i];
+  }
+  ws = slot_allsum<NT>(ws, nullptr);
+  const T inv_c = (T)(4.0 / ws);
+  slot_sync<64>();
+  // y = (B^T x B^T)(wj * (B x B) x) for the column layout of thread p
+  auto mass = [&](const T (&x)[N], T (&y)[N], bool with_bwd) {
+    if (with_bwd) {
+      // q -> j: thread p writes T1[j][p]
+      if (pm) {
+#pragma unroll 2
+        for (int j = 0; j < Q; ++j) {
+          const T* Bj = tb.B + j * N;
+          T s = 0;
+#pragma unroll
+          for (int q = 0; q < N; ++q) s += Bj[q] * x[q];
+          sm[j * N + t] = s;
+        }
+      }
+      slot_sync<64>();
+    }
+    // p -> i, times w detJ, i -> p: thread j
+    T s[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) s[p] = T(0);
+    if (pj) {
+      T a[N];
+      if (with_bwd) {
+#pragma unroll
+        for (int p = 0; p < N; ++p) a[p] = sm[t * N + p];
+      }
+#pragma unroll 2
+      for (int i = 0; i < Q; ++i) {
+        const T* Bi = tb.B + i * N;
+        T u;
+        if (with_bwd) {
+          u = 0;
+#pragma unroll
+          for (int p = 0; p < N; ++p) u += Bi[p] * a[p];
+        } else {
+          u = sm[i + Q * t];   // point values staged in LDS
+        }
+        const T mm = wj[i] * u;
+#pragma unroll
+        for (int p = 0; p < N; ++p) s[p] += Bi[p] * mm;
+      }
+    }
+    slot_sync<64>();
+    if (pj) {
+#pragma unroll
+      for (int p = 0; p < N; ++p) sm[t * N + p] = s[p];
+    }
+    slot_sync<64>();
+    // j -> q: thread p
+#pragma unroll
+    for (int q = 0; q < N; ++q) y[q] = T(0);
+    if (pm) {
+#pragma unroll 2
+      for (int j = 0; j < Q; ++j) {
+        const T* Bj = tb.B + j * N;
+        const T v = sm[j * N + t];
+#pragma unroll
+        for (int q = 0; q < N; ++q) y[q] += Bj[q] * v;
+      }
+    }
+    slot_sync<64>();
+  };
+  auto precond = [&](const T (&r)[N], T (&z)[N]) {
+    const T* VT = tab;
+    const T* V = tab + NN;
+    const T* S = tab + 2 * NN;
+    if (pm) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) sm[q * N + t] = r[q];
+    }
+    slot_sync<64>();
+    fd2_contract<T, N, 1>(sm, VT, t, live);
+    fd2_contract<T, N, 0>(sm, VT, t, live);
+    if (pm) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) sm[q * N + t] *= inv_c * S[q * N + t];
+    }
+    slot_sync<64>();
+    fd2_contract<T, N, 0>(sm, V, t, live);
+    fd2_contract<T, N, 1>(sm, V, t, live);
+#pragma unroll
+    for (int q = 0; q < N; ++q) z[q] = pm ? sm[q * N + t] : T(0);
+    slot_sync<64>();
+  };
+  // b = I_e(f): stage f in LDS, then the transposed sweeps
+  const T* fe = in + ee * (int64_t)QQ;
+  if (live) {
+    for (int k = t; k < QQ; k += NT) sm[k] = fe[k];
+  }
+  slot_sync<64>();
+  T b[N], dummy[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) dummy[q] = T(0);
+  mass(dummy, b, false);
+  T x[N], r[N], p[N], q[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    x[k] = T(0);
+    r[k] = b[k];
+  }
+  const double bb = slot_allsum<NT>(col_dot(b, b), nullptr);
+  precond(r, p);
+  double rz = slot_allsum<NT>(col_dot(r, p), nullptr);
+  bool done = !(bb > 0.0);
+  for (int it = 0; it < maxit && !done; ++it) {
+    mass(p, q, true);
+    const double pq = slot_allsum<NT>(col_dot(p, q), nullptr);
+    if (!(pq > 0.0)) break;
+    const T alpha = (T)(rz / pq);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      x[k] += alpha * p[k];
+      r[k] -= alpha * q[k];
+    }
+    const double rr = slot_allsum<NT>(col_dot(r, r), nullptr);
+    if (rr <= rtol2 * bb) {
+      done = true;
+      continue;
+    }
+    precond(r, q);
+    const double rzn = slot_allsum<NT>(col_dot(r, q), nullptr);
+    const T beta = (T)(rzn / rz);
+    rz = rzn;
+#pragma unroll
+    for (int k = 0; k < N; ++k) p[k] = q[k] + beta * p[k];
+  }
+  if (pm) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[e * NN + k * N + t] = x[k];
+  }
+}
+
 // ----------------------------------------------------------------- launchers
 
 template <typename T, int P>
@@ -582,6 +782,18 @@ static hipError_t run_deriv(int which, int dim, const DerivArgs& a) {
     else
       hipLaunchKernelGGL((k_iprod_deriv2<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
                          tb, a.nelem, in, out, df);
+    return hipGetLastError();
+  }
+  if (which == DERIV_FWD && dim == 2) {
+    constexpr int NT2 = slot2_threads<Q>();
+    constexpr int EPB2 = 64 / NT2;
+    const int64_t nb2 = (a.nelem + EPB2 - 1) / EPB2;
+    if (nb2 > 0x7fffffff) return hipErrorInvalidValue;
+    const T* tab = fastdiag_table<T>(P, Q, 2);
+    if (!tab) return hipErrorOutOfMemory;
+    const double rtol = sizeof(T) == 8 ? 1e-13 : 2e-6;
+    hipLaunchKernelGGL((k_fwd_trans2<T, N, Q, EPB2>), dim3((unsigned)nb2), dim3(64), 0, s, tb, tab,
+                       a.nelem, in, out, df, rtol * rtol, kFwdMaxIt);
     return hipGetLastError();
   }
   if (which == DERIV_FWD && dim == 3) {

@@ -259,7 +259,7 @@ def iprod_wrt_deriv_base(space: Space, f, coeffs=None, dtype=F64):
 
 
 def fwd_trans(space: Space, phys, coeffs=None, dtype=F64):
-    """coeffs = FwdTrans(phys): per-element L2 projection (3-D spaces)."""
+    """coeffs = FwdTrans(phys): per-element L2 projection."""
     _, nc, _ = space.sizes()
     td = _tdtype(dtype)
     coeffs = _out(coeffs, nc, td, phys.device)

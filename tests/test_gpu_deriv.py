@@ -106,16 +106,63 @@ def test_fwd_trans_inverts_bwd_trans_on_gpu():
     assert rel_err(got, c) <= 1e-8
 
 
-def test_fwd_trans_2d_unsupported_and_empty_space():
+@pytest.mark.parametrize("P", [1, 3, 4, 7, 10])
+def test_fwd_trans_2d_matches_oracle(P):
     torch = torch_cuda()
     m = nk()
-    P, Q = 3, 5
-    Jg, _, lat = _mesh(2, P)
+    Q = P + 2
+    Jg, Jo, lat = _mesh(2, P, shape=(3, 2))
+    E = lat.nelem
+    ops = oracle.ElementOps(2, P, Q, Jo)
+    f = W.uniform(W.seed(0, 1) + 200 + P, (E, Q ** 2))
+    ref = ops.fwd(f)
+    rhs = ops.iprod(f)
     space = m.Space.create(2, P, Q, to_dev(Jg))
-    with pytest.raises(m.NkError) as ei:
-        m.fwd_trans(space, torch.zeros(lat.nelem * Q * Q, dtype=torch.float64, device="cuda"))
-    assert ei.value.status == m.NK_EUNSUPPORTED
-    # zero elements: every operator is a no-op
+    x = m.fwd_trans(space, to_dev(f.ravel())).cpu().numpy().reshape(E, -1)
+    res = np.stack([rhs[e] - ops.mass_matrix(e) @ x[e] for e in range(E)])
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(rhs)
+    assert _mass_norm(ops, x - ref) <= 1e-10 * _mass_norm(ops, ref)
+    x32 = m.fwd_trans(space, to_dev(f.ravel(), torch.float32), dtype=m.F32)
+    x32 = x32.double().cpu().numpy().reshape(E, -1)
+    assert _mass_norm(ops, x32 - ref) <= 2e-5 * _mass_norm(ops, ref)
+
+
+def test_listing_projection_and_integral_on_gpu():
+    """The listing of section 3.5 on the GPU: one standard quadrilateral
+    [-1,1]^2, 8 modes (P=7) and 9 GLL points per direction, f = cos x cos y.
+    Its integral (the sum of the four vertex-mode entries of
+    IProductWRTBase(f), since the vertex modes sum to 1) is 4 sin^2(1), the
+    value the text prints (tests/golden); FwdTrans(f) is the Galerkin
+    projection: the oracle finds I(f - BwdTrans(FwdTrans f)) = 0 and the
+    projection's integral equals the integral of f."""
+    import os
+    torch = torch_cuda()
+    m = nk()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "listing1_integral.txt")) as fh:
+        nm, npts, exact = [l for l in fh if not l.startswith("#")][0].split()
+    P, Q, exact = int(nm) - 1, int(npts), float(exact)
+    xg = m.basis_tables(P, Q)[0]
+    J = np.zeros((1, 2, 2, Q * Q))
+    J[0, 0, 0] = J[0, 1, 1] = 1.0
+    space = m.Space.create(2, P, Q, to_dev(J))
+    X, Y = np.meshgrid(xg, xg, indexing="ij")
+    f = (np.cos(X) * np.cos(Y)).T.ravel()          # point q = i + Q j
+    n = P + 1
+    vert = [0, P, P * n, P * n + P]
+    I = m.iprod_wrt_base(space, to_dev(f)).cpu().numpy()
+    assert abs(I[vert].sum() - exact) < 1e-14
+    c = m.fwd_trans(space, to_dev(f))
+    Ic = m.iprod_wrt_base(space, m.bwd_trans(space, c)).cpu().numpy()
+    assert abs(Ic[vert].sum() - exact) < 1e-13
+    ops = oracle.ElementOps(2, P, Q, J)
+    r = ops.iprod(f[None] - ops.bwd(c.cpu().numpy()[None]))
+    assert np.abs(r).max() < 1e-14
+
+
+def test_empty_space_derivative_operators():
+    torch = torch_cuda()
+    m = nk()
+    P = 3
     J0 = np.zeros((0, 3, 3, (P + 2) ** 3))
     s0 = m.Space.create(3, P, P + 2, to_dev(J0))
     e = torch.zeros(0, dtype=torch.float64, device="cuda")
