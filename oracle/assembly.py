@@ -19,24 +19,36 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
+def _ragged(l2g):
+    """True for a list of per-element maps of different lengths (elements of
+    different orders); such maps and their local vectors stay lists."""
+    return isinstance(l2g, (list, tuple)) and len({len(g) for g in l2g}) > 1
+
+
 def gather(x, l2g):
     """Local copies x_loc[e, m] = x[l2g[e, m]]."""
-    return np.asarray(x, np.float64)[np.asarray(l2g)]
+    x = np.asarray(x, np.float64)
+    if _ragged(l2g):
+        return [x[np.asarray(g)] for g in l2g]
+    return x[np.asarray(l2g)]
 
 
 def assemble_vector(yloc, l2g, nglobal):
     """Scatter-add y[l2g[e, m]] += yloc[e, m] (the transpose of `gather`)."""
     y = np.zeros(nglobal)
+    if _ragged(l2g):
+        for g, v in zip(l2g, yloc):
+            np.add.at(y, np.asarray(g), np.asarray(v, np.float64))
+        return y
     np.add.at(y, np.asarray(l2g).ravel(), np.asarray(yloc, np.float64).ravel())
     return y
 
 
 def assembled_matrix(mats, l2g, nglobal):
     """Global sparse matrix sum_e A_e^T H_e A_e from elemental matrices."""
-    l2g = np.asarray(l2g)
     rows, cols, vals = [], [], []
     for e, H in enumerate(mats):
-        g = l2g[e]
+        g = np.asarray(l2g[e])
         rows.append(np.repeat(g, g.size))
         cols.append(np.tile(g, g.size))
         vals.append(np.asarray(H).ravel())
@@ -48,8 +60,8 @@ def assembled_matrix(mats, l2g, nglobal):
 def jacobi_diagonal(mats, l2g, nglobal, dirichlet):
     """diag(A) assembled from the elemental diagonals; Dirichlet rows set to
     one (they are not unknowns)."""
-    dloc = np.stack([np.diag(H) for H in mats])
-    d = assemble_vector(dloc, l2g, nglobal)
+    dloc = [np.diag(H) for H in mats]
+    d = assemble_vector(dloc if _ragged(l2g) else np.stack(dloc), l2g, nglobal)
     d[np.asarray(dirichlet, bool)] = 1.0
     return d
 
@@ -59,14 +71,16 @@ class MaskedOperator:
 
     def __init__(self, mats, l2g, nglobal, dirichlet):
         self.mats = mats
-        self.l2g = np.asarray(l2g)
+        self.l2g = l2g if _ragged(l2g) else np.asarray(l2g)
         self.nglobal = int(nglobal)
         self.free = ~np.asarray(dirichlet, bool)
 
     def __call__(self, x):
         xm = np.where(self.free, x, 0.0)
         xl = gather(xm, self.l2g)
-        yl = np.stack([H @ xl[e] for e, H in enumerate(self.mats)])
+        yl = [H @ xl[e] for e, H in enumerate(self.mats)]
+        if not _ragged(self.l2g):
+            yl = np.stack(yl)
         y = assemble_vector(yl, self.l2g, self.nglobal)
         return np.where(self.free, y, 0.0)
 

@@ -533,3 +533,95 @@ def test_fwd_trans_inverts_bwd_and_is_galerkin(P):
     f = rng.uniform(-1, 1, (ops.nelem, (P + 2) ** 3))
     r = ops.iprod(f - ops.bwd(ops.fwd(f)))
     assert np.abs(r).max() < 1e-13 * np.abs(ops.iprod(f)).max()
+
+
+# ------------------------------------------- conforming variable-order assembly
+# (section 3.6: the order varies per element and the variation is built into
+# the assembly between neighbours; the modified basis' boundary-interior
+# decomposition makes the minimum rule on shared faces and edges conforming)
+
+def _varp_problem(shape, orders, amp=0.05, lam=1.0, mass_only=False):
+    perm, l2g, ng, dm = W.varp_lattice_l2g(shape, orders)
+    lat = W.lattice(shape)
+    ords = np.asarray(orders)[perm]
+    groups, mats = [], []
+    for P in sorted(set(ords.tolist())):
+        idx = perm[ords == P]
+        Q = P + 2
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[idx])
+        ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], sub, amp), lam=lam)
+        groups.append((P, idx, ops))
+        mats += oracle.mass_matrices(ops) if mass_only else oracle.helmholtz_matrices(ops)
+    return perm, l2g, ng, dm, groups, mats
+
+
+def _eval_expansion(P, c, pts):
+    """u(xi) = sum_m c_m phi_p(xi_1) phi_q(xi_2) phi_r(xi_3), m = p + n(q + n r)."""
+    n = P + 1
+    B = [oracle.modified_basis(P, pts[:, a])[0] for a in range(3)]     # (npts, n) each
+    C = c.reshape(n, n, n)                                             # [r][q][p]
+    return np.einsum("rqp,kp,kq,kr->k", C, B[0], B[1], B[2])
+
+
+def test_varp_uniform_orders_reduce_to_the_lattice_map():
+    perm, l2g, ng, dm = W.varp_lattice_l2g((2, 3, 2), [4] * 12)
+    g0, ng0, dm0 = W.lattice_l2g((2, 3, 2), 4)
+    assert ng == ng0 + 1 and dm[-1] == 1
+    np.testing.assert_array_equal(np.stack(l2g), g0)
+    np.testing.assert_array_equal(dm[:-1], dm0)
+
+
+def test_varp_assembly_is_continuous_across_faces():
+    """Any global coefficient vector gives element expansions whose traces
+    agree on every shared face (checked at random face points, both
+    elements' own bases): the minimum rule makes the space conforming."""
+    shape = (3, 2, 2)
+    orders = [2, 5, 3, 4, 2, 6, 3, 3, 5, 2, 4, 6]
+    perm, l2g, ng, dm, _, _ = _varp_problem(shape, orders)
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, ng)
+    x[-1] = 0.0                              # the constrained-mode DOF is zero
+    pos = {int(e): k for k, e in enumerate(perm)}
+    st = (1, shape[0], shape[0] * shape[1])
+    st_ = np.asarray(st)
+    ords = np.asarray(orders)
+    checked = 0
+    for e in range(int(np.prod(shape))):
+        ce = np.indices(shape[::-1]).reshape(3, -1)[::-1][:, e]
+        for a in range(3):
+            if ce[a] + 1 >= shape[a]:
+                continue
+            nb = e + st[a]
+            pts = rng.uniform(-1, 1, (9, 3))
+            pe, pn = pts.copy(), pts.copy()
+            pe[:, a], pn[:, a] = 1.0, -1.0
+            ue = _eval_expansion(ords[e], x[l2g[pos[e]]], pe)
+            un = _eval_expansion(ords[nb], x[l2g[pos[nb]]], pn)
+            np.testing.assert_allclose(ue, un, atol=1e-13)
+            checked += 1
+    assert checked == 20
+
+
+def test_varp_projection_reproduces_a_conforming_polynomial():
+    """X(1-X)Y(1-Y)Z(1-Z) (degree 2 per direction, zero on the boundary) lies
+    in the assembled variable-order space when every order is >= 2, so its
+    Galerkin projection with the assembled mass matrix returns it exactly at
+    every element's points (affine lattice)."""
+    shape = (2, 3, 2)
+    orders = [2, 3, 4, 2, 5, 2, 3, 4, 2, 6, 3, 2]
+    perm, l2g, ng, dm, groups, mats = _varp_problem(shape, orders, amp=0.0, mass_only=True)
+    lat = W.lattice(shape)
+    bl, fl = [None] * len(perm), {}
+    for P, idx, ops in groups:
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[idx])
+        X = W.lattice_points(ops.x, sub)                           # (E_g, 3, nq)
+        f = np.prod(X * (1 - X), axis=1)
+        rhs = ops.iprod(f)
+        for k, e in enumerate(idx):
+            k_space = int(np.flatnonzero(perm == e)[0])
+            bl[k_space] = rhs[k]
+            fl[k_space] = (ops, k, f[k])
+    b = oracle.assemble_vector(bl, l2g, ng)
+    x = direct_solve(mats, l2g, ng, dm, b)
+    for k_space, (ops, k, fk) in fl.items():
+        np.testing.assert_allclose(ops.bwd(x[l2g[k_space]][None])[0], fk, atol=1e-13)

@@ -146,7 +146,7 @@ def element_jacobians(xi: np.ndarray, lat: Lattice, amp: float) -> np.ndarray:
     X = lattice_points(xi, lat)
     if amp == 0.0:
         d = lat.dim
-        J = np.zeros((lat.nelem, d, d, X.shape[-1]))
+        J = np.zeros((X.shape[0], d, d, X.shape[-1]))
         for a in range(d):
             J[:, a, a, :] = lat.h[a] / 2.0
         return J
@@ -213,6 +213,77 @@ def lattice_l2g(shape, P: int):
     for c in range(d):
         dir_mask |= ((gall[c] == 0) | (gall[c] == G[c] - 1)).astype(np.uint8)
     return g.astype(np.int32), nglobal, dir_mask
+
+
+def varp_lattice_l2g(shape, orders):
+    """Conforming C0 map of a structured lattice whose elements carry their
+    own order P_e (per-element isotropic), by the minimum rule: a bubble mode
+    on a face or edge is a global DOF only up to the lowest order among the
+    elements sharing that face or edge; higher modes there are constrained
+    to zero.  The modified basis is hierarchical (bubble p is the same
+    function whatever P), so the kept face/edge modes coincide between
+    neighbours.
+
+    Elements are returned grouped by ascending order (the element order of a
+    mixed-order space): `perm[k]` is the lattice index of space element k.
+    Local modes are numbered p fastest as for uniform order.  Constrained
+    modes map to one extra global DOF (the last) that is flagged Dirichlet,
+    so they read as zero and receive nothing.  Global DOFs are numbered in
+    lattice order of their position on the P_max grid; Dirichlet = lattice
+    boundary.  Returns (perm, [l2g of each space element], nglobal,
+    dirichlet uint8)."""
+    shape = tuple(int(s) for s in shape)
+    d = len(shape)
+    E = int(np.prod(shape))
+    orders = np.asarray(orders, np.int64).reshape(E)
+    Pm = int(orders.max())
+    G = [s * Pm + 1 for s in shape]
+    eidx = np.indices(shape[::-1]).reshape(d, -1)[::-1].T          # (E, d)
+    strides = np.cumprod([1] + list(shape[:-1]))
+    keys, sharedmin = [], {}
+    for e in range(E):
+        P = int(orders[e])
+        m = np.indices((P + 1,) * d).reshape(d, -1)[::-1]            # (d, n^d)
+        side = np.where(m == 0, 0, np.where(m == P, 2, 1))           # L, B, R
+        pat = (side * (3 ** np.arange(d))[:, None]).sum(axis=0)
+        ok = np.ones(m.shape[1], bool)
+        g = np.zeros(m.shape[1], np.int64)
+        for c in range(d - 1, -1, -1):
+            gc = eidx[e, c] * Pm + np.where(side[c] == 0, 0, np.where(side[c] == 2, Pm, m[c]))
+            g = gc + G[c] * g
+        for s in np.unique(pat):
+            sd = [(s // 3 ** c) % 3 for c in range(d)]
+            if all(x == 1 for x in sd) or all(x != 1 for x in sd):
+                continue                     # interior modes, or a vertex: nothing to limit
+            pmin = P
+            offs = [[0] if x == 1 else ([0, -1] if x == 0 else [0, 1]) for x in sd]
+            for dl in np.array(np.meshgrid(*offs, indexing="ij")).reshape(d, -1).T:
+                nb = eidx[e] + dl
+                if np.all(nb >= 0) and np.all(nb < np.asarray(shape)):
+                    pmin = min(pmin, int(orders[int(nb @ strides)]))
+            sel = pat == s
+            for c in range(d):
+                if sd[c] == 1:
+                    ok[sel] &= m[c][sel] <= pmin - 1
+        g[~ok] = -1
+        keys.append(g)
+    used = np.unique(np.concatenate([k[k >= 0] for k in keys]))
+    nglobal = used.size + 1                                        # + the zero DOF
+    rank = {int(v): i for i, v in enumerate(used)}
+    zero = nglobal - 1
+    perm = np.argsort(orders, kind="stable")
+    l2g = []
+    for e in perm:
+        k = keys[e]
+        l2g.append(np.array([rank[int(v)] if v >= 0 else zero for v in k], np.int32))
+    gl = used.copy()
+    dirichlet = np.zeros(nglobal, np.uint8)
+    for c in range(d):
+        gc = gl % G[c]
+        gl = gl // G[c]
+        dirichlet[:-1] |= ((gc == 0) | (gc == G[c] - 1)).astype(np.uint8)
+    dirichlet[zero] = 1
+    return perm, l2g, nglobal, dirichlet
 
 
 # ----------------------------------------------------------- draws
