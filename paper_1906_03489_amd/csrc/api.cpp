@@ -660,7 +660,7 @@ static hipError_t alloc_state(CgState& c, int n) {
   return hipMemset(c.cnt, 0, n * sizeof(int32_t));
 }
 
-static int tune_asm_tile(nk_system y, nk_dtype t, hipStream_t st);
+static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st);
 
 nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
                                    const int64_t* dof_off, const int32_t* l2g,
@@ -669,8 +669,9 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   if (!out) return fail(NK_EINVAL, "out is NULL");
   *out = nullptr;
   if (!s) return fail(NK_EINVAL, "space is NULL");
-  if (s->groups.size() != 1) return fail(NK_EINVAL, "systems need a single-order space");
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
+  if (s->groups.size() != 1 && nsys != 1)
+    return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
   if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
     return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");
@@ -680,9 +681,8 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
       return fail(NK_EINVAL, "offsets must be non-decreasing");
   }
   if (dof_off[nsys] >= ((int64_t)1 << 30)) return fail(NK_EINVAL, "too many global DOFs");
-  const Group& G = s->groups[0];
-  const int nloc = (int)ipow(G.n, s->dim);
-  NK_CHECK(check_buf(l2g, (size_t)s->nelem * nloc * 4, "l2g"));
+  if (s->ncoeff >= ((int64_t)1 << 31) - 1) return fail(NK_EINVAL, "too many local coefficients");
+  NK_CHECK(check_buf(l2g, (size_t)s->ncoeff * 4, "l2g"));
   NK_CHECK(check_buf(dirichlet, (size_t)dof_off[nsys], "dirichlet"));
   if (lambda) NK_CHECK(check_buf(lambda, s->nelem * 8, "lambda"));
   NK_CHECK(check_device());
@@ -741,7 +741,7 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   NK_ALLOC(y->d_blk_first, nsys + 1);
   NK_ALLOC(y->d_blk_seg, y->L.nblk);
   NK_ALLOC(y->elem_seg, std::max<int64_t>(s->nelem, 1));
-  NK_ALLOC(y->l2g, std::max<int64_t>(s->nelem * nloc, 1));
+  NK_ALLOC(y->l2g, std::max<int64_t>(s->ncoeff, 1));
   if (lambda) NK_ALLOC(y->lam, s->nelem);
   NK_ALLOC(y->diag, np);
   NK_ALLOC(y->dinv64, np);
@@ -791,16 +791,24 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   // setup runs on the caller's stream, then synchronises it
   int* d_bad = nullptr;
   double *d_B = nullptr, *d_D = nullptr;
-  const int QN = G.Q * G.n;
-  if ((e = dmalloc(&d_bad, 1)) || (e = dmalloc(&d_B, QN)) || (e = dmalloc(&d_D, QN))) {
+  // 1-D tables of every order group, one after the other
+  std::vector<double> hB, hD;
+  std::vector<int64_t> tab_off;
+  for (const Group& G : s->groups) {
+    const int QN = G.Q * G.n;
+    std::vector<double> xq(G.Q), wq(G.Q), b(QN), d(QN);
+    gll_points(G.Q, xq.data(), wq.data());
+    modified_basis(G.P, G.Q, xq.data(), b.data(), d.data());
+    tab_off.push_back((int64_t)hB.size());
+    hB.insert(hB.end(), b.begin(), b.end());
+    hD.insert(hD.end(), d.begin(), d.end());
+  }
+  if ((e = dmalloc(&d_bad, 1)) || (e = dmalloc(&d_B, hB.size())) || (e = dmalloc(&d_D, hD.size()))) {
     dfree(d_bad);
     dfree(d_B);
     dfree(d_D);
     return cleanup(hip_fail(e, "hipMalloc"));
   }
-  std::vector<double> xq(G.Q), wq(G.Q), hB(QN), hD(QN);
-  gll_points(G.Q, xq.data(), wq.data());
-  modified_basis(G.P, G.Q, xq.data(), hB.data(), hD.data());
   do {
     if ((e = hipMemcpyAsync(y->d_dof_off, dof_off, (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
     if ((e = hipMemcpyAsync(y->d_pdof_off, y->pdof_off.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
@@ -815,23 +823,29 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
     if (s->nelem > 0 &&
         (e = hipMemcpyAsync(y->elem_seg, eseg.data(), s->nelem * 4, hipMemcpyHostToDevice, st))) break;
     if (lambda && (e = hipMemcpyAsync(y->lam, lambda, s->nelem * 8, hipMemcpyDeviceToDevice, st))) break;
-    if ((e = hipMemcpyAsync(d_B, hB.data(), QN * 8, hipMemcpyHostToDevice, st))) break;
-    if ((e = hipMemcpyAsync(d_D, hD.data(), QN * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(d_B, hB.data(), hB.size() * 8, hipMemcpyHostToDevice, st))) break;
+    if ((e = hipMemcpyAsync(d_D, hD.data(), hD.size() * 8, hipMemcpyHostToDevice, st))) break;
     if ((e = hipMemsetAsync(d_bad, 0, 4, st))) break;
-    if ((e = build_l2g(s->nelem, nloc, y->elem_seg, y->d_dof_off, y->d_pdof_off, l2g, dirichlet,
-                       y->l2g, d_bad, st)))
-      break;
     if ((e = vec_fill<double>(y->diag, np, 0.0, st))) break;
     if ((e = vec_fill<double>(y->y, np, 0.0, st))) break;
-    if ((e = mark_free(s->nelem, nloc, y->l2g, y->y, st))) break;
-    if ((e = launch_diag(s->dim, G.P, G.Q, s->nelem, d_B, d_D, s->fac64, y->lam, y->lam0, y->l2g,
-                         y->diag, st)))
-      break;
+    for (size_t g = 0; g < s->groups.size() && e == hipSuccess; ++g) {
+      const Group& G = s->groups[g];
+      const int nl = (int)ipow(G.n, s->dim);
+      if ((e = build_l2g(G.nelem, nl, y->elem_seg + G.e0, y->d_dof_off, y->d_pdof_off, l2g + G.c0,
+                         dirichlet, y->l2g + G.c0, d_bad, st)))
+        break;
+      if ((e = mark_free(G.nelem, nl, y->l2g + G.c0, y->y, st))) break;
+      e = launch_diag(s->dim, G.P, G.Q, G.nelem, d_B + tab_off[g], d_D + tab_off[g], s->fac64 + G.f0,
+                      y->lam ? y->lam + G.e0 : nullptr, y->lam0, y->l2g + G.c0, y->diag, st);
+    }
+    if (e) break;
     if ((e = diag_finish(y->L, y->diag, y->y, y->dinv64, y->dinv32, y->diag, st))) break;
     for (double* v : {y->b, y->x, y->r, y->p, y->y, y->u, y->s})
       if ((e = vec_fill<double>(v, np, 0.0, st))) break;
+    if (e) break;
     for (float* v : {y->r32, y->p32, y->y32, y->d32, y->u32, y->s32})
       if ((e = vec_fill<float>(v, np, 0.f, st))) break;
+    if (e) break;
     if ((e = vec_fill<int32_t>(y->outer_cnt, nsys, 0, st))) break;
     if ((e = vec_fill<int32_t>(y->cnt_aux, nsys, 0, st))) break;
     e = hipStreamSynchronize(st);
@@ -843,8 +857,10 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   dfree(d_D);
   if (e != hipSuccess) return cleanup(hip_fail(e, "system setup"));
   if (bad) return cleanup(fail(NK_EINVAL, "l2g index outside its system's DOF range"));
-  y->tile64 = tune_asm_tile(y, NK_F64, st);
-  y->tile32 = tune_asm_tile(y, NK_F32, st);
+  for (size_t g = 0; g < s->groups.size(); ++g) {
+    y->tiles64.push_back(tune_asm_tile(y, NK_F64, (int)g, st));
+    y->tiles32.push_back(tune_asm_tile(y, NK_F32, (int)g, st));
+  }
   // the timing runs wrote into the work vectors: clear them again
   if ((e = vec_fill<double>(y->y, np, 0.0, st)) || (e = vec_fill<float>(y->y32, np, 0.f, st)) ||
       (e = hipStreamSynchronize(st)))
@@ -869,11 +885,12 @@ nk_status nk_system_destroy(nk_system sys) {
   return NK_OK;
 }
 
-// y (padded) += A x (padded) over all elements; dots per element if requested.
-static hipError_t sys_op(nk_system y, nk_dtype t, const void* x, void* out, double* dots,
-                         const int32_t* seg_done, int tile, hipStream_t st) {
+// y (padded) += A x (padded) over the elements of order group g; dots per
+// element if requested.
+static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, void* out,
+                               double* dots, const int32_t* seg_done, int tile, hipStream_t st) {
   nk_space s = y->space;
-  const Group& G = s->groups[0];
+  const Group& G = s->groups[g];
   OpArgs a;
   a.op = OP_HELM_ASM;
   a.dim = s->dim;
@@ -882,17 +899,30 @@ static hipError_t sys_op(nk_system y, nk_dtype t, const void* x, void* out, doub
   a.nelem = G.nelem;
   a.in = x;
   a.out = out;
-  a.fac = t == NK_F64 ? (const void*)s->fac64 : (const void*)s->fac32;
-  a.lam = y->lam;
+  a.fac = t == NK_F64 ? (const void*)(s->fac64 + G.f0) : (const void*)(s->fac32 + G.f0);
+  a.lam = y->lam ? y->lam + G.e0 : nullptr;
   a.lam0 = y->lam0;
-  a.l2g = y->l2g;
+  a.l2g = y->l2g + G.c0;
   a.dots = dots;
-  a.dslot = dots ? y->dslot : nullptr;
-  a.elem_seg = seg_done ? y->elem_seg : nullptr;
+  a.dslot = dots ? y->dslot + G.e0 : nullptr;
+  a.elem_seg = seg_done ? y->elem_seg + G.e0 : nullptr;
   a.seg_done = seg_done;
   a.tile = tile;
   a.stream = st;
   return launch_op(s->dim, t, a);
+}
+
+// y (padded) += A x (padded) over all elements, each order group with its
+// own tuned tile.
+static hipError_t sys_op(nk_system y, nk_dtype t, const void* x, void* out, double* dots,
+                         const int32_t* seg_done, hipStream_t st) {
+  const std::vector<int>& tiles = t == NK_F64 ? y->tiles64 : y->tiles32;
+  for (size_t g = 0; g < y->space->groups.size(); ++g) {
+    const hipError_t e = sys_op_group(y, t, (int)g, x, out, dots, seg_done,
+                                      g < tiles.size() ? tiles[g] : 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* yv, void* stream) {
@@ -907,7 +937,7 @@ nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* yv, vo
     if ((e = pad_in<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, (const double*)x,
                             sys->dinv64, sys->p, st)) ||
         (e = vec_fill<double>(sys->y, np, 0.0, st)) ||
-        (e = sys_op(sys, t, sys->p, sys->y, nullptr, nullptr, sys->tile64, st)) ||
+        (e = sys_op(sys, t, sys->p, sys->y, nullptr, nullptr, st)) ||
         (e = pad_out<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->y,
                              (double*)yv, st)))
       return hip_fail(e, "system apply");
@@ -915,7 +945,7 @@ nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* yv, vo
     if ((e = pad_in<float>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, (const float*)x,
                            sys->dinv64, sys->p32, st)) ||
         (e = vec_fill<float>(sys->y32, np, 0.f, st)) ||
-        (e = sys_op(sys, t, sys->p32, sys->y32, nullptr, nullptr, sys->tile32, st)) ||
+        (e = sys_op(sys, t, sys->p32, sys->y32, nullptr, nullptr, st)) ||
         (e = pad_out<float>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->y32,
                             (float*)yv, st)))
       return hip_fail(e, "system apply");
@@ -928,13 +958,12 @@ nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* yv, vo
 nk_status nk_assemble(nk_system sys, const double* y_loc, double* b, void* stream) {
   if (!sys) return fail(NK_EINVAL, "system is NULL");
   nk_space s = sys->space;
-  const int nloc = (int)ipow(s->groups[0].n, s->dim);
-  NK_CHECK(check_buf(y_loc, (size_t)s->nelem * nloc * 8, "y_loc"));
+  NK_CHECK(check_buf(y_loc, (size_t)s->ncoeff * 8, "y_loc"));
   NK_CHECK(check_buf(b, sys->nuser * 8, "b"));
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if ((e = vec_fill<double>(sys->y, sys->L.npad, 0.0, st)) ||
-      (e = scatter_add(s->nelem, nloc, sys->l2g, y_loc, sys->y, st)) ||
+      (e = scatter_add(s->ncoeff, 1, sys->l2g, y_loc, sys->y, st)) ||
       (e = pad_out<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, sys->y, b, st)) ||
       (e = hipStreamSynchronize(st)))
     return hip_fail(e, "assemble");
@@ -944,9 +973,8 @@ nk_status nk_assemble(nk_system sys, const double* y_loc, double* b, void* strea
 nk_status nk_gather(nk_system sys, const double* x, double* x_loc, void* stream) {
   if (!sys) return fail(NK_EINVAL, "system is NULL");
   nk_space s = sys->space;
-  const int nloc = (int)ipow(s->groups[0].n, s->dim);
   NK_CHECK(check_buf(x, sys->nuser * 8, "x"));
-  NK_CHECK(check_buf(x_loc, (size_t)s->nelem * nloc * 8, "x_loc"));
+  NK_CHECK(check_buf(x_loc, (size_t)s->ncoeff * 8, "x_loc"));
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   // Dirichlet entries are gathered as they are (not masked): the reported
@@ -954,7 +982,7 @@ nk_status nk_gather(nk_system sys, const double* x, double* x_loc, void* stream)
   // all-pass mask.
   if ((e = pad_in<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, x, sys->diag,
                           sys->p, st)) ||
-      (e = gather_user(s->nelem, nloc, sys->l2g, sys->p, x_loc, st)) ||
+      (e = gather_user(s->ncoeff, 1, sys->l2g, sys->p, x_loc, st)) ||
       (e = hipStreamSynchronize(st)))
     return hip_fail(e, "gather");
   return NK_OK;
@@ -1000,8 +1028,7 @@ static hipError_t cg_iteration(nk_system y, int maxit) {
   const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
   hipError_t e;
   if ((e = cg_update<T>(y->L, st, x, r, u, p, s, w, dinv, y->part, y->cs))) return e;
-  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, st.done, f64 ? y->tile64 : y->tile32,
-                  y->cs)))
+  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, st.done, y->cs)))
     return e;
   return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, maxit, f64, false, 0.0, nullptr,
                    nullptr, nullptr, y->cs);
@@ -1021,8 +1048,7 @@ static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int3
   const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
   hipError_t e;
   if ((e = cg_start<T>(y->L, b, w, r, u, p, s, dinv, y->part, y->cs))) return e;
-  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, nullptr, f64 ? y->tile64 : y->tile32,
-                  y->cs)))
+  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, nullptr, y->cs)))
     return e;
   return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, 1 << 30, f64, true, tau2,
                    outer_done, y->outer_tol2, y->outer_rr, y->cs);
@@ -1109,7 +1135,7 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
     if (mode == NK_SOLVE_F64) {
       if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->st64.tol2, cs))) break;
       if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
-      if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
+      if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) break;
       if ((e = cg_begin<double>(y, y->b, 0.0, nullptr))) break;
       if ((e = cg_loop<double>(y, maxit, y->st64.done))) break;
       if ((e = hipMemcpyAsync(y->h_flags, y->st64.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
@@ -1124,7 +1150,7 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
       const int max_outer = 60;
       int k = 0;
       for (; k < max_outer; ++k) {
-        if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
+        if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) break;
         if ((e = cg_residual(y->L, outer_st, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs)))
           break;
         if ((e = hipMemcpyAsync(y->h_flags, y->outer_done, ns * 4, hipMemcpyDeviceToHost, cs))) break;
@@ -1157,7 +1183,7 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
     chk.tol2 = y->outer_tol2;
     chk.cnt = y->cnt_aux;
     if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
-    if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->tile64, cs))) break;
+    if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) break;
     if ((e = cg_residual(y->L, chk, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs))) break;
     if ((e = pad_out<double>(ns, y->d_dof_off, y->d_pdof_off, y->nuser, y->x, x, cs))) break;
     if ((e = hipEventRecord(y->ev, cs)) || (e = hipStreamWaitEvent(us, y->ev, 0))) break;
@@ -1232,13 +1258,13 @@ static void cache_store(const std::string& key, int tile, double us) {
   f << key << " " << tile << " " << us << "\n";
 }
 
-// Tile of a system's assembled operator: the caller's explicit Helmholtz
-// choice if there is one, else the fastest candidate timed on this system's
-// own operator (2 warm-up + 4 timed applications each), remembered per
+// Tile of a system's assembled operator for order group g: the caller's
+// explicit Helmholtz choice if there is one, else the fastest candidate timed
+// on this system's own operator (2 warm-up + 4 timed applications each), remembered per
 // process (and in NK_AUTOTUNE_CACHE) by order and dtype.
-static int tune_asm_tile(nk_system y, nk_dtype t, hipStream_t st) {
+static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st) {
   nk_space s = y->space;
-  const Group& G = s->groups[0];
+  const Group& G = s->groups[g];
   const int fallback = cur_tile(OP_HELM_ASM, s->dim, G.P, t);
   const int nt = tile_count(OP_HELM_ASM, s->dim, G.P);
   if (nt <= 1 || G.nelem == 0 || g_tile_forced[s->dim - 2][G.P][t].load()) return fallback;
@@ -1261,9 +1287,9 @@ static int tune_asm_tile(nk_system y, nk_dtype t, hipStream_t st) {
     double best_us = 1e30;
     for (int k = 0; k < nt; ++k) {
       hipError_t e = hipSuccess;
-      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = sys_op(y, t, x, o, nullptr, nullptr, k, st);
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = sys_op_group(y, t, g, x, o, nullptr, nullptr, k, st);
       (void)hipEventRecord(e0, st);
-      for (int r = 0; r < 4 && e == hipSuccess; ++r) e = sys_op(y, t, x, o, nullptr, nullptr, k, st);
+      for (int r = 0; r < 4 && e == hipSuccess; ++r) e = sys_op_group(y, t, g, x, o, nullptr, nullptr, k, st);
       (void)hipEventRecord(e1, st);
       (void)hipEventSynchronize(e1);
       if (e != hipSuccess) {

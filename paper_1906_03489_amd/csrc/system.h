@@ -131,5 +131,5 @@ struct nk_system_s {
   hipEvent_t ev = nullptr;
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
   int g64_iters = 0, g32_iters = 0, g_maxit64 = -1, g_maxit32 = -1;
-  int tile64 = 0, tile32 = 0;
+  std::vector<int> tiles64, tiles32;   // assembled-operator tile per order group
 };

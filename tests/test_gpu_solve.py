@@ -210,3 +210,68 @@ def test_assembled_operator_and_cg_matrix_core_variant(P):
     finally:
         for dt in (m.F64, m.F32):
             m.set_tile_config(m.OP_HELM, 3, P, dt, 0)
+
+
+# ------------------------------------------- mixed-order (conforming) systems
+
+def _varp_case(shape, orders, amp=W.WARP_AMPLITUDE):
+    """Mixed-order space (groups by ascending order), its conforming map and
+    the oracle's elemental matrices in the same element order."""
+    from gpu_common import lib_points
+    m = nk()
+    perm, l2g, ng, dm = W.varp_lattice_l2g(shape, orders)
+    lat = W.lattice(shape)
+    ords = np.asarray(orders)[perm]
+    Ps = sorted(set(ords.tolist()))
+    jacs, mats, rhs_loc = [], [], []
+    for P in Ps:
+        idx = perm[ords == P]
+        Q = P + 2
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[idx])
+        jacs.append(to_dev(np.ascontiguousarray(W.element_jacobians(lib_points(P, Q), sub, amp))))
+        ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], sub, amp), lam=1.0)
+        mats += oracle.helmholtz_matrices(ops)
+        U, dU = W.manufactured_ref_gradient(ops.x, sub)
+        rhs_loc += list(ops.weak_rhs(U, dU))
+    space = m.Space.create_varp(3, Ps, [P + 2 for P in Ps], jacs)
+    sysm = m.System.create(space, ng, to_dev(np.concatenate(l2g)), to_dev(dm), lam0=1.0)
+    b = oracle.assemble_vector(rhs_loc, l2g, ng)
+    b[dm.astype(bool)] = 0.0
+    return dict(space=space, sysm=sysm, l2g=l2g, ng=ng, dm=dm, mats=mats, b=b)
+
+
+@pytest.mark.parametrize("shape,orders", [((3, 2, 2), [2, 5, 3, 4, 2, 6, 3, 3, 5, 2, 4, 6]),
+                                          ((2, 2, 2), [1, 8, 2, 7, 3, 6, 4, 10])])
+def test_mixed_order_assembled_operator_and_solves(shape, orders):
+    """Conforming variable-order system (minimum rule): the assembled operator
+    against the oracle's, FP64 and FP32-refined CG against the sparse direct
+    solve (residual recomputed by the oracle), gather and assembly."""
+    torch = torch_cuda()
+    m = nk()
+    c = _varp_case(shape, orders)
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"])
+    x = np.random.default_rng(11).uniform(-1, 1, c["ng"])
+    ref = A(x)
+    assert_close(c["sysm"].apply(to_dev(x)).cpu().numpy(), ref, FP64_RTOL, "varp apply")
+    y32 = c["sysm"].apply(to_dev(x, torch.float32), dtype=m.F32).double().cpu().numpy()
+    assert_close(y32, ref, FP32_RTOL, "varp apply32")
+    d = c["sysm"].diagonal().cpu().numpy()
+    assert_close(d, jacobi_diagonal(c["mats"], c["l2g"], c["ng"], c["dm"]), FP64_RTOL, "varp diag")
+    b = c["b"]
+    xs, _ = c["sysm"].solve(to_dev(b), rtol=1e-12)
+    xs = xs.cpu().numpy()
+    assert np.linalg.norm(b - A(xs)) / np.linalg.norm(b) <= 1.05e-12
+    xd = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b)
+    assert rel_err(xs, xd) < 1e-8
+    xr, _ = c["sysm"].solve(to_dev(b), rtol=1e-10, mode=m.SOLVE_F32_REFINED)
+    assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
+    # gather / assemble through the ragged map
+    xl = c["sysm"].gather(to_dev(x)).cpu().numpy()
+    np.testing.assert_array_equal(xl, np.concatenate(oracle.gather(x, c["l2g"])))
+    yl = np.random.default_rng(12).uniform(-1, 1, xl.size)
+    sizes = np.cumsum([0] + [len(g) for g in c["l2g"]])
+    ylist = [yl[sizes[k]:sizes[k + 1]] for k in range(len(c["l2g"]))]
+    got = c["sysm"].assemble(to_dev(yl)).cpu().numpy()
+    want = oracle.assemble_vector(ylist, c["l2g"], c["ng"])
+    want[c["dm"].astype(bool)] = 0.0        # Dirichlet rows (and the zero DOF) receive nothing
+    assert_close(got, want, FP64_RTOL, "varp assemble")
