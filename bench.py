@@ -313,6 +313,45 @@ def section_varp(nk, W, torch, reps=20):
     return out
 
 
+def section_varp_solve(nk, W, torch, shape=(12, 12, 12), orders=(2, 8)):
+    """A conforming variable-order solve: curved lattice with per-element
+    order drawn from {2..8}, C0 map by the minimum rule, manufactured-sine
+    weak right-hand side, FP64 CG and the FP32-refined solve to 1e-10."""
+    cfg = W.CONFIGS[3]
+    lat = W.lattice(shape)
+    Pe = W.varp_orders(W.seed(3, 4) + 1, lat.nelem, *orders)
+    perm, l2g, ng, dm = W.varp_lattice_l2g(shape, Pe)
+    ords = Pe[perm]
+    Ps = sorted(set(int(p) for p in ords))
+    jacs, Us, dUs = [], [], []
+    for P in Ps:
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[perm[ords == P]])
+        xq = nk.basis_tables(P, P + 2)[0]
+        jacs.append(torch.from_numpy(W.element_jacobians(xq, sub, cfg["warp"])).cuda())
+        U, dU = W.manufactured_ref_gradient(xq, sub)
+        Us.append(U.ravel())
+        dUs.append(dU.ravel())
+    space = nk.Space.create_varp(3, Ps, [p + 2 for p in Ps], jacs)
+    sysm = nk.System.create(space, ng, torch.from_numpy(np.concatenate(l2g)).cuda(),
+                            torch.from_numpy(dm).cuda(), lam0=1.0)
+    yl = nk.helmholtz_weak_rhs(space, torch.from_numpy(np.concatenate(Us)).cuda(),
+                               torch.from_numpy(np.concatenate(dUs)).cuda(), lam0=1.0)
+    b = sysm.assemble(yl)
+    out = {"shape": list(shape), "orders": Ps, "nelem": int(lat.nelem), "nglobal": int(ng),
+           "local_dof": int(sum((P + 1) ** 3 for P in ords))}
+    for mode, name in ((nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")):
+        sysm.solve(b, rtol=1e-10, mode=mode)         # graphs and tiles warmed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = sysm.solve(b, rtol=1e-10, mode=mode)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": round(ms, 2), "iters": info[0]["iters"],
+                     "outer_iters": info[0]["outer_iters"], "rel_resid": info[0]["rel_resid"]}
+        log(f"varp solve {name}: {ms:.1f} ms, {info[0]['iters']} it")
+    return out
+
+
 def section_many_solves(nk, W, torch):
     """256 independent P=5 Helmholtz solves on curved boxes of 64..4096 hexes
     (log-uniform sizes): one batched solve (one operator launch per CG
@@ -559,6 +598,9 @@ def main():
     if "batch" in secs:
         log("section batch (mixed order) ...")
         sections["batch_varp_20000"] = section_varp(nk, W, torch)
+        torch.cuda.empty_cache()
+        log("section batch (mixed-order solve) ...")
+        sections["varp_solve_12c"] = section_varp_solve(nk, W, torch)
         torch.cuda.empty_cache()
         log("section batch (256 solves) ...")
         sections["batch_256_solves"] = section_many_solves(nk, W, torch)
