@@ -352,6 +352,34 @@ def section_varp_solve(nk, W, torch, shape=(12, 12, 12), orders=(2, 8)):
     return out
 
 
+def section_filter(nk, W, torch, shape=(24, 24, 24), P=6):
+    """The modified forward transform of Eq. (3), u** - alpha^2 lap u** = u*
+    with du**/dn = 0, on the 24^3 curved lattice at P=6; filter width two
+    element sizes, alpha = 2h / (2 pi).  Right-hand side: assembled
+    IProductWRTBase of a seeded point field; FP64 CG and FP32-refined."""
+    Q = P + 2
+    lat = W.lattice(shape)
+    alpha = 2.0 * lat.h[0] / (2.0 * math.pi)
+    nq = Q ** 3
+    kap = torch.full((lat.nelem * nq,), alpha ** 2, dtype=torch.float64, device="cuda")
+    space, _ = make_space(nk, W, shape, P, W.WARP_AMPLITUDE, torch, kappa=kap)
+    l2g, ng, _ = W.lattice_l2g(shape, P)
+    sysm = nk.System.create(space, ng, torch.from_numpy(l2g).cuda(),
+                            torch.zeros(ng, dtype=torch.uint8, device="cuda"), lam0=1.0)
+    ustar = torch.from_numpy(W.uniform(W.seed(2, 1), lat.nelem * nq)).cuda()
+    out = {"alpha": alpha, "nglobal": int(ng)}
+    for mode, name in ((nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")):
+        nk.filtered_fwd_trans(space, sysm, ustar, rtol=1e-10, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = nk.filtered_fwd_trans(space, sysm, ustar, rtol=1e-10, mode=mode)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": round(ms, 2), "iters": info[0]["iters"], "rel_resid": info[0]["rel_resid"]}
+        log(f"filter {name}: {ms:.1f} ms, {info[0]['iters']} it")
+    return out
+
+
 def section_many_solves(nk, W, torch):
     """256 independent P=5 Helmholtz solves on curved boxes of 64..4096 hexes
     (log-uniform sizes): one batched solve (one operator launch per CG
@@ -595,6 +623,10 @@ def main():
     if "cg" in secs:
         log("section cg ...")
         sections["cg_24c"] = section_cg(nk, W, torch, [int(p) for p in args.cg_orders.split(",") if p])
+        torch.cuda.empty_cache()
+        log("section cg (filter equation) ...")
+        sections["filter_24c_P6"] = section_filter(nk, W, torch)
+        torch.cuda.empty_cache()
     if "batch" in secs:
         log("section batch (mixed order) ...")
         sections["batch_varp_20000"] = section_varp(nk, W, torch)

@@ -10,7 +10,7 @@ adjoint gradients behind torch.autograd.
 """
 from .nk import (  # noqa: F401
     F32, F64, SOLVE_F32_REFINED, SOLVE_F64, OP_BWD, OP_IPROD, OP_HELM, OP_HELM_ASM,
-    NkError, Space, System, autotune, basis_tables, bwd_trans, device_count, fwd_trans, helmholtz,
+    NkError, Space, System, autotune, basis_tables, bwd_trans, device_count, filtered_fwd_trans, fwd_trans, helmholtz,
     helmholtz_weak_rhs, iprod_wrt_base, iprod_wrt_deriv_base, lib, param_grad, phys_deriv,
     set_tile_config, tile_config, tile_count,
 )

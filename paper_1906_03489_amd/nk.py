@@ -268,6 +268,16 @@ def fwd_trans(space: Space, phys, coeffs=None, dtype=F64):
     return coeffs
 
 
+def filtered_fwd_trans(space: Space, system, phys, rtol: float = 1e-12, mode=SOLVE_F64):
+    """The modified forward transform of Eq. (3): global C0 coefficients of
+    u** with u** - alpha^2 lap u** = u*, du**/dn = 0, for point values u*
+    (phys, [E][Q^d]).  The space must carry kappa = alpha^2 and the system
+    lambda = 1 and no Dirichlet DOFs; the right-hand side is the assembled
+    IProductWRTBase of u*.  Returns (coefficients, [SolveInfo dicts])."""
+    b = system.assemble(iprod_wrt_base(space, phys))
+    return system.solve(b, rtol=rtol, mode=mode)
+
+
 def helmholtz(space: Space, x, y=None, lam=None, lam0: float = 1.0, dtype=F64):
     """y = (L + lambda M) x, elementwise (local), matrix-free."""
     import torch

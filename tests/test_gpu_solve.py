@@ -275,3 +275,49 @@ def test_mixed_order_assembled_operator_and_solves(shape, orders):
     want = oracle.assemble_vector(ylist, c["l2g"], c["ng"])
     want[c["dm"].astype(bool)] = 0.0        # Dirichlet rows (and the zero DOF) receive nothing
     assert_close(got, want, FP64_RTOL, "varp assemble")
+
+
+# ----------------------------------------- the Neumann filter equation (3)
+
+def test_filter_equation_neumann_solve():
+    """u** - alpha^2 lap u** = u*, du**/dn = 0 on curved hexes: the GPU's
+    modified forward transform (assembled IProductWRTBase of u*, CG on the
+    Helmholtz system with kappa = alpha^2, lambda = 1, no Dirichlet DOF)
+    against the oracle's sparse direct solve of the same problem; and, on an
+    affine lattice, the exact recovery of a polynomial with zero normal
+    derivative from its strong-form right-hand side."""
+    torch = torch_cuda()
+    m = nk()
+    P, shape, alpha = 5, (2, 2, 2), 0.15
+    Q = P + 2
+    Jg, Jo, lat = jacobians(shape, P, W.WARP_AMPLITUDE)
+    E, nq = lat.nelem, Q ** 3
+    kap = np.full((E, nq), alpha ** 2)
+    ops = oracle.ElementOps(3, P, Q, Jo, kappa=kap, lam=1.0)
+    l2g, ng, _ = W.lattice_l2g(shape, P)
+    none = np.zeros(ng, np.uint8)
+    space = m.Space.create(3, P, Q, to_dev(Jg), kappa=to_dev(kap))
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(none), lam0=1.0)
+    ustar = W.uniform(W.seed(2, 1) + 3, (E, nq))
+    x, _ = m.filtered_fwd_trans(space, sysm, to_dev(ustar.ravel()), rtol=1e-12)
+    x = x.cpu().numpy()
+    mats = oracle.helmholtz_matrices(ops)
+    b = oracle.assemble_vector(ops.iprod(ustar), l2g, ng)
+    A = MaskedOperator(mats, l2g, ng, none)
+    assert np.linalg.norm(b - A(x)) / np.linalg.norm(b) <= 1.05e-12
+    assert rel_err(x, direct_solve(mats, l2g, ng, none, b)) < 1e-9
+    # polynomial with zero normal derivative, affine lattice, P = 4
+    P, Q = 4, 6
+    Jg, _, lat = jacobians(shape, P, 0.0)
+    kap = np.full((E, Q ** 3), alpha ** 2)
+    space = m.Space.create(3, P, Q, to_dev(Jg), kappa=to_dev(kap))
+    l2g, ng, _ = W.lattice_l2g(shape, P)
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(np.zeros(ng, np.uint8)), lam0=1.0)
+    X = W.lattice_points(m.basis_tables(P, Q)[0], lat)
+    g = X ** 2 * (1 - X) ** 2
+    d2g = 2 - 12 * X + 12 * X ** 2
+    U = g.prod(axis=1)
+    lapU = d2g[:, 0] * g[:, 1] * g[:, 2] + g[:, 0] * d2g[:, 1] * g[:, 2] + g[:, 0] * g[:, 1] * d2g[:, 2]
+    x, _ = m.filtered_fwd_trans(space, sysm, to_dev((U - alpha ** 2 * lapU).ravel()), rtol=1e-13)
+    u = m.bwd_trans(space, sysm.gather(x)).cpu().numpy()
+    assert np.abs(u - U.ravel()).max() < 1e-12

@@ -625,3 +625,31 @@ def test_varp_projection_reproduces_a_conforming_polynomial():
     x = direct_solve(mats, l2g, ng, dm, b)
     for k_space, (ops, k, fk) in fl.items():
         np.testing.assert_allclose(ops.bwd(x[l2g[k_space]][None])[0], fk, atol=1e-13)
+
+
+# ----------------------------------------- the Neumann filter equation (3)
+# u** - alpha^2 lap u** = u*, du**/dn = 0 (section 3.4, Eq. (3)): the same
+# Helmholtz operator with kappa = alpha^2, lambda = 1 and no Dirichlet DOFs.
+
+def test_neumann_filter_equation_exact_for_a_polynomial_solution():
+    """U = g(X) g(Y) g(Z), g = X^2 (1-X)^2, has zero normal derivative on the
+    unit cube and degree 4 per direction.  With the right-hand side taken from
+    the strong form, f = U - alpha^2 lap U (integrated exactly at Q = 6), the
+    Neumann Galerkin solve at P = 4 on an affine lattice returns U exactly --
+    only if the operator is mass + alpha^2 times the stiffness and no boundary
+    DOF is constrained (integration by parts with dU/dn = 0)."""
+    shape, P, alpha = (2, 2, 2), 4, 0.3
+    Q = P + 2
+    lat = W.lattice(shape)
+    J = W.element_jacobians(oracle.gll(Q)[0], lat, 0.0)
+    kap = np.full((lat.nelem, Q ** 3), alpha ** 2)
+    ops = oracle.ElementOps(3, P, Q, J, kappa=kap, lam=1.0)
+    X = W.lattice_points(ops.x, lat)                       # (E, 3, nq)
+    g = X ** 2 * (1 - X) ** 2
+    d2g = 2 - 12 * X + 12 * X ** 2
+    U = g.prod(axis=1)
+    lapU = d2g[:, 0] * g[:, 1] * g[:, 2] + g[:, 0] * d2g[:, 1] * g[:, 2] + g[:, 0] * g[:, 1] * d2g[:, 2]
+    l2g, ng, _ = W.lattice_l2g(shape, P)
+    b = oracle.assemble_vector(ops.iprod(U - alpha ** 2 * lapU), l2g, ng)
+    x = direct_solve(oracle.helmholtz_matrices(ops), l2g, ng, np.zeros(ng, np.uint8), b)
+    np.testing.assert_allclose(ops.bwd(oracle.gather(x, l2g)), U, atol=1e-14)
