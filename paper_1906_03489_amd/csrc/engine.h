@@ -413,7 +413,7 @@ constexpr int slot_threads() {
   return Q * Q <= 1 ? 1 : Q * Q <= 4 ? 4 : Q * Q <= 16 ? 16 : Q * Q <= 64 ? 64 : Q * Q;
 }
 
-template <typename T, int N, int Q, int EPB, int OP>
+template <typename T, int N, int Q, int EPB, int OP, bool LEAN = false>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
     k_op3(const Tab<T, N, Q> tb, const DevArgs<T> a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q, S = Q * Q * N;
@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
       for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   } else if constexpr (OP == OP_HELM || OP == OP_HELM_ASM) {
-    helm3_body<T, N, Q, NT, ASM>(tb, sm, red, slot, t, live, e, a);
+    helm3_body<T, N, Q, NT, ASM, LEAN>(tb, sm, red, slot, t, live, e, a);
   } else if constexpr (OP == OP_RHS) {
     const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
     T sa[N], sb[N], sc[N];

@@ -37,4 +37,15 @@ constexpr int kVarpEPB[11] = {0, 16, 16, 4, 4, 4, 4, 3, 2, 2, 1};
 
 constexpr bool op_has_tiles(int op) { return op <= 3; }
 
+// The 3-D Helmholtz operators (local and assembled) have each elements-per-
+// block candidate twice: with the factors of the next point prefetched into a
+// second register set, and "lean" (one set: fewer registers, more waves per
+// SIMD).  Which wins depends on the order and precision, so both are timed.
+constexpr int epb3_count(int P) {
+  int c = 0;
+  for (int k = 0; k < kMaxTiles; ++k) c += kTileEPB3[P][k] > 0 ? 1 : 0;
+  return c;
+}
+constexpr bool op_has_lean(int op) { return op == 2 || op == 3; }
+
 }  // namespace nk
