@@ -1,0 +1,172 @@
+"""Collapsed-coordinate triangles (oracle; test infrastructure only).
+
+Section 2.1 of arXiv 1906.03489: triangles (and the other unstructured
+shapes) are quadrilaterals with one coordinate direction collapsed, reached
+through the Duffy map omega_T, and they carry expansions that factor in the
+collapsed coordinates, which keeps sum-factorisation available (section 3.3).
+The paper defers the basis and quadrature to the textbook it cites, so the
+following readings are taken (each is pinned by tests/test_oracle.py):
+
+* reference triangle T = {xi_1, xi_2 >= -1, xi_1 + xi_2 <= 0}; collapsed
+  coordinates eta_1 = 2 (1 + xi_1) / (1 - xi_2) - 1, eta_2 = xi_2, so
+  xi_1 = (1 + eta_1)(1 - eta_2)/2 - 1;
+* modes, grouped by the eta_1 index p (the order used for the coefficients):
+    p = 0:      q = 0: vertex A = a_0(eta_1) (1-eta_2)/2;  1 <= q < P: edge
+                a_0(eta_1) b_q(eta_2);  q = P: vertex C = (1+eta_2)/2 (not
+                multiplied by a_0: the collapsed vertex);
+    0 < p < P:  q = 0: a_p(eta_1) ((1-eta_2)/2)^(p+1) (bottom edge);
+                1 <= q <= P-1-p: a_p(eta_1) ((1-eta_2)/2)^(p+1) (1+eta_2)/2
+                P^{2p+1,1}_{q-1}(eta_2) (interior);
+    p = P:      q = 0: vertex B = a_P(eta_1) (1-eta_2)/2;  1 <= q < P: edge
+                a_P(eta_1) b_q(eta_2),
+  with a_p the 1-D modified basis of section 2.1 and b_q(z) = (1-z)/2 (1+z)/2
+  P^{1,1}_{q-1}(z) its bubbles; (P+1)(P+2)/2 modes spanning the polynomials
+  of total degree <= P;
+* quadrature: Q Gauss-Lobatto-Legendre points in eta_1, Q-1 Gauss-Radau
+  points of the weight (1 - eta_2) in eta_2 (eta_2 = -1 included, the
+  collapsed vertex eta_2 = 1 excluded); dxi = (1 - eta_2)/2 deta, the factor
+  (1 - eta_2) being the Radau weight.  Point q = i + Q j (eta_1 fastest).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import roots_jacobi
+
+from .basis import gll, jacobi_p, modified_basis
+
+
+def gauss_radau_jacobi(n: int, alpha: float, beta: float):
+    """n Gauss-Radau points (x = -1 included) and weights of the weight
+    (1-x)^alpha (1+x)^beta on [-1, 1]: the interior points are the roots of
+    P^{alpha, beta+1}_{n-1}; the weights are fixed by exactness on the
+    monomials 1, x, ..., x^(n-1), whose moments come from a Gauss-Jacobi rule
+    of the same weight (exact far beyond that degree)."""
+    if n < 1:
+        raise ValueError("n >= 1")
+    inner = np.sort(roots_jacobi(n - 1, alpha, beta + 1)[0]) if n > 1 else np.zeros(0)
+    x = np.concatenate([[-1.0], inner])
+    xg, wg = roots_jacobi(n + 8, alpha, beta)
+    k = np.arange(n)
+    moments = (wg[None, :] * xg[None, :] ** k[:, None]).sum(axis=1)
+    V = x[None, :] ** k[:, None]
+    w = np.linalg.solve(V, moments)
+    return x, w
+
+
+def tri_modes(P: int):
+    """List of (p, q) in coefficient order (see the module docstring)."""
+    modes = [(0, q) for q in range(P + 1)]
+    for p in range(1, P):
+        modes += [(p, q) for q in range(P - p)]
+    modes += [(P, q) for q in range(P)]
+    return modes
+
+
+def _b_funcs(P: int, p: int, q: int, z):
+    """(value, derivative) of the eta_2 factor of mode (p, q)."""
+    z = np.asarray(z, np.float64)
+    if p == 0 or p == P:
+        if q == 0:
+            return (1 - z) / 2, np.full_like(z, -0.5)
+        if p == 0 and q == P:
+            return (1 + z) / 2, np.full_like(z, 0.5)
+        B, D = modified_basis(P, z)       # bubble q of the 1-D basis (q < P)
+        return B[:, q], D[:, q]
+    a = (1 - z) / 2
+    if q == 0:
+        return a ** (p + 1), -(p + 1) / 2 * a ** p
+    J = jacobi_p(q - 1, 2 * p + 1, 1, z)
+    dJ = ((q - 1 + 2 * p + 3) / 2 * jacobi_p(q - 2, 2 * p + 2, 2, z)) if q >= 2 else np.zeros_like(z)
+    f = a ** (p + 1) * (1 + z) / 2
+    df = -(p + 1) / 2 * a ** p * (1 + z) / 2 + a ** (p + 1) / 2
+    return f * J, df * J + f * dJ
+
+
+def tri_basis(P: int, e1, e2):
+    """Basis values and collapsed-coordinate derivatives at points (e1, e2):
+    (Phi, dPhi/deta_1, dPhi/deta_2), each (npts, nmodes)."""
+    e1 = np.asarray(e1, np.float64)
+    e2 = np.asarray(e2, np.float64)
+    A, DA = modified_basis(P, e1)
+    modes = tri_modes(P)
+    Phi = np.zeros((e1.size, len(modes)))
+    D1 = np.zeros_like(Phi)
+    D2 = np.zeros_like(Phi)
+    for m, (p, q) in enumerate(modes):
+        b, db = _b_funcs(P, p, q, e2)
+        if p == 0 and q == P:           # the collapsed vertex C: no eta_1 factor
+            Phi[:, m], D1[:, m], D2[:, m] = b, 0.0, db
+        else:
+            Phi[:, m] = A[:, p] * b
+            D1[:, m] = DA[:, p] * b
+            D2[:, m] = A[:, p] * db
+    return Phi, D1, D2
+
+
+def tri_points(Q: int):
+    """Collapsed quadrature: eta_1 (GLL, Q), eta_2 (Radau, Q-1) and the
+    weights of dxi at every point q = i + Q j."""
+    x1, w1 = gll(Q)
+    x2, w2 = gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    E1 = np.tile(x1, Q - 1)
+    E2 = np.repeat(x2, Q)
+    W = np.outer(w2 / 2, w1).ravel()          # (1 - eta_2)/2 deta = (w2 / 2) w1
+    return E1, E2, W
+
+
+def xi_of_eta(e1, e2):
+    return (1 + e1) * (1 - e2) / 2 - 1, e2
+
+
+class TriOps:
+    """Dense elemental operators of straight- or curved-sided triangles of
+    order P with the collapsed quadrature of Q points.  J[e, c, a, q] =
+    d x_c / d xi_a at the quadrature points."""
+
+    def __init__(self, P, Q, J, kappa=None, lam=1.0):
+        self.P, self.Q = int(P), int(Q)
+        self.e1, self.e2, self.W = tri_points(self.Q)
+        self.Bt, D1, D2 = tri_basis(self.P, self.e1, self.e2)
+        # xi-derivatives by the chain rule through the Duffy map
+        d1 = 2.0 / (1 - self.e2)
+        d2 = (1 + self.e1) / (1 - self.e2)
+        self.Dt = [d1[:, None] * D1, d2[:, None] * D1 + D2]
+        Jm = np.moveaxis(np.asarray(J, np.float64), -1, 1)          # (E, nq, c, a)
+        self.detJ = np.linalg.det(Jm)
+        Ji = np.linalg.inv(Jm)
+        self.G = np.einsum("eqac,eqbc->eqab", Ji, Ji)
+        E = self.detJ.shape[0]
+        self.nelem = E
+        nq = self.W.size
+        self.kappa = np.ones((E, nq)) if kappa is None else np.asarray(kappa, np.float64).reshape(E, nq)
+        lam = np.asarray(lam, np.float64)
+        self.lam = np.broadcast_to(lam, (E,)).copy() if lam.ndim == 0 else lam.reshape(E).copy()
+        self.wJ = self.W[None, :] * self.detJ
+
+    def mass_matrix(self, e):
+        return self.Bt.T @ (self.wJ[e][:, None] * self.Bt)
+
+    def laplacian_matrix(self, e):
+        c = self.wJ[e] * self.kappa[e]
+        L = np.zeros((self.Bt.shape[1],) * 2)
+        for a in range(2):
+            for b in range(2):
+                L += self.Dt[a].T @ ((c * self.G[e, :, a, b])[:, None] * self.Dt[b])
+        return L
+
+    def helmholtz_matrix(self, e):
+        return self.laplacian_matrix(e) + self.lam[e] * self.mass_matrix(e)
+
+    def bwd(self, coeffs):
+        return np.asarray(coeffs, np.float64) @ self.Bt.T
+
+    def iprod(self, f):
+        return (self.wJ * np.asarray(f, np.float64)) @ self.Bt
+
+    def helmholtz(self, x):
+        x = np.asarray(x, np.float64)
+        return np.stack([self.helmholtz_matrix(e) @ x[e] for e in range(self.nelem)])
+
+    def fwd(self, f):
+        rhs = self.iprod(f)
+        return np.stack([np.linalg.solve(self.mass_matrix(e), rhs[e]) for e in range(self.nelem)])

@@ -653,3 +653,120 @@ def test_neumann_filter_equation_exact_for_a_polynomial_solution():
     b = oracle.assemble_vector(ops.iprod(U - alpha ** 2 * lapU), l2g, ng)
     x = direct_solve(oracle.helmholtz_matrices(ops), l2g, ng, np.zeros(ng, np.uint8), b)
     np.testing.assert_allclose(ops.bwd(oracle.gather(x, l2g)), U, atol=1e-14)
+
+
+# ------------------------------------- collapsed-coordinate triangles (2.1)
+from math import comb, factorial
+
+from oracle import collapsed as C
+
+
+def _tri_integral(a, b):
+    """Closed form of the integral of xi_1^a xi_2^b over the reference
+    triangle (shifted to u, v >= 0, u + v <= 2: a Dirichlet integral)."""
+    s = 0.0
+    for i in range(a + 1):
+        for j in range(b + 1):
+            s += (comb(a, i) * comb(b, j) * (-1) ** (a - i + b - j)
+                  * 2.0 ** (i + j + 2) * factorial(i) * factorial(j) / factorial(i + j + 2))
+    return s
+
+
+@pytest.mark.parametrize("n", [2, 4, 7])
+def test_gauss_radau_jacobi_exactness(n):
+    x, w = C.gauss_radau_jacobi(n, 1.0, 0.0)
+    assert x[0] == -1.0 and np.all(np.diff(x) > 0) and x[-1] < 1.0
+    for k in range(2 * n):
+        # int_{-1}^{1} x^k (1-x) dx = int x^k - int x^(k+1)
+        ik = (2.0 / (k + 1)) if k % 2 == 0 else 0.0
+        ik1 = (2.0 / (k + 2)) if (k + 1) % 2 == 0 else 0.0
+        got = w @ x ** k
+        if k <= 2 * n - 2:
+            assert abs(got - (ik - ik1)) < 1e-13, (n, k)
+        else:
+            assert abs(got - (ik - ik1)) > 1e-8, (n, k)
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_triangle_quadrature_integrates_degree_2P(P):
+    Q = P + 2
+    e1, e2, W = C.tri_points(Q)
+    x1, x2 = C.xi_of_eta(e1, e2)
+    assert abs(W.sum() - 2.0) < 1e-14
+    for a in range(2 * P + 1):
+        for b in range(2 * P + 1 - a):
+            # the closed form sums alternating binomial terms: allow 1e-12
+            assert abs(W @ (x1 ** a * x2 ** b) - _tri_integral(a, b)) < 1e-12, (a, b)
+
+
+@pytest.mark.parametrize("P", [1, 3, 5, 8])
+def test_triangle_basis_spans_total_degree_P(P):
+    """Every mode is a polynomial of total degree <= P in xi, and the
+    (P+1)(P+2)/2 modes are independent: they span exactly that space."""
+    rng = np.random.default_rng(P)
+    e1, e2 = rng.uniform(-1, 1, 200), rng.uniform(-1, 0.95, 200)
+    x1, x2 = C.xi_of_eta(e1, e2)
+    Phi, _, _ = C.tri_basis(P, e1, e2)
+    nm = (P + 1) * (P + 2) // 2
+    assert Phi.shape[1] == nm
+    Mon = np.stack([x1 ** a * x2 ** b for a in range(P + 1) for b in range(P + 1 - a)], axis=1)
+    coef, *_ = np.linalg.lstsq(Mon, Phi, rcond=None)
+    assert np.abs(Mon @ coef - Phi).max() < 1e-11
+    assert np.linalg.matrix_rank(Phi) == nm
+
+
+@pytest.mark.parametrize("P", [2, 5])
+def test_triangle_vertex_edge_interior_structure(P):
+    """A + B + C = 1; interior modes vanish on all three edges; each edge
+    carries only its two vertices and its own edge modes."""
+    modes = C.tri_modes(P)
+    iA, iC, iB = modes.index((0, 0)), modes.index((0, P)), modes.index((P, 0))
+    t = np.linspace(-1, 1, 9)
+    Phi, _, _ = C.tri_basis(P, t, np.full_like(t, 0.3))
+    np.testing.assert_allclose(Phi[:, iA] + Phi[:, iB] + Phi[:, iC], 1.0, atol=1e-14)
+    interior = [m for m, (p, q) in enumerate(modes) if 0 < p < P and q >= 1]
+    bottom = {iA, iB} | {m for m, (p, q) in enumerate(modes) if 0 < p < P and q == 0}
+    left = {iA, iC} | {m for m, (p, q) in enumerate(modes) if p == 0 and 0 < q < P}
+    right = {iB, iC} | {m for m, (p, q) in enumerate(modes) if p == P and 0 < q < P}
+    s = np.linspace(-0.9, 0.9, 7)
+    for edge, (e1, e2) in (("bottom", (s, -np.ones_like(s))), ("left", (-np.ones_like(s), s)),
+                           ("right", (np.ones_like(s), s))):
+        Phi, _, _ = C.tri_basis(P, e1, e2)
+        keep = {"bottom": bottom, "left": left, "right": right}[edge]
+        others = [m for m in range(len(modes)) if m not in keep]
+        assert np.abs(Phi[:, others]).max() < 1e-14, edge
+        if interior:
+            assert np.abs(Phi[:, interior]).max() < 1e-14
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_triangle_mass_projection_and_laplacian(P):
+    """On a sheared affine triangle: M SPD, 1^T M 1 = area, FwdTrans o BwdTrans
+    = I, total-degree-P polynomials reproduced, L 1 = 0, and the stiffness
+    form of the physical polynomial u = x1^2 - x1 x2 + 2 x2 equals the
+    integral of |grad u|^2 (gradient (2 x1 - x2, -x1 + 2))."""
+    Q = P + 2
+    A = np.array([[0.8, 0.35], [-0.1, 1.2]])
+    nq = Q * (Q - 1)
+    J = np.broadcast_to(A[None, :, :, None], (1, 2, 2, nq)).copy()
+    ops = C.TriOps(P, Q, J, lam=0.0)
+    M = ops.mass_matrix(0)
+    np.linalg.cholesky(M)
+    modes = C.tri_modes(P)
+    one = np.zeros(len(modes))
+    for v in ((0, 0), (0, P), (P, 0)):
+        one[modes.index(v)] = 1.0
+    area = 2.0 * abs(np.linalg.det(A))
+    assert abs(one @ M @ one - area) < 1e-13
+    rng = np.random.default_rng(9)
+    c = rng.uniform(-1, 1, (1, len(modes)))
+    np.testing.assert_allclose(ops.fwd(ops.bwd(c)), c, atol=1e-10)
+    np.testing.assert_allclose(ops.laplacian_matrix(0) @ one, 0.0, atol=1e-12)
+    x1r, x2r = C.xi_of_eta(ops.e1, ops.e2)
+    X = A @ np.stack([x1r, x2r])
+    u = X[0] ** 2 - X[0] * X[1] + 2 * X[1]
+    cu = ops.fwd(u[None])[0]
+    np.testing.assert_allclose(ops.bwd(cu[None])[0], u, atol=1e-12)
+    grad2 = (2 * X[0] - X[1]) ** 2 + (-X[0] + 2) ** 2
+    exact = ops.wJ[0] @ grad2          # degree 2 <= 2P: the rule is exact
+    assert abs(cu @ ops.laplacian_matrix(0) @ cu - exact) < 1e-12 * exact
