@@ -134,6 +134,25 @@ nk_status nk_space_destroy(nk_space s);
 nk_status nk_space_set_strategy(nk_space s, nk_dtype t, int strategy);
 int nk_space_get_strategy(nk_space s, nk_dtype t);   /* -1 on bad arguments */
 
+/* Collapsed-coordinate triangles (section 2.1: a quadrilateral with one
+ * direction collapsed by the Duffy map; the expansion factors in the collapsed
+ * coordinates eta_1 = 2(1+xi_1)/(1-xi_2) - 1, eta_2 = xi_2 on the reference
+ * triangle xi_1, xi_2 >= -1, xi_1 + xi_2 <= 0).  Quadrature: Q GLL points in
+ * eta_1 and Q-1 Gauss-Radau points of the weight (1 - eta_2) in eta_2 (-1
+ * included); point q = i + Q j.  nk_tri_points returns them (host arrays of
+ * Q, Q, Q-1, Q-1 doubles; the eta_2 weights include the factor (1 - eta_2)).
+ * Modes ((P+1)(P+2)/2 per element) are grouped by the eta_1 index p: p = 0
+ * with q = 0..P (q = P the collapsed vertex (1+eta_2)/2), 0 < p < P with
+ * q = 0..P-1-p, p = P with q = 0..P-1.
+ * nk_space_create_tri: nelem triangles of order P (1..10, Q = P + 2); jac:
+ * device [E][2][2][Q(Q-1)] FP64, jac[e][c][a][q] = d x_c / d xi_a at the
+ * points; kappa: device [E][Q(Q-1)] or NULL.  Such a space supports
+ * nk_bwd_trans, nk_iprod_wrt_base and nk_helmholtz (coefficients [E][nmodes],
+ * points [E][Q(Q-1)]); other calls return NK_EUNSUPPORTED. */
+nk_status nk_tri_points(int Q, double* eta1, double* w1, double* eta2, double* w2);
+nk_status nk_space_create_tri(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                              const double* kappa, void* stream);
+
 /* Sizes of a space: total elements, coefficients (sum n^d) and points
  * (sum Q^d).  Any output may be NULL. */
 nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints);

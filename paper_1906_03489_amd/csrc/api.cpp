@@ -383,6 +383,69 @@ nk_status nk_space_create(nk_space* out, int dim, int64_t nelem, int P, int Q, c
   return nk_space_create_varp(out, dim, 1, &P, &Q, &nelem, j, kappa ? k : nullptr, stream);
 }
 
+nk_status nk_tri_points(int Q, double* eta1, double* w1, double* eta2, double* w2) {
+  if (Q < 3 || Q > kMaxP + 2 || !eta1 || !w1 || !eta2 || !w2)
+    return fail(NK_EINVAL, "need 3 <= Q <= 12 and non-NULL outputs");
+  tri_points(Q, eta1, w1, eta2, w2);
+  return NK_OK;
+}
+
+nk_status nk_space_create_tri(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                              const double* kappa, void* stream) {
+  if (!out) return fail(NK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nelem < 0) return fail(NK_EINVAL, "nelem must be >= 0");
+  if (P < 1 || P > kMaxP || Q != P + 2)
+    return fail(NK_EUNSUPPORTED, "compiled triangle orders: 1 <= P <= 10 with Q = P + 2");
+  const int64_t NP = (int64_t)Q * (Q - 1), NM = (int64_t)(P + 1) * (P + 2) / 2;
+  if (nelem > 0 && !jac) return fail(NK_EINVAL, "jac is NULL");
+  NK_CHECK(check_buf(jac, (size_t)nelem * 4 * NP * 8, "jac"));
+  if (kappa) NK_CHECK(check_buf(kappa, (size_t)nelem * NP * 8, "kappa"));
+  NK_CHECK(check_device());
+  hipStream_t st = (hipStream_t)stream;
+  nk_space s = new nk_space_s();
+  s->dim = 2;
+  s->shape = 1;
+  (void)hipGetDevice(&s->device);
+  Group G;
+  G.P = P;
+  G.Q = Q;
+  G.n = P + 1;
+  G.nelem = nelem;
+  s->groups.push_back(G);
+  s->nelem = nelem;
+  s->ncoeff = nelem * NM;
+  s->npoint = nelem * NP;
+  s->nfac = nelem * 4 * NP;
+  auto cleanup = [&](nk_status stt) {
+    space_free(s);
+    return stt;
+  };
+  hipError_t e;
+  if ((e = dmalloc(&s->fac64, s->nfac)) || (e = dmalloc(&s->fac32, s->nfac)))
+    return cleanup(hip_fail(e, "hipMalloc"));
+  std::vector<double> pts(2 * Q + 2 * (Q - 1));
+  tri_points(Q, pts.data(), pts.data() + Q, pts.data() + 2 * Q, pts.data() + 2 * Q + (Q - 1));
+  int* d_bad = nullptr;
+  double* d_pts = nullptr;
+  if ((e = dmalloc(&d_bad, 1)) || (e = dmalloc(&d_pts, pts.size()))) {
+    dfree(d_bad);
+    return cleanup(hip_fail(e, "hipMalloc"));
+  }
+  int bad = 0;
+  if (!(e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) &&
+      !(e = hipMemcpyAsync(d_pts, pts.data(), pts.size() * 8, hipMemcpyHostToDevice, st)) &&
+      !(e = launch_geom_tri(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)) &&
+      !(e = hipStreamSynchronize(st)))
+    e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
+  dfree(d_bad);
+  dfree(d_pts);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "triangle space setup"));
+  if (bad) return cleanup(fail(NK_EINVAL, "non-positive Jacobian determinant or kappa"));
+  *out = s;
+  return NK_OK;
+}
+
 nk_status nk_space_destroy(nk_space s) {
   if (!s) return fail(NK_EINVAL, "space is NULL");
   (void)hipDeviceSynchronize();
@@ -412,6 +475,8 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
   if (lam) NK_CHECK(check_buf(lam, s->nelem * 8, "lambda"));
   if (op == OP_RHS) NK_CHECK(check_buf(in2, s->npoint * d * 8, "du"));
   if (in == out && in != nullptr) return fail(NK_EINVAL, "input and output must not alias");
+  if (s->shape == 1 && op != OP_BWD && op != OP_IPROD && op != OP_HELM)
+    return fail(NK_EUNSUPPORTED, "triangle spaces provide BwdTrans, IProductWRTBase and Helmholtz");
   hipStream_t st = (hipStream_t)stream;
   const char* fac = t == NK_F64 ? (const char*)s->fac64 : (const char*)s->fac32;
   auto group_args = [&](const Group& G) {
@@ -431,6 +496,11 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
     a.stream = st;
     return a;
   };
+  if (s->shape == 1) {
+    const hipError_t e = launch_tri(t, group_args(s->groups[0]));
+    if (e != hipSuccess) return hip_fail(e, "triangle operator launch");
+    return NK_OK;
+  }
   int strategy = VARP_SEQUENTIAL;
   if (s->groups.size() > 1)
     strategy = (op == OP_HELM) ? s->varp_strategy[t] : VARP_CONCURRENT;
@@ -531,6 +601,7 @@ static nk_status deriv_op(nk_space s, int which, nk_dtype t, const void* in, voi
   if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
   const size_t sz = dsize(t);
   const int d = s->dim;
+  if (s->shape != 0) return fail(NK_EUNSUPPORTED, "derivative operators are built for quadrilaterals and hexahedra");
   // element-major blocks: points [Q^d], vector fields [d][Q^d], coefficients [n^d]
   const int64_t vin = which == DERIV_IPROD ? d : 1, vout = which == DERIV_PHYS ? d : 1;
   const bool coeff_out = which != DERIV_PHYS;
@@ -568,6 +639,7 @@ nk_status nk_helmholtz_param_grad(nk_space s, const double* z_loc, const double*
                                   double* dkappa, double* dlambda, void* stream) {
   if (!s) return fail(NK_EINVAL, "space is NULL");
   if (s->groups.size() != 1) return fail(NK_EINVAL, "gradient needs a single-order space");
+  if (s->shape != 0) return fail(NK_EUNSUPPORTED, "gradient kernel is built for hexahedra");
   NK_CHECK(check_buf(z_loc, s->ncoeff * 8, "z_loc"));
   NK_CHECK(check_buf(u_loc, s->ncoeff * 8, "u_loc"));
   if (dkappa) NK_CHECK(check_buf(dkappa, s->npoint * 8, "dkappa"));
@@ -672,6 +744,7 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   *out = nullptr;
   if (!s) return fail(NK_EINVAL, "space is NULL");
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
+  if (s->shape != 0) return fail(NK_EUNSUPPORTED, "assembled systems are built for quadrilaterals and hexahedra");
   if (s->groups.size() != 1 && nsys != 1)
     return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
@@ -1317,6 +1390,7 @@ static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st) {
 
 nk_status nk_autotune(nk_space s, int op_mask, void* stream) {
   if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (s->shape != 0) return NK_OK;   // triangles have a single launch shape per order
   NK_CHECK(check_device());
   std::lock_guard<std::mutex> lk(g_tune_mu);
   hipStream_t st = (hipStream_t)stream;

@@ -11,6 +11,7 @@
 // derivative in closed form, phi_p'(x) = -(p/2) L_p(x).  Both need only the
 // Legendre three-term recurrence.
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include "nk_internal.h"
@@ -153,6 +154,112 @@ void symmetric_eigen(int n, const double* A, double* V, double* lam) {
       }
   }
   for (int i = 0; i < n; ++i) lam[i] = a[i * n + i];
+}
+
+// P_k^{(a,b)}(x) by the textbook three-term recurrence in k.
+static double jacobi_poly(int k, double a, double b, double x) {
+  if (k < 0) return 0.0;
+  double p0 = 1.0;
+  if (k == 0) return p0;
+  double p1 = 0.5 * ((a + b + 2.0) * x + (a - b));
+  for (int n = 1; n < k; ++n) {
+    const double c = 2.0 * n + a + b;
+    const double a1 = 2.0 * (n + 1) * (n + a + b + 1) * c;
+    const double a2 = (c + 1) * (a * a - b * b);
+    const double a3 = c * (c + 1) * (c + 2);
+    const double a4 = 2.0 * (n + a) * (n + b) * (c + 2);
+    const double p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Collapsed triangle quadrature: Q Gauss-Lobatto-Legendre points in eta_1
+// and Q-1 Gauss-Radau points of the weight (1 - eta_2) in eta_2 (-1
+// included).  The Radau interior points are the roots of P^{1,1}_{Q-2}, i.e.
+// the interior GLL points of order Q; the weights are fixed by exactness on
+// 1, x, ..., x^{Q-2} (moments of (1-x) in closed form), solved by Gaussian
+// elimination with partial pivoting.
+void tri_points(int Q, double* e1, double* w1, double* e2, double* w2) {
+  gll_points(Q, e1, w1);
+  const int n = Q - 1;
+  e2[0] = -1.0;
+  for (int k = 1; k < n; ++k) e2[k] = e1[k];
+  std::vector<double> A(n * n), rhs(n);
+  for (int k = 0; k < n; ++k) {
+    const double ik = (k % 2 == 0) ? 2.0 / (k + 1) : 0.0;        // int x^k
+    const double ik1 = ((k + 1) % 2 == 0) ? 2.0 / (k + 2) : 0.0; // int x^(k+1)
+    rhs[k] = ik - ik1;
+    for (int j = 0; j < n; ++j) A[k * n + j] = std::pow(e2[j], k);
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(A[c * n + j], A[piv * n + j]);
+      std::swap(rhs[c], rhs[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int j = c; j < n; ++j) A[r * n + j] -= f * A[c * n + j];
+      rhs[r] -= f * rhs[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double s = rhs[c];
+    for (int j = c + 1; j < n; ++j) s -= A[c * n + j] * w2[j];
+    w2[c] = s / A[c * n + c];
+  }
+}
+
+// eta_2 factor of every triangle mode at the points z (values and
+// derivatives, [nz][nmodes]); modes grouped by the eta_1 index p: p = 0 with
+// q = 0..P (q = P the collapsed vertex (1+z)/2), 0 < p < P with
+// q = 0..P-1-p, p = P with q = 0..P-1.
+void tri_btable(int P, int nz, const double* z, double* Bt, double* dBt) {
+  const int nm = (P + 1) * (P + 2) / 2;
+  std::vector<double> L(P + 2), dL(P + 2);
+  for (int j = 0; j < nz; ++j) {
+    const double x = z[j];
+    legendre_all(P, x, L.data(), dL.data());
+    int m = 0;
+    for (int p = 0; p <= P; ++p) {
+      const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
+      for (int q = 0; q < nq; ++q, ++m) {
+        double v, d;
+        if (p == 0 || p == P) {
+          if (q == 0) {
+            v = 0.5 * (1.0 - x);
+            d = -0.5;
+          } else if (p == 0 && q == P) {
+            v = 0.5 * (1.0 + x);
+            d = 0.5;
+          } else {  // 1-D bubble q
+            v = (1.0 - x * x) * dL[q] / (2.0 * (q + 1.0));
+            d = -0.5 * q * L[q];
+          }
+        } else {
+          const double a = 0.5 * (1.0 - x);
+          const double ap = std::pow(a, p), ap1 = ap * a;
+          if (q == 0) {
+            v = ap1;
+            d = -0.5 * (p + 1) * ap;
+          } else {
+            const double f = ap1 * 0.5 * (1.0 + x);
+            const double df = -0.5 * (p + 1) * ap * 0.5 * (1.0 + x) + 0.5 * ap1;
+            const double J = jacobi_poly(q - 1, 2.0 * p + 1, 1.0, x);
+            const double dJ = q >= 2 ? 0.5 * (q + 2.0 * p + 2) * jacobi_poly(q - 2, 2.0 * p + 2, 2.0, x) : 0.0;
+            v = f * J;
+            d = df * J + f * dJ;
+          }
+        }
+        Bt[j * nm + m] = v;
+        dBt[j * nm + m] = d;
+      }
+    }
+  }
 }
 
 }  // namespace nk

@@ -24,6 +24,8 @@ void gll_points(int Q, double* x, double* w);
 void modified_basis(int P, int Q, const double* x, double* B, double* DB);
 void collocation_derivative(int Q, const double* x, double* Dc);
 void symmetric_eigen(int n, const double* A, double* V, double* lam);
+void tri_points(int Q, double* e1, double* w1, double* e2, double* w2);
+void tri_btable(int P, int nz, const double* z, double* Bt, double* dBt);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -141,6 +143,11 @@ struct DerivArgs {
 };
 hipError_t launch_deriv(nk_dtype t, int which, int dim, int P, const DerivArgs& a);
 
+// Collapsed triangles (tri.hip): BwdTrans, IProductWRTBase, Helmholtz.
+hipError_t launch_tri(nk_dtype t, const OpArgs& a);
+hipError_t launch_geom_tri(int Q, int64_t nelem, const double* jac, const double* kappa,
+                           const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
+
 // Geometry: per-point factors from Jacobians.
 hipError_t launch_geom(int dim, int Q, int64_t nelem, const double* jac, const double* kappa,
                        const double* wq, double* fac64, float* fac32, double* dfac64,
@@ -161,6 +168,7 @@ struct Group {
 
 struct nk_space_s {
   int dim = 3;
+  int shape = 0;             // 0: quadrilaterals / hexahedra, 1: collapsed triangles
   int device = 0;
   std::vector<nk::Group> groups;
   int64_t nelem = 0, ncoeff = 0, npoint = 0, nfac = 0;

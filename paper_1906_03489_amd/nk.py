@@ -33,6 +33,7 @@ EXPORTS = [
     "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
+    "nk_tri_points", "nk_space_create_tri",
 ]
 
 
@@ -96,6 +97,8 @@ def lib():
         "nk_phys_deriv": (i32, [vp, i32, vp, vp, vp]),
         "nk_iprod_wrt_deriv_base": (i32, [vp, i32, vp, vp, vp]),
         "nk_fwd_trans": (i32, [vp, i32, vp, vp, vp]),
+        "nk_tri_points": (i32, [i32, vp, vp, vp, vp]),
+        "nk_space_create_tri": (i32, [pp, i64, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -138,6 +141,16 @@ def _tdtype(code):
 
 def device_count() -> int:
     return int(lib().nk_device_count())
+
+
+def tri_points(Q: int):
+    """(eta1, w1, eta2, w2) of the library's collapsed triangle quadrature."""
+    import numpy as np
+    e1, w1 = np.zeros(Q), np.zeros(Q)
+    e2, w2 = np.zeros(Q - 1), np.zeros(Q - 1)
+    _check(lib().nk_tri_points(Q, e1.ctypes.data_as(ctypes.c_void_p), w1.ctypes.data_as(ctypes.c_void_p),
+                               e2.ctypes.data_as(ctypes.c_void_p), w2.ctypes.data_as(ctypes.c_void_p)))
+    return e1, w1, e2, w2
 
 
 def basis_tables(P: int, Q: int):
@@ -186,6 +199,16 @@ class Space:
         h = ctypes.c_void_p()
         _check(lib().nk_space_create_varp(ctypes.byref(h), dim, ng, Pa, Qa, ne, ja, ka, _stream()))
         return cls(h.value, dim, [(P, Q, int(n)) for P, Q, n in zip(Ps, Qs, ne)])
+
+    @classmethod
+    def create_tri(cls, P: int, Q: int, jac, kappa=None):
+        """Collapsed-coordinate triangles: jac [E, 2, 2, Q(Q-1)] FP64 on the GPU."""
+        import torch
+        E = int(jac.shape[0]) if jac.dim() > 1 else jac.numel() // (4 * Q * (Q - 1))
+        h = ctypes.c_void_p()
+        _check(lib().nk_space_create_tri(ctypes.byref(h), E, P, Q, _ptr(jac, torch.float64, "jac"),
+                                         _ptr(kappa, torch.float64, "kappa"), _stream()))
+        return cls(h.value, 2, [(P, Q, E)])
 
     STRATEGIES = {0: "persistent", 1: "persistent_2bpc", 2: "concurrent", 3: "sequential"}
 

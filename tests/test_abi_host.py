@@ -88,3 +88,21 @@ def test_no_device_reports_edevice():
     h = ctypes.c_void_p()
     assert L.nk_space_create(ctypes.byref(h), 3, 1, 2, 4, ctypes.c_void_p(8), None, None) == nk.NK_EDEVICE
     assert b"device" in L.nk_last_error()
+
+
+@pytest.mark.parametrize("Q", [3, 6, 12])
+def test_library_triangle_quadrature_matches_oracle(Q):
+    """The library's collapsed-triangle points and weights (Newton GLL, Radau
+    weights by exactness) against the oracle's (scipy Jacobi roots, moments)."""
+    import numpy as np
+    from oracle import collapsed as C
+    import oracle
+    nk, L = _lib()
+    e1, w1, e2, w2 = nk.tri_points(Q)
+    x, w = oracle.gll(Q)
+    np.testing.assert_allclose(e1, x, atol=1e-15)
+    np.testing.assert_allclose(w1, w, atol=1e-15)
+    xr, wr = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    np.testing.assert_allclose(e2, xr, atol=1e-14)
+    np.testing.assert_allclose(w2, wr, atol=1e-13)
+    assert L.nk_tri_points(2, None, None, None, None) == nk.NK_EINVAL

@@ -286,6 +286,41 @@ def varp_lattice_l2g(shape, orders):
     return perm, l2g, nglobal, dirichlet
 
 
+def tri_lattice_jacobians(n: int, e1, e2, amp: float = 0.05):
+    """Jacobians of a triangle mesh of the unit square: an n x n lattice of
+    squares, each split along its diagonal into the lower-right triangle
+    (v0, v1, v2) = (x0, x0 + h e_x, x0 + h e_x + h e_y) and the upper-left one
+    (x0, x0 + h(e_x + e_y), x0 + h e_y), both counter-clockwise, composed with
+    the curving map x' = x + a s(x) s(y), y' = y + a/2 s(x) s(y), s(t) =
+    sin(2 pi t).  The affine reference map is x = v0 (-(xi_1 + xi_2)/2)
+    + v1 (1 + xi_1)/2 + v2 (1 + xi_2)/2 evaluated at the collapsed points
+    (eta_1, eta_2) (xi_1 = (1 + eta_1)(1 - eta_2)/2 - 1, xi_2 = eta_2).
+    Returns J[E, c, a, q] = d x'_c / d xi_a with q = i + Q j over (e1, e2)."""
+    e1 = np.asarray(e1, np.float64)
+    e2 = np.asarray(e2, np.float64)
+    E1 = np.tile(e1, e2.size)
+    E2 = np.repeat(e2, e1.size)
+    x1 = (1 + E1) * (1 - E2) / 2 - 1
+    x2 = E2
+    h = 1.0 / n
+    Js = []
+    for k in range(n * n):
+        ox, oy = (k % n) * h, (k // n) * h
+        v0 = np.array([ox, oy])
+        for v1, v2 in ((v0 + [h, 0], v0 + [h, h]), (v0 + [h, h], v0 + [0, h])):
+            A = np.stack([(v1 - v0) / 2, (v2 - v0) / 2], axis=1)          # d x / d xi
+            X = v0[:, None] * (-(x1 + x2) / 2) + v1[:, None] * (1 + x1) / 2 + v2[:, None] * (1 + x2) / 2
+            sx, sy = np.sin(2 * np.pi * X[0]), np.sin(2 * np.pi * X[1])
+            cx, cy = 2 * np.pi * np.cos(2 * np.pi * X[0]), 2 * np.pi * np.cos(2 * np.pi * X[1])
+            W = np.zeros((2, 2, X.shape[1]))                              # d x' / d x
+            W[0, 0] = 1 + amp * cx * sy
+            W[0, 1] = amp * sx * cy
+            W[1, 0] = amp / 2 * cx * sy
+            W[1, 1] = 1 + amp / 2 * sx * cy
+            Js.append(np.einsum("cbq,ba->caq", W, A))
+    return np.stack(Js)
+
+
 # ----------------------------------------------------------- draws
 
 def varp_orders(seed_: int, nelem: int, lo: int = 2, hi: int = 10) -> np.ndarray:
