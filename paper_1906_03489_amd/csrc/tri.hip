@@ -29,10 +29,11 @@ namespace nk {
 template <int P>
 struct TriShape {
   static constexpr int N = P + 1, Q = P + 2, Q2 = Q - 1, NP = Q * Q2, NM = N * (N + 1) / 2;
-  static constexpr int need = NP > NM ? NP : NM;
+  static constexpr int need0 = NP > NM ? NP : NM;
+  static constexpr int need = need0 > Q2 * N ? need0 : Q2 * N;
   static constexpr int NT = need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64
                                                           : (need + 63) / 64 * 64;
-  static constexpr int EPB = NT <= 64 ? 128 / NT : 1;
+  static constexpr int EPB = NT <= 64 ? 512 / NT : 1;   // amortises the table copy
   static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
   static constexpr int off(int p) {
     int o = 0;
@@ -105,24 +106,22 @@ __global__ void __launch_bounds__(TriShape<P>::EPB * TriShape<P>::NT)
   if constexpr (OP == OP_BWD || HELM) {
     if (live && t < NM) C[t] = a.in[e * NM + t];
     slot_sync<NT>();
-    // eta_2 stage: v_p(eta_2j) (and its derivative) for every p
-    if (live && t < Q2) {
-      const int j = t;
-#pragma unroll
-      for (int p = 0; p < N; ++p) {
-        T v = 0, dv = 0;
-#pragma unroll
-        for (int q = 0; q < S::cnt(p); ++q) {
-          const int m = S::off(p) + q;
-          v += B2[j * NM + m] * C[m];
-          if constexpr (HELM) dv += dB2[j * NM + m] * C[m];
-        }
-        V[j * N + p] = v;
-        if constexpr (HELM) dV[j * N + p] = dv;
+    // eta_2 stage: thread (j, p) forms v_p(eta_2j) (and its derivative)
+    if (live && t < Q2 * N) {
+      const int j = t / N, p = t - (t / N) * N;
+      const int m0 = p == 0 ? 0 : (P + 1) + (p - 1) * P - (p - 1) * p / 2;
+      const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
+      T v = 0, dv = 0;
+      for (int q = 0; q < nq; ++q) {
+        v += B2[j * NM + m0 + q] * C[m0 + q];
+        if constexpr (HELM) dv += dB2[j * NM + m0 + q] * C[m0 + q];
       }
-      // the collapsed vertex also multiplies a_P
-      V[j * N + P] += cz[j] * C[P];
-      if constexpr (HELM) dV[j * N + P] += T(0.5) * C[P];
+      if (p == P) {   // the collapsed vertex also multiplies a_P
+        v += cz[j] * C[P];
+        if constexpr (HELM) dv += T(0.5) * C[P];
+      }
+      V[j * N + p] = v;
+      if constexpr (HELM) dV[j * N + p] = dv;
     }
     slot_sync<NT>();
     // eta_1 stage: thread per point
@@ -152,36 +151,20 @@ __global__ void __launch_bounds__(TriShape<P>::EPB * TriShape<P>::NT)
     if (live && t < NP) Mq[t] = a.fac[e * (int64_t)(4 * NP) + t] * a.in[e * NP + t];
   }
   slot_sync<NT>();
-  // transposed eta_1 stage: thread j accumulates over i for every p
-  if (live && t < Q2) {
-    const int j = t;
-    T sa[N], sb[N];
+  // transposed eta_1 stage: thread (j, p) accumulates over i
+  if (live && t < Q2 * N) {
+    const int j = t / N, p = t - (t / N) * N;
+    T sa = 0, sb = 0;
 #pragma unroll
-    for (int p = 0; p < N; ++p) sa[p] = sb[p] = T(0);
-#pragma unroll 2
     for (int i = 0; i < Q; ++i) {
-      const T* Ai = tb.B + i * N;
-      const T* Di = tb.D + i * N;
-      const T mv = Mq[i + Q * j];
-      T g1 = 0, g2 = 0;
+      sa += A[i * N + p] * Mq[i + Q * j];
       if constexpr (HELM) {
-        g1 = G1[i + Q * j];
-        g2 = G2[i + Q * j];
-      }
-#pragma unroll
-      for (int p = 0; p < N; ++p) {
-        sa[p] += Ai[p] * mv;
-        if constexpr (HELM) {
-          sa[p] += Di[p] * g1;
-          sb[p] += Ai[p] * g2;
-        }
+        sa += DA[i * N + p] * G1[i + Q * j];
+        sb += A[i * N + p] * G2[i + Q * j];
       }
     }
-#pragma unroll
-    for (int p = 0; p < N; ++p) {
-      V[j * N + p] = sa[p];
-      if constexpr (HELM) dV[j * N + p] = sb[p];
-    }
+    V[j * N + p] = sa;
+    if constexpr (HELM) dV[j * N + p] = sb;
   }
   slot_sync<NT>();
   // transposed eta_2 stage: thread per mode

@@ -303,22 +303,23 @@ def tri_lattice_jacobians(n: int, e1, e2, amp: float = 0.05):
     x1 = (1 + E1) * (1 - E2) / 2 - 1
     x2 = E2
     h = 1.0 / n
-    Js = []
-    for k in range(n * n):
-        ox, oy = (k % n) * h, (k // n) * h
-        v0 = np.array([ox, oy])
-        for v1, v2 in ((v0 + [h, 0], v0 + [h, h]), (v0 + [h, h], v0 + [0, h])):
-            A = np.stack([(v1 - v0) / 2, (v2 - v0) / 2], axis=1)          # d x / d xi
-            X = v0[:, None] * (-(x1 + x2) / 2) + v1[:, None] * (1 + x1) / 2 + v2[:, None] * (1 + x2) / 2
-            sx, sy = np.sin(2 * np.pi * X[0]), np.sin(2 * np.pi * X[1])
-            cx, cy = 2 * np.pi * np.cos(2 * np.pi * X[0]), 2 * np.pi * np.cos(2 * np.pi * X[1])
-            W = np.zeros((2, 2, X.shape[1]))                              # d x' / d x
-            W[0, 0] = 1 + amp * cx * sy
-            W[0, 1] = amp * sx * cy
-            W[1, 0] = amp / 2 * cx * sy
-            W[1, 1] = 1 + amp / 2 * sx * cy
-            Js.append(np.einsum("cbq,ba->caq", W, A))
-    return np.stack(Js)
+    k = np.arange(n * n)
+    V0 = np.stack([(k % n) * h, (k // n) * h], axis=1)                     # (n^2, 2)
+    out = np.empty((2 * n * n, 2, 2, x1.size))
+    for t, (d1, d2) in enumerate((([h, 0], [h, h]), ([h, h], [0, h]))):
+        V1, V2 = V0 + d1, V0 + d2
+        A = np.stack([(V1 - V0) / 2, (V2 - V0) / 2], axis=2)                # (n^2, c, a)
+        X = (V0[:, :, None] * (-(x1 + x2) / 2) + V1[:, :, None] * (1 + x1) / 2
+             + V2[:, :, None] * (1 + x2) / 2)                               # (n^2, 2, nq)
+        sx, sy = np.sin(2 * np.pi * X[:, 0]), np.sin(2 * np.pi * X[:, 1])
+        cx, cy = 2 * np.pi * np.cos(2 * np.pi * X[:, 0]), 2 * np.pi * np.cos(2 * np.pi * X[:, 1])
+        Wm = np.empty((n * n, 2, 2, x1.size))                              # d x' / d x
+        Wm[:, 0, 0] = 1 + amp * cx * sy
+        Wm[:, 0, 1] = amp * sx * cy
+        Wm[:, 1, 0] = amp / 2 * cx * sy
+        Wm[:, 1, 1] = 1 + amp / 2 * sx * cy
+        out[t::2] = np.einsum("ecbq,eba->ecaq", Wm, A)
+    return out
 
 
 # ----------------------------------------------------------- draws
