@@ -416,7 +416,7 @@ nk_status nk_space_create_tri(nk_space* out, int64_t nelem, int P, int Q, const 
   s->nelem = nelem;
   s->ncoeff = nelem * NM;
   s->npoint = nelem * NP;
-  s->nfac = nelem * 4 * NP;
+  s->nfac = tri_fac_count(Q, nelem);   // padded to whole wavefront groups
   auto cleanup = [&](nk_status stt) {
     space_free(s);
     return stt;
@@ -434,6 +434,8 @@ nk_status nk_space_create_tri(nk_space* out, int64_t nelem, int P, int Q, const 
   }
   int bad = 0;
   if (!(e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) &&
+      !(e = hipMemsetAsync(s->fac64, 0, s->nfac * 8, st)) &&
+      !(e = hipMemsetAsync(s->fac32, 0, s->nfac * 4, st)) &&
       !(e = hipMemcpyAsync(d_pts, pts.data(), pts.size() * 8, hipMemcpyHostToDevice, st)) &&
       !(e = launch_geom_tri(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)) &&
       !(e = hipStreamSynchronize(st)))

@@ -143,7 +143,15 @@ struct DerivArgs {
 };
 hipError_t launch_deriv(nk_dtype t, int which, int dim, int P, const DerivArgs& a);
 
-// Collapsed triangles (tri.hip): BwdTrans, IProductWRTBase, Helmholtz.
+// Collapsed triangles (tri.hip): BwdTrans, IProductWRTBase, Helmholtz.  The
+// operator kernels give each lane one eta_2 point row of a triangle, so a
+// wavefront holds tri_epw(Q) triangles, and the geometric factors are stored
+// in groups of that many triangles ([group][4][Q][tri_epw(Q) * (Q-1)]).
+constexpr int tri_epw(int Q) { return 64 / (Q - 1); }
+inline int64_t tri_fac_count(int Q, int64_t nelem) {
+  const int64_t g = (nelem + tri_epw(Q) - 1) / tri_epw(Q);
+  return g * tri_epw(Q) * 4 * (int64_t)Q * (Q - 1);
+}
 hipError_t launch_tri(nk_dtype t, const OpArgs& a);
 hipError_t launch_geom_tri(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);

@@ -11,12 +11,12 @@
 // evaluated as a_0 b + a_P b (a_0 + a_P = 1), so every stage is a plain
 // per-p contraction.
 //
-// Per element (one slot): coefficients -> LDS; eta_2 stage (thread j: v_p and
-// dv_p/deta_2 at point row j for every p); eta_1 stage (thread per point: u,
-// du/deta_1, du/deta_2); pointwise factors; transposed eta_1 stage (thread
-// j); transposed eta_2 stage (thread per mode).  Factors per point (built at
-// space creation): w detJ, then w detJ kappa (T^T G T) with T the Duffy
-// chain rule d xi / d eta, so the kernel works in collapsed derivatives.
+// Lanes own (triangle, eta_2 row) pairs, so the eta_1 stages, which use the
+// same 1-D tables for every lane, run from registers with scalar table
+// operands; only the eta_2 stages read per-lane table rows from LDS.  Factors
+// per point (built at space creation): w detJ, then w detJ kappa (T^T G T)
+// with T the Duffy chain rule d xi / d eta, so the kernel works in collapsed
+// derivatives.
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -29,23 +29,28 @@ namespace nk {
 template <int P>
 struct TriShape {
   static constexpr int N = P + 1, Q = P + 2, Q2 = Q - 1, NP = Q * Q2, NM = N * (N + 1) / 2;
-  static constexpr int need0 = NP > NM ? NP : NM;
-  static constexpr int need = need0 > Q2 * N ? need0 : Q2 * N;
-  static constexpr int NT = need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : need <= 64 ? 64
-                                                          : (need + 63) / 64 * 64;
-  static constexpr int EPB = NT <= 64 ? 512 / NT : 1;   // amortises the table copy
+  static constexpr int EPW = tri_epw(Q);        // triangles per wavefront
+  static constexpr int LANES = EPW * Q2;        // lane = (triangle, eta_2 row)
+  static constexpr int WPB = 4;                 // wavefronts per block
+  // LDS strides (in scalars), odd so that the distinct addresses a wave
+  // reads at once fall into distinct banks
+  static constexpr int TS = NM | 1;             // eta_2 table row
+  static constexpr int CS = NM | 1;             // one triangle's coefficients
+  static constexpr int RS = Q | 1;              // one eta_2 row of point values
+  static constexpr int XS0 = Q2 * RS, XS1 = 2 * Q2 * N;
+  static constexpr int XS = (XS0 > XS1 ? XS0 : XS1) | 1;   // per-triangle staging
+  static constexpr int TAB = 2 * Q2 * TS;       // B2, dB2
+  static constexpr int WAVE = EPW * (CS + XS);
   static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
   static constexpr int off(int p) {
     int o = 0;
     for (int k = 0; k < p; ++k) o += cnt(k);
     return o;
   }
-  static constexpr int TAB = 2 * Q * N + 2 * Q2 * NM + Q2;   // A, DA, B2, dB2, (1+eta_2)/2
-  static constexpr int SLOT = NM + 2 * Q2 * N + 3 * NP;
 };
 
-// Device table of order P: A [Q][N], DA [Q][N], B2 [Q2][NM], dB2 [Q2][NM],
-// c [Q2] = (1 + eta_2)/2.
+// Device table of order P: B2 [Q2][NM] and dB2 [Q2][NM], the eta_2 factor of
+// every mode and its derivative at the Radau points.
 template <typename T>
 static const T* tri_table(int P) {
   static std::mutex mu;
@@ -56,17 +61,13 @@ static const T* tri_table(int P) {
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  const int N = P + 1, Q = P + 2, Q2 = Q - 1, NM = N * (N + 1) / 2;
-  std::vector<double> e1(Q), w1(Q), e2(Q2), w2(Q2), A(Q * N), DA(Q * N), B2(Q2 * NM), dB2(Q2 * NM);
+  const int Q = P + 2, Q2 = Q - 1, NM = (P + 1) * (P + 2) / 2;
+  std::vector<double> e1(Q), w1(Q), e2(Q2), w2(Q2), B2(Q2 * NM), dB2(Q2 * NM);
   tri_points(Q, e1.data(), w1.data(), e2.data(), w2.data());
-  modified_basis(P, Q, e1.data(), A.data(), DA.data());
   tri_btable(P, Q2, e2.data(), B2.data(), dB2.data());
   std::vector<T> h;
-  for (double v : A) h.push_back((T)v);
-  for (double v : DA) h.push_back((T)v);
   for (double v : B2) h.push_back((T)v);
   for (double v : dB2) h.push_back((T)v);
-  for (double v : e2) h.push_back((T)(0.5 * (1.0 + v)));
   T* d = nullptr;
   if (hipMalloc((void**)&d, h.size() * sizeof(T)) != hipSuccess) return nullptr;
   if (hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
@@ -77,116 +78,211 @@ static const T* tri_table(int P) {
   return d;
 }
 
+// Per wavefront: groups of EPW consecutive triangles, lane (el, j) owning
+// eta_2 row j of triangle el.  Stages per group:
+//  1. coefficients of the group -> LDS (one contiguous, coalesced run);
+//  2. eta_2 stage: v_p(eta_2j) and dv_p/deta_2 for every p, from the LDS
+//     table rows of j (registers V[N], dV[N]);
+//  3. one loop over the eta_1 points i: the eta_1 stage (values and both
+//     collapsed derivatives), the 4 pointwise factors, and the transposed
+//     eta_1 stage accumulated into registers SA[N], SB[N]; the eta_1 tables
+//     are the same for every lane, so they are scalar operands;
+//  4. SA, SB -> LDS; transposed eta_2 stage with lane (el, t) forming the
+//     modes t, t + Q2, ...; results staged in LDS and stored contiguously.
+// Each wavefront works only in its own LDS region, so stages are separated
+// by wavefront-level fences.
 template <typename T, int P, int OP>
-__global__ void __launch_bounds__(TriShape<P>::EPB * TriShape<P>::NT)
+__global__ void __launch_bounds__(TriShape<P>::WPB * 64)
     k_tri(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const DevArgs<T> a) {
   using S = TriShape<P>;
-  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NP = S::NP, NM = S::NM, NT = S::NT;
-  constexpr int EPB = S::EPB;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NP = S::NP, NM = S::NM, EPW = S::EPW;
   constexpr bool HELM = OP == OP_HELM;
   __shared__ T stab[S::TAB];
-  __shared__ T smem[EPB * S::SLOT];
-  for (int k = threadIdx.x; k < S::TAB; k += EPB * NT) stab[k] = tab[k];
+  __shared__ T smem[S::WPB * S::WAVE];
+  for (int k = threadIdx.x; k < Q2 * NM; k += S::WPB * 64) {
+    const int j = k / NM, m = k - j * NM;
+    stab[j * S::TS + m] = tab[k];
+    stab[(Q2 + j) * S::TS + m] = tab[Q2 * NM + k];
+  }
   __syncthreads();
-  const T* A = stab;
-  const T* DA = stab + Q * N;
-  const T* B2 = stab + 2 * Q * N;
-  const T* dB2 = B2 + Q2 * NM;
-  const T* cz = dB2 + Q2 * NM;
-  const int slot = threadIdx.x / NT, t = threadIdx.x - slot * NT;
-  const int64_t nblk = (a.nelem + EPB - 1) / EPB;
-  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
-  const bool live = e < a.nelem;
-  T* C = smem + slot * S::SLOT;   // coefficients [NM]
-  T* V = C + NM;                   // [Q2][N]
-  T* dV = V + Q2 * N;              // [Q2][N]
-  T* Mq = dV + Q2 * N;             // [NP] each
-  T* G1 = Mq + NP;
-  T* G2 = G1 + NP;
-  if constexpr (OP == OP_BWD || HELM) {
-    if (live && t < NM) C[t] = a.in[e * NM + t];
-    slot_sync<NT>();
-    // eta_2 stage: thread (j, p) forms v_p(eta_2j) (and its derivative)
-    if (live && t < Q2 * N) {
-      const int j = t / N, p = t - (t / N) * N;
-      const int m0 = p == 0 ? 0 : (P + 1) + (p - 1) * P - (p - 1) * p / 2;
-      const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
-      T v = 0, dv = 0;
-      for (int q = 0; q < nq; ++q) {
-        v += B2[j * NM + m0 + q] * C[m0 + q];
-        if constexpr (HELM) dv += dB2[j * NM + m0 + q] * C[m0 + q];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int el = lane / Q2, j = lane - el * Q2;
+  const bool row = lane < S::LANES;
+  const int ela = row ? el : 0;           // addressing: idle lanes use triangle 0
+  T* Cw = smem + wave * S::WAVE;          // [EPW][CS] coefficients, later results
+  T* Xw = Cw + EPW * S::CS;               // [EPW][XS] point values / SA, SB
+  const T* B2 = stab + j * S::TS;
+  const T* dB2 = stab + (Q2 + j) * S::TS;
+  const int64_t ngrp = (a.nelem + EPW - 1) / EPW;
+  const int64_t nwave = (int64_t)gridDim.x * S::WPB;
+  const int64_t per = (ngrp + nwave - 1) / nwave;
+  const int64_t g0 = ((int64_t)blockIdx.x * S::WPB + wave) * per;
+  const int64_t g1 = g0 + per < ngrp ? g0 + per : ngrp;
+  for (int64_t g = g0; g < g1; ++g) {
+    const int64_t e0 = g * EPW;
+    const int ne = a.nelem - e0 < EPW ? (int)(a.nelem - e0) : EPW;   // live triangles
+    const int64_t e = e0 + (el < ne ? el : 0);
+    const bool live = row && el < ne;
+    T SA[N], SB[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) SA[p] = SB[p] = T(0);
+    if constexpr (OP == OP_BWD || HELM) {
+      for (int k = lane; k < ne * NM; k += 64) {
+        const int ee = k / NM;
+        Cw[ee * S::CS + (k - ee * NM)] = a.in[e0 * NM + k];
       }
-      if (p == P) {   // the collapsed vertex also multiplies a_P
-        v += cz[j] * C[P];
-        if constexpr (HELM) dv += T(0.5) * C[P];
-      }
-      V[j * N + p] = v;
-      if constexpr (HELM) dV[j * N + p] = dv;
-    }
-    slot_sync<NT>();
-    // eta_1 stage: thread per point
-    if (live && t < NP) {
-      const int i = t % Q, j = t / Q;
-      T u = 0, u1 = 0, u2 = 0;
+      slot_sync<64>();
+      T V[N], dV[N];
+#pragma unroll
+      for (int p = 0; p < N; ++p) V[p] = dV[p] = T(0);
+      const T* c = Cw + ela * S::CS;
 #pragma unroll
       for (int p = 0; p < N; ++p) {
-        u += A[i * N + p] * V[j * N + p];
+#pragma unroll
+        for (int q = 0; q < S::cnt(p); ++q) {
+          const T cm = c[S::off(p) + q];
+          V[p] += B2[S::off(p) + q] * cm;
+          if constexpr (HELM) dV[p] += dB2[S::off(p) + q] * cm;
+        }
+        // finish one mode group before the next group's loads are issued, so
+        // only one group's table entries are held in registers
         if constexpr (HELM) {
-          u1 += DA[i * N + p] * V[j * N + p];
-          u2 += A[i * N + p] * dV[j * N + p];
+          __asm__ volatile("" : "+v"(V[p]), "+v"(dV[p])::"memory");
+        } else {
+          __asm__ volatile("" : "+v"(V[p])::"memory");
         }
       }
+      {   // the collapsed vertex (mode P of group p = 0) also multiplies a_P
+        const T cm = c[P];
+        V[P] += B2[P] * cm;
+        if constexpr (HELM) dV[P] += dB2[P] * cm;
+      }
       if constexpr (OP == OP_BWD) {
-        a.out[e * NP + t] = u;
+        T* x = Xw + ela * S::XS + j * S::RS;
+#pragma unroll 1
+        for (int i = 0; i < Q; ++i) {
+          T u = T(0);
+#pragma unroll
+          for (int p = 0; p < N; ++p) u += tb.B[i * N + p] * V[p];
+          if (row) x[i] = u;
+        }
+        slot_sync<64>();
+        for (int k = lane; k < ne * NP; k += 64) {
+          const int ee = k / NP, q = k - ee * NP, jj = q / Q;
+          a.out[e0 * NP + k] = Xw[ee * S::XS + jj * S::RS + (q - jj * Q)];
+        }
+        slot_sync<64>();
+        continue;
       } else {
-        const T* f = a.fac + e * (int64_t)(4 * NP) + t;
         const T lam = (T)(a.lam ? a.lam[e] : a.lam0);
-        Mq[t] = lam * f[0] * u;
-        G1[t] = f[NP] * u1 + f[2 * NP] * u2;
-        G2[t] = f[2 * NP] * u1 + f[3 * NP] * u2;
-      }
-    }
-    if constexpr (OP == OP_BWD) return;
-  } else {  // IProductWRTBase: point values times w detJ
-    if (live && t < NP) Mq[t] = a.fac[e * (int64_t)(4 * NP) + t] * a.in[e * NP + t];
-  }
-  slot_sync<NT>();
-  // transposed eta_1 stage: thread (j, p) accumulates over i
-  if (live && t < Q2 * N) {
-    const int j = t / N, p = t - (t / N) * N;
-    T sa = 0, sb = 0;
+        const T* f = a.fac + g * (int64_t)(4 * Q * S::LANES) + lane;
+#pragma unroll 1
+        for (int i = 0; i < Q; ++i) {
+          T u = T(0), u1 = T(0), u2 = T(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      sa += A[i * N + p] * Mq[i + Q * j];
-      if constexpr (HELM) {
-        sa += DA[i * N + p] * G1[i + Q * j];
-        sb += A[i * N + p] * G2[i + Q * j];
-      }
-    }
-    V[j * N + p] = sa;
-    if constexpr (HELM) dV[j * N + p] = sb;
-  }
-  slot_sync<NT>();
-  // transposed eta_2 stage: thread per mode
-  if (live && t < NM) {
-    int p = 0;
+          for (int p = 0; p < N; ++p) {
+            u += tb.B[i * N + p] * V[p];
+            u1 += tb.D[i * N + p] * V[p];
+            u2 += tb.B[i * N + p] * dV[p];
+          }
+          T f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+          if (row) {
+            f0 = f[(0 * Q + i) * S::LANES];
+            f1 = f[(1 * Q + i) * S::LANES];
+            f2 = f[(2 * Q + i) * S::LANES];
+            f3 = f[(3 * Q + i) * S::LANES];
+          }
+          const T mq = lam * f0 * u;
+          const T g1_ = f1 * u1 + f2 * u2;
+          const T g2_ = f2 * u1 + f3 * u2;
 #pragma unroll
-    for (int k = 1; k < N; ++k) p += (t >= S::off(k)) ? 1 : 0;
-    T y = 0;
-#pragma unroll 4
-    for (int j = 0; j < Q2; ++j) {
-      y += B2[j * NM + t] * V[j * N + p];
-      if constexpr (HELM) y += dB2[j * NM + t] * dV[j * N + p];
-    }
-    if (t == P) {   // the collapsed vertex: its a_P part
-#pragma unroll 4
-      for (int j = 0; j < Q2; ++j) {
-        y += cz[j] * V[j * N + P];
-        if constexpr (HELM) y += T(0.5) * dV[j * N + P];
+          for (int p = 0; p < N; ++p) {
+            SA[p] += tb.B[i * N + p] * mq + tb.D[i * N + p] * g1_;
+            SB[p] += tb.B[i * N + p] * g2_;
+          }
+        }
       }
+    } else {   // IProductWRTBase: point values staged through LDS, times w detJ
+      for (int k = lane; k < ne * NP; k += 64) {
+        const int ee = k / NP, q = k - ee * NP, jj = q / Q;
+        Xw[ee * S::XS + jj * S::RS + (q - jj * Q)] = a.in[e0 * NP + k];
+      }
+      slot_sync<64>();
+      const T* x = Xw + ela * S::XS + j * S::RS;
+      const T* f = a.fac + g * (int64_t)(4 * Q * S::LANES) + lane;
+#pragma unroll 1
+      for (int i = 0; i < Q; ++i) {
+        const T mq = row ? f[i * S::LANES] * x[i] : T(0);
+#pragma unroll
+        for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
+      }
+      slot_sync<64>();
     }
-    a.out[e * NM + t] = y;
+    // transposed eta_2 stage
+    {
+      T* s = Xw + ela * S::XS;
+      if (row) {
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          s[j * N + p] = SA[p];
+          if constexpr (HELM) s[(Q2 + j) * N + p] = SB[p];
+        }
+      }
+      slot_sync<64>();
+      if (live) {
+        const T* sa = Xw + el * S::XS;
+        for (int m = j; m < NM; m += Q2) {
+          int p = 0;
+#pragma unroll
+          for (int k = 1; k < N; ++k) p += (m >= S::off(k)) ? 1 : 0;
+          T y = T(0);
+#pragma unroll
+          for (int jj = 0; jj < Q2; ++jj) {
+            y += stab[jj * S::TS + m] * sa[jj * N + p];
+            if constexpr (HELM) y += stab[(Q2 + jj) * S::TS + m] * sa[(Q2 + jj) * N + p];
+          }
+          if (m == P) {   // the collapsed vertex: its a_P part
+#pragma unroll
+            for (int jj = 0; jj < Q2; ++jj) {
+              y += stab[jj * S::TS + P] * sa[jj * N + P];
+              if constexpr (HELM) y += stab[(Q2 + jj) * S::TS + P] * sa[(Q2 + jj) * N + P];
+            }
+          }
+          Cw[el * S::CS + m] = y;
+        }
+      }
+      slot_sync<64>();
+      for (int k = lane; k < ne * NM; k += 64) {
+        const int ee = k / NM;
+        a.out[e0 * NM + k] = Cw[ee * S::CS + (k - ee * NM)];
+      }
+      slot_sync<64>();
+    }
   }
+}
+
+// Persistent grid: every resident block of the device, times kTriWaves so a
+// block finishing early still leaves work for the scheduler to balance.
+constexpr int kTriWaves = 4;
+
+template <typename T, int P>
+static int64_t tri_grid(int op) {
+  static std::unordered_map<int, int64_t> cached;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  int dev = 0, cus = 0, nb = 0;
+  (void)hipGetDevice(&dev);
+  const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : 2);
+  auto it = cached.find(key);
+  if (it != cached.end()) return it->second;
+  using S = TriShape<P>;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const void* fn = op == OP_BWD ? (const void*)k_tri<T, P, OP_BWD>
+                   : op == OP_IPROD ? (const void*)k_tri<T, P, OP_IPROD> : (const void*)k_tri<T, P, OP_HELM>;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, S::WPB * 64, 0);
+  const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (nb > 0 ? nb : 1) * kTriWaves;
+  cached[key] = grid;
+  return grid;
 }
 
 template <typename T, int P>
@@ -194,11 +290,12 @@ static hipError_t run_tri(const OpArgs& a) {
   using S = TriShape<P>;
   const T* tab = tri_table<T>(P);
   if (!tab) return hipErrorOutOfMemory;
-  const int64_t nblk = (a.nelem + S::EPB - 1) / S::EPB;
-  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t ngrp = (a.nelem + S::EPW - 1) / S::EPW;
+  const int64_t need = (ngrp + S::WPB - 1) / S::WPB;
   const Tab<T, P + 1, P + 2>& tb = host_tab<T, P + 1, P + 2>();
   const DevArgs<T> d = dev_args<T>(a);
-  const dim3 g((unsigned)nblk), b(S::EPB * S::NT);
+  const int64_t nb = need < tri_grid<T, P>(a.op) ? need : tri_grid<T, P>(a.op);
+  const dim3 g((unsigned)nb), b(S::WPB * 64);
   switch (a.op) {
     case OP_BWD: hipLaunchKernelGGL((k_tri<T, P, OP_BWD>), g, b, 0, a.stream, tb, tab, d); break;
     case OP_IPROD: hipLaunchKernelGGL((k_tri<T, P, OP_IPROD>), g, b, 0, a.stream, tb, tab, d); break;
@@ -267,9 +364,15 @@ __global__ void __launch_bounds__(256)
   const double wj = 0.5 * w1 * w2 * det;
   const double f[4] = {wj, wj * kap * H[0][0], wj * kap * H[0][1], wj * kap * H[1][1]};
   if (!(det > 0.0) || !(kap > 0.0)) atomicOr(bad, 1);
+  // wavefront-blocked layout: group g of EPW triangles holds [4][Q][EPW * Q2],
+  // lane (el, j) of the operator kernels reading one contiguous run per (k, i)
+  const int epw = tri_epw(Q), lanes = epw * Q2;
+  const int64_t g = e / epw;
+  const int lane = (int)(e - g * epw) * Q2 + j;
   for (int k = 0; k < 4; ++k) {
-    fac64[(e * 4 + k) * NP + q] = f[k];
-    fac32[(e * 4 + k) * NP + q] = (float)f[k];
+    const int64_t o = (g * 4 * Q + k * Q + i) * lanes + lane;
+    fac64[o] = f[k];
+    fac32[o] = (float)f[k];
   }
 }
 
