@@ -37,10 +37,15 @@ struct TriShape {
   static constexpr int TS = NM | 1;             // eta_2 table row
   static constexpr int CS = NM | 1;             // one triangle's coefficients
   static constexpr int RS = Q | 1;              // one eta_2 row of point values
-  static constexpr int XS0 = Q2 * RS, XS1 = 2 * Q2 * N;
-  static constexpr int XS = (XS0 > XS1 ? XS0 : XS1) | 1;   // per-triangle staging
-  static constexpr int TAB = 2 * Q2 * TS;       // B2, dB2
-  static constexpr int WAVE = EPW * (CS + XS);
+  // per-triangle staging: point values (BwdTrans out, IProductWRTBase in)
+  // and the transposed eta_1 results SA (and SB for Helmholtz)
+  static constexpr int xs(int op) {
+    return (op == OP_BWD ? Q2 * RS
+            : op == OP_IPROD ? (Q2 * RS > Q2 * N ? Q2 * RS : Q2 * N)
+                             : 2 * Q2 * N) | 1;
+  }
+  static constexpr int ntab(int op) { return op == OP_HELM ? 2 : 1; }   // B2 (, dB2)
+  static constexpr int wave_lds(int op) { return EPW * (CS + xs(op)); }
   static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
   static constexpr int off(int p) {
     int o = 0;
@@ -80,7 +85,8 @@ static const T* tri_table(int P) {
 
 // Per wavefront: groups of EPW consecutive triangles, lane (el, j) owning
 // eta_2 row j of triangle el.  Stages per group:
-//  1. coefficients of the group -> LDS (one contiguous, coalesced run);
+//  1. the group's inputs (coefficients, or point values for IProductWRTBase;
+//     one contiguous run through registers) -> LDS;
 //  2. eta_2 stage: v_p(eta_2j) and dv_p/deta_2 for every p, from the LDS
 //     table rows of j (registers V[N], dV[N]);
 //  3. one loop over the eta_1 points i: the eta_1 stage (values and both
@@ -96,20 +102,22 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
     k_tri(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const DevArgs<T> a) {
   using S = TriShape<P>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NP = S::NP, NM = S::NM, EPW = S::EPW;
+  constexpr int LANES = S::LANES, XS = S::xs(OP), WAVE = S::wave_lds(OP);
   constexpr bool HELM = OP == OP_HELM;
-  __shared__ T stab[S::TAB];
-  __shared__ T smem[S::WPB * S::WAVE];
-  for (int k = threadIdx.x; k < Q2 * NM; k += S::WPB * 64) {
-    const int j = k / NM, m = k - j * NM;
-    stab[j * S::TS + m] = tab[k];
-    stab[(Q2 + j) * S::TS + m] = tab[Q2 * NM + k];
+  constexpr int NIN = OP == OP_IPROD ? NP : NM;          // inputs per triangle
+  constexpr int KIN = (EPW * NIN + 63) / 64;             // inputs per lane per group
+  __shared__ T stab[S::ntab(OP) * Q2 * S::TS];
+  __shared__ T smem[S::WPB * WAVE];
+  for (int k = threadIdx.x; k < S::ntab(OP) * Q2 * NM; k += S::WPB * 64) {
+    const int r = k / NM;
+    stab[r * S::TS + (k - r * NM)] = tab[k];
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int el = lane / Q2, j = lane - el * Q2;
-  const bool row = lane < S::LANES;
+  const bool row = lane < LANES;
   const int ela = row ? el : 0;           // addressing: idle lanes use triangle 0
-  T* Cw = smem + wave * S::WAVE;          // [EPW][CS] coefficients, later results
+  T* Cw = smem + wave * WAVE;             // [EPW][CS] coefficients, later results
   T* Xw = Cw + EPW * S::CS;               // [EPW][XS] point values / SA, SB
   const T* B2 = stab + j * S::TS;
   const T* dB2 = stab + (Q2 + j) * S::TS;
@@ -118,20 +126,58 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
   const int64_t per = (ngrp + nwave - 1) / nwave;
   const int64_t g0 = ((int64_t)blockIdx.x * S::WPB + wave) * per;
   const int64_t g1 = g0 + per < ngrp ? g0 + per : ngrp;
+  auto group_size = [&](int64_t g) {
+    const int64_t left = a.nelem - g * EPW;
+    return left < EPW ? (int)left : EPW;
+  };
+  T pre[KIN];
+  auto load_in = [&](int64_t g) {
+    const int lim = group_size(g) * NIN;
+    const T* src = a.in + g * EPW * NIN;
+#pragma unroll
+    for (int r = 0; r < KIN; ++r) {
+      const int k = lane + 64 * r;
+      pre[r] = k < lim ? src[k] : T(0);
+    }
+  };
+  // BwdTrans and IProductWRTBase request the next group's inputs before
+  // computing the current one; Helmholtz loads its group at the start, since
+  // its factor loads inside the point loop would wait for the prefetch anyway
+  // (loads retire in order) and the prefetch registers cost occupancy.
+  constexpr bool PREFETCH = !HELM;
+  if (PREFETCH && g0 < g1) load_in(g0);
   for (int64_t g = g0; g < g1; ++g) {
     const int64_t e0 = g * EPW;
-    const int ne = a.nelem - e0 < EPW ? (int)(a.nelem - e0) : EPW;   // live triangles
+    const int ne = group_size(g);                       // live triangles
     const int64_t e = e0 + (el < ne ? el : 0);
     const bool live = row && el < ne;
-    T SA[N], SB[N];
+    if constexpr (PREFETCH) {
 #pragma unroll
-    for (int p = 0; p < N; ++p) SA[p] = SB[p] = T(0);
-    if constexpr (OP == OP_BWD || HELM) {
+      for (int r = 0; r < KIN; ++r) {
+        const int k = lane + 64 * r;
+        if (k < ne * NIN) {
+          const int ee = k / NIN, q = k - ee * NIN;
+          if constexpr (OP == OP_IPROD) {
+            const int jj = q / Q;
+            Xw[ee * XS + jj * S::RS + (q - jj * Q)] = pre[r];
+          } else {
+            Cw[ee * S::CS + q] = pre[r];
+          }
+        }
+      }
+      slot_sync<64>();
+      if (g + 1 < g1) load_in(g + 1);
+    } else {
       for (int k = lane; k < ne * NM; k += 64) {
         const int ee = k / NM;
         Cw[ee * S::CS + (k - ee * NM)] = a.in[e0 * NM + k];
       }
       slot_sync<64>();
+    }
+    T SA[N], SB[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) SA[p] = SB[p] = T(0);
+    if constexpr (OP == OP_BWD || HELM) {
       T V[N], dV[N];
 #pragma unroll
       for (int p = 0; p < N; ++p) V[p] = dV[p] = T(0);
@@ -158,7 +204,7 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
         if constexpr (HELM) dV[P] += dB2[P] * cm;
       }
       if constexpr (OP == OP_BWD) {
-        T* x = Xw + ela * S::XS + j * S::RS;
+        T* x = Xw + ela * XS + j * S::RS;
 #pragma unroll 1
         for (int i = 0; i < Q; ++i) {
           T u = T(0);
@@ -169,15 +215,20 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
         slot_sync<64>();
         for (int k = lane; k < ne * NP; k += 64) {
           const int ee = k / NP, q = k - ee * NP, jj = q / Q;
-          a.out[e0 * NP + k] = Xw[ee * S::XS + jj * S::RS + (q - jj * Q)];
+          a.out[e0 * NP + k] = Xw[ee * XS + jj * S::RS + (q - jj * Q)];
         }
         slot_sync<64>();
         continue;
       } else {
         const T lam = (T)(a.lam ? a.lam[e] : a.lam0);
-        const T* f = a.fac + g * (int64_t)(4 * Q * S::LANES) + lane;
+        const T* f = a.fac + g * (int64_t)(4 * Q * LANES) + lane;
 #pragma unroll 1
         for (int i = 0; i < Q; ++i) {
+          T fa[4] = {T(0), T(0), T(0), T(0)};
+          if (row) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fa[k] = f[(k * Q + i) * LANES];
+          }
           T u = T(0), u1 = T(0), u2 = T(0);
 #pragma unroll
           for (int p = 0; p < N; ++p) {
@@ -185,16 +236,9 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
             u1 += tb.D[i * N + p] * V[p];
             u2 += tb.B[i * N + p] * dV[p];
           }
-          T f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-          if (row) {
-            f0 = f[(0 * Q + i) * S::LANES];
-            f1 = f[(1 * Q + i) * S::LANES];
-            f2 = f[(2 * Q + i) * S::LANES];
-            f3 = f[(3 * Q + i) * S::LANES];
-          }
-          const T mq = lam * f0 * u;
-          const T g1_ = f1 * u1 + f2 * u2;
-          const T g2_ = f2 * u1 + f3 * u2;
+          const T mq = lam * fa[0] * u;
+          const T g1_ = fa[1] * u1 + fa[2] * u2;
+          const T g2_ = fa[2] * u1 + fa[3] * u2;
 #pragma unroll
           for (int p = 0; p < N; ++p) {
             SA[p] += tb.B[i * N + p] * mq + tb.D[i * N + p] * g1_;
@@ -202,25 +246,24 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
           }
         }
       }
-    } else {   // IProductWRTBase: point values staged through LDS, times w detJ
-      for (int k = lane; k < ne * NP; k += 64) {
-        const int ee = k / NP, q = k - ee * NP, jj = q / Q;
-        Xw[ee * S::XS + jj * S::RS + (q - jj * Q)] = a.in[e0 * NP + k];
-      }
-      slot_sync<64>();
-      const T* x = Xw + ela * S::XS + j * S::RS;
-      const T* f = a.fac + g * (int64_t)(4 * Q * S::LANES) + lane;
+    } else {   // IProductWRTBase: staged point values times w detJ
+      const T* x = Xw + ela * XS + j * S::RS;
+      const T* f = a.fac + g * (int64_t)(4 * Q * LANES) + lane;
+      T fa = row ? f[0] : T(0), fb = row ? f[LANES] : T(0);
 #pragma unroll 1
       for (int i = 0; i < Q; ++i) {
-        const T mq = row ? f[i * S::LANES] * x[i] : T(0);
+        const T fc = (row && i + 2 < Q) ? f[(i + 2) * LANES] : T(0);
+        const T mq = row ? fa * x[i] : T(0);
 #pragma unroll
         for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
+        fa = fb;
+        fb = fc;
       }
       slot_sync<64>();
     }
     // transposed eta_2 stage
     {
-      T* s = Xw + ela * S::XS;
+      T* s = Xw + ela * XS;
       if (row) {
 #pragma unroll
         for (int p = 0; p < N; ++p) {
@@ -230,25 +273,25 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
       }
       slot_sync<64>();
       if (live) {
-        const T* sa = Xw + el * S::XS;
-        for (int m = j; m < NM; m += Q2) {
+        const T* sa = Xw + el * XS;
+        for (int mm = j; mm < NM; mm += Q2) {
           int p = 0;
 #pragma unroll
-          for (int k = 1; k < N; ++k) p += (m >= S::off(k)) ? 1 : 0;
+          for (int k = 1; k < N; ++k) p += (mm >= S::off(k)) ? 1 : 0;
           T y = T(0);
 #pragma unroll
           for (int jj = 0; jj < Q2; ++jj) {
-            y += stab[jj * S::TS + m] * sa[jj * N + p];
-            if constexpr (HELM) y += stab[(Q2 + jj) * S::TS + m] * sa[(Q2 + jj) * N + p];
+            y += stab[jj * S::TS + mm] * sa[jj * N + p];
+            if constexpr (HELM) y += stab[(Q2 + jj) * S::TS + mm] * sa[(Q2 + jj) * N + p];
           }
-          if (m == P) {   // the collapsed vertex: its a_P part
+          if (mm == P) {   // the collapsed vertex: its a_P part
 #pragma unroll
             for (int jj = 0; jj < Q2; ++jj) {
               y += stab[jj * S::TS + P] * sa[jj * N + P];
               if constexpr (HELM) y += stab[(Q2 + jj) * S::TS + P] * sa[(Q2 + jj) * N + P];
             }
           }
-          Cw[el * S::CS + m] = y;
+          Cw[el * S::CS + mm] = y;
         }
       }
       slot_sync<64>();
