@@ -211,10 +211,29 @@ nk_status nk_helmholtz_weak_rhs(nk_space s, const double* lambda, double lambda0
  * single group: nglobal global coefficients, l2g device int32 [E][n^d]
  * mapping local to global modes (no sign flips), dirichlet device uint8
  * [nglobal] (1 = homogeneous Dirichlet DOF, fixed at zero), lambda device
- * [E] or NULL (lambda0).  Builds the Jacobi diagonal on the GPU. */
+ * [E] or NULL (lambda0).  Builds the Jacobi diagonal on the GPU.  Triangle
+ * spaces take l2g [E][(P+1)(P+2)/2] in the space's mode order; the global
+ * functions of an unstructured mesh generally need nk_system_create_signed.
+ * The padded system (each system's DOFs rounded up to 2048) must stay below
+ * 2^30 DOFs (NK_EINVAL otherwise). */
 nk_status nk_system_create(nk_system* out, nk_space s, int64_t nglobal, const int32_t* l2g,
                            const uint8_t* dirichlet, const double* lambda, double lambda0,
                            void* stream);
+
+/* As nk_system_create, with orientation signs for unstructured meshes
+ * (section 2.1: the assembly operator maps local to global modes, and an
+ * edge or face that an element traverses against the global direction sees
+ * the odd-parity bubbles of that edge or face negated).  sign: device int8
+ * [E][modes] with entries +1 or -1 (NULL = all +1): the local mode equals
+ * sign times the global function l2g names, so gathering reads sign * x[g]
+ * and scattering adds sign * y_local.  Any other sign value or an l2g index
+ * outside [0, nglobal) returns NK_EINVAL.  Index permutations (a face seen
+ * transposed) are expressed through l2g itself.  Nothing is retained: the
+ * map and signs are copied into the system. */
+nk_status nk_system_create_signed(nk_system* out, nk_space s, int64_t nglobal,
+                                  const int32_t* l2g, const int8_t* sign,
+                                  const uint8_t* dirichlet, const double* lambda, double lambda0,
+                                  void* stream);
 
 /* Many independent systems solved together (the union is block diagonal):
  * system k owns elements [elem_off[k], elem_off[k+1]) of the space and global

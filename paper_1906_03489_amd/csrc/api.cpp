@@ -738,17 +738,17 @@ static hipError_t alloc_state(CgState& c, int n) {
 
 static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st);
 
-nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
-                                   const int64_t* dof_off, const int32_t* l2g,
-                                   const uint8_t* dirichlet, const double* lambda, double lambda0,
-                                   void* stream) {
+static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
+                               const int64_t* dof_off, const int32_t* l2g, const int8_t* sign,
+                               const uint8_t* dirichlet, const double* lambda, double lambda0,
+                               void* stream) {
   if (!out) return fail(NK_EINVAL, "out is NULL");
   *out = nullptr;
   if (!s) return fail(NK_EINVAL, "space is NULL");
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
-  if (s->shape != 0) return fail(NK_EUNSUPPORTED, "assembled systems are built for quadrilaterals and hexahedra");
   if (s->groups.size() != 1 && nsys != 1)
     return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
+  if (s->shape == 1 && nsys != 1) return fail(NK_EINVAL, "a triangle space takes one system (nsys = 1)");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
   if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
     return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");
@@ -760,6 +760,7 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   if (dof_off[nsys] >= ((int64_t)1 << 30)) return fail(NK_EINVAL, "too many global DOFs");
   if (s->ncoeff >= ((int64_t)1 << 31) - 1) return fail(NK_EINVAL, "too many local coefficients");
   NK_CHECK(check_buf(l2g, (size_t)s->ncoeff * 4, "l2g"));
+  if (sign) NK_CHECK(check_buf(sign, (size_t)s->ncoeff, "sign"));
   NK_CHECK(check_buf(dirichlet, (size_t)dof_off[nsys], "dirichlet"));
   if (lambda) NK_CHECK(check_buf(lambda, s->nelem * 8, "lambda"));
   NK_CHECK(check_device());
@@ -791,7 +792,7 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   }
   y->Ld.npad = y->pdot_off[nsys];
   y->Ld.nblk = y->Ld.npad / kSegAlign;
-  if (y->L.npad >= ((int64_t)1 << 31) - 1) {
+  if (y->L.npad >= (int64_t)kL2gNeg) {   // bit 30 of an internal l2g entry is the sign flag
     system_free(y);
     return fail(NK_EINVAL, "padded system too large");
   }
@@ -907,13 +908,18 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
     if ((e = vec_fill<double>(y->y, np, 0.0, st))) break;
     for (size_t g = 0; g < s->groups.size() && e == hipSuccess; ++g) {
       const Group& G = s->groups[g];
-      const int nl = (int)ipow(G.n, s->dim);
+      const int nl = s->shape == 1 ? G.n * (G.n + 1) / 2 : (int)ipow(G.n, s->dim);
       if ((e = build_l2g(G.nelem, nl, y->elem_seg + G.e0, y->d_dof_off, y->d_pdof_off, l2g + G.c0,
-                         dirichlet, y->l2g + G.c0, d_bad, st)))
+                         sign ? sign + G.c0 : nullptr, dirichlet, y->l2g + G.c0, d_bad, st)))
         break;
       if ((e = mark_free(G.nelem, nl, y->l2g + G.c0, y->y, st))) break;
-      e = launch_diag(s->dim, G.P, G.Q, G.nelem, d_B + tab_off[g], d_D + tab_off[g], s->fac64 + G.f0,
-                      y->lam ? y->lam + G.e0 : nullptr, y->lam0, y->l2g + G.c0, y->diag, st);
+      if (s->shape == 1)
+        e = launch_diag_tri(G.P, G.nelem, s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr, y->lam0,
+                            y->l2g + G.c0, y->diag, st);
+      else
+        e = launch_diag(s->dim, G.P, G.Q, G.nelem, d_B + tab_off[g], d_D + tab_off[g],
+                        s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr, y->lam0, y->l2g + G.c0,
+                        y->diag, st);
     }
     if (e) break;
     if ((e = diag_finish(y->L, y->diag, y->y, y->dinv64, y->dinv32, y->diag, st))) break;
@@ -933,7 +939,7 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
   dfree(d_B);
   dfree(d_D);
   if (e != hipSuccess) return cleanup(hip_fail(e, "system setup"));
-  if (bad) return cleanup(fail(NK_EINVAL, "l2g index outside its system's DOF range"));
+  if (bad) return cleanup(fail(NK_EINVAL, "l2g index outside its system's DOF range, or a sign other than +-1"));
   for (size_t g = 0; g < s->groups.size(); ++g) {
     y->tiles64.push_back(tune_asm_tile(y, NK_F64, (int)g, st));
     y->tiles32.push_back(tune_asm_tile(y, NK_F32, (int)g, st));
@@ -944,6 +950,23 @@ nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const i
     return cleanup(hip_fail(e, "system setup"));
   *out = y;
   return NK_OK;
+}
+
+nk_status nk_system_create_batched(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
+                                   const int64_t* dof_off, const int32_t* l2g,
+                                   const uint8_t* dirichlet, const double* lambda, double lambda0,
+                                   void* stream) {
+  return system_create(out, s, nsys, elem_off, dof_off, l2g, nullptr, dirichlet, lambda, lambda0,
+                       stream);
+}
+
+nk_status nk_system_create_signed(nk_system* out, nk_space s, int64_t nglobal, const int32_t* l2g,
+                                  const int8_t* sign, const uint8_t* dirichlet,
+                                  const double* lambda, double lambda0, void* stream) {
+  if (!s) return fail(NK_EINVAL, "space is NULL");
+  if (nglobal < 1) return fail(NK_EINVAL, "nglobal must be >= 1");
+  const int64_t eo[2] = {0, s->nelem}, dofo[2] = {0, nglobal};
+  return system_create(out, s, 1, eo, dofo, l2g, sign, dirichlet, lambda, lambda0, stream);
 }
 
 nk_status nk_system_create(nk_system* out, nk_space s, int64_t nglobal, const int32_t* l2g,
@@ -986,6 +1009,7 @@ static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, vo
   a.seg_done = seg_done;
   a.tile = tile;
   a.stream = st;
+  if (s->shape == 1) return launch_tri(t, a);
   return launch_op(s->dim, t, a);
 }
 
@@ -1342,6 +1366,7 @@ static void cache_store(const std::string& key, int tile, double us) {
 static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st) {
   nk_space s = y->space;
   const Group& G = s->groups[g];
+  if (s->shape == 1) return 0;   // triangle kernels have one launch shape
   const int fallback = cur_tile(OP_HELM_ASM, s->dim, G.P, t);
   const int nt = tile_count(OP_HELM_ASM, s->dim, G.P);
   if (nt <= 1 || G.nelem == 0 || g_tile_forced[s->dim - 2][G.P][t].load()) return fallback;

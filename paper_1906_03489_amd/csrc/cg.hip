@@ -408,12 +408,13 @@ hipError_t pad_out(int nsys, const int64_t* dof_off, const int64_t* pdof_off, in
   return hipGetLastError();
 }
 
-// Internal l2g: user global index g of system s -> padded index gi, stored as
-// gi (free) or -1-gi (Dirichlet).  Out-of-range indices set *bad.
+// Internal l2g: user global index g of system s -> padded index gi, with the
+// sign flag (bit 30) for sign[id] = -1, stored as gi (free) or -1-gi
+// (Dirichlet).  Out-of-range indices or signs other than +-1 set *bad.
 __global__ void k_build_l2g(int64_t nelem, int nloc, const int32_t* __restrict__ elem_seg,
                             const int64_t* __restrict__ dof_off,
                             const int64_t* __restrict__ pdof_off,
-                            const int32_t* __restrict__ l2g_user,
+                            const int32_t* __restrict__ l2g_user, const int8_t* __restrict__ sign,
                             const uint8_t* __restrict__ dirichlet, int32_t* __restrict__ l2g_int,
                             int* bad) {
   const int64_t tot = nelem * nloc;
@@ -422,25 +423,26 @@ __global__ void k_build_l2g(int64_t nelem, int nloc, const int32_t* __restrict__
     const int64_t e = id / nloc;
     const int s = elem_seg[e];
     const int64_t g = l2g_user[id];
-    if (g < dof_off[s] || g >= dof_off[s + 1]) {
+    const int sg = sign ? sign[id] : 1;
+    if (g < dof_off[s] || g >= dof_off[s + 1] || (sg != 1 && sg != -1)) {
       atomicOr(bad, 1);
       l2g_int[id] = -1 - (int32_t)pdof_off[s];
       continue;
     }
-    const int64_t gi = g - dof_off[s] + pdof_off[s];
-    l2g_int[id] = dirichlet[g] ? (int32_t)(-1 - gi) : (int32_t)gi;
+    const int32_t gi = (int32_t)(g - dof_off[s] + pdof_off[s]) | (sg < 0 ? kL2gNeg : 0);
+    l2g_int[id] = dirichlet[g] ? -1 - gi : gi;
   }
 }
 
 hipError_t build_l2g(int64_t nelem, int nloc, const int32_t* elem_seg, const int64_t* dof_off,
-                     const int64_t* pdof_off, const int32_t* l2g_user, const uint8_t* dirichlet,
-                     int32_t* l2g_int, int* bad, hipStream_t s) {
+                     const int64_t* pdof_off, const int32_t* l2g_user, const int8_t* sign,
+                     const uint8_t* dirichlet, int32_t* l2g_int, int* bad, hipStream_t s) {
   const int64_t tot = nelem * nloc;
   if (tot == 0) return hipSuccess;
   int64_t nb = (tot + 255) / 256;
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(k_build_l2g, dim3((unsigned)nb), dim3(256), 0, s, nelem, nloc, elem_seg,
-                     dof_off, pdof_off, l2g_user, dirichlet, l2g_int, bad);
+                     dof_off, pdof_off, l2g_user, sign, dirichlet, l2g_int, bad);
   return hipGetLastError();
 }
 
@@ -474,7 +476,7 @@ __global__ void k_mark(int64_t tot, const int32_t* __restrict__ l2g, double* __r
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < tot;
        id += (int64_t)gridDim.x * blockDim.x) {
     const int32_t g = l2g[id];
-    if (g >= 0) mark[g] = 1.0;
+    if (g >= 0) mark[l2g_dof(g)] = 1.0;
   }
 }
 
@@ -492,7 +494,7 @@ __global__ void k_gather(int64_t tot, const int32_t* __restrict__ l2g,
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < tot;
        id += (int64_t)gridDim.x * blockDim.x) {
     const int32_t g = l2g[id];
-    xl[id] = x[g >= 0 ? g : -1 - g];
+    xl[id] = l2g_sign(g, x[l2g_dof(g)]);
   }
 }
 
@@ -511,7 +513,7 @@ __global__ void k_scatter(int64_t tot, const int32_t* __restrict__ l2g,
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < tot;
        id += (int64_t)gridDim.x * blockDim.x) {
     const int32_t g = l2g[id];
-    if (g >= 0) unsafeAtomicAdd(y + g, yl[id]);
+    if (g >= 0) unsafeAtomicAdd(y + l2g_dof(g), l2g_sign(g, yl[id]));
   }
 }
 

@@ -311,7 +311,7 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
       if constexpr (ASM) {
         const int32_t g = a.l2g[ee * N3 + r * NN + t];
         gidx[r] = g;
-        xin[r] = g >= 0 ? a.in[g] : T(0);
+        xin[r] = g >= 0 ? l2g_sign(g, a.in[l2g_dof(g)]) : T(0);
       } else {
         xin[r] = a.in[ee * N3 + r * NN + t];
       }
@@ -392,7 +392,7 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
     if (pq) {
 #pragma unroll
       for (int r = 0; r < N; ++r) {
-        if (gidx[r] >= 0) atomic_add(a.out + gidx[r], yv[r]);
+        if (gidx[r] >= 0) atomic_add(a.out + l2g_dof(gidx[r]), l2g_sign(gidx[r], yv[r]));
         dp += (double)xin[r] * (double)yv[r];
       }
     }

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  unsafeAtomicAdd(diag + g, s);
+  unsafeAtomicAdd(diag + l2g_dof(g), s);
 }
 
 hipError_t launch_diag(int dim, int P, int Q, int64_t nelem, const double* Bt, const double* Dt,

@@ -212,11 +212,11 @@ __global__ void __launch_bounds__(EPB * 64)
         if constexpr (ASM) {
           if (r0 < N) {
             const int32_t gi = l2ge[r0 * NN + col];
-            x0 = gi >= 0 ? xe[gi] : T(0);
+            x0 = gi >= 0 ? l2g_sign(gi, xe[l2g_dof(gi)]) : T(0);
           }
           if (r1 < N) {
             const int32_t gi = l2ge[r1 * NN + col];
-            x1 = gi >= 0 ? xe[gi] : T(0);
+            x1 = gi >= 0 ? l2g_sign(gi, xe[l2g_dof(gi)]) : T(0);
           }
         } else {
           if (r0 < N) x0 = xe[r0 * NN + col];
@@ -426,8 +426,9 @@ __global__ void __launch_bounds__(EPB * 64)
             if constexpr (ASM) {
               const int32_t gi = l2ge[r * NN + col];
               if (gi >= 0) {
-                atomic_add(a.out + gi, acc[v]);
-                dp += (double)xe[gi] * (double)acc[v];
+                const T yv = l2g_sign(gi, acc[v]);
+                atomic_add(a.out + l2g_dof(gi), yv);
+                dp += (double)xe[l2g_dof(gi)] * (double)yv;
               }
             } else {
               a.out[e * N3 + r * NN + col] = acc[v];

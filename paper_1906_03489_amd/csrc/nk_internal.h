@@ -19,6 +19,23 @@ constexpr int kNF2 = 4;            // per-point factors in 2-D
 constexpr int kVecBlock = 256;     // threads per block of the CG vector kernels
 constexpr int64_t kSegAlign = 2048;  // DOF ranges of each system padded to this (one vector block)
 
+// Internal l2g entries of assembled systems: v >= 0 is the free padded DOF v,
+// v < 0 the Dirichlet padded DOF -1-v.  In both, bit 30 of the DOF marks a
+// local mode whose global function is the negative of the local one (an edge
+// or face that the element traverses against its global direction); the DOF
+// index is the value with that bit cleared, so padded systems stay below 2^30.
+constexpr int32_t kL2gNeg = 1 << 30;
+__host__ __device__ __forceinline__ int32_t l2g_dof(int32_t v) {
+  return (v >= 0 ? v : -1 - v) & (kL2gNeg - 1);
+}
+__host__ __device__ __forceinline__ bool l2g_neg(int32_t v) {
+  return ((v >= 0 ? v : -1 - v) & kL2gNeg) != 0;
+}
+template <typename T>
+__host__ __device__ __forceinline__ T l2g_sign(int32_t v, T x) {
+  return l2g_neg(v) ? -x : x;
+}
+
 // ------------------------------------------------------------ host tables
 void gll_points(int Q, double* x, double* w);
 void modified_basis(int P, int Q, const double* x, double* B, double* DB);
@@ -152,7 +169,9 @@ inline int64_t tri_fac_count(int Q, int64_t nelem) {
   const int64_t g = (nelem + tri_epw(Q) - 1) / tri_epw(Q);
   return g * tri_epw(Q) * 4 * (int64_t)Q * (Q - 1);
 }
-hipError_t launch_tri(nk_dtype t, const OpArgs& a);
+hipError_t launch_tri(nk_dtype t, const OpArgs& a);   // also OP_HELM_ASM (assembled)
+hipError_t launch_diag_tri(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                           const int32_t* l2g, double* diag, hipStream_t st);
 hipError_t launch_geom_tri(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 

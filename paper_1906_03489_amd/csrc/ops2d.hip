@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(EPB * Q)
         if constexpr (ASM) {
           const int32_t g = l2g_e[q * N + t];
           gidx[q] = g;
-          xin[q] = g >= 0 ? in[g] : T(0);
+          xin[q] = g >= 0 ? l2g_sign(g, in[l2g_dof(g)]) : T(0);
         } else {
           xin[q] = in[q * N + t];
         }
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(EPB * Q)
       if (live && t < N) {
 #pragma unroll
         for (int q = 0; q < N; ++q) {
-          if (gidx[q] >= 0) atomic_add(a.out + gidx[q], yv[q]);
+          if (gidx[q] >= 0) atomic_add(a.out + l2g_dof(gidx[q]), l2g_sign(gidx[q], yv[q]));
           dp += (double)xin[q] * (double)yv[q];
         }
       }

@@ -64,8 +64,8 @@ template <typename T>
 hipError_t pad_out(int nsys, const int64_t* dof_off, const int64_t* pdof_off, int64_t nuser,
                    const T* padded, T* user, hipStream_t s);
 hipError_t build_l2g(int64_t nelem, int nloc, const int32_t* elem_seg, const int64_t* dof_off,
-                     const int64_t* pdof_off, const int32_t* l2g_user, const uint8_t* dirichlet,
-                     int32_t* l2g_int, int* bad, hipStream_t s);
+                     const int64_t* pdof_off, const int32_t* l2g_user, const int8_t* sign,
+                     const uint8_t* dirichlet, int32_t* l2g_int, int* bad, hipStream_t s);
 hipError_t diag_finish(const VecLayout& L, const double* diag, const double* mark,
                        double* dinv64, float* dinv32, double* diag_out, hipStream_t s);
 hipError_t mark_free(int64_t nelem, int nloc, const int32_t* l2g_int, double* mark, hipStream_t s);

@@ -44,7 +44,8 @@ struct TriShape {
             : op == OP_IPROD ? (Q2 * RS > Q2 * N ? Q2 * RS : Q2 * N)
                              : 2 * Q2 * N) | 1;
   }
-  static constexpr int ntab(int op) { return op == OP_HELM ? 2 : 1; }   // B2 (, dB2)
+  static constexpr bool helm(int op) { return op == OP_HELM || op == OP_HELM_ASM; }
+  static constexpr int ntab(int op) { return helm(op) ? 2 : 1; }   // B2 (, dB2)
   static constexpr int wave_lds(int op) { return EPW * (CS + xs(op)); }
   static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
   static constexpr int off(int p) {
@@ -103,11 +104,13 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
   using S = TriShape<P>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NP = S::NP, NM = S::NM, EPW = S::EPW;
   constexpr int LANES = S::LANES, XS = S::xs(OP), WAVE = S::wave_lds(OP);
-  constexpr bool HELM = OP == OP_HELM;
+  constexpr bool HELM = S::helm(OP);
+  constexpr bool ASM = OP == OP_HELM_ASM;                 // gathered input, scattered output
   constexpr int NIN = OP == OP_IPROD ? NP : NM;          // inputs per triangle
   constexpr int KIN = (EPW * NIN + 63) / 64;             // inputs per lane per group
   __shared__ T stab[S::ntab(OP) * Q2 * S::TS];
   __shared__ T smem[S::WPB * WAVE];
+  __shared__ double sdot[ASM ? S::WPB * 64 : 1];        // per-lane parts of x_e . (H_e x_e)
   for (int k = threadIdx.x; k < S::ntab(OP) * Q2 * NM; k += S::WPB * 64) {
     const int r = k / NM;
     stab[r * S::TS + (k - r * NM)] = tab[k];
@@ -151,6 +154,8 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
     const int ne = group_size(g);                       // live triangles
     const int64_t e = e0 + (el < ne ? el : 0);
     const bool live = row && el < ne;
+    // a converged system skips its operator (one system per triangle space)
+    if (ASM && a.elem_seg != nullptr && a.seg_done[a.elem_seg[e0]] != 0) continue;
     if constexpr (PREFETCH) {
 #pragma unroll
       for (int r = 0; r < KIN; ++r) {
@@ -170,7 +175,14 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
     } else {
       for (int k = lane; k < ne * NM; k += 64) {
         const int ee = k / NM;
-        Cw[ee * S::CS + (k - ee * NM)] = a.in[e0 * NM + k];
+        T v;
+        if constexpr (ASM) {
+          const int32_t gv = a.l2g[e0 * NM + k];
+          v = gv >= 0 ? l2g_sign(gv, a.in[l2g_dof(gv)]) : T(0);
+        } else {
+          v = a.in[e0 * NM + k];
+        }
+        Cw[ee * S::CS + (k - ee * NM)] = v;
       }
       slot_sync<64>();
     }
@@ -272,6 +284,7 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
         }
       }
       slot_sync<64>();
+      double dp = 0.0;
       if (live) {
         const T* sa = Xw + el * XS;
         for (int mm = j; mm < NM; mm += Q2) {
@@ -291,13 +304,29 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
               if constexpr (HELM) y += stab[(Q2 + jj) * S::TS + P] * sa[(Q2 + jj) * N + P];
             }
           }
+          if constexpr (ASM) dp += (double)Cw[el * S::CS + mm] * (double)y;   // x_m y_m
           Cw[el * S::CS + mm] = y;
         }
       }
+      if constexpr (ASM) sdot[wave * 64 + lane] = dp;
       slot_sync<64>();
+      if constexpr (ASM) {
+        if (live && j == 0 && a.dots) {
+          double s = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < Q2; ++jj) s += sdot[wave * 64 + lane + jj];
+          a.dots[a.dslot ? a.dslot[e] : e] = s;
+        }
+      }
       for (int k = lane; k < ne * NM; k += 64) {
         const int ee = k / NM;
-        a.out[e0 * NM + k] = Cw[ee * S::CS + (k - ee * NM)];
+        const T y = Cw[ee * S::CS + (k - ee * NM)];
+        if constexpr (ASM) {
+          const int32_t gv = a.l2g[e0 * NM + k];
+          if (gv >= 0) atomic_add(a.out + l2g_dof(gv), l2g_sign(gv, y));
+        } else {
+          a.out[e0 * NM + k] = y;
+        }
       }
       slot_sync<64>();
     }
@@ -315,13 +344,15 @@ static int64_t tri_grid(int op) {
   std::lock_guard<std::mutex> lk(mu);
   int dev = 0, cus = 0, nb = 0;
   (void)hipGetDevice(&dev);
-  const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : 2);
+  const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : op == OP_HELM ? 2 : 3);
   auto it = cached.find(key);
   if (it != cached.end()) return it->second;
   using S = TriShape<P>;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const void* fn = op == OP_BWD ? (const void*)k_tri<T, P, OP_BWD>
-                   : op == OP_IPROD ? (const void*)k_tri<T, P, OP_IPROD> : (const void*)k_tri<T, P, OP_HELM>;
+  const void* fn = op == OP_BWD     ? (const void*)k_tri<T, P, OP_BWD>
+                   : op == OP_IPROD ? (const void*)k_tri<T, P, OP_IPROD>
+                   : op == OP_HELM  ? (const void*)k_tri<T, P, OP_HELM>
+                                    : (const void*)k_tri<T, P, OP_HELM_ASM>;
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, S::WPB * 64, 0);
   const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (nb > 0 ? nb : 1) * kTriWaves;
   cached[key] = grid;
@@ -343,6 +374,9 @@ static hipError_t run_tri(const OpArgs& a) {
     case OP_BWD: hipLaunchKernelGGL((k_tri<T, P, OP_BWD>), g, b, 0, a.stream, tb, tab, d); break;
     case OP_IPROD: hipLaunchKernelGGL((k_tri<T, P, OP_IPROD>), g, b, 0, a.stream, tb, tab, d); break;
     case OP_HELM: hipLaunchKernelGGL((k_tri<T, P, OP_HELM>), g, b, 0, a.stream, tb, tab, d); break;
+    case OP_HELM_ASM:
+      hipLaunchKernelGGL((k_tri<T, P, OP_HELM_ASM>), g, b, 0, a.stream, tb, tab, d);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -366,6 +400,80 @@ hipError_t launch_tri(nk_dtype t, const OpArgs& a) {
     case 8: return run_tri_p<8>(t, a);
     case 9: return run_tri_p<9>(t, a);
     case 10: return run_tri_p<10>(t, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Diagonal of the triangle Helmholtz operator, thread per (triangle, mode),
+// scatter-added into the padded global diagonal (Dirichlet modes skipped):
+//   diag H_e[m] = sum_points ( lambda f0 phi_m^2 + f1 d1^2 + 2 f2 d1 d2 + f3 d2^2 )
+// with d1, d2 the collapsed derivatives of phi_m; the collapsed vertex is
+// evaluated as (a_0 + a_P) times its eta_2 factor, as in the operator.
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_diag_tri(const Tab<double, P + 1, P + 2> tb, const double* __restrict__ tab, int64_t nelem,
+               const double* __restrict__ fac, const double* __restrict__ lam, double lam0,
+               const int32_t* __restrict__ l2g, double* __restrict__ diag) {
+  using S = TriShape<P>;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NM = S::NM;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nelem * NM) return;
+  const int64_t e = id / NM;
+  const int m = (int)(id - e * NM);
+  const int32_t g = l2g[id];
+  if (g < 0) return;  // Dirichlet: row replaced by the identity
+  int p = 0;
+  for (int k = 1; k < N; ++k) p += (m >= S::off(k)) ? 1 : 0;
+  const double* B2 = tab;
+  const double* dB2 = tab + Q2 * NM;
+  const int64_t grp = e / S::EPW;
+  const int lane0 = (int)(e - grp * S::EPW) * Q2;
+  const double* f = fac + grp * (int64_t)(4 * Q * S::LANES) + lane0;
+  const double lm = lam ? lam[e] : lam0;
+  double s = 0.0;
+  for (int j = 0; j < Q2; ++j) {
+    const double b = B2[j * NM + m], db = dB2[j * NM + m];
+    for (int i = 0; i < Q; ++i) {
+      double av = tb.B[i * N + p], dav = tb.D[i * N + p];
+      if (m == P) {
+        av += tb.B[i * N + P];
+        dav += tb.D[i * N + P];
+      }
+      const double ph = av * b, d1 = dav * b, d2 = av * db;
+      const double* fp = f + (int64_t)i * S::LANES + j;
+      const double f0 = fp[0], f1 = fp[Q * S::LANES], f2 = fp[2 * Q * S::LANES],
+                   f3 = fp[3 * Q * S::LANES];
+      s += lm * f0 * ph * ph + f1 * d1 * d1 + 2.0 * f2 * d1 * d2 + f3 * d2 * d2;
+    }
+  }
+  unsafeAtomicAdd(diag + l2g_dof(g), s);
+}
+
+template <int P>
+static hipError_t run_diag_tri(int64_t nelem, const double* fac, const double* lam, double lam0,
+                               const int32_t* l2g, double* diag, hipStream_t st) {
+  const double* tab = tri_table<double>(P);
+  if (!tab) return hipErrorOutOfMemory;
+  const int64_t tot = nelem * TriShape<P>::NM;
+  hipLaunchKernelGGL(k_diag_tri<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     host_tab<double, P + 1, P + 2>(), tab, nelem, fac, lam, lam0, l2g, diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_tri(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                           const int32_t* l2g, double* diag, hipStream_t st) {
+  if (nelem == 0) return hipSuccess;
+  switch (P) {
+    case 1: return run_diag_tri<1>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 2: return run_diag_tri<2>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 3: return run_diag_tri<3>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 4: return run_diag_tri<4>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 5: return run_diag_tri<5>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 6: return run_diag_tri<6>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 7: return run_diag_tri<7>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 8: return run_diag_tri<8>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 9: return run_diag_tri<9>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 10: return run_diag_tri<10>(nelem, fac, lam, lam0, l2g, diag, st);
   }
   return hipErrorInvalidValue;
 }

@@ -29,7 +29,7 @@ EXPORTS = [
     "nk_last_error", "nk_version", "nk_device_count", "nk_basis_tables", "nk_space_create",
     "nk_space_create_varp", "nk_space_destroy", "nk_space_sizes", "nk_bwd_trans",
     "nk_iprod_wrt_base", "nk_helmholtz", "nk_helmholtz_weak_rhs", "nk_system_create",
-    "nk_system_create_batched", "nk_system_destroy", "nk_system_apply", "nk_assemble",
+    "nk_system_create_batched", "nk_system_create_signed", "nk_system_destroy", "nk_system_apply", "nk_assemble",
     "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
@@ -81,6 +81,7 @@ def lib():
         "nk_helmholtz_weak_rhs": (i32, [vp, vp, dbl, vp, vp, vp, vp]),
         "nk_system_create": (i32, [pp, vp, i64, vp, vp, vp, dbl, vp]),
         "nk_system_create_batched": (i32, [pp, vp, i32, vp, vp, vp, vp, vp, dbl, vp]),
+        "nk_system_create_signed": (i32, [pp, vp, i64, vp, vp, vp, vp, dbl, vp]),
         "nk_system_destroy": (i32, [vp]),
         "nk_system_apply": (i32, [vp, i32, vp, vp, vp]),
         "nk_assemble": (i32, [vp, vp, vp, vp]),
@@ -362,12 +363,19 @@ class System:
         self.nsys = nsys
 
     @classmethod
-    def create(cls, space: Space, nglobal: int, l2g, dirichlet, lam=None, lam0: float = 1.0):
+    def create(cls, space: Space, nglobal: int, l2g, dirichlet, lam=None, lam0: float = 1.0, sign=None):
+        """sign: optional int8 device tensor of +-1 per local mode (orientation)."""
         import torch
         h = ctypes.c_void_p()
-        _check(lib().nk_system_create(ctypes.byref(h), space.handle, int(nglobal),
-                                      _ptr(l2g, torch.int32, "l2g"), _ptr(dirichlet, torch.uint8, "dirichlet"),
-                                      _ptr(lam, torch.float64, "lambda"), float(lam0), _stream()))
+        if sign is None:
+            _check(lib().nk_system_create(ctypes.byref(h), space.handle, int(nglobal),
+                                          _ptr(l2g, torch.int32, "l2g"), _ptr(dirichlet, torch.uint8, "dirichlet"),
+                                          _ptr(lam, torch.float64, "lambda"), float(lam0), _stream()))
+        else:
+            _check(lib().nk_system_create_signed(ctypes.byref(h), space.handle, int(nglobal),
+                                                 _ptr(l2g, torch.int32, "l2g"), _ptr(sign, torch.int8, "sign"),
+                                                 _ptr(dirichlet, torch.uint8, "dirichlet"),
+                                                 _ptr(lam, torch.float64, "lambda"), float(lam0), _stream()))
         return cls(h.value, space, int(nglobal), 1)
 
     @classmethod

@@ -770,3 +770,107 @@ def test_triangle_mass_projection_and_laplacian(P):
     grad2 = (2 * X[0] - X[1]) ** 2 + (-X[0] + 2) ** 2
     exact = ops.wJ[0] @ grad2          # degree 2 <= 2P: the rule is exact
     assert abs(cu @ ops.laplacian_matrix(0) @ cu - exact) < 1e-12 * exact
+
+
+# ------------------------- triangle meshes: C0 assembly with orientation signs
+
+def _tri_affine_mesh(n, P, rot):
+    """Oracle operators of the affine triangle mesh of the unit square with
+    rotated local vertex orders, its signed numbering and the physical
+    coordinates of every quadrature point."""
+    Q = P + 2
+    x1r, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    J = W.tri_lattice_jacobians(n, oracle.gll(Q)[0], x1r, 0.0, rot)
+    ops = C.TriOps(P, Q, J)
+    V = W.tri_lattice_vertices(n)
+    V = np.take_along_axis(V, (np.asarray(rot)[:, None] + np.arange(3)[None, :]) % 3, axis=1)
+    xy = np.stack([V % (n + 1), V // (n + 1)], axis=-1) / n          # (E, 3, 2)
+    x1, x2 = C.xi_of_eta(ops.e1, ops.e2)
+    X = (xy[:, 0, None, :] * (-(x1 + x2) / 2)[None, :, None] + xy[:, 1, None, :] * ((1 + x1) / 2)[None, :, None]
+         + xy[:, 2, None, :] * ((1 + x2) / 2)[None, :, None])        # (E, nq, 2)
+    return ops, V, X
+
+
+def _edge_traces(P, V, xloc, s):
+    """Values of each element's expansion along its three edges at the global
+    edge parameters s (edges run from the lower to the higher vertex id)."""
+    out = {}
+    for e in range(V.shape[0]):
+        A_, B_, C_ = V[e]
+        for a_, b_, which in ((A_, B_, "AB"), (A_, C_, "AC"), (B_, C_, "BC")):
+            t = s if a_ < b_ else -s
+            if which == "AB":
+                e1, e2 = t, -np.ones_like(t)
+            elif which == "AC":
+                e1, e2 = -np.ones_like(t), t
+            else:
+                e1, e2 = np.ones_like(t), t
+            Phi, _, _ = C.tri_basis(P, e1, e2)
+            out.setdefault((min(a_, b_), max(a_, b_)), []).append(Phi @ xloc[e])
+    return out
+
+
+@pytest.mark.parametrize("P", [2, 4, 5])
+def test_signed_triangle_numbering_is_continuous_across_edges(P):
+    """A random global vector, gathered with the signs, gives element
+    expansions that agree along every shared edge (the traces are continuous);
+    dropping the signs breaks continuity from P = 3 on (bubble k = 2 is the
+    first that changes sign when its edge is traversed the other way)."""
+    n = 3
+    E = 2 * n * n
+    rot = W.tri_rotations(11 + P, E)
+    l2g, sign, ng, _ = W.tri_lattice_l2g(n, P, rot)
+    V = np.take_along_axis(W.tri_lattice_vertices(n), (rot[:, None] + np.arange(3)[None, :]) % 3, axis=1)
+    x = np.random.default_rng(P).uniform(-1, 1, ng)
+    s = np.linspace(-0.9, 0.8, 7)
+    worst = 0.0
+    for vals in _edge_traces(P, V, oracle.gather(x, l2g, sign), s).values():
+        if len(vals) == 2:
+            worst = max(worst, np.abs(vals[0] - vals[1]).max())
+    assert worst < 1e-12
+    if P < 3:
+        return
+    bad = 0.0
+    for vals in _edge_traces(P, V, oracle.gather(x, l2g), s).values():
+        if len(vals) == 2:
+            bad = max(bad, np.abs(vals[0] - vals[1]).max())
+    assert bad > 1e-3
+
+
+@pytest.mark.parametrize("P", [4, 6])
+def test_signed_triangle_projection_is_exact_for_degree_P(P):
+    """Global L2 projection (assembled mass matrix with signs) reproduces a
+    polynomial of total degree P on the affine mesh; without the signs it
+    does not."""
+    n = 3
+    E = 2 * n * n
+    rot = W.tri_rotations(21 + P, E)
+    ops, V, X = _tri_affine_mesh(n, P, rot)
+    l2g, sign, ng, _ = W.tri_lattice_l2g(n, P, rot)
+    u = X[..., 0] ** 3 * X[..., 1] - 2 * X[..., 0] * X[..., 1] ** 2 + 0.5 * X[..., 0] ** 4 + X[..., 1]
+    mats = [ops.mass_matrix(e) for e in range(E)]
+    none = np.zeros(ng, np.uint8)
+    for sg, ok in ((sign, True), (None, False)):
+        b = oracle.assemble_vector(ops.iprod(u), l2g, ng, sg)
+        x = oracle.direct_solve(mats, l2g, ng, none, b, sg)
+        err = np.abs(ops.bwd(oracle.gather(x, l2g, sg)) - u).max()
+        assert (err < 1e-11) == ok, (sg is None, err)
+
+
+@pytest.mark.parametrize("P", [4, 5])
+def test_signed_triangle_helmholtz_solve_is_exact(P):
+    """-lap u + u = f on the unit square, u = x(1-x)y(1-y) (zero on the
+    boundary), weak right-hand side integral f phi_m, Dirichlet boundary
+    DOFs: the assembled solve with signs reproduces u at every point."""
+    n = 3
+    E = 2 * n * n
+    rot = W.tri_rotations(31 + P, E)
+    ops, V, X = _tri_affine_mesh(n, P, rot)
+    l2g, sign, ng, dirichlet = W.tri_lattice_l2g(n, P, rot)
+    x_, y_ = X[..., 0], X[..., 1]
+    u = x_ * (1 - x_) * y_ * (1 - y_)
+    f = 2 * y_ * (1 - y_) + 2 * x_ * (1 - x_) + u
+    mats = [ops.helmholtz_matrix(e) for e in range(E)]
+    b = oracle.assemble_vector(ops.iprod(f), l2g, ng, sign)
+    x = oracle.direct_solve(mats, l2g, ng, dirichlet, b, sign)
+    assert np.abs(ops.bwd(oracle.gather(x, l2g, sign)) - u).max() < 1e-12

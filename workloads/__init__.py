@@ -286,14 +286,32 @@ def varp_lattice_l2g(shape, orders):
     return perm, l2g, nglobal, dirichlet
 
 
-def tri_lattice_jacobians(n: int, e1, e2, amp: float = 0.05):
-    """Jacobians of a triangle mesh of the unit square: an n x n lattice of
-    squares, each split along its diagonal into the lower-right triangle
-    (v0, v1, v2) = (x0, x0 + h e_x, x0 + h e_x + h e_y) and the upper-left one
-    (x0, x0 + h(e_x + e_y), x0 + h e_y), both counter-clockwise, composed with
-    the curving map x' = x + a s(x) s(y), y' = y + a/2 s(x) s(y), s(t) =
-    sin(2 pi t).  The affine reference map is x = v0 (-(xi_1 + xi_2)/2)
-    + v1 (1 + xi_1)/2 + v2 (1 + xi_2)/2 evaluated at the collapsed points
+def tri_lattice_vertices(n: int):
+    """Vertex ids (lattice point i + (n+1) j) of the triangle mesh of the unit
+    square: square k = i + n j gives element 2k = (v00, v10, v11) and element
+    2k+1 = (v00, v11, v01), both counter-clockwise.  Returns (E, 3) int64."""
+    k = np.arange(n * n)
+    i, j = k % n, k // n
+    v00, v10 = i + (n + 1) * j, i + 1 + (n + 1) * j
+    v11, v01 = i + 1 + (n + 1) * (j + 1), i + (n + 1) * (j + 1)
+    out = np.empty((2 * n * n, 3), np.int64)
+    out[0::2] = np.stack([v00, v10, v11], axis=1)
+    out[1::2] = np.stack([v00, v11, v01], axis=1)
+    return out
+
+
+def tri_rotations(seed_: int, nelem: int) -> np.ndarray:
+    """Seeded cyclic rotation r in {0, 1, 2} of each triangle's local vertex
+    order: local (A, B, C) = (v_r, v_{r+1}, v_{r+2}) (orientation kept)."""
+    return np.random.default_rng(seed_).integers(0, 3, size=nelem)
+
+
+def tri_lattice_jacobians(n: int, e1, e2, amp: float = 0.05, rot=None):
+    """Jacobians of the triangle mesh of the unit square (tri_lattice_vertices),
+    composed with the curving map x' = x + a s(x) s(y), y' = y + a/2 s(x) s(y),
+    s(t) = sin(2 pi t).  With local vertices (A, B, C) (rotated by rot, if
+    given), the affine reference map is x = A (-(xi_1 + xi_2)/2)
+    + B (1 + xi_1)/2 + C (1 + xi_2)/2 evaluated at the collapsed points
     (eta_1, eta_2) (xi_1 = (1 + eta_1)(1 - eta_2)/2 - 1, xi_2 = eta_2).
     Returns J[E, c, a, q] = d x'_c / d xi_a with q = i + Q j over (e1, e2)."""
     e1 = np.asarray(e1, np.float64)
@@ -304,10 +322,15 @@ def tri_lattice_jacobians(n: int, e1, e2, amp: float = 0.05):
     x2 = E2
     h = 1.0 / n
     k = np.arange(n * n)
-    V0 = np.stack([(k % n) * h, (k // n) * h], axis=1)                     # (n^2, 2)
+    V0s = np.stack([(k % n) * h, (k // n) * h], axis=1)                    # (n^2, 2)
     out = np.empty((2 * n * n, 2, 2, x1.size))
     for t, (d1, d2) in enumerate((([h, 0], [h, h]), ([h, h], [0, h]))):
-        V1, V2 = V0 + d1, V0 + d2
+        corners = np.stack([V0s, V0s + d1, V0s + d2], axis=1)               # (n^2, 3, 2)
+        if rot is not None:
+            r = np.asarray(rot)[t::2]
+            idx = (r[:, None] + np.arange(3)[None, :]) % 3
+            corners = np.take_along_axis(corners, idx[:, :, None], axis=1)
+        V0, V1, V2 = corners[:, 0], corners[:, 1], corners[:, 2]
         A = np.stack([(V1 - V0) / 2, (V2 - V0) / 2], axis=2)                # (n^2, c, a)
         X = (V0[:, :, None] * (-(x1 + x2) / 2) + V1[:, :, None] * (1 + x1) / 2
              + V2[:, :, None] * (1 + x2) / 2)                               # (n^2, 2, nq)
@@ -320,6 +343,70 @@ def tri_lattice_jacobians(n: int, e1, e2, amp: float = 0.05):
         Wm[:, 1, 1] = 1 + amp / 2 * sx * cy
         out[t::2] = np.einsum("ecbq,eba->ecaq", Wm, A)
     return out
+
+
+def tri_lattice_l2g(n: int, P: int, rot=None):
+    """C0 numbering of the triangle mesh (tri_lattice_vertices) for the
+    collapsed modal basis in its mode order (p = 0: q = 0 vertex A, q = 1..P-1
+    edge AC, q = P vertex C; 0 < p < P: q = 0 edge AB, q >= 1 interior; p = P:
+    q = 0 vertex B, q >= 1 edge BC), with orientation signs.  Global DOFs:
+    mesh vertices, then P-1 per mesh edge, then the interior modes of each
+    triangle.  A mesh edge runs from its lower to its higher vertex id; a
+    triangle traversing it the other way sees its k-th edge bubble (k =
+    1..P-1) as (-1)^(k-1) times the global one, the parity of the 1-D
+    bubbles (1-x)(1+x)/4 P^{1,1}_{k-1}(x).  Dirichlet: vertices and edges on
+    the boundary of the unit square.
+    Returns (l2g (E, nm) int32, sign (E, nm) int8, nglobal, dirichlet uint8)."""
+    V = tri_lattice_vertices(n)
+    E = V.shape[0]
+    if rot is not None:
+        r = np.asarray(rot)
+        V = np.take_along_axis(V, (r[:, None] + np.arange(3)[None, :]) % 3, axis=1)
+    nv = (n + 1) ** 2
+    nb = max(P - 1, 0)
+    nint = max((P - 1) * (P - 2) // 2, 0)
+    edges = {}
+    for a_, b_ in np.concatenate([V[:, [0, 1]], V[:, [0, 2]], V[:, [1, 2]]]):
+        key = (min(a_, b_), max(a_, b_))
+        if key not in edges:
+            edges[key] = len(edges)
+    ne = len(edges)
+    nglobal = nv + ne * nb + E * nint
+    modes = [(0, q) for q in range(P + 1)] + [(p, q) for p in range(1, P) for q in range(P - p)] \
+        + [(P, q) for q in range(P)]
+    l2g = np.empty((E, len(modes)), np.int64)
+    sign = np.ones((E, len(modes)), np.int8)
+    for e in range(E):
+        A_, B_, C_ = V[e]
+        def edge(a_, b_, k):
+            g = nv + edges[(min(a_, b_), max(a_, b_))] * nb + (k - 1)
+            return g, (1 if a_ < b_ or k % 2 == 1 else -1)
+        it = 0
+        for m, (p, q) in enumerate(modes):
+            if p == 0 and q == 0:
+                g, s = A_, 1
+            elif p == 0 and q == P:
+                g, s = C_, 1
+            elif p == 0:
+                g, s = edge(A_, C_, q)
+            elif p == P and q == 0:
+                g, s = B_, 1
+            elif p == P:
+                g, s = edge(B_, C_, q)
+            elif q == 0:
+                g, s = edge(A_, B_, p)
+            else:
+                g, s = nv + ne * nb + e * nint + it, 1
+                it += 1
+            l2g[e, m], sign[e, m] = g, s
+    on_bd = lambda v: (v % (n + 1) == 0) | (v % (n + 1) == n) | (v // (n + 1) == 0) | (v // (n + 1) == n)
+    dirichlet = np.zeros(nglobal, np.uint8)
+    dirichlet[:nv][on_bd(np.arange(nv))] = 1
+    for (a_, b_), k in edges.items():
+        ia, ja, ib, jb = a_ % (n + 1), a_ // (n + 1), b_ % (n + 1), b_ // (n + 1)
+        if (ia == ib and ia in (0, n)) or (ja == jb and ja in (0, n)):
+            dirichlet[nv + k * nb: nv + (k + 1) * nb] = 1
+    return l2g.astype(np.int32), sign, nglobal, dirichlet
 
 
 # ----------------------------------------------------------- draws
