@@ -26,6 +26,19 @@ following readings are taken (each is pinned by tests/test_oracle.py):
   points of the weight (1 - eta_2) in eta_2 (eta_2 = -1 included, the
   collapsed vertex eta_2 = 1 excluded); dxi = (1 - eta_2)/2 deta, the factor
   (1 - eta_2) being the Radau weight.  Point q = i + Q j (eta_1 fastest).
+
+Tetrahedra (the 3-D collapsed shape of section 2.1) are read the same way:
+reference tetrahedron {xi_a >= -1, xi_1 + xi_2 + xi_3 <= -1}; collapsed
+coordinates eta_1 = 2 (1 + xi_1)/(-xi_2 - xi_3) - 1, eta_2 = 2 (1 + xi_2)/
+(1 - xi_3) - 1, eta_3 = xi_3.  Every mode is a triangle mode T_t(eta_1, eta_2)
+of the order-P triangle above, of total degree s_t, times an eta_3 factor:
+((1-eta_3)/2)^s_t for r = 0 (the modes of face ABC) and ((1-eta_3)/2)^s_t
+(1+eta_3)/2 P^{2 s_t - 1, 1}_{r-1}(eta_3) for 1 <= r <= P - s_t (rising edge,
+face and interior modes), plus the top vertex D = (1+eta_3)/2.  Coefficients
+are grouped by triangle mode (in triangle order, r fastest), D last:
+(P+1)(P+2)(P+3)/6 modes spanning total degree <= P.  Quadrature: Q GLL
+points in eta_1, Q-1 Gauss-Radau points of the weight (1-eta_2) in eta_2 and
+Q-1 of the weight (1-eta_3)^2 in eta_3; point q = i + Q (j + (Q-1) k).
 """
 from __future__ import annotations
 
@@ -151,6 +164,146 @@ class TriOps:
         L = np.zeros((self.Bt.shape[1],) * 2)
         for a in range(2):
             for b in range(2):
+                L += self.Dt[a].T @ ((c * self.G[e, :, a, b])[:, None] * self.Dt[b])
+        return L
+
+    def helmholtz_matrix(self, e):
+        return self.laplacian_matrix(e) + self.lam[e] * self.mass_matrix(e)
+
+    def bwd(self, coeffs):
+        return np.asarray(coeffs, np.float64) @ self.Bt.T
+
+    def iprod(self, f):
+        return (self.wJ * np.asarray(f, np.float64)) @ self.Bt
+
+    def helmholtz(self, x):
+        x = np.asarray(x, np.float64)
+        return np.stack([self.helmholtz_matrix(e) @ x[e] for e in range(self.nelem)])
+
+    def fwd(self, f):
+        rhs = self.iprod(f)
+        return np.stack([np.linalg.solve(self.mass_matrix(e), rhs[e]) for e in range(self.nelem)])
+
+
+# ------------------------------------------------------------- tetrahedra
+
+def tri_degree(P: int, p: int, q: int) -> int:
+    """Total polynomial degree of triangle mode (p, q)."""
+    if (p == 0 or p == P) and q == 0:
+        return 1                  # vertices A, B
+    if p == 0 and q == P:
+        return 1                  # vertex C
+    if p == 0 or p == P:
+        return q + 1              # edges AC, BC: 1-D bubble q
+    if q == 0:
+        return p + 1              # edge AB
+    return p + q + 1              # interior
+
+
+def tet_modes(P: int):
+    """List of (t, s, r) in coefficient order: t the index of the triangle
+    mode in tri_modes(P), s its degree, r = 0..P-s; the top vertex D last as
+    (-1, 0, 1)."""
+    out = []
+    for t, (p, q) in enumerate(tri_modes(P)):
+        s = tri_degree(P, p, q)
+        out += [(t, s, r) for r in range(P - s + 1)]
+    return out + [(-1, 0, 1)]
+
+
+def _c_funcs(s: int, r: int, z):
+    """(value, derivative) of the eta_3 factor of a tet mode built on a
+    triangle mode of degree s."""
+    z = np.asarray(z, np.float64)
+    a = (1 - z) / 2
+    f = a ** s
+    df = -s / 2 * a ** (s - 1) if s > 0 else np.zeros_like(z)
+    if r == 0:
+        return f, df
+    g = (1 + z) / 2
+    J = jacobi_p(r - 1, 2 * s - 1, 1, z)
+    dJ = ((r - 1 + 2 * s + 1) / 2 * jacobi_p(r - 2, 2 * s, 2, z)) if r >= 2 else np.zeros_like(z)
+    return f * g * J, df * g * J + f * 0.5 * J + f * g * dJ
+
+
+def tet_basis(P: int, e1, e2, e3):
+    """Basis values and collapsed-coordinate derivatives at points (e1, e2,
+    e3): (Phi, dPhi/deta_1, dPhi/deta_2, dPhi/deta_3), each (npts, nmodes)."""
+    e3 = np.asarray(e3, np.float64)
+    T, T1, T2 = tri_basis(P, e1, e2)
+    modes = tet_modes(P)
+    Phi = np.zeros((e3.size, len(modes)))
+    D1, D2, D3 = np.zeros_like(Phi), np.zeros_like(Phi), np.zeros_like(Phi)
+    for m, (t, s, r) in enumerate(modes):
+        if t < 0:                       # top vertex D: no eta_1, eta_2 factor
+            Phi[:, m], D3[:, m] = (1 + e3) / 2, 0.5
+            continue
+        c, dc = _c_funcs(s, r, e3)
+        Phi[:, m] = T[:, t] * c
+        D1[:, m] = T1[:, t] * c
+        D2[:, m] = T2[:, t] * c
+        D3[:, m] = T[:, t] * dc
+    return Phi, D1, D2, D3
+
+
+def tet_points(Q: int):
+    """Collapsed quadrature: eta_1 (GLL, Q), eta_2 (Radau of (1-x), Q-1),
+    eta_3 (Radau of (1-x)^2, Q-1) and the weights of dxi at every point
+    q = i + Q (j + (Q-1) k)."""
+    x1, w1 = gll(Q)
+    x2, w2 = gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    x3, w3 = gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    n2 = Q - 1
+    E1 = np.tile(x1, n2 * n2)
+    E2 = np.tile(np.repeat(x2, Q), n2)
+    E3 = np.repeat(x3, Q * n2)
+    # dxi = (1-eta_2)/2 ((1-eta_3)/2)^2 deta: the Radau weights carry (1-eta_2), (1-eta_3)^2
+    W = (np.outer(w3 / 4, np.outer(w2 / 2, w1).ravel())).ravel()
+    return E1, E2, E3, W
+
+
+def xi_of_eta3(e1, e2, e3):
+    e1, e2, e3 = (np.asarray(v, np.float64) for v in (e1, e2, e3))
+    return (1 + e1) * (1 - e2) * (1 - e3) / 4 - 1, (1 + e2) * (1 - e3) / 2 - 1, e3
+
+
+class TetOps:
+    """Dense elemental operators of straight- or curved-sided tetrahedra of
+    order P with the collapsed quadrature of Q points.  J[e, c, a, q] =
+    d x_c / d xi_a at the quadrature points."""
+
+    def __init__(self, P, Q, J, kappa=None, lam=1.0):
+        self.P, self.Q = int(P), int(Q)
+        self.e1, self.e2, self.e3, self.W = tet_points(self.Q)
+        self.Bt, D1, D2, D3 = tet_basis(self.P, self.e1, self.e2, self.e3)
+        e1, e2, e3 = self.e1, self.e2, self.e3
+        # d eta_b / d xi_a of the collapsed map, then the chain rule
+        g = (2.0 / ((1 - e2) * (1 - e3)))[:, None]
+        c1 = (1 + e1)[:, None]
+        dxi1 = 2 * g * D1
+        dxi2 = c1 * g * D1 + (2.0 / (1 - e3))[:, None] * D2
+        dxi3 = c1 * g * D1 + ((1 + e2) / (1 - e3))[:, None] * D2 + D3
+        self.Dt = [dxi1, dxi2, dxi3]
+        Jm = np.moveaxis(np.asarray(J, np.float64), -1, 1)          # (E, nq, c, a)
+        self.detJ = np.linalg.det(Jm)
+        Ji = np.linalg.inv(Jm)
+        self.G = np.einsum("eqac,eqbc->eqab", Ji, Ji)
+        E = self.detJ.shape[0]
+        self.nelem = E
+        nq = self.W.size
+        self.kappa = np.ones((E, nq)) if kappa is None else np.asarray(kappa, np.float64).reshape(E, nq)
+        lam = np.asarray(lam, np.float64)
+        self.lam = np.broadcast_to(lam, (E,)).copy() if lam.ndim == 0 else lam.reshape(E).copy()
+        self.wJ = self.W[None, :] * self.detJ
+
+    def mass_matrix(self, e):
+        return self.Bt.T @ (self.wJ[e][:, None] * self.Bt)
+
+    def laplacian_matrix(self, e):
+        c = self.wJ[e] * self.kappa[e]
+        L = np.zeros((self.Bt.shape[1],) * 2)
+        for a in range(3):
+            for b in range(3):
                 L += self.Dt[a].T @ ((c * self.G[e, :, a, b])[:, None] * self.Dt[b])
         return L
 

@@ -874,3 +874,137 @@ def test_signed_triangle_helmholtz_solve_is_exact(P):
     b = oracle.assemble_vector(ops.iprod(f), l2g, ng, sign)
     x = oracle.direct_solve(mats, l2g, ng, dirichlet, b, sign)
     assert np.abs(ops.bwd(oracle.gather(x, l2g, sign)) - u).max() < 1e-12
+
+
+# ------------------------------------------------- collapsed-coordinate tetrahedra (2.1)
+
+def _tet_integral(a, b, c):
+    """Closed form of the integral of xi_1^a xi_2^b xi_3^c over the reference
+    tetrahedron (shifted to u = 1 + xi, u >= 0, u_1 + u_2 + u_3 <= 2: a
+    Dirichlet integral 2^(i+j+k+3) i! j! k! / (i+j+k+3)!)."""
+    s = 0.0
+    for i in range(a + 1):
+        for j in range(b + 1):
+            for k in range(c + 1):
+                s += (comb(a, i) * comb(b, j) * comb(c, k) * (-1) ** (a - i + b - j + c - k)
+                      * 2.0 ** (i + j + k + 3) * factorial(i) * factorial(j) * factorial(k)
+                      / factorial(i + j + k + 3))
+    return s
+
+
+def test_gauss_radau_jacobi_weight_two_exactness():
+    for n in (2, 3, 6):
+        x, w = C.gauss_radau_jacobi(n, 2.0, 0.0)
+        for k in range(2 * n):
+            # int_{-1}^{1} x^k (1-x)^2 dx = I_k - 2 I_{k+1} + I_{k+2}
+            I = lambda j: (2.0 / (j + 1)) if j % 2 == 0 else 0.0
+            exact = I(k) - 2 * I(k + 1) + I(k + 2)
+            err = abs(w @ x ** k - exact)
+            assert (err < 1e-13) == (k <= 2 * n - 2), (n, k, err)
+
+
+@pytest.mark.parametrize("P", [1, 2, 4])
+def test_tetrahedron_quadrature_integrates_degree_2P(P):
+    Q = P + 2
+    e1, e2, e3, W = C.tet_points(Q)
+    x1, x2, x3 = C.xi_of_eta3(e1, e2, e3)
+    assert abs(W.sum() - 4.0 / 3.0) < 1e-14
+    for a in range(2 * P + 1):
+        for b in range(2 * P + 1 - a):
+            for c in range(2 * P + 1 - a - b):
+                got = W @ (x1 ** a * x2 ** b * x3 ** c)
+                assert abs(got - _tet_integral(a, b, c)) < 1e-12, (a, b, c)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 5])
+def test_tetrahedron_basis_spans_total_degree_P(P):
+    """(P+1)(P+2)(P+3)/6 independent modes that reproduce every monomial of
+    total degree <= P (L2 projection exact), but not every one of degree P+1."""
+    Q = P + 2
+    e1, e2, e3, W = C.tet_points(Q)
+    x1, x2, x3 = C.xi_of_eta3(e1, e2, e3)
+    Phi, _, _, _ = C.tet_basis(P, e1, e2, e3)
+    assert Phi.shape[1] == (P + 1) * (P + 2) * (P + 3) // 6
+    M = Phi.T @ (W[:, None] * Phi)
+    np.linalg.cholesky(M)
+    for a in range(P + 1):
+        for b in range(P + 1 - a):
+            for c in range(P + 1 - a - b):
+                f = x1 ** a * x2 ** b * x3 ** c
+                cf = np.linalg.solve(M, Phi.T @ (W * f))
+                assert np.abs(Phi @ cf - f).max() < 1e-11, (a, b, c)
+    worst = 0.0                      # some monomial of degree P+1 is not reproduced
+    for a in range(P + 2):
+        for b in range(P + 2 - a):
+            f = x1 ** a * x2 ** b * x3 ** (P + 1 - a - b)
+            cf = np.linalg.solve(M, Phi.T @ (W * f))
+            worst = max(worst, np.abs(Phi @ cf - f).max())
+    assert worst > 1e-6
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_tetrahedron_vertex_modes_and_bottom_face(P):
+    """The four vertex modes are 1 at their vertex and 0 at the other three,
+    every other mode vanishes at all four vertices, the vertex modes sum to 1,
+    and on face ABC (eta_3 = -1) the r = 0 modes are the triangle basis while
+    all rising modes and D vanish."""
+    modes = C.tet_modes(P)
+    tri = C.tri_modes(P)
+    verts = {"A": (-1.0, -1.0, -1.0), "B": (1.0, -1.0, -1.0), "C": (0.3, 1.0, -1.0), "D": (0.3, -0.2, 1.0)}
+    vidx = {"A": modes.index((tri.index((0, 0)), 1, 0)), "B": modes.index((tri.index((P, 0)), 1, 0)),
+            "C": modes.index((tri.index((0, P)), 1, 0)), "D": len(modes) - 1}
+    for name, (a, b, c) in verts.items():
+        Phi, _, _, _ = C.tet_basis(P, np.array([a]), np.array([b]), np.array([c]))
+        expect = np.zeros(len(modes))
+        expect[vidx[name]] = 1.0
+        np.testing.assert_allclose(Phi[0], expect, atol=1e-13)
+    rng = np.random.default_rng(3)
+    e1, e2, e3 = rng.uniform(-1, 1, (3, 20))
+    Phi, _, _, _ = C.tet_basis(P, e1, e2, e3)
+    np.testing.assert_allclose(Phi[:, list(vidx.values())].sum(axis=1), 1.0, atol=1e-13)
+    PhiB, _, _, _ = C.tet_basis(P, e1, e2, -np.ones(20))
+    T, _, _ = C.tri_basis(P, e1, e2)
+    for m, (t, s, r) in enumerate(modes):
+        if t >= 0 and r == 0:
+            np.testing.assert_allclose(PhiB[:, m], T[:, t], atol=1e-13)
+        else:
+            np.testing.assert_allclose(PhiB[:, m], 0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_tetrahedron_projection_gradient_and_laplacian(P):
+    """On a sheared affine tetrahedron: M SPD, 1^T M 1 = volume, FwdTrans o
+    BwdTrans = I, L 1 = 0, the xi-gradient of the basis (chain rule through
+    the collapsed map) reproduces the gradient of a physical polynomial, and
+    the stiffness form of that polynomial equals the exact integral of its
+    squared gradient."""
+    Q = P + 2
+    A = np.array([[0.9, 0.2, -0.1], [0.1, 1.1, 0.3], [-0.2, 0.05, 0.8]])
+    nq = Q * (Q - 1) ** 2
+    J = np.broadcast_to(A[None, :, :, None], (1, 3, 3, nq)).copy()
+    ops = C.TetOps(P, Q, J, lam=0.0)
+    M = ops.mass_matrix(0)
+    np.linalg.cholesky(M)
+    modes = C.tet_modes(P)
+    tri = C.tri_modes(P)
+    one = np.zeros(len(modes))
+    for v in ((0, 0), (P, 0), (0, P)):
+        one[modes.index((tri.index(v), 1, 0))] = 1.0
+    one[-1] = 1.0
+    vol = abs(np.linalg.det(A)) * 4.0 / 3.0
+    assert abs(one @ M @ one - vol) < 1e-13
+    c = np.random.default_rng(5).uniform(-1, 1, (1, len(modes)))
+    np.testing.assert_allclose(ops.fwd(ops.bwd(c)), c, atol=1e-9)
+    np.testing.assert_allclose(ops.laplacian_matrix(0) @ one, 0.0, atol=1e-12)
+    xr = np.stack(C.xi_of_eta3(ops.e1, ops.e2, ops.e3))
+    X = A @ xr
+    x, y, z = X
+    u = x * y - 0.5 * z ** 2 + 2 * x
+    grad = np.stack([y + 2, x, -z])
+    cu = ops.fwd(u[None])[0]
+    np.testing.assert_allclose(ops.bwd(cu[None])[0], u, atol=1e-12)
+    # reference gradient of the expansion, mapped to physical: grad_x = A^{-T} grad_xi
+    gxi = np.stack([ops.Dt[a] @ cu for a in range(3)])
+    np.testing.assert_allclose(np.linalg.solve(A.T, gxi), grad, atol=1e-11)
+    exact = ops.wJ[0] @ (grad ** 2).sum(axis=0)
+    assert abs(cu @ ops.laplacian_matrix(0) @ cu - exact) < 1e-12 * exact
