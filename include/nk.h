@@ -153,6 +153,31 @@ nk_status nk_tri_points(int Q, double* eta1, double* w1, double* eta2, double* w
 nk_status nk_space_create_tri(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
                               const double* kappa, void* stream);
 
+/* Collapsed-coordinate tetrahedra (section 2.1: the tetrahedron reached from
+ * the hexahedron by collapsing two directions, eta_1 = 2(1+xi_1)/(-xi_2-xi_3)
+ * - 1, eta_2 = 2(1+xi_2)/(1-xi_3) - 1, eta_3 = xi_3 on the reference
+ * tetrahedron xi_a >= -1, xi_1 + xi_2 + xi_3 <= -1).  Quadrature: Q GLL points
+ * in eta_1, Q-1 Gauss-Radau points of the weight (1 - eta_2) in eta_2 and Q-1
+ * of the weight (1 - eta_3)^2 in eta_3 (-1 included in both); point
+ * q = i + Q (j + (Q-1) k).  nk_tet_points returns them (host arrays of Q, Q,
+ * Q-1 (x4) doubles; the Radau weights include their weight functions).
+ * Modes ((P+1)(P+2)(P+3)/6 per element): each triangle mode t of the order-P
+ * triangle (nk_space_create_tri's order), of total degree s, times
+ * ((1-eta_3)/2)^s for r = 0 and ((1-eta_3)/2)^s (1+eta_3)/2
+ * P^{2s-1,1}_{r-1}(eta_3) for 1 <= r <= P - s, grouped by t with r fastest;
+ * the top vertex (1+eta_3)/2 last.
+ * nk_space_create_tet: nelem tetrahedra of order P (1..10, Q = P + 2); jac:
+ * device [E][3][3][Q(Q-1)^2] FP64, jac[e][c][a][q] = d x_c / d xi_a at the
+ * points; kappa: device [E][Q(Q-1)^2] or NULL.  Such a space supports
+ * nk_bwd_trans, nk_iprod_wrt_base and nk_helmholtz (coefficients [E][nmodes],
+ * points [E][Q(Q-1)^2]); other calls, systems included, return
+ * NK_EUNSUPPORTED.  A non-positive Jacobian determinant or kappa returns
+ * NK_EINVAL. */
+nk_status nk_tet_points(int Q, double* eta1, double* w1, double* eta2, double* w2, double* eta3,
+                        double* w3);
+nk_status nk_space_create_tet(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                              const double* kappa, void* stream);
+
 /* Sizes of a space: total elements, coefficients (sum n^d) and points
  * (sum Q^d).  Any output may be NULL. */
 nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints);

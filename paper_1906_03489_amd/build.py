@@ -26,7 +26,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wno-unused-c
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 SOURCES = [("api.cpp", []), ("basis.cpp", []), ("geom.hip", []), ("cg.hip", []),
-           ("varp.hip", []), ("ops2d.hip", []), ("mfma.hip", []), ("deriv.hip", []), ("tri.hip", [])] + \
+           ("varp.hip", []), ("ops2d.hip", []), ("mfma.hip", []), ("deriv.hip", []), ("tri.hip", []),
+           ("tet.hip", [])] + \
           [("ops3d_inst.hip", [f"-DNK_PSET={k}"]) for k in range(7)]
 
 

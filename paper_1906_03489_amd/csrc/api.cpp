@@ -448,6 +448,72 @@ nk_status nk_space_create_tri(nk_space* out, int64_t nelem, int P, int Q, const 
   return NK_OK;
 }
 
+nk_status nk_tet_points(int Q, double* eta1, double* w1, double* eta2, double* w2, double* eta3,
+                        double* w3) {
+  if (Q < 3 || Q > kMaxP + 2 || !eta1 || !w1 || !eta2 || !w2 || !eta3 || !w3)
+    return fail(NK_EINVAL, "need 3 <= Q <= 12 and non-NULL outputs");
+  tet_points(Q, eta1, w1, eta2, w2, eta3, w3);
+  return NK_OK;
+}
+
+nk_status nk_space_create_tet(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                              const double* kappa, void* stream) {
+  if (!out) return fail(NK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nelem < 0) return fail(NK_EINVAL, "nelem must be >= 0");
+  if (P < 1 || P > kMaxP || Q != P + 2)
+    return fail(NK_EUNSUPPORTED, "compiled tetrahedron orders: 1 <= P <= 10 with Q = P + 2");
+  const int64_t NP = (int64_t)Q * (Q - 1) * (Q - 1), NM = (int64_t)(P + 1) * (P + 2) * (P + 3) / 6;
+  if (nelem > 0 && !jac) return fail(NK_EINVAL, "jac is NULL");
+  NK_CHECK(check_buf(jac, (size_t)nelem * 9 * NP * 8, "jac"));
+  if (kappa) NK_CHECK(check_buf(kappa, (size_t)nelem * NP * 8, "kappa"));
+  NK_CHECK(check_device());
+  hipStream_t st = (hipStream_t)stream;
+  nk_space s = new nk_space_s();
+  s->dim = 3;
+  s->shape = 2;
+  (void)hipGetDevice(&s->device);
+  Group G;
+  G.P = P;
+  G.Q = Q;
+  G.n = P + 1;
+  G.nelem = nelem;
+  s->groups.push_back(G);
+  s->nelem = nelem;
+  s->ncoeff = nelem * NM;
+  s->npoint = nelem * NP;
+  s->nfac = nelem * 7 * NP;
+  auto cleanup = [&](nk_status stt) {
+    space_free(s);
+    return stt;
+  };
+  hipError_t e;
+  if ((e = dmalloc(&s->fac64, s->nfac)) || (e = dmalloc(&s->fac32, s->nfac)))
+    return cleanup(hip_fail(e, "hipMalloc"));
+  std::vector<double> pts(2 * Q + 4 * (Q - 1));
+  double* p = pts.data();
+  tet_points(Q, p, p + Q, p + 2 * Q, p + 2 * Q + (Q - 1), p + 2 * Q + 2 * (Q - 1),
+             p + 2 * Q + 3 * (Q - 1));
+  int* d_bad = nullptr;
+  double* d_pts = nullptr;
+  if ((e = dmalloc(&d_bad, 1)) || (e = dmalloc(&d_pts, pts.size()))) {
+    dfree(d_bad);
+    return cleanup(hip_fail(e, "hipMalloc"));
+  }
+  int bad = 0;
+  if (!(e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) &&
+      !(e = hipMemcpyAsync(d_pts, pts.data(), pts.size() * 8, hipMemcpyHostToDevice, st)) &&
+      !(e = launch_geom_tet(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)) &&
+      !(e = hipStreamSynchronize(st)))
+    e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
+  dfree(d_bad);
+  dfree(d_pts);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "tetrahedron space setup"));
+  if (bad) return cleanup(fail(NK_EINVAL, "non-positive Jacobian determinant or kappa"));
+  *out = s;
+  return NK_OK;
+}
+
 nk_status nk_space_destroy(nk_space s) {
   if (!s) return fail(NK_EINVAL, "space is NULL");
   (void)hipDeviceSynchronize();
@@ -477,8 +543,8 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
   if (lam) NK_CHECK(check_buf(lam, s->nelem * 8, "lambda"));
   if (op == OP_RHS) NK_CHECK(check_buf(in2, s->npoint * d * 8, "du"));
   if (in == out && in != nullptr) return fail(NK_EINVAL, "input and output must not alias");
-  if (s->shape == 1 && op != OP_BWD && op != OP_IPROD && op != OP_HELM)
-    return fail(NK_EUNSUPPORTED, "triangle spaces provide BwdTrans, IProductWRTBase and Helmholtz");
+  if (s->shape != 0 && op != OP_BWD && op != OP_IPROD && op != OP_HELM)
+    return fail(NK_EUNSUPPORTED, "triangle and tetrahedron spaces provide BwdTrans, IProductWRTBase and Helmholtz");
   hipStream_t st = (hipStream_t)stream;
   const char* fac = t == NK_F64 ? (const char*)s->fac64 : (const char*)s->fac32;
   auto group_args = [&](const Group& G) {
@@ -501,6 +567,11 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
   if (s->shape == 1) {
     const hipError_t e = launch_tri(t, group_args(s->groups[0]));
     if (e != hipSuccess) return hip_fail(e, "triangle operator launch");
+    return NK_OK;
+  }
+  if (s->shape == 2) {
+    const hipError_t e = launch_tet(t, group_args(s->groups[0]));
+    if (e != hipSuccess) return hip_fail(e, "tetrahedron operator launch");
     return NK_OK;
   }
   int strategy = VARP_SEQUENTIAL;
@@ -749,6 +820,7 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   if (s->groups.size() != 1 && nsys != 1)
     return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
   if (s->shape == 1 && nsys != 1) return fail(NK_EINVAL, "a triangle space takes one system (nsys = 1)");
+  if (s->shape == 2) return fail(NK_EUNSUPPORTED, "assembled systems are not built for tetrahedra");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
   if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
     return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");

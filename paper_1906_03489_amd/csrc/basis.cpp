@@ -10,6 +10,7 @@
 // since P^{1,1}_{p-1} = 2 L_p' / (p+1); Legendre's equation then gives the
 // derivative in closed form, phi_p'(x) = -(p/2) L_p(x).  Both need only the
 // Legendre three-term recurrence.
+#include <algorithm>
 #include <cmath>
 #include <utility>
 #include <vector>
@@ -211,6 +212,126 @@ void tri_points(int Q, double* e1, double* w1, double* e2, double* w2) {
     double s = rhs[c];
     for (int j = c + 1; j < n; ++j) s -= A[c * n + j] * w2[j];
     w2[c] = s / A[c * n + c];
+  }
+}
+
+// n Gauss-Radau points (x = -1 included) and weights of the weight
+// (1-x)^alpha on [-1, 1] (the eta_3 rule of tetrahedra uses alpha = 2).  The
+// interior points are the roots of P^{alpha,1}_{n-1}: eigenvalues of its
+// symmetric tridiagonal recurrence matrix (Golub-Welsch), found by
+// symmetric_eigen and polished by Newton steps on the three-term recurrence;
+// the weights are fixed by exactness on 1, x, ..., x^{n-1}, the moments of
+// (1-x)^alpha in closed form (binomial expansion), solved by Gaussian
+// elimination with partial pivoting.
+void radau_points(int n, int alpha, double* x, double* w) {
+  x[0] = -1.0;
+  const int m = n - 1;
+  if (m > 0) {
+    const double a = alpha, b = 1.0;
+    std::vector<double> T(m * m, 0.0), V(m * m), lam(m);
+    for (int k = 0; k < m; ++k) {
+      const double c = 2.0 * k + a + b;
+      T[k * m + k] = (k == 0) ? (b - a) / (a + b + 2.0) : (b * b - a * a) / (c * (c + 2.0));
+      if (k + 1 < m) {
+        const double kk = k + 1.0, c1 = 2.0 * kk + a + b;
+        const double off = std::sqrt(4.0 * kk * (kk + a) * (kk + b) * (kk + a + b) /
+                                     (c1 * c1 * (c1 + 1.0) * (c1 - 1.0)));
+        T[k * m + k + 1] = T[(k + 1) * m + k] = off;
+      }
+    }
+    symmetric_eigen(m, T.data(), V.data(), lam.data());
+    std::sort(lam.begin(), lam.end());
+    for (int k = 0; k < m; ++k) {
+      double r = lam[k];
+      for (int it = 0; it < 20; ++it) {   // Newton: P' = (m + a + b + 1)/2 P^{a+1,b+1}_{m-1}
+        const double f = jacobi_poly(m, a, b, r);
+        const double df = 0.5 * (m + a + b + 1.0) * jacobi_poly(m - 1, a + 1.0, b + 1.0, r);
+        const double dr = f / df;
+        r -= dr;
+        if (std::fabs(dr) < 1e-16) break;
+      }
+      x[k + 1] = r;
+    }
+  }
+  // moments int_{-1}^{1} x^k (1-x)^alpha dx = sum_l binom(alpha, l) (-1)^l int x^{k+l}
+  std::vector<double> A(n * n), rhs(n);
+  for (int k = 0; k < n; ++k) {
+    double mk = 0.0, bin = 1.0;
+    for (int l = 0; l <= alpha; ++l) {
+      const int d = k + l;
+      const double ik = (d % 2 == 0) ? 2.0 / (d + 1) : 0.0;
+      mk += ((l % 2) ? -bin : bin) * ik;
+      bin = bin * (alpha - l) / (l + 1.0);
+    }
+    rhs[k] = mk;
+    for (int j = 0; j < n; ++j) A[k * n + j] = std::pow(x[j], k);
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(A[c * n + j], A[piv * n + j]);
+      std::swap(rhs[c], rhs[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int j = c; j < n; ++j) A[r * n + j] -= f * A[c * n + j];
+      rhs[r] -= f * rhs[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double s = rhs[c];
+    for (int j = c + 1; j < n; ++j) s -= A[c * n + j] * w[j];
+    w[c] = s / A[c * n + c];
+  }
+}
+
+// Collapsed tetrahedron quadrature: GLL (Q) in eta_1, Radau of (1-x) (Q-1)
+// in eta_2, Radau of (1-x)^2 (Q-1) in eta_3.
+void tet_points(int Q, double* e1, double* w1, double* e2, double* w2, double* e3, double* w3) {
+  tri_points(Q, e1, w1, e2, w2);
+  radau_points(Q - 1, 2, e3, w3);
+}
+
+// Total polynomial degree of triangle mode (p, q) of order P.
+int tri_mode_degree(int P, int p, int q) {
+  if ((p == 0 || p == P) && q == 0) return 1;   // vertices A, B
+  if (p == 0 && q == P) return 1;               // vertex C
+  if (p == 0 || p == P) return q + 1;           // edges AC, BC
+  if (q == 0) return p + 1;                     // edge AB
+  return p + q + 1;                             // interior
+}
+
+// eta_3 factor of every tetrahedron mode at the points z (values and
+// derivatives, [nz][nm3]): modes grouped by triangle mode t (degree s),
+// r = 0..P-s: ((1-z)/2)^s, times (1+z)/2 P^{2s-1,1}_{r-1}(z) for r >= 1;
+// the top vertex (1+z)/2 last.
+void tet_ctable(int P, int nz, const double* z, double* Ct, double* dCt) {
+  const int nm3 = (P + 1) * (P + 2) * (P + 3) / 6;
+  for (int k = 0; k < nz; ++k) {
+    const double x = z[k], a = 0.5 * (1.0 - x), g = 0.5 * (1.0 + x);
+    int m = 0;
+    for (int p = 0; p <= P; ++p) {
+      const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
+      for (int q = 0; q < nq; ++q) {
+        const int s = tri_mode_degree(P, p, q);
+        const double f = std::pow(a, s), df = s > 0 ? -0.5 * s * std::pow(a, s - 1) : 0.0;
+        for (int r = 0; r <= P - s; ++r, ++m) {
+          if (r == 0) {
+            Ct[k * nm3 + m] = f;
+            dCt[k * nm3 + m] = df;
+          } else {
+            const double J = jacobi_poly(r - 1, 2.0 * s - 1.0, 1.0, x);
+            const double dJ = r >= 2 ? 0.5 * (r + 2.0 * s) * jacobi_poly(r - 2, 2.0 * s, 2.0, x) : 0.0;
+            Ct[k * nm3 + m] = f * g * J;
+            dCt[k * nm3 + m] = df * g * J + f * 0.5 * J + f * g * dJ;
+          }
+        }
+      }
+    }
+    Ct[k * nm3 + m] = g;   // top vertex
+    dCt[k * nm3 + m] = 0.5;
   }
 }
 

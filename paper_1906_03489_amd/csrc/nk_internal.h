@@ -43,6 +43,10 @@ void collocation_derivative(int Q, const double* x, double* Dc);
 void symmetric_eigen(int n, const double* A, double* V, double* lam);
 void tri_points(int Q, double* e1, double* w1, double* e2, double* w2);
 void tri_btable(int P, int nz, const double* z, double* Bt, double* dBt);
+void radau_points(int n, int alpha, double* x, double* w);
+void tet_points(int Q, double* e1, double* w1, double* e2, double* w2, double* e3, double* w3);
+int tri_mode_degree(int P, int p, int q);
+void tet_ctable(int P, int nz, const double* z, double* Ct, double* dCt);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -172,6 +176,10 @@ inline int64_t tri_fac_count(int Q, int64_t nelem) {
 hipError_t launch_tri(nk_dtype t, const OpArgs& a);   // also OP_HELM_ASM (assembled)
 hipError_t launch_diag_tri(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
                            const int32_t* l2g, double* diag, hipStream_t st);
+// Collapsed tetrahedra (tet.hip): BwdTrans, IProductWRTBase, Helmholtz.
+hipError_t launch_tet(nk_dtype t, const OpArgs& a);
+hipError_t launch_geom_tet(int Q, int64_t nelem, const double* jac, const double* kappa,
+                           const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 hipError_t launch_geom_tri(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 

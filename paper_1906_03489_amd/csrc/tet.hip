@@ -1,0 +1,492 @@
+// Collapsed-coordinate tetrahedra (section 2.1: the tetrahedron is a hexahedron
+// collapsed twice through the Duffy map; section 3.3: the expansion factors
+// in the collapsed coordinates, so the operators stay sum-factorised).
+// Elemental BwdTrans, IProductWRTBase and Helmholtz.
+//
+// Basis: every mode is a triangle mode T_t(eta_1, eta_2) of the order-P
+// triangle (tri.hip), of total degree s_t, times an eta_3 factor c_{s,r}:
+// ((1-eta_3)/2)^s for r = 0, times (1+eta_3)/2 P^{2s-1,1}_{r-1}(eta_3) for
+// 1 <= r <= P - s; plus the top vertex D = (1+eta_3)/2, evaluated as
+// (A + B + C)_triangle * D since the triangle's vertex modes sum to one.
+// Coefficients are grouped by triangle mode (r fastest), D last.  Points: Q
+// GLL points in eta_1, Q-1 Radau points of (1-x) in eta_2 and Q-1 of (1-x)^2
+// in eta_3, q = i + Q (j + (Q-1) k).
+//
+// So a tetrahedron is Q-1 triangle expansions, one per eta_3 point k, whose
+// coefficients w_t(k) = sum_r c_{s_t,r}(eta_3k) u_{t,r} come from an eta_3
+// stage.  A thread owns the eta_1 row (j, k) of one tetrahedron: after the
+// eta_3 stage (threads over (k, t) pairs), the triangle stages run as in
+// tri.hip with the eta_1 tables as scalar operands; the transposed stages
+// mirror them.  Helmholtz carries dw/deta_3 through the triangle stage too,
+// for the third collapsed derivative.  Factors per point (built at space
+// creation): w detJ, then the 6 entries of w detJ kappa M G M^T with M the
+// collapsed chain rule d eta / d xi.
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "engine.h"
+#include "tables.h"
+
+namespace nk {
+
+template <int P>
+struct TetShape {
+  static constexpr int N = P + 1, Q = P + 2, Q2 = Q - 1, NS = Q2 * Q2, NPT = Q * NS;
+  static constexpr int NMT = N * (N + 1) / 2;            // triangle modes
+  static constexpr int NM3 = N * (N + 1) * (N + 2) / 6;  // tetrahedron modes
+  // LDS row strides (in scalars), odd so that distinct rows fall into
+  // distinct banks
+  static constexpr int TS = NMT | 1, CS = NM3 | 1;
+  static constexpr int NTAB = 2 * Q2 * TS + 2 * Q2 * CS;        // B2, dB2, C3, dC3
+  static constexpr int NITAB = 2 * NMT + 1 + NM3;               // toff3, tp, mt
+  static constexpr int SLOT = NM3 + 2 * Q2 * NMT + 3 * NS * N;  // u, w | w', SA | SB | SC
+  // tetrahedra per block: up to 256 threads, within ~150 KB of LDS
+  template <typename T>
+  static constexpr int epb() {
+    const int by_threads = 256 / NS > 0 ? 256 / NS : 1;
+    const int by_lds = (int)((150000 / sizeof(T) - NTAB) / SLOT);
+    const int e = by_threads < by_lds ? by_threads : by_lds;
+    return e > 0 ? e : 1;
+  }
+  static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
+  static constexpr int off(int p) {
+    int o = 0;
+    for (int k = 0; k < p; ++k) o += cnt(k);
+    return o;
+  }
+};
+
+// Device tables of order P: B2 [Q2][NMT], dB2 [Q2][NMT] at the eta_2 points,
+// C3 [Q2][NM3], dC3 [Q2][NM3] at the eta_3 points (scalars of type T), and
+// the integer maps toff3 [NMT+1] (first coefficient of each triangle mode),
+// tp [NMT] (eta_1 index p of each triangle mode), mt [NM3] (triangle mode of
+// each coefficient, -1 for the top vertex).
+struct TetTables {
+  const void* tab = nullptr;
+  const int* itab = nullptr;
+};
+
+template <typename T>
+static TetTables tet_tables(int P) {
+  static std::mutex mu;
+  static std::unordered_map<long, TetTables> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return {};
+  const long key = dev * 64L + P;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const int N = P + 1, Q = P + 2, Q2 = Q - 1, NMT = N * (N + 1) / 2, NM3 = N * (N + 1) * (N + 2) / 6;
+  std::vector<double> e1(Q), w1(Q), e2(Q2), w2(Q2), e3(Q2), w3(Q2);
+  tet_points(Q, e1.data(), w1.data(), e2.data(), w2.data(), e3.data(), w3.data());
+  std::vector<double> B2(Q2 * NMT), dB2(Q2 * NMT), C3(Q2 * NM3), dC3(Q2 * NM3);
+  tri_btable(P, Q2, e2.data(), B2.data(), dB2.data());
+  tet_ctable(P, Q2, e3.data(), C3.data(), dC3.data());
+  std::vector<T> h;
+  for (const auto* v : {&B2, &dB2, &C3, &dC3})
+    for (double x : *v) h.push_back((T)x);
+  std::vector<int> it_(2 * NMT + 1 + NM3);
+  int t = 0, m = 0;
+  for (int p = 0; p <= P; ++p) {
+    const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
+    for (int q = 0; q < nq; ++q, ++t) {
+      it_[t] = m;                 // toff3
+      it_[NMT + 1 + t] = p;       // tp
+      const int s = tri_mode_degree(P, p, q);
+      for (int r = 0; r <= P - s; ++r, ++m) it_[2 * NMT + 1 + m] = t;   // mt
+    }
+  }
+  it_[NMT] = m;                   // end of the last group; m = NM3 - 1 (top vertex)
+  it_[2 * NMT + 1 + m] = -1;
+  TetTables out;
+  T* d = nullptr;
+  int* di = nullptr;
+  if (hipMalloc((void**)&d, h.size() * sizeof(T)) != hipSuccess) return {};
+  if (hipMalloc((void**)&di, it_.size() * sizeof(int)) != hipSuccess) {
+    (void)hipFree(d);
+    return {};
+  }
+  if (hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(di, it_.data(), it_.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    (void)hipFree(di);
+    return {};
+  }
+  out.tab = d;
+  out.itab = di;
+  cache[key] = out;
+  return out;
+}
+
+template <typename T, int P, int OP>
+__global__ void __launch_bounds__(256)
+    k_tet(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const int* __restrict__ itab,
+          const DevArgs<T> a) {
+  using S = TetShape<P>;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NS = S::NS, NPT = S::NPT;
+  constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS;
+  constexpr int EPB = S::template epb<T>();
+  constexpr bool HELM = OP == OP_HELM;
+  constexpr int VA = 0, VC = P, VB = NMT - P;   // triangle vertex modes A, C, B
+  __shared__ T stab[S::NTAB];
+  __shared__ int sit[S::NITAB];
+  __shared__ T smem[EPB * S::SLOT];
+  for (int k = threadIdx.x; k < Q2 * NMT; k += blockDim.x) {
+    const int r = k / NMT, m = k - r * NMT;
+    stab[r * TS + m] = tab[k];
+    stab[(Q2 + r) * TS + m] = tab[Q2 * NMT + k];
+  }
+  for (int k = threadIdx.x; k < Q2 * NM3; k += blockDim.x) {
+    const int r = k / NM3, m = k - r * NM3;
+    stab[2 * Q2 * TS + r * CS + m] = tab[2 * Q2 * NMT + k];
+    stab[2 * Q2 * TS + (Q2 + r) * CS + m] = tab[2 * Q2 * NMT + Q2 * NM3 + k];
+  }
+  for (int k = threadIdx.x; k < S::NITAB; k += blockDim.x) sit[k] = itab[k];
+  __syncthreads();
+  const T* B2 = stab;
+  const T* dB2 = stab + Q2 * TS;
+  const T* C3 = stab + 2 * Q2 * TS;
+  const T* dC3 = C3 + Q2 * CS;
+  const int* toff3 = sit;
+  const int* tp = sit + NMT + 1;
+  const int* mt = tp + NMT;
+  const int slot0 = threadIdx.x / NS;
+  const bool act = slot0 < EPB;                     // threads past EPB slots only synchronise
+  const int slot = act ? slot0 : 0;
+  const int t = threadIdx.x - slot0 * NS;           // row lane: t = j + Q2 k
+  const int j = act ? t % Q2 : 0, k = act ? t / Q2 : 0;
+  T* U = smem + slot * S::SLOT;                     // [NM3] coefficients
+  T* W = U + NM3;                                   // [Q2][NMT] w, later z
+  T* W3 = W + Q2 * NMT;                             // [Q2][NMT] dw/deta_3, later z'
+  T* SS = W3 + Q2 * NMT;                            // [3][NS][N]
+  const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
+  for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
+    const int64_t e = g * EPB + slot;
+    const bool live = act && e < a.nelem;
+    T SA[N], SB[N], SC[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) SA[p] = SB[p] = SC[p] = T(0);
+    if constexpr (OP != OP_IPROD) {
+      if (live)
+        for (int m = t; m < NM3; m += NS) U[m] = a.in[e * NM3 + m];
+      __syncthreads();
+      // eta_3 stage: w_t(k') (and dw/deta_3) for every (k', t) pair
+      if (live) {
+        for (int idx = t; idx < Q2 * NMT; idx += NS) {
+          const int kk = idx / NMT, tt = idx - kk * NMT;
+          const int o = toff3[tt], c = toff3[tt + 1] - o;
+          const T* cr = C3 + kk * CS + o;
+          const T* dcr = dC3 + kk * CS + o;
+          T w = T(0), w3 = T(0);
+          for (int r = 0; r < c; ++r) {
+            w += cr[r] * U[o + r];
+            if constexpr (HELM) w3 += dcr[r] * U[o + r];
+          }
+          if (tt == VA || tt == VB || tt == VC) {   // the top vertex rides on A + B + C
+            w += C3[kk * CS + NM3 - 1] * U[NM3 - 1];
+            if constexpr (HELM) w3 += dC3[kk * CS + NM3 - 1] * U[NM3 - 1];
+          }
+          W[kk * NMT + tt] = w;
+          if constexpr (HELM) W3[kk * NMT + tt] = w3;
+        }
+      }
+      __syncthreads();
+      // eta_2 stage of slice k, row j
+      T V[N], dV[N], V3[N];
+#pragma unroll
+      for (int p = 0; p < N; ++p) V[p] = dV[p] = V3[p] = T(0);
+      const T* w = W + k * NMT;
+      const T* w3 = W3 + k * NMT;
+      const T* b2 = B2 + j * TS;
+      const T* db2 = dB2 + j * TS;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+#pragma unroll
+        for (int q = 0; q < S::cnt(p); ++q) {
+          const int m = S::off(p) + q;
+          V[p] += b2[m] * w[m];
+          if constexpr (HELM) {
+            dV[p] += db2[m] * w[m];
+            V3[p] += b2[m] * w3[m];
+          }
+        }
+        // finish one mode group before the next group's loads are issued
+        if constexpr (HELM) {
+          __asm__ volatile("" : "+v"(V[p]), "+v"(dV[p]), "+v"(V3[p])::"memory");
+        } else {
+          __asm__ volatile("" : "+v"(V[p])::"memory");
+        }
+      }
+      {   // the collapsed triangle vertex C also multiplies a_P
+        V[P] += b2[P] * w[P];
+        if constexpr (HELM) {
+          dV[P] += db2[P] * w[P];
+          V3[P] += b2[P] * w3[P];
+        }
+      }
+      if constexpr (OP == OP_BWD) {
+#pragma unroll 1
+        for (int i = 0; i < Q; ++i) {
+          T u = T(0);
+#pragma unroll
+          for (int p = 0; p < N; ++p) u += tb.B[i * N + p] * V[p];
+          if (live) a.out[e * NPT + i + Q * t] = u;
+        }
+        continue;
+      } else {
+        const T lam = (T)(a.lam ? a.lam[live ? e : 0] : a.lam0);
+        const T* f = a.fac + (live ? e : 0) * (int64_t)(7 * NPT) + t;
+#pragma unroll 1
+        for (int i = 0; i < Q; ++i) {
+          T u = T(0), u1 = T(0), u2 = T(0), u3 = T(0);
+#pragma unroll
+          for (int p = 0; p < N; ++p) {
+            u += tb.B[i * N + p] * V[p];
+            u1 += tb.D[i * N + p] * V[p];
+            u2 += tb.B[i * N + p] * dV[p];
+            u3 += tb.B[i * N + p] * V3[p];
+          }
+          T fv[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+          if (live) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) fv[c] = f[(c * Q + i) * NS];
+          }
+          const T mq = lam * fv[0] * u;
+          const T g1 = fv[1] * u1 + fv[2] * u2 + fv[3] * u3;
+          const T g2 = fv[2] * u1 + fv[4] * u2 + fv[5] * u3;
+          const T g3 = fv[3] * u1 + fv[5] * u2 + fv[6] * u3;
+#pragma unroll
+          for (int p = 0; p < N; ++p) {
+            SA[p] += tb.B[i * N + p] * mq + tb.D[i * N + p] * g1;
+            SB[p] += tb.B[i * N + p] * g2;
+            SC[p] += tb.B[i * N + p] * g3;
+          }
+        }
+      }
+    } else {   // IProductWRTBase: point values times w detJ
+      const T* x = a.in + (live ? e : 0) * (int64_t)NPT + Q * t;
+      const T* f = a.fac + (live ? e : 0) * (int64_t)(7 * NPT) + t;
+#pragma unroll 1
+      for (int i = 0; i < Q; ++i) {
+        const T mq = live ? f[i * NS] * x[i] : T(0);
+#pragma unroll
+        for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
+      }
+    }
+    // transposed eta_1 results -> LDS
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        SS[t * N + p] = SA[p];
+        if constexpr (HELM) {
+          SS[(NS + t) * N + p] = SB[p];
+          SS[(2 * NS + t) * N + p] = SC[p];
+        }
+      }
+    }
+    __syncthreads();
+    // transposed eta_2 stage: z_t(k'), z'_t(k') for every (k', t) pair
+    if (live) {
+      for (int idx = t; idx < Q2 * NMT; idx += NS) {
+        const int kk = idx / NMT, tt = idx - kk * NMT, p = tp[tt];
+        T z = T(0), z3 = T(0);
+#pragma unroll
+        for (int jj = 0; jj < Q2; ++jj) {
+          const int row = jj + Q2 * kk;
+          z += B2[jj * TS + tt] * SS[row * N + p];
+          if constexpr (HELM) {
+            z += dB2[jj * TS + tt] * SS[(NS + row) * N + p];
+            z3 += B2[jj * TS + tt] * SS[(2 * NS + row) * N + p];
+          }
+        }
+        if (tt == VC) {   // the collapsed triangle vertex: its a_P part
+#pragma unroll
+          for (int jj = 0; jj < Q2; ++jj) {
+            const int row = jj + Q2 * kk;
+            z += B2[jj * TS + P] * SS[row * N + P];
+            if constexpr (HELM) {
+              z += dB2[jj * TS + P] * SS[(NS + row) * N + P];
+              z3 += B2[jj * TS + P] * SS[(2 * NS + row) * N + P];
+            }
+          }
+        }
+        W[kk * NMT + tt] = z;
+        if constexpr (HELM) W3[kk * NMT + tt] = z3;
+      }
+    }
+    __syncthreads();
+    // transposed eta_3 stage: one output coefficient per iteration
+    if (live) {
+      for (int m = t; m < NM3; m += NS) {
+        const int tt = mt[m];
+        T y = T(0);
+        if (tt >= 0) {
+#pragma unroll
+          for (int kk = 0; kk < Q2; ++kk) {
+            y += C3[kk * CS + m] * W[kk * NMT + tt];
+            if constexpr (HELM) y += dC3[kk * CS + m] * W3[kk * NMT + tt];
+          }
+        } else {   // top vertex
+#pragma unroll
+          for (int kk = 0; kk < Q2; ++kk) {
+            const T* zr = W + kk * NMT;
+            y += C3[kk * CS + m] * (zr[VA] + zr[VB] + zr[VC]);
+            if constexpr (HELM) {
+              const T* z3r = W3 + kk * NMT;
+              y += dC3[kk * CS + m] * (z3r[VA] + z3r[VB] + z3r[VC]);
+            }
+          }
+        }
+        a.out[e * NM3 + m] = y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int P>
+static int64_t tet_grid(int op) {
+  static std::unordered_map<int, int64_t> cached;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  int dev = 0, cus = 0, nb = 0;
+  (void)hipGetDevice(&dev);
+  const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : 2);
+  auto it = cached.find(key);
+  if (it != cached.end()) return it->second;
+  using S = TetShape<P>;
+  constexpr int threads = (S::template epb<T>() * S::NS + 63) / 64 * 64;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const void* fn = op == OP_BWD     ? (const void*)k_tet<T, P, OP_BWD>
+                   : op == OP_IPROD ? (const void*)k_tet<T, P, OP_IPROD>
+                                    : (const void*)k_tet<T, P, OP_HELM>;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0);
+  const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (nb > 0 ? nb : 1) * 4;
+  cached[key] = grid;
+  return grid;
+}
+
+template <typename T, int P>
+static hipError_t run_tet(const OpArgs& a) {
+  using S = TetShape<P>;
+  const TetTables tt = tet_tables<T>(P);
+  if (!tt.tab) return hipErrorOutOfMemory;
+  constexpr int EPB = S::template epb<T>();
+  constexpr int threads = (EPB * S::NS + 63) / 64 * 64;
+  static_assert(threads <= 256, "block size");
+  const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
+  const int64_t gmax = tet_grid<T, P>(a.op);
+  const int64_t nb = ngrp < gmax ? ngrp : gmax;
+  const Tab<T, P + 1, P + 2>& tb = host_tab<T, P + 1, P + 2>();
+  const DevArgs<T> d = dev_args<T>(a);
+  const T* tab = static_cast<const T*>(tt.tab);
+  const dim3 g((unsigned)nb), b(threads);
+  switch (a.op) {
+    case OP_BWD: hipLaunchKernelGGL((k_tet<T, P, OP_BWD>), g, b, 0, a.stream, tb, tab, tt.itab, d); break;
+    case OP_IPROD:
+      hipLaunchKernelGGL((k_tet<T, P, OP_IPROD>), g, b, 0, a.stream, tb, tab, tt.itab, d);
+      break;
+    case OP_HELM: hipLaunchKernelGGL((k_tet<T, P, OP_HELM>), g, b, 0, a.stream, tb, tab, tt.itab, d); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t run_tet_p(nk_dtype t, const OpArgs& a) {
+  return t == NK_F64 ? run_tet<double, P>(a) : run_tet<float, P>(a);
+}
+
+hipError_t launch_tet(nk_dtype t, const OpArgs& a) {
+  if (a.nelem == 0) return hipSuccess;
+  switch (a.P) {
+    case 1: return run_tet_p<1>(t, a);
+    case 2: return run_tet_p<2>(t, a);
+    case 3: return run_tet_p<3>(t, a);
+    case 4: return run_tet_p<4>(t, a);
+    case 5: return run_tet_p<5>(t, a);
+    case 6: return run_tet_p<6>(t, a);
+    case 7: return run_tet_p<7>(t, a);
+    case 8: return run_tet_p<8>(t, a);
+    case 9: return run_tet_p<9>(t, a);
+    case 10: return run_tet_p<10>(t, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Factors of the collapsed tetrahedron at every point (thread per point):
+// f0 = w detJ with w = w1_i (w2_j / 2) (w3_k / 4) (the Radau weights carry
+// (1 - eta_2) and (1 - eta_3)^2), f1..f6 = w detJ kappa (M G M^T)_{11,12,13,
+// 22,23,33} with G = J^{-1} J^{-T} and M_ba = d eta_b / d xi_a.  Layout
+// [E][7][Q][(Q-1)^2]: for each factor and eta_1 index i, the rows j + (Q-1) k
+// are contiguous, the order in which the operator's threads read them.
+__global__ void __launch_bounds__(256)
+    k_geom_tet(int Q, int64_t nelem, const double* __restrict__ jac, const double* __restrict__ kappa,
+               const double* __restrict__ pts, double* __restrict__ fac64, float* __restrict__ fac32,
+               int* __restrict__ bad) {
+  const int Q2 = Q - 1, NS = Q2 * Q2, NP = Q * NS;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nelem * NP) return;
+  const int64_t e = id / NP;
+  const int q = (int)(id - e * NP);
+  const int i = q % Q, row = q / Q, j = row % Q2, k = row / Q2;
+  const double e1 = pts[i], w1 = pts[Q + i];
+  const double e2 = pts[2 * Q + j], w2 = pts[2 * Q + Q2 + j];
+  const double e3 = pts[2 * Q + 2 * Q2 + k], w3 = pts[2 * Q + 3 * Q2 + k];
+  double J[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int b = 0; b < 3; ++b) J[c][b] = jac[((e * 3 + c) * 3 + b) * NP + q];
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  const double id_ = 1.0 / det;
+  double Ji[3][3];   // Ji[a][c] = d xi_a / d x_c
+  Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id_;
+  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id_;
+  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id_;
+  Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id_;
+  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id_;
+  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id_;
+  Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id_;
+  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id_;
+  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id_;
+  double G[3][3];
+  for (int a_ = 0; a_ < 3; ++a_)
+    for (int b = 0; b < 3; ++b)
+      G[a_][b] = Ji[a_][0] * Ji[b][0] + Ji[a_][1] * Ji[b][1] + Ji[a_][2] * Ji[b][2];
+  // M[b][a] = d eta_b / d xi_a of the collapsed map
+  const double g = 2.0 / ((1.0 - e2) * (1.0 - e3));
+  const double M[3][3] = {{2.0 * g, (1.0 + e1) * g, (1.0 + e1) * g},
+                          {0.0, 2.0 / (1.0 - e3), (1.0 + e2) / (1.0 - e3)},
+                          {0.0, 0.0, 1.0}};
+  double H[3][3];   // M G M^T
+  for (int a_ = 0; a_ < 3; ++a_)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0.0;
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) s += M[a_][c] * G[c][d] * M[b][d];
+      H[a_][b] = s;
+    }
+  const double kap = kappa ? kappa[e * NP + q] : 1.0;
+  const double wj = w1 * 0.5 * w2 * 0.25 * w3 * det;
+  const double ck = wj * kap;
+  const double f[7] = {wj, ck * H[0][0], ck * H[0][1], ck * H[0][2], ck * H[1][1], ck * H[1][2], ck * H[2][2]};
+  if (!(det > 0.0) || !(kap > 0.0)) atomicOr(bad, 1);
+  for (int c = 0; c < 7; ++c) {
+    const int64_t o = (e * 7 + c) * (int64_t)NP + (int64_t)i * NS + row;
+    fac64[o] = f[c];
+    fac32[o] = (float)f[c];
+  }
+}
+
+hipError_t launch_geom_tet(int Q, int64_t nelem, const double* jac, const double* kappa,
+                           const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s) {
+  const int64_t n = nelem * Q * (Q - 1) * (Q - 1);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_geom_tet, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, nelem, jac,
+                     kappa, pts, fac64, fac32, bad);
+  return hipGetLastError();
+}
+
+}  // namespace nk

@@ -33,7 +33,7 @@ EXPORTS = [
     "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
-    "nk_tri_points", "nk_space_create_tri",
+    "nk_tri_points", "nk_space_create_tri", "nk_tet_points", "nk_space_create_tet",
 ]
 
 
@@ -100,6 +100,8 @@ def lib():
         "nk_fwd_trans": (i32, [vp, i32, vp, vp, vp]),
         "nk_tri_points": (i32, [i32, vp, vp, vp, vp]),
         "nk_space_create_tri": (i32, [pp, i64, i32, i32, vp, vp, vp]),
+        "nk_tet_points": (i32, [i32, vp, vp, vp, vp, vp, vp]),
+        "nk_space_create_tet": (i32, [pp, i64, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -152,6 +154,15 @@ def tri_points(Q: int):
     _check(lib().nk_tri_points(Q, e1.ctypes.data_as(ctypes.c_void_p), w1.ctypes.data_as(ctypes.c_void_p),
                                e2.ctypes.data_as(ctypes.c_void_p), w2.ctypes.data_as(ctypes.c_void_p)))
     return e1, w1, e2, w2
+
+
+def tet_points(Q: int):
+    """(eta1, w1, eta2, w2, eta3, w3) of the library's collapsed tetrahedron
+    quadrature."""
+    import numpy as np
+    arrs = [np.zeros(Q), np.zeros(Q)] + [np.zeros(Q - 1) for _ in range(4)]
+    _check(lib().nk_tet_points(Q, *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs]))
+    return tuple(arrs)
 
 
 def basis_tables(P: int, Q: int):
@@ -210,6 +221,16 @@ class Space:
         _check(lib().nk_space_create_tri(ctypes.byref(h), E, P, Q, _ptr(jac, torch.float64, "jac"),
                                          _ptr(kappa, torch.float64, "kappa"), _stream()))
         return cls(h.value, 2, [(P, Q, E)])
+
+    @classmethod
+    def create_tet(cls, P: int, Q: int, jac, kappa=None):
+        """Collapsed-coordinate tetrahedra: jac [E, 3, 3, Q(Q-1)^2] FP64 on the GPU."""
+        import torch
+        E = int(jac.shape[0]) if jac.dim() > 1 else jac.numel() // (9 * Q * (Q - 1) ** 2)
+        h = ctypes.c_void_p()
+        _check(lib().nk_space_create_tet(ctypes.byref(h), E, P, Q, _ptr(jac, torch.float64, "jac"),
+                                         _ptr(kappa, torch.float64, "kappa"), _stream()))
+        return cls(h.value, 3, [(P, Q, E)])
 
     STRATEGIES = {0: "persistent", 1: "persistent_2bpc", 2: "concurrent", 3: "sequential"}
 

@@ -106,3 +106,21 @@ def test_library_triangle_quadrature_matches_oracle(Q):
     np.testing.assert_allclose(e2, xr, atol=1e-14)
     np.testing.assert_allclose(w2, wr, atol=1e-13)
     assert L.nk_tri_points(2, None, None, None, None) == nk.NK_EINVAL
+
+
+@pytest.mark.parametrize("Q", [3, 4, 7, 12])
+def test_library_tetrahedron_quadrature_matches_oracle(Q):
+    """The library's collapsed-tetrahedron rule (Golub-Welsch roots of
+    P^{2,1}, Newton-polished, weights by exactness) against the oracle's
+    (scipy Jacobi roots, Gauss-Jacobi moments)."""
+    import numpy as np
+    from oracle import collapsed as C
+    nk, L = _lib()
+    e1, w1, e2, w2, e3, w3 = nk.tet_points(Q)
+    t1, tw1, t2, tw2 = nk.tri_points(Q)
+    np.testing.assert_array_equal(e1, t1)
+    np.testing.assert_array_equal(e2, t2)
+    xr, wr = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    np.testing.assert_allclose(e3, xr, atol=1e-14)
+    np.testing.assert_allclose(w3, wr, atol=1e-13)
+    assert L.nk_tet_points(2, None, None, None, None, None, None) == nk.NK_EINVAL

@@ -1,0 +1,130 @@
+"""GPU parity of the collapsed-coordinate tetrahedron operators (BwdTrans,
+IProductWRTBase, Helmholtz with per-point kappa and per-element lambda)
+against the oracle's dense elemental matrices, on the curved tetrahedral mesh
+of the unit cube; FP64 1e-12 and FP32 2e-6 relative 2-norm, as for the other
+operators."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import collapsed as C
+from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _jacobians(P, n, amp=W.WARP_AMPLITUDE, elems=None):
+    """(J at the library's points, J at the oracle's points)."""
+    m = nk()
+    Q = P + 2
+    e1g, _, e2g, _, e3g, _ = m.tet_points(Q)
+    Jg = W.tet_lattice_jacobians(n, e1g, e2g, e3g, amp, elems)
+    x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    x2, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    Jo = W.tet_lattice_jacobians(n, oracle.gll(Q)[0], x1, x2, amp, elems)
+    return Jg, Jo
+
+
+@pytest.mark.parametrize("P", list(range(1, 11)))
+def test_tetrahedron_operators_match_oracle(P):
+    torch = torch_cuda()
+    m = nk()
+    Q = P + 2
+    n = 2 if P <= 6 else 1
+    Jg, Jo = _jacobians(P, n)
+    E, nq = Jg.shape[0], Q * (Q - 1) ** 2
+    nm = (P + 1) * (P + 2) * (P + 3) // 6
+    rng = np.random.default_rng(170 + P)
+    kap = rng.uniform(0.5, 2.0, (E, nq))
+    lam = rng.uniform(0.5, 2.0, E)
+    ops = C.TetOps(P, Q, Jo, kappa=kap, lam=lam)
+    space = m.Space.create_tet(P, Q, to_dev(Jg), kappa=to_dev(kap))
+    c = W.uniform(W.seed(0, 0) + 400 + P, (E, nm))
+    f = W.uniform(W.seed(0, 1) + 400 + P, (E, nq))
+    ref = [ops.bwd(c), ops.iprod(f), ops.helmholtz(c)]
+    for dt, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_RTOL)):
+        td = torch.float64 if dt == m.F64 else torch.float32
+        got = [m.bwd_trans(space, to_dev(c.ravel(), td), dtype=dt),
+               m.iprod_wrt_base(space, to_dev(f.ravel(), td), dtype=dt),
+               m.helmholtz(space, to_dev(c.ravel(), td), lam=to_dev(lam), dtype=dt)]
+        for name, g, r in zip(("bwd", "iprod", "helm"), got, ref):
+            assert_close(g.double().cpu().numpy(), r.ravel(), tol, f"tet {name} P={P} dt={dt}")
+
+
+def test_tetrahedron_helmholtz_constant_and_symmetry():
+    """L 1 = 0 (the Helmholtz operator with lambda = 0 annihilates the
+    constant, the sum of the four vertex modes) and x^T H y = y^T H x on the
+    GPU at P = 5."""
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 5, 7
+    Jg, _ = _jacobians(P, 2)
+    E = Jg.shape[0]
+    modes = C.tet_modes(P)
+    tri = C.tri_modes(P)
+    one = np.zeros(len(modes))
+    for v in ((0, 0), (P, 0), (0, P)):
+        one[modes.index((tri.index(v), 1, 0))] = 1.0
+    one[-1] = 1.0
+    space = m.Space.create_tet(P, Q, to_dev(Jg))
+    y = m.helmholtz(space, to_dev(np.tile(one, E)), lam0=0.0).cpu().numpy()
+    assert np.abs(y).max() < 1e-12
+    rng = np.random.default_rng(1)
+    a, b = rng.uniform(-1, 1, (2, E * len(modes)))
+    Ha = m.helmholtz(space, to_dev(a)).cpu().numpy()
+    Hb = m.helmholtz(space, to_dev(b)).cpu().numpy()
+    assert abs(b @ Ha - a @ Hb) < 1e-12 * abs(b @ Ha)
+
+
+def test_empty_tetrahedron_space_and_unsupported_calls():
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 3, 5
+    nq = Q * (Q - 1) ** 2
+    space0 = m.Space.create_tet(P, Q, to_dev(np.zeros((0, 3, 3, nq))))
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    assert m.bwd_trans(space0, e).numel() == 0
+    assert m.helmholtz(space0, e).numel() == 0
+    Jg, _ = _jacobians(P, 1)
+    space = m.Space.create_tet(P, Q, to_dev(Jg))
+    with pytest.raises(m.NkError) as ei:
+        m.phys_deriv(space, torch.zeros(Jg.shape[0] * nq, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    nm = (P + 1) * (P + 2) * (P + 3) // 6
+    l2g = np.arange(Jg.shape[0] * nm, dtype=np.int32)
+    with pytest.raises(m.NkError) as ei:
+        m.System.create(space, l2g.size, to_dev(l2g), to_dev(np.zeros(l2g.size, np.uint8)))
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    bad = Jg.copy()
+    bad[0, :, 0] *= -1.0          # mirrored element
+    with pytest.raises(m.NkError):
+        m.Space.create_tet(P, Q, to_dev(bad))
+
+
+def test_full_size_tetrahedra_p4_sampled():
+    """The tetrahedral workload the benchmark times (20^3 cubes, 48 000
+    curved tetrahedra, P=4, Q=6) at full size and in the same launch
+    configuration; the oracle checks a seeded sample of elements (first,
+    last and 10 random) of all three operators in FP64 and FP32."""
+    torch = torch_cuda()
+    m = nk()
+    n, P = 20, 4
+    Q = P + 2
+    E, nq, nm = 6 * n ** 3, Q * (Q - 1) ** 2, (P + 1) * (P + 2) * (P + 3) // 6
+    e1g, _, e2g, _, e3g, _ = m.tet_points(Q)
+    space = m.Space.create_tet(P, Q, to_dev(W.tet_lattice_jacobians(n, e1g, e2g, e3g)))
+    c = W.uniform(W.seed(1, 0), E * nm)
+    f = W.uniform(W.seed(1, 1), E * nq)
+    sample = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(8).choice(E, 10, replace=False)]))
+    _, Jo = _jacobians(P, n, elems=sample)
+    ops = C.TetOps(P, Q, Jo)
+    cs, fs = c.reshape(E, nm)[sample], f.reshape(E, nq)[sample]
+    ref = [ops.bwd(cs), ops.iprod(fs), ops.helmholtz(cs)]
+    for dt, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_RTOL)):
+        td = torch.float64 if dt == m.F64 else torch.float32
+        got = [m.bwd_trans(space, to_dev(c, td), dtype=dt).double().cpu().numpy().reshape(E, nq),
+               m.iprod_wrt_base(space, to_dev(f, td), dtype=dt).double().cpu().numpy().reshape(E, nm),
+               m.helmholtz(space, to_dev(c, td), lam0=1.0, dtype=dt).double().cpu().numpy().reshape(E, nm)]
+        for name, g, r in zip(("bwd", "iprod", "helm"), got, ref):
+            assert_close(g[sample], r, tol, f"full-size tet {name} dt={dt}")

@@ -1008,3 +1008,22 @@ def test_tetrahedron_projection_gradient_and_laplacian(P):
     np.testing.assert_allclose(np.linalg.solve(A.T, gxi), grad, atol=1e-11)
     exact = ops.wJ[0] @ (grad ** 2).sum(axis=0)
     assert abs(cu @ ops.laplacian_matrix(0) @ cu - exact) < 1e-12 * exact
+
+
+def test_tetrahedral_mesh_volume_and_orientation():
+    """The tetrahedral mesh of the unit cube: straight-sided, the volumes sum
+    to one exactly; curved by the cyclic warp (which maps the cube onto
+    itself), every Jacobian determinant is positive and the quadrature
+    volume converges to one spectrally (its determinant is not a
+    polynomial)."""
+    errs = []
+    for Q, amp in ((6, 0.0), (4, W.WARP_AMPLITUDE), (8, W.WARP_AMPLITUDE), (12, W.WARP_AMPLITUDE)):
+        x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+        x2, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+        J = W.tet_lattice_jacobians(2, oracle.gll(Q)[0], x1, x2, amp)
+        ops = C.TetOps(Q - 2, Q, J)
+        assert ops.detJ.min() > 0
+        errs.append(abs(ops.wJ.sum() - 1.0))
+    assert errs[0] < 1e-14
+    assert errs[1] < 1e-3 and errs[2] < 2e-6 and errs[3] < 1e-10
+    assert errs[3] < errs[2] < errs[1]

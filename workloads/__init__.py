@@ -409,6 +409,60 @@ def tri_lattice_l2g(n: int, P: int, rot=None):
     return l2g.astype(np.int32), sign, nglobal, dirichlet
 
 
+def tet_lattice_vertices(n: int) -> np.ndarray:
+    """Vertex coordinates of the tetrahedral mesh of the unit cube: an n^3
+    lattice of cubes (cube index i + n (j + n k)), each split into the six
+    tetrahedra of the path decomposition, v0 = corner, v1 = v0 + h e_a,
+    v2 = v1 + h e_b, v3 = v0 + h (1, 1, 1) for the permutations (a, b, c)
+    of the axes; for odd permutations v1 and v2 are swapped so that every
+    tetrahedron (A, B, C, D) = (v0, v1, v2, v3) is positively oriented.
+    Returns (E, 4, 3), E = 6 n^3, element 6 cube + permutation index."""
+    h = 1.0 / n
+    c = np.arange(n ** 3)
+    corner = np.stack([c % n, (c // n) % n, c // (n * n)], axis=1) * h      # (n^3, 3)
+    perms = [(0, 1, 2), (1, 2, 0), (2, 0, 1), (0, 2, 1), (2, 1, 0), (1, 0, 2)]   # 3 even, 3 odd
+    eye = np.eye(3) * h
+    out = np.empty((n ** 3, 6, 4, 3))
+    for t, (a, b, _) in enumerate(perms):
+        v0 = corner
+        v1 = v0 + eye[a]
+        v2 = v1 + eye[b]
+        v3 = v0 + h
+        if t >= 3:
+            v1, v2 = v2, v1
+        out[:, t] = np.stack([v0, v1, v2, v3], axis=1)
+    return out.reshape(-1, 4, 3)
+
+
+def tet_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems=None):
+    """Jacobians of the tetrahedral mesh of the unit cube
+    (tet_lattice_vertices), composed with the cyclic curving map `warp`.  With
+    vertices (A, B, C, D), the affine reference map is x = A (-(1 + xi_1 +
+    xi_2 + xi_3)/2) + B (1 + xi_1)/2 + C (1 + xi_2)/2 + D (1 + xi_3)/2, taken at
+    the collapsed points (xi_3 = eta_3, xi_2 = (1 + eta_2)(1 - eta_3)/2 - 1,
+    xi_1 = (1 + eta_1)(1 - eta_2)(1 - eta_3)/4 - 1) of the 1-D point sets
+    (e1, e2, e3), q = i + len(e1) (j + len(e2) k).  elems: optional subset of
+    element indices.  Returns J[E, c, a, q] = d x'_c / d xi_a."""
+    e1, e2, e3 = (np.asarray(v, np.float64) for v in (e1, e2, e3))
+    n1, n2 = e1.size, e2.size
+    E1 = np.tile(e1, n2 * e3.size)
+    E2 = np.tile(np.repeat(e2, n1), e3.size)
+    E3 = np.repeat(e3, n1 * n2)
+    x3 = E3
+    x2 = (1 + E2) * (1 - E3) / 2 - 1
+    x1 = (1 + E1) * (1 - E2) * (1 - E3) / 4 - 1
+    V = tet_lattice_vertices(n)
+    if elems is not None:
+        V = V[np.asarray(elems)]
+    A = np.stack([(V[:, 1] - V[:, 0]) / 2, (V[:, 2] - V[:, 0]) / 2, (V[:, 3] - V[:, 0]) / 2], axis=2)
+    if amp == 0.0:
+        return np.broadcast_to(A[:, :, :, None], A.shape + (x1.size,)).copy()
+    X = (V[:, 0, :, None] * (-(1 + x1 + x2 + x3) / 2) + V[:, 1, :, None] * ((1 + x1) / 2)
+         + V[:, 2, :, None] * ((1 + x2) / 2) + V[:, 3, :, None] * ((1 + x3) / 2))     # (E, 3, nq)
+    Wm = warp_jacobian(X, amp)                                                        # (E, c, b, nq)
+    return np.einsum("ecbq,eba->ecaq", Wm, A)
+
+
 # ----------------------------------------------------------- draws
 
 def varp_orders(seed_: int, nelem: int, lo: int = 2, hi: int = 10) -> np.ndarray:
