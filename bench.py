@@ -307,6 +307,54 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
     return out
 
 
+def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30):
+    """Collapsed-coordinate tetrahedra: the unit cube split into n^3 cubes of
+    six curved tetrahedra each, BwdTrans / IProductWRTBase / Helmholtz per
+    order, FP64 and FP32.  Algorithmic bytes per element (nm modes,
+    np = Q (Q-1)^2 points, s bytes): BwdTrans s(nm + np), IProductWRTBase
+    s(2 np + nm), Helmholtz s(2 nm + 7 np) (7 factors per point)."""
+    out = {}
+    for n, P in cases:
+        Q = P + 2
+        e1, _, e2, _, e3, _ = nk.tet_points(Q)
+        J = torch.from_numpy(W.tet_lattice_jacobians(n, e1, e2, e3)).cuda()
+        space = nk.Space.create_tet(P, Q, J)
+        del J
+        E = 6 * n ** 3
+        nm, npt = (P + 1) * (P + 2) * (P + 3) // 6, Q * (Q - 1) ** 2
+        res = {"nelem": E}
+        for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
+            td = torch.float64 if dt == nk.F64 else torch.float32
+            cs = [torch.from_numpy(W.uniform(W.seed(1, 0) + k, E * nm)).to(td).cuda() for k in range(3)]
+            fs = [torch.from_numpy(W.uniform(W.seed(1, 1) + k, E * npt)).to(td).cuda() for k in range(3)]
+            us = [torch.empty(E * npt, dtype=td, device="cuda") for _ in range(3)]
+            ys = [torch.empty(E * nm, dtype=td, device="cuda") for _ in range(3)]
+            for op, bpe, fn in (
+                ("bwd_trans", s * (nm + npt), lambda k: nk.bwd_trans(space, cs[k], us[k], dtype=dt)),
+                ("iprod_wrt_base", s * (2 * npt + nm), lambda k: nk.iprod_wrt_base(space, fs[k], ys[k], dtype=dt)),
+                ("helmholtz", s * (2 * nm + 7 * npt), lambda k: nk.helmholtz(space, cs[k], ys[k], lam0=1.0, dtype=dt)),
+            ):
+                for k in range(3):
+                    fn(k)
+                cnt = [0]
+
+                def step():
+                    fn(cnt[0] % 3)
+                    cnt[0] += 1
+                ms = time_launches(step, reps, torch)
+                gbs = bpe * E / (ms * 1e-3) / 1e9
+                res[f"{op}_{name}"] = {"ms": round(ms, 5), "gdof_s": round(E * nm / (ms * 1e-3) / 1e9, 3),
+                                       "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            del cs, fs, us, ys
+        out[f"P{P}"] = res
+        log(f"tet P={P} ({E} elements): helmholtz f64 {res['helmholtz_f64']['ms'] * 1e3:.1f} us "
+            f"({res['helmholtz_f64']['hbm_frac']:.1%} HBM), bwd {res['bwd_trans_f64']['hbm_frac']:.1%}, "
+            f"iprod {res['iprod_wrt_base_f64']['hbm_frac']:.1%}")
+        del space
+        torch.cuda.empty_cache()
+    return out
+
+
 def section_tri_solve(nk, W, torch, n=128, orders=(4, 6)):
     """Assembled C0 solve on 2 n^2 curved triangles of the unit square with
     rotated local vertex orders (orientation signs on the shared edges),
@@ -632,8 +680,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="ops,deriv,tri,cg,batch,grad,cpu",
-                    help="comma list of ops,deriv,tri,cg,batch,grad,cpu (or 'none')")
+    ap.add_argument("--sections", default="ops,deriv,tri,tet,cg,batch,grad,cpu",
+                    help="comma list of ops,deriv,tri,tet,cg,batch,grad,cpu (or 'none')")
     ap.add_argument("--cg-orders", default="4,6,8")
     ap.add_argument("--calib", action="store_true",
                     help="after the timed region, one 1 GiB device-to-device copy (counter calibration)")
@@ -715,6 +763,9 @@ def main():
         sections["tri_131072"] = section_tri(nk, W, torch)
         log("section tri solve ...")
         sections["tri_solve_32768"] = section_tri_solve(nk, W, torch)
+    if "tet" in secs:
+        log("section tet ...")
+        sections["tet"] = section_tet(nk, W, torch)
     del space, x, y
     torch.cuda.empty_cache()
     if "cg" in secs:
