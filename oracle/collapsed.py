@@ -39,6 +39,13 @@ are grouped by triangle mode (in triangle order, r fastest), D last:
 (P+1)(P+2)(P+3)/6 modes spanning total degree <= P.  Quadrature: Q GLL
 points in eta_1, Q-1 Gauss-Radau points of the weight (1-eta_2) in eta_2 and
 Q-1 of the weight (1-eta_3)^2 in eta_3; point q = i + Q (j + (Q-1) k).
+
+Prisms: the triangle above in (xi_1, xi_2), extruded along xi_3 in [-1, 1]
+(eta_1 = 2 (1 + xi_1)/(1 - xi_2) - 1, eta_2 = xi_2, xi_3 uncollapsed).  Every
+mode is a triangle mode times the 1-D modified basis phi_r(xi_3), r = 0..P,
+grouped by triangle mode with r fastest: (P+1)^2 (P+2)/2 modes spanning
+P_P(triangle) x P_P(line).  Quadrature: GLL (Q) x Radau of (1-eta_2) (Q-1) x
+GLL (Q); point q = i + Q (j + (Q-1) k).
 """
 from __future__ import annotations
 
@@ -284,6 +291,9 @@ class TetOps:
         dxi2 = c1 * g * D1 + (2.0 / (1 - e3))[:, None] * D2
         dxi3 = c1 * g * D1 + ((1 + e2) / (1 - e3))[:, None] * D2 + D3
         self.Dt = [dxi1, dxi2, dxi3]
+        self._geometry(J, kappa, lam)
+
+    def _geometry(self, J, kappa, lam):
         Jm = np.moveaxis(np.asarray(J, np.float64), -1, 1)          # (E, nq, c, a)
         self.detJ = np.linalg.det(Jm)
         Ji = np.linalg.inv(Jm)
@@ -323,3 +333,52 @@ class TetOps:
     def fwd(self, f):
         rhs = self.iprod(f)
         return np.stack([np.linalg.solve(self.mass_matrix(e), rhs[e]) for e in range(self.nelem)])
+
+
+# ----------------------------------------------------------------- prisms
+
+def prism_modes(P: int):
+    """List of (t, r) in coefficient order: triangle mode t, r = 0..P."""
+    return [(t, r) for t in range(len(tri_modes(P))) for r in range(P + 1)]
+
+
+def prism_basis(P: int, e1, e2, x3):
+    """Basis values and derivatives at points (eta_1, eta_2, xi_3):
+    (Phi, dPhi/deta_1, dPhi/deta_2, dPhi/dxi_3), each (npts, nmodes)."""
+    T, T1, T2 = tri_basis(P, e1, e2)
+    B, DB = modified_basis(P, np.asarray(x3, np.float64))
+    modes = prism_modes(P)
+    Phi = np.stack([T[:, t] * B[:, r] for t, r in modes], axis=1)
+    D1 = np.stack([T1[:, t] * B[:, r] for t, r in modes], axis=1)
+    D2 = np.stack([T2[:, t] * B[:, r] for t, r in modes], axis=1)
+    D3 = np.stack([T[:, t] * DB[:, r] for t, r in modes], axis=1)
+    return Phi, D1, D2, D3
+
+
+def prism_points(Q: int):
+    """eta_1 (GLL, Q), eta_2 (Radau of (1-x), Q-1), xi_3 (GLL, Q) and the
+    weights of dxi at every point q = i + Q (j + (Q-1) k)."""
+    x1, w1 = gll(Q)
+    x2, w2 = gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    n2 = Q - 1
+    E1 = np.tile(x1, n2 * Q)
+    E2 = np.tile(np.repeat(x2, Q), Q)
+    X3 = np.repeat(x1, Q * n2)
+    W = (np.outer(w1, np.outer(w2 / 2, w1).ravel())).ravel()
+    return E1, E2, X3, W
+
+
+class PrismOps(TetOps):
+    """Dense elemental operators of straight- or curved-sided prisms of order
+    P with the quadrature of prism_points(Q).  J[e, c, a, q] = d x_c / d xi_a."""
+
+    def __init__(self, P, Q, J, kappa=None, lam=1.0):
+        self.P, self.Q = int(P), int(Q)
+        self.e1, self.e2, self.e3, self.W = prism_points(self.Q)
+        self.Bt, D1, D2, D3 = prism_basis(self.P, self.e1, self.e2, self.e3)
+        e1, e2 = self.e1, self.e2
+        # d eta / d xi of the collapsed triangle; xi_3 is not collapsed
+        self.Dt = [(2.0 / (1 - e2))[:, None] * D1,
+                   ((1 + e1) / (1 - e2))[:, None] * D1 + D2,
+                   D3]
+        self._geometry(J, kappa, lam)

@@ -463,6 +463,43 @@ def tet_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems
     return np.einsum("ecbq,eba->ecaq", Wm, A)
 
 
+def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, elems=None):
+    """Jacobians of the prismatic mesh of the unit cube: the triangle mesh of
+    the unit square (tri_lattice_vertices) extruded into n layers, prism
+    e = layer * 2 n^2 + triangle, curved by the cyclic warp.  With the
+    triangle's vertices (A, B, C) and the layer [z0, z0 + h], the affine
+    reference map is (x, y) = A (-(xi_1 + xi_2)/2) + B (1 + xi_1)/2
+    + C (1 + xi_2)/2, z = z0 + h (1 + xi_3)/2, taken at the points of the 1-D
+    sets (e1 = eta_1, e2 = eta_2 = xi_2, x3 = xi_3), q = i + len(e1) (j +
+    len(e2) k), xi_1 = (1 + eta_1)(1 - eta_2)/2 - 1.  Returns J[E, c, a, q]."""
+    e1, e2, x3 = (np.asarray(v, np.float64) for v in (e1, e2, x3))
+    n1, n2 = e1.size, e2.size
+    E1 = np.tile(e1, n2 * x3.size)
+    E2 = np.tile(np.repeat(e2, n1), x3.size)
+    X3 = np.repeat(x3, n1 * n2)
+    xi1 = (1 + E1) * (1 - E2) / 2 - 1
+    xi2 = E2
+    h = 1.0 / n
+    V = tri_lattice_vertices(n)
+    xy = np.stack([V % (n + 1), V // (n + 1)], axis=-1) * h          # (2 n^2, 3, 2)
+    nt = xy.shape[0]
+    e = np.arange(n * nt) if elems is None else np.asarray(elems)
+    tri, layer = e % nt, e // nt
+    T = xy[tri]
+    A = np.zeros((e.size, 3, 3))
+    A[:, :2, 0] = (T[:, 1] - T[:, 0]) / 2
+    A[:, :2, 1] = (T[:, 2] - T[:, 0]) / 2
+    A[:, 2, 2] = h / 2
+    if amp == 0.0:
+        return np.broadcast_to(A[:, :, :, None], A.shape + (xi1.size,)).copy()
+    XY = (T[:, 0, :, None] * (-(xi1 + xi2) / 2) + T[:, 1, :, None] * ((1 + xi1) / 2)
+          + T[:, 2, :, None] * ((1 + xi2) / 2))                          # (E, 2, nq)
+    Z = layer[:, None] * h + h * (1 + X3[None, :]) / 2
+    X = np.concatenate([XY, Z[:, None, :]], axis=1)
+    Wm = warp_jacobian(X, amp)
+    return np.einsum("ecbq,eba->ecaq", Wm, A)
+
+
 # ----------------------------------------------------------- draws
 
 def varp_orders(seed_: int, nelem: int, lo: int = 2, hi: int = 10) -> np.ndarray:
