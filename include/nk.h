@@ -178,6 +178,17 @@ nk_status nk_tet_points(int Q, double* eta1, double* w1, double* eta2, double* w
 nk_status nk_space_create_tet(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
                               const double* kappa, void* stream);
 
+/* Prisms (section 2.1: the hexahedron with one direction collapsed): the
+ * triangle of nk_space_create_tri in (xi_1, xi_2), extruded along xi_3 in
+ * [-1, 1].  Quadrature: the triangle's points (nk_tri_points) times Q GLL
+ * points in xi_3 (nk_basis_tables); point q = i + Q (j + (Q-1) k).  Modes
+ * ((P+1)^2 (P+2)/2 per element): each triangle mode times the 1-D modified
+ * basis phi_r(xi_3), r = 0..P, grouped by triangle mode with r fastest.
+ * jac: device [E][3][3][Q^2 (Q-1)] FP64, kappa: device [E][Q^2 (Q-1)] or
+ * NULL; supported calls and errors as for tetrahedra. */
+nk_status nk_space_create_prism(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                                const double* kappa, void* stream);
+
 /* Sizes of a space: total elements, coefficients (sum n^d) and points
  * (sum Q^d).  Any output may be NULL. */
 nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints);

@@ -1,7 +1,14 @@
-// Collapsed-coordinate tetrahedra (section 2.1: the tetrahedron is a hexahedron
-// collapsed twice through the Duffy map; section 3.3: the expansion factors
-// in the collapsed coordinates, so the operators stay sum-factorised).
+// Collapsed-coordinate tetrahedra and prisms (section 2.1: shapes reached
+// from the hexahedron through the Duffy map, collapsing two directions for
+// the tetrahedron and one for the prism; section 3.3: the expansion factors in
+// the collapsed coordinates, so the operators stay sum-factorised).
 // Elemental BwdTrans, IProductWRTBase and Helmholtz.
+//
+// Prisms: the triangle of tri.hip in (xi_1, xi_2) extruded along xi_3, every
+// mode a triangle mode times the 1-D modified basis phi_r(xi_3), r = 0..P
+// (r fastest); Q GLL points in xi_3.  The kernel below serves both shapes:
+// for a prism the eta_3 table holds phi_r at the GLL points and there is no
+// top vertex.
 //
 // Basis: every mode is a triangle mode T_t(eta_1, eta_2) of the order-P
 // triangle (tri.hip), of total degree s_t, times an eta_3 factor c_{s,r}:
@@ -30,17 +37,25 @@
 
 namespace nk {
 
-template <int P>
+constexpr int kTet = 0, kPrism = 1;
+
+template <int P, int SH>
 struct TetShape {
-  static constexpr int N = P + 1, Q = P + 2, Q2 = Q - 1, NS = Q2 * Q2, NPT = Q * NS;
+  static constexpr int N = P + 1, Q = P + 2, Q2 = Q - 1;
+  static constexpr int Q3 = SH == kTet ? Q - 1 : Q;      // points in the third direction
+  static constexpr int NS = Q2 * Q3, NPT = Q * NS;
   static constexpr int NMT = N * (N + 1) / 2;            // triangle modes
-  static constexpr int NM3 = N * (N + 1) * (N + 2) / 6;  // tetrahedron modes
+  static constexpr int NM3 = SH == kTet ? N * (N + 1) * (N + 2) / 6 : NMT * N;
+  // columns of the third-direction table: one per mode for tetrahedra, one
+  // per 1-D mode r for prisms (the factor depends on r only)
+  static constexpr int NC = SH == kTet ? NM3 : N;
   // LDS row strides (in scalars), odd so that distinct rows fall into
   // distinct banks
-  static constexpr int TS = NMT | 1, CS = NM3 | 1;
-  static constexpr int NTAB = 2 * Q2 * TS + 2 * Q2 * CS;        // B2, dB2, C3, dC3
+  static constexpr int TS = NMT | 1, CS = NC | 1;
+  static constexpr int NTAB = 2 * Q2 * TS + 2 * Q3 * CS;        // B2, dB2, C3, dC3
+  static constexpr int ccol(int m) { return SH == kTet ? m : m % N; }
   static constexpr int NITAB = 2 * NMT + 1 + NM3;               // toff3, tp, mt
-  static constexpr int SLOT = NM3 + 2 * Q2 * NMT + 3 * NS * N;  // u, w | w', SA | SB | SC
+  static constexpr int SLOT = NM3 + 2 * Q3 * NMT + 3 * NS * N;  // u, w | w', SA | SB | SC
   // tetrahedra per block: up to 256 threads, within ~150 KB of LDS
   template <typename T>
   static constexpr int epb() {
@@ -58,31 +73,41 @@ struct TetShape {
 };
 
 // Device tables of order P: B2 [Q2][NMT], dB2 [Q2][NMT] at the eta_2 points,
-// C3 [Q2][NM3], dC3 [Q2][NM3] at the eta_3 points (scalars of type T), and
-// the integer maps toff3 [NMT+1] (first coefficient of each triangle mode),
-// tp [NMT] (eta_1 index p of each triangle mode), mt [NM3] (triangle mode of
-// each coefficient, -1 for the top vertex).
+// C3 [Q3][NC], dC3 [Q3][NC] at the third-direction points (NC = NM3 for
+// tetrahedra, P+1 for prisms; scalars of type T), and the integer maps toff3 [NMT+1] (first coefficient of each triangle
+// mode), tp [NMT] (eta_1 index p of each triangle mode), mt [NM3] (triangle
+// mode of each coefficient, -1 for the top vertex).
 struct TetTables {
   const void* tab = nullptr;
   const int* itab = nullptr;
 };
 
 template <typename T>
-static TetTables tet_tables(int P) {
+static TetTables tet_tables(int P, int sh) {
   static std::mutex mu;
   static std::unordered_map<long, TetTables> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return {};
-  const long key = dev * 64L + P;
+  const long key = (dev * 64L + P) * 2 + sh;
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  const int N = P + 1, Q = P + 2, Q2 = Q - 1, NMT = N * (N + 1) / 2, NM3 = N * (N + 1) * (N + 2) / 6;
-  std::vector<double> e1(Q), w1(Q), e2(Q2), w2(Q2), e3(Q2), w3(Q2);
-  tet_points(Q, e1.data(), w1.data(), e2.data(), w2.data(), e3.data(), w3.data());
-  std::vector<double> B2(Q2 * NMT), dB2(Q2 * NMT), C3(Q2 * NM3), dC3(Q2 * NM3);
+  const int N = P + 1, Q = P + 2, Q2 = Q - 1, NMT = N * (N + 1) / 2;
+  const int Q3 = sh == kTet ? Q2 : Q, NM3 = sh == kTet ? N * (N + 1) * (N + 2) / 6 : NMT * N;
+  std::vector<double> e1(Q), w1(Q), e2(Q2), w2(Q2), e3(Q3), w3(Q3);
+  if (sh == kTet) {
+    tet_points(Q, e1.data(), w1.data(), e2.data(), w2.data(), e3.data(), w3.data());
+  } else {
+    tri_points(Q, e1.data(), w1.data(), e2.data(), w2.data());
+    gll_points(Q, e3.data(), w3.data());
+  }
+  const int NC = sh == kTet ? NM3 : N;
+  std::vector<double> B2(Q2 * NMT), dB2(Q2 * NMT), C3(Q3 * NC), dC3(Q3 * NC);
   tri_btable(P, Q2, e2.data(), B2.data(), dB2.data());
-  tet_ctable(P, Q2, e3.data(), C3.data(), dC3.data());
+  if (sh == kTet)
+    tet_ctable(P, Q2, e3.data(), C3.data(), dC3.data());
+  else   // phi_r(xi_3)
+    modified_basis(P, Q, e3.data(), C3.data(), dC3.data());
   std::vector<T> h;
   for (const auto* v : {&B2, &dB2, &C3, &dC3})
     for (double x : *v) h.push_back((T)x);
@@ -93,12 +118,12 @@ static TetTables tet_tables(int P) {
     for (int q = 0; q < nq; ++q, ++t) {
       it_[t] = m;                 // toff3
       it_[NMT + 1 + t] = p;       // tp
-      const int s = tri_mode_degree(P, p, q);
-      for (int r = 0; r <= P - s; ++r, ++m) it_[2 * NMT + 1 + m] = t;   // mt
+      const int nr = sh == kTet ? P - tri_mode_degree(P, p, q) + 1 : N;
+      for (int r = 0; r < nr; ++r, ++m) it_[2 * NMT + 1 + m] = t;   // mt
     }
   }
-  it_[NMT] = m;                   // end of the last group; m = NM3 - 1 (top vertex)
-  it_[2 * NMT + 1 + m] = -1;
+  it_[NMT] = m;                   // end of the last group
+  if (sh == kTet) it_[2 * NMT + 1 + m] = -1;   // m = NM3 - 1: the top vertex
   TetTables out;
   T* d = nullptr;
   int* di = nullptr;
@@ -119,13 +144,14 @@ static TetTables tet_tables(int P) {
   return out;
 }
 
-template <typename T, int P, int OP>
+template <typename T, int P, int SH, int OP>
 __global__ void __launch_bounds__(256)
     k_tet(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const int* __restrict__ itab,
           const DevArgs<T> a) {
-  using S = TetShape<P>;
-  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NS = S::NS, NPT = S::NPT;
-  constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS;
+  using S = TetShape<P, SH>;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
+  constexpr bool TET = SH == kTet;
+  constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS, NC = S::NC;
   constexpr int EPB = S::template epb<T>();
   constexpr bool HELM = OP == OP_HELM;
   constexpr int VA = 0, VC = P, VB = NMT - P;   // triangle vertex modes A, C, B
@@ -137,17 +163,17 @@ __global__ void __launch_bounds__(256)
     stab[r * TS + m] = tab[k];
     stab[(Q2 + r) * TS + m] = tab[Q2 * NMT + k];
   }
-  for (int k = threadIdx.x; k < Q2 * NM3; k += blockDim.x) {
-    const int r = k / NM3, m = k - r * NM3;
+  for (int k = threadIdx.x; k < Q3 * NC; k += blockDim.x) {
+    const int r = k / NC, m = k - r * NC;
     stab[2 * Q2 * TS + r * CS + m] = tab[2 * Q2 * NMT + k];
-    stab[2 * Q2 * TS + (Q2 + r) * CS + m] = tab[2 * Q2 * NMT + Q2 * NM3 + k];
+    stab[2 * Q2 * TS + (Q3 + r) * CS + m] = tab[2 * Q2 * NMT + Q3 * NC + k];
   }
   for (int k = threadIdx.x; k < S::NITAB; k += blockDim.x) sit[k] = itab[k];
   __syncthreads();
   const T* B2 = stab;
   const T* dB2 = stab + Q2 * TS;
   const T* C3 = stab + 2 * Q2 * TS;
-  const T* dC3 = C3 + Q2 * CS;
+  const T* dC3 = C3 + Q3 * CS;
   const int* toff3 = sit;
   const int* tp = sit + NMT + 1;
   const int* mt = tp + NMT;
@@ -157,9 +183,9 @@ __global__ void __launch_bounds__(256)
   const int t = threadIdx.x - slot0 * NS;           // row lane: t = j + Q2 k
   const int j = act ? t % Q2 : 0, k = act ? t / Q2 : 0;
   T* U = smem + slot * S::SLOT;                     // [NM3] coefficients
-  T* W = U + NM3;                                   // [Q2][NMT] w, later z
-  T* W3 = W + Q2 * NMT;                             // [Q2][NMT] dw/deta_3, later z'
-  T* SS = W3 + Q2 * NMT;                            // [3][NS][N]
+  T* W = U + NM3;                                   // [Q3][NMT] w, later z
+  T* W3 = W + Q3 * NMT;                             // [Q3][NMT] dw/deta_3, later z'
+  T* SS = W3 + Q3 * NMT;                            // [3][NS][N]
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
     const int64_t e = g * EPB + slot;
@@ -173,19 +199,21 @@ __global__ void __launch_bounds__(256)
       __syncthreads();
       // eta_3 stage: w_t(k') (and dw/deta_3) for every (k', t) pair
       if (live) {
-        for (int idx = t; idx < Q2 * NMT; idx += NS) {
+        for (int idx = t; idx < Q3 * NMT; idx += NS) {
           const int kk = idx / NMT, tt = idx - kk * NMT;
           const int o = toff3[tt], c = toff3[tt + 1] - o;
-          const T* cr = C3 + kk * CS + o;
-          const T* dcr = dC3 + kk * CS + o;
+          const T* cr = C3 + kk * CS + (TET ? o : 0);
+          const T* dcr = dC3 + kk * CS + (TET ? o : 0);
           T w = T(0), w3 = T(0);
           for (int r = 0; r < c; ++r) {
             w += cr[r] * U[o + r];
             if constexpr (HELM) w3 += dcr[r] * U[o + r];
           }
-          if (tt == VA || tt == VB || tt == VC) {   // the top vertex rides on A + B + C
-            w += C3[kk * CS + NM3 - 1] * U[NM3 - 1];
-            if constexpr (HELM) w3 += dC3[kk * CS + NM3 - 1] * U[NM3 - 1];
+          if constexpr (TET) {
+            if (tt == VA || tt == VB || tt == VC) {   // the top vertex rides on A + B + C
+              w += C3[kk * CS + NM3 - 1] * U[NM3 - 1];
+              if constexpr (HELM) w3 += dC3[kk * CS + NM3 - 1] * U[NM3 - 1];
+            }
           }
           W[kk * NMT + tt] = w;
           if constexpr (HELM) W3[kk * NMT + tt] = w3;
@@ -288,7 +316,7 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     // transposed eta_2 stage: z_t(k'), z'_t(k') for every (k', t) pair
     if (live) {
-      for (int idx = t; idx < Q2 * NMT; idx += NS) {
+      for (int idx = t; idx < Q3 * NMT; idx += NS) {
         const int kk = idx / NMT, tt = idx - kk * NMT, p = tp[tt];
         T z = T(0), z3 = T(0);
 #pragma unroll
@@ -321,15 +349,16 @@ __global__ void __launch_bounds__(256)
       for (int m = t; m < NM3; m += NS) {
         const int tt = mt[m];
         T y = T(0);
-        if (tt >= 0) {
+        if (!TET || tt >= 0) {
+          const int cm = S::ccol(m);
 #pragma unroll
-          for (int kk = 0; kk < Q2; ++kk) {
-            y += C3[kk * CS + m] * W[kk * NMT + tt];
-            if constexpr (HELM) y += dC3[kk * CS + m] * W3[kk * NMT + tt];
+          for (int kk = 0; kk < Q3; ++kk) {
+            y += C3[kk * CS + cm] * W[kk * NMT + tt];
+            if constexpr (HELM) y += dC3[kk * CS + cm] * W3[kk * NMT + tt];
           }
         } else {   // top vertex
 #pragma unroll
-          for (int kk = 0; kk < Q2; ++kk) {
+          for (int kk = 0; kk < Q3; ++kk) {
             const T* zr = W + kk * NMT;
             y += C3[kk * CS + m] * (zr[VA] + zr[VB] + zr[VC]);
             if constexpr (HELM) {
@@ -345,7 +374,7 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <typename T, int P>
+template <typename T, int P, int SH>
 static int64_t tet_grid(int op) {
   static std::unordered_map<int, int64_t> cached;
   static std::mutex mu;
@@ -355,77 +384,87 @@ static int64_t tet_grid(int op) {
   const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : 2);
   auto it = cached.find(key);
   if (it != cached.end()) return it->second;
-  using S = TetShape<P>;
+  using S = TetShape<P, SH>;
   constexpr int threads = (S::template epb<T>() * S::NS + 63) / 64 * 64;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const void* fn = op == OP_BWD     ? (const void*)k_tet<T, P, OP_BWD>
-                   : op == OP_IPROD ? (const void*)k_tet<T, P, OP_IPROD>
-                                    : (const void*)k_tet<T, P, OP_HELM>;
+  const void* fn = op == OP_BWD     ? (const void*)k_tet<T, P, SH, OP_BWD>
+                   : op == OP_IPROD ? (const void*)k_tet<T, P, SH, OP_IPROD>
+                                    : (const void*)k_tet<T, P, SH, OP_HELM>;
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0);
   const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (nb > 0 ? nb : 1) * 4;
   cached[key] = grid;
   return grid;
 }
 
-template <typename T, int P>
+template <typename T, int P, int SH>
 static hipError_t run_tet(const OpArgs& a) {
-  using S = TetShape<P>;
-  const TetTables tt = tet_tables<T>(P);
+  using S = TetShape<P, SH>;
+  const TetTables tt = tet_tables<T>(P, SH);
   if (!tt.tab) return hipErrorOutOfMemory;
   constexpr int EPB = S::template epb<T>();
   constexpr int threads = (EPB * S::NS + 63) / 64 * 64;
   static_assert(threads <= 256, "block size");
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
-  const int64_t gmax = tet_grid<T, P>(a.op);
+  const int64_t gmax = tet_grid<T, P, SH>(a.op);
   const int64_t nb = ngrp < gmax ? ngrp : gmax;
   const Tab<T, P + 1, P + 2>& tb = host_tab<T, P + 1, P + 2>();
   const DevArgs<T> d = dev_args<T>(a);
   const T* tab = static_cast<const T*>(tt.tab);
   const dim3 g((unsigned)nb), b(threads);
   switch (a.op) {
-    case OP_BWD: hipLaunchKernelGGL((k_tet<T, P, OP_BWD>), g, b, 0, a.stream, tb, tab, tt.itab, d); break;
-    case OP_IPROD:
-      hipLaunchKernelGGL((k_tet<T, P, OP_IPROD>), g, b, 0, a.stream, tb, tab, tt.itab, d);
+    case OP_BWD:
+      hipLaunchKernelGGL((k_tet<T, P, SH, OP_BWD>), g, b, 0, a.stream, tb, tab, tt.itab, d);
       break;
-    case OP_HELM: hipLaunchKernelGGL((k_tet<T, P, OP_HELM>), g, b, 0, a.stream, tb, tab, tt.itab, d); break;
+    case OP_IPROD:
+      hipLaunchKernelGGL((k_tet<T, P, SH, OP_IPROD>), g, b, 0, a.stream, tb, tab, tt.itab, d);
+      break;
+    case OP_HELM:
+      hipLaunchKernelGGL((k_tet<T, P, SH, OP_HELM>), g, b, 0, a.stream, tb, tab, tt.itab, d);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <int P>
+template <int P, int SH>
 static hipError_t run_tet_p(nk_dtype t, const OpArgs& a) {
-  return t == NK_F64 ? run_tet<double, P>(a) : run_tet<float, P>(a);
+  return t == NK_F64 ? run_tet<double, P, SH>(a) : run_tet<float, P, SH>(a);
 }
 
-hipError_t launch_tet(nk_dtype t, const OpArgs& a) {
+template <int SH>
+static hipError_t launch_col(nk_dtype t, const OpArgs& a) {
   if (a.nelem == 0) return hipSuccess;
   switch (a.P) {
-    case 1: return run_tet_p<1>(t, a);
-    case 2: return run_tet_p<2>(t, a);
-    case 3: return run_tet_p<3>(t, a);
-    case 4: return run_tet_p<4>(t, a);
-    case 5: return run_tet_p<5>(t, a);
-    case 6: return run_tet_p<6>(t, a);
-    case 7: return run_tet_p<7>(t, a);
-    case 8: return run_tet_p<8>(t, a);
-    case 9: return run_tet_p<9>(t, a);
-    case 10: return run_tet_p<10>(t, a);
+    case 1: return run_tet_p<1, SH>(t, a);
+    case 2: return run_tet_p<2, SH>(t, a);
+    case 3: return run_tet_p<3, SH>(t, a);
+    case 4: return run_tet_p<4, SH>(t, a);
+    case 5: return run_tet_p<5, SH>(t, a);
+    case 6: return run_tet_p<6, SH>(t, a);
+    case 7: return run_tet_p<7, SH>(t, a);
+    case 8: return run_tet_p<8, SH>(t, a);
+    case 9: return run_tet_p<9, SH>(t, a);
+    case 10: return run_tet_p<10, SH>(t, a);
   }
   return hipErrorInvalidValue;
 }
 
-// Factors of the collapsed tetrahedron at every point (thread per point):
-// f0 = w detJ with w = w1_i (w2_j / 2) (w3_k / 4) (the Radau weights carry
-// (1 - eta_2) and (1 - eta_3)^2), f1..f6 = w detJ kappa (M G M^T)_{11,12,13,
-// 22,23,33} with G = J^{-1} J^{-T} and M_ba = d eta_b / d xi_a.  Layout
-// [E][7][Q][(Q-1)^2]: for each factor and eta_1 index i, the rows j + (Q-1) k
-// are contiguous, the order in which the operator's threads read them.
+hipError_t launch_tet(nk_dtype t, const OpArgs& a) { return launch_col<kTet>(t, a); }
+hipError_t launch_prism(nk_dtype t, const OpArgs& a) { return launch_col<kPrism>(t, a); }
+
+// Factors of the collapsed tetrahedron or prism at every point (thread per
+// point): f0 = w detJ, f1..f6 = w detJ kappa (M G M^T)_{11,12,13,22,23,33}
+// with G = J^{-1} J^{-T} and M_ba = d eta_b / d xi_a.  Tetrahedron: w = w1_i
+// (w2_j / 2) (w3_k / 4) (the Radau weights carry (1 - eta_2) and
+// (1 - eta_3)^2); prism: w = w1_i (w2_j / 2) w3_k.  Layout [E][7][Q][NS]:
+// for each factor and eta_1 index i, the rows j + (Q-1) k are contiguous, the
+// order in which the operator's threads read them.
+template <int SH>
 __global__ void __launch_bounds__(256)
     k_geom_tet(int Q, int64_t nelem, const double* __restrict__ jac, const double* __restrict__ kappa,
                const double* __restrict__ pts, double* __restrict__ fac64, float* __restrict__ fac32,
                int* __restrict__ bad) {
-  const int Q2 = Q - 1, NS = Q2 * Q2, NP = Q * NS;
+  const int Q2 = Q - 1, Q3 = SH == kTet ? Q - 1 : Q, NS = Q2 * Q3, NP = Q * NS;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nelem * NP) return;
   const int64_t e = id / NP;
@@ -433,7 +472,7 @@ __global__ void __launch_bounds__(256)
   const int i = q % Q, row = q / Q, j = row % Q2, k = row / Q2;
   const double e1 = pts[i], w1 = pts[Q + i];
   const double e2 = pts[2 * Q + j], w2 = pts[2 * Q + Q2 + j];
-  const double e3 = pts[2 * Q + 2 * Q2 + k], w3 = pts[2 * Q + 3 * Q2 + k];
+  const double e3 = pts[2 * Q + 2 * Q2 + k], w3 = pts[2 * Q + 2 * Q2 + Q3 + k];
   double J[3][3];
   for (int c = 0; c < 3; ++c)
     for (int b = 0; b < 3; ++b) J[c][b] = jac[((e * 3 + c) * 3 + b) * NP + q];
@@ -456,10 +495,21 @@ __global__ void __launch_bounds__(256)
     for (int b = 0; b < 3; ++b)
       G[a_][b] = Ji[a_][0] * Ji[b][0] + Ji[a_][1] * Ji[b][1] + Ji[a_][2] * Ji[b][2];
   // M[b][a] = d eta_b / d xi_a of the collapsed map
-  const double g = 2.0 / ((1.0 - e2) * (1.0 - e3));
-  const double M[3][3] = {{2.0 * g, (1.0 + e1) * g, (1.0 + e1) * g},
-                          {0.0, 2.0 / (1.0 - e3), (1.0 + e2) / (1.0 - e3)},
-                          {0.0, 0.0, 1.0}};
+  double M[3][3];
+  if (SH == kTet) {
+    const double g = 2.0 / ((1.0 - e2) * (1.0 - e3));
+    const double Mt[3][3] = {{2.0 * g, (1.0 + e1) * g, (1.0 + e1) * g},
+                             {0.0, 2.0 / (1.0 - e3), (1.0 + e2) / (1.0 - e3)},
+                             {0.0, 0.0, 1.0}};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) M[r][c] = Mt[r][c];
+  } else {   // prism: eta_1 = 2 (1 + xi_1)/(1 - xi_2) - 1, eta_2 = xi_2, xi_3
+    const double Mp[3][3] = {{2.0 / (1.0 - e2), (1.0 + e1) / (1.0 - e2), 0.0},
+                             {0.0, 1.0, 0.0},
+                             {0.0, 0.0, 1.0}};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) M[r][c] = Mp[r][c];
+  }
   double H[3][3];   // M G M^T
   for (int a_ = 0; a_ < 3; ++a_)
     for (int b = 0; b < 3; ++b) {
@@ -469,7 +519,7 @@ __global__ void __launch_bounds__(256)
       H[a_][b] = s;
     }
   const double kap = kappa ? kappa[e * NP + q] : 1.0;
-  const double wj = w1 * 0.5 * w2 * 0.25 * w3 * det;
+  const double wj = w1 * 0.5 * w2 * (SH == kTet ? 0.25 : 1.0) * w3 * det;
   const double ck = wj * kap;
   const double f[7] = {wj, ck * H[0][0], ck * H[0][1], ck * H[0][2], ck * H[1][1], ck * H[1][2], ck * H[2][2]};
   if (!(det > 0.0) || !(kap > 0.0)) atomicOr(bad, 1);
@@ -484,8 +534,17 @@ hipError_t launch_geom_tet(int Q, int64_t nelem, const double* jac, const double
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s) {
   const int64_t n = nelem * Q * (Q - 1) * (Q - 1);
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_geom_tet, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, nelem, jac,
-                     kappa, pts, fac64, fac32, bad);
+  hipLaunchKernelGGL(k_geom_tet<kTet>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, nelem,
+                     jac, kappa, pts, fac64, fac32, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_geom_prism(int Q, int64_t nelem, const double* jac, const double* kappa,
+                             const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s) {
+  const int64_t n = nelem * Q * (Q - 1) * Q;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_geom_tet<kPrism>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q,
+                     nelem, jac, kappa, pts, fac64, fac32, bad);
   return hipGetLastError();
 }
 

@@ -176,10 +176,15 @@ inline int64_t tri_fac_count(int Q, int64_t nelem) {
 hipError_t launch_tri(nk_dtype t, const OpArgs& a);   // also OP_HELM_ASM (assembled)
 hipError_t launch_diag_tri(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
                            const int32_t* l2g, double* diag, hipStream_t st);
-// Collapsed tetrahedra (tet.hip): BwdTrans, IProductWRTBase, Helmholtz.
+// Collapsed tetrahedra and prisms (collapsed3d.hip): BwdTrans,
+// IProductWRTBase, Helmholtz.  pts: e1, w1 (Q), e2, w2 (Q-1), e3, w3 (Q-1
+// for tetrahedra, Q for prisms).
 hipError_t launch_tet(nk_dtype t, const OpArgs& a);
+hipError_t launch_prism(nk_dtype t, const OpArgs& a);
 hipError_t launch_geom_tet(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
+hipError_t launch_geom_prism(int Q, int64_t nelem, const double* jac, const double* kappa,
+                             const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 hipError_t launch_geom_tri(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 

@@ -1,0 +1,115 @@
+"""GPU parity of the prism operators (BwdTrans, IProductWRTBase, Helmholtz
+with per-point kappa and per-element lambda) against the oracle's dense
+elemental matrices, on the curved prismatic mesh of the unit cube; FP64
+1e-12 and FP32 2e-6 relative 2-norm, as for the other operators."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import collapsed as C
+from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _jacobians(P, n, amp=W.WARP_AMPLITUDE, elems=None):
+    """(J at the library's points, J at the oracle's points)."""
+    m = nk()
+    Q = P + 2
+    e1g, _, e2g, _ = m.tri_points(Q)
+    Jg = W.prism_lattice_jacobians(n, e1g, e2g, e1g, amp, elems)
+    x, _ = oracle.gll(Q)
+    xr, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    Jo = W.prism_lattice_jacobians(n, x, xr, x, amp, elems)
+    return Jg, Jo
+
+
+@pytest.mark.parametrize("P", list(range(1, 11)))
+def test_prism_operators_match_oracle(P):
+    torch = torch_cuda()
+    m = nk()
+    Q = P + 2
+    Jg, Jo = _jacobians(P, 2 if P <= 6 else 1)
+    E, nq = Jg.shape[0], Q * Q * (Q - 1)
+    nm = (P + 1) ** 2 * (P + 2) // 2
+    rng = np.random.default_rng(270 + P)
+    kap = rng.uniform(0.5, 2.0, (E, nq))
+    lam = rng.uniform(0.5, 2.0, E)
+    ops = C.PrismOps(P, Q, Jo, kappa=kap, lam=lam)
+    space = m.Space.create_prism(P, Q, to_dev(Jg), kappa=to_dev(kap))
+    c = W.uniform(W.seed(0, 0) + 500 + P, (E, nm))
+    f = W.uniform(W.seed(0, 1) + 500 + P, (E, nq))
+    ref = [ops.bwd(c), ops.iprod(f), ops.helmholtz(c)]
+    for dt, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_RTOL)):
+        td = torch.float64 if dt == m.F64 else torch.float32
+        got = [m.bwd_trans(space, to_dev(c.ravel(), td), dtype=dt),
+               m.iprod_wrt_base(space, to_dev(f.ravel(), td), dtype=dt),
+               m.helmholtz(space, to_dev(c.ravel(), td), lam=to_dev(lam), dtype=dt)]
+        for name, g, r in zip(("bwd", "iprod", "helm"), got, ref):
+            assert_close(g.double().cpu().numpy(), r.ravel(), tol, f"prism {name} P={P} dt={dt}")
+
+
+def test_prism_helmholtz_constant_symmetry_and_errors():
+    """L 1 = 0 and x^T H y = y^T H x on the GPU at P = 4; an empty space;
+    systems and derivative calls are rejected; a mirrored element too."""
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 4, 6
+    Jg, _ = _jacobians(P, 2)
+    E = Jg.shape[0]
+    modes = C.prism_modes(P)
+    tri = C.tri_modes(P)
+    one = np.zeros(len(modes))
+    for v in ((0, 0), (P, 0), (0, P)):
+        for r in (0, P):
+            one[modes.index((tri.index(v), r))] = 1.0
+    space = m.Space.create_prism(P, Q, to_dev(Jg))
+    y = m.helmholtz(space, to_dev(np.tile(one, E)), lam0=0.0).cpu().numpy()
+    assert np.abs(y).max() < 1e-12
+    rng = np.random.default_rng(1)
+    a, b = rng.uniform(-1, 1, (2, E * len(modes)))
+    Ha = m.helmholtz(space, to_dev(a)).cpu().numpy()
+    Hb = m.helmholtz(space, to_dev(b)).cpu().numpy()
+    assert abs(b @ Ha - a @ Hb) < 1e-12 * abs(b @ Ha)
+    nq = Q * Q * (Q - 1)
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    assert m.bwd_trans(m.Space.create_prism(P, Q, to_dev(np.zeros((0, 3, 3, nq)))), e).numel() == 0
+    with pytest.raises(m.NkError) as ei:
+        m.phys_deriv(space, torch.zeros(E * nq, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    l2g = np.arange(E * len(modes), dtype=np.int32)
+    with pytest.raises(m.NkError) as ei:
+        m.System.create(space, l2g.size, to_dev(l2g), to_dev(np.zeros(l2g.size, np.uint8)))
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    bad = Jg.copy()
+    bad[0, :, 2] *= -1.0
+    with pytest.raises(m.NkError):
+        m.Space.create_prism(P, Q, to_dev(bad))
+
+
+def test_full_size_prisms_p4_sampled():
+    """The prismatic workload the benchmark times (2 x 24^3 = 27 648 curved
+    prisms, P=4, Q=6) at full size and in the same launch configuration; the
+    oracle checks a seeded sample of elements in FP64 and FP32."""
+    torch = torch_cuda()
+    m = nk()
+    n, P = 24, 4
+    Q = P + 2
+    E, nq, nm = 2 * n ** 3, Q * Q * (Q - 1), (P + 1) ** 2 * (P + 2) // 2
+    e1g, _, e2g, _ = m.tri_points(Q)
+    space = m.Space.create_prism(P, Q, to_dev(W.prism_lattice_jacobians(n, e1g, e2g, e1g)))
+    c = W.uniform(W.seed(1, 0), E * nm)
+    f = W.uniform(W.seed(1, 1), E * nq)
+    sample = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(9).choice(E, 10, replace=False)]))
+    _, Jo = _jacobians(P, n, elems=sample)
+    ops = C.PrismOps(P, Q, Jo)
+    cs, fs = c.reshape(E, nm)[sample], f.reshape(E, nq)[sample]
+    ref = [ops.bwd(cs), ops.iprod(fs), ops.helmholtz(cs)]
+    for dt, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_RTOL)):
+        td = torch.float64 if dt == m.F64 else torch.float32
+        got = [m.bwd_trans(space, to_dev(c, td), dtype=dt).double().cpu().numpy().reshape(E, nq),
+               m.iprod_wrt_base(space, to_dev(f, td), dtype=dt).double().cpu().numpy().reshape(E, nm),
+               m.helmholtz(space, to_dev(c, td), lam0=1.0, dtype=dt).double().cpu().numpy().reshape(E, nm)]
+        for name, g, r in zip(("bwd", "iprod", "helm"), got, ref):
+            assert_close(g[sample], r, tol, f"full-size prism {name} dt={dt}")
