@@ -307,21 +307,30 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
     return out
 
 
-def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30):
-    """Collapsed-coordinate tetrahedra: the unit cube split into n^3 cubes of
-    six curved tetrahedra each, BwdTrans / IProductWRTBase / Helmholtz per
-    order, FP64 and FP32.  Algorithmic bytes per element (nm modes,
-    np = Q (Q-1)^2 points, s bytes): BwdTrans s(nm + np), IProductWRTBase
-    s(2 np + nm), Helmholtz s(2 nm + 7 np) (7 factors per point)."""
+def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30, shape="tet"):
+    """Collapsed-coordinate tetrahedra (the unit cube split into n^3 cubes of
+    six curved tetrahedra each) or prisms (the triangle mesh of the unit
+    square extruded into n layers, 2 n^3 curved prisms): BwdTrans /
+    IProductWRTBase / Helmholtz per order, FP64 and FP32.  Algorithmic bytes
+    per element (nm modes, np points, s bytes): BwdTrans s(nm + np),
+    IProductWRTBase s(2 np + nm), Helmholtz s(2 nm + 7 np) (7 factors per
+    point)."""
     out = {}
     for n, P in cases:
         Q = P + 2
-        e1, _, e2, _, e3, _ = nk.tet_points(Q)
-        J = torch.from_numpy(W.tet_lattice_jacobians(n, e1, e2, e3)).cuda()
-        space = nk.Space.create_tet(P, Q, J)
+        if shape == "tet":
+            e1, _, e2, _, e3, _ = nk.tet_points(Q)
+            J = torch.from_numpy(W.tet_lattice_jacobians(n, e1, e2, e3)).cuda()
+            space = nk.Space.create_tet(P, Q, J)
+            E = 6 * n ** 3
+            nm, npt = (P + 1) * (P + 2) * (P + 3) // 6, Q * (Q - 1) ** 2
+        else:
+            e1, _, e2, _ = nk.tri_points(Q)
+            J = torch.from_numpy(W.prism_lattice_jacobians(n, e1, e2, e1)).cuda()
+            space = nk.Space.create_prism(P, Q, J)
+            E = 2 * n ** 3
+            nm, npt = (P + 1) ** 2 * (P + 2) // 2, Q * Q * (Q - 1)
         del J
-        E = 6 * n ** 3
-        nm, npt = (P + 1) * (P + 2) * (P + 3) // 6, Q * (Q - 1) ** 2
         res = {"nelem": E}
         for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
             td = torch.float64 if dt == nk.F64 else torch.float32
@@ -347,7 +356,7 @@ def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30):
                                        "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
             del cs, fs, us, ys
         out[f"P{P}"] = res
-        log(f"tet P={P} ({E} elements): helmholtz f64 {res['helmholtz_f64']['ms'] * 1e3:.1f} us "
+        log(f"{shape} P={P} ({E} elements): helmholtz f64 {res['helmholtz_f64']['ms'] * 1e3:.1f} us "
             f"({res['helmholtz_f64']['hbm_frac']:.1%} HBM), bwd {res['bwd_trans_f64']['hbm_frac']:.1%}, "
             f"iprod {res['iprod_wrt_base_f64']['hbm_frac']:.1%}")
         del space
@@ -766,6 +775,8 @@ def main():
     if "tet" in secs:
         log("section tet ...")
         sections["tet"] = section_tet(nk, W, torch)
+        log("section prism ...")
+        sections["prism"] = section_tet(nk, W, torch, cases=((24, 4), (24, 6), (16, 8)), shape="prism")
     del space, x, y
     torch.cuda.empty_cache()
     if "cg" in secs:

@@ -185,7 +185,10 @@ __global__ void __launch_bounds__(256)
   T* U = smem + slot * S::SLOT;                     // [NM3] coefficients
   T* W = U + NM3;                                   // [Q3][NMT] w, later z
   T* W3 = W + Q3 * NMT;                             // [Q3][NMT] dw/deta_3, later z'
-  T* SS = W3 + Q3 * NMT;                            // [3][NS][N]
+  T* SS = W3 + Q3 * NMT;                            // [3][NS][N]; point staging [NS][RS]
+  constexpr int SSO = NM3 + 2 * Q3 * NMT;           // offset of SS in a slot
+  constexpr int RS = Q | 1;                         // staged row stride (odd)
+  static_assert(NS * RS <= 3 * NS * N, "point staging fits the SA/SB/SC region");
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
     const int64_t e = g * EPB + slot;
@@ -254,13 +257,23 @@ __global__ void __launch_bounds__(256)
         }
       }
       if constexpr (OP == OP_BWD) {
+        // rows staged in LDS (row stride RS), then the block's contiguous run
+        // of point values leaves in one coalesced sweep
 #pragma unroll 1
         for (int i = 0; i < Q; ++i) {
           T u = T(0);
 #pragma unroll
           for (int p = 0; p < N; ++p) u += tb.B[i * N + p] * V[p];
-          if (live) a.out[e * NPT + i + Q * t] = u;
+          if (act) SS[t * RS + i] = u;
         }
+        __syncthreads();
+        const int64_t e0 = g * EPB;
+        const int ne = a.nelem - e0 < EPB ? (int)(a.nelem - e0) : EPB;
+        for (int idx = threadIdx.x; idx < ne * NPT; idx += blockDim.x) {
+          const int sl = idx / NPT, q = idx - sl * NPT, row = q / Q;
+          a.out[e0 * NPT + idx] = smem[sl * S::SLOT + SSO + row * RS + (q - row * Q)];
+        }
+        __syncthreads();
         continue;
       } else {
         const T lam = (T)(a.lam ? a.lam[live ? e : 0] : a.lam0);
@@ -292,7 +305,9 @@ __global__ void __launch_bounds__(256)
           }
         }
       }
-    } else {   // IProductWRTBase: point values times w detJ
+    } else {   // IProductWRTBase: point values times w detJ (read row by row:
+               // staging them through LDS measured slower, the barriers
+               // serialising the loads behind the arithmetic)
       const T* x = a.in + (live ? e : 0) * (int64_t)NPT + Q * t;
       const T* f = a.fac + (live ? e : 0) * (int64_t)(7 * NPT) + t;
 #pragma unroll 1
