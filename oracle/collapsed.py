@@ -46,6 +46,19 @@ mode is a triangle mode times the 1-D modified basis phi_r(xi_3), r = 0..P,
 grouped by triangle mode with r fastest: (P+1)^2 (P+2)/2 modes spanning
 P_P(triangle) x P_P(line).  Quadrature: GLL (Q) x Radau of (1-eta_2) (Q-1) x
 GLL (Q); point q = i + Q (j + (Q-1) k).
+
+Pyramids: base [-1, 1]^2 at xi_3 = -1, apex (-1, -1, 1) (xi_1 + xi_3 <= 0,
+xi_2 + xi_3 <= 0); eta_1 = 2 (1 + xi_1)/(1 - xi_3) - 1, eta_2 = 2 (1 + xi_2)/
+(1 - xi_3) - 1, eta_3 = xi_3.  Every mode is a base mode phi_p(eta_1)
+phi_q(eta_2) (1-D modified bases) with s = max(deg phi_p, deg phi_q), times
+((1-eta_3)/2)^s for r = 0 and ((1-eta_3)/2)^s (1+eta_3)/2
+P^{2s-1,1}_{r-1}(eta_3) for 1 <= r <= P - s, grouped by base mode (p slow, q
+fast, r fastest), plus the apex (1+eta_3)/2 last: (P+1)(P+2)(2P+3)/6 modes.
+The base face carries the tensor-product quadrilateral basis and each
+triangular face the triangle space above; the space contains every
+polynomial of total degree <= P (with rational functions beyond, as the
+collapsed construction gives).  Quadrature: GLL (Q) x GLL (Q) x Radau of
+(1-eta_3)^2 (Q-1); point q = i + Q (j + Q k).
 """
 from __future__ import annotations
 
@@ -381,4 +394,75 @@ class PrismOps(TetOps):
         self.Dt = [(2.0 / (1 - e2))[:, None] * D1,
                    ((1 + e1) / (1 - e2))[:, None] * D1 + D2,
                    D3]
+        self._geometry(J, kappa, lam)
+
+
+# --------------------------------------------------------------- pyramids
+
+def _deg1(P: int, p: int) -> int:
+    """Polynomial degree of the 1-D modified basis function p."""
+    return 1 if p in (0, P) else p + 1
+
+
+def pyr_modes(P: int):
+    """List of (p, q, s, r) in coefficient order; the apex last as
+    (-1, -1, 0, 1)."""
+    out = []
+    for p in range(P + 1):
+        for q in range(P + 1):
+            s = max(_deg1(P, p), _deg1(P, q))
+            out += [(p, q, s, r) for r in range(P - s + 1)]
+    return out + [(-1, -1, 0, 1)]
+
+
+def pyr_basis(P: int, e1, e2, e3):
+    """Basis values and collapsed derivatives at points (eta_1, eta_2,
+    eta_3): (Phi, d/deta_1, d/deta_2, d/deta_3), each (npts, nmodes)."""
+    e3 = np.asarray(e3, np.float64)
+    A1, D1a = modified_basis(P, np.asarray(e1, np.float64))
+    A2, D2a = modified_basis(P, np.asarray(e2, np.float64))
+    modes = pyr_modes(P)
+    Phi = np.zeros((e3.size, len(modes)))
+    D1, D2, D3 = np.zeros_like(Phi), np.zeros_like(Phi), np.zeros_like(Phi)
+    for m, (p, q, s, r) in enumerate(modes):
+        if p < 0:
+            Phi[:, m], D3[:, m] = (1 + e3) / 2, 0.5
+            continue
+        c, dc = _c_funcs(s, r, e3)
+        Phi[:, m] = A1[:, p] * A2[:, q] * c
+        D1[:, m] = D1a[:, p] * A2[:, q] * c
+        D2[:, m] = A1[:, p] * D2a[:, q] * c
+        D3[:, m] = A1[:, p] * A2[:, q] * dc
+    return Phi, D1, D2, D3
+
+
+def pyr_points(Q: int):
+    """GLL (Q) x GLL (Q) x Radau of (1-x)^2 (Q-1) and the weights of dxi,
+    q = i + Q (j + Q k)."""
+    x1, w1 = gll(Q)
+    x3, w3 = gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    E1 = np.tile(x1, Q * (Q - 1))
+    E2 = np.tile(np.repeat(x1, Q), Q - 1)
+    E3 = np.repeat(x3, Q * Q)
+    W = np.outer(w3 / 4, np.outer(w1, w1).ravel()).ravel()
+    return E1, E2, E3, W
+
+
+def xi_of_eta_pyr(e1, e2, e3):
+    e1, e2, e3 = (np.asarray(v, np.float64) for v in (e1, e2, e3))
+    return (1 + e1) * (1 - e3) / 2 - 1, (1 + e2) * (1 - e3) / 2 - 1, e3
+
+
+class PyrOps(TetOps):
+    """Dense elemental operators of pyramids of order P with the quadrature
+    of pyr_points(Q).  J[e, c, a, q] = d x_c / d xi_a."""
+
+    def __init__(self, P, Q, J, kappa=None, lam=1.0):
+        self.P, self.Q = int(P), int(Q)
+        self.e1, self.e2, self.e3, self.W = pyr_points(self.Q)
+        self.Bt, D1, D2, D3 = pyr_basis(self.P, self.e1, self.e2, self.e3)
+        e1, e2, e3 = self.e1, self.e2, self.e3
+        g = (2.0 / (1 - e3))[:, None]
+        self.Dt = [g * D1, g * D2,
+                   ((1 + e1) / (1 - e3))[:, None] * D1 + ((1 + e2) / (1 - e3))[:, None] * D2 + D3]
         self._geometry(J, kappa, lam)

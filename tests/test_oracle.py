@@ -1112,3 +1112,119 @@ def test_prismatic_mesh_volume_and_orientation():
         assert ops.detJ.min() > 0
         errs.append(abs(ops.wJ.sum() - 1.0))
     assert max(errs) < 1e-13
+
+
+# ------------------------------------------------------------- pyramids (2.1)
+
+def _pyr_integral(a, b, c):
+    """Integral of xi_1^a xi_2^b xi_3^c over the reference pyramid: for each
+    xi_3 the square [-1, -xi_3]^2, integrated in closed form per direction
+    and then in xi_3 by exact polynomial arithmetic."""
+    from numpy.polynomial import polynomial as Pn
+
+    def side(k):   # int_{-1}^{-z} x^k dx as a polynomial in z
+        coef = np.zeros(k + 2)
+        coef[k + 1] = (-1.0) ** (k + 1) / (k + 1)
+        coef[0] -= (-1.0) ** (k + 1) / (k + 1)
+        return coef
+    poly = Pn.polymul(Pn.polymul(side(a), side(b)), np.eye(c + 1)[c])
+    anti = Pn.polyint(poly)
+    return Pn.polyval(1.0, anti) - Pn.polyval(-1.0, anti)
+
+
+@pytest.mark.parametrize("P", [1, 2, 4])
+def test_pyramid_quadrature_and_span(P):
+    Q = P + 2
+    e1, e2, e3, W = C.pyr_points(Q)
+    x1, x2, x3 = C.xi_of_eta_pyr(e1, e2, e3)
+    assert abs(W.sum() - 8.0 / 3.0) < 1e-14
+    for a in range(2 * P + 1):
+        for b in range(2 * P + 1 - a):
+            for c in range(2 * P + 1 - a - b):
+                assert abs(W @ (x1 ** a * x2 ** b * x3 ** c) - _pyr_integral(a, b, c)) < 1e-12, (a, b, c)
+    Phi, _, _, _ = C.pyr_basis(P, e1, e2, e3)
+    assert Phi.shape[1] == (P + 1) * (P + 2) * (2 * P + 3) // 6
+    M = Phi.T @ (W[:, None] * Phi)
+    np.linalg.cholesky(M)
+    for a in range(P + 1):
+        for b in range(P + 1 - a):
+            for c in range(P + 1 - a - b):
+                f = x1 ** a * x2 ** b * x3 ** c
+                cf = np.linalg.solve(M, Phi.T @ (W * f))
+                assert np.abs(Phi @ cf - f).max() < 1e-11, (a, b, c)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_pyramid_faces(P):
+    """Base face (eta_3 = -1): the r = 0 modes are the tensor-product 1-D
+    modified basis, every other mode vanishes.  Triangular face xi_1 = -1:
+    the p = 0 modes and the apex are exactly the triangle basis in the face's
+    collapsed coordinates (eta_2, eta_3), every other mode vanishes."""
+    rng = np.random.default_rng(4)
+    u, v = rng.uniform(-1, 1, (2, 20))
+    modes = C.pyr_modes(P)
+    Phi, _, _, _ = C.pyr_basis(P, u, v, -np.ones(20))
+    A1, _ = oracle.modified_basis(P, u)
+    A2, _ = oracle.modified_basis(P, v)
+    for m, (p, q, s, r) in enumerate(modes):
+        expect = A1[:, p] * A2[:, q] if (p >= 0 and r == 0) else 0.0
+        np.testing.assert_allclose(Phi[:, m], expect, atol=1e-13)
+    Phi, _, _, _ = C.pyr_basis(P, -np.ones(20), u, v)
+    T, _, _ = C.tri_basis(P, u, v)
+    tri = C.tri_modes(P)
+    for m, (p, q, s, r) in enumerate(modes):
+        if p < 0:
+            t = tri.index((0, P))                       # the apex: triangle vertex C
+        elif p != 0:
+            np.testing.assert_allclose(Phi[:, m], 0.0, atol=1e-13)
+            continue
+        elif q == 0:
+            t = tri.index((0, r))
+        elif q == P:
+            t = tri.index((P, r))
+        else:
+            t = tri.index((q, r))
+        np.testing.assert_allclose(Phi[:, m], T[:, t], atol=1e-13)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_pyramid_projection_gradient_and_laplacian(P):
+    Q = P + 2
+    A = np.array([[0.9, 0.2, -0.1], [0.1, 1.1, 0.3], [-0.2, 0.05, 0.8]])
+    nq = Q * Q * (Q - 1)
+    J = np.broadcast_to(A[None, :, :, None], (1, 3, 3, nq)).copy()
+    ops = C.PyrOps(P, Q, J, lam=0.0)
+    M = ops.mass_matrix(0)
+    np.linalg.cholesky(M)
+    modes = C.pyr_modes(P)
+    one = np.zeros(len(modes))
+    for m, (p, q, s, r) in enumerate(modes):
+        if p < 0 or (p in (0, P) and q in (0, P) and r == 0):
+            one[m] = 1.0
+    assert abs(one @ M @ one - 8.0 / 3.0 * abs(np.linalg.det(A))) < 1e-13
+    np.testing.assert_allclose(ops.laplacian_matrix(0) @ one, 0.0, atol=1e-12)
+    X = A @ np.stack(C.xi_of_eta_pyr(ops.e1, ops.e2, ops.e3))
+    x, y, z = X
+    u = x * y - 0.5 * z ** 2 + 2 * x
+    grad = np.stack([y + 2, x, -z])
+    cu = ops.fwd(u[None])[0]
+    np.testing.assert_allclose(ops.bwd(cu[None])[0], u, atol=1e-12)
+    gxi = np.stack([ops.Dt[a] @ cu for a in range(3)])
+    np.testing.assert_allclose(np.linalg.solve(A.T, gxi), grad, atol=1e-11)
+    exact = ops.wJ[0] @ (grad ** 2).sum(axis=0)
+    assert abs(cu @ ops.laplacian_matrix(0) @ cu - exact) < 1e-12 * exact
+
+
+def test_pyramidal_mesh_volume_and_orientation():
+    """The pyramidal mesh of the unit cube: positive determinants and volume
+    one, straight-sided and curved (the warp's sine terms cancel between the
+    six pyramids of each cube, so the curved volume is exact too)."""
+    errs = []
+    for Q, amp in ((6, 0.0), (4, W.WARP_AMPLITUDE), (8, W.WARP_AMPLITUDE), (12, W.WARP_AMPLITUDE)):
+        x, _ = oracle.gll(Q)
+        x3, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+        J = W.pyr_lattice_jacobians(2, x, x, x3, amp)
+        ops = C.PyrOps(Q - 2, Q, J)
+        assert ops.detJ.min() > 0
+        errs.append(abs(ops.wJ.sum() - 1.0))
+    assert max(errs) < 1e-13

@@ -500,6 +500,53 @@ def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, ele
     return np.einsum("ecbq,eba->ecaq", Wm, A)
 
 
+def pyr_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems=None):
+    """Jacobians of the pyramidal mesh of the unit cube: an n^3 lattice of
+    cubes, each split into six pyramids with the cube's centre as apex and
+    one face as base (element 6 cube + face, faces -x, +x, -y, +y, -z, +z),
+    curved by the cyclic warp.  With base corner a, its neighbours b and d
+    (ordered so the map is positively oriented) and apex e, the reference
+    map is x = a + (b - a)(1 + xi_1)/2 + (d - a)(1 + xi_2)/2 + (e - a)(1 + xi_3)/2,
+    taken at the collapsed points (xi_1 = (1 + eta_1)(1 - eta_3)/2 - 1, xi_2
+    likewise with eta_2, xi_3 = eta_3) of the 1-D sets (e1, e2, e3),
+    q = i + len(e1) (j + len(e2) k).  Returns J[E, c, a, q]."""
+    e1, e2, e3 = (np.asarray(v, np.float64) for v in (e1, e2, e3))
+    n1, n2 = e1.size, e2.size
+    E1 = np.tile(e1, n2 * e3.size)
+    E2 = np.tile(np.repeat(e2, n1), e3.size)
+    E3 = np.repeat(e3, n1 * n2)
+    x1 = (1 + E1) * (1 - E3) / 2 - 1
+    x2 = (1 + E2) * (1 - E3) / 2 - 1
+    x3 = E3
+    h = 1.0 / n
+    c = np.arange(n ** 3)
+    corner = np.stack([c % n, (c // n) % n, c // (n * n)], axis=1) * h
+    faces = []
+    for ax in range(3):
+        u, v = [d for d in range(3) if d != ax]
+        for side in (0, 1):
+            a = np.zeros(3)
+            a[ax] = side * h
+            b, d = a.copy(), a.copy()
+            b[u] += h
+            d[v] += h
+            eap = np.full(3, h / 2)
+            if np.linalg.det(np.stack([b - a, d - a, eap - a], axis=1)) < 0:
+                b, d = d, b
+            faces.append((a, b, d, eap))
+    V = np.stack([np.stack([corner + f[k] for k in range(4)], axis=1) for f in faces], axis=1)
+    V = V.reshape(-1, 4, 3)                                            # (E, [a, b, d, e], 3)
+    if elems is not None:
+        V = V[np.asarray(elems)]
+    A = np.stack([(V[:, 1] - V[:, 0]) / 2, (V[:, 2] - V[:, 0]) / 2, (V[:, 3] - V[:, 0]) / 2], axis=2)
+    if amp == 0.0:
+        return np.broadcast_to(A[:, :, :, None], A.shape + (x1.size,)).copy()
+    X = (V[:, 0, :, None] + A[:, :, 0, None] * (1 + x1) + A[:, :, 1, None] * (1 + x2)
+         + A[:, :, 2, None] * (1 + x3))
+    Wm = warp_jacobian(X, amp)
+    return np.einsum("ecbq,eba->ecaq", Wm, A)
+
+
 # ----------------------------------------------------------- draws
 
 def varp_orders(seed_: int, nelem: int, lo: int = 2, hi: int = 10) -> np.ndarray:
