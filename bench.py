@@ -309,8 +309,9 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
 
 def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30, shape="tet"):
     """Collapsed-coordinate tetrahedra (the unit cube split into n^3 cubes of
-    six curved tetrahedra each) or prisms (the triangle mesh of the unit
-    square extruded into n layers, 2 n^3 curved prisms): BwdTrans /
+    six curved tetrahedra each), prisms (the triangle mesh of the unit
+    square extruded into n layers, 2 n^3 curved prisms) or pyramids (six per
+    cube, apex at its centre): BwdTrans /
     IProductWRTBase / Helmholtz per order, FP64 and FP32.  Algorithmic bytes
     per element (nm modes, np points, s bytes): BwdTrans s(nm + np),
     IProductWRTBase s(2 np + nm), Helmholtz s(2 nm + 7 np) (7 factors per
@@ -324,12 +325,18 @@ def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30, shape=
             space = nk.Space.create_tet(P, Q, J)
             E = 6 * n ** 3
             nm, npt = (P + 1) * (P + 2) * (P + 3) // 6, Q * (Q - 1) ** 2
-        else:
+        elif shape == "prism":
             e1, _, e2, _ = nk.tri_points(Q)
             J = torch.from_numpy(W.prism_lattice_jacobians(n, e1, e2, e1)).cuda()
             space = nk.Space.create_prism(P, Q, J)
             E = 2 * n ** 3
             nm, npt = (P + 1) ** 2 * (P + 2) // 2, Q * Q * (Q - 1)
+        else:   # pyramids: 6 per cube
+            xg = nk.basis_tables(P, Q)[0]
+            J = torch.from_numpy(W.pyr_lattice_jacobians(n, xg, xg, nk.tet_points(Q)[4])).cuda()
+            space = nk.Space.create_pyr(P, Q, J)
+            E = 6 * n ** 3
+            nm, npt = (P + 1) * (P + 2) * (2 * P + 3) // 6, Q * Q * (Q - 1)
         del J
         res = {"nelem": E}
         for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
@@ -777,6 +784,8 @@ def main():
         sections["tet"] = section_tet(nk, W, torch)
         log("section prism ...")
         sections["prism"] = section_tet(nk, W, torch, cases=((24, 4), (24, 6), (16, 8)), shape="prism")
+        log("section pyramid ...")
+        sections["pyramid"] = section_tet(nk, W, torch, cases=((20, 4), (16, 6), (10, 8)), shape="pyramid")
     del space, x, y
     torch.cuda.empty_cache()
     if "cg" in secs:

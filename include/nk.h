@@ -189,6 +189,20 @@ nk_status nk_space_create_tet(nk_space* out, int64_t nelem, int P, int Q, const 
 nk_status nk_space_create_prism(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
                                 const double* kappa, void* stream);
 
+/* Pyramids (section 2.1: the hexahedron with its top face collapsed to a
+ * point): base [-1, 1]^2 at xi_3 = -1, apex (-1, -1, 1); eta_a = 2(1+xi_a)/
+ * (1-xi_3) - 1 (a = 1, 2), eta_3 = xi_3.  Quadrature: Q GLL points in eta_1
+ * and eta_2 (nk_basis_tables), Q-1 Gauss-Radau points of (1-eta_3)^2 in
+ * eta_3 (nk_tet_points' third set); point q = i + Q (j + Q k).  Modes
+ * ((P+1)(P+2)(2P+3)/6 per element): each base mode phi_p(eta_1)
+ * phi_q(eta_2) (p slow, q fast) with s = max(deg phi_p, deg phi_q), times
+ * ((1-eta_3)/2)^s for r = 0 and ((1-eta_3)/2)^s (1+eta_3)/2
+ * P^{2s-1,1}_{r-1}(eta_3) for 1 <= r <= P - s (r fastest); the apex
+ * (1+eta_3)/2 last.  jac: device [E][3][3][Q^2 (Q-1)] FP64, kappa: device
+ * [E][Q^2 (Q-1)] or NULL; supported calls and errors as for tetrahedra. */
+nk_status nk_space_create_pyr(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                              const double* kappa, void* stream);
+
 /* Sizes of a space: total elements, coefficients (sum n^d) and points
  * (sum Q^d).  Any output may be NULL. */
 nk_status nk_space_sizes(nk_space s, int64_t* nelem, int64_t* ncoeffs, int64_t* npoints);

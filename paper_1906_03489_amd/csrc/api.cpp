@@ -456,8 +456,8 @@ nk_status nk_tet_points(int Q, double* eta1, double* w1, double* eta2, double* w
   return NK_OK;
 }
 
-// Tetrahedra (shape 2) and prisms (shape 3): one order group, 7 factors per
-// point built by the collapsed-shape geometry kernel.
+// Tetrahedra (shape 2), prisms (shape 3) and pyramids (shape 4): one order
+// group, 7 factors per point built by the collapsed-shape geometry kernel.
 static nk_status space_create_col3(nk_space* out, int shape, int64_t nelem, int P, int Q,
                                    const double* jac, const double* kappa, void* stream) {
   if (!out) return fail(NK_EINVAL, "out is NULL");
@@ -465,10 +465,12 @@ static nk_status space_create_col3(nk_space* out, int shape, int64_t nelem, int 
   if (nelem < 0) return fail(NK_EINVAL, "nelem must be >= 0");
   if (P < 1 || P > kMaxP || Q != P + 2)
     return fail(NK_EUNSUPPORTED, "compiled orders: 1 <= P <= 10 with Q = P + 2");
-  const bool tet = shape == 2;
-  const int Q3 = tet ? Q - 1 : Q;
-  const int64_t NP = (int64_t)Q * (Q - 1) * Q3;
-  const int64_t NM = tet ? (int64_t)(P + 1) * (P + 2) * (P + 3) / 6 : (int64_t)(P + 1) * (P + 1) * (P + 2) / 2;
+  const bool tet = shape == 2, pyr = shape == 4;
+  const int Q2 = pyr ? Q : Q - 1, Q3 = shape == 3 ? Q : Q - 1;
+  const int64_t NP = (int64_t)Q * Q2 * Q3;
+  const int64_t NM = tet   ? (int64_t)(P + 1) * (P + 2) * (P + 3) / 6
+                     : pyr ? (int64_t)(P + 1) * (P + 2) * (2 * P + 3) / 6
+                           : (int64_t)(P + 1) * (P + 1) * (P + 2) / 2;
   if (nelem > 0 && !jac) return fail(NK_EINVAL, "jac is NULL");
   NK_CHECK(check_buf(jac, (size_t)nelem * 9 * NP * 8, "jac"));
   if (kappa) NK_CHECK(check_buf(kappa, (size_t)nelem * NP * 8, "kappa"));
@@ -495,14 +497,18 @@ static nk_status space_create_col3(nk_space* out, int shape, int64_t nelem, int 
   hipError_t e;
   if ((e = dmalloc(&s->fac64, s->nfac)) || (e = dmalloc(&s->fac32, s->nfac)))
     return cleanup(hip_fail(e, "hipMalloc"));
-  // e1, w1 (Q), e2, w2 (Q-1), e3, w3 (Q3)
-  std::vector<double> pts(2 * Q + 2 * (Q - 1) + 2 * Q3);
+  // e1, w1 (Q), e2, w2 (Q2), e3, w3 (Q3)
+  std::vector<double> pts(2 * Q + 2 * Q2 + 2 * Q3);
   double* p = pts.data();
-  double* p3 = p + 2 * Q + 2 * (Q - 1);
+  double* p3 = p + 2 * Q + 2 * Q2;
   if (tet) {
-    tet_points(Q, p, p + Q, p + 2 * Q, p + 2 * Q + (Q - 1), p3, p3 + Q3);
+    tet_points(Q, p, p + Q, p + 2 * Q, p + 2 * Q + Q2, p3, p3 + Q3);
+  } else if (pyr) {
+    gll_points(Q, p, p + Q);
+    gll_points(Q, p + 2 * Q, p + 3 * Q);
+    radau_points(Q3, 2, p3, p3 + Q3);
   } else {
-    tri_points(Q, p, p + Q, p + 2 * Q, p + 2 * Q + (Q - 1));
+    tri_points(Q, p, p + Q, p + 2 * Q, p + 2 * Q + Q2);
     gll_points(Q, p3, p3 + Q3);
   }
   int* d_bad = nullptr;
@@ -514,8 +520,9 @@ static nk_status space_create_col3(nk_space* out, int shape, int64_t nelem, int 
   int bad = 0;
   if (!(e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) &&
       !(e = hipMemcpyAsync(d_pts, pts.data(), pts.size() * 8, hipMemcpyHostToDevice, st)) &&
-      !(e = tet ? launch_geom_tet(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)
-                : launch_geom_prism(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)) &&
+      !(e = tet   ? launch_geom_tet(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)
+            : pyr ? launch_geom_pyr(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)
+                  : launch_geom_prism(Q, nelem, jac, kappa, d_pts, s->fac64, s->fac32, d_bad, st)) &&
       !(e = hipStreamSynchronize(st)))
     e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
   dfree(d_bad);
@@ -534,6 +541,11 @@ nk_status nk_space_create_tet(nk_space* out, int64_t nelem, int P, int Q, const 
 nk_status nk_space_create_prism(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
                                 const double* kappa, void* stream) {
   return space_create_col3(out, 3, nelem, P, Q, jac, kappa, stream);
+}
+
+nk_status nk_space_create_pyr(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
+                              const double* kappa, void* stream) {
+  return space_create_col3(out, 4, nelem, P, Q, jac, kappa, stream);
 }
 
 nk_status nk_space_destroy(nk_space s) {
@@ -566,7 +578,7 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
   if (op == OP_RHS) NK_CHECK(check_buf(in2, s->npoint * d * 8, "du"));
   if (in == out && in != nullptr) return fail(NK_EINVAL, "input and output must not alias");
   if (s->shape != 0 && op != OP_BWD && op != OP_IPROD && op != OP_HELM)
-    return fail(NK_EUNSUPPORTED, "triangle, tetrahedron and prism spaces provide BwdTrans, IProductWRTBase and Helmholtz");
+    return fail(NK_EUNSUPPORTED, "collapsed-coordinate spaces provide BwdTrans, IProductWRTBase and Helmholtz");
   hipStream_t st = (hipStream_t)stream;
   const char* fac = t == NK_F64 ? (const char*)s->fac64 : (const char*)s->fac32;
   auto group_args = [&](const Group& G) {
@@ -591,9 +603,10 @@ static nk_status space_op(nk_space s, int op, nk_dtype t, const void* in, void* 
     if (e != hipSuccess) return hip_fail(e, "triangle operator launch");
     return NK_OK;
   }
-  if (s->shape == 2 || s->shape == 3) {
-    const hipError_t e = s->shape == 2 ? launch_tet(t, group_args(s->groups[0]))
-                                       : launch_prism(t, group_args(s->groups[0]));
+  if (s->shape >= 2) {
+    const hipError_t e = s->shape == 2   ? launch_tet(t, group_args(s->groups[0]))
+                         : s->shape == 3 ? launch_prism(t, group_args(s->groups[0]))
+                                         : launch_pyr(t, group_args(s->groups[0]));
     if (e != hipSuccess) return hip_fail(e, "collapsed-shape operator launch");
     return NK_OK;
   }
@@ -843,7 +856,7 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   if (s->groups.size() != 1 && nsys != 1)
     return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
   if (s->shape == 1 && nsys != 1) return fail(NK_EINVAL, "a triangle space takes one system (nsys = 1)");
-  if (s->shape >= 2) return fail(NK_EUNSUPPORTED, "assembled systems are not built for tetrahedra and prisms");
+  if (s->shape >= 2) return fail(NK_EUNSUPPORTED, "assembled systems are not built for tetrahedra, prisms and pyramids");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
   if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
     return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");

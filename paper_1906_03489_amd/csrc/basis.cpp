@@ -303,35 +303,59 @@ int tri_mode_degree(int P, int p, int q) {
   return p + q + 1;                             // interior
 }
 
+// The eta_3 factor of a collapsed-shape mode whose lower part has degree s:
+// ((1-x)/2)^s for r = 0, times (1+x)/2 P^{2s-1,1}_{r-1}(x) for r >= 1; value
+// and derivative.
+static void cfactor(int s, int r, double x, double* v, double* d) {
+  const double a = 0.5 * (1.0 - x), g = 0.5 * (1.0 + x);
+  const double f = std::pow(a, s), df = s > 0 ? -0.5 * s * std::pow(a, s - 1) : 0.0;
+  if (r == 0) {
+    *v = f;
+    *d = df;
+    return;
+  }
+  const double J = jacobi_poly(r - 1, 2.0 * s - 1.0, 1.0, x);
+  const double dJ = r >= 2 ? 0.5 * (r + 2.0 * s) * jacobi_poly(r - 2, 2.0 * s, 2.0, x) : 0.0;
+  *v = f * g * J;
+  *d = df * g * J + f * 0.5 * J + f * g * dJ;
+}
+
 // eta_3 factor of every tetrahedron mode at the points z (values and
 // derivatives, [nz][nm3]): modes grouped by triangle mode t (degree s),
-// r = 0..P-s: ((1-z)/2)^s, times (1+z)/2 P^{2s-1,1}_{r-1}(z) for r >= 1;
-// the top vertex (1+z)/2 last.
+// r = 0..P-s; the top vertex (1+z)/2 last.
 void tet_ctable(int P, int nz, const double* z, double* Ct, double* dCt) {
   const int nm3 = (P + 1) * (P + 2) * (P + 3) / 6;
   for (int k = 0; k < nz; ++k) {
-    const double x = z[k], a = 0.5 * (1.0 - x), g = 0.5 * (1.0 + x);
     int m = 0;
     for (int p = 0; p <= P; ++p) {
       const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
       for (int q = 0; q < nq; ++q) {
         const int s = tri_mode_degree(P, p, q);
-        const double f = std::pow(a, s), df = s > 0 ? -0.5 * s * std::pow(a, s - 1) : 0.0;
-        for (int r = 0; r <= P - s; ++r, ++m) {
-          if (r == 0) {
-            Ct[k * nm3 + m] = f;
-            dCt[k * nm3 + m] = df;
-          } else {
-            const double J = jacobi_poly(r - 1, 2.0 * s - 1.0, 1.0, x);
-            const double dJ = r >= 2 ? 0.5 * (r + 2.0 * s) * jacobi_poly(r - 2, 2.0 * s, 2.0, x) : 0.0;
-            Ct[k * nm3 + m] = f * g * J;
-            dCt[k * nm3 + m] = df * g * J + f * 0.5 * J + f * g * dJ;
-          }
-        }
+        for (int r = 0; r <= P - s; ++r, ++m) cfactor(s, r, z[k], &Ct[k * nm3 + m], &dCt[k * nm3 + m]);
       }
     }
-    Ct[k * nm3 + m] = g;   // top vertex
+    Ct[k * nm3 + m] = 0.5 * (1.0 + z[k]);   // top vertex
     dCt[k * nm3 + m] = 0.5;
+  }
+}
+
+// Degree of the 1-D modified basis function p of order P.
+int mod_degree(int P, int p) { return (p == 0 || p == P) ? 1 : p + 1; }
+
+// eta_3 factor of every pyramid mode at the points z ([nz][nm]): modes
+// grouped by base mode (p slow, q fast) with s = max(deg p, deg q),
+// r = 0..P-s; the apex (1+z)/2 last.
+void pyr_ctable(int P, int nz, const double* z, double* Ct, double* dCt) {
+  const int nm = (P + 1) * (P + 2) * (2 * P + 3) / 6;
+  for (int k = 0; k < nz; ++k) {
+    int m = 0;
+    for (int p = 0; p <= P; ++p)
+      for (int q = 0; q <= P; ++q) {
+        const int s = std::max(mod_degree(P, p), mod_degree(P, q));
+        for (int r = 0; r <= P - s; ++r, ++m) cfactor(s, r, z[k], &Ct[k * nm + m], &dCt[k * nm + m]);
+      }
+    Ct[k * nm + m] = 0.5 * (1.0 + z[k]);   // apex
+    dCt[k * nm + m] = 0.5;
   }
 }
 

@@ -6,9 +6,13 @@
 //
 // Prisms: the triangle of tri.hip in (xi_1, xi_2) extruded along xi_3, every
 // mode a triangle mode times the 1-D modified basis phi_r(xi_3), r = 0..P
-// (r fastest); Q GLL points in xi_3.  The kernel below serves both shapes:
-// for a prism the eta_3 table holds phi_r at the GLL points and there is no
-// top vertex.
+// (r fastest); Q GLL points in xi_3.  Pyramids: the lower part is the
+// tensor-product quadrilateral phi_p(eta_1) phi_q(eta_2) (GLL points in both)
+// instead of a triangle, with s = max(deg phi_p, deg phi_q) and the apex
+// (1+eta_3)/2 riding on the four base vertex modes.  The kernel below serves
+// all three shapes: the "lower" stages are the triangle's (tetrahedron,
+// prism) or the quadrilateral's (pyramid), and the eta_3 table holds the
+// shape's third-direction factors.
 //
 // Basis: every mode is a triangle mode T_t(eta_1, eta_2) of the order-P
 // triangle (tri.hip), of total degree s_t, times an eta_3 factor c_{s,r}:
@@ -37,23 +41,37 @@
 
 namespace nk {
 
-constexpr int kTet = 0, kPrism = 1;
+constexpr int kTet = 0, kPrism = 1, kPyr = 2;
 
 template <int P, int SH>
 struct TetShape {
-  static constexpr int N = P + 1, Q = P + 2, Q2 = Q - 1;
-  static constexpr int Q3 = SH == kTet ? Q - 1 : Q;      // points in the third direction
+  static constexpr int N = P + 1, Q = P + 2;
+  static constexpr int Q2 = SH == kPyr ? Q : Q - 1;      // points in eta_2
+  static constexpr int Q3 = SH == kPrism ? Q : Q - 1;    // points in the third direction
   static constexpr int NS = Q2 * Q3, NPT = Q * NS;
-  static constexpr int NMT = N * (N + 1) / 2;            // triangle modes
-  static constexpr int NM3 = SH == kTet ? N * (N + 1) * (N + 2) / 6 : NMT * N;
-  // columns of the third-direction table: one per mode for tetrahedra, one
-  // per 1-D mode r for prisms (the factor depends on r only)
-  static constexpr int NC = SH == kTet ? NM3 : N;
+  // modes of the lower part: triangle modes, or the pyramid's base modes
+  static constexpr int NMT = SH == kPyr ? N * N : N * (N + 1) / 2;
+  static constexpr int NM3 = SH == kTet     ? N * (N + 1) * (N + 2) / 6
+                             : SH == kPrism ? NMT * N
+                                            : N * (N + 1) * (2 * N + 1) / 6;
+  static constexpr bool APEX = SH != kPrism;   // a top vertex riding on the lower vertices
+  // columns of the third-direction table: one per mode, or one per 1-D mode
+  // r for prisms (the factor depends on r only)
+  static constexpr int NC = SH == kPrism ? N : NM3;
+  // columns of the eta_2 table: one per lower mode, or one per 1-D mode q
+  // for pyramids (phi_q(eta_2) depends on q only)
+  static constexpr int NB = SH == kPyr ? N : NMT;
+  static constexpr int bcol(int t) { return SH == kPyr ? t % N : t; }
   // LDS row strides (in scalars), odd so that distinct rows fall into
   // distinct banks
-  static constexpr int TS = NMT | 1, CS = NC | 1;
+  static constexpr int TS = NB | 1, CS = NC | 1;
   static constexpr int NTAB = 2 * Q2 * TS + 2 * Q3 * CS;        // B2, dB2, C3, dC3
-  static constexpr int ccol(int m) { return SH == kTet ? m : m % N; }
+  static constexpr int ccol(int m) { return SH == kPrism ? m % N : m; }
+  // vertex modes of the lower part (the apex rides on them)
+  static constexpr bool lower_vertex(int t) {
+    return SH == kPyr ? (t == 0 || t == P || t == P * N || t == P * N + P)
+                      : (t == 0 || t == P || t == NMT - P);
+  }
   static constexpr int NITAB = 2 * NMT + 1 + NM3;               // toff3, tp, mt
   static constexpr int SLOT = NM3 + 2 * Q3 * NMT + 3 * NS * N;  // u, w | w', SA | SB | SC
   // tetrahedra per block: up to 256 threads, within ~150 KB of LDS
@@ -64,7 +82,7 @@ struct TetShape {
     const int e = by_threads < by_lds ? by_threads : by_lds;
     return e > 0 ? e : 1;
   }
-  static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
+  static constexpr int cnt(int p) { return SH == kPyr ? N : (p == 0 ? P + 1 : (p == P ? P : P - p)); }
   static constexpr int off(int p) {
     int o = 0;
     for (int k = 0; k < p; ++k) o += cnt(k);
@@ -72,7 +90,8 @@ struct TetShape {
   }
 };
 
-// Device tables of order P: B2 [Q2][NMT], dB2 [Q2][NMT] at the eta_2 points,
+// Device tables of order P: B2 [Q2][NB], dB2 [Q2][NB] at the eta_2 points (NB
+// = NMT lower modes, or P+1 for pyramids),
 // C3 [Q3][NC], dC3 [Q3][NC] at the third-direction points (NC = NM3 for
 // tetrahedra, P+1 for prisms; scalars of type T), and the integer maps toff3 [NMT+1] (first coefficient of each triangle
 // mode), tp [NMT] (eta_1 index p of each triangle mode), mt [NM3] (triangle
@@ -88,42 +107,54 @@ static TetTables tet_tables(int P, int sh) {
   static std::unordered_map<long, TetTables> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return {};
-  const long key = (dev * 64L + P) * 2 + sh;
+  const long key = (dev * 64L + P) * 4 + sh;   // sh < 4
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  const int N = P + 1, Q = P + 2, Q2 = Q - 1, NMT = N * (N + 1) / 2;
-  const int Q3 = sh == kTet ? Q2 : Q, NM3 = sh == kTet ? N * (N + 1) * (N + 2) / 6 : NMT * N;
+  const int N = P + 1, Q = P + 2, Q2 = sh == kPyr ? Q : Q - 1, Q3 = sh == kPrism ? Q : Q - 1;
+  const int NMT = sh == kPyr ? N * N : N * (N + 1) / 2;
+  const int NM3 = sh == kTet ? N * (N + 1) * (N + 2) / 6 : sh == kPrism ? NMT * N : N * (N + 1) * (2 * N + 1) / 6;
   std::vector<double> e1(Q), w1(Q), e2(Q2), w2(Q2), e3(Q3), w3(Q3);
   if (sh == kTet) {
     tet_points(Q, e1.data(), w1.data(), e2.data(), w2.data(), e3.data(), w3.data());
-  } else {
+  } else if (sh == kPrism) {
     tri_points(Q, e1.data(), w1.data(), e2.data(), w2.data());
     gll_points(Q, e3.data(), w3.data());
+  } else {
+    gll_points(Q, e2.data(), w2.data());
+    radau_points(Q3, 2, e3.data(), w3.data());
   }
-  const int NC = sh == kTet ? NM3 : N;
-  std::vector<double> B2(Q2 * NMT), dB2(Q2 * NMT), C3(Q3 * NC), dC3(Q3 * NC);
-  tri_btable(P, Q2, e2.data(), B2.data(), dB2.data());
+  const int NC = sh == kPrism ? N : NM3;
+  const int NB = sh == kPyr ? N : NMT;
+  std::vector<double> B2(Q2 * NB), dB2(Q2 * NB), C3(Q3 * NC), dC3(Q3 * NC);
+  if (sh == kPyr)   // base mode (p, q) = p N + q: phi_q(eta_2), one column per q
+    modified_basis(P, Q, e2.data(), B2.data(), dB2.data());
+  else
+    tri_btable(P, Q2, e2.data(), B2.data(), dB2.data());
   if (sh == kTet)
     tet_ctable(P, Q2, e3.data(), C3.data(), dC3.data());
-  else   // phi_r(xi_3)
+  else if (sh == kPrism)   // phi_r(xi_3)
     modified_basis(P, Q, e3.data(), C3.data(), dC3.data());
+  else
+    pyr_ctable(P, Q3, e3.data(), C3.data(), dC3.data());
   std::vector<T> h;
   for (const auto* v : {&B2, &dB2, &C3, &dC3})
     for (double x : *v) h.push_back((T)x);
   std::vector<int> it_(2 * NMT + 1 + NM3);
   int t = 0, m = 0;
   for (int p = 0; p <= P; ++p) {
-    const int nq = p == 0 ? P + 1 : (p == P ? P : P - p);
+    const int nq = sh == kPyr ? N : (p == 0 ? P + 1 : (p == P ? P : P - p));
     for (int q = 0; q < nq; ++q, ++t) {
       it_[t] = m;                 // toff3
       it_[NMT + 1 + t] = p;       // tp
-      const int nr = sh == kTet ? P - tri_mode_degree(P, p, q) + 1 : N;
+      const int nr = sh == kTet     ? P - tri_mode_degree(P, p, q) + 1
+                     : sh == kPrism ? N
+                                    : P - std::max(mod_degree(P, p), mod_degree(P, q)) + 1;
       for (int r = 0; r < nr; ++r, ++m) it_[2 * NMT + 1 + m] = t;   // mt
     }
   }
   it_[NMT] = m;                   // end of the last group
-  if (sh == kTet) it_[2 * NMT + 1 + m] = -1;   // m = NM3 - 1: the top vertex
+  if (sh != kPrism) it_[2 * NMT + 1 + m] = -1;   // m = NM3 - 1: the top vertex
   TetTables out;
   T* d = nullptr;
   int* di = nullptr;
@@ -150,23 +181,22 @@ __global__ void __launch_bounds__(256)
           const DevArgs<T> a) {
   using S = TetShape<P, SH>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
-  constexpr bool TET = SH == kTet;
-  constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS, NC = S::NC;
+  constexpr bool APEX = S::APEX, TRI = SH != kPyr;   // TRI: triangle lower part
+  constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS, NC = S::NC, NB = S::NB;
   constexpr int EPB = S::template epb<T>();
   constexpr bool HELM = OP == OP_HELM;
-  constexpr int VA = 0, VC = P, VB = NMT - P;   // triangle vertex modes A, C, B
   __shared__ T stab[S::NTAB];
   __shared__ int sit[S::NITAB];
   __shared__ T smem[EPB * S::SLOT];
-  for (int k = threadIdx.x; k < Q2 * NMT; k += blockDim.x) {
-    const int r = k / NMT, m = k - r * NMT;
+  for (int k = threadIdx.x; k < Q2 * NB; k += blockDim.x) {
+    const int r = k / NB, m = k - r * NB;
     stab[r * TS + m] = tab[k];
-    stab[(Q2 + r) * TS + m] = tab[Q2 * NMT + k];
+    stab[(Q2 + r) * TS + m] = tab[Q2 * NB + k];
   }
   for (int k = threadIdx.x; k < Q3 * NC; k += blockDim.x) {
     const int r = k / NC, m = k - r * NC;
-    stab[2 * Q2 * TS + r * CS + m] = tab[2 * Q2 * NMT + k];
-    stab[2 * Q2 * TS + (Q3 + r) * CS + m] = tab[2 * Q2 * NMT + Q3 * NC + k];
+    stab[2 * Q2 * TS + r * CS + m] = tab[2 * Q2 * NB + k];
+    stab[2 * Q2 * TS + (Q3 + r) * CS + m] = tab[2 * Q2 * NB + Q3 * NC + k];
   }
   for (int k = threadIdx.x; k < S::NITAB; k += blockDim.x) sit[k] = itab[k];
   __syncthreads();
@@ -205,15 +235,15 @@ __global__ void __launch_bounds__(256)
         for (int idx = t; idx < Q3 * NMT; idx += NS) {
           const int kk = idx / NMT, tt = idx - kk * NMT;
           const int o = toff3[tt], c = toff3[tt + 1] - o;
-          const T* cr = C3 + kk * CS + (TET ? o : 0);
-          const T* dcr = dC3 + kk * CS + (TET ? o : 0);
+          const T* cr = C3 + kk * CS + (SH == kPrism ? 0 : o);
+          const T* dcr = dC3 + kk * CS + (SH == kPrism ? 0 : o);
           T w = T(0), w3 = T(0);
           for (int r = 0; r < c; ++r) {
             w += cr[r] * U[o + r];
             if constexpr (HELM) w3 += dcr[r] * U[o + r];
           }
-          if constexpr (TET) {
-            if (tt == VA || tt == VB || tt == VC) {   // the top vertex rides on A + B + C
+          if constexpr (APEX) {
+            if (S::lower_vertex(tt)) {   // the top vertex rides on the lower vertex modes
               w += C3[kk * CS + NM3 - 1] * U[NM3 - 1];
               if constexpr (HELM) w3 += dC3[kk * CS + NM3 - 1] * U[NM3 - 1];
             }
@@ -235,11 +265,11 @@ __global__ void __launch_bounds__(256)
       for (int p = 0; p < N; ++p) {
 #pragma unroll
         for (int q = 0; q < S::cnt(p); ++q) {
-          const int m = S::off(p) + q;
-          V[p] += b2[m] * w[m];
+          const int m = S::off(p) + q, mb = S::bcol(m);
+          V[p] += b2[mb] * w[m];
           if constexpr (HELM) {
-            dV[p] += db2[m] * w[m];
-            V3[p] += b2[m] * w3[m];
+            dV[p] += db2[mb] * w[m];
+            V3[p] += b2[mb] * w3[m];
           }
         }
         // finish one mode group before the next group's loads are issued
@@ -249,7 +279,7 @@ __global__ void __launch_bounds__(256)
           __asm__ volatile("" : "+v"(V[p])::"memory");
         }
       }
-      {   // the collapsed triangle vertex C also multiplies a_P
+      if constexpr (TRI) {   // the collapsed triangle vertex C also multiplies a_P
         V[P] += b2[P] * w[P];
         if constexpr (HELM) {
           dV[P] += db2[P] * w[P];
@@ -332,18 +362,18 @@ __global__ void __launch_bounds__(256)
     // transposed eta_2 stage: z_t(k'), z'_t(k') for every (k', t) pair
     if (live) {
       for (int idx = t; idx < Q3 * NMT; idx += NS) {
-        const int kk = idx / NMT, tt = idx - kk * NMT, p = tp[tt];
+        const int kk = idx / NMT, tt = idx - kk * NMT, p = tp[tt], tb_ = S::bcol(tt);
         T z = T(0), z3 = T(0);
 #pragma unroll
         for (int jj = 0; jj < Q2; ++jj) {
           const int row = jj + Q2 * kk;
-          z += B2[jj * TS + tt] * SS[row * N + p];
+          z += B2[jj * TS + tb_] * SS[row * N + p];
           if constexpr (HELM) {
-            z += dB2[jj * TS + tt] * SS[(NS + row) * N + p];
-            z3 += B2[jj * TS + tt] * SS[(2 * NS + row) * N + p];
+            z += dB2[jj * TS + tb_] * SS[(NS + row) * N + p];
+            z3 += B2[jj * TS + tb_] * SS[(2 * NS + row) * N + p];
           }
         }
-        if (tt == VC) {   // the collapsed triangle vertex: its a_P part
+        if (TRI && tt == P) {   // the collapsed triangle vertex C: its a_P part
 #pragma unroll
           for (int jj = 0; jj < Q2; ++jj) {
             const int row = jj + Q2 * kk;
@@ -364,7 +394,7 @@ __global__ void __launch_bounds__(256)
       for (int m = t; m < NM3; m += NS) {
         const int tt = mt[m];
         T y = T(0);
-        if (!TET || tt >= 0) {
+        if (!APEX || tt >= 0) {
           const int cm = S::ccol(m);
 #pragma unroll
           for (int kk = 0; kk < Q3; ++kk) {
@@ -375,10 +405,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int kk = 0; kk < Q3; ++kk) {
             const T* zr = W + kk * NMT;
-            y += C3[kk * CS + m] * (zr[VA] + zr[VB] + zr[VC]);
+            T zs = zr[0] + zr[P] + (TRI ? zr[NMT - P] : zr[P * N] + zr[P * N + P]);
+            y += C3[kk * CS + m] * zs;
             if constexpr (HELM) {
               const T* z3r = W3 + kk * NMT;
-              y += dC3[kk * CS + m] * (z3r[VA] + z3r[VB] + z3r[VC]);
+              zs = z3r[0] + z3r[P] + (TRI ? z3r[NMT - P] : z3r[P * N] + z3r[P * N + P]);
+              y += dC3[kk * CS + m] * zs;
             }
           }
         }
@@ -466,6 +498,7 @@ static hipError_t launch_col(nk_dtype t, const OpArgs& a) {
 
 hipError_t launch_tet(nk_dtype t, const OpArgs& a) { return launch_col<kTet>(t, a); }
 hipError_t launch_prism(nk_dtype t, const OpArgs& a) { return launch_col<kPrism>(t, a); }
+hipError_t launch_pyr(nk_dtype t, const OpArgs& a) { return launch_col<kPyr>(t, a); }
 
 // Factors of the collapsed tetrahedron or prism at every point (thread per
 // point): f0 = w detJ, f1..f6 = w detJ kappa (M G M^T)_{11,12,13,22,23,33}
@@ -479,7 +512,7 @@ __global__ void __launch_bounds__(256)
     k_geom_tet(int Q, int64_t nelem, const double* __restrict__ jac, const double* __restrict__ kappa,
                const double* __restrict__ pts, double* __restrict__ fac64, float* __restrict__ fac32,
                int* __restrict__ bad) {
-  const int Q2 = Q - 1, Q3 = SH == kTet ? Q - 1 : Q, NS = Q2 * Q3, NP = Q * NS;
+  const int Q2 = SH == kPyr ? Q : Q - 1, Q3 = SH == kPrism ? Q : Q - 1, NS = Q2 * Q3, NP = Q * NS;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nelem * NP) return;
   const int64_t e = id / NP;
@@ -518,12 +551,19 @@ __global__ void __launch_bounds__(256)
                              {0.0, 0.0, 1.0}};
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) M[r][c] = Mt[r][c];
-  } else {   // prism: eta_1 = 2 (1 + xi_1)/(1 - xi_2) - 1, eta_2 = xi_2, xi_3
+  } else if (SH == kPrism) {   // eta_1 = 2 (1 + xi_1)/(1 - xi_2) - 1, eta_2 = xi_2, xi_3
     const double Mp[3][3] = {{2.0 / (1.0 - e2), (1.0 + e1) / (1.0 - e2), 0.0},
                              {0.0, 1.0, 0.0},
                              {0.0, 0.0, 1.0}};
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) M[r][c] = Mp[r][c];
+  } else {   // pyramid: eta_a = 2 (1 + xi_a)/(1 - xi_3) - 1 (a = 1, 2), eta_3 = xi_3
+    const double g = 2.0 / (1.0 - e3);
+    const double My[3][3] = {{g, 0.0, (1.0 + e1) / (1.0 - e3)},
+                             {0.0, g, (1.0 + e2) / (1.0 - e3)},
+                             {0.0, 0.0, 1.0}};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) M[r][c] = My[r][c];
   }
   double H[3][3];   // M G M^T
   for (int a_ = 0; a_ < 3; ++a_)
@@ -534,7 +574,9 @@ __global__ void __launch_bounds__(256)
       H[a_][b] = s;
     }
   const double kap = kappa ? kappa[e * NP + q] : 1.0;
-  const double wj = w1 * 0.5 * w2 * (SH == kTet ? 0.25 : 1.0) * w3 * det;
+  // the Radau weights carry (1 - eta_2) (tetrahedron, prism) and
+  // (1 - eta_3)^2 (tetrahedron, pyramid)
+  const double wj = w1 * (SH == kPyr ? 1.0 : 0.5) * w2 * (SH == kPrism ? 1.0 : 0.25) * w3 * det;
   const double ck = wj * kap;
   const double f[7] = {wj, ck * H[0][0], ck * H[0][1], ck * H[0][2], ck * H[1][1], ck * H[1][2], ck * H[2][2]};
   if (!(det > 0.0) || !(kap > 0.0)) atomicOr(bad, 1);
@@ -563,4 +605,13 @@ hipError_t launch_geom_prism(int Q, int64_t nelem, const double* jac, const doub
   return hipGetLastError();
 }
 
+
+hipError_t launch_geom_pyr(int Q, int64_t nelem, const double* jac, const double* kappa,
+                           const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s) {
+  const int64_t n = nelem * Q * Q * (Q - 1);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_geom_tet<kPyr>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, nelem,
+                     jac, kappa, pts, fac64, fac32, bad);
+  return hipGetLastError();
+}
 }  // namespace nk

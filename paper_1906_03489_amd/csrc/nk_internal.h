@@ -47,6 +47,8 @@ void radau_points(int n, int alpha, double* x, double* w);
 void tet_points(int Q, double* e1, double* w1, double* e2, double* w2, double* e3, double* w3);
 int tri_mode_degree(int P, int p, int q);
 void tet_ctable(int P, int nz, const double* z, double* Ct, double* dCt);
+int mod_degree(int P, int p);
+void pyr_ctable(int P, int nz, const double* z, double* Ct, double* dCt);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -177,14 +179,17 @@ hipError_t launch_tri(nk_dtype t, const OpArgs& a);   // also OP_HELM_ASM (assem
 hipError_t launch_diag_tri(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
                            const int32_t* l2g, double* diag, hipStream_t st);
 // Collapsed tetrahedra and prisms (collapsed3d.hip): BwdTrans,
-// IProductWRTBase, Helmholtz.  pts: e1, w1 (Q), e2, w2 (Q-1), e3, w3 (Q-1
-// for tetrahedra, Q for prisms).
+// IProductWRTBase, Helmholtz; pyramids too.  pts: e1, w1 (Q), e2, w2 (Q-1,
+// Q for pyramids), e3, w3 (Q-1, Q for prisms).
 hipError_t launch_tet(nk_dtype t, const OpArgs& a);
 hipError_t launch_prism(nk_dtype t, const OpArgs& a);
+hipError_t launch_pyr(nk_dtype t, const OpArgs& a);
 hipError_t launch_geom_tet(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 hipError_t launch_geom_prism(int Q, int64_t nelem, const double* jac, const double* kappa,
                              const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
+hipError_t launch_geom_pyr(int Q, int64_t nelem, const double* jac, const double* kappa,
+                           const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 hipError_t launch_geom_tri(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
     "nk_tri_points", "nk_space_create_tri", "nk_tet_points", "nk_space_create_tet",
-    "nk_space_create_prism",
+    "nk_space_create_prism", "nk_space_create_pyr",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
         "nk_tet_points": (i32, [i32, vp, vp, vp, vp, vp, vp]),
         "nk_space_create_tet": (i32, [pp, i64, i32, i32, vp, vp, vp]),
         "nk_space_create_prism": (i32, [pp, i64, i32, i32, vp, vp, vp]),
+        "nk_space_create_pyr": (i32, [pp, i64, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -242,6 +243,16 @@ class Space:
         h = ctypes.c_void_p()
         _check(lib().nk_space_create_prism(ctypes.byref(h), E, P, Q, _ptr(jac, torch.float64, "jac"),
                                            _ptr(kappa, torch.float64, "kappa"), _stream()))
+        return cls(h.value, 3, [(P, Q, E)])
+
+    @classmethod
+    def create_pyr(cls, P: int, Q: int, jac, kappa=None):
+        """Pyramids: jac [E, 3, 3, Q^2 (Q-1)] FP64 on the GPU."""
+        import torch
+        E = int(jac.shape[0]) if jac.dim() > 1 else jac.numel() // (9 * Q * Q * (Q - 1))
+        h = ctypes.c_void_p()
+        _check(lib().nk_space_create_pyr(ctypes.byref(h), E, P, Q, _ptr(jac, torch.float64, "jac"),
+                                         _ptr(kappa, torch.float64, "kappa"), _stream()))
         return cls(h.value, 3, [(P, Q, E)])
 
     STRATEGIES = {0: "persistent", 1: "persistent_2bpc", 2: "concurrent", 3: "sequential"}
