@@ -73,7 +73,9 @@ struct TetShape {
                       : (t == 0 || t == P || t == NMT - P);
   }
   static constexpr int NITAB = 2 * NMT + 1 + NM3;               // toff3, tp, mt
-  static constexpr int SLOT = NM3 + 2 * Q3 * NMT + 3 * NS * N;  // u, w | w', SA | SB | SC
+  // u, w | w', the transposed eta_1 buffer (one of SA, SB, SC at a time, or
+  // BwdTrans's staged rows of stride Q | 1)
+  static constexpr int SLOT = NM3 + 2 * Q3 * NMT + NS * (Q | 1);
   // tetrahedra per block: up to 256 threads, within ~150 KB of LDS
   template <typename T>
   static constexpr int epb() {
@@ -215,10 +217,9 @@ __global__ void __launch_bounds__(256)
   T* U = smem + slot * S::SLOT;                     // [NM3] coefficients
   T* W = U + NM3;                                   // [Q3][NMT] w, later z
   T* W3 = W + Q3 * NMT;                             // [Q3][NMT] dw/deta_3, later z'
-  T* SS = W3 + Q3 * NMT;                            // [3][NS][N]; point staging [NS][RS]
+  T* SS = W3 + Q3 * NMT;                            // [NS][N]; point staging [NS][RS]
   constexpr int SSO = NM3 + 2 * Q3 * NMT;           // offset of SS in a slot
   constexpr int RS = Q | 1;                         // staged row stride (odd)
-  static_assert(NS * RS <= 3 * NS * N, "point staging fits the SA/SB/SC region");
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
     const int64_t e = g * EPB + slot;
@@ -347,48 +348,36 @@ __global__ void __launch_bounds__(256)
         for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
       }
     }
-    // transposed eta_1 results -> LDS
-    if (act) {
+    // transposed eta_2 stage, z_t(k') and z'_t(k') for every (k', t) pair,
+    // from the transposed eta_1 results SA (with B2), SB (with dB2) and SC
+    // (with B2, into z'), which pass through one LDS buffer in turn so that a
+    // tetrahedron holds a third of them at a time
+    auto tpass = [&](const T (&R)[N], const T* tab2, T* dst, bool accumulate) {
+      if (act) {
 #pragma unroll
-      for (int p = 0; p < N; ++p) {
-        SS[t * N + p] = SA[p];
-        if constexpr (HELM) {
-          SS[(NS + t) * N + p] = SB[p];
-          SS[(2 * NS + t) * N + p] = SC[p];
+        for (int p = 0; p < N; ++p) SS[t * N + p] = R[p];
+      }
+      __syncthreads();
+      if (live) {
+        for (int idx = t; idx < Q3 * NMT; idx += NS) {
+          const int kk = idx / NMT, tt = idx - kk * NMT, p = tp[tt], tb_ = S::bcol(tt);
+          T z = accumulate ? dst[kk * NMT + tt] : T(0);
+#pragma unroll
+          for (int jj = 0; jj < Q2; ++jj) z += tab2[jj * TS + tb_] * SS[(jj + Q2 * kk) * N + p];
+          if (TRI && tt == P) {   // the collapsed triangle vertex C: its a_P part
+#pragma unroll
+            for (int jj = 0; jj < Q2; ++jj) z += tab2[jj * TS + P] * SS[(jj + Q2 * kk) * N + P];
+          }
+          dst[kk * NMT + tt] = z;
         }
       }
+      __syncthreads();
+    };
+    tpass(SA, B2, W, false);
+    if constexpr (HELM) {
+      tpass(SB, dB2, W, true);
+      tpass(SC, B2, W3, false);
     }
-    __syncthreads();
-    // transposed eta_2 stage: z_t(k'), z'_t(k') for every (k', t) pair
-    if (live) {
-      for (int idx = t; idx < Q3 * NMT; idx += NS) {
-        const int kk = idx / NMT, tt = idx - kk * NMT, p = tp[tt], tb_ = S::bcol(tt);
-        T z = T(0), z3 = T(0);
-#pragma unroll
-        for (int jj = 0; jj < Q2; ++jj) {
-          const int row = jj + Q2 * kk;
-          z += B2[jj * TS + tb_] * SS[row * N + p];
-          if constexpr (HELM) {
-            z += dB2[jj * TS + tb_] * SS[(NS + row) * N + p];
-            z3 += B2[jj * TS + tb_] * SS[(2 * NS + row) * N + p];
-          }
-        }
-        if (TRI && tt == P) {   // the collapsed triangle vertex C: its a_P part
-#pragma unroll
-          for (int jj = 0; jj < Q2; ++jj) {
-            const int row = jj + Q2 * kk;
-            z += B2[jj * TS + P] * SS[row * N + P];
-            if constexpr (HELM) {
-              z += dB2[jj * TS + P] * SS[(NS + row) * N + P];
-              z3 += B2[jj * TS + P] * SS[(2 * NS + row) * N + P];
-            }
-          }
-        }
-        W[kk * NMT + tt] = z;
-        if constexpr (HELM) W3[kk * NMT + tt] = z3;
-      }
-    }
-    __syncthreads();
     // transposed eta_3 stage: one output coefficient per iteration
     if (live) {
       for (int m = t; m < NM3; m += NS) {
