@@ -360,3 +360,34 @@ def test_signed_assembled_operator(dim, P, tile):
         if tile == "mfma":
             for dt in (m.F64, m.F32):
                 m.set_tile_config(m.OP_HELM, dim, P, dt, 0)
+
+
+@pytest.mark.parametrize("P", [2, 4, 7])
+def test_interior_last_numbering_operator_and_solve(P):
+    """The boundary-interior renumbering of the lattice (element interiors as
+    contiguous blocks): the assembled operator and the FP64 and FP32-refined
+    solves against the oracle with the same numbering."""
+    torch = torch_cuda()
+    m = nk()
+    shape = (3, 2, 2)
+    pb = _problem(shape, P, lam_seed=11)
+    l2g, ng, dm = W.lattice_l2g(shape, P, interior_last=True)
+    mats = oracle.helmholtz_matrices(pb["ops"])
+    A = MaskedOperator(mats, l2g, ng, dm)
+    space = m.Space.create(3, P, P + 2, to_dev(pb["Jg"]))
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm), lam=to_dev(pb["lam"]))
+    x = np.random.default_rng(5).uniform(-1, 1, ng)
+    assert_close(sysm.apply(to_dev(x)).cpu().numpy(), A(x), FP64_RTOL, f"interior-last apply P={P}")
+    y32 = sysm.apply(to_dev(x, torch.float32), dtype=m.F32).double().cpu().numpy()
+    assert_close(y32, A(x), FP32_RTOL, f"interior-last apply32 P={P}")
+    b = np.random.default_rng(6).uniform(-1, 1, ng)
+    b[dm.astype(bool)] = 0.0
+    # a rough random right-hand side: the true residual of the FP64 solve may
+    # exceed the recursive one it stops on by O(cond(A) eps) ~ 1e-11 at P = 7
+    xs, info = sysm.solve(to_dev(b), rtol=1e-12)
+    res = np.linalg.norm(b - A(xs.cpu().numpy())) / np.linalg.norm(b)
+    assert res <= 1e-11 and abs(res - info[0]["rel_resid"]) <= 1e-13
+    xref = direct_solve(mats, l2g, ng, dm, b)
+    assert rel_err(xs.cpu().numpy(), xref) < 1e-8
+    xr, info = sysm.solve(to_dev(b), rtol=1e-10, mode=m.SOLVE_F32_REFINED)
+    assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10

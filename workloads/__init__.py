@@ -185,7 +185,7 @@ def manufactured_ref_gradient(xi: np.ndarray, lat: Lattice):
 
 # ------------------------------------------------ lattice C0 numbering
 
-def lattice_l2g(shape, P: int):
+def lattice_l2g(shape, P: int, interior_last: bool = False):
     """Local-to-global map of a conforming structured lattice at uniform
     order P with the modified-basis mode order (vertex modes at 0 and P).
 
@@ -194,8 +194,12 @@ def lattice_l2g(shape, P: int):
       g = gx + Gx*(gy + Gy*gz),  G_c = N_c*P + 1.
     Right vertex mode P of element e coincides with left vertex mode 0 of
     element e+1; bubble modes interior to an element edge are shared along
-    that edge in the other directions.  Returns (l2g[E, n^d] int32, nglobal,
-    dirichlet[nglobal] uint8) with Dirichlet DOFs on the lattice boundary.
+    that edge in the other directions.  With interior_last, the same global
+    functions are renumbered: DOFs on element boundaries first (in the order
+    above), then each element's interior modes as one contiguous block, in
+    element order (the boundary-interior ordering).  Returns (l2g[E, n^d]
+    int32, nglobal, dirichlet[nglobal] uint8) with Dirichlet DOFs on the
+    lattice boundary.
     """
     shape = tuple(int(s) for s in shape)
     d = len(shape)
@@ -212,6 +216,17 @@ def lattice_l2g(shape, P: int):
     dir_mask = np.zeros(nglobal, np.uint8)
     for c in range(d):
         dir_mask |= ((gall[c] == 0) | (gall[c] == G[c] - 1)).astype(np.uint8)
+    if interior_last:
+        inner = np.all((midx > 0) & (midx < P), axis=0)             # (n^d,)
+        is_int = np.zeros(nglobal, bool)
+        is_int[g[:, inner].ravel()] = True
+        bnd = np.flatnonzero(~is_int)
+        new = np.empty(nglobal, np.int64)
+        new[bnd] = np.arange(bnd.size)
+        new[g[:, inner].ravel()] = bnd.size + np.arange(int(inner.sum()) * g.shape[0])
+        dm = np.empty_like(dir_mask)
+        dm[new] = dir_mask
+        return new[g].astype(np.int32), nglobal, dm
     return g.astype(np.int32), nglobal, dir_mask
 
 
