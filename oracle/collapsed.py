@@ -317,7 +317,9 @@ class TetOps:
         self.kappa = np.ones((E, nq)) if kappa is None else np.asarray(kappa, np.float64).reshape(E, nq)
         lam = np.asarray(lam, np.float64)
         self.lam = np.broadcast_to(lam, (E,)).copy() if lam.ndim == 0 else lam.reshape(E).copy()
-        self.wJ = self.W[None, :] * self.detJ
+        # the integrals take |det J|: an element given with left-handed vertex
+        # order (as sorting its vertices by global id can produce) has det J < 0
+        self.wJ = self.W[None, :] * np.abs(self.detJ)
 
     def mass_matrix(self, e):
         return self.Bt.T @ (self.wJ[e][:, None] * self.Bt)

@@ -1228,3 +1228,97 @@ def test_pyramidal_mesh_volume_and_orientation():
         assert ops.detJ.min() > 0
         errs.append(abs(ops.wJ.sum() - 1.0))
     assert max(errs) < 1e-13
+
+
+# --------------------- tetrahedral meshes: C0 assembly with sorted vertex orders
+
+def _tet_ref_coords(V, X):
+    """Reference coordinates (collapsed) of physical points X (k, 3) in the
+    straight-sided tetrahedron with vertices V (4, 3)."""
+    M = np.stack([V[1] - V[0], V[2] - V[0], V[3] - V[0]], axis=1)
+    xi = 2 * np.linalg.solve(M, (X - V[0]).T).T - 1
+    e3 = xi[:, 2]
+    e2 = 2 * (1 + xi[:, 1]) / (1 - xi[:, 2]) - 1
+    e1 = 2 * (1 + xi[:, 0]) / (-xi[:, 1] - xi[:, 2]) - 1
+    return e1, e2, e3
+
+
+@pytest.mark.parametrize("P", [2, 3, 5])
+def test_sorted_tetrahedral_numbering_is_continuous_across_faces(P):
+    """A random global vector gathered with the sorted-vertex numbering gives
+    element expansions that agree at random points of every shared face; with
+    the same numbering on the positively reordered vertices (B and C swapped
+    in half the elements) they do not."""
+    n = 2
+    l2g, ng, _ = W.tet_lattice_l2g(n, P)
+    x = np.random.default_rng(P).uniform(-1, 1, ng)
+    xl = oracle.gather(x, l2g)
+    rng = np.random.default_rng(10 + P)
+    for sorted_ids, expect_ok in ((True, True), (False, False)):
+        V = W.tet_lattice_vertices(n, sorted_ids=sorted_ids)
+        faces = {}
+        for e in range(V.shape[0]):
+            for f in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+                key = tuple(sorted(tuple(np.round(V[e, k] * n).astype(int)) for k in f))
+                faces.setdefault(key, []).append(e)
+        worst = 0.0
+        for key, els in faces.items():
+            if len(els) != 2:
+                continue
+            w = rng.dirichlet(np.ones(3), 4)
+            X = w @ (np.array(key, float) / n)
+            vals = []
+            for e in els:
+                Phi, _, _, _ = C.tet_basis(P, *_tet_ref_coords(V[e], X))
+                vals.append(Phi @ xl[e])
+            worst = max(worst, np.abs(vals[0] - vals[1]).max())
+        assert (worst < 1e-11) == expect_ok, (sorted_ids, worst)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_sorted_tetrahedral_projection_is_exact(P):
+    """Global L2 projection with the assembled mass matrix of the sorted
+    tetrahedral mesh (half the elements left-handed, |det J| in the
+    integrals) reproduces a polynomial of total degree P."""
+    n, Q = 2, P + 2
+    x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    x2, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    J = W.tet_lattice_jacobians(n, oracle.gll(Q)[0], x1, x2, 0.0, sorted_ids=True)
+    ops = C.TetOps(P, Q, J)
+    assert (ops.detJ < 0).any() and (ops.detJ > 0).any()
+    l2g, ng, _ = W.tet_lattice_l2g(n, P)
+    V = W.tet_lattice_vertices(n, sorted_ids=True)
+    r1, r2, r3 = C.xi_of_eta3(ops.e1, ops.e2, ops.e3)
+    X = (V[:, 0, :, None] + (V[:, 1] - V[:, 0])[:, :, None] * (1 + r1) / 2
+         + (V[:, 2] - V[:, 0])[:, :, None] * (1 + r2) / 2 + (V[:, 3] - V[:, 0])[:, :, None] * (1 + r3) / 2)
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    u = x ** (P - 1) * y - 2 * x * y * z ** (P - 2) + z ** P + 1
+    mats = [ops.mass_matrix(e) for e in range(ops.nelem)]
+    b = oracle.assemble_vector(ops.iprod(u), l2g, ng)
+    sol = oracle.direct_solve(mats, l2g, ng, np.zeros(ng, np.uint8), b)
+    assert np.abs(ops.bwd(oracle.gather(sol, l2g)) - u).max() < 1e-11
+
+
+def test_sorted_tetrahedral_helmholtz_solve_is_exact():
+    """-lap u + u = f on the unit cube, u = x(1-x)y(1-y)z(1-z) (degree 6,
+    zero on the boundary), P = 6, weak right-hand side, Dirichlet boundary:
+    the assembled tetrahedral solve reproduces u at every point."""
+    n, P = 1, 6
+    Q = P + 2
+    x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    x2, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    J = W.tet_lattice_jacobians(n, oracle.gll(Q)[0], x1, x2, 0.0, sorted_ids=True)
+    ops = C.TetOps(P, Q, J)
+    l2g, ng, dm = W.tet_lattice_l2g(n, P)
+    V = W.tet_lattice_vertices(n, sorted_ids=True)
+    r1, r2, r3 = C.xi_of_eta3(ops.e1, ops.e2, ops.e3)
+    X = (V[:, 0, :, None] + (V[:, 1] - V[:, 0])[:, :, None] * (1 + r1) / 2
+         + (V[:, 2] - V[:, 0])[:, :, None] * (1 + r2) / 2 + (V[:, 3] - V[:, 0])[:, :, None] * (1 + r3) / 2)
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    s = lambda t: t * (1 - t)
+    u = s(x) * s(y) * s(z)
+    f = 2 * (s(y) * s(z) + s(x) * s(z) + s(x) * s(y)) + u
+    mats = [ops.helmholtz_matrix(e) for e in range(ops.nelem)]
+    b = oracle.assemble_vector(ops.iprod(f), l2g, ng)
+    sol = oracle.direct_solve(mats, l2g, ng, dm, b)
+    assert np.abs(ops.bwd(oracle.gather(sol, l2g)) - u).max() < 1e-12

@@ -424,14 +424,17 @@ def tri_lattice_l2g(n: int, P: int, rot=None):
     return l2g.astype(np.int32), sign, nglobal, dirichlet
 
 
-def tet_lattice_vertices(n: int) -> np.ndarray:
+def tet_lattice_vertices(n: int, sorted_ids: bool = False) -> np.ndarray:
     """Vertex coordinates of the tetrahedral mesh of the unit cube: an n^3
     lattice of cubes (cube index i + n (j + n k)), each split into the six
     tetrahedra of the path decomposition, v0 = corner, v1 = v0 + h e_a,
     v2 = v1 + h e_b, v3 = v0 + h (1, 1, 1) for the permutations (a, b, c)
-    of the axes; for odd permutations v1 and v2 are swapped so that every
-    tetrahedron (A, B, C, D) = (v0, v1, v2, v3) is positively oriented.
-    Returns (E, 4, 3), E = 6 n^3, element 6 cube + permutation index."""
+    of the axes.  By default v1 and v2 are swapped for odd permutations so
+    that every tetrahedron (A, B, C, D) = (v0, v1, v2, v3) is positively
+    oriented; with sorted_ids the path order is kept, which is the order of
+    the lattice vertex ids i + (n+1)(j + (n+1) k) (half the tetrahedra are
+    then left-handed).  Returns (E, 4, 3), E = 6 n^3, element 6 cube +
+    permutation index."""
     h = 1.0 / n
     c = np.arange(n ** 3)
     corner = np.stack([c % n, (c // n) % n, c // (n * n)], axis=1) * h      # (n^3, 3)
@@ -443,13 +446,14 @@ def tet_lattice_vertices(n: int) -> np.ndarray:
         v1 = v0 + eye[a]
         v2 = v1 + eye[b]
         v3 = v0 + h
-        if t >= 3:
+        if t >= 3 and not sorted_ids:
             v1, v2 = v2, v1
         out[:, t] = np.stack([v0, v1, v2, v3], axis=1)
     return out.reshape(-1, 4, 3)
 
 
-def tet_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems=None):
+def tet_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems=None,
+                          sorted_ids: bool = False):
     """Jacobians of the tetrahedral mesh of the unit cube
     (tet_lattice_vertices), composed with the cyclic curving map `warp`.  With
     vertices (A, B, C, D), the affine reference map is x = A (-(1 + xi_1 +
@@ -466,7 +470,7 @@ def tet_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems
     x3 = E3
     x2 = (1 + E2) * (1 - E3) / 2 - 1
     x1 = (1 + E1) * (1 - E2) * (1 - E3) / 4 - 1
-    V = tet_lattice_vertices(n)
+    V = tet_lattice_vertices(n, sorted_ids)
     if elems is not None:
         V = V[np.asarray(elems)]
     A = np.stack([(V[:, 1] - V[:, 0]) / 2, (V[:, 2] - V[:, 0]) / 2, (V[:, 3] - V[:, 0]) / 2], axis=2)
@@ -476,6 +480,101 @@ def tet_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems
          + V[:, 2, :, None] * ((1 + x2) / 2) + V[:, 3, :, None] * ((1 + x3) / 2))     # (E, 3, nq)
     Wm = warp_jacobian(X, amp)                                                        # (E, c, b, nq)
     return np.einsum("ecbq,eba->ecaq", Wm, A)
+
+
+def tet_lattice_l2g(n: int, P: int):
+    """C0 numbering of the tetrahedral mesh with sorted vertex orders
+    (tet_lattice_vertices(n, sorted_ids=True)), for the tetrahedron modes
+    (triangle mode t = (p, q) of the order-P triangle in its mode order, r
+    fastest, the top vertex last).  With every element's vertices in
+    increasing global id, each edge is traversed from its lower to its
+    higher vertex and each face has its highest vertex as the collapsed one,
+    in every element that shares it, so no signs are needed.  Global DOFs:
+    lattice vertices; P-1 bubbles per mesh edge (k = 1..P-1); the interior
+    modes (i, j), i, j >= 1, i + j <= P-1, of each mesh face; then the
+    interior modes of each element.  Local modes by the tetrahedron's
+    entities: vertices A = ((0,0), 0), B = ((P,0), 0), C = ((0,P), 0), D (top);
+    edges AB ((p,0), 0), AC ((0,q), 0), BC ((P,q), 0) with bubble p or q, AD
+    ((0,0), r), BD ((P,0), r), CD ((0,P), r) with bubble r; faces ABC
+    ((p,q), 0) -> (p, q), ABD ((p,0), r) -> (p, r), ACD ((0,q), r) -> (q, r),
+    BCD ((P,q), r) -> (q, r); interior ((p,q), r >= 1) with p, q >= 1.
+    Dirichlet: vertices, edges and faces on the boundary of the unit cube.
+    Returns (l2g (E, nm) int32, nglobal, dirichlet uint8)."""
+    V = tet_lattice_vertices(n, sorted_ids=True)
+    E = V.shape[0]
+    ids = np.rint(V[..., 0] * n).astype(np.int64) + (n + 1) * (
+        np.rint(V[..., 1] * n).astype(np.int64) + (n + 1) * np.rint(V[..., 2] * n).astype(np.int64))
+    assert np.all(np.diff(ids, axis=1) > 0)
+    nv = (n + 1) ** 3
+    nb = max(P - 1, 0)
+    fmodes = [(i, j) for i in range(1, P) for j in range(1, P - i)]
+    nf = len(fmodes)
+    fidx = {ij: k for k, ij in enumerate(fmodes)}
+    tri = [(0, q) for q in range(P + 1)] + [(p, q) for p in range(1, P) for q in range(P - p)] \
+        + [(P, q) for q in range(P)]
+
+    def deg(p, q):
+        if (p in (0, P) and q == 0) or (p == 0 and q == P):
+            return 1
+        if p in (0, P):
+            return q + 1
+        return p + 1 if q == 0 else p + q + 1
+    modes = [((p, q), r) for (p, q) in tri for r in range(P - deg(p, q) + 1)] + [None]
+    ninner = sum(1 for mm in modes if mm and mm[0][0] not in (0, P) and mm[0][1] >= 1 and mm[1] >= 1)
+    edges, faces = {}, {}
+    for e in range(E):
+        a, b, c, d = ids[e]
+        for pair in ((a, b), (a, c), (b, c), (a, d), (b, d), (c, d)):
+            edges.setdefault(pair, len(edges))
+        for tri3 in ((a, b, c), (a, b, d), (a, c, d), (b, c, d)):
+            faces.setdefault(tri3, len(faces))
+    ne, nfc = len(edges), len(faces)
+    e0, f0 = nv, nv + ne * nb
+    i0 = f0 + nfc * nf
+    nglobal = i0 + E * ninner
+    l2g = np.empty((E, len(modes)), np.int64)
+    for e in range(E):
+        A_, B_, C_, D_ = ids[e]
+        it = 0
+        for mi, mm in enumerate(modes):
+            if mm is None:
+                g = D_
+            else:
+                (p, q), r = mm
+                vert = {(0, 0): A_, (P, 0): B_, (0, P): C_}
+                if (p, q) in vert and r == 0:
+                    g = vert[(p, q)]
+                elif (p, q) in vert:                       # rising edges AD, BD, CD
+                    g = e0 + edges[(vert[(p, q)], D_)] * nb + r - 1
+                elif r == 0 and q == 0:                     # edge AB
+                    g = e0 + edges[(A_, B_)] * nb + p - 1
+                elif r == 0 and p == 0:                     # edge AC
+                    g = e0 + edges[(A_, C_)] * nb + q - 1
+                elif r == 0 and p == P:                     # edge BC
+                    g = e0 + edges[(B_, C_)] * nb + q - 1
+                elif r == 0:                                # face ABC
+                    g = f0 + faces[(A_, B_, C_)] * nf + fidx[(p, q)]
+                elif q == 0:                                # face ABD
+                    g = f0 + faces[(A_, B_, D_)] * nf + fidx[(p, r)]
+                elif p == 0:                                # face ACD
+                    g = f0 + faces[(A_, C_, D_)] * nf + fidx[(q, r)]
+                elif p == P:                                # face BCD
+                    g = f0 + faces[(B_, C_, D_)] * nf + fidx[(q, r)]
+                else:                                       # interior
+                    g = i0 + e * ninner + it
+                    it += 1
+            l2g[e, mi] = g
+    coord = lambda v: np.stack([v % (n + 1), (v // (n + 1)) % (n + 1), v // (n + 1) ** 2], axis=-1)
+    on = lambda v: (coord(v) == 0) | (coord(v) == n)                  # (…, 3) per axis
+    dm = np.zeros(nglobal, np.uint8)
+    dm[:nv][np.any(on(np.arange(nv)), axis=1)] = 1
+    for (a, b), k in edges.items():
+        if np.any(on(a) & on(b) & (coord(a) == coord(b))):
+            dm[e0 + k * nb: e0 + (k + 1) * nb] = 1
+    for (a, b, c), k in faces.items():
+        if np.any(on(a) & on(b) & on(c) & (coord(a) == coord(b)) & (coord(b) == coord(c))):
+            dm[f0 + k * nf: f0 + (k + 1) * nf] = 1
+    return l2g.astype(np.int32), nglobal, dm
 
 
 def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, elems=None):
