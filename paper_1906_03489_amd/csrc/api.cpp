@@ -855,8 +855,9 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
   if (s->groups.size() != 1 && nsys != 1)
     return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
-  if (s->shape == 1 && nsys != 1) return fail(NK_EINVAL, "a triangle space takes one system (nsys = 1)");
-  if (s->shape >= 2) return fail(NK_EUNSUPPORTED, "assembled systems are not built for tetrahedra, prisms and pyramids");
+  if ((s->shape == 1 || s->shape == 2) && nsys != 1)
+    return fail(NK_EINVAL, "a triangle or tetrahedron space takes one system (nsys = 1)");
+  if (s->shape >= 3) return fail(NK_EUNSUPPORTED, "assembled systems are not built for prisms and pyramids");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
   if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
     return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");
@@ -1016,13 +1017,18 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
     if ((e = vec_fill<double>(y->y, np, 0.0, st))) break;
     for (size_t g = 0; g < s->groups.size() && e == hipSuccess; ++g) {
       const Group& G = s->groups[g];
-      const int nl = s->shape == 1 ? G.n * (G.n + 1) / 2 : (int)ipow(G.n, s->dim);
+      const int nl = s->shape == 1   ? G.n * (G.n + 1) / 2
+                     : s->shape == 2 ? G.n * (G.n + 1) * (G.n + 2) / 6
+                                     : (int)ipow(G.n, s->dim);
       if ((e = build_l2g(G.nelem, nl, y->elem_seg + G.e0, y->d_dof_off, y->d_pdof_off, l2g + G.c0,
                          sign ? sign + G.c0 : nullptr, dirichlet, y->l2g + G.c0, d_bad, st)))
         break;
       if ((e = mark_free(G.nelem, nl, y->l2g + G.c0, y->y, st))) break;
       if (s->shape == 1)
         e = launch_diag_tri(G.P, G.nelem, s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr, y->lam0,
+                            y->l2g + G.c0, y->diag, st);
+      else if (s->shape == 2)
+        e = launch_diag_tet(G.P, G.nelem, s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr, y->lam0,
                             y->l2g + G.c0, y->diag, st);
       else
         e = launch_diag(s->dim, G.P, G.Q, G.nelem, d_B + tab_off[g], d_D + tab_off[g],
@@ -1118,6 +1124,7 @@ static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, vo
   a.tile = tile;
   a.stream = st;
   if (s->shape == 1) return launch_tri(t, a);
+  if (s->shape == 2) return launch_tet(t, a);
   return launch_op(s->dim, t, a);
 }
 
@@ -1474,7 +1481,7 @@ static void cache_store(const std::string& key, int tile, double us) {
 static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st) {
   nk_space s = y->space;
   const Group& G = s->groups[g];
-  if (s->shape == 1) return 0;   // triangle kernels have one launch shape
+  if (s->shape != 0) return 0;   // collapsed-shape kernels have one launch shape
   const int fallback = cur_tile(OP_HELM_ASM, s->dim, G.P, t);
   const int nt = tile_count(OP_HELM_ASM, s->dim, G.P);
   if (nt <= 1 || G.nelem == 0 || g_tile_forced[s->dim - 2][G.P][t].load()) return fallback;

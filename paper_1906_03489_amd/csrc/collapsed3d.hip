@@ -186,10 +186,12 @@ __global__ void __launch_bounds__(256)
   constexpr bool APEX = S::APEX, TRI = SH != kPyr;   // TRI: triangle lower part
   constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS, NC = S::NC, NB = S::NB;
   constexpr int EPB = S::template epb<T>();
-  constexpr bool HELM = OP == OP_HELM;
+  constexpr bool ASM = OP == OP_HELM_ASM;                // gathered input, scattered output
+  constexpr bool HELM = OP == OP_HELM || ASM;
   __shared__ T stab[S::NTAB];
   __shared__ int sit[S::NITAB];
   __shared__ T smem[EPB * S::SLOT];
+  __shared__ double sred[ASM ? 256 : 1];                 // per-thread energy parts
   for (int k = threadIdx.x; k < Q2 * NB; k += blockDim.x) {
     const int r = k / NB, m = k - r * NB;
     stab[r * TS + m] = tab[k];
@@ -222,14 +224,24 @@ __global__ void __launch_bounds__(256)
   constexpr int RS = Q | 1;                         // staged row stride (odd)
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
+    // a converged system skips its operator (one system per collapsed space)
+    if (ASM && a.elem_seg != nullptr && a.seg_done[a.elem_seg[g * EPB]] != 0) continue;
     const int64_t e = g * EPB + slot;
     const bool live = act && e < a.nelem;
     T SA[N], SB[N], SC[N];
 #pragma unroll
     for (int p = 0; p < N; ++p) SA[p] = SB[p] = SC[p] = T(0);
     if constexpr (OP != OP_IPROD) {
-      if (live)
-        for (int m = t; m < NM3; m += NS) U[m] = a.in[e * NM3 + m];
+      if (live) {
+        for (int m = t; m < NM3; m += NS) {
+          if constexpr (ASM) {
+            const int32_t gv = a.l2g[e * NM3 + m];
+            U[m] = gv >= 0 ? l2g_sign(gv, a.in[l2g_dof(gv)]) : T(0);
+          } else {
+            U[m] = a.in[e * NM3 + m];
+          }
+        }
+      }
       __syncthreads();
       // eta_3 stage: w_t(k') (and dw/deta_3) for every (k', t) pair
       if (live) {
@@ -379,6 +391,7 @@ __global__ void __launch_bounds__(256)
       tpass(SC, B2, W3, false);
     }
     // transposed eta_3 stage: one output coefficient per iteration
+    double dp = 0.0;   // this thread's part of x_e . (H_e x_e)
     if (live) {
       for (int m = t; m < NM3; m += NS) {
         const int tt = mt[m];
@@ -403,11 +416,35 @@ __global__ void __launch_bounds__(256)
             }
           }
         }
-        a.out[e * NM3 + m] = y;
+        if constexpr (ASM) {
+          dp += (double)U[m] * (double)y;
+          const int32_t gv = a.l2g[e * NM3 + m];
+          if (gv >= 0) atomic_add(a.out + l2g_dof(gv), l2g_sign(gv, y));
+        } else {
+          a.out[e * NM3 + m] = y;
+        }
+      }
+    }
+    if constexpr (ASM) {   // per-element energy for the CG step length
+      sred[threadIdx.x] = dp;
+      __syncthreads();
+      if (live && t == 0 && a.dots) {
+        double s_ = 0.0;
+        for (int k2 = 0; k2 < NS; ++k2) s_ += sred[slot * NS + k2];
+        a.dots[a.dslot ? a.dslot[e] : e] = s_;
       }
     }
     __syncthreads();
   }
+}
+
+// The assembled operator exists for tetrahedra only (sorted-vertex meshes).
+template <typename T, int P, int SH>
+static const void* asm_kernel() {
+  if constexpr (SH == kTet)
+    return (const void*)k_tet<T, P, SH, OP_HELM_ASM>;
+  else
+    return nullptr;
 }
 
 template <typename T, int P, int SH>
@@ -417,7 +454,7 @@ static int64_t tet_grid(int op) {
   std::lock_guard<std::mutex> lk(mu);
   int dev = 0, cus = 0, nb = 0;
   (void)hipGetDevice(&dev);
-  const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : 2);
+  const int key = dev * 4 + (op == OP_BWD ? 0 : op == OP_IPROD ? 1 : op == OP_HELM ? 2 : 3);
   auto it = cached.find(key);
   if (it != cached.end()) return it->second;
   using S = TetShape<P, SH>;
@@ -425,7 +462,8 @@ static int64_t tet_grid(int op) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const void* fn = op == OP_BWD     ? (const void*)k_tet<T, P, SH, OP_BWD>
                    : op == OP_IPROD ? (const void*)k_tet<T, P, SH, OP_IPROD>
-                                    : (const void*)k_tet<T, P, SH, OP_HELM>;
+                   : op == OP_HELM  ? (const void*)k_tet<T, P, SH, OP_HELM>
+                                    : asm_kernel<T, P, SH>();
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0);
   const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (nb > 0 ? nb : 1) * 4;
   cached[key] = grid;
@@ -457,6 +495,13 @@ static hipError_t run_tet(const OpArgs& a) {
     case OP_HELM:
       hipLaunchKernelGGL((k_tet<T, P, SH, OP_HELM>), g, b, 0, a.stream, tb, tab, tt.itab, d);
       break;
+    case OP_HELM_ASM:
+      if constexpr (SH == kTet) {
+        hipLaunchKernelGGL((k_tet<T, P, SH, OP_HELM_ASM>), g, b, 0, a.stream, tb, tab, tt.itab, d);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -488,6 +533,96 @@ static hipError_t launch_col(nk_dtype t, const OpArgs& a) {
 hipError_t launch_tet(nk_dtype t, const OpArgs& a) { return launch_col<kTet>(t, a); }
 hipError_t launch_prism(nk_dtype t, const OpArgs& a) { return launch_col<kPrism>(t, a); }
 hipError_t launch_pyr(nk_dtype t, const OpArgs& a) { return launch_col<kPyr>(t, a); }
+
+// Diagonal of the tetrahedron Helmholtz operator, thread per (tetrahedron,
+// mode), scatter-added into the padded global diagonal (Dirichlet modes
+// skipped): diag H_e[m] = sum_points (lambda f0 phi_m^2 + d^T G' d) with d the
+// three collapsed derivatives of phi_m and G' the 6 stored factors.  A mode
+// is T_t(eta_1, eta_2) c(eta_3) (the collapsed triangle vertex C as
+// (a_0 + a_P) times its eta_2 factor), the top vertex c(eta_3) alone.
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_diag_tet(const Tab<double, P + 1, P + 2> tb, const double* __restrict__ tab,
+               const int* __restrict__ itab, int64_t nelem, const double* __restrict__ fac,
+               const double* __restrict__ lam, double lam0, const int32_t* __restrict__ l2g,
+               double* __restrict__ diag) {
+  using S = TetShape<P, kTet>;
+  constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
+  constexpr int NMT = S::NMT, NM3 = S::NM3;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nelem * NM3) return;
+  const int64_t e = id / NM3;
+  const int m = (int)(id - e * NM3);
+  const int32_t g = l2g[id];
+  if (g < 0) return;  // Dirichlet: row replaced by the identity
+  const double* B2 = tab;
+  const double* dB2 = tab + Q2 * NMT;
+  const double* C3 = tab + 2 * Q2 * NMT;
+  const double* dC3 = C3 + Q3 * NM3;
+  const int tt = itab[2 * NMT + 1 + m];       // triangle mode, -1 for the top vertex
+  const int p = tt >= 0 ? itab[NMT + 1 + tt] : 0;
+  const double* f = fac + e * (int64_t)(7 * NPT);
+  const double lm = lam ? lam[e] : lam0;
+  double s = 0.0;
+  for (int k = 0; k < Q3; ++k) {
+    const double c = C3[k * NM3 + m], dc = dC3[k * NM3 + m];
+    for (int j = 0; j < Q2; ++j) {
+      double b = 1.0, db = 0.0;
+      if (tt >= 0) {
+        b = B2[j * NMT + tt];
+        db = dB2[j * NMT + tt];
+      }
+      for (int i = 0; i < Q; ++i) {
+        double av = 1.0, dav = 0.0;
+        if (tt >= 0) {
+          av = tb.B[i * N + p];
+          dav = tb.D[i * N + p];
+          if (tt == P) {   // collapsed triangle vertex
+            av += tb.B[i * N + P];
+            dav += tb.D[i * N + P];
+          }
+        }
+        const double ph = av * b * c, d1 = dav * b * c, d2 = av * db * c, d3 = av * b * dc;
+        const double* fp = f + (int64_t)i * NS + j + Q2 * k;
+        const double f0 = fp[0], g11 = fp[NPT], g12 = fp[2 * NPT], g13 = fp[3 * NPT],
+                     g22 = fp[4 * NPT], g23 = fp[5 * NPT], g33 = fp[6 * NPT];
+        s += lm * f0 * ph * ph + g11 * d1 * d1 + g22 * d2 * d2 + g33 * d3 * d3 +
+             2.0 * (g12 * d1 * d2 + g13 * d1 * d3 + g23 * d2 * d3);
+      }
+    }
+  }
+  unsafeAtomicAdd(diag + l2g_dof(g), s);
+}
+
+template <int P>
+static hipError_t run_diag_tet(int64_t nelem, const double* fac, const double* lam, double lam0,
+                               const int32_t* l2g, double* diag, hipStream_t st) {
+  const TetTables tt = tet_tables<double>(P, kTet);
+  if (!tt.tab) return hipErrorOutOfMemory;
+  const int64_t tot = nelem * TetShape<P, kTet>::NM3;
+  hipLaunchKernelGGL(k_diag_tet<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     host_tab<double, P + 1, P + 2>(), static_cast<const double*>(tt.tab), tt.itab,
+                     nelem, fac, lam, lam0, l2g, diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_tet(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                           const int32_t* l2g, double* diag, hipStream_t st) {
+  if (nelem == 0) return hipSuccess;
+  switch (P) {
+    case 1: return run_diag_tet<1>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 2: return run_diag_tet<2>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 3: return run_diag_tet<3>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 4: return run_diag_tet<4>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 5: return run_diag_tet<5>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 6: return run_diag_tet<6>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 7: return run_diag_tet<7>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 8: return run_diag_tet<8>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 9: return run_diag_tet<9>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 10: return run_diag_tet<10>(nelem, fac, lam, lam0, l2g, diag, st);
+  }
+  return hipErrorInvalidValue;
+}
 
 // Factors of the collapsed tetrahedron or prism at every point (thread per
 // point): f0 = w detJ, f1..f6 = w detJ kappa (M G M^T)_{11,12,13,22,23,33}
@@ -563,12 +698,16 @@ __global__ void __launch_bounds__(256)
       H[a_][b] = s;
     }
   const double kap = kappa ? kappa[e * NP + q] : 1.0;
+  // tetrahedra may be left-handed (sorted vertex orders give det J < 0 in
+  // half the elements of a mesh): the integrals take |det J|, and only a zero
+  // or non-finite determinant is rejected
+  const double adet = SH == kTet ? fabs(det) : det;
+  if (!(adet > 0.0) || !(adet < 1e300) || !(kap > 0.0)) atomicOr(bad, 1);
   // the Radau weights carry (1 - eta_2) (tetrahedron, prism) and
   // (1 - eta_3)^2 (tetrahedron, pyramid)
-  const double wj = w1 * (SH == kPyr ? 1.0 : 0.5) * w2 * (SH == kPrism ? 1.0 : 0.25) * w3 * det;
+  const double wj = w1 * (SH == kPyr ? 1.0 : 0.5) * w2 * (SH == kPrism ? 1.0 : 0.25) * w3 * adet;
   const double ck = wj * kap;
   const double f[7] = {wj, ck * H[0][0], ck * H[0][1], ck * H[0][2], ck * H[1][1], ck * H[1][2], ck * H[2][2]};
-  if (!(det > 0.0) || !(kap > 0.0)) atomicOr(bad, 1);
   for (int c = 0; c < 7; ++c) {
     const int64_t o = (e * 7 + c) * (int64_t)NP + (int64_t)i * NS + row;
     fac64[o] = f[c];

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import workloads as W
 from oracle import collapsed as C
-from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, to_dev, torch_cuda
+from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, rel_err, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -91,15 +91,11 @@ def test_empty_tetrahedron_space_and_unsupported_calls():
     with pytest.raises(m.NkError) as ei:
         m.phys_deriv(space, torch.zeros(Jg.shape[0] * nq, dtype=torch.float64, device="cuda"))
     assert ei.value.status == m.NK_EUNSUPPORTED
-    nm = (P + 1) * (P + 2) * (P + 3) // 6
-    l2g = np.arange(Jg.shape[0] * nm, dtype=np.int32)
-    with pytest.raises(m.NkError) as ei:
-        m.System.create(space, l2g.size, to_dev(l2g), to_dev(np.zeros(l2g.size, np.uint8)))
-    assert ei.value.status == m.NK_EUNSUPPORTED
     bad = Jg.copy()
-    bad[0, :, 0] *= -1.0          # mirrored element
-    with pytest.raises(m.NkError):
+    bad[0, :, 0] = 0.0            # degenerate element (det J = 0)
+    with pytest.raises(m.NkError) as ei:
         m.Space.create_tet(P, Q, to_dev(bad))
+    assert ei.value.status == m.NK_EINVAL
 
 
 def test_full_size_tetrahedra_p4_sampled():
@@ -128,3 +124,76 @@ def test_full_size_tetrahedra_p4_sampled():
                m.helmholtz(space, to_dev(c, td), lam0=1.0, dtype=dt).double().cpu().numpy().reshape(E, nm)]
         for name, g, r in zip(("bwd", "iprod", "helm"), got, ref):
             assert_close(g[sample], r, tol, f"full-size tet {name} dt={dt}")
+
+
+# ---------------------------- assembled tetrahedral systems (sorted vertex orders)
+
+def _tet_system_case(P, n=2, amp=W.WARP_AMPLITUDE):
+    """Curved tetrahedral mesh with sorted (partly left-handed) vertex
+    orders, per-point kappa and per-element lambda; the oracle's elemental
+    matrices and the GPU system built from the same numbering."""
+    m = nk()
+    Q = P + 2
+    e1g, _, e2g, _, e3g, _ = m.tet_points(Q)
+    Jg = W.tet_lattice_jacobians(n, e1g, e2g, e3g, amp, sorted_ids=True)
+    x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    x2, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    Jo = W.tet_lattice_jacobians(n, oracle.gll(Q)[0], x1, x2, amp, sorted_ids=True)
+    l2g, ng, dm = W.tet_lattice_l2g(n, P)
+    E, nq = Jg.shape[0], Q * (Q - 1) ** 2
+    rng = np.random.default_rng(190 + P)
+    kap = rng.uniform(0.5, 2.0, (E, nq))
+    lam = rng.uniform(0.5, 2.0, E)
+    ops = C.TetOps(P, Q, Jo, kappa=kap, lam=lam)
+    mats = [ops.helmholtz_matrix(e) for e in range(E)]
+    space = m.Space.create_tet(P, Q, to_dev(Jg), kappa=to_dev(kap))
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm), lam=to_dev(lam))
+    return dict(ops=ops, mats=mats, l2g=l2g, ng=ng, dm=dm, space=space, sys=sysm, E=E)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 5, 7])
+def test_tetrahedral_system_operator_diag_gather_assemble(P):
+    """The assembled tetrahedral operator (gather, elemental Helmholtz with
+    |det J|, scatter-add, Dirichlet rows masked), its Jacobi diagonal, gather
+    and assembly against the oracle."""
+    from oracle.assembly import MaskedOperator, jacobi_diagonal
+    torch = torch_cuda()
+    m = nk()
+    c = _tet_system_case(P, n=2 if P <= 5 else 1)
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"])
+    x = np.random.default_rng(P).uniform(-1, 1, c["ng"])
+    ref = A(x)
+    sysm = c["sys"]
+    assert_close(sysm.apply(to_dev(x)).cpu().numpy(), ref, FP64_RTOL, f"tet apply P={P}")
+    y32 = sysm.apply(to_dev(x, torch.float32), dtype=m.F32).double().cpu().numpy()
+    assert_close(y32, ref, FP32_RTOL, f"tet apply32 P={P}")
+    dref = jacobi_diagonal(c["mats"], c["l2g"], c["ng"], c["dm"])
+    assert_close(sysm.diagonal().cpu().numpy(), dref, FP64_RTOL, f"tet diag P={P}")
+    xl = sysm.gather(to_dev(x)).cpu().numpy()
+    np.testing.assert_array_equal(xl, oracle.gather(x, c["l2g"]).ravel())
+    yl = np.random.default_rng(P + 1).uniform(-1, 1, xl.size)
+    bref = oracle.assemble_vector(yl.reshape(c["E"], -1), c["l2g"], c["ng"])
+    bref[c["dm"].astype(bool)] = 0.0
+    assert_close(sysm.assemble(to_dev(yl)).cpu().numpy(), bref, 1e-14, f"tet assemble P={P}")
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_tetrahedral_cg_solves_match_direct_solve(P):
+    """FP64 PCG to 1e-12 and the FP32-refined solve to 1e-10 on the curved
+    tetrahedral mesh, against the oracle's sparse direct solve."""
+    from oracle.assembly import MaskedOperator, direct_solve
+    m = nk()
+    torch_cuda()
+    c = _tet_system_case(P, n=3)
+    b = np.random.default_rng(95 + P).uniform(-1, 1, c["ng"])
+    b[c["dm"].astype(bool)] = 0.0
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"])
+    xref = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b)
+    x, info = c["sys"].solve(to_dev(b), rtol=1e-12, maxit=20000)
+    xs = x.cpu().numpy()
+    assert info[0]["status"] == 0
+    assert np.linalg.norm(b - A(xs)) / np.linalg.norm(b) <= 1e-11
+    assert rel_err(xs, xref) < 1e-8
+    xr, info = c["sys"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_F32_REFINED)
+    assert info[0]["status"] == 0
+    assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
