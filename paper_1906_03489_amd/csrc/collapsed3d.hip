@@ -55,9 +55,11 @@ struct TetShape {
                              : SH == kPrism ? NMT * N
                                             : N * (N + 1) * (2 * N + 1) / 6;
   static constexpr bool APEX = SH != kPrism;   // a top vertex riding on the lower vertices
-  // columns of the third-direction table: one per mode, or one per 1-D mode
-  // r for prisms (the factor depends on r only)
-  static constexpr int NC = SH == kPrism ? N : NM3;
+  // columns of the third-direction table.  A tetrahedron or pyramid mode's
+  // third-direction factor depends only on the degree s >= 1 of its lower
+  // mode and on r (0 <= r <= P - s), so the table holds one column per (s, r)
+  // pair, s slow, then the top vertex; a prism's depends on r only
+  static constexpr int NC = SH == kPrism ? N : P * (P + 1) / 2 + 1;
   // columns of the eta_2 table: one per lower mode, or one per 1-D mode q
   // for pyramids (phi_q(eta_2) depends on q only)
   static constexpr int NB = SH == kPyr ? N : NMT;
@@ -66,21 +68,29 @@ struct TetShape {
   // distinct banks
   static constexpr int TS = NB | 1, CS = NC | 1;
   static constexpr int NTAB = 2 * Q2 * TS + 2 * Q3 * CS;        // B2, dB2, C3, dC3
-  static constexpr int ccol(int m) { return SH == kPrism ? m % N : m; }
   // vertex modes of the lower part (the apex rides on them)
   static constexpr bool lower_vertex(int t) {
     return SH == kPyr ? (t == 0 || t == P || t == P * N || t == P * N + P)
                       : (t == 0 || t == P || t == NMT - P);
   }
-  static constexpr int NITAB = 2 * NMT + 1 + NM3;               // toff3, tp, mt
-  // u, w | w', the transposed eta_1 buffer (one of SA, SB, SC at a time, or
-  // BwdTrans's staged rows of stride Q | 1)
-  static constexpr int SLOT = NM3 + 2 * Q3 * NMT + NS * (Q | 1);
-  // tetrahedra per block: up to 256 threads, within ~150 KB of LDS
+  static constexpr int NITAB = 3 * NMT + 1 + NM3;               // toff3, tp, mt, tcol
+  // Per-element LDS of operator OP, in scalars: the coefficients u (not for
+  // IProductWRTBase), w, w' (Helmholtz only), then the transposed eta_1
+  // buffer [NS][N] (one of SA, SB, SC at a time) or BwdTrans's staged point
+  // rows [NS][Q | 1]
+  static constexpr int RS = Q | 1;
+  static constexpr int u_off(int) { return 0; }
+  static constexpr int w_off(int op) { return op == OP_IPROD ? 0 : NM3; }
+  static constexpr int w3_off(int op) { return w_off(op) + Q3 * NMT; }
+  static constexpr int ss_off(int op) {
+    return w3_off(op) + (op == OP_HELM || op == OP_HELM_ASM ? Q3 * NMT : 0);
+  }
+  static constexpr int slot(int op) { return ss_off(op) + NS * (op == OP_BWD ? RS : N); }
+  // elements per block: up to 256 threads, within ~150 KB of LDS
   template <typename T>
-  static constexpr int epb() {
+  static constexpr int epb(int op) {
     const int by_threads = 256 / NS > 0 ? 256 / NS : 1;
-    const int by_lds = (int)((150000 / sizeof(T) - NTAB) / SLOT);
+    const int by_lds = (int)((150000 / sizeof(T) - NTAB) / slot(op));
     const int e = by_threads < by_lds ? by_threads : by_lds;
     return e > 0 ? e : 1;
   }
@@ -92,12 +102,14 @@ struct TetShape {
   }
 };
 
-// Device tables of order P: B2 [Q2][NB], dB2 [Q2][NB] at the eta_2 points (NB
-// = NMT lower modes, or P+1 for pyramids),
-// C3 [Q3][NC], dC3 [Q3][NC] at the third-direction points (NC = NM3 for
-// tetrahedra, P+1 for prisms; scalars of type T), and the integer maps toff3 [NMT+1] (first coefficient of each triangle
-// mode), tp [NMT] (eta_1 index p of each triangle mode), mt [NM3] (triangle
-// mode of each coefficient, -1 for the top vertex).
+// Device tables of order P (scalars of type T): B2 [Q2][NB], dB2 [Q2][NB] at
+// the eta_2 points (NB = NMT lower modes, or P+1 for pyramids); C3 [Q3][NC],
+// dC3 [Q3][NC] at the third-direction points (one column per (degree, r)
+// pair and the top vertex for tetrahedra and pyramids, P+1 for prisms).
+// Integer maps: toff3 [NMT+1] (first coefficient of each lower mode), tp
+// [NMT] (eta_1 index p of each lower mode), mt [NM3] (lower mode of each
+// coefficient, -1 for the top vertex), tcol [NMT] (first C3 column of each
+// lower mode).
 struct TetTables {
   const void* tab = nullptr;
   const int* itab = nullptr;
@@ -126,37 +138,63 @@ static TetTables tet_tables(int P, int sh) {
     gll_points(Q, e2.data(), w2.data());
     radau_points(Q3, 2, e3.data(), w3.data());
   }
-  const int NC = sh == kPrism ? N : NM3;
+  const int NC = sh == kPrism ? N : P * (P + 1) / 2 + 1;
   const int NB = sh == kPyr ? N : NMT;
   std::vector<double> B2(Q2 * NB), dB2(Q2 * NB), C3(Q3 * NC), dC3(Q3 * NC);
   if (sh == kPyr)   // base mode (p, q) = p N + q: phi_q(eta_2), one column per q
     modified_basis(P, Q, e2.data(), B2.data(), dB2.data());
   else
     tri_btable(P, Q2, e2.data(), B2.data(), dB2.data());
+  // per-mode third-direction factors [Q3][NM3] (prisms: phi_r(xi_3), [Q3][N])
+  std::vector<double> F3(Q3 * (sh == kPrism ? N : NM3)), dF3(F3.size());
   if (sh == kTet)
-    tet_ctable(P, Q2, e3.data(), C3.data(), dC3.data());
-  else if (sh == kPrism)   // phi_r(xi_3)
-    modified_basis(P, Q, e3.data(), C3.data(), dC3.data());
+    tet_ctable(P, Q2, e3.data(), F3.data(), dF3.data());
+  else if (sh == kPrism)
+    modified_basis(P, Q, e3.data(), F3.data(), dF3.data());
   else
-    pyr_ctable(P, Q3, e3.data(), C3.data(), dC3.data());
-  std::vector<T> h;
-  for (const auto* v : {&B2, &dB2, &C3, &dC3})
-    for (double x : *v) h.push_back((T)x);
-  std::vector<int> it_(2 * NMT + 1 + NM3);
+    pyr_ctable(P, Q3, e3.data(), F3.data(), dF3.data());
+  // integer maps, and the columns (s, r) -> sum_{s' < s} (P - s' + 1) + r of
+  // the compressed third-direction table (the top vertex last)
+  std::vector<int> it_(3 * NMT + 1 + NM3);
+  auto coff = [P](int s_) { return (s_ - 1) * (P + 1) - (s_ - 1) * s_ / 2; };
   int t = 0, m = 0;
   for (int p = 0; p <= P; ++p) {
     const int nq = sh == kPyr ? N : (p == 0 ? P + 1 : (p == P ? P : P - p));
     for (int q = 0; q < nq; ++q, ++t) {
       it_[t] = m;                 // toff3
       it_[NMT + 1 + t] = p;       // tp
-      const int nr = sh == kTet     ? P - tri_mode_degree(P, p, q) + 1
-                     : sh == kPrism ? N
-                                    : P - std::max(mod_degree(P, p), mod_degree(P, q)) + 1;
-      for (int r = 0; r < nr; ++r, ++m) it_[2 * NMT + 1 + m] = t;   // mt
+      const int deg = sh == kTet     ? tri_mode_degree(P, p, q)
+                      : sh == kPrism ? 1
+                                     : std::max(mod_degree(P, p), mod_degree(P, q));
+      const int nr = sh == kPrism ? N : P - deg + 1;
+      const int c0 = sh == kPrism ? 0 : coff(deg);
+      if (deg < 1 || deg > P || (sh != kPrism && c0 + nr > NC - 1)) return {};
+      it_[2 * NMT + 1 + NM3 + t] = c0;   // tcol
+      for (int r = 0; r < nr; ++r, ++m) {
+        it_[2 * NMT + 1 + m] = t;   // mt
+        if (sh != kPrism) {
+          for (int kk = 0; kk < Q3; ++kk) {
+            C3[kk * NC + c0 + r] = F3[kk * NM3 + m];
+            dC3[kk * NC + c0 + r] = dF3[kk * NM3 + m];
+          }
+        }
+      }
     }
   }
   it_[NMT] = m;                   // end of the last group
-  if (sh != kPrism) it_[2 * NMT + 1 + m] = -1;   // m = NM3 - 1: the top vertex
+  if (sh != kPrism) {
+    it_[2 * NMT + 1 + m] = -1;    // m = NM3 - 1: the top vertex
+    for (int kk = 0; kk < Q3; ++kk) {
+      C3[kk * NC + NC - 1] = F3[kk * NM3 + m];
+      dC3[kk * NC + NC - 1] = dF3[kk * NM3 + m];
+    }
+  } else {
+    C3 = F3;
+    dC3 = dF3;
+  }
+  std::vector<T> h;
+  for (const auto* v : {&B2, &dB2, &C3, &dC3})
+    for (double x : *v) h.push_back((T)x);
   TetTables out;
   T* d = nullptr;
   int* di = nullptr;
@@ -185,12 +223,12 @@ __global__ void __launch_bounds__(256)
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
   constexpr bool APEX = S::APEX, TRI = SH != kPyr;   // TRI: triangle lower part
   constexpr int NMT = S::NMT, NM3 = S::NM3, TS = S::TS, CS = S::CS, NC = S::NC, NB = S::NB;
-  constexpr int EPB = S::template epb<T>();
+  constexpr int EPB = S::template epb<T>(OP), SLOT = S::slot(OP);
   constexpr bool ASM = OP == OP_HELM_ASM;                // gathered input, scattered output
   constexpr bool HELM = OP == OP_HELM || ASM;
   __shared__ T stab[S::NTAB];
   __shared__ int sit[S::NITAB];
-  __shared__ T smem[EPB * S::SLOT];
+  __shared__ T smem[EPB * SLOT];
   __shared__ double sred[ASM ? 256 : 1];                 // per-thread energy parts
   for (int k = threadIdx.x; k < Q2 * NB; k += blockDim.x) {
     const int r = k / NB, m = k - r * NB;
@@ -211,17 +249,18 @@ __global__ void __launch_bounds__(256)
   const int* toff3 = sit;
   const int* tp = sit + NMT + 1;
   const int* mt = tp + NMT;
+  const int* tcol = mt + NM3;                       // first C3 column of each lower mode
   const int slot0 = threadIdx.x / NS;
   const bool act = slot0 < EPB;                     // threads past EPB slots only synchronise
   const int slot = act ? slot0 : 0;
   const int t = threadIdx.x - slot0 * NS;           // row lane: t = j + Q2 k
   const int j = act ? t % Q2 : 0, k = act ? t / Q2 : 0;
-  T* U = smem + slot * S::SLOT;                     // [NM3] coefficients
-  T* W = U + NM3;                                   // [Q3][NMT] w, later z
-  T* W3 = W + Q3 * NMT;                             // [Q3][NMT] dw/deta_3, later z'
-  T* SS = W3 + Q3 * NMT;                            // [NS][N]; point staging [NS][RS]
-  constexpr int SSO = NM3 + 2 * Q3 * NMT;           // offset of SS in a slot
-  constexpr int RS = Q | 1;                         // staged row stride (odd)
+  T* U = smem + slot * SLOT + S::u_off(OP);         // [NM3] coefficients
+  T* W = smem + slot * SLOT + S::w_off(OP);         // [Q3][NMT] w, later z
+  T* W3 = smem + slot * SLOT + S::w3_off(OP);       // [Q3][NMT] dw/deta_3, later z'
+  constexpr int SSO = S::ss_off(OP);                // offset of SS in a slot
+  T* SS = smem + slot * SLOT + SSO;                 // [NS][N]; point staging [NS][RS]
+  constexpr int RS = S::RS;                         // staged row stride (odd)
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
     // a converged system skips its operator (one system per collapsed space)
@@ -248,8 +287,8 @@ __global__ void __launch_bounds__(256)
         for (int idx = t; idx < Q3 * NMT; idx += NS) {
           const int kk = idx / NMT, tt = idx - kk * NMT;
           const int o = toff3[tt], c = toff3[tt + 1] - o;
-          const T* cr = C3 + kk * CS + (SH == kPrism ? 0 : o);
-          const T* dcr = dC3 + kk * CS + (SH == kPrism ? 0 : o);
+          const T* cr = C3 + kk * CS + tcol[tt];
+          const T* dcr = dC3 + kk * CS + tcol[tt];
           T w = T(0), w3 = T(0);
           for (int r = 0; r < c; ++r) {
             w += cr[r] * U[o + r];
@@ -257,8 +296,8 @@ __global__ void __launch_bounds__(256)
           }
           if constexpr (APEX) {
             if (S::lower_vertex(tt)) {   // the top vertex rides on the lower vertex modes
-              w += C3[kk * CS + NM3 - 1] * U[NM3 - 1];
-              if constexpr (HELM) w3 += dC3[kk * CS + NM3 - 1] * U[NM3 - 1];
+              w += C3[kk * CS + NC - 1] * U[NM3 - 1];
+              if constexpr (HELM) w3 += dC3[kk * CS + NC - 1] * U[NM3 - 1];
             }
           }
           W[kk * NMT + tt] = w;
@@ -314,7 +353,7 @@ __global__ void __launch_bounds__(256)
         const int ne = a.nelem - e0 < EPB ? (int)(a.nelem - e0) : EPB;
         for (int idx = threadIdx.x; idx < ne * NPT; idx += blockDim.x) {
           const int sl = idx / NPT, q = idx - sl * NPT, row = q / Q;
-          a.out[e0 * NPT + idx] = smem[sl * S::SLOT + SSO + row * RS + (q - row * Q)];
+          a.out[e0 * NPT + idx] = smem[sl * SLOT + SSO + row * RS + (q - row * Q)];
         }
         __syncthreads();
         continue;
@@ -397,7 +436,7 @@ __global__ void __launch_bounds__(256)
         const int tt = mt[m];
         T y = T(0);
         if (!APEX || tt >= 0) {
-          const int cm = S::ccol(m);
+          const int cm = tcol[tt] + (m - toff3[tt]);
 #pragma unroll
           for (int kk = 0; kk < Q3; ++kk) {
             y += C3[kk * CS + cm] * W[kk * NMT + tt];
@@ -408,11 +447,11 @@ __global__ void __launch_bounds__(256)
           for (int kk = 0; kk < Q3; ++kk) {
             const T* zr = W + kk * NMT;
             T zs = zr[0] + zr[P] + (TRI ? zr[NMT - P] : zr[P * N] + zr[P * N + P]);
-            y += C3[kk * CS + m] * zs;
+            y += C3[kk * CS + NC - 1] * zs;
             if constexpr (HELM) {
               const T* z3r = W3 + kk * NMT;
               zs = z3r[0] + z3r[P] + (TRI ? z3r[NMT - P] : z3r[P * N] + z3r[P * N + P]);
-              y += dC3[kk * CS + m] * zs;
+              y += dC3[kk * CS + NC - 1] * zs;
             }
           }
         }
@@ -458,7 +497,11 @@ static int64_t tet_grid(int op) {
   auto it = cached.find(key);
   if (it != cached.end()) return it->second;
   using S = TetShape<P, SH>;
-  constexpr int threads = (S::template epb<T>() * S::NS + 63) / 64 * 64;
+  const int epb = op == OP_BWD     ? S::template epb<T>(OP_BWD)
+                  : op == OP_IPROD ? S::template epb<T>(OP_IPROD)
+                  : op == OP_HELM  ? S::template epb<T>(OP_HELM)
+                                   : S::template epb<T>(OP_HELM_ASM);
+  const int threads = (epb * S::NS + 63) / 64 * 64;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const void* fn = op == OP_BWD     ? (const void*)k_tet<T, P, SH, OP_BWD>
                    : op == OP_IPROD ? (const void*)k_tet<T, P, SH, OP_IPROD>
@@ -470,41 +513,34 @@ static int64_t tet_grid(int op) {
   return grid;
 }
 
-template <typename T, int P, int SH>
-static hipError_t run_tet(const OpArgs& a) {
+template <typename T, int P, int SH, int OP>
+static hipError_t run_tet_op(const OpArgs& a, const TetTables& tt) {
   using S = TetShape<P, SH>;
-  const TetTables tt = tet_tables<T>(P, SH);
-  if (!tt.tab) return hipErrorOutOfMemory;
-  constexpr int EPB = S::template epb<T>();
+  constexpr int EPB = S::template epb<T>(OP);
   constexpr int threads = (EPB * S::NS + 63) / 64 * 64;
   static_assert(threads <= 256, "block size");
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
-  const int64_t gmax = tet_grid<T, P, SH>(a.op);
+  const int64_t gmax = tet_grid<T, P, SH>(OP);
   const int64_t nb = ngrp < gmax ? ngrp : gmax;
-  const Tab<T, P + 1, P + 2>& tb = host_tab<T, P + 1, P + 2>();
-  const DevArgs<T> d = dev_args<T>(a);
-  const T* tab = static_cast<const T*>(tt.tab);
-  const dim3 g((unsigned)nb), b(threads);
+  hipLaunchKernelGGL((k_tet<T, P, SH, OP>), dim3((unsigned)nb), dim3(threads), 0, a.stream,
+                     host_tab<T, P + 1, P + 2>(), static_cast<const T*>(tt.tab), tt.itab,
+                     dev_args<T>(a));
+  return hipGetLastError();
+}
+
+template <typename T, int P, int SH>
+static hipError_t run_tet(const OpArgs& a) {
+  const TetTables tt = tet_tables<T>(P, SH);
+  if (!tt.tab) return hipErrorOutOfMemory;
   switch (a.op) {
-    case OP_BWD:
-      hipLaunchKernelGGL((k_tet<T, P, SH, OP_BWD>), g, b, 0, a.stream, tb, tab, tt.itab, d);
-      break;
-    case OP_IPROD:
-      hipLaunchKernelGGL((k_tet<T, P, SH, OP_IPROD>), g, b, 0, a.stream, tb, tab, tt.itab, d);
-      break;
-    case OP_HELM:
-      hipLaunchKernelGGL((k_tet<T, P, SH, OP_HELM>), g, b, 0, a.stream, tb, tab, tt.itab, d);
-      break;
+    case OP_BWD: return run_tet_op<T, P, SH, OP_BWD>(a, tt);
+    case OP_IPROD: return run_tet_op<T, P, SH, OP_IPROD>(a, tt);
+    case OP_HELM: return run_tet_op<T, P, SH, OP_HELM>(a, tt);
     case OP_HELM_ASM:
-      if constexpr (SH == kTet) {
-        hipLaunchKernelGGL((k_tet<T, P, SH, OP_HELM_ASM>), g, b, 0, a.stream, tb, tab, tt.itab, d);
-        break;
-      } else {
-        return hipErrorInvalidValue;
-      }
+      if constexpr (SH == kTet) return run_tet_op<T, P, SH, OP_HELM_ASM>(a, tt);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <int P, int SH>
@@ -548,7 +584,7 @@ __global__ void __launch_bounds__(256)
                double* __restrict__ diag) {
   using S = TetShape<P, kTet>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
-  constexpr int NMT = S::NMT, NM3 = S::NM3;
+  constexpr int NMT = S::NMT, NM3 = S::NM3, NC = S::NC;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nelem * NM3) return;
   const int64_t e = id / NM3;
@@ -558,14 +594,16 @@ __global__ void __launch_bounds__(256)
   const double* B2 = tab;
   const double* dB2 = tab + Q2 * NMT;
   const double* C3 = tab + 2 * Q2 * NMT;
-  const double* dC3 = C3 + Q3 * NM3;
+  const double* dC3 = C3 + Q3 * NC;
   const int tt = itab[2 * NMT + 1 + m];       // triangle mode, -1 for the top vertex
   const int p = tt >= 0 ? itab[NMT + 1 + tt] : 0;
+  // column of the compressed eta_3 table
+  const int cm = tt >= 0 ? itab[2 * NMT + 1 + NM3 + tt] + (m - itab[tt]) : NC - 1;
   const double* f = fac + e * (int64_t)(7 * NPT);
   const double lm = lam ? lam[e] : lam0;
   double s = 0.0;
   for (int k = 0; k < Q3; ++k) {
-    const double c = C3[k * NM3 + m], dc = dC3[k * NM3 + m];
+    const double c = C3[k * NC + cm], dc = dC3[k * NC + cm];
     for (int j = 0; j < Q2; ++j) {
       double b = 1.0, db = 0.0;
       if (tt >= 0) {
