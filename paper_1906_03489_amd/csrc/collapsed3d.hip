@@ -215,6 +215,20 @@ static TetTables tet_tables(int P, int sh) {
   return out;
 }
 
+// Local Helmholtz with the factors of the next point in flight while the
+// current point is computed.  The second factor set costs 14-30 VGPRs (FP64)
+// and sometimes a wave per SIMD; measured per shape and order on MI355X, it
+// loses for FP64 tetrahedra at P <= 4, prisms at P >= 8 and pyramids at
+// P >= 6, for FP32 tetrahedra at P = 6 and pyramids at P >= 8, and for the
+// assembled tetrahedron operator (one wave per SIMD fewer at P = 6).
+template <typename T>
+constexpr bool tet_helm_prefetch(int P, int SH, int OP) {
+  if (OP != OP_HELM) return false;
+  if (sizeof(T) == 8)
+    return !((SH == kTet && P <= 4) || (SH == kPrism && P >= 8) || (SH == kPyr && P >= 6));
+  return !((SH == kTet && P == 6) || (SH == kPyr && P >= 8));
+}
+
 template <typename T, int P, int SH, int OP>
 __global__ void __launch_bounds__(256)
     k_tet(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const int* __restrict__ itab,
@@ -226,6 +240,7 @@ __global__ void __launch_bounds__(256)
   constexpr int EPB = S::template epb<T>(OP), SLOT = S::slot(OP);
   constexpr bool ASM = OP == OP_HELM_ASM;                // gathered input, scattered output
   constexpr bool HELM = OP == OP_HELM || ASM;
+  constexpr bool HPF = HELM && tet_helm_prefetch<T>(P, SH, OP);
   __shared__ T stab[S::NTAB];
   __shared__ int sit[S::NITAB];
   __shared__ T smem[EPB * SLOT];
@@ -262,6 +277,29 @@ __global__ void __launch_bounds__(256)
   T* SS = smem + slot * SLOT + SSO;                 // [NS][N]; point staging [NS][RS]
   constexpr int RS = S::RS;                         // staged row stride (odd)
   const int64_t ngrp = (a.nelem + EPB - 1) / EPB;
+  // the element's coefficients, NL per thread (m = t + l NS), all requested
+  // before any is used
+  constexpr int NL = (NM3 + NS - 1) / NS;
+  auto load_u = [&](int64_t eg, T (&r)[NL]) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int m = t + l * NS;
+      r[l] = T(0);
+      if (act && eg < a.nelem && m < NM3) {
+        if constexpr (ASM) {
+          const int32_t gv = a.l2g[eg * NM3 + m];
+          if (gv >= 0) r[l] = l2g_sign(gv, a.in[l2g_dof(gv)]);
+        } else {
+          r[l] = a.in[eg * NM3 + m];
+        }
+      }
+    }
+  };
+  // BwdTrans requests the next group's coefficients while it computes the
+  // current group (its loads are otherwise the one long wait per group)
+  constexpr bool PREFETCH = OP == OP_BWD;
+  T un[NL];
+  if constexpr (PREFETCH) load_u(blockIdx.x * (int64_t)EPB + slot, un);
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
     // a converged system skips its operator (one system per collapsed space)
     if (ASM && a.elem_seg != nullptr && a.seg_done[a.elem_seg[g * EPB]] != 0) continue;
@@ -271,15 +309,18 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int p = 0; p < N; ++p) SA[p] = SB[p] = SC[p] = T(0);
     if constexpr (OP != OP_IPROD) {
+      T uc[NL];
+      if constexpr (PREFETCH) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) uc[l] = un[l];
+        load_u((g + gridDim.x) * EPB + slot, un);
+      } else {
+        load_u(e, uc);
+      }
       if (live) {
-        for (int m = t; m < NM3; m += NS) {
-          if constexpr (ASM) {
-            const int32_t gv = a.l2g[e * NM3 + m];
-            U[m] = gv >= 0 ? l2g_sign(gv, a.in[l2g_dof(gv)]) : T(0);
-          } else {
-            U[m] = a.in[e * NM3 + m];
-          }
-        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+          if (t + l * NS < NM3) U[t + l * NS] = uc[l];
       }
       __syncthreads();
       // eta_3 stage: w_t(k') (and dw/deta_3) for every (k', t) pair
@@ -360,8 +401,8 @@ __global__ void __launch_bounds__(256)
       } else {
         const T lam = (T)(a.lam ? a.lam[live ? e : 0] : a.lam0);
         const T* f = a.fac + (live ? e : 0) * (int64_t)(7 * NPT) + t;
-#pragma unroll 1
-        for (int i = 0; i < Q; ++i) {
+        // one point i: eta_1 stage, the 7 factors, transposed eta_1 stage
+        auto point = [&](int i, const T (&fv)[7]) {
           T u = T(0), u1 = T(0), u2 = T(0), u3 = T(0);
 #pragma unroll
           for (int p = 0; p < N; ++p) {
@@ -369,11 +410,6 @@ __global__ void __launch_bounds__(256)
             u1 += tb.D[i * N + p] * V[p];
             u2 += tb.B[i * N + p] * dV[p];
             u3 += tb.B[i * N + p] * V3[p];
-          }
-          T fv[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-          if (live) {
-#pragma unroll
-            for (int c = 0; c < 7; ++c) fv[c] = f[(c * Q + i) * NS];
           }
           const T mq = lam * fv[0] * u;
           const T g1 = fv[1] * u1 + fv[2] * u2 + fv[3] * u3;
@@ -385,16 +421,49 @@ __global__ void __launch_bounds__(256)
             SB[p] += tb.B[i * N + p] * g2;
             SC[p] += tb.B[i * N + p] * g3;
           }
+        };
+        // f points into element 0 for threads without a live element, so
+        // every load is in bounds (their results are never used)
+        auto load = [&](int i, T (&fv)[7]) {
+#pragma unroll
+          for (int c = 0; c < 7; ++c) fv[c] = f[(c * Q + i) * NS];
+        };
+        if constexpr (HPF) {
+          // two register sets alternate: the factors of point i+1 are in
+          // flight while point i is computed
+          T fA[7], fB[7];
+          load(0, fA);
+#pragma unroll 1
+          for (int i = 0; i < Q; i += 2) {
+            load(i + 1 < Q ? i + 1 : Q - 1, fB);
+            point(i, fA);
+            load(i + 2 < Q ? i + 2 : Q - 1, fA);
+            if (i + 1 < Q) point(i + 1, fB);
+          }
+        } else {
+#pragma unroll 1
+          for (int i = 0; i < Q; ++i) {
+            T fv[7];
+            load(i, fv);
+            point(i, fv);
+          }
         }
       }
-    } else {   // IProductWRTBase: point values times w detJ (read row by row:
-               // staging them through LDS measured slower, the barriers
-               // serialising the loads behind the arithmetic)
+    } else {   // IProductWRTBase: point values times w detJ, read by rows
+               // straight into registers (staging them through LDS measured
+               // slower: its barriers serialise the loads behind the arithmetic)
       const T* x = a.in + (live ? e : 0) * (int64_t)NPT + Q * t;
       const T* f = a.fac + (live ? e : 0) * (int64_t)(7 * NPT) + t;
-#pragma unroll 1
+      // the row's Q values and weights are all requested before the first use
+      T xv[Q], wv[Q];
+#pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const T mq = live ? f[i * NS] * x[i] : T(0);
+        xv[i] = live ? x[i] : T(0);
+        wv[i] = live ? f[i * NS] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const T mq = wv[i] * xv[i];
 #pragma unroll
         for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
       }
