@@ -281,18 +281,24 @@ __global__ void __launch_bounds__(256)
   // before any is used
   constexpr int NL = (NM3 + NS - 1) / NS;
   auto load_u = [&](int64_t eg, T (&r)[NL]) {
+    int32_t gv[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const int m = t + l * NS;
       r[l] = T(0);
+      gv[l] = -1;
       if (act && eg < a.nelem && m < NM3) {
         if constexpr (ASM) {
-          const int32_t gv = a.l2g[eg * NM3 + m];
-          if (gv >= 0) r[l] = l2g_sign(gv, a.in[l2g_dof(gv)]);
+          gv[l] = a.l2g[eg * NM3 + m];
+          r[l] = a.in[l2g_dof(gv[l])];
         } else {
           r[l] = a.in[eg * NM3 + m];
         }
       }
+    }
+    if constexpr (ASM) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) r[l] = l2g_value(gv[l], r[l]);
     }
   };
   // BwdTrans requests the next group's coefficients while it computes the

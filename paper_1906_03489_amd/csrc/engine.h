@@ -293,10 +293,12 @@ __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int 
 
 // Helmholtz of one element per slot.  The I stage, the pointwise geometric
 // factors with the lambda mass term and the transposed I stage run as one
-// loop over the point index i; the factors of point i+1 are loaded while
-// point i is processed.  Local store or (ASM) atomic scatter-add into the
-// global vector with the element's p_e . (H_e p_e).
-template <typename T, int N, int Q, int NT, bool ASM, bool LEAN = false>
+// loop over the point index i; PF register sets hold the factors of points
+// i .. i+PF-1, so the loads of the next PF-1 points are in flight while point
+// i is processed (PF = 1: none, fewest registers).  Local store or (ASM)
+// atomic scatter-add into the global vector with the element's
+// p_e . (H_e p_e).
+template <typename T, int N, int Q, int NT, bool ASM, int PF = 2>
 __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
                                            const DevArgs<T>& a) {
@@ -311,10 +313,14 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
       if constexpr (ASM) {
         const int32_t g = a.l2g[ee * N3 + r * NN + t];
         gidx[r] = g;
-        xin[r] = g >= 0 ? l2g_sign(g, a.in[l2g_dof(g)]) : T(0);
+        xin[r] = a.in[l2g_dof(g)];
       } else {
         xin[r] = a.in[ee * N3 + r * NN + t];
       }
+    }
+    if constexpr (ASM) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) xin[r] = l2g_value(gidx[r], xin[r]);
     }
   }
   stage_k<T, N, Q, true>(tb, sm, t, live, xin);
@@ -356,10 +362,7 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
 #pragma unroll
       for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
     };
-    // two register sets alternate so the factors of the next point are in
-    // flight while the current point is computed
-    if constexpr (LEAN) {
-      // fewer live registers (used where occupancy matters more than latency)
+    if constexpr (PF == 1) {
 #pragma unroll 1
       for (int i = 0; i < Q; ++i) {
         T f[kNF3];
@@ -367,16 +370,21 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
         point(i, f);
       }
     } else {
-      T fA[kNF3], fB[kNF3];
-      load(0, fA);
+      // set s holds point i+s; before point i+s is computed, the loads of
+      // point i+s+PF-1 go into the set that point i+s-1 has just released.
+      // Loads are unconditional (clamped index) so that the waits for them
+      // can be placed right before their first use.
+      T f[PF][kNF3];
+#pragma unroll
+      for (int s = 0; s + 1 < PF; ++s) load(s < Q ? s : Q - 1, f[s]);
 #pragma unroll 1
-      for (int i = 0; i < Q; i += 2) {
-        // loads are unconditional (clamped index) so that the waits for them
-        // can be placed right before their first use
-        load(i + 1 < Q ? i + 1 : Q - 1, fB);
-        point(i, fA);
-        load(i + 2 < Q ? i + 2 : Q - 1, fA);
-        if (Q % 2 == 0 || i + 1 < Q) point(i + 1, fB);
+      for (int i = 0; i < Q; i += PF) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+          const int nx = i + s + PF - 1;
+          load(nx < Q ? nx : Q - 1, f[(s + PF - 1) % PF]);
+          if (Q % PF == 0 || i + s < Q) point(i + s, f[s]);
+        }
       }
     }
   }
@@ -413,7 +421,7 @@ constexpr int slot_threads() {
   return Q * Q <= 1 ? 1 : Q * Q <= 4 ? 4 : Q * Q <= 16 ? 16 : Q * Q <= 64 ? 64 : Q * Q;
 }
 
-template <typename T, int N, int Q, int EPB, int OP, bool LEAN = false>
+template <typename T, int N, int Q, int EPB, int OP, int PF = 2>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
     k_op3(const Tab<T, N, Q> tb, const DevArgs<T> a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q, S = Q * Q * N;
@@ -495,7 +503,7 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
       for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   } else if constexpr (OP == OP_HELM || OP == OP_HELM_ASM) {
-    helm3_body<T, N, Q, NT, ASM, LEAN>(tb, sm, red, slot, t, live, e, a);
+    helm3_body<T, N, Q, NT, ASM, PF>(tb, sm, red, slot, t, live, e, a);
   } else if constexpr (OP == OP_RHS) {
     const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
     T sa[N], sb[N], sc[N];

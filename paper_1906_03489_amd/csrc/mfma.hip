@@ -210,14 +210,17 @@ __global__ void __launch_bounds__(EPB * 64)
       if (col < NN) {
         const int r0 = g, r1 = 4 + g;
         if constexpr (ASM) {
+          int32_t g0 = -1, g1 = -1;
           if (r0 < N) {
-            const int32_t gi = l2ge[r0 * NN + col];
-            x0 = gi >= 0 ? l2g_sign(gi, xe[l2g_dof(gi)]) : T(0);
+            g0 = l2ge[r0 * NN + col];
+            x0 = xe[l2g_dof(g0)];
           }
           if (r1 < N) {
-            const int32_t gi = l2ge[r1 * NN + col];
-            x1 = gi >= 0 ? l2g_sign(gi, xe[l2g_dof(gi)]) : T(0);
+            g1 = l2ge[r1 * NN + col];
+            x1 = xe[l2g_dof(g1)];
           }
+          x0 = l2g_value(g0, x0);
+          x1 = l2g_value(g1, x1);
         } else {
           if (r0 < N) x0 = xe[r0 * NN + col];
           if (r1 < N) x1 = xe[r1 * NN + col];

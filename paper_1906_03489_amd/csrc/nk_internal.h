@@ -35,6 +35,16 @@ template <typename T>
 __host__ __device__ __forceinline__ T l2g_sign(int32_t v, T x) {
   return l2g_neg(v) ? -x : x;
 }
+// Gathers read x[l2g_dof(v)] for every entry, Dirichlet ones included (their
+// -1-g also names a valid DOF), with no branch, so that the loads of all of a
+// thread's entries are in flight together; l2g_value then turns the raw value
+// into the local one (0 for a Dirichlet entry, sign flipped for a negative
+// orientation).  Applying the sign inside a per-entry branch made the
+// compiler wait for each load in turn.
+template <typename T>
+__host__ __device__ __forceinline__ T l2g_value(int32_t v, T raw) {
+  return v >= 0 ? l2g_sign(v, raw) : T(0);
+}
 
 // ------------------------------------------------------------ host tables
 void gll_points(int Q, double* x, double* w);

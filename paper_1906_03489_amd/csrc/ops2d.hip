@@ -37,10 +37,14 @@ __global__ void __launch_bounds__(EPB * Q)
         if constexpr (ASM) {
           const int32_t g = l2g_e[q * N + t];
           gidx[q] = g;
-          xin[q] = g >= 0 ? l2g_sign(g, in[l2g_dof(g)]) : T(0);
+          xin[q] = in[l2g_dof(g)];
         } else {
           xin[q] = in[q * N + t];
         }
+      }
+      if constexpr (ASM) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) xin[q] = l2g_value(gidx[q], xin[q]);
       }
 #pragma unroll
       for (int j = 0; j < Q; ++j) {

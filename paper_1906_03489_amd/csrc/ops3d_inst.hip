@@ -13,14 +13,14 @@
 
 namespace nk {
 
-template <typename T, int P, int EPB, int OP, bool LEAN = false>
+template <typename T, int P, int EPB, int OP, int PF = 2>
 static hipError_t run3(const OpArgs& a) {
   constexpr int N = P + 1, Q = P + 2;
   static_assert(EPB > 0, "tile");
   const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, LEAN>), dim3((unsigned)nblk), dim3(EPB * slot_threads<Q>()), 0,
+  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, PF>), dim3((unsigned)nblk), dim3(EPB * slot_threads<Q>()), 0,
                      a.stream, tb, dev_args<T>(a));
   return hipGetLastError();
 }
@@ -30,11 +30,16 @@ static hipError_t run3_tiled(const OpArgs& a) {
   constexpr int E0 = kTileEPB3[P][0], E1 = kTileEPB3[P][1], E2 = kTileEPB3[P][2];
   constexpr int NE = epb3_count(P);
   if constexpr (op_has_lean(OP)) {
-    if (a.tile >= NE) {
-      const int k = a.tile - NE;
-      if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, true>(a);
-      if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, true>(a);
-      return run3<T, P, E0, OP, true>(a);
+    if (a.tile >= NE) {   // candidates NE.. : one factor set, then four
+      const int k = (a.tile - NE) % NE;
+      if (a.tile >= 2 * NE) {
+        if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, kDeepPF>(a);
+        if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, kDeepPF>(a);
+        return run3<T, P, E0, OP, kDeepPF>(a);
+      }
+      if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, 1>(a);
+      if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, 1>(a);
+      return run3<T, P, E0, OP, 1>(a);
     }
   }
   if (a.tile == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP>(a);

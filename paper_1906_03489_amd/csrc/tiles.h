@@ -38,9 +38,13 @@ constexpr int kVarpEPB[11] = {0, 16, 16, 4, 4, 4, 4, 3, 2, 2, 1};
 constexpr bool op_has_tiles(int op) { return op <= 3; }
 
 // The 3-D Helmholtz operators (local and assembled) have each elements-per-
-// block candidate twice: with the factors of the next point prefetched into a
-// second register set, and "lean" (one set: fewer registers, more waves per
-// SIMD).  Which wins depends on the order and precision, so both are timed.
+// block candidate in three forms: with the factors of the next point
+// prefetched into a second register set, "lean" (one set: fewer registers,
+// more waves per SIMD) and "deep" (kDeepPF sets: the loads of kDeepPF - 1
+// points ahead in flight).  Which wins depends on the order and precision, so
+// all are timed.
+constexpr int kDeepPF = 4;
+constexpr int kHelmForms = 3;
 constexpr int epb3_count(int P) {
   int c = 0;
   for (int k = 0; k < kMaxTiles; ++k) c += kTileEPB3[P][k] > 0 ? 1 : 0;

@@ -173,16 +173,31 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
       slot_sync<64>();
       if (g + 1 < g1) load_in(g + 1);
     } else {
-      for (int k = lane; k < ne * NM; k += 64) {
-        const int ee = k / NM;
-        T v;
-        if constexpr (ASM) {
-          const int32_t gv = a.l2g[e0 * NM + k];
-          v = gv >= 0 ? l2g_sign(gv, a.in[l2g_dof(gv)]) : T(0);
-        } else {
-          v = a.in[e0 * NM + k];
+      // the group's coefficients, all requested before any is stored
+      constexpr int KM = (EPW * NM + 63) / 64;
+      T v[KM];
+      int32_t gv[KM];
+#pragma unroll
+      for (int r = 0; r < KM; ++r) {
+        const int k = lane + 64 * r;
+        v[r] = T(0);
+        gv[r] = -1;
+        if (k < ne * NM) {
+          if constexpr (ASM) {
+            gv[r] = a.l2g[e0 * NM + k];
+            v[r] = a.in[l2g_dof(gv[r])];
+          } else {
+            v[r] = a.in[e0 * NM + k];
+          }
         }
-        Cw[ee * S::CS + (k - ee * NM)] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < KM; ++r) {
+        const int k = lane + 64 * r;
+        if (k < ne * NM) {
+          const int ee = k / NM;
+          Cw[ee * S::CS + (k - ee * NM)] = ASM ? l2g_value(gv[r], v[r]) : v[r];
+        }
       }
       slot_sync<64>();
     }

@@ -71,7 +71,7 @@ __device__ __forceinline__ void varp_body(const VarpDev<T>& a, const VarpGroup& 
   d.lam = a.lam ? a.lam + lam_off : nullptr;
   d.lam0 = a.lam0;
   T* sm = smem + (slot < EPB ? slot : 0) * 3 * Q * Q * N;
-  helm3_body<T, N, Q, NT, false, (P >= 8)>(tb, sm, nullptr, slot, t, live, e, d);
+  helm3_body<T, N, Q, NT, false, (P >= 8 ? 1 : 2)>(tb, sm, nullptr, slot, t, live, e, d);
 }
 
 // MINB = minimum resident blocks per CU requested from the compiler (1 or 2):

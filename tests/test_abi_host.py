@@ -75,8 +75,8 @@ def test_invalid_arguments_rejected_before_device_work():
     assert L.nk_system_destroy(None) == nk.NK_EINVAL
     assert L.nk_set_tile_config(2, 3, 6, 0, 99) == nk.NK_EINVAL
     assert L.nk_set_tile_config(9, 3, 6, 0, 0) == nk.NK_EINVAL
-    # three vector tiles, each also in its lean form, + the matrix-core variant
-    assert L.nk_tile_count(2, 3, 6) == 7
+    # three vector tiles, each also in its lean and deep forms, + the matrix-core variant
+    assert L.nk_tile_count(2, 3, 6) == 10
     assert L.nk_tile_count(0, 3, 6) == 3      # BwdTrans: no lean form
     assert L.nk_tile_config(2, 3, 6, 0).decode().startswith("epb")
 
