@@ -1120,7 +1120,8 @@ static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, vo
   a.l2g = y->l2g + G.c0;
   a.dots = dots;
   a.dslot = dots ? y->dslot + G.e0 : nullptr;
-  a.elem_seg = seg_done ? y->elem_seg + G.e0 : nullptr;
+  // one system: its single converged flag needs no per-element index
+  a.elem_seg = seg_done && y->nsys > 1 ? y->elem_seg + G.e0 : nullptr;
   a.seg_done = seg_done;
   a.tile = tile;
   a.stream = st;

@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256)
   if constexpr (PREFETCH) load_u(blockIdx.x * (int64_t)EPB + slot, un);
   for (int64_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
     // a converged system skips its operator (one system per collapsed space)
-    if (ASM && a.elem_seg != nullptr && a.seg_done[a.elem_seg[g * EPB]] != 0) continue;
+    if (ASM && seg_converged(a.elem_seg, a.seg_done, g * EPB)) continue;
     const int64_t e = g * EPB + slot;
     const bool live = act && e < a.nelem;
     T SA[N], SB[N], SC[N];

@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
   bool live = e < a.nelem;
-  if (live && a.elem_seg != nullptr) live = a.seg_done[a.elem_seg[e]] == 0;
+  if (live && seg_converged(a.elem_seg, a.seg_done, e)) live = false;
   const int64_t ee = live ? e : 0;
   T* sm = smem + slot * SLOT;
   const T* fe = a.fac + ee * (int64_t)(kNF3 * Q3) + t;

@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(EPB * 64)
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
   bool live = e < a.nelem;
-  if (live && a.elem_seg != nullptr) live = a.seg_done[a.elem_seg[e]] == 0;
+  if (live && seg_converged(a.elem_seg, a.seg_done, e)) live = false;
   if (!live) return;  // the slot is one whole wavefront: nothing else waits for it
   T* sm = smem + slot * 3 * S;
   T* sA = sm;

@@ -46,6 +46,17 @@ __host__ __device__ __forceinline__ T l2g_value(int32_t v, T raw) {
   return v >= 0 ? l2g_sign(v, raw) : T(0);
 }
 
+// Whether element e belongs to a converged system (its operator work is
+// skipped).  Batched systems look the flag up through the element's system
+// index; a single system passes no index and its one flag is a uniform
+// (scalar) load, so no per-element chain of two dependent loads precedes
+// the element's gather.
+__device__ __forceinline__ bool seg_converged(const int32_t* elem_seg, const int32_t* seg_done,
+                                              int64_t e) {
+  if (seg_done == nullptr) return false;
+  return (elem_seg != nullptr ? seg_done[elem_seg[e]] : seg_done[0]) != 0;
+}
+
 // ------------------------------------------------------------ host tables
 void gll_points(int Q, double* x, double* w);
 void modified_basis(int P, int Q, const double* x, double* B, double* DB);

@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(EPB * Q)
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
   bool live = e < a.nelem;
-  if (live && a.elem_seg != nullptr) live = a.seg_done[a.elem_seg[e]] == 0;
+  if (live && seg_converged(a.elem_seg, a.seg_done, e)) live = false;
   T* sm = smem + slot * NTEN * S;
   const int64_t ee = live ? e : 0;
   const T* fe = a.fac + ee * (int64_t)(kNF2 * Q2);

@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64)
     const int64_t e = e0 + (el < ne ? el : 0);
     const bool live = row && el < ne;
     // a converged system skips its operator (one system per triangle space)
-    if (ASM && a.elem_seg != nullptr && a.seg_done[a.elem_seg[e0]] != 0) continue;
+    if (ASM && seg_converged(a.elem_seg, a.seg_done, e0)) continue;
     if constexpr (PREFETCH) {
 #pragma unroll
       for (int r = 0; r < KIN; ++r) {
