@@ -1322,3 +1322,118 @@ def test_sorted_tetrahedral_helmholtz_solve_is_exact():
     b = oracle.assemble_vector(ops.iprod(f), l2g, ng)
     sol = oracle.direct_solve(mats, l2g, ng, dm, b)
     assert np.abs(ops.bwd(oracle.gather(sol, l2g)) - u).max() < 1e-12
+
+
+# ------------- prismatic meshes: C0 assembly of the signed triangle numbering in layers
+
+def _prism_ref_coords(T, z0, h, X):
+    """Collapsed reference coordinates (eta_1, eta_2, xi_3) of physical points
+    X (k, 3) in the straight prism over the triangle T (3, 2) and the layer
+    [z0, z0 + h]."""
+    M = np.stack([T[1] - T[0], T[2] - T[0]], axis=1)
+    xi = 2 * np.linalg.solve(M, (X[:, :2] - T[0]).T).T - 1
+    e2 = xi[:, 1]
+    e1 = 2 * (1 + xi[:, 0]) / (1 - xi[:, 1]) - 1
+    return e1, e2, 2 * (X[:, 2] - z0) / h - 1
+
+
+@pytest.mark.parametrize("P", [2, 3, 5])
+def test_prismatic_numbering_is_continuous_across_faces(P):
+    """A random global vector gathered with the signed prismatic numbering
+    (rotated triangle vertex orders) gives element expansions that agree at
+    random points of every shared vertical (quadrilateral) and horizontal
+    (triangular) face; with the signs dropped they do not (from P = 3, where
+    odd edge bubbles exist; at P = 2 every sign is +1)."""
+    n = 2
+    nt = 2 * n * n
+    rot = W.tri_rotations(60 + P, nt)
+    l2g, sign, ng, _ = W.prism_lattice_l2g(n, P, rot)
+    T = W.prism_lattice_vertices(n, rot)
+    h = 1.0 / n
+    x = np.random.default_rng(P).uniform(-1, 1, ng)
+    rng = np.random.default_rng(20 + P)
+    # shared vertical faces: triangle edges shared by two columns, in each layer
+    edge_cols = {}
+    for c in range(nt):
+        for a, b in ((0, 1), (1, 2), (0, 2)):
+            key = tuple(sorted((tuple(np.rint(T[c, a] * n).astype(int)), tuple(np.rint(T[c, b] * n).astype(int)))))
+            edge_cols.setdefault(key, []).append(c)
+    if P == 2:
+        assert np.all(sign == 1)
+    for signed, expect_ok in ((True, True), (False, P == 2)):
+        xl = oracle.gather(x, l2g, sign if signed else None)
+        worst = 0.0
+        for key, cols in edge_cols.items():
+            if len(cols) != 2:
+                continue
+            a, b = (np.array(v, float) / n for v in key)
+            for layer in range(n):
+                t = rng.uniform(0.05, 0.95, 4)
+                X = np.concatenate([a + t[:, None] * (b - a), (layer + rng.uniform(0.05, 0.95, 4))[:, None] * h], axis=1)
+                vals = [C.prism_basis(P, *_prism_ref_coords(T[c], layer * h, h, X))[0] @ xl[layer * nt + c]
+                        for c in cols]
+                worst = max(worst, np.abs(vals[0] - vals[1]).max())
+        for c in range(nt):
+            for layer in range(n - 1):
+                w = rng.dirichlet(np.ones(3), 4)
+                X = np.concatenate([w @ T[c], np.full((4, 1), (layer + 1) * h)], axis=1)
+                lo = C.prism_basis(P, *_prism_ref_coords(T[c], layer * h, h, X))[0] @ xl[layer * nt + c]
+                hi = C.prism_basis(P, *_prism_ref_coords(T[c], (layer + 1) * h, h, X))[0] @ xl[(layer + 1) * nt + c]
+                worst = max(worst, np.abs(lo - hi).max())
+        assert (worst < 1e-11) == expect_ok, (signed, worst)
+
+
+def _prism_points_xyz(ops, T, n):
+    """Physical points of every prism of the straight prismatic mesh."""
+    h = 1.0 / n
+    nt = T.shape[0]
+    xi1 = (1 + ops.e1) * (1 - ops.e2) / 2 - 1
+    E = ops.nelem
+    col, layer = np.arange(E) % nt, np.arange(E) // nt
+    Tc = T[col]
+    XY = (Tc[:, 0, :, None] * (-(xi1 + ops.e2) / 2) + Tc[:, 1, :, None] * ((1 + xi1) / 2)
+          + Tc[:, 2, :, None] * ((1 + ops.e2) / 2))
+    Z = layer[:, None] * h + h * (1 + ops.e3[None, :]) / 2
+    return XY[:, 0], XY[:, 1], Z
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_prismatic_projection_is_exact(P):
+    """Global L2 projection with the assembled mass matrix of the signed
+    prismatic mesh reproduces a function of the prism space (total degree P
+    in x, y times degree P in z)."""
+    n, Q = 2, P + 2
+    rot = W.tri_rotations(70 + P, 2 * n * n)
+    x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    g = oracle.gll(Q)[0]
+    ops = C.PrismOps(P, Q, W.prism_lattice_jacobians(n, g, x1, g, 0.0, rot=rot))
+    l2g, sign, ng, _ = W.prism_lattice_l2g(n, P, rot)
+    x, y, z = _prism_points_xyz(ops, W.prism_lattice_vertices(n, rot), n)
+    u = x ** (P - 1) * y - 2 * x * y * z ** (P - 2) + z ** P * (1 + x) + 1
+    mats = [ops.mass_matrix(e) for e in range(ops.nelem)]
+    b = oracle.assemble_vector(ops.iprod(u), l2g, ng, sign)
+    sol = oracle.direct_solve(mats, l2g, ng, np.zeros(ng, np.uint8), b, sign)
+    assert np.abs(ops.bwd(oracle.gather(sol, l2g, sign)) - u).max() < 1e-11 * np.abs(u).max()
+
+
+def test_prismatic_helmholtz_solve_is_exact():
+    """-lap u + u = f on the unit cube, u = x(1-x)y(1-y)z(1-z) (total degree
+    4 in x, y, degree 2 in z, zero on the boundary), P = 4, weak right-hand
+    side, Dirichlet boundary, rotated triangle vertex orders: the assembled
+    prismatic solve reproduces u at every point."""
+    n, P = 2, 4
+    Q = P + 2
+    rot = W.tri_rotations(80, 2 * n * n)
+    x1, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    g = oracle.gll(Q)[0]
+    ops = C.PrismOps(P, Q, W.prism_lattice_jacobians(n, g, x1, g, 0.0, rot=rot))
+    l2g, sign, ng, dm = W.prism_lattice_l2g(n, P, rot)
+    x, y, z = _prism_points_xyz(ops, W.prism_lattice_vertices(n, rot), n)
+    s = lambda t: t * (1 - t)
+    u = s(x) * s(y) * s(z)
+    f = 2 * (s(y) * s(z) + s(x) * s(z) + s(x) * s(y)) + u
+    mats = [ops.helmholtz_matrix(e) for e in range(ops.nelem)]
+    b = oracle.assemble_vector(ops.iprod(f), l2g, ng, sign)
+    b[dm.astype(bool)] = 0.0
+    sol = oracle.direct_solve(mats, l2g, ng, dm, b, sign)
+    assert np.abs(ops.bwd(oracle.gather(sol, l2g, sign)) - u).max() < 1e-12

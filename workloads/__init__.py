@@ -577,11 +577,24 @@ def tet_lattice_l2g(n: int, P: int):
     return l2g.astype(np.int32), nglobal, dm
 
 
-def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, elems=None):
+def prism_lattice_vertices(n: int, rot=None) -> np.ndarray:
+    """(x, y) of the local triangle vertices (A, B, C) of the prismatic mesh's
+    2 n^2 columns: the triangles of tri_lattice_vertices, each rotated by
+    rot (one cyclic rotation per column, shared by its n layers), if given.
+    Returns (2 n^2, 3, 2)."""
+    V = tri_lattice_vertices(n)
+    if rot is not None:
+        r = np.asarray(rot)
+        V = np.take_along_axis(V, (r[:, None] + np.arange(3)[None, :]) % 3, axis=1)
+    return np.stack([V % (n + 1), V // (n + 1)], axis=-1) / n
+
+
+def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, elems=None, rot=None):
     """Jacobians of the prismatic mesh of the unit cube: the triangle mesh of
     the unit square (tri_lattice_vertices) extruded into n layers, prism
     e = layer * 2 n^2 + triangle, curved by the cyclic warp.  With the
-    triangle's vertices (A, B, C) and the layer [z0, z0 + h], the affine
+    triangle's vertices (A, B, C) (rotated by rot per column, if given) and
+    the layer [z0, z0 + h], the affine
     reference map is (x, y) = A (-(xi_1 + xi_2)/2) + B (1 + xi_1)/2
     + C (1 + xi_2)/2, z = z0 + h (1 + xi_3)/2, taken at the points of the 1-D
     sets (e1 = eta_1, e2 = eta_2 = xi_2, x3 = xi_3), q = i + len(e1) (j +
@@ -594,8 +607,7 @@ def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, ele
     xi1 = (1 + E1) * (1 - E2) / 2 - 1
     xi2 = E2
     h = 1.0 / n
-    V = tri_lattice_vertices(n)
-    xy = np.stack([V % (n + 1), V // (n + 1)], axis=-1) * h          # (2 n^2, 3, 2)
+    xy = prism_lattice_vertices(n, rot)                                # (2 n^2, 3, 2)
     nt = xy.shape[0]
     e = np.arange(n * nt) if elems is None else np.asarray(elems)
     tri, layer = e % nt, e // nt
@@ -612,6 +624,32 @@ def prism_lattice_jacobians(n: int, e1, e2, x3, amp: float = WARP_AMPLITUDE, ele
     X = np.concatenate([XY, Z[:, None, :]], axis=1)
     Wm = warp_jacobian(X, amp)
     return np.einsum("ecbq,eba->ecaq", Wm, A)
+
+
+def prism_lattice_l2g(n: int, P: int, rot=None):
+    """C0 numbering of the prismatic mesh (prism_lattice_jacobians, the same
+    rot), for the prism modes (triangle mode t in its mode order, r fastest):
+    the signed triangle numbering of tri_lattice_l2g(n, P, rot) times the
+    1-D numbering of each column, layer * P + r (r = 0 bottom vertex, P top
+    vertex, bubbles between), so global = g_t + ng_t (layer P + r) with the
+    triangle mode's sign.  Vertical faces are a triangle edge times the
+    column, so their orientation is the edge's; horizontal faces are whole
+    triangles of one column and match exactly.  Dirichlet: the triangle
+    numbering's boundary DOFs in every layer, and the bottom and top planes.
+    Returns (l2g (E, nm) int32, sign (E, nm) int8, nglobal, dirichlet uint8)."""
+    l2, s2, ng2, dm2 = tri_lattice_l2g(n, P, rot)
+    nt = l2.shape[0]
+    nz = n * P + 1
+    layer = np.repeat(np.arange(n), nt)
+    tri = np.tile(np.arange(nt), n)
+    r = np.arange(P + 1)
+    g = l2[tri][:, :, None].astype(np.int64) + ng2 * (layer[:, None, None] * P + r[None, None, :])
+    l2g = g.reshape(n * nt, -1)
+    sign = np.repeat(s2[tri], P + 1, axis=1)
+    zbd = np.zeros(nz, bool)
+    zbd[[0, nz - 1]] = True
+    dm = (dm2[None, :].astype(bool) | zbd[:, None]).astype(np.uint8).ravel()
+    return l2g.astype(np.int32), sign, ng2 * nz, dm
 
 
 def pyr_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems=None):
