@@ -552,10 +552,11 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// The assembled operator exists for tetrahedra only (sorted-vertex meshes).
+// The assembled operator exists for tetrahedra (sorted-vertex meshes) and
+// prisms (signed triangle numbering extruded in layers).
 template <typename T, int P, int SH>
 static const void* asm_kernel() {
-  if constexpr (SH == kTet)
+  if constexpr (SH == kTet || SH == kPrism)
     return (const void*)k_tet<T, P, SH, OP_HELM_ASM>;
   else
     return nullptr;
@@ -612,7 +613,7 @@ static hipError_t run_tet(const OpArgs& a) {
     case OP_IPROD: return run_tet_op<T, P, SH, OP_IPROD>(a, tt);
     case OP_HELM: return run_tet_op<T, P, SH, OP_HELM>(a, tt);
     case OP_HELM_ASM:
-      if constexpr (SH == kTet) return run_tet_op<T, P, SH, OP_HELM_ASM>(a, tt);
+      if constexpr (SH == kTet || SH == kPrism) return run_tet_op<T, P, SH, OP_HELM_ASM>(a, tt);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -645,19 +646,19 @@ hipError_t launch_tet(nk_dtype t, const OpArgs& a) { return launch_col<kTet>(t, 
 hipError_t launch_prism(nk_dtype t, const OpArgs& a) { return launch_col<kPrism>(t, a); }
 hipError_t launch_pyr(nk_dtype t, const OpArgs& a) { return launch_col<kPyr>(t, a); }
 
-// Diagonal of the tetrahedron Helmholtz operator, thread per (tetrahedron,
-// mode), scatter-added into the padded global diagonal (Dirichlet modes
+// Diagonal of the tetrahedron or prism Helmholtz operator, thread per
+// (element, mode), scatter-added into the padded global diagonal (Dirichlet modes
 // skipped): diag H_e[m] = sum_points (lambda f0 phi_m^2 + d^T G' d) with d the
 // three collapsed derivatives of phi_m and G' the 6 stored factors.  A mode
 // is T_t(eta_1, eta_2) c(eta_3) (the collapsed triangle vertex C as
 // (a_0 + a_P) times its eta_2 factor), the top vertex c(eta_3) alone.
-template <int P>
+template <int P, int SH>
 __global__ void __launch_bounds__(256)
-    k_diag_tet(const Tab<double, P + 1, P + 2> tb, const double* __restrict__ tab,
+    k_diag_col(const Tab<double, P + 1, P + 2> tb, const double* __restrict__ tab,
                const int* __restrict__ itab, int64_t nelem, const double* __restrict__ fac,
                const double* __restrict__ lam, double lam0, const int32_t* __restrict__ l2g,
                double* __restrict__ diag) {
-  using S = TetShape<P, kTet>;
+  using S = TetShape<P, SH>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
   constexpr int NMT = S::NMT, NM3 = S::NM3, NC = S::NC;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -707,34 +708,45 @@ __global__ void __launch_bounds__(256)
   unsafeAtomicAdd(diag + l2g_dof(g), s);
 }
 
-template <int P>
-static hipError_t run_diag_tet(int64_t nelem, const double* fac, const double* lam, double lam0,
+template <int P, int SH>
+static hipError_t run_diag_col(int64_t nelem, const double* fac, const double* lam, double lam0,
                                const int32_t* l2g, double* diag, hipStream_t st) {
-  const TetTables tt = tet_tables<double>(P, kTet);
+  const TetTables tt = tet_tables<double>(P, SH);
   if (!tt.tab) return hipErrorOutOfMemory;
-  const int64_t tot = nelem * TetShape<P, kTet>::NM3;
-  hipLaunchKernelGGL(k_diag_tet<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+  const int64_t tot = nelem * TetShape<P, SH>::NM3;
+  hipLaunchKernelGGL((k_diag_col<P, SH>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                      host_tab<double, P + 1, P + 2>(), static_cast<const double*>(tt.tab), tt.itab,
                      nelem, fac, lam, lam0, l2g, diag);
   return hipGetLastError();
 }
 
-hipError_t launch_diag_tet(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+template <int SH>
+static hipError_t diag_col(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
                            const int32_t* l2g, double* diag, hipStream_t st) {
   if (nelem == 0) return hipSuccess;
   switch (P) {
-    case 1: return run_diag_tet<1>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 2: return run_diag_tet<2>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 3: return run_diag_tet<3>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 4: return run_diag_tet<4>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 5: return run_diag_tet<5>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 6: return run_diag_tet<6>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 7: return run_diag_tet<7>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 8: return run_diag_tet<8>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 9: return run_diag_tet<9>(nelem, fac, lam, lam0, l2g, diag, st);
-    case 10: return run_diag_tet<10>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 1: return run_diag_col<1, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 2: return run_diag_col<2, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 3: return run_diag_col<3, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 4: return run_diag_col<4, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 5: return run_diag_col<5, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 6: return run_diag_col<6, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 7: return run_diag_col<7, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 8: return run_diag_col<8, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 9: return run_diag_col<9, SH>(nelem, fac, lam, lam0, l2g, diag, st);
+    case 10: return run_diag_col<10, SH>(nelem, fac, lam, lam0, l2g, diag, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_diag_tet(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                           const int32_t* l2g, double* diag, hipStream_t st) {
+  return diag_col<kTet>(P, nelem, fac, lam, lam0, l2g, diag, st);
+}
+
+hipError_t launch_diag_prism(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                             const int32_t* l2g, double* diag, hipStream_t st) {
+  return diag_col<kPrism>(P, nelem, fac, lam, lam0, l2g, diag, st);
 }
 
 // Factors of the collapsed tetrahedron or prism at every point (thread per

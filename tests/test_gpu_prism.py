@@ -8,7 +8,7 @@ import pytest
 import oracle
 import workloads as W
 from oracle import collapsed as C
-from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, to_dev, torch_cuda
+from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, rel_err, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_prism_operators_match_oracle(P):
 
 def test_prism_helmholtz_constant_symmetry_and_errors():
     """L 1 = 0 and x^T H y = y^T H x on the GPU at P = 4; an empty space;
-    systems and derivative calls are rejected; a mirrored element too."""
+    derivative calls are rejected; a mirrored element too."""
     torch = torch_cuda()
     m = nk()
     P, Q = 4, 6
@@ -77,10 +77,6 @@ def test_prism_helmholtz_constant_symmetry_and_errors():
     assert m.bwd_trans(m.Space.create_prism(P, Q, to_dev(np.zeros((0, 3, 3, nq)))), e).numel() == 0
     with pytest.raises(m.NkError) as ei:
         m.phys_deriv(space, torch.zeros(E * nq, dtype=torch.float64, device="cuda"))
-    assert ei.value.status == m.NK_EUNSUPPORTED
-    l2g = np.arange(E * len(modes), dtype=np.int32)
-    with pytest.raises(m.NkError) as ei:
-        m.System.create(space, l2g.size, to_dev(l2g), to_dev(np.zeros(l2g.size, np.uint8)))
     assert ei.value.status == m.NK_EUNSUPPORTED
     bad = Jg.copy()
     bad[0, :, 2] *= -1.0
@@ -113,3 +109,93 @@ def test_full_size_prisms_p4_sampled():
                m.helmholtz(space, to_dev(c, td), lam0=1.0, dtype=dt).double().cpu().numpy().reshape(E, nm)]
         for name, g, r in zip(("bwd", "iprod", "helm"), got, ref):
             assert_close(g[sample], r, tol, f"full-size prism {name} dt={dt}")
+
+
+# ------------------------- assembled prismatic systems with orientation signs
+
+def _prism_system_case(P, n=2, amp=W.WARP_AMPLITUDE):
+    """Curved prismatic mesh with rotated triangle vertex orders (signed
+    edges), per-point kappa and per-element lambda; the oracle's elemental
+    matrices and the GPU system built from the same signed numbering."""
+    m = nk()
+    Q = P + 2
+    rot = W.tri_rotations(290 + P, 2 * n * n)
+    e1g, _, e2g, _ = m.tri_points(Q)
+    Jg = W.prism_lattice_jacobians(n, e1g, e2g, e1g, amp, rot=rot)
+    x, _ = oracle.gll(Q)
+    xr, _ = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)
+    Jo = W.prism_lattice_jacobians(n, x, xr, x, amp, rot=rot)
+    l2g, sign, ng, dm = W.prism_lattice_l2g(n, P, rot)
+    E, nq = Jg.shape[0], Q * Q * (Q - 1)
+    rng = np.random.default_rng(300 + P)
+    kap = rng.uniform(0.5, 2.0, (E, nq))
+    lam = rng.uniform(0.5, 2.0, E)
+    ops = C.PrismOps(P, Q, Jo, kappa=kap, lam=lam)
+    mats = [ops.helmholtz_matrix(e) for e in range(E)]
+    space = m.Space.create_prism(P, Q, to_dev(Jg), kappa=to_dev(kap))
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm), lam=to_dev(lam), sign=to_dev(sign))
+    return dict(ops=ops, mats=mats, l2g=l2g, sign=sign, ng=ng, dm=dm, space=space, sys=sysm, E=E)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 5, 7])
+def test_prismatic_system_operator_diag_gather_assemble(P):
+    """The signed assembled prismatic operator (signed gather, elemental
+    Helmholtz, signed scatter-add, Dirichlet rows masked), its Jacobi
+    diagonal, gather and assembly against the oracle's signed assembly."""
+    from oracle.assembly import MaskedOperator, jacobi_diagonal
+    torch = torch_cuda()
+    m = nk()
+    c = _prism_system_case(P, n=2 if P <= 5 else 1)
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"], c["sign"])
+    x = np.random.default_rng(P).uniform(-1, 1, c["ng"])
+    ref = A(x)
+    sysm = c["sys"]
+    assert_close(sysm.apply(to_dev(x)).cpu().numpy(), ref, FP64_RTOL, f"prism apply P={P}")
+    y32 = sysm.apply(to_dev(x, torch.float32), dtype=m.F32).double().cpu().numpy()
+    assert_close(y32, ref, FP32_RTOL, f"prism apply32 P={P}")
+    dref = jacobi_diagonal(c["mats"], c["l2g"], c["ng"], c["dm"], c["sign"])
+    assert_close(sysm.diagonal().cpu().numpy(), dref, FP64_RTOL, f"prism diag P={P}")
+    xl = sysm.gather(to_dev(x)).cpu().numpy()
+    np.testing.assert_array_equal(xl, oracle.gather(x, c["l2g"], c["sign"]).ravel())
+    yl = np.random.default_rng(P + 1).uniform(-1, 1, xl.size)
+    bref = oracle.assemble_vector(yl.reshape(c["E"], -1), c["l2g"], c["ng"], c["sign"])
+    bref[c["dm"].astype(bool)] = 0.0
+    assert_close(sysm.assemble(to_dev(yl)).cpu().numpy(), bref, 1e-14, f"prism assemble P={P}")
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_prismatic_cg_solves_match_direct_solve(P):
+    """FP64 PCG to 1e-12 and the FP32-refined solve to 1e-10 on the signed
+    curved prismatic mesh, against the oracle's sparse direct solve."""
+    from oracle.assembly import MaskedOperator, direct_solve
+    m = nk()
+    torch_cuda()
+    c = _prism_system_case(P, n=3)
+    b = np.random.default_rng(305 + P).uniform(-1, 1, c["ng"])
+    b[c["dm"].astype(bool)] = 0.0
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"], c["sign"])
+    xref = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b, c["sign"])
+    x, info = c["sys"].solve(to_dev(b), rtol=1e-12, maxit=20000)
+    xs = x.cpu().numpy()
+    assert info[0]["status"] == 0
+    assert np.linalg.norm(b - A(xs)) / np.linalg.norm(b) <= 1e-11
+    assert rel_err(xs, xref) < 1e-8
+    xr, info = c["sys"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_F32_REFINED)
+    assert info[0]["status"] == 0
+    assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
+
+
+def test_pyramid_systems_are_rejected():
+    """Assembled systems are not built for pyramids: creation reports
+    NK_EUNSUPPORTED before any device work."""
+    m = nk()
+    torch = torch_cuda()
+    P, Q = 2, 4
+    xg = m.basis_tables(P, Q)[0]
+    J = W.pyr_lattice_jacobians(1, xg, xg, m.tet_points(Q)[4], W.WARP_AMPLITUDE)
+    space = m.Space.create_pyr(P, Q, to_dev(J))
+    nm = (P + 1) * (P + 2) * (2 * P + 3) // 6
+    l2g = np.arange(J.shape[0] * nm, dtype=np.int32).reshape(J.shape[0], nm)
+    with pytest.raises(m.NkError) as ei:
+        m.System.create(space, int(l2g.size), to_dev(l2g), to_dev(np.zeros(l2g.size, np.uint8)))
+    assert ei.value.status == m.NK_EUNSUPPORTED
