@@ -1437,3 +1437,115 @@ def test_prismatic_helmholtz_solve_is_exact():
     b[dm.astype(bool)] = 0.0
     sol = oracle.direct_solve(mats, l2g, ng, dm, b, sign)
     assert np.abs(ops.bwd(oracle.gather(sol, l2g, sign)) - u).max() < 1e-12
+
+
+# -------------------- pyramidal meshes: C0 assembly without signs
+
+def _pyr_ref_coords(Vx, X):
+    """Collapsed reference coordinates of physical points X (k, 3) in the
+    straight pyramid with vertices Vx = (a, b, d, e)."""
+    M = np.stack([Vx[1] - Vx[0], Vx[2] - Vx[0], Vx[3] - Vx[0]], axis=1)
+    xi = 2 * np.linalg.solve(M, (X - Vx[0]).T).T - 1
+    e3 = xi[:, 2]
+    return 2 * (1 + xi[:, 0]) / (1 - e3) - 1, 2 * (1 + xi[:, 1]) / (1 - e3) - 1, e3
+
+
+def _pyr_shared_faces(V, n):
+    """Shared faces of the pyramidal mesh: {key: (elements, corner points)}
+    for the triangular faces inside each cube and the square bases between
+    cubes."""
+    faces = {}
+    for e in range(V.shape[0]):
+        a, b, d, ap = V[e]
+        c = b + d - a
+        cand = [(a, b, ap), (a, d, ap), (b, c, ap), (d, c, ap), (a, b, c, d)]
+        for f in cand:
+            key = tuple(sorted(tuple(np.rint(np.asarray(v) * 2 * n).astype(int)) for v in f))
+            faces.setdefault(key, ([], np.array(f)))[0].append(e)
+    return {k: v for k, v in faces.items() if len(v[0]) == 2}
+
+
+@pytest.mark.parametrize("P", [2, 3, 5])
+def test_pyramidal_numbering_is_continuous_across_faces(P):
+    """A random global vector gathered with the pyramidal numbering gives
+    element expansions that agree at random points of every shared
+    triangular face and every shared square base; without the transposition
+    of the base modes where an element's b and d are swapped, the bases do
+    not."""
+    n = 2
+    V = W.pyr_lattice_vertices(n)
+    l2g, ng, _ = W.pyr_lattice_l2g(n, P)
+    modes = C.pyr_modes(P)
+    swapped = [int(np.flatnonzero(V[e, 1] != V[e, 0])[0]) > int(np.flatnonzero(V[e, 2] != V[e, 0])[0])
+               for e in range(V.shape[0])]
+    assert any(swapped) and not all(swapped)
+    # the numbering without that transposition: base-face mode (p, q) of a
+    # swapped element takes the global index of its own (q, p)
+    broken = l2g.copy()
+    pos = {(p, q): m for m, (p, q, s, r) in enumerate(modes) if r == 0 and 0 < p < P and 0 < q < P}
+    for e in np.flatnonzero(swapped):
+        for (p, q), m in pos.items():
+            broken[e, m] = l2g[e, pos[(q, p)]]
+    x = np.random.default_rng(P).uniform(-1, 1, ng)
+    rng = np.random.default_rng(30 + P)
+    faces = _pyr_shared_faces(V, n)
+    assert any(len(f[1]) == 4 for f in faces.values()) and any(len(f[1]) == 3 for f in faces.values())
+    for numbering, expect_ok in ((l2g, True), (broken, P == 2)):
+        xl = oracle.gather(x, numbering)
+        worst = 0.0
+        for els, corners in faces.values():
+            if len(corners) == 3:
+                X = rng.dirichlet(np.ones(3), 4) @ corners
+            else:
+                s, t = rng.uniform(0.05, 0.95, (2, 4))
+                X = corners[0] + s[:, None] * (corners[1] - corners[0]) + t[:, None] * (corners[3] - corners[0])
+            vals = [C.pyr_basis(P, *_pyr_ref_coords(V[e], X))[0] @ xl[e] for e in els]
+            worst = max(worst, np.abs(vals[0] - vals[1]).max())
+        assert (worst < 1e-11) == expect_ok, (expect_ok, worst)
+
+
+def _pyr_points_xyz(ops, V):
+    r1, r2, r3 = C.xi_of_eta_pyr(ops.e1, ops.e2, ops.e3)
+    X = (V[:, 0, :, None] + (V[:, 1] - V[:, 0])[:, :, None] * (1 + r1) / 2
+         + (V[:, 2] - V[:, 0])[:, :, None] * (1 + r2) / 2 + (V[:, 3] - V[:, 0])[:, :, None] * (1 + r3) / 2)
+    return X[:, 0], X[:, 1], X[:, 2]
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_pyramidal_projection_is_exact(P):
+    """Global L2 projection with the assembled mass matrix of the pyramidal
+    mesh reproduces a polynomial of total degree P, to the rounding the
+    matrix's condition number allows (1.4e5 at P = 2, 2.9e7 at P = 4; an
+    error in the numbering shows as O(1))."""
+    n, Q = 2, P + 2
+    x, _ = oracle.gll(Q)
+    x3, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    ops = C.PyrOps(P, Q, W.pyr_lattice_jacobians(n, x, x, x3, 0.0))
+    l2g, ng, _ = W.pyr_lattice_l2g(n, P)
+    X, Y, Z = _pyr_points_xyz(ops, W.pyr_lattice_vertices(n))
+    u = X ** (P - 1) * Y - 2 * X * Y * Z ** (P - 2) + Z ** P + 1
+    mats = [ops.mass_matrix(e) for e in range(ops.nelem)]
+    b = oracle.assemble_vector(ops.iprod(u), l2g, ng)
+    sol = oracle.direct_solve(mats, l2g, ng, np.zeros(ng, np.uint8), b)
+    assert np.abs(ops.bwd(oracle.gather(sol, l2g)) - u).max() < 1e-9 * np.abs(u).max()
+
+
+def test_pyramidal_helmholtz_solve_is_exact():
+    """-lap u + u = f on the unit cube, u = x(1-x)y(1-y)z(1-z) (total degree
+    6, zero on the boundary), P = 6, weak right-hand side, Dirichlet boundary:
+    the assembled pyramidal solve reproduces u at every point."""
+    n, P = 1, 6
+    Q = P + 2
+    x, _ = oracle.gll(Q)
+    x3, _ = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)
+    ops = C.PyrOps(P, Q, W.pyr_lattice_jacobians(n, x, x, x3, 0.0))
+    l2g, ng, dm = W.pyr_lattice_l2g(n, P)
+    X, Y, Z = _pyr_points_xyz(ops, W.pyr_lattice_vertices(n))
+    s = lambda t: t * (1 - t)
+    u = s(X) * s(Y) * s(Z)
+    f = 2 * (s(Y) * s(Z) + s(X) * s(Z) + s(X) * s(Y)) + u
+    mats = [ops.helmholtz_matrix(e) for e in range(ops.nelem)]
+    b = oracle.assemble_vector(ops.iprod(f), l2g, ng)
+    b[dm.astype(bool)] = 0.0
+    sol = oracle.direct_solve(mats, l2g, ng, dm, b)
+    assert np.abs(ops.bwd(oracle.gather(sol, l2g)) - u).max() < 1e-12

@@ -670,6 +670,24 @@ def pyr_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems
     x1 = (1 + E1) * (1 - E3) / 2 - 1
     x2 = (1 + E2) * (1 - E3) / 2 - 1
     x3 = E3
+    V = pyr_lattice_vertices(n)
+    if elems is not None:
+        V = V[np.asarray(elems)]
+    A = np.stack([(V[:, 1] - V[:, 0]) / 2, (V[:, 2] - V[:, 0]) / 2, (V[:, 3] - V[:, 0]) / 2], axis=2)
+    if amp == 0.0:
+        return np.broadcast_to(A[:, :, :, None], A.shape + (x1.size,)).copy()
+    X = (V[:, 0, :, None] + A[:, :, 0, None] * (1 + x1) + A[:, :, 1, None] * (1 + x2)
+         + A[:, :, 2, None] * (1 + x3))
+    Wm = warp_jacobian(X, amp)
+    return np.einsum("ecbq,eba->ecaq", Wm, A)
+
+
+def pyr_lattice_vertices(n: int) -> np.ndarray:
+    """Vertices (a, b, d, e) of the pyramidal mesh's elements (6 per cube,
+    element 6 cube + face, faces -x, +x, -y, +y, -z, +z): a the face's lowest
+    corner, b and d its neighbours along the face's two axes (swapped where
+    needed so the map is positively oriented), e the cube's centre; the base's
+    fourth corner is c = b + d - a.  Returns (E, 4, 3)."""
     h = 1.0 / n
     c = np.arange(n ** 3)
     corner = np.stack([c % n, (c // n) % n, c // (n * n)], axis=1) * h
@@ -687,16 +705,108 @@ def pyr_lattice_jacobians(n: int, e1, e2, e3, amp: float = WARP_AMPLITUDE, elems
                 b, d = d, b
             faces.append((a, b, d, eap))
     V = np.stack([np.stack([corner + f[k] for k in range(4)], axis=1) for f in faces], axis=1)
-    V = V.reshape(-1, 4, 3)                                            # (E, [a, b, d, e], 3)
-    if elems is not None:
-        V = V[np.asarray(elems)]
-    A = np.stack([(V[:, 1] - V[:, 0]) / 2, (V[:, 2] - V[:, 0]) / 2, (V[:, 3] - V[:, 0]) / 2], axis=2)
-    if amp == 0.0:
-        return np.broadcast_to(A[:, :, :, None], A.shape + (x1.size,)).copy()
-    X = (V[:, 0, :, None] + A[:, :, 0, None] * (1 + x1) + A[:, :, 1, None] * (1 + x2)
-         + A[:, :, 2, None] * (1 + x3))
-    Wm = warp_jacobian(X, amp)
-    return np.einsum("ecbq,eba->ecaq", Wm, A)
+    return V.reshape(-1, 4, 3)
+
+
+def pyr_lattice_l2g(n: int, P: int):
+    """C0 numbering of the pyramidal mesh (pyr_lattice_vertices) for the
+    pyramid modes (base mode (p, q), p slow, r fastest, the apex last).  Every
+    base edge runs along + x, + y or + z from the base's lowest corner a, and
+    every rising edge from a cube corner to the cube's centre, in each element
+    that holds it, so no signs are needed: a shared triangular face (centre
+    and a cube edge) has the same edge direction and collapsed apex in both
+    pyramids, and a shared base (a cube face between two cubes) is the same
+    tensor face, seen with its two axes swapped where b and d were swapped.
+    Global DOFs: lattice corners, cube centres; P-1 bubbles per edge (cube
+    edges, corner-centre edges); (P-1)^2 per cube face, indexed (i, j) along
+    its lower and higher axis; (P-1)(P-2)/2 per triangular face, (k, r) with
+    k the edge bubble; then each element's interior modes ((p, q) bubbles,
+    r >= 1).  Dirichlet: corners, cube edges and cube faces on the boundary
+    of the unit cube.  Returns (l2g (E, nm) int32, nglobal, dirichlet
+    uint8)."""
+    V = pyr_lattice_vertices(n)
+    E = V.shape[0]
+    K = np.rint(V * 2 * n).astype(np.int64)                            # corners even, centres odd
+    nc = (n + 1) ** 3
+
+    def vid(k):
+        if k[0] % 2 == 0:
+            i, j, l = k // 2
+            return int(i + (n + 1) * (j + (n + 1) * l))
+        i, j, l = (k - 1) // 2
+        return int(nc + i + n * (j + n * l))
+    deg = lambda p: 1 if p in (0, P) else p + 1
+    modes = [(p, q, r) for p in range(P + 1) for q in range(P + 1)
+             for r in range(P - max(deg(p), deg(q)) + 1)] + [None]
+    nb = max(P - 1, 0)
+    nq = nb * nb
+    tmodes = [(k, r) for k in range(1, P) for r in range(1, P - k)]
+    tidx = {kr: i for i, kr in enumerate(tmodes)}
+    nt = len(tmodes)
+    ninner = sum(1 for mm in modes if mm and 0 < mm[0] < P and 0 < mm[1] < P and mm[2] >= 1)
+    edges, qfaces, tfaces = {}, {}, {}
+    ent = []
+    for e in range(E):
+        a, b, d, ap = (vid(K[e, k]) for k in range(4))
+        c = vid(K[e, 1] + K[e, 2] - K[e, 0])
+        ax_b = int(np.flatnonzero(K[e, 1] != K[e, 0])[0])
+        ax_d = int(np.flatnonzero(K[e, 2] != K[e, 0])[0])
+        for pr in ((a, b), (a, d), (b, c), (d, c), (a, ap), (b, ap), (d, ap), (c, ap)):
+            edges.setdefault(pr, len(edges))
+        qk = tuple(sorted((a, b, c, d)))
+        qfaces.setdefault(qk, len(qfaces))
+        for pr in ((a, b), (a, d), (b, c), (d, c)):
+            tfaces.setdefault(pr + (ap,), len(tfaces))
+        ent.append((a, b, c, d, ap, ax_b < ax_d, qk))
+    ne, nqf, ntf = len(edges), len(qfaces), len(tfaces)
+    nv = nc + n ** 3
+    e0 = nv
+    q0 = e0 + ne * nb
+    t0 = q0 + nqf * nq
+    i0 = t0 + ntf * nt
+    nglobal = i0 + E * ninner
+    l2g = np.empty((E, len(modes)), np.int64)
+    for e in range(E):
+        a, b, c, d, ap, straight, qk = ent[e]
+        vert = {(0, 0): a, (P, 0): b, (0, P): d, (P, P): c}
+        it = 0
+        for m, mm in enumerate(modes):
+            if mm is None:
+                g = ap
+            else:
+                p, q, r = mm
+                pv, qv = p in (0, P), q in (0, P)
+                if pv and qv:                                   # corner, or rising edge
+                    g = vert[(p, q)] if r == 0 else e0 + edges[(vert[(p, q)], ap)] * nb + r - 1
+                elif r == 0 and qv:                             # edge a-b (q = 0) or d-c
+                    g = e0 + edges[(vert[(0, q)], vert[(P, q)])] * nb + p - 1
+                elif r == 0 and pv:                             # edge a-d (p = 0) or b-c
+                    g = e0 + edges[(vert[(p, 0)], vert[(p, P)])] * nb + q - 1
+                elif r == 0:                                    # base face, axes (u, v)
+                    i, j = (p, q) if straight else (q, p)
+                    g = q0 + qfaces[qk] * nq + (i - 1) + nb * (j - 1)
+                elif qv:                                        # triangle on edge a-b / d-c
+                    g = t0 + tfaces[(vert[(0, q)], vert[(P, q)], ap)] * nt + tidx[(p, r)]
+                elif pv:                                        # triangle on edge a-d / b-c
+                    g = t0 + tfaces[(vert[(p, 0)], vert[(p, P)], ap)] * nt + tidx[(q, r)]
+                else:
+                    g = i0 + e * ninner + it
+                    it += 1
+            l2g[e, m] = g
+    coord = lambda v: np.array([v % (n + 1), (v // (n + 1)) % (n + 1), v // (n + 1) ** 2])
+    on_bd = lambda v: v < nc and bool(np.any((coord(v) == 0) | (coord(v) == n)))
+    dm = np.zeros(nglobal, np.uint8)
+    for v in range(nc):
+        dm[v] = on_bd(v)
+    same_plane = lambda vs: vs[0] < nc and all(v < nc for v in vs) and bool(np.any(
+        np.all([(coord(v) == coord(vs[0])) & ((coord(v) == 0) | (coord(v) == n)) for v in vs], axis=0)))
+    for (u, w), k in edges.items():
+        if same_plane((u, w)):
+            dm[e0 + k * nb: e0 + (k + 1) * nb] = 1
+    for qk, k in qfaces.items():
+        if same_plane(qk):
+            dm[q0 + k * nq: q0 + (k + 1) * nq] = 1
+    return l2g.astype(np.int32), nglobal, dm
 
 
 # ----------------------------------------------------------- draws
