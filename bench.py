@@ -502,6 +502,47 @@ def section_prism_solve(nk, W, torch, n=16, orders=(4, 6)):
     return out
 
 
+def section_pyr_solve(nk, W, torch, n=10, orders=(4, 6)):
+    """Assembled C0 solve on 6 n^3 curved pyramids of the unit cube (each cube
+    split into six pyramids around its centre), Dirichlet boundary,
+    lambda = 1: -lap u + u = 1, FP64 vs FP32-refined to 1e-10."""
+    out = {}
+    E = 6 * n ** 3
+    for P in orders:
+        Q = P + 2
+        xg = nk.basis_tables(P, Q)[0]
+        J = torch.from_numpy(W.pyr_lattice_jacobians(n, xg, xg, nk.tet_points(Q)[4])).cuda()
+        space = nk.Space.create_pyr(P, Q, J)
+        del J
+        l2g, ng, dm = W.pyr_lattice_l2g(n, P)
+        sysm = nk.System.create(space, ng, torch.from_numpy(l2g).cuda(), torch.from_numpy(dm).cuda(), lam0=1.0)
+        ones = torch.ones(E * Q * Q * (Q - 1), dtype=torch.float64, device="cuda")
+        b = sysm.assemble(nk.iprod_wrt_base(space, ones))
+        sysm.solve(b, rtol=1e-2, maxit=64, raise_on_fail=False)
+        sysm.solve(b, rtol=1e-2, maxit=64, mode=nk.SOLVE_F32_REFINED, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x64, i64 = sysm.solve(b, rtol=1e-10, maxit=50000)
+        t64 = (time.perf_counter() - t) * 1e3
+        t = time.perf_counter()
+        x32, i32 = sysm.solve(b, rtol=1e-10, maxit=50000, mode=nk.SOLVE_F32_REFINED)
+        t32 = (time.perf_counter() - t) * 1e3
+        diff = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+        out[f"P{P}"] = {
+            "nglobal": int(ng), "nelem": E,
+            "f64": {"ms": round(t64, 2), "iters": i64[0]["iters"], "rel_resid": i64[0]["rel_resid"],
+                    "ms_per_iter": round(t64 / max(i64[0]["iters"], 1), 4)},
+            "f32_refined": {"ms": round(t32, 2), "inner_iters": i32[0]["iters"],
+                            "outer_iters": i32[0]["outer_iters"], "rel_resid": i32[0]["rel_resid"],
+                            "rel_diff_vs_f64": diff},
+            "speedup_refined_vs_f64": round(t64 / t32, 3),
+        }
+        log(f"pyramid solve P={P}: {ng} DOF, f64 {t64:.1f} ms ({i64[0]['iters']} it), refined {t32:.1f} ms")
+        del space, sysm, b, x64, x32, ones
+        torch.cuda.empty_cache()
+    return out
+
+
 def section_varp(nk, W, torch, reps=20):
     """20 000 hexes (20x20x50 curved lattice) with per-element order drawn from
     {2..10}: one persistent mixed-order launch vs one launch per order group."""
@@ -876,6 +917,8 @@ def main():
         sections["tet_solve_10368"] = section_tet_solve(nk, W, torch)
         log("section prism solve ...")
         sections["prism_solve_8192"] = section_prism_solve(nk, W, torch)
+        log("section pyramid solve ...")
+        sections["pyramid_solve_6000"] = section_pyr_solve(nk, W, torch)
     del space, x, y
     torch.cuda.empty_cache()
     if "cg" in secs:

@@ -206,9 +206,7 @@ nk_status nk_space_create_prism(nk_space* out, int64_t nelem, int P, int Q, cons
  * ((1-eta_3)/2)^s for r = 0 and ((1-eta_3)/2)^s (1+eta_3)/2
  * P^{2s-1,1}_{r-1}(eta_3) for 1 <= r <= P - s (r fastest); the apex
  * (1+eta_3)/2 last.  jac: device [E][3][3][Q^2 (Q-1)] FP64, kappa: device
- * [E][Q^2 (Q-1)] or NULL; nk_bwd_trans, nk_iprod_wrt_base and
- * nk_helmholtz are supported, other calls (assembled systems included)
- * return NK_EUNSUPPORTED; errors as for prisms. */
+ * [E][Q^2 (Q-1)] or NULL; supported calls and errors as for prisms. */
 nk_status nk_space_create_pyr(nk_space* out, int64_t nelem, int P, int Q, const double* jac,
                               const double* kappa, void* stream);
 
@@ -272,10 +270,10 @@ nk_status nk_helmholtz_weak_rhs(nk_space s, const double* lambda, double lambda0
  * [nglobal] (1 = homogeneous Dirichlet DOF, fixed at zero), lambda device
  * [E] or NULL (lambda0).  Builds the Jacobi diagonal on the GPU.  Triangle
  * spaces take l2g [E][(P+1)(P+2)/2], tetrahedron spaces l2g
- * [E][(P+1)(P+2)(P+3)/6] and prism spaces l2g [E][(P+1)^2 (P+2)/2] in the
- * space's mode order (one system each); pyramid spaces return
- * NK_EUNSUPPORTED.  The global functions of unstructured triangle and
- * prism meshes generally need nk_system_create_signed.
+ * [E][(P+1)(P+2)(P+3)/6], prism spaces l2g [E][(P+1)^2 (P+2)/2] and
+ * pyramid spaces l2g [E][(P+1)(P+2)(2P+3)/6] in the space's mode order (one
+ * system each).  The global functions of unstructured triangle and prism
+ * meshes generally need nk_system_create_signed.
  * The padded system (each system's DOFs rounded up to 2048) must stay below
  * 2^30 DOFs (NK_EINVAL otherwise). */
 nk_status nk_system_create(nk_system* out, nk_space s, int64_t nglobal, const int32_t* l2g,

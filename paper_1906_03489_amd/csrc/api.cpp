@@ -856,9 +856,8 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
   if (s->groups.size() != 1 && nsys != 1)
     return fail(NK_EINVAL, "a mixed-order space takes one system (nsys = 1)");
-  if ((s->shape == 1 || s->shape == 2 || s->shape == 3) && nsys != 1)
-    return fail(NK_EINVAL, "a triangle, tetrahedron or prism space takes one system (nsys = 1)");
-  if (s->shape >= 4) return fail(NK_EUNSUPPORTED, "assembled systems are not built for pyramids");
+  if (s->shape != 0 && nsys != 1)
+    return fail(NK_EINVAL, "a triangle, tetrahedron, prism or pyramid space takes one system (nsys = 1)");
   if (!elem_off || !dof_off) return fail(NK_EINVAL, "offsets must be non-NULL");
   if (elem_off[0] != 0 || elem_off[nsys] != s->nelem)
     return fail(NK_EINVAL, "elem_off must start at 0 and end at the space's element count");
@@ -1021,6 +1020,7 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
       const int nl = s->shape == 1   ? G.n * (G.n + 1) / 2
                      : s->shape == 2 ? G.n * (G.n + 1) * (G.n + 2) / 6
                      : s->shape == 3 ? G.n * G.n * (G.n + 1) / 2
+                     : s->shape == 4 ? G.n * (G.n + 1) * (2 * G.n + 1) / 6
                                      : (int)ipow(G.n, s->dim);
       if ((e = build_l2g(G.nelem, nl, y->elem_seg + G.e0, y->d_dof_off, y->d_pdof_off, l2g + G.c0,
                          sign ? sign + G.c0 : nullptr, dirichlet, y->l2g + G.c0, d_bad, st)))
@@ -1035,6 +1035,9 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
       else if (s->shape == 3)
         e = launch_diag_prism(G.P, G.nelem, s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr,
                               y->lam0, y->l2g + G.c0, y->diag, st);
+      else if (s->shape == 4)
+        e = launch_diag_pyr(G.P, G.nelem, s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr, y->lam0,
+                            y->l2g + G.c0, y->diag, st);
       else
         e = launch_diag(s->dim, G.P, G.Q, G.nelem, d_B + tab_off[g], d_D + tab_off[g],
                         s->fac64 + G.f0, y->lam ? y->lam + G.e0 : nullptr, y->lam0, y->l2g + G.c0,
@@ -1132,6 +1135,7 @@ static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, vo
   if (s->shape == 1) return launch_tri(t, a);
   if (s->shape == 2) return launch_tet(t, a);
   if (s->shape == 3) return launch_prism(t, a);
+  if (s->shape == 4) return launch_pyr(t, a);
   return launch_op(s->dim, t, a);
 }
 

@@ -552,14 +552,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// The assembled operator exists for tetrahedra (sorted-vertex meshes) and
-// prisms (signed triangle numbering extruded in layers).
+// The assembled operator of every collapsed shape.
 template <typename T, int P, int SH>
 static const void* asm_kernel() {
-  if constexpr (SH == kTet || SH == kPrism)
-    return (const void*)k_tet<T, P, SH, OP_HELM_ASM>;
-  else
-    return nullptr;
+  return (const void*)k_tet<T, P, SH, OP_HELM_ASM>;
 }
 
 template <typename T, int P, int SH>
@@ -612,9 +608,7 @@ static hipError_t run_tet(const OpArgs& a) {
     case OP_BWD: return run_tet_op<T, P, SH, OP_BWD>(a, tt);
     case OP_IPROD: return run_tet_op<T, P, SH, OP_IPROD>(a, tt);
     case OP_HELM: return run_tet_op<T, P, SH, OP_HELM>(a, tt);
-    case OP_HELM_ASM:
-      if constexpr (SH == kTet || SH == kPrism) return run_tet_op<T, P, SH, OP_HELM_ASM>(a, tt);
-      return hipErrorInvalidValue;
+    case OP_HELM_ASM: return run_tet_op<T, P, SH, OP_HELM_ASM>(a, tt);
     default: return hipErrorInvalidValue;
   }
 }
@@ -646,8 +640,8 @@ hipError_t launch_tet(nk_dtype t, const OpArgs& a) { return launch_col<kTet>(t, 
 hipError_t launch_prism(nk_dtype t, const OpArgs& a) { return launch_col<kPrism>(t, a); }
 hipError_t launch_pyr(nk_dtype t, const OpArgs& a) { return launch_col<kPyr>(t, a); }
 
-// Diagonal of the tetrahedron or prism Helmholtz operator, thread per
-// (element, mode), scatter-added into the padded global diagonal (Dirichlet modes
+// Diagonal of the tetrahedron, prism or pyramid Helmholtz operator, thread
+// per (element, mode), scatter-added into the padded global diagonal (Dirichlet modes
 // skipped): diag H_e[m] = sum_points (lambda f0 phi_m^2 + d^T G' d) with d the
 // three collapsed derivatives of phi_m and G' the 6 stored factors.  A mode
 // is T_t(eta_1, eta_2) c(eta_3) (the collapsed triangle vertex C as
@@ -660,7 +654,8 @@ __global__ void __launch_bounds__(256)
                double* __restrict__ diag) {
   using S = TetShape<P, SH>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, Q3 = S::Q3, NS = S::NS, NPT = S::NPT;
-  constexpr int NMT = S::NMT, NM3 = S::NM3, NC = S::NC;
+  constexpr int NMT = S::NMT, NM3 = S::NM3, NC = S::NC, NB = S::NB;
+  constexpr bool TRI = SH != kPyr;   // triangle lower part (else the pyramid's base)
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nelem * NM3) return;
   const int64_t e = id / NM3;
@@ -668,10 +663,10 @@ __global__ void __launch_bounds__(256)
   const int32_t g = l2g[id];
   if (g < 0) return;  // Dirichlet: row replaced by the identity
   const double* B2 = tab;
-  const double* dB2 = tab + Q2 * NMT;
-  const double* C3 = tab + 2 * Q2 * NMT;
+  const double* dB2 = tab + Q2 * NB;
+  const double* C3 = tab + 2 * Q2 * NB;
   const double* dC3 = C3 + Q3 * NC;
-  const int tt = itab[2 * NMT + 1 + m];       // triangle mode, -1 for the top vertex
+  const int tt = itab[2 * NMT + 1 + m];       // lower mode, -1 for the top vertex
   const int p = tt >= 0 ? itab[NMT + 1 + tt] : 0;
   // column of the compressed eta_3 table
   const int cm = tt >= 0 ? itab[2 * NMT + 1 + NM3 + tt] + (m - itab[tt]) : NC - 1;
@@ -683,15 +678,15 @@ __global__ void __launch_bounds__(256)
     for (int j = 0; j < Q2; ++j) {
       double b = 1.0, db = 0.0;
       if (tt >= 0) {
-        b = B2[j * NMT + tt];
-        db = dB2[j * NMT + tt];
+        b = B2[j * NB + S::bcol(tt)];
+        db = dB2[j * NB + S::bcol(tt)];
       }
       for (int i = 0; i < Q; ++i) {
         double av = 1.0, dav = 0.0;
         if (tt >= 0) {
           av = tb.B[i * N + p];
           dav = tb.D[i * N + p];
-          if (tt == P) {   // collapsed triangle vertex
+          if (TRI && tt == P) {   // collapsed triangle vertex
             av += tb.B[i * N + P];
             dav += tb.D[i * N + P];
           }
@@ -747,6 +742,11 @@ hipError_t launch_diag_tet(int P, int64_t nelem, const double* fac, const double
 hipError_t launch_diag_prism(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
                              const int32_t* l2g, double* diag, hipStream_t st) {
   return diag_col<kPrism>(P, nelem, fac, lam, lam0, l2g, diag, st);
+}
+
+hipError_t launch_diag_pyr(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                           const int32_t* l2g, double* diag, hipStream_t st) {
+  return diag_col<kPyr>(P, nelem, fac, lam, lam0, l2g, diag, st);
 }
 
 // Factors of the collapsed tetrahedron or prism at every point (thread per
@@ -867,4 +867,5 @@ hipError_t launch_geom_pyr(int Q, int64_t nelem, const double* jac, const double
                      jac, kappa, pts, fac64, fac32, bad);
   return hipGetLastError();
 }
+
 }  // namespace nk

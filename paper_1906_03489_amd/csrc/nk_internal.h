@@ -209,6 +209,8 @@ hipError_t launch_diag_tet(int P, int64_t nelem, const double* fac, const double
                            const int32_t* l2g, double* diag, hipStream_t st);
 hipError_t launch_diag_prism(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
                              const int32_t* l2g, double* diag, hipStream_t st);
+hipError_t launch_diag_pyr(int P, int64_t nelem, const double* fac, const double* lam, double lam0,
+                           const int32_t* l2g, double* diag, hipStream_t st);
 hipError_t launch_geom_tet(int Q, int64_t nelem, const double* jac, const double* kappa,
                            const double* pts, double* fac64, float* fac32, int* bad, hipStream_t s);
 hipError_t launch_geom_prism(int Q, int64_t nelem, const double* jac, const double* kappa,

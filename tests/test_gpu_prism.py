@@ -183,19 +183,3 @@ def test_prismatic_cg_solves_match_direct_solve(P):
     xr, info = c["sys"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_F32_REFINED)
     assert info[0]["status"] == 0
     assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
-
-
-def test_pyramid_systems_are_rejected():
-    """Assembled systems are not built for pyramids: creation reports
-    NK_EUNSUPPORTED before any device work."""
-    m = nk()
-    torch = torch_cuda()
-    P, Q = 2, 4
-    xg = m.basis_tables(P, Q)[0]
-    J = W.pyr_lattice_jacobians(1, xg, xg, m.tet_points(Q)[4], W.WARP_AMPLITUDE)
-    space = m.Space.create_pyr(P, Q, to_dev(J))
-    nm = (P + 1) * (P + 2) * (2 * P + 3) // 6
-    l2g = np.arange(J.shape[0] * nm, dtype=np.int32).reshape(J.shape[0], nm)
-    with pytest.raises(m.NkError) as ei:
-        m.System.create(space, int(l2g.size), to_dev(l2g), to_dev(np.zeros(l2g.size, np.uint8)))
-    assert ei.value.status == m.NK_EUNSUPPORTED
