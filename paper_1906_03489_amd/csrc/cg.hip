@@ -25,6 +25,31 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 constexpr int kFinThreads = 1024;
 
+// K block sums at once (one barrier round for all of them), valid in thread 0.
+template <int NTH, int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * (NTH / 64) + w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
+      for (int i = 0; i < NTH / 64; ++i) t += sh[k * (NTH / 64) + i];
+      v[k] = t;
+    }
+  }
+}
+
 // Register the block's partials (a, b); returns true in thread 0 of the last
 // block of system `s` to arrive, which then sees every block's partials.
 __device__ __forceinline__ bool last_block(double a, double b, double* part, int32_t* cnt, int s,
@@ -79,7 +104,7 @@ __global__ void __launch_bounds__(kVecBlock)
     k_cg_update(const int32_t* __restrict__ blk_seg, CgState st, T* __restrict__ x,
                 T* __restrict__ r, T* __restrict__ u, T* __restrict__ p, T* __restrict__ s,
                 T* __restrict__ w, const T* __restrict__ dinv, double* __restrict__ part) {
-  __shared__ double sh[kVecBlock / 64];
+  __shared__ double sh[2 * (kVecBlock / 64)];
   const int sg = blk_seg[blockIdx.x];
   if (st.done[sg]) return;
   const T alpha = (T)st.alpha[sg], beta = (T)st.beta[sg];
@@ -103,9 +128,9 @@ __global__ void __launch_bounds__(kVecBlock)
     g += (double)rn * (double)un;
     rr += (double)rn * (double)rn;
   }
-  g = block_sum(g, sh);
-  rr = block_sum(rr, sh);
-  store_parts(g, rr, part);
+  double v[2] = {g, rr};
+  block_sums<kVecBlock, 2>(v, sh);
+  store_parts(v[0], v[1], part);
 }
 
 template <typename T>
@@ -123,7 +148,7 @@ __global__ void __launch_bounds__(kVecBlock)
     k_cg_start(const int32_t* __restrict__ blk_seg, const double* __restrict__ b,
                T* __restrict__ w, T* __restrict__ r, T* __restrict__ u, T* __restrict__ p,
                T* __restrict__ s, const T* __restrict__ dinv, double* __restrict__ part) {
-  __shared__ double sh[kVecBlock / 64];
+  __shared__ double sh[2 * (kVecBlock / 64)];
   (void)blk_seg;
   const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
   double g = 0.0, rr = 0.0;
@@ -141,9 +166,9 @@ __global__ void __launch_bounds__(kVecBlock)
     g += (double)ri * (double)ui;
     rr += (double)ri * (double)ri;
   }
-  g = block_sum(g, sh);
-  rr = block_sum(rr, sh);
-  store_parts(g, rr, part);
+  double v[2] = {g, rr};
+  block_sums<kVecBlock, 2>(v, sh);
+  store_parts(v[0], v[1], part);
 }
 
 template <typename T>
@@ -163,22 +188,48 @@ __global__ void __launch_bounds__(kFinThreads)
                 const double* __restrict__ part, const double* __restrict__ dots, CgState st,
                 int maxit, int fatal, int start, double tau2, const int32_t* __restrict__ outer_done,
                 const double* __restrict__ outer_tol2, const double* __restrict__ outer_rr) {
-  __shared__ double sh[kFinThreads / 64];
+  __shared__ double sh[3 * (kFinThreads / 64)];
   const int sg = blockIdx.x;
   if (!start && st.done[sg]) return;
-  double g = 0.0, rr = 0.0, dl = 0.0;
+  // Every thread requests kFinLoads values per round before adding any (the
+  // indices are clamped into the range, so every load is in bounds and
+  // needs no branch), so a system of up to kFinLoads * kFinThreads elements
+  // takes one memory round trip instead of one per value.
+  constexpr int kFinLoads = 16;
+  double dl = 0.0, g = 0.0, rr = 0.0;
   // dots are padded per system to whole kSegAlign blocks (padding is zero)
   const int64_t d0 = dblk_first[sg] * kSegAlign, d1 = dblk_first[sg + 1] * kSegAlign;
-#pragma unroll 4
-  for (int64_t i = d0 + threadIdx.x; i < d1; i += kFinThreads) dl += dots[i];
-#pragma unroll 4
-  for (int64_t b = blk_first[sg] + threadIdx.x; b < blk_first[sg + 1]; b += kFinThreads) {
-    g += part[2 * b];
-    rr += part[2 * b + 1];
+  for (int64_t i0 = d0 + threadIdx.x; i0 < d1; i0 += (int64_t)kFinLoads * kFinThreads) {
+    double v[kFinLoads];
+#pragma unroll
+    for (int k = 0; k < kFinLoads; ++k) {
+      const int64_t i = i0 + (int64_t)k * kFinThreads;
+      v[k] = dots[i < d1 ? i : d1 - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kFinLoads; ++k) dl += i0 + (int64_t)k * kFinThreads < d1 ? v[k] : 0.0;
   }
-  g = block_sum<kFinThreads>(g, sh);
-  rr = block_sum<kFinThreads>(rr, sh);
-  dl = block_sum<kFinThreads>(dl, sh);
+  const int64_t b0 = blk_first[sg], b1 = blk_first[sg + 1];
+  for (int64_t j0 = b0 + threadIdx.x; j0 < b1; j0 += (int64_t)kFinLoads * kFinThreads) {
+    double va[kFinLoads], vb[kFinLoads];
+#pragma unroll
+    for (int k = 0; k < kFinLoads; ++k) {
+      const int64_t j = j0 + (int64_t)k * kFinThreads, jc = j < b1 ? j : b1 - 1;
+      va[k] = part[2 * jc];
+      vb[k] = part[2 * jc + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kFinLoads; ++k) {
+      const bool in = j0 + (int64_t)k * kFinThreads < b1;
+      g += in ? va[k] : 0.0;
+      rr += in ? vb[k] : 0.0;
+    }
+  }
+  double v3[3] = {g, rr, dl};
+  block_sums<kFinThreads, 3>(v3, sh);
+  g = v3[0];
+  rr = v3[1];
+  dl = v3[2];
   if (threadIdx.x != 0) return;
   if (start) {
     st.iters[sg] = 0;
