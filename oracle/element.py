@@ -140,6 +140,26 @@ class ElementOps:
         elems = range(self.nelem) if elems is None else elems
         return np.stack([self.helmholtz_matrix(e) @ x[e] for e in elems])
 
+    def helmholtz_action(self, x, elems=None):
+        """y_e = H_e x_e for the listed elements (x holds one row per listed
+        element, or per element when none are listed), evaluated as the same
+        quadrature sums without forming H_e: the reference gradient D_b B x_e
+        and value B x_e at every point, weighted by w detJ (kappa G_ab, and
+        lambda for the mass term), tested against D_a B and B.  Equal to
+        `helmholtz` up to rounding; it costs O(Q^d n^d) per element instead
+        of O(Q^d n^2d), so full-size meshes can be sampled at high order."""
+        x = np.asarray(x, np.float64)
+        elems = list(range(self.nelem)) if elems is None else list(elems)
+        out = []
+        for k, e in enumerate(elems):
+            xe = x[k]
+            grad = np.stack([self.Dt[b] @ xe for b in range(self.dim)])          # (d, nq)
+            c = self.wJ[e] * self.kappa[e]
+            flux = np.einsum("qab,bq->aq", self.G[e], grad) * c[None, :]
+            y = sum(self.Dt[a].T @ flux[a] for a in range(self.dim))
+            out.append(y + self.lam[e] * (self.Bt.T @ (self.wJ[e] * (self.Bt @ xe))))
+        return np.stack(out)
+
     def weak_rhs(self, U, dU):
         """l_e[m] = a_e(U, phi_m) for a field given by its values U[e, q] and
         reference gradient dU[e, a, q] at the quadrature points:

@@ -1549,3 +1549,25 @@ def test_pyramidal_helmholtz_solve_is_exact():
     b[dm.astype(bool)] = 0.0
     sol = oracle.direct_solve(mats, l2g, ng, dm, b)
     assert np.abs(ops.bwd(oracle.gather(sol, l2g)) - u).max() < 1e-12
+
+
+@pytest.mark.parametrize("dim,P", [(2, 3), (3, 2), (3, 4)])
+def test_helmholtz_action_equals_the_elemental_matrices(dim, P):
+    """The matrix-free form of the oracle's Helmholtz (quadrature sums
+    without forming H_e) equals H_e x_e with the pinned elemental matrices,
+    on curved elements with per-point kappa and per-element lambda."""
+    Q = P + 2
+    shape = (2,) * dim
+    lat = W.lattice(shape)
+    J = W.element_jacobians(oracle.gll(Q)[0], lat, 0.05)
+    E = lat.nelem
+    rng = np.random.default_rng(dim * 10 + P)
+    kap = rng.uniform(0.5, 2.0, (E, Q ** dim))
+    lam = rng.uniform(0.5, 2.0, E)
+    ops = oracle.ElementOps(dim, P, Q, J, kappa=kap, lam=lam)
+    x = rng.uniform(-1, 1, (E, (P + 1) ** dim))
+    ref = ops.helmholtz(x)
+    got = ops.helmholtz_action(x)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    sub = [E - 1, 0]
+    assert np.abs(ops.helmholtz_action(x[sub], sub) - ref[sub]).max() <= 1e-13 * np.abs(ref).max()
