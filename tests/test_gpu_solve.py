@@ -391,3 +391,54 @@ def test_interior_last_numbering_operator_and_solve(P):
     assert rel_err(xs.cpu().numpy(), xref) < 1e-8
     xr, info = sysm.solve(to_dev(b), rtol=1e-10, mode=m.SOLVE_F32_REFINED)
     assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
+
+
+@pytest.mark.parametrize("P", [4, 6, 8])
+def test_full_size_24c_cg_sampled_residuals(P):
+    """The 24^3 curved-hex CG problem of the benchmark at full size, in its
+    launch configuration (the system's own tuned tile): FP64 PCG and the
+    FP32-refined solve to 1e-10 on a seeded right-hand side.  The oracle
+    recomputes (A x)_g at a seeded sample of free global DOFs (lattice
+    vertices, shared by eight elements, and random DOFs) from the elements
+    that hold them: every sampled residual obeys |b_g - (A x)_g| <= 1e-10
+    ||b||_2 (implied by the 2-norm criterion), and the GPU's own A x agrees
+    with the oracle's there to 1e-12 of the summed contributions."""
+    from gpu_common import lib_points
+    m = nk()
+    torch_cuda()
+    shape, Q = (24, 24, 24), P + 2
+    lat = W.lattice(shape)
+    space = m.Space.create(3, P, Q, to_dev(W.element_jacobians(lib_points(P, Q), lat, W.WARP_AMPLITUDE)))
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm), lam0=1.0)
+    fixed = dm.astype(bool)
+    b = W.uniform(W.seed(2, 1) + P, ng)
+    b[fixed] = 0.0
+    x64, info = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000)
+    assert info[0]["status"] == 0
+    x32, info = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000, mode=m.SOLVE_F32_REFINED)
+    assert info[0]["status"] == 0
+    Ax = sysm.apply(x64).cpu().numpy()
+    G = [s * P + 1 for s in shape]
+    free = np.flatnonzero(~fixed)
+    gx, gy, gz = free % G[0], (free // G[0]) % G[1], free // (G[0] * G[1])
+    verts = free[(gx % P == 0) & (gy % P == 0) & (gz % P == 0)]
+    rng = np.random.default_rng(40 + P)
+    sample = np.unique(np.concatenate([rng.choice(verts, 4, replace=False), rng.choice(free, 8, replace=False)]))
+    hits = {int(g): np.argwhere(l2g == g) for g in sample}          # (e, local mode) pairs
+    elems = np.unique(np.concatenate([h[:, 0] for h in hits.values()]))
+    assert max(len(h) for h in hits.values()) == 8
+    pos = {int(e): k for k, e in enumerate(elems)}
+    Jo = W.element_jacobians(oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[elems]), W.WARP_AMPLITUDE)
+    ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0)
+    bn = np.linalg.norm(b)
+    for x, tag in ((x64, "f64"), (x32, "f32-refined")):
+        xs = x.cpu().numpy().copy()
+        xs[fixed] = 0.0
+        y = ops.helmholtz_action(xs[l2g[elems]])
+        for g, h in hits.items():
+            parts = np.array([y[pos[int(e)], mm] for e, mm in h])
+            Ag = parts.sum()
+            assert abs(b[g] - Ag) <= 1e-10 * bn, (tag, g, abs(b[g] - Ag) / bn)
+            if tag == "f64":
+                assert abs(Ax[g] - Ag) <= 1e-12 * np.abs(parts).sum(), (g, Ax[g], Ag)
