@@ -1,0 +1,150 @@
+"""GPU parity at the benchmark's full sizes, on sampled outputs the oracle
+computes one element (or one global DOF) at a time, in the launch
+configurations the benchmark times:
+
+* the 20x20x50 curved lattice with per-element orders 2..10 (20 000 hexes):
+  Helmholtz of every mixed-order strategy, FP64 and FP32, on sampled elements
+  of every order;
+* the 256 independent P=5 solves (~250 000 hexes in one batched system):
+  the smallest systems against the oracle's sparse direct solves, the largest
+  through oracle residuals at sampled DOFs;
+* the adjoint gradient kernel on the 16^3 P=6 workload with per-point kappa
+  and per-element lambda, on sampled elements.
+
+The 32^3 operators and the 24^3 CG solves are covered the same way in
+test_gpu_ops.py and test_gpu_solve.py."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.assembly import direct_solve
+from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, lib_points, nk, rel_err, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def test_full_size_20000_mixed_orders_sampled():
+    torch = torch_cuda()
+    m = nk()
+    cfg = W.CONFIGS[3]
+    lat = W.lattice(cfg["varp_shape"])
+    Pe = W.varp_orders(W.seed(3, 4), lat.nelem, *cfg["varp_P"])
+    Ps = sorted(set(int(p) for p in Pe))
+    jacs, xs, sels = [], [], []
+    for P in Ps:
+        sel = np.flatnonzero(Pe == P)
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[sel])
+        jacs.append(to_dev(W.element_jacobians(lib_points(P, P + 2), sub, cfg["warp"])))
+        xs.append(W.uniform(W.seed(3, 0) + P, (sel.size, (P + 1) ** 3)))
+        sels.append(sel)
+    space = m.Space.create_varp(3, Ps, [p + 2 for p in Ps], jacs)
+    x = np.concatenate([v.ravel() for v in xs])
+    rng = np.random.default_rng(33)
+    refs, picks = [], []
+    for P, sel, v in zip(Ps, sels, xs):
+        pick = np.unique(np.concatenate([[0, sel.size - 1], rng.choice(sel.size, 3, replace=False)]))
+        sub = W.Lattice(lat.shape, lat.h, lat.origins[sel[pick]])
+        ops = oracle.ElementOps(3, P, P + 2, W.element_jacobians(oracle.gll(P + 2)[0], sub, cfg["warp"]),
+                                lam=cfg["lam"])
+        refs.append(ops.helmholtz_action(v[pick]))
+        picks.append(pick)
+    for dt, tol in ((m.F64, FP64_RTOL), (m.F32, FP32_RTOL)):
+        td = torch.float64 if dt == m.F64 else torch.float32
+        for strategy in range(4):
+            space.set_strategy(dt, strategy)
+            y = m.helmholtz(space, to_dev(x, td), lam0=1.0, dtype=dt).double().cpu().numpy()
+            off = 0
+            for P, sel, pick, ref in zip(Ps, sels, picks, refs):
+                nm = (P + 1) ** 3
+                got = y[off:off + sel.size * nm].reshape(sel.size, nm)[pick]
+                assert_close(got, ref, tol, f"mixed order P={P} strategy={strategy} dt={dt}")
+                off += sel.size * nm
+            assert off == y.size
+
+
+def test_full_size_256_solves_sampled():
+    torch = torch_cuda()
+    m = nk()
+    cfg = W.CONFIGS[3]
+    P, Q = cfg["solve_P"], cfg["solve_P"] + 2
+    boxes = W.solve_boxes(W.seed(3, 5), cfg["nsolves"], *cfg["solve_sizes"])
+    xq = lib_points(P, Q)
+    nel = [a * b * c for a, b, c in boxes]
+    E = int(sum(nel))
+    J = torch.empty((E, 3, 3, Q ** 3), dtype=torch.float64, device="cuda")
+    l2gs, dms, eoff, doff = [], [], [0], [0]
+    for bx in boxes:
+        lat = W.lattice(bx)
+        J[eoff[-1]:eoff[-1] + lat.nelem] = torch.from_numpy(W.element_jacobians(xq, lat, cfg["warp"]))
+        l2g, ng, dm = W.lattice_l2g(bx, P)
+        l2gs.append(l2g)
+        dms.append(dm)
+        eoff.append(eoff[-1] + lat.nelem)
+        doff.append(doff[-1] + ng)
+    space = m.Space.create(3, P, Q, J)
+    del J
+    sysb = m.System.create_batched(space, eoff, doff,
+                                   to_dev(np.concatenate([l + o for l, o in zip(l2gs, doff[:-1])]).astype(np.int32)),
+                                   to_dev(np.concatenate(dms)), lam0=1.0)
+    b = W.uniform(W.seed(3, 1), doff[-1])
+    b[np.concatenate(dms).astype(bool)] = 0.0
+    order = np.argsort(nel)
+    small, large = [int(k) for k in order[:2]], int(order[-1])
+    # error <= cond(A) times the residual: 1e-6 leaves room for cond(A) up to 1e4
+    for mode, tol, err_tol in ((m.SOLVE_F64, 1e-10, 1e-6), (m.SOLVE_F32_REFINED, 1e-10, 1e-6)):
+        x, info = sysb.solve(to_dev(b), rtol=tol, maxit=50000, mode=mode)
+        xs = x.cpu().numpy()
+        assert len(info) == len(boxes)
+        # the CG stops on its recurrence residual; the true FP64 residual the
+        # library recomputes may drift past it by a little (cond(A) eps)
+        worst = max(i["rel_resid"] for i in info)
+        assert all(i["status"] == 0 for i in info) and worst <= 1.1 * tol, (mode, worst)
+        for k in small:
+            lat = W.lattice(boxes[k])
+            ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], lat, cfg["warp"]), lam=1.0)
+            bk = b[doff[k]:doff[k + 1]]
+            ref = direct_solve(oracle.helmholtz_matrices(ops), l2gs[k], doff[k + 1] - doff[k], dms[k], bk)
+            assert rel_err(xs[doff[k]:doff[k + 1]], ref) < err_tol, (k, mode)
+        # the largest system: oracle residuals at sampled free DOFs
+        k = large
+        lat = W.lattice(boxes[k])
+        bk, xk, l2g, fixed = b[doff[k]:doff[k + 1]], xs[doff[k]:doff[k + 1]].copy(), l2gs[k], dms[k].astype(bool)
+        xk[fixed] = 0.0
+        sample = np.random.default_rng(44).choice(np.flatnonzero(~fixed), 10, replace=False)
+        hits = {int(g): np.argwhere(l2g == g) for g in sample}
+        elems = np.unique(np.concatenate([h[:, 0] for h in hits.values()]))
+        pos = {int(e): j for j, e in enumerate(elems)}
+        ops = oracle.ElementOps(3, P, Q, W.element_jacobians(
+            oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[elems]), cfg["warp"]), lam=1.0)
+        y = ops.helmholtz_action(xk[l2g[elems]])
+        bn = np.linalg.norm(bk)
+        for g, h in hits.items():
+            Ag = sum(y[pos[int(e)], mm] for e, mm in h)
+            assert abs(bk[g] - Ag) <= 1.1 * tol * bn, (mode, g, abs(bk[g] - Ag) / bn)
+
+
+def test_full_size_16c_gradient_kernel_sampled():
+    torch_cuda()
+    m = nk()
+    cfg = W.CONFIGS[4]
+    P, Q = cfg["P"], cfg["Q"]
+    lat = W.lattice(cfg["shape"])
+    E, nq, nm = lat.nelem, Q ** 3, (P + 1) ** 3
+    kap = W.uniform(W.seed(4, 3), (E, nq), *cfg["coef_range"])
+    lam = W.uniform(W.seed(4, 2), (E,), *cfg["coef_range"])
+    space = m.Space.create(3, P, Q, to_dev(W.element_jacobians(lib_points(P, Q), lat, cfg["warp"])),
+                           kappa=to_dev(kap))
+    ul = W.uniform(W.seed(4, 0), (E, nm))
+    zl = W.uniform(W.seed(4, 1), (E, nm))
+    dk, dl = m.param_grad(space, to_dev(zl.ravel()), to_dev(ul.ravel()))
+    dk = dk.cpu().numpy().reshape(E, nq)
+    dl = dl.cpu().numpy()
+    pick = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(45).choice(E, 3, replace=False)]))
+    sub = W.Lattice(lat.shape, lat.h, lat.origins[pick])
+    ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], sub, cfg["warp"]),
+                            kappa=kap[pick], lam=lam[pick])
+    loc = np.arange(pick.size * nm).reshape(pick.size, nm)
+    dk_ref, dl_ref = oracle.param_grad(ops, loc, ul[pick].ravel(), zl[pick].ravel())
+    assert_close(dk[pick], dk_ref, FP64_RTOL, "full-size dkappa")
+    assert_close(dl[pick], dl_ref, FP64_RTOL, "full-size dlambda")
