@@ -379,9 +379,21 @@ __global__ void __launch_bounds__(256)
           const T* cr = C3 + kk * CS + tcol[tt];
           const T* dcr = dC3 + kk * CS + tcol[tt];
           T w = T(0), w3 = T(0);
-          for (int r = 0; r < c; ++r) {
-            w += cr[r] * U[o + r];
-            if constexpr (HELM) w3 += dcr[r] * U[o + r];
+          if constexpr (SH == kPrism) {
+            // every triangle mode has all N factors: a fixed-length sum whose
+            // LDS reads are issued together (measured 2-4% faster; unrolling
+            // the variable-length sums of the other shapes with zero-weighted
+            // padding did not pay)
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+              w += cr[r] * U[o + r];
+              if constexpr (HELM) w3 += dcr[r] * U[o + r];
+            }
+          } else {
+            for (int r = 0; r < c; ++r) {
+              w += cr[r] * U[o + r];
+              if constexpr (HELM) w3 += dcr[r] * U[o + r];
+            }
           }
           if constexpr (APEX) {
             if (S::lower_vertex(tt)) {   // the top vertex rides on the lower vertex modes
