@@ -79,7 +79,10 @@ static int vector_tile_count(int op, int dim, int P) {
   int c = 0;
   for (int k = 0; k < kMaxTiles; ++k)
     c += (dim == 3 ? kTileEPB3[P][k] : kTileEPB2[P][k]) > 0 ? 1 : 0;
-  if (dim == 3 && op_has_lean(op)) c *= kHelmForms;   // each candidate also lean and deep
+  if (dim == 3 && op_has_lean(op)) {
+    c *= kHelmForms;                       // each candidate also lean and deep
+    if (packed_epb3(P) > 0) c += 1;        // and the packed slots
+  }
   return c;
 }
 
@@ -100,10 +103,14 @@ const char* tile_name(int op, int dim, int P, int tile) {
     return buf;
   }
   const int form = dim == 3 && op_has_lean(op) ? tile / epb3_count(P) : 0;   // 0, lean, deep
-  if (dim == 3) tile %= epb3_count(P);
-  const int epb = dim == 3 ? kTileEPB3[P][tile] : kTileEPB2[P][tile];
   const int q = P + 2;
   const int q2 = q * q;
+  if (form == kHelmForms) {
+    std::snprintf(buf, sizeof buf, "epb%d_thr%d_packed", packed_epb3(P), packed_epb3(P) * q2);
+    return buf;
+  }
+  if (dim == 3) tile %= epb3_count(P);
+  const int epb = dim == 3 ? kTileEPB3[P][tile] : kTileEPB2[P][tile];
   const int slot = dim == 3 ? (q2 <= 16 ? 16 : q2 <= 64 ? 64 : q2) : q;
   std::snprintf(buf, sizeof buf, "epb%d_thr%d%s", epb, epb * slot,
                 form == 1 ? "_lean" : form == 2 ? "_deep" : "");

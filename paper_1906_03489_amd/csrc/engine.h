@@ -421,11 +421,13 @@ constexpr int slot_threads() {
   return Q * Q <= 1 ? 1 : Q * Q <= 4 ? 4 : Q * Q <= 16 ? 16 : Q * Q <= 64 ? 64 : Q * Q;
 }
 
-template <typename T, int N, int Q, int EPB, int OP, int PF = 2>
-__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+// NTX: threads per slot, 0 for slot_threads<Q>(); Q*Q packs slots without
+// idle lanes at the price of block barriers (Q*Q does not divide 64).
+template <typename T, int N, int Q, int EPB, int OP, int PF = 2, int NTX = 0>
+__global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
     k_op3(const Tab<T, N, Q> tb, const DevArgs<T> a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q, S = Q * Q * N;
-  constexpr int NT = slot_threads<Q>();
+  constexpr int NT = NTX ? NTX : slot_threads<Q>();
   constexpr bool DER = (OP == OP_HELM || OP == OP_HELM_ASM || OP == OP_GRAD || OP == OP_RHS);
   constexpr int NTEN = DER ? 3 : 1;
   constexpr bool ASM = (OP == OP_HELM_ASM);

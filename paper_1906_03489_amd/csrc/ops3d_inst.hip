@@ -13,14 +13,15 @@
 
 namespace nk {
 
-template <typename T, int P, int EPB, int OP, int PF = 2>
+template <typename T, int P, int EPB, int OP, int PF = 2, int NTX = 0>
 static hipError_t run3(const OpArgs& a) {
   constexpr int N = P + 1, Q = P + 2;
   static_assert(EPB > 0, "tile");
   const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, PF>), dim3((unsigned)nblk), dim3(EPB * slot_threads<Q>()), 0,
+  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, PF, NTX>), dim3((unsigned)nblk),
+                     dim3(EPB * (NTX ? NTX : slot_threads<Q>())), 0,
                      a.stream, tb, dev_args<T>(a));
   return hipGetLastError();
 }
@@ -30,6 +31,10 @@ static hipError_t run3_tiled(const OpArgs& a) {
   constexpr int E0 = kTileEPB3[P][0], E1 = kTileEPB3[P][1], E2 = kTileEPB3[P][2];
   constexpr int NE = epb3_count(P);
   if constexpr (op_has_lean(OP)) {
+    constexpr int EPK = packed_epb3(P);
+    if constexpr (EPK > 0) {   // the packed slots, after the three factor-set forms
+      if (a.tile == kHelmForms * NE) return run3<T, P, EPK, OP, 2, (P + 2) * (P + 2)>(a);
+    }
     if (a.tile >= NE) {   // candidates NE.. : one factor set, then four
       const int k = (a.tile - NE) % NE;
       if (a.tile >= 2 * NE) {

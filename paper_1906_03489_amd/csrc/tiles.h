@@ -45,6 +45,15 @@ constexpr bool op_has_tiles(int op) { return op <= 3; }
 // all are timed.
 constexpr int kDeepPF = 4;
 constexpr int kHelmForms = 3;
+
+// One more Helmholtz candidate where a slot of Q*Q threads leaves lanes idle
+// when rounded up to 64 (Q = 5, 6, 7: 25, 36, 49 of 64): slots of exactly
+// Q*Q threads packed into blocks of up to 256 (block barriers between the
+// stages).  Elements per block, 0 where there is no such candidate.
+constexpr int packed_epb3(int P) {
+  const int q2 = (P + 2) * (P + 2);
+  return (q2 > 16 && q2 < 64) ? 256 / q2 : 0;
+}
 constexpr int epb3_count(int P) {
   int c = 0;
   for (int k = 0; k < kMaxTiles; ++k) c += kTileEPB3[P][k] > 0 ? 1 : 0;
