@@ -1580,7 +1580,11 @@ nk_status nk_autotune(nk_space s, int op_mask, void* stream) {
                           (t == NK_F64 ? "f64" : "f32") + "_" + dev;
         int best = 0;
         if (nt > 1 && !cache_lookup(key, &best)) {
-          double best_us = 1e30;
+          // two interleaved passes over the candidates, each candidate's
+          // best pass kept, so a clock or thermal drift during one pass does
+          // not decide between candidates a few per cent apart
+          std::vector<double> us_k(nt, 1e30);
+          for (int pass = 0; pass < 2 && result == NK_OK; ++pass)
           for (int k = 0; k < nt; ++k) {
             OpArgs o;
             o.op = op;
@@ -1606,13 +1610,11 @@ nk_status nk_autotune(nk_space s, int op_mask, void* stream) {
             }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            const double us = 1000.0 * ms / reps;
-            if (us < best_us) {
-              best_us = us;
-              best = k;
-            }
+            us_k[k] = std::min(us_k[k], 1000.0 * ms / reps);
           }
-          if (result == NK_OK) cache_store(key, best, best_us);
+          for (int k = 1; k < nt; ++k)
+            if (us_k[k] < us_k[best]) best = k;
+          if (result == NK_OK) cache_store(key, best, us_k[best]);
         }
         if (result == NK_OK) {
           (void)cur_tile(op, s->dim, G.P, t);  // runs the one-time default initialisation
