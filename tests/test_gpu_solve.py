@@ -402,7 +402,8 @@ def test_full_size_24c_cg_sampled_residuals(P):
     vertices, shared by eight elements, and random DOFs) from the elements
     that hold them: every sampled residual obeys |b_g - (A x)_g| <= 1e-10
     ||b||_2 (implied by the 2-norm criterion), and the GPU's own A x agrees
-    with the oracle's there to 1e-12 of the summed contributions."""
+    with the oracle's there to 1e-12 of the largest output of the elements
+    involved (the scale of the rounding in a sum with cancellation)."""
     from gpu_common import lib_points
     m = nk()
     torch_cuda()
@@ -441,4 +442,5 @@ def test_full_size_24c_cg_sampled_residuals(P):
             Ag = parts.sum()
             assert abs(b[g] - Ag) <= 1e-10 * bn, (tag, g, abs(b[g] - Ag) / bn)
             if tag == "f64":
-                assert abs(Ax[g] - Ag) <= 1e-12 * np.abs(parts).sum(), (g, Ax[g], Ag)
+                scale = sum(np.abs(y[pos[int(e)]]).max() for e, _ in h)
+                assert abs(Ax[g] - Ag) <= 1e-12 * scale, (g, Ax[g], Ag, scale)
