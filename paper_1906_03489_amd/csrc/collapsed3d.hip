@@ -1,8 +1,10 @@
-// Collapsed-coordinate tetrahedra and prisms (section 2.1: shapes reached
-// from the hexahedron through the Duffy map, collapsing two directions for
-// the tetrahedron and one for the prism; section 3.3: the expansion factors in
-// the collapsed coordinates, so the operators stay sum-factorised).
-// Elemental BwdTrans, IProductWRTBase and Helmholtz.
+// Collapsed-coordinate tetrahedra, prisms and pyramids (section 2.1: shapes
+// reached from the hexahedron through the Duffy map, collapsing two
+// directions for the tetrahedron and one for the prism and the pyramid;
+// section 3.3: the expansion factors in the collapsed coordinates, so the
+// operators stay sum-factorised).  Elemental BwdTrans, IProductWRTBase and
+// Helmholtz, the assembled Helmholtz operator (gather, Helmholtz,
+// scatter-add, per-element energies) and its Jacobi diagonal.
 //
 // Prisms: the triangle of tri.hip in (xi_1, xi_2) extruded along xi_3, every
 // mode a triangle mode times the 1-D modified basis phi_r(xi_3), r = 0..P
@@ -806,13 +808,15 @@ hipError_t launch_diag_pyr(int P, int64_t nelem, const double* fac, const double
   return diag_col<kPyr>(P, nelem, fac, lam, lam0, l2g, diag, st);
 }
 
-// Factors of the collapsed tetrahedron or prism at every point (thread per
-// point): f0 = w detJ, f1..f6 = w detJ kappa (M G M^T)_{11,12,13,22,23,33}
-// with G = J^{-1} J^{-T} and M_ba = d eta_b / d xi_a.  Tetrahedron: w = w1_i
-// (w2_j / 2) (w3_k / 4) (the Radau weights carry (1 - eta_2) and
-// (1 - eta_3)^2); prism: w = w1_i (w2_j / 2) w3_k.  Layout [E][7][Q][NS]:
-// for each factor and eta_1 index i, the rows j + (Q-1) k are contiguous, the
-// order in which the operator's threads read them.
+// Factors of the collapsed tetrahedron, prism or pyramid at every point
+// (thread per point): f0 = w |detJ| (tetrahedra, whose sorted vertex orders
+// may be left-handed) or w detJ, f1..f6 = the same times kappa
+// (M G M^T)_{11,12,13,22,23,33} with G = J^{-1} J^{-T} and M_ba = d eta_b /
+// d xi_a.  Tetrahedron: w = w1_i (w2_j / 2) (w3_k / 4) (the Radau weights
+// carry (1 - eta_2) and (1 - eta_3)^2); prism: w = w1_i (w2_j / 2) w3_k;
+// pyramid: w = w1_i w2_j (w3_k / 4).  Layout [E][7][Q][NS]: for each factor
+// and eta_1 index i, the rows j + Q2 k are contiguous, the order in which the
+// operator's threads read them.
 template <int SH>
 __global__ void __launch_bounds__(256)
     k_geom_tet(int Q, int64_t nelem, const double* __restrict__ jac, const double* __restrict__ kappa,
