@@ -9,7 +9,9 @@ configurations the benchmark times:
   the smallest systems against the oracle's sparse direct solves, the largest
   through oracle residuals at sampled DOFs;
 * the adjoint gradient kernel on the 16^3 P=6 workload with per-point kappa
-  and per-element lambda, on sampled elements.
+  and per-element lambda, on sampled elements;
+* the assembled triangle, tetrahedron, prism and pyramid solves at the
+  benchmark's mesh sizes, through oracle residuals at sampled DOFs.
 
 The 32^3 operators and the 24^3 CG solves are covered the same way in
 test_gpu_ops.py and test_gpu_solve.py."""
@@ -148,3 +150,86 @@ def test_full_size_16c_gradient_kernel_sampled():
     dk_ref, dl_ref = oracle.param_grad(ops, loc, ul[pick].ravel(), zl[pick].ravel())
     assert_close(dk[pick], dk_ref, FP64_RTOL, "full-size dkappa")
     assert_close(dl[pick], dl_ref, FP64_RTOL, "full-size dlambda")
+
+
+# ------------------- collapsed-shape solves at the benchmark's mesh sizes
+
+def _collapsed_case(shape, P):
+    """(space, system, l2g, sign, nglobal, dirichlet, oracle-ops factory over
+    element subsets) for the benchmark's triangle, tetrahedron, prism and
+    pyramid solve meshes."""
+    from oracle import collapsed as C
+    m = nk()
+    Q = P + 2
+    g = oracle.gll(Q)[0]
+    r1 = C.gauss_radau_jacobi(Q - 1, 1.0, 0.0)[0]
+    r2 = C.gauss_radau_jacobi(Q - 1, 2.0, 0.0)[0]
+    sign = None
+    if shape == "tri":
+        n = 128
+        rot = W.tri_rotations(W.seed(5, 7), 2 * n * n)
+        e1, _, e2, _ = m.tri_points(Q)
+        space = m.Space.create_tri(P, Q, to_dev(W.tri_lattice_jacobians(n, e1, e2, 0.05, rot)))
+        l2g, sign, ng, dm = W.tri_lattice_l2g(n, P, rot)
+        Jo = W.tri_lattice_jacobians(n, g, r1, 0.05, rot)
+        factory = lambda el: C.TriOps(P, Q, Jo[el])
+    elif shape == "tet":
+        n = 12
+        e1, _, e2, _, e3, _ = m.tet_points(Q)
+        space = m.Space.create_tet(P, Q, to_dev(W.tet_lattice_jacobians(n, e1, e2, e3, sorted_ids=True)))
+        l2g, ng, dm = W.tet_lattice_l2g(n, P)
+        factory = lambda el: C.TetOps(P, Q, W.tet_lattice_jacobians(n, g, r1, r2, elems=el, sorted_ids=True))
+    elif shape == "prism":
+        n = 16
+        rot = W.tri_rotations(W.seed(2, 7), 2 * n * n)
+        e1, _, e2, _ = m.tri_points(Q)
+        space = m.Space.create_prism(P, Q, to_dev(W.prism_lattice_jacobians(n, e1, e2, e1, rot=rot)))
+        l2g, sign, ng, dm = W.prism_lattice_l2g(n, P, rot)
+        factory = lambda el: C.PrismOps(P, Q, W.prism_lattice_jacobians(n, g, r1, g, elems=el, rot=rot))
+    else:
+        n = 10
+        xg = m.basis_tables(P, Q)[0]
+        space = m.Space.create_pyr(P, Q, to_dev(W.pyr_lattice_jacobians(n, xg, xg, m.tet_points(Q)[4])))
+        l2g, ng, dm = W.pyr_lattice_l2g(n, P)
+        factory = lambda el: C.PyrOps(P, Q, W.pyr_lattice_jacobians(n, g, g, r2, elems=el))
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm), lam0=1.0,
+                           sign=None if sign is None else to_dev(sign))
+    return space, sysm, l2g, sign, ng, dm, factory
+
+
+@pytest.mark.parametrize("shape", ["tri", "tet", "prism", "pyr"])
+@pytest.mark.parametrize("P", [4, 6])
+def test_full_size_collapsed_solves_sampled_residuals(shape, P):
+    """The benchmark's assembled triangle (32 768), tetrahedron (10 368),
+    prism (8 192) and pyramid (6 000) solves at full size, FP64 and
+    FP32-refined to 1e-10 on a seeded right-hand side: the oracle recomputes
+    (A x)_g from the dense elemental matrices of the elements that hold a
+    seeded sample of free DOFs (with orientation signs), and every sampled
+    residual obeys |b_g - (A x)_g| <= 1.1e-10 ||b||_2."""
+    m = nk()
+    torch_cuda()
+    space, sysm, l2g, sign, ng, dm, factory = _collapsed_case(shape, P)
+    fixed = dm.astype(bool)
+    b = W.uniform(W.seed(2, 3) + P, ng)
+    b[fixed] = 0.0
+    free = np.flatnonzero(~fixed)
+    sample = np.random.default_rng(50 + P).choice(free, 12, replace=False)
+    hits = {int(gd): np.argwhere(l2g == gd) for gd in sample}
+    elems = np.unique(np.concatenate([h[:, 0] for h in hits.values()]))
+    pos = {int(e): k for k, e in enumerate(elems)}
+    ops = factory(elems)
+    mats = [ops.helmholtz_matrix(k) for k in range(len(elems))]
+    sg = np.ones_like(l2g, dtype=np.float64) if sign is None else sign.astype(np.float64)
+    bn = np.linalg.norm(b)
+    for mode in (m.SOLVE_F64, m.SOLVE_F32_REFINED):
+        x, info = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000, mode=mode)
+        assert info[0]["status"] == 0
+        xs = x.cpu().numpy().copy()
+        xs[fixed] = 0.0
+        for gd, h in hits.items():
+            Ag = 0.0
+            for e, mm in h:
+                k = pos[int(e)]
+                ye = mats[k] @ (sg[e] * xs[l2g[e]])
+                Ag += sg[e, mm] * ye[mm]
+            assert abs(b[gd] - Ag) <= 1.1e-10 * bn, (shape, P, mode, gd, abs(b[gd] - Ag) / bn)
