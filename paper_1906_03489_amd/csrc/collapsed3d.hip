@@ -247,17 +247,28 @@ static TetTables tet_tables(int P, int sh) {
 // and sometimes a wave per SIMD; measured per shape and order on MI355X, it
 // loses for FP64 tetrahedra at P <= 4, prisms at P >= 8 and pyramids at
 // P >= 6, for FP32 tetrahedra at P = 6 and pyramids at P >= 8, and for the
-// assembled tetrahedron operator (one wave per SIMD fewer at P = 6).
+// assembled tetrahedron operator (one wave per SIMD fewer at P = 6); FP64 at
+// P = 6 trades it for a fourth wave per SIMD instead (tet_min_waves).
 template <typename T>
 constexpr bool tet_helm_prefetch(int P, int SH, int OP) {
   if (OP != OP_HELM) return false;
+  if (sizeof(T) == 8 && P == 6) return false;   // held to 128 VGPRs instead (below)
   if (sizeof(T) == 8)
     return !((SH == kTet && P <= 4) || (SH == kPrism && P >= 8) || (SH == kPyr && P >= 6));
   return !((SH == kTet && P == 6) || (SH == kPyr && P >= 8));
 }
 
+// FP64 Helmholtz at P = 6 asks the compiler for four waves per SIMD (at most
+// 128 VGPRs, instead of 134-162 and three waves): measured 4-5% faster for
+// tetrahedra and prisms (the compiler keeps 150-160 for the pyramid and the
+// assembled tetrahedron operator, which are unchanged).  Elsewhere no target.
+template <typename T>
+constexpr int tet_min_waves(int P, int OP) {
+  return sizeof(T) == 8 && P == 6 && (OP == OP_HELM || OP == OP_HELM_ASM) ? 4 : 1;
+}
+
 template <typename T, int P, int SH, int OP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_min_waves<T>(P, OP))))
     k_tet(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const int* __restrict__ itab,
           const DevArgs<T> a) {
   using S = TetShape<P, SH>;
