@@ -98,8 +98,15 @@ static const T* tri_table(int P) {
 //     modes t, t + Q2, ...; results staged in LDS and stored contiguously.
 // Each wavefront works only in its own LDS region, so stages are separated
 // by wavefront-level fences.
+// FP64 Helmholtz at P = 6 fits four waves per SIMD (126 VGPRs, no spill)
+// when asked for them, instead of 134 VGPRs and three.
+template <typename T>
+constexpr int tri_min_waves(int P, int OP) {
+  return sizeof(T) == 8 && P == 6 && OP == OP_HELM ? 4 : 1;
+}
+
 template <typename T, int P, int OP>
-__global__ void __launch_bounds__(TriShape<P>::WPB * 64)
+__global__ void __launch_bounds__(TriShape<P>::WPB * 64) __attribute__((amdgpu_waves_per_eu(tri_min_waves<T>(P, OP))))
     k_tri(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const DevArgs<T> a) {
   using S = TriShape<P>;
   constexpr int N = S::N, Q = S::Q, Q2 = S::Q2, NP = S::NP, NM = S::NM, EPW = S::EPW;
