@@ -11,7 +11,12 @@
  * Helmholtz operator of the weak problem a(u, v) = l(v) of Eqs. (1)-(2), all
  * by sum-factorisation (the display in section 3.3).  On top of these it
  * assembles the C0 system (section 2.1, assembly operator) and solves it with
- * Jacobi-preconditioned conjugate gradients.
+ * Jacobi-preconditioned conjugate gradients (FP64, or FP32 inside FP64
+ * iterative refinement), batches independent systems and mixed orders, and
+ * differentiates the solve with respect to kappa and lambda.  Besides
+ * quadrilaterals and hexahedra it covers the collapsed-coordinate triangles,
+ * tetrahedra, prisms and pyramids of section 2.1 (their elemental operators
+ * and assembled solves; nk_space_create_tri / _tet / _prism / _pyr).
  *
  * Discretisation (section 2.1):
  *   - 1-D modified hierarchical C0 basis phi_p, 0 <= p <= P (P = polynomial
