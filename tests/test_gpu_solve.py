@@ -444,3 +444,29 @@ def test_full_size_24c_cg_sampled_residuals(P):
             if tag == "f64":
                 scale = sum(np.abs(y[pos[int(e)]]).max() for e, _ in h)
                 assert abs(Ax[g] - Ag) <= 1e-12 * scale, (g, Ax[g], Ag, scale)
+
+
+def test_system_size_limit_rejected():
+    """Bit 30 of an internal l2g entry carries the orientation sign, so a
+    system holds fewer than 2^30 DOFs both as given and after each system's
+    DOF range is padded to whole reduction blocks. Both limits are rejected
+    with NK_EINVAL on the host before any device allocation."""
+    torch = torch_cuda()
+    m = nk()
+    P, Q = 1, 3
+    Jg, _, _ = jacobians((1, 1, 1), P, 0.0)
+    space = m.Space.create(3, P, Q, to_dev(Jg))
+    l2g = to_dev(np.arange(8, dtype=np.int32).reshape(1, 8))
+    small = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(m.NkError) as ei:
+        m.System.create(space, 1 << 30, l2g, small)
+    assert ei.value.status == m.NK_EINVAL
+    assert "too many global DOFs" in str(ei.value)
+    ng = (1 << 30) - 1
+    dm = torch.zeros(ng, dtype=torch.uint8, device="cuda")
+    with pytest.raises(m.NkError) as ei:
+        m.System.create(space, ng, l2g, dm)
+    assert ei.value.status == m.NK_EINVAL
+    assert "padded system too large" in str(ei.value)
+    del dm
+    torch.cuda.empty_cache()
