@@ -78,16 +78,19 @@ struct TetShape {
   static constexpr int NITAB = 3 * NMT + 1 + NM3;               // toff3, tp, mt, tcol
   // Per-element LDS of operator OP, in scalars: the coefficients u (not for
   // IProductWRTBase), w, w' (Helmholtz only), then the transposed eta_1
-  // buffer [NS][N] (one of SA, SB, SC at a time) or BwdTrans's staged point
-  // rows [NS][Q | 1]
+  // buffer [NS][N] (one of SA, SB, SC at a time).  BwdTrans stages its point
+  // rows [NS][Q | 1] over u and w, which are dead once the eta_2 stage has
+  // read them: the smaller slot lets half as many blocks again share a CU
   static constexpr int RS = Q | 1;
   static constexpr int u_off(int) { return 0; }
   static constexpr int w_off(int op) { return op == OP_IPROD ? 0 : NM3; }
   static constexpr int w3_off(int op) { return w_off(op) + Q3 * NMT; }
   static constexpr int ss_off(int op) {
-    return w3_off(op) + (op == OP_HELM || op == OP_HELM_ASM ? Q3 * NMT : 0);
+    return op == OP_BWD ? 0 : w3_off(op) + (op == OP_HELM || op == OP_HELM_ASM ? Q3 * NMT : 0);
   }
-  static constexpr int slot(int op) { return ss_off(op) + NS * (op == OP_BWD ? RS : N); }
+  static constexpr int slot(int op) {
+    return op == OP_BWD ? (w3_off(op) > NS * RS ? w3_off(op) : NS * RS) : ss_off(op) + NS * N;
+  }
   // elements that fit in ~150 KB of LDS beside the tables
   template <typename T>
   static constexpr int by_lds(int op) {
@@ -453,8 +456,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
         }
       }
       if constexpr (OP == OP_BWD) {
-        // rows staged in LDS (row stride RS), then the block's contiguous run
-        // of point values leaves in one coalesced sweep
+        // rows staged in LDS (row stride RS) over u and w, once every thread
+        // of the element has read them; then the block's contiguous run of
+        // point values leaves in one coalesced sweep
+        esync();
 #pragma unroll 1
         for (int i = 0; i < Q; ++i) {
           T u = T(0);
