@@ -69,7 +69,11 @@ struct TetShape {
   // LDS row strides (in scalars), odd so that distinct rows fall into
   // distinct banks
   static constexpr int TS = NB | 1, CS = NC | 1;
-  static constexpr int NTAB = 2 * Q2 * TS + 2 * Q3 * CS;        // B2, dB2, C3, dC3
+  // LDS tables B2, C3, then dB2, dC3 for Helmholtz only (the other
+  // operators read no derivatives)
+  static constexpr int ntab(int op) {
+    return (op == OP_HELM || op == OP_HELM_ASM ? 2 : 1) * (Q2 * TS + Q3 * CS);
+  }
   // vertex modes of the lower part (the apex rides on them)
   static constexpr bool lower_vertex(int t) {
     return SH == kPyr ? (t == 0 || t == P || t == P * N || t == P * N + P)
@@ -94,7 +98,7 @@ struct TetShape {
   // elements that fit in ~150 KB of LDS beside the tables
   template <typename T>
   static constexpr int by_lds(int op) {
-    return (int)((150000 / sizeof(T) - NTAB) / slot(op));
+    return (int)((150000 / sizeof(T) - ntab(op)) / slot(op));
   }
   // Wavefront-aligned elements: when an element's NS rows fit in one
   // wavefront, each wavefront holds EPW whole elements (lanes past EPW NS
@@ -284,26 +288,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
   constexpr bool ASM = OP == OP_HELM_ASM;                // gathered input, scattered output
   constexpr bool HELM = OP == OP_HELM || ASM;
   constexpr bool HPF = HELM && tet_helm_prefetch<T>(P, SH, OP);
-  __shared__ T stab[S::NTAB];
+  __shared__ T stab[S::ntab(OP)];
   __shared__ int sit[S::NITAB];
   __shared__ T smem[EPB * SLOT];
   __shared__ double sred[ASM ? 256 : 1];                 // per-thread energy parts
+  constexpr int DT = Q2 * TS + Q3 * CS;                  // offset of dB2, dC3
   for (int k = threadIdx.x; k < Q2 * NB; k += blockDim.x) {
     const int r = k / NB, m = k - r * NB;
     stab[r * TS + m] = tab[k];
-    stab[(Q2 + r) * TS + m] = tab[Q2 * NB + k];
+    if constexpr (HELM) stab[DT + r * TS + m] = tab[Q2 * NB + k];
   }
   for (int k = threadIdx.x; k < Q3 * NC; k += blockDim.x) {
     const int r = k / NC, m = k - r * NC;
-    stab[2 * Q2 * TS + r * CS + m] = tab[2 * Q2 * NB + k];
-    stab[2 * Q2 * TS + (Q3 + r) * CS + m] = tab[2 * Q2 * NB + Q3 * NC + k];
+    stab[Q2 * TS + r * CS + m] = tab[2 * Q2 * NB + k];
+    if constexpr (HELM) stab[DT + Q2 * TS + r * CS + m] = tab[2 * Q2 * NB + Q3 * NC + k];
   }
   for (int k = threadIdx.x; k < S::NITAB; k += blockDim.x) sit[k] = itab[k];
   __syncthreads();
   const T* B2 = stab;
-  const T* dB2 = stab + Q2 * TS;
-  const T* C3 = stab + 2 * Q2 * TS;
-  const T* dC3 = C3 + Q3 * CS;
+  const T* C3 = stab + Q2 * TS;
+  const T* dB2 = HELM ? stab + DT : B2;             // read by Helmholtz only
+  const T* dC3 = HELM ? dB2 + Q2 * TS : C3;
   const int* toff3 = sit;
   const int* tp = sit + NMT + 1;
   const int* mt = tp + NMT;
