@@ -46,7 +46,11 @@ struct TriShape {
   }
   static constexpr bool helm(int op) { return op == OP_HELM || op == OP_HELM_ASM; }
   static constexpr int ntab(int op) { return helm(op) ? 2 : 1; }   // B2 (, dB2)
-  static constexpr int wave_lds(int op) { return EPW * (CS + xs(op)); }
+  // a wavefront's LDS; BwdTrans stages its point values over the coefficients,
+  // which are dead once its eta_2 stage has read them
+  static constexpr int wave_lds(int op) {
+    return op == OP_BWD ? EPW * (CS > xs(op) ? CS : xs(op)) : EPW * (CS + xs(op));
+  }
   static constexpr int cnt(int p) { return p == 0 ? P + 1 : (p == P ? P : P - p); }
   static constexpr int off(int p) {
     int o = 0;
@@ -128,7 +132,7 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64) __attribute__((amdgpu_w
   const bool row = lane < LANES;
   const int ela = row ? el : 0;           // addressing: idle lanes use triangle 0
   T* Cw = smem + wave * WAVE;             // [EPW][CS] coefficients, later results
-  T* Xw = Cw + EPW * S::CS;               // [EPW][XS] point values / SA, SB
+  T* Xw = Cw + (OP == OP_BWD ? 0 : EPW * S::CS);   // [EPW][XS] point values / SA, SB
   const T* B2 = stab + j * S::TS;
   const T* dB2 = stab + (Q2 + j) * S::TS;
   const int64_t ngrp = (a.nelem + EPW - 1) / EPW;
@@ -238,6 +242,7 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64) __attribute__((amdgpu_w
         if constexpr (HELM) dV[P] += dB2[P] * cm;
       }
       if constexpr (OP == OP_BWD) {
+        slot_sync<64>();   // every lane has read the coefficients under Xw
         T* x = Xw + ela * XS + j * S::RS;
 #pragma unroll 1
         for (int i = 0; i < Q; ++i) {
