@@ -274,6 +274,12 @@ constexpr int tet_min_waves(int P, int OP) {
   return sizeof(T) == 8 && P == 6 && (OP == OP_HELM || OP == OP_HELM_ASM) ? 4 : 1;
 }
 
+// Pyramids hold a row's N eta_2 factors in registers (measured on MI355X,
+// FP64: BwdTrans 6-8% faster at P = 4, 6, 8, Helmholtz 2-3% at P = 6), except
+// the local Helmholtz operator at P <= 4, where the extra registers cost it a
+// wave per SIMD (10% slower at P = 4)
+constexpr bool pyr_hold_b2(int P, int SH, int OP) { return SH == kPyr && !(OP == OP_HELM && P <= 4); }
+
 template <typename T, int P, int SH, int OP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_min_waves<T>(P, OP))))
     k_tet(const Tab<T, P + 1, P + 2> tb, const T* __restrict__ tab, const int* __restrict__ itab,
@@ -435,15 +441,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
       const T* w3 = W3 + k * NMT;
       const T* b2 = B2 + j * TS;
       const T* db2 = dB2 + j * TS;
+      // a pyramid row's eta_2 factors depend on q only: N values, held in
+      // registers rather than re-read for every p behind the group fences
+      constexpr bool HOLD = pyr_hold_b2(P, SH, OP);
+      T hb[HOLD ? N : 1], hdb[HOLD && HELM ? N : 1];
+      if constexpr (HOLD) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          hb[q] = b2[q];
+          if constexpr (HELM) hdb[q] = db2[q];
+        }
+      }
 #pragma unroll
       for (int p = 0; p < N; ++p) {
 #pragma unroll
         for (int q = 0; q < S::cnt(p); ++q) {
           const int m = S::off(p) + q, mb = S::bcol(m);
-          V[p] += b2[mb] * w[m];
+          const T bq = HOLD ? hb[HOLD ? q : 0] : b2[mb];
+          V[p] += bq * w[m];
           if constexpr (HELM) {
-            dV[p] += db2[mb] * w[m];
-            V3[p] += b2[mb] * w3[m];
+            dV[p] += (HOLD ? hdb[HOLD && HELM ? q : 0] : db2[mb]) * w[m];
+            V3[p] += bq * w3[m];
           }
         }
         // finish one mode group before the next group's loads are issued
