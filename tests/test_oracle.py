@@ -536,7 +536,7 @@ def test_fwd_trans_inverts_bwd_and_is_galerkin(P):
 
 
 # ------------------------------------------- conforming variable-order assembly
-# (section 3.6: the order varies per element and the variation is built into
+# (section 4.2: the order varies per element and the variation is built into
 # the assembly between neighbours; the modified basis' boundary-interior
 # decomposition makes the minimum rule on shared faces and edges conforming)
 
@@ -1571,3 +1571,60 @@ def test_helmholtz_action_equals_the_elemental_matrices(dim, P):
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     sub = [E - 1, 0]
     assert np.abs(ops.helmholtz_action(x[sub], sub) - ref[sub]).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ------------------------------------------------- Jacobi diagonal (a7)
+# The preconditioner is diag(A) of the Dirichlet-restricted assembled
+# operator, with the Dirichlet rows (not unknowns) set to one.  Two pins that
+# do not go through `jacobi_diagonal`'s own route (elemental diagonals
+# scatter-added): brute force -- apply the masked operator, built from the
+# full elemental matrices through gather / scatter-add, to every unit vector
+# e_g and read row g -- and the diagonal of the sparse assembled matrix.
+
+def _probe_diagonal(mats, l2g, ng, dm, sign=None):
+    A = MaskedOperator(mats, l2g, ng, dm, sign)
+    d = np.empty(ng)
+    for g in range(ng):
+        e = np.zeros(ng)
+        e[g] = 1.0
+        d[g] = A(e)[g]
+    d[np.asarray(dm, bool)] = 1.0
+    return d
+
+
+def _check_jacobi_diagonal(mats, l2g, ng, dm, sign=None):
+    d = jacobi_diagonal(mats, l2g, ng, dm, sign)
+    dmb = np.asarray(dm, bool)
+    assert dmb.any() and (~dmb).any()
+    np.testing.assert_allclose(d, _probe_diagonal(mats, l2g, ng, dm, sign), rtol=1e-13, atol=1e-15)
+    sparse = oracle.assembled_matrix(mats, l2g, ng, sign).diagonal()
+    np.testing.assert_allclose(d[~dmb], sparse[~dmb], rtol=1e-13, atol=1e-15)
+    np.testing.assert_array_equal(d[dmb], 1.0)
+    assert (d[~dmb] > 0).all()
+
+
+def test_jacobi_diagonal_unsigned_hex_lattice():
+    P, shape = 3, (2, 2, 2)
+    ops, _ = _warped_ops(shape, P, lam=1.3)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    _check_jacobi_diagonal(oracle.helmholtz_matrices(ops), l2g, ng, dm)
+
+
+@pytest.mark.parametrize("P", [3, 5])
+def test_jacobi_diagonal_signed_triangle_mesh(P):
+    """Signs square away on the diagonal: a negated odd-parity edge bubble
+    keeps its positive diagonal entry.  The mesh has negative signs."""
+    n = 2
+    E = 2 * n * n
+    rot = W.tri_rotations(41 + P, E)
+    ops, _, _ = _tri_affine_mesh(n, P, rot)
+    l2g, sign, ng, dm = W.tri_lattice_l2g(n, P, rot)
+    assert (np.asarray(sign) < 0).any()
+    _check_jacobi_diagonal([ops.helmholtz_matrix(e) for e in range(E)], l2g, ng, dm, sign)
+
+
+def test_jacobi_diagonal_ragged_mixed_order_map():
+    shape = (2, 2, 1)
+    perm, l2g, ng, dm, _, mats = _varp_problem(shape, [2, 4, 3, 5])
+    assert len({len(g) for g in l2g}) > 1
+    _check_jacobi_diagonal(mats, l2g, ng, dm)
