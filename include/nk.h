@@ -69,7 +69,8 @@ typedef enum {
   NK_ENOMEM = 2,        /* device allocation failed                        */
   NK_EDEVICE = 3,       /* no usable HIP device                            */
   NK_EHIP = 4,          /* a HIP runtime call failed                       */
-  NK_ENOCONV = 5,       /* CG hit maxit; x holds the last iterate          */
+  NK_ENOCONV = 5,       /* true residual above rtol when the iteration
+                           budget ran out; x holds the last iterate         */
   NK_EBREAKDOWN = 6,    /* CG breakdown (p.Ap <= 0 or non-finite)          */
   NK_EUNSUPPORTED = 7   /* (dim, P, Q) combination not compiled in         */
 } nk_status;
@@ -82,7 +83,8 @@ typedef struct nk_space_s* nk_space;
 typedef struct nk_system_s* nk_system;
 
 typedef struct {
-  int iters;             /* CG iterations (FP64 mode) or inner FP32 iterations summed */
+  int iters;             /* CG iterations summed over restarts (FP64 mode) or inner
+                            FP32 iterations summed over refinement steps            */
   int outer_iters;       /* refinement steps (FP32-refined mode), 0 otherwise          */
   double rel_resid;      /* true ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit    */
   double solve_ms;       /* wall time of the solve on the host clock                   */
@@ -329,14 +331,21 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
 
 /* Solve R A R x = b by Jacobi-preconditioned CG.  b, x: device FP64
  * [nglobal] (x: initial guess in, solution out; Dirichlet entries of x are
- * forced to zero).  Stops when the residual ||r||_2 <= rtol ||b||_2 or after
- * maxit iterations.  NK_SOLVE_F64: FP64 throughout.  NK_SOLVE_F32_REFINED:
- * the operator and CG vectors run in FP32 (dot products accumulated in FP64)
- * inside an FP64 iterative-refinement loop whose residual, dot products and
- * solution update are FP64.  Iterations run as captured HIP graphs.  info
- * (host, may be NULL) receives one entry per system (nsys entries for a
- * batched system).  Returns NK_ENOCONV / NK_EBREAKDOWN if any system did
- * not converge. */
+ * forced to zero).  NK_OK means that the true residual, recomputed in FP64
+ * from the returned x, satisfies ||b - A x||_2 <= rtol ||b||_2 for every
+ * system (info.rel_resid is that ratio).  maxit bounds the CG iterations of a
+ * system in total.  NK_SOLVE_F64: FP64 throughout; CG stops on its recursive
+ * residual, and while the true residual is still above rtol (the two drift
+ * apart by rounding) it restarts from the current x, within the budget.
+ * NK_SOLVE_F32_REFINED: the operator and CG vectors run in FP32 (dot products
+ * accumulated in FP64) inside an FP64 iterative-refinement loop whose
+ * residual, dot products and solution update are FP64; the loop ends on the
+ * true residual of the returned x, and maxit bounds the inner iterations
+ * summed over refinement steps.  Iterations run as captured HIP graphs that
+ * do not depend on rtol or maxit.  info (host, may be NULL) receives one
+ * entry per system (nsys entries for a batched system).  Returns NK_ENOCONV
+ * (budget spent with the true residual above rtol) or NK_EBREAKDOWN if any
+ * system did not converge. */
 nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double* x,
                       double rtol, int maxit, nk_solve_info* info, void* stream);
 

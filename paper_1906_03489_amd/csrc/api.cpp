@@ -826,6 +826,7 @@ static void system_free(nk_system y) {
     dfree(c->iters);
     dfree(c->status);
     dfree(c->cnt);
+    dfree(c->maxit);
   }
   dfree(y->bb);
   dfree(y->rr_true);
@@ -836,6 +837,7 @@ static void system_free(nk_system y) {
   dfree(y->outer_cnt);
   dfree(y->outer_status);
   if (y->h_flags) (void)hipHostFree(y->h_flags);
+  if (y->h_budget) (void)hipHostFree(y->h_budget);
   if (y->h_d) (void)hipHostFree(y->h_d);
   if (y->ev) (void)hipEventDestroy(y->ev);
   if (y->cs) (void)hipStreamDestroy(y->cs);
@@ -846,7 +848,8 @@ static hipError_t alloc_state(CgState& c, int n) {
   hipError_t e;
   if ((e = dmalloc(&c.rz, n)) || (e = dmalloc(&c.rr, n)) || (e = dmalloc(&c.tol2, n)) ||
       (e = dmalloc(&c.alpha, n)) || (e = dmalloc(&c.beta, n)) || (e = dmalloc(&c.done, n)) ||
-      (e = dmalloc(&c.iters, n)) || (e = dmalloc(&c.status, n)) || (e = dmalloc(&c.cnt, n)))
+      (e = dmalloc(&c.iters, n)) || (e = dmalloc(&c.status, n)) || (e = dmalloc(&c.cnt, n)) ||
+      (e = dmalloc(&c.maxit, n)))
     return e;
   return hipMemset(c.cnt, 0, n * sizeof(int32_t));
 }
@@ -971,6 +974,8 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   if ((e = alloc_state(y->st64, nsys)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = alloc_state(y->st32, nsys)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = hipHostMalloc((void**)&y->h_flags, nsys * sizeof(int32_t), 0)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostMalloc"));
+  if ((e = hipHostMalloc((void**)&y->h_budget, nsys * sizeof(int32_t), 0)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc"));
   if ((e = hipHostMalloc((void**)&y->h_d, nsys * sizeof(double), 0)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc"));
@@ -1248,9 +1253,11 @@ static double inner_tol() {
 }
 
 // One CG iteration of precision T on the system's stream: vector update,
-// assembled operator w = A u with per-element u.Au, per-system finish.
+// assembled operator w = A u with per-element u.Au, per-system finish.  The
+// iteration budget is read from device memory, so captured graphs do not
+// depend on it.
 template <typename T>
-static hipError_t cg_iteration(nk_system y, int maxit) {
+static hipError_t cg_iteration(nk_system y) {
   const bool f64 = std::is_same<T, double>::value;
   CgState& st = f64 ? y->st64 : y->st32;
   T* x = f64 ? (T*)y->x : (T*)y->d32;
@@ -1264,14 +1271,15 @@ static hipError_t cg_iteration(nk_system y, int maxit) {
   if ((e = cg_update<T>(y->L, st, x, r, u, p, s, w, dinv, y->part, y->cs))) return e;
   if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, st.done, y->cs)))
     return e;
-  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, maxit, f64, false, 0.0, nullptr,
+  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, f64, false, 0.0, nullptr,
                    nullptr, nullptr, y->cs);
 }
 
 // First step of a CG solve in precision T: r = b - w (w = A x0 or 0),
-// u = M^{-1} r, w = A u, alpha from (r,u)/(w,u).
+// u = M^{-1} r, w = A u, alpha from (r,u)/(w,u).  Systems whose skip flag is
+// set (or whose residual already meets tol2) are marked done at once.
 template <typename T>
-static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int32_t* outer_done) {
+static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int32_t* skip) {
   const bool f64 = std::is_same<T, double>::value;
   CgState& st = f64 ? y->st64 : y->st32;
   T* r = f64 ? (T*)y->r : (T*)y->r32;
@@ -1284,18 +1292,17 @@ static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int3
   if ((e = cg_start<T>(y->L, b, w, r, u, p, s, dinv, y->part, y->cs))) return e;
   if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, nullptr, y->cs)))
     return e;
-  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, 1 << 30, f64, true, tau2,
-                   outer_done, y->outer_tol2, y->outer_rr, y->cs);
+  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, f64, true, tau2, skip,
+                   y->outer_tol2, y->outer_rr, y->cs);
 }
 
 template <typename T>
-static hipError_t ensure_graph(nk_system y, int maxit) {
+static hipError_t ensure_graph(nk_system y) {
   const bool f64 = std::is_same<T, double>::value;
   hipGraphExec_t& ge = f64 ? y->g64 : y->g32;
   int& gi = f64 ? y->g64_iters : y->g32_iters;
-  int& gm = f64 ? y->g_maxit64 : y->g_maxit32;
   const int k = graph_iters();
-  if (ge && gi == k && gm == maxit) return hipSuccess;
+  if (ge && gi == k) return hipSuccess;
   if (ge) {
     (void)hipGraphExecDestroy(ge);
     ge = nullptr;
@@ -1304,7 +1311,7 @@ static hipError_t ensure_graph(nk_system y, int maxit) {
   hipError_t e = hipStreamBeginCapture(y->cs, hipStreamCaptureModeThreadLocal);
   if (e) return e;
   hipError_t e2 = hipSuccess;
-  for (int i = 0; i < k && e2 == hipSuccess; ++i) e2 = cg_iteration<T>(y, maxit);
+  for (int i = 0; i < k && e2 == hipSuccess; ++i) e2 = cg_iteration<T>(y);
   e = hipStreamEndCapture(y->cs, &g);
   if (e2) {
     if (g) (void)hipGraphDestroy(g);
@@ -1315,18 +1322,24 @@ static hipError_t ensure_graph(nk_system y, int maxit) {
   (void)hipGraphDestroy(g);
   if (e) return e;
   gi = k;
-  gm = maxit;
   return hipSuccess;
 }
 
-// Run graph launches of CG iterations until every system reports done.
+// Copy per-system iteration budgets to the device state of precision T.
+static hipError_t set_budgets(nk_system y, const CgState& st, const std::vector<int>& budget) {
+  for (int i = 0; i < y->nsys; ++i) y->h_budget[i] = budget[i];
+  return hipMemcpyAsync(st.maxit, y->h_budget, y->nsys * 4, hipMemcpyHostToDevice, y->cs);
+}
+
+// Run graph launches of CG iterations until every system reports done; the
+// largest budget bounds the number of launches.
 template <typename T>
-static hipError_t cg_loop(nk_system y, int maxit, const int32_t* done_dev) {
-  hipError_t e = ensure_graph<T>(y, maxit);
+static hipError_t cg_loop(nk_system y, int max_budget, const int32_t* done_dev) {
+  hipError_t e = ensure_graph<T>(y);
   if (e) return e;
   const hipGraphExec_t ge = std::is_same<T, double>::value ? y->g64 : y->g32;
   const int k = std::is_same<T, double>::value ? y->g64_iters : y->g32_iters;
-  const int64_t max_launch = (int64_t)maxit / k + 2;
+  const int64_t max_launch = (int64_t)max_budget / k + 2;
   for (int64_t l = 0; l < max_launch; ++l) {
     if ((e = hipGraphLaunch(ge, y->cs))) return e;
     if ((e = hipMemcpyAsync(y->h_flags, done_dev, y->nsys * 4, hipMemcpyDeviceToHost, y->cs)))
@@ -1336,6 +1349,163 @@ static hipError_t cg_loop(nk_system y, int maxit, const int32_t* done_dev) {
     for (int i = 0; i < y->nsys; ++i) all = all && y->h_flags[i] != 0;
     if (all) break;
   }
+  return hipSuccess;
+}
+
+// True FP64 residual of the current x: rr_true = ||b - A x||^2 per system
+// (r holds b - A x on free DOFs, y is left zero).
+static hipError_t true_residual(nk_system y) {
+  CgState chk;
+  chk.rr = y->rr_true;
+  chk.tol2 = y->outer_tol2;
+  chk.cnt = y->cnt_aux;
+  hipError_t e;
+  if ((e = vec_fill<double>(y->y, y->L.npad, 0.0, y->cs))) return e;
+  if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->cs))) return e;
+  return cg_residual(y->L, chk, y->b, y->y, y->dinv64, y->r, nullptr, y->part, y->cs);
+}
+
+// Relative residual as reported in nk_solve_info; convergence decisions on
+// the host use this same expression, so NK_OK implies rel_resid <= rtol.
+static double rel_of(double rr, double bb) { return bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr); }
+
+// Read an nsys-long device array through the pinned staging buffer.
+template <typename V>
+static hipError_t read_sys(nk_system y, const V* dev, std::vector<V>& out) {
+  out.resize(y->nsys);
+  V* h = sizeof(V) == 8 ? (V*)y->h_d : (V*)y->h_flags;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h, dev, y->nsys * sizeof(V), hipMemcpyDeviceToHost, y->cs))) return e;
+  if ((e = hipStreamSynchronize(y->cs))) return e;
+  for (int i = 0; i < y->nsys; ++i) out[i] = h[i];
+  return hipSuccess;
+}
+
+// FP64 CG restarted from the current x while the true residual of a system
+// is above rtol and its budget lasts: the recursive residual the iteration
+// stops on drifts from b - A x by rounding, so one restart (a few
+// iterations) usually closes the gap.  On return rr_true holds each system's
+// true squared residual and stat its status.
+static hipError_t solve_f64(nk_system y, double rtol, int maxit, std::vector<int>& iters,
+                            std::vector<int32_t>& stat, std::vector<double>& rr) {
+  const int ns = y->nsys;
+  const int kMaxPasses = 8;
+  std::vector<double> bb;
+  std::vector<int32_t> it_dev, st_dev;
+  std::vector<int> budget(ns, maxit);
+  std::vector<char> fin(ns, 0);
+  hipError_t e;
+  if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->st64.tol2, y->cs))) return e;
+  if ((e = vec_fill<int32_t>(y->outer_done, ns, 0, y->cs))) return e;
+  if ((e = read_sys(y, y->bb, bb))) return e;
+  stat.assign(ns, NK_OK);
+  for (int pass = 0; pass < kMaxPasses; ++pass) {
+    int maxb = 0;
+    for (int i = 0; i < ns; ++i) {
+      budget[i] = fin[i] ? 0 : maxit - iters[i];
+      maxb = std::max(maxb, budget[i]);
+    }
+    if ((e = set_budgets(y, y->st64, budget))) return e;
+    if ((e = vec_fill<double>(y->y, y->L.npad, 0.0, y->cs))) return e;
+    if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->cs))) return e;
+    if ((e = cg_begin<double>(y, y->b, 0.0, y->outer_done))) return e;
+    if ((e = cg_loop<double>(y, maxb, y->st64.done))) return e;
+    if ((e = read_sys(y, y->st64.iters, it_dev)) || (e = read_sys(y, y->st64.status, st_dev)))
+      return e;
+    if ((e = true_residual(y)) || (e = read_sys(y, y->rr_true, rr))) return e;
+    bool again = false;
+    for (int i = 0; i < ns; ++i) {
+      if (fin[i]) continue;
+      iters[i] += it_dev[i];
+      const bool met = rel_of(rr[i], bb[i]) <= rtol;
+      if (st_dev[i] != NK_OK || met || iters[i] >= maxit) {
+        fin[i] = 1;
+        stat[i] = st_dev[i] != NK_OK ? st_dev[i] : met ? NK_OK : NK_ENOCONV;
+      } else {
+        again = true;
+      }
+    }
+    if (!again) break;
+    for (int i = 0; i < ns; ++i) y->h_budget[i] = fin[i];
+    if ((e = hipMemcpyAsync(y->outer_done, y->h_budget, ns * 4, hipMemcpyHostToDevice, y->cs)) ||
+        (e = hipStreamSynchronize(y->cs)))
+      return e;
+  }
+  for (int i = 0; i < ns; ++i)
+    if (!fin[i]) stat[i] = NK_ENOCONV;
+  return hipSuccess;
+}
+
+// FP64 iterative refinement around an FP32 inner CG.  maxit bounds the
+// inner iterations summed over refinement steps; a system whose budget runs
+// out gets an infinite outer tolerance (so it is skipped from then on) and
+// status NK_ENOCONV.  The outer residual that ends the loop is the true FP64
+// residual of the returned x (x does not change after it), left in rr_true.
+static hipError_t solve_refined(nk_system y, double rtol, int maxit, std::vector<int>& iters,
+                                std::vector<int>& outer, std::vector<int32_t>& stat,
+                                std::vector<double>& rr) {
+  const int ns = y->nsys;
+  const int64_t np = y->L.npad;
+  hipStream_t cs = y->cs;
+  CgState outer_st;
+  outer_st.rr = y->outer_rr;
+  outer_st.tol2 = y->outer_tol2;
+  outer_st.done = y->outer_done;
+  outer_st.status = y->outer_status;
+  outer_st.cnt = y->outer_cnt;
+  std::vector<double> bb;
+  std::vector<int32_t> done, it_dev;
+  std::vector<int> budget(ns, 0);
+  std::vector<char> spent(ns, 0);
+  hipError_t e;
+  // the device stops on rr <= (rtol (1 - 1e-14))^2 ||b||^2, a hair inside
+  // the host's rel_of(rr, bb) <= rtol, so the two never disagree by rounding
+  const double rtol_dev = rtol * (1.0 - 1e-14);
+  if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol_dev, y->outer_tol2, cs)))
+    return e;
+  if ((e = read_sys(y, y->bb, bb))) return e;
+  const double tau = inner_tol();
+  const int max_outer = 60;
+  bool all = false;
+  for (int k = 0; k <= max_outer; ++k) {
+    if ((e = vec_fill<double>(y->y, np, 0.0, cs))) return e;
+    if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) return e;
+    if ((e = cg_residual(y->L, outer_st, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs)))
+      return e;
+    if ((e = read_sys(y, y->outer_done, done))) return e;
+    all = true;
+    int maxb = 0;
+    for (int i = 0; i < ns; ++i) {
+      all = all && done[i] != 0;
+      budget[i] = done[i] ? 0 : maxit - iters[i];
+      maxb = std::max(maxb, budget[i]);
+    }
+    if (all || k == max_outer) break;
+    for (int i = 0; i < ns; ++i)
+      if (!done[i]) outer[i] += 1;
+    if ((e = set_budgets(y, y->st32, budget))) return e;
+    if ((e = vec_fill<float>(y->d32, np, 0.f, cs))) return e;
+    if ((e = vec_fill<float>(y->y32, np, 0.f, cs))) return e;
+    if ((e = cg_begin<float>(y, y->r, tau * tau, y->outer_done))) return e;
+    if ((e = cg_loop<float>(y, maxb, y->st32.done))) return e;
+    if ((e = read_sys(y, y->st32.iters, it_dev))) return e;
+    bool newly_spent = false;
+    for (int i = 0; i < ns; ++i) {
+      if (done[i]) continue;
+      iters[i] += it_dev[i];
+      if (iters[i] >= maxit && !spent[i]) spent[i] = newly_spent = true;
+    }
+    if ((e = cg_correct(y->L, y->outer_done, y->d32, y->x, cs))) return e;
+    if (newly_spent) {
+      // out of budget: this system's x is final after the correction above
+      for (int i = 0; i < ns; ++i) y->h_d[i] = spent[i] ? HUGE_VAL : rtol_dev * rtol_dev * bb[i];
+      if ((e = hipMemcpyAsync(y->outer_tol2, y->h_d, ns * 8, hipMemcpyHostToDevice, cs))) return e;
+      if ((e = hipStreamSynchronize(cs))) return e;
+    }
+  }
+  if ((e = read_sys(y, y->outer_rr, rr))) return e;
+  stat.assign(ns, NK_OK);
+  for (int i = 0; i < ns; ++i) stat[i] = rel_of(rr[i], bb[i]) <= rtol ? NK_OK : NK_ENOCONV;
   return hipSuccess;
 }
 
@@ -1351,95 +1521,33 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
   hipStream_t us = (hipStream_t)stream;
   hipStream_t cs = y->cs;
   const int ns = y->nsys;
-  const int64_t np = y->L.npad;
   std::vector<int> iters(ns, 0), outer(ns, 0);
+  std::vector<int32_t> stat;
+  std::vector<double> rr, bbv;
   hipError_t e = hipSuccess;
   // order the private stream after the caller's work
   if ((e = hipEventRecord(y->ev, us)) || (e = hipStreamWaitEvent(cs, y->ev, 0)))
     return hip_fail(e, "stream ordering");
-  CgState outer_st;
-  outer_st.rr = y->outer_rr;
-  outer_st.tol2 = y->outer_tol2;
-  outer_st.done = y->outer_done;
-  outer_st.status = y->outer_status;
-  outer_st.cnt = y->outer_cnt;
   do {
     if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, b, y->dinv64, y->b, cs))) break;
     if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, x, y->dinv64, y->x, cs))) break;
-    if (mode == NK_SOLVE_F64) {
-      if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->st64.tol2, cs))) break;
-      if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
-      if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) break;
-      if ((e = cg_begin<double>(y, y->b, 0.0, nullptr))) break;
-      if ((e = cg_loop<double>(y, maxit, y->st64.done))) break;
-      if ((e = hipMemcpyAsync(y->h_flags, y->st64.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
-      if ((e = hipStreamSynchronize(cs))) break;
-      for (int i = 0; i < ns; ++i) iters[i] = y->h_flags[i];
-    } else {
-      // FP64 outer refinement around an FP32 inner CG
-      if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, y->outer_tol2, cs))) break;
-      if ((e = vec_fill<int32_t>(y->outer_status, ns, 0, cs))) break;
-      if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
-      const double tau = inner_tol();
-      const int max_outer = 60;
-      int k = 0;
-      for (; k < max_outer; ++k) {
-        if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) break;
-        if ((e = cg_residual(y->L, outer_st, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs)))
-          break;
-        if ((e = hipMemcpyAsync(y->h_flags, y->outer_done, ns * 4, hipMemcpyDeviceToHost, cs))) break;
-        if ((e = hipStreamSynchronize(cs))) break;
-        bool all = true;
-        for (int i = 0; i < ns; ++i) {
-          all = all && y->h_flags[i] != 0;
-          if (!y->h_flags[i]) outer[i] += 1;
-        }
-        if (all) break;
-        if ((e = vec_fill<float>(y->d32, np, 0.f, cs))) break;
-        if ((e = vec_fill<float>(y->y32, np, 0.f, cs))) break;
-        if ((e = cg_begin<float>(y, y->r, tau * tau, y->outer_done))) break;
-        if ((e = cg_loop<float>(y, maxit, y->st32.done))) break;
-        if ((e = hipMemcpyAsync(y->h_flags, y->st32.iters, ns * 4, hipMemcpyDeviceToHost, cs))) break;
-        if ((e = hipStreamSynchronize(cs))) break;
-        for (int i = 0; i < ns; ++i) iters[i] += y->h_flags[i];
-        if ((e = cg_correct(y->L, y->outer_done, y->d32, y->x, cs))) break;
-      }
-      if (e) break;
-      if (k == max_outer) {
-        // mark systems that never reached the tolerance
-        if ((e = hipMemcpyAsync(y->h_flags, y->outer_done, ns * 4, hipMemcpyDeviceToHost, cs))) break;
-        if ((e = hipStreamSynchronize(cs))) break;
-      }
-    }
-    // true residual in FP64
-    CgState chk;
-    chk.rr = y->rr_true;
-    chk.tol2 = y->outer_tol2;
-    chk.cnt = y->cnt_aux;
-    if ((e = vec_fill<double>(y->y, np, 0.0, cs))) break;
-    if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) break;
-    if ((e = cg_residual(y->L, chk, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs))) break;
+    if (mode == NK_SOLVE_F64)
+      e = solve_f64(y, rtol, maxit, iters, stat, rr);
+    else
+      e = solve_refined(y, rtol, maxit, iters, outer, stat, rr);
+    if (e) break;
+    if ((e = read_sys(y, y->bb, bbv))) break;
     if ((e = pad_out<double>(ns, y->d_dof_off, y->d_pdof_off, y->nuser, y->x, x, cs))) break;
     if ((e = hipEventRecord(y->ev, cs)) || (e = hipStreamWaitEvent(us, y->ev, 0))) break;
     e = hipStreamSynchronize(cs);
   } while (0);
   if (e != hipSuccess) return hip_fail(e, "cg solve");
-  // collect per-system results
-  std::vector<double> rr(ns), bbv(ns);
-  std::vector<int32_t> stat(ns);
-  if ((e = hipMemcpy(rr.data(), y->rr_true, ns * 8, hipMemcpyDeviceToHost)) ||
-      (e = hipMemcpy(bbv.data(), y->bb, ns * 8, hipMemcpyDeviceToHost)) ||
-      (e = hipMemcpy(stat.data(), mode == NK_SOLVE_F64 ? y->st64.status : y->outer_status, ns * 4,
-                     hipMemcpyDeviceToHost)))
-    return hip_fail(e, "cg solve");
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   nk_status worst = NK_OK;
   for (int i = 0; i < ns; ++i) {
-    const double rel = bbv[i] > 0.0 ? std::sqrt(rr[i] / bbv[i]) : std::sqrt(rr[i]);
-    int sti = stat[i];
-    if (sti == NK_OK && mode == NK_SOLVE_F32_REFINED && !(rel <= rtol * 1.0000001)) sti = NK_ENOCONV;
-    if (sti == NK_OK && mode == NK_SOLVE_F64 && iters[i] >= maxit && !(rel <= rtol)) sti = NK_ENOCONV;
+    const double rel = rel_of(rr[i], bbv[i]);
+    const int sti = stat[i];
     if (info) {
       info[i].iters = iters[i];
       info[i].outer_iters = mode == NK_SOLVE_F32_REFINED ? outer[i] : 0;

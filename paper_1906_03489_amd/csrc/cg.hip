@@ -186,7 +186,7 @@ hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p,
 __global__ void __launch_bounds__(kFinThreads)
     k_cg_finish(const int64_t* __restrict__ blk_first, const int64_t* __restrict__ dblk_first,
                 const double* __restrict__ part, const double* __restrict__ dots, CgState st,
-                int maxit, int fatal, int start, double tau2, const int32_t* __restrict__ outer_done,
+                int fatal, int start, double tau2, const int32_t* __restrict__ outer_done,
                 const double* __restrict__ outer_tol2, const double* __restrict__ outer_rr) {
   __shared__ double sh[3 * (kFinThreads / 64)];
   const int sg = blockIdx.x;
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(kFinThreads)
     st.status[sg] = NK_EBREAKDOWN;
     return;
   }
-  if (it >= maxit) {
+  if (it >= st.maxit[sg]) {
     st.done[sg] = 1;
     if (fatal) st.status[sg] = NK_ENOCONV;
     return;
@@ -287,11 +287,11 @@ __global__ void __launch_bounds__(kFinThreads)
 }
 
 hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
-                     const double* dots, CgState st, int maxit, bool fatal, bool start,
+                     const double* dots, CgState st, bool fatal, bool start,
                      double tau2, const int32_t* outer_done, const double* outer_tol2,
                      const double* outer_rr, hipStream_t stream) {
   hipLaunchKernelGGL(k_cg_finish, dim3(nsys), dim3(kFinThreads), 0, stream, L.blk_first,
-                     Ld.blk_first, part, dots, st, maxit, fatal ? 1 : 0, start ? 1 : 0, tau2,
+                     Ld.blk_first, part, dots, st, fatal ? 1 : 0, start ? 1 : 0, tau2,
                      outer_done, outer_tol2, outer_rr);
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@ struct CgState {
   int32_t* iters = nullptr;
   int32_t* status = nullptr;
   int32_t* cnt = nullptr;   // finished-block counter of the fused reduction
+  int32_t* maxit = nullptr; // iteration budget of the current CG run (device, per system)
 };
 
 // Vector-kernel geometry: DOF ranges of every system are padded to multiples
@@ -40,7 +41,7 @@ template <typename T>
 hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p, T* s,
                     const T* dinv, double* part, hipStream_t stream);
 hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
-                     const double* dots, CgState st, int maxit, bool fatal, bool start,
+                     const double* dots, CgState st, bool fatal, bool start,
                      double tau2, const int32_t* outer_done, const double* outer_tol2,
                      const double* outer_rr, hipStream_t stream);
 
@@ -126,10 +127,11 @@ struct nk_system_s {
   int32_t* outer_status = nullptr;
   // host staging (pinned)
   int32_t* h_flags = nullptr;             // nsys
+  int32_t* h_budget = nullptr;            // nsys: iteration budgets on their way to the device
   double* h_d = nullptr;                  // nsys
   hipStream_t cs = nullptr;               // private stream (graphs are captured here)
   hipEvent_t ev = nullptr;
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
-  int g64_iters = 0, g32_iters = 0, g_maxit64 = -1, g_maxit32 = -1;
+  int g64_iters = 0, g32_iters = 0;
   std::vector<int> tiles64, tiles32;   // assembled-operator tile per order group
 };

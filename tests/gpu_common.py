@@ -64,3 +64,33 @@ def assert_close(y, ref, rtol, what=""):
     m = np.abs(np.asarray(ref)).max()
     assert d <= 100 * rtol * max(m, 1e-300), f"{what}: max abs diff {d:.3e} vs max {m:.3e}"
     return e
+
+
+U64 = 2.0 ** -53
+
+
+def residual_allowance(mats, l2g, nglobal, dirichlet, x, b):
+    """Rounding scale of one FP64 evaluation of ||b - A x|| / ||b||.
+
+    Each entry of A x is a sum of k products (k = local modes per element
+    times the elements meeting at a vertex, 8); its rounding error is about
+    sqrt(k) u (|A| |x|)_i at most in the probabilistic model (u = 2^-53), so
+    two independent evaluations (the library's and the oracle's) of the
+    relative residual differ by at most 2 sqrt(k) u |||A||x|||_2 / ||b||_2.
+    The library's NK_OK guarantees its own value <= rtol; the oracle's may
+    exceed rtol by this much and no more."""
+    from oracle.assembly import MaskedOperator
+    k = max(np.shape(H)[1] for H in mats) * 8
+    absA = MaskedOperator([np.abs(H) for H in mats], l2g, nglobal, dirichlet)
+    return 2.0 * np.sqrt(k) * U64 * np.linalg.norm(absA(np.abs(x))) / np.linalg.norm(b)
+
+
+def assert_true_residual(info, rtol, A, mats, l2g, nglobal, dirichlet, x, b, what=""):
+    """NK_OK, the library's true residual <= rtol exactly, and the oracle's
+    own residual of x <= rtol up to the rounding of one evaluation."""
+    assert info["status"] == 0, f"{what}: status {info['status']}"
+    assert info["rel_resid"] <= rtol, f"{what}: library residual {info['rel_resid']:.3e} > {rtol:.1e}"
+    res = np.linalg.norm(b - A(x)) / np.linalg.norm(b)
+    allow = residual_allowance(mats, l2g, nglobal, dirichlet, x, b)
+    assert res <= rtol + allow, f"{what}: oracle residual {res:.3e} > {rtol:.1e} + {allow:.1e}"
+    return res

@@ -9,7 +9,8 @@ import pytest
 import oracle
 import workloads as W
 from oracle import collapsed as C
-from gpu_common import FP32_RTOL, FP64_RTOL, assert_close, nk, rel_err, to_dev, torch_cuda
+from gpu_common import (FP32_RTOL, FP64_RTOL, assert_close, assert_true_residual, nk, rel_err, to_dev,
+                        torch_cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -191,9 +192,8 @@ def test_tetrahedral_cg_solves_match_direct_solve(P):
     xref = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b)
     x, info = c["sys"].solve(to_dev(b), rtol=1e-12, maxit=20000)
     xs = x.cpu().numpy()
-    assert info[0]["status"] == 0
-    assert np.linalg.norm(b - A(xs)) / np.linalg.norm(b) <= 1e-11
+    assert_true_residual(info[0], 1e-12, A, c["mats"], c["l2g"], c["ng"], c["dm"], xs, b, "f64")
     assert rel_err(xs, xref) < 1e-8
     xr, info = c["sys"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_F32_REFINED)
-    assert info[0]["status"] == 0
-    assert np.linalg.norm(b - A(xr.cpu().numpy())) / np.linalg.norm(b) <= 1.2e-10
+    assert_true_residual(info[0], 1e-10, A, c["mats"], c["l2g"], c["ng"], c["dm"],
+                         xr.cpu().numpy(), b, "refined")
