@@ -318,6 +318,19 @@ nk_status nk_system_destroy(nk_system sys);
  * given precision.  x, y: device [nglobal] of type t. */
 nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* y, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = R A R x as nk_system_apply, same kernels and arguments, but the padded
+ * input and output staging lives in a static device array of the library
+ * (64 MiB per GPU, held until the process ends) instead of the system's work
+ * vectors.  The call allocates nothing, does not synchronise (it is ordered
+ * on `stream` only) and needs the system's device to be current.  Limit:
+ * 2 x padded DOFs x scalar size <= 64 MiB (4 Mi padded DOFs in FP64, 8 Mi in
+ * FP32); larger systems return NK_EINVAL with the sizes in nk_last_error.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams or threads without ordering between them) race. */
+nk_status nk_system_apply_noalloc(nk_system sys, nk_dtype t, const void* x, void* y, void* stream);
+
 /* b = R (sum_e A_e^T y_loc_e): scatter-add of local vectors into the global
  * numbering with Dirichlet entries zeroed.  FP64 device arrays. */
 nk_status nk_assemble(nk_system sys, const double* y_loc, double* b, void* stream);

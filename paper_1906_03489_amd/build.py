@@ -45,7 +45,8 @@ def _obj(src: str, defs) -> str:
 
 def _compile(src, defs):
     obj = _obj(src, defs)
-    flags = COMMON + (DEVICE if src.endswith(".hip") else []) + list(defs)
+    # hipcc compiles .cpp sources as HIP too (api.cpp holds a device array)
+    flags = COMMON + DEVICE + list(defs)
     cmd = [hipcc()] + flags + ["-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)

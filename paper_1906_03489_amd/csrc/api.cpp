@@ -1194,6 +1194,81 @@ nk_status nk_system_apply(nk_system sys, nk_dtype t, const void* x, void* yv, vo
   return NK_OK;
 }
 
+// ------------------------------------------------ allocation-free apply
+// Staging of nk_system_apply_noalloc: the padded input and output vectors of
+// the assembled operator live in this file-scope device array instead of the
+// system's work vectors.  Each GPU the library runs on holds its own copy
+// (kScratchBytes) until the process ends.  Host code never passes `scratch`
+// itself to a kernel: its device address is looked up once per device
+// (scratch_base) and only that address is used.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kScratchMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, looked up on the
+// first call on that device (with it current) and kept.
+static nk_status scratch_base(int dev, void** out) {
+  if (dev < 0 || dev >= kScratchMaxDevices) return fail(NK_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(NK_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return NK_OK;
+}
+
+nk_status nk_system_apply_noalloc(nk_system sys, nk_dtype t, const void* x, void* yv,
+                                  void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  if (t != NK_F64 && t != NK_F32) return fail(NK_EINVAL, "bad dtype");
+  NK_CHECK(check_buf(x, sys->nuser * dsize(t), "x"));
+  NK_CHECK(check_buf(yv, sys->nuser * dsize(t), "y"));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != sys->device)
+    return fail(NK_EINVAL, "the system's device must be current (system on device " +
+                               std::to_string(sys->device) + ", current " + std::to_string(dev) + ")");
+  const int64_t np = sys->L.npad;
+  const size_t need = 2 * (size_t)np * dsize(t);
+  if (need > kScratchBytes)
+    return fail(NK_EINVAL, "system too large for the static scratch: needs " + std::to_string(need) +
+                               " bytes (two padded vectors of " + std::to_string(np) +
+                               " entries), the maximum is " + std::to_string(kScratchBytes) +
+                               " bytes");
+  void* base = nullptr;
+  NK_CHECK(scratch_base(dev, &base));
+  hipStream_t st = (hipStream_t)stream;
+  if (t == NK_F64) {
+    double* xin = (double*)base;
+    double* yout = xin + np;
+    if ((e = pad_in<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, (const double*)x,
+                            sys->dinv64, xin, st)) ||
+        (e = vec_fill<double>(yout, np, 0.0, st)) ||
+        (e = sys_op(sys, t, xin, yout, nullptr, nullptr, st)) ||
+        (e = pad_out<double>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, yout,
+                             (double*)yv, st)))
+      return hip_fail(e, "system apply (no allocation)");
+  } else {
+    float* xin = (float*)base;
+    float* yout = xin + np;
+    if ((e = pad_in<float>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->L, (const float*)x,
+                           sys->dinv64, xin, st)) ||
+        (e = vec_fill<float>(yout, np, 0.f, st)) ||
+        (e = sys_op(sys, t, xin, yout, nullptr, nullptr, st)) ||
+        (e = pad_out<float>(sys->nsys, sys->d_dof_off, sys->d_pdof_off, sys->nuser, yout,
+                            (float*)yv, st)))
+      return hip_fail(e, "system apply (no allocation)");
+  }
+  return NK_OK;
+}
+
 nk_status nk_assemble(nk_system sys, const double* y_loc, double* b, void* stream) {
   if (!sys) return fail(NK_EINVAL, "system is NULL");
   nk_space s = sys->space;

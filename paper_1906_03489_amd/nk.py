@@ -29,8 +29,8 @@ EXPORTS = [
     "nk_last_error", "nk_version", "nk_device_count", "nk_basis_tables", "nk_space_create",
     "nk_space_create_varp", "nk_space_destroy", "nk_space_sizes", "nk_bwd_trans",
     "nk_iprod_wrt_base", "nk_helmholtz", "nk_helmholtz_weak_rhs", "nk_system_create",
-    "nk_system_create_batched", "nk_system_create_signed", "nk_system_destroy", "nk_system_apply", "nk_assemble",
-    "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
+    "nk_system_create_batched", "nk_system_create_signed", "nk_system_destroy", "nk_system_apply",
+    "nk_system_apply_noalloc", "nk_assemble", "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
     "nk_tri_points", "nk_space_create_tri", "nk_tet_points", "nk_space_create_tet",
@@ -85,6 +85,7 @@ def lib():
         "nk_system_create_signed": (i32, [pp, vp, i64, vp, vp, vp, vp, dbl, vp]),
         "nk_system_destroy": (i32, [vp]),
         "nk_system_apply": (i32, [vp, i32, vp, vp, vp]),
+        "nk_system_apply_noalloc": (i32, [vp, i32, vp, vp, vp]),
         "nk_assemble": (i32, [vp, vp, vp, vp]),
         "nk_gather": (i32, [vp, vp, vp, vp]),
         "nk_system_diagonal": (i32, [vp, vp, vp]),
@@ -440,6 +441,13 @@ class System:
         td = _tdtype(dtype)
         y = _out(y, self.nglobal, td, x.device)
         _check(lib().nk_system_apply(self.handle, dtype, _ptr(x, td, "x"), _ptr(y, td, "y"), _stream()))
+        return y
+
+    def apply_noalloc(self, x, y, dtype=F64):
+        """nk_system_apply_noalloc: y must be given (the call allocates nothing)."""
+        td = _tdtype(dtype)
+        _check(lib().nk_system_apply_noalloc(self.handle, dtype, _ptr(x, td, "x"), _ptr(y, td, "y"),
+                                             _stream()))
         return y
 
     def assemble(self, y_loc, b=None):
