@@ -362,6 +362,26 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
 nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double* x,
                       double rtol, int maxit, nk_solve_info* info, void* stream);
 
+/* Several separately created systems (their own spaces, orders and maps)
+ * solved in one call, as nk_cg_solve solves each: sys, b, x are host arrays
+ * of nsys entries (b[k], x[k]: device FP64 [nglobal of system k]); info
+ * (host, may be NULL) receives one entry per system, NK_OK meaning the same
+ * per-system true-residual criterion.  One-system hexahedral/quadrilateral
+ * systems of one (dim, P, Q) are solved together as one batched system (the
+ * library concatenates their factors, maps and coefficients into a cached
+ * union), so each CG iteration runs one assembled-operator launch per order
+ * class with per-system CG scalars, in captured HIP graphs; other systems
+ * (mixed-order, collapsed shapes, already batched: their entry reports the
+ * sub-system with the largest residual) run alongside, each on its own
+ * stream.  The union of a member list is built on first use (a copy of the
+ * members' factors: device memory comparable to their spaces) and kept for
+ * later calls with the same list, at most four lists, until a member is
+ * destroyed.  A system may appear once per call; all must live on the
+ * current device.  Synchronises like nk_cg_solve. */
+nk_status nk_cg_solve_batched(nk_system* sys, int nsys, nk_solve_mode mode,
+                              const double* const* b, double* const* x, double rtol, int maxit,
+                              nk_solve_info* info, void* stream);
+
 /* Adjoint-gradient kernel for a loss of a Helmholtz solve: with u_loc and
  * z_loc the local (gathered) forward and adjoint solutions, writes
  *   dkappa[e][k] = -w_k detJ_k (grad_xi z)^T G (grad_xi u) at point k,

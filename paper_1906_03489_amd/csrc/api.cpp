@@ -16,6 +16,8 @@
 #include <numeric>
 #include <sstream>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "nk_internal.h"
@@ -1113,8 +1115,11 @@ nk_status nk_system_create(nk_system* out, nk_space s, int64_t nglobal, const in
   return nk_system_create_batched(out, s, 1, eo, dofo, l2g, dirichlet, lambda, lambda0, stream);
 }
 
+static void union_forget(nk_system y);
+
 nk_status nk_system_destroy(nk_system sys) {
   if (!sys) return fail(NK_EINVAL, "system is NULL");
+  union_forget(sys);
   system_free(sys);
   return NK_OK;
 }
@@ -1584,21 +1589,51 @@ static hipError_t solve_refined(nk_system y, double rtol, int maxit, std::vector
   return hipSuccess;
 }
 
-nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* x, double rtol,
-                      int maxit, nk_solve_info* info, void* stream) {
-  if (!y) return fail(NK_EINVAL, "system is NULL");
+// Per-system results of one solve of a (possibly batched) system.
+struct SolveOut {
+  std::vector<int> iters, outer;
+  std::vector<int32_t> stat;
+  std::vector<double> rr, bb;
+};
+
+// Solve on the padded work vectors y->b (right-hand side) and y->x (initial
+// guess, then solution), already filled, on the system's private stream.
+static hipError_t solve_padded(nk_system y, nk_solve_mode mode, double rtol, int maxit,
+                               SolveOut& o) {
+  o.iters.assign(y->nsys, 0);
+  o.outer.assign(y->nsys, 0);
+  hipError_t e = mode == NK_SOLVE_F64 ? solve_f64(y, rtol, maxit, o.iters, o.stat, o.rr)
+                                      : solve_refined(y, rtol, maxit, o.iters, o.outer, o.stat, o.rr);
+  if (e) return e;
+  return read_sys(y, y->bb, o.bb);
+}
+
+static nk_status check_solve_args(nk_solve_mode mode, double rtol, int maxit) {
   if (mode != NK_SOLVE_F64 && mode != NK_SOLVE_F32_REFINED) return fail(NK_EINVAL, "bad mode");
   if (!(rtol > 0.0) || rtol >= 1.0) return fail(NK_EINVAL, "rtol must be in (0, 1)");
   if (maxit < 1) return fail(NK_EINVAL, "maxit must be >= 1");
+  return NK_OK;
+}
+
+static void fill_info(nk_solve_info* info, const SolveOut& o, int i, nk_solve_mode mode, double ms) {
+  info->iters = o.iters[i];
+  info->outer_iters = mode == NK_SOLVE_F32_REFINED ? o.outer[i] : 0;
+  info->rel_resid = rel_of(o.rr[i], o.bb[i]);
+  info->solve_ms = ms;
+  info->status = o.stat[i];
+}
+
+nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* x, double rtol,
+                      int maxit, nk_solve_info* info, void* stream) {
+  if (!y) return fail(NK_EINVAL, "system is NULL");
+  NK_CHECK(check_solve_args(mode, rtol, maxit));
   NK_CHECK(check_buf(b, y->nuser * 8, "b"));
   NK_CHECK(check_buf(x, y->nuser * 8, "x"));
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t us = (hipStream_t)stream;
   hipStream_t cs = y->cs;
   const int ns = y->nsys;
-  std::vector<int> iters(ns, 0), outer(ns, 0);
-  std::vector<int32_t> stat;
-  std::vector<double> rr, bbv;
+  SolveOut o;
   hipError_t e = hipSuccess;
   // order the private stream after the caller's work
   if ((e = hipEventRecord(y->ev, us)) || (e = hipStreamWaitEvent(cs, y->ev, 0)))
@@ -1606,12 +1641,7 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
   do {
     if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, b, y->dinv64, y->b, cs))) break;
     if ((e = pad_in<double>(ns, y->d_dof_off, y->d_pdof_off, y->L, x, y->dinv64, y->x, cs))) break;
-    if (mode == NK_SOLVE_F64)
-      e = solve_f64(y, rtol, maxit, iters, stat, rr);
-    else
-      e = solve_refined(y, rtol, maxit, iters, outer, stat, rr);
-    if (e) break;
-    if ((e = read_sys(y, y->bb, bbv))) break;
+    if ((e = solve_padded(y, mode, rtol, maxit, o))) break;
     if ((e = pad_out<double>(ns, y->d_dof_off, y->d_pdof_off, y->nuser, y->x, x, cs))) break;
     if ((e = hipEventRecord(y->ev, cs)) || (e = hipStreamWaitEvent(us, y->ev, 0))) break;
     e = hipStreamSynchronize(cs);
@@ -1621,16 +1651,303 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   nk_status worst = NK_OK;
   for (int i = 0; i < ns; ++i) {
-    const double rel = rel_of(rr[i], bbv[i]);
-    const int sti = stat[i];
-    if (info) {
-      info[i].iters = iters[i];
-      info[i].outer_iters = mode == NK_SOLVE_F32_REFINED ? outer[i] : 0;
-      info[i].rel_resid = rel;
-      info[i].solve_ms = ms;
-      info[i].status = sti;
+    if (info) fill_info(info + i, o, i, mode, ms);
+    if (o.stat[i] != NK_OK && worst == NK_OK) worst = (nk_status)o.stat[i];
+  }
+  if (worst != NK_OK)
+    return fail(worst, worst == NK_EBREAKDOWN ? "CG breakdown" : "CG did not converge");
+  return NK_OK;
+}
+
+// ------------------------------------------- batched solve of separate systems
+// Systems created separately (their own spaces, orders and maps) solved in one
+// call.  One-system hexahedral / quadrilateral systems of one (dim, P, Q) form
+// a class; a class of two or more is solved as one batched union system
+// (their factors, maps, masks and coefficients concatenated into a library-
+// owned space and system), so each CG iteration runs one operator launch per
+// class with per-system scalars, captured in HIP graphs.  Other systems
+// (mixed-order, collapsed shapes, already batched) run as their own lanes.
+// Lanes run concurrently, each on its own private stream.  Unions are cached
+// by their member list (at most kMaxUnions, least recently used dropped) and
+// freed when a member is destroyed.
+namespace {
+struct UnionLane {
+  std::vector<nk_system> members;
+  nk_space space = nullptr;
+  nk_system sys = nullptr;
+};
+std::mutex g_union_mu;
+std::vector<UnionLane*> g_unions;   // least recently used first
+constexpr size_t kMaxUnions = 4;
+}  // namespace
+
+static void union_free(UnionLane* u) {
+  if (!u) return;
+  system_free(u->sys);
+  space_free(u->space);
+  delete u;
+}
+
+// Drop every cached union that holds system y (called on destroy).
+static void union_forget(nk_system y) {
+  std::lock_guard<std::mutex> lk(g_union_mu);
+  for (size_t i = 0; i < g_unions.size();) {
+    UnionLane* u = g_unions[i];
+    if (std::find(u->members.begin(), u->members.end(), y) != u->members.end()) {
+      union_free(u);
+      g_unions.erase(g_unions.begin() + i);
+    } else {
+      ++i;
     }
-    if (sti != NK_OK && worst == NK_OK) worst = (nk_status)sti;
+  }
+}
+
+static bool union_member_ok(nk_system y) {
+  return y->nsys == 1 && y->space->shape == 0 && y->space->groups.size() == 1;
+}
+
+// Build the union of members (same dim, P, Q; one system each) on stream st.
+static nk_status union_build(const std::vector<nk_system>& mem, hipStream_t st, UnionLane** out) {
+  const int m = (int)mem.size();
+  const nk_space s0 = mem[0]->space;
+  const Group& G0 = s0->groups[0];
+  std::vector<int64_t> eoff(m + 1, 0), doff(m + 1, 0), coff(m + 1, 0);
+  int64_t nfac = 0;
+  bool per_elem_lam = false;
+  for (int k = 0; k < m; ++k) {
+    const nk_space sk = mem[k]->space;
+    eoff[k + 1] = eoff[k] + sk->nelem;
+    doff[k + 1] = doff[k] + mem[k]->nuser;
+    coff[k + 1] = coff[k] + sk->ncoeff;
+    nfac += sk->nfac;
+    if (mem[k]->lam || mem[k]->lam0 != mem[0]->lam0) per_elem_lam = true;
+  }
+  if (doff[m] >= ((int64_t)1 << 30)) return fail(NK_EINVAL, "batched systems: too many global DOFs");
+  UnionLane* u = new UnionLane();
+  u->members = mem;
+  nk_space s = new nk_space_s();
+  u->space = s;
+  s->dim = s0->dim;
+  s->shape = 0;
+  s->device = s0->device;
+  Group G;
+  G.P = G0.P;
+  G.Q = G0.Q;
+  G.n = G0.n;
+  G.nelem = eoff[m];
+  s->groups.push_back(G);
+  s->nelem = eoff[m];
+  s->ncoeff = coff[m];
+  s->npoint = eoff[m] * ipow(G.Q, s->dim);
+  s->nfac = nfac;
+  int32_t* l2g = nullptr;
+  int8_t* sign = nullptr;
+  uint8_t* dir = nullptr;
+  double* lam = nullptr;
+  auto done = [&](nk_status stt) {
+    dfree(l2g);
+    dfree(sign);
+    dfree(dir);
+    dfree(lam);
+    if (stt != NK_OK) union_free(u);
+    return stt;
+  };
+  hipError_t e;
+  if ((e = dmalloc(&s->fac64, std::max<int64_t>(nfac, 1))) ||
+      (e = dmalloc(&s->fac32, std::max<int64_t>(nfac, 1))) ||
+      (e = dmalloc(&l2g, std::max<int64_t>(coff[m], 1))) ||
+      (e = dmalloc(&sign, std::max<int64_t>(coff[m], 1))) ||
+      (e = dmalloc(&dir, std::max<int64_t>((doff[m] + 3) / 4 * 4, 4))) ||
+      (per_elem_lam && (e = dmalloc(&lam, std::max<int64_t>(eoff[m], 1)))))
+    return done(hip_fail(e, "hipMalloc"));
+  do {
+    if ((e = vec_fill<int32_t>((int32_t*)dir, (doff[m] + 3) / 4, 0, st))) break;
+    int64_t f = 0;
+    for (int k = 0; k < m && e == hipSuccess; ++k) {
+      const nk_space sk = mem[k]->space;
+      if (sk->nfac > 0 &&
+          ((e = hipMemcpyAsync(s->fac64 + f, sk->fac64, sk->nfac * 8, hipMemcpyDeviceToDevice, st)) ||
+           (e = hipMemcpyAsync(s->fac32 + f, sk->fac32, sk->nfac * 4, hipMemcpyDeviceToDevice, st))))
+        break;
+      f += sk->nfac;
+      if ((e = decode_l2g(sk->ncoeff, mem[k]->l2g, doff[k], l2g + coff[k], sign + coff[k], dir, st)))
+        break;
+      if (per_elem_lam && sk->nelem > 0) {
+        if (mem[k]->lam)
+          e = hipMemcpyAsync(lam + eoff[k], mem[k]->lam, sk->nelem * 8, hipMemcpyDeviceToDevice, st);
+        else
+          e = vec_fill<double>(lam + eoff[k], sk->nelem, mem[k]->lam0, st);
+      }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  } while (0);
+  if (e != hipSuccess) return done(hip_fail(e, "batched systems setup"));
+  const nk_status cs = system_create(&u->sys, s, m, eoff.data(), doff.data(), l2g, sign, dir, lam,
+                                     mem[0]->lam0, st);
+  if (cs != NK_OK) return done(cs);
+  *out = u;
+  return done(NK_OK);
+}
+
+// The cached union of exactly these members, built if absent.
+static nk_status union_get(const std::vector<nk_system>& mem, hipStream_t st, UnionLane** out) {
+  std::lock_guard<std::mutex> lk(g_union_mu);
+  for (size_t i = 0; i < g_unions.size(); ++i) {
+    if (g_unions[i]->members == mem) {
+      UnionLane* u = g_unions[i];
+      g_unions.erase(g_unions.begin() + i);
+      g_unions.push_back(u);
+      *out = u;
+      return NK_OK;
+    }
+  }
+  UnionLane* u = nullptr;
+  NK_CHECK(union_build(mem, st, &u));
+  if (g_unions.size() >= kMaxUnions) {
+    union_free(g_unions.front());
+    g_unions.erase(g_unions.begin());
+  }
+  g_unions.push_back(u);
+  *out = u;
+  return NK_OK;
+}
+
+namespace {
+struct Lane {
+  nk_system sys = nullptr;    // what is solved: a union or one caller system
+  bool is_union = false;
+  std::vector<int> idx;       // caller indices, in the system's order
+  SolveOut out;
+  hipError_t err = hipSuccess;
+};
+}  // namespace
+
+static void run_lane(Lane& L, int dev, nk_solve_mode mode, const double* const* b, double* const* x,
+                     double rtol, int maxit) {
+  nk_system y = L.sys;
+  hipStream_t cs = y->cs;
+  hipError_t e = hipSetDevice(dev);
+  do {
+    if (e) break;
+    if (L.is_union) {
+      for (int k = 0; k < y->nsys && e == hipSuccess; ++k) {
+        const int64_t n = y->dof_off[k + 1] - y->dof_off[k];
+        const int64_t p0 = y->pdof_off[k], np = y->pdof_off[k + 1] - p0;
+        if ((e = seg_in(n, np, b[L.idx[k]], y->dinv64 + p0, y->b + p0, cs))) break;
+        e = seg_in(n, np, x[L.idx[k]], y->dinv64 + p0, y->x + p0, cs);
+      }
+    } else {
+      const int j = L.idx[0];
+      if ((e = pad_in<double>(y->nsys, y->d_dof_off, y->d_pdof_off, y->L, b[j], y->dinv64, y->b, cs)))
+        break;
+      e = pad_in<double>(y->nsys, y->d_dof_off, y->d_pdof_off, y->L, x[j], y->dinv64, y->x, cs);
+    }
+    if (e) break;
+    if ((e = solve_padded(y, mode, rtol, maxit, L.out))) break;
+    if (L.is_union) {
+      for (int k = 0; k < y->nsys && e == hipSuccess; ++k)
+        e = seg_out(y->dof_off[k + 1] - y->dof_off[k], y->x + y->pdof_off[k], x[L.idx[k]], cs);
+    } else {
+      e = pad_out<double>(y->nsys, y->d_dof_off, y->d_pdof_off, y->nuser, y->x, x[L.idx[0]], cs);
+    }
+    if (e) break;
+    e = hipStreamSynchronize(cs);
+  } while (0);
+  L.err = e;
+}
+
+nk_status nk_cg_solve_batched(nk_system* sys, int nsys, nk_solve_mode mode, const double* const* b,
+                              double* const* x, double rtol, int maxit, nk_solve_info* info,
+                              void* stream) {
+  if (!sys || !b || !x) return fail(NK_EINVAL, "sys, b and x must be non-NULL");
+  if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
+  NK_CHECK(check_solve_args(mode, rtol, maxit));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  for (int i = 0; i < nsys; ++i) {
+    if (!sys[i]) return fail(NK_EINVAL, "system " + std::to_string(i) + " is NULL");
+    if (sys[i]->device != dev)
+      return fail(NK_EINVAL, "system " + std::to_string(i) + " lives on another device");
+    for (int j = 0; j < i; ++j)
+      if (sys[j] == sys[i]) return fail(NK_EINVAL, "a system appears twice in the batch");
+    NK_CHECK(check_buf(b[i], sys[i]->nuser * 8, "b"));
+    NK_CHECK(check_buf(x[i], sys[i]->nuser * 8, "x"));
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t us = (hipStream_t)stream;
+  // classes of union-able systems, in caller order
+  std::vector<Lane> lanes;
+  std::map<std::tuple<int, int, int>, std::vector<int>> cls;
+  std::vector<std::tuple<int, int, int>> cls_order;
+  for (int i = 0; i < nsys; ++i) {
+    if (union_member_ok(sys[i])) {
+      const Group& G = sys[i]->space->groups[0];
+      const auto key = std::make_tuple(sys[i]->space->dim, G.P, G.Q);
+      if (!cls.count(key)) cls_order.push_back(key);
+      cls[key].push_back(i);
+    } else {
+      Lane L;
+      L.sys = sys[i];
+      L.idx = {i};
+      lanes.push_back(std::move(L));
+    }
+  }
+  // a union's setup runs on the caller's stream after the caller's work
+  for (const auto& key : cls_order) {
+    const std::vector<int>& ids = cls[key];
+    Lane L;
+    L.idx = ids;
+    if (ids.size() == 1) {
+      L.sys = sys[ids[0]];
+    } else {
+      std::vector<nk_system> mem;
+      for (int i : ids) mem.push_back(sys[i]);
+      UnionLane* u = nullptr;
+      NK_CHECK(union_get(mem, us, &u));
+      L.sys = u->sys;
+      L.is_union = true;
+    }
+    lanes.push_back(std::move(L));
+  }
+  // order every lane's private stream after the caller's work
+  for (Lane& L : lanes)
+    if ((e = hipEventRecord(L.sys->ev, us)) || (e = hipStreamWaitEvent(L.sys->cs, L.sys->ev, 0)))
+      return hip_fail(e, "stream ordering");
+  if (lanes.size() == 1) {
+    run_lane(lanes[0], dev, mode, b, x, rtol, maxit);
+  } else {
+    std::vector<std::thread> th;
+    for (Lane& L : lanes)
+      th.emplace_back(run_lane, std::ref(L), dev, mode, b, x, rtol, maxit);
+    for (std::thread& t : th) t.join();
+  }
+  for (Lane& L : lanes)
+    if (L.err != hipSuccess) return hip_fail(L.err, "batched cg solve");
+  for (Lane& L : lanes)
+    if ((e = hipEventRecord(L.sys->ev, L.sys->cs)) || (e = hipStreamWaitEvent(us, L.sys->ev, 0)))
+      return hip_fail(e, "stream ordering");
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  nk_status worst = NK_OK;
+  for (Lane& L : lanes) {
+    for (int32_t st : L.out.stat)
+      if (st != NK_OK && worst == NK_OK) worst = (nk_status)st;
+    if (!info) continue;
+    if (L.is_union || L.sys->nsys == 1) {
+      for (size_t k = 0; k < L.idx.size(); ++k) fill_info(info + L.idx[k], L.out, (int)k, mode, ms);
+    } else {
+      // a caller system that is itself batched: its entry is the sub-system
+      // with the largest residual, with the worst status of all of them
+      int kw = 0;
+      for (int k = 1; k < L.sys->nsys; ++k)
+        if (rel_of(L.out.rr[k], L.out.bb[k]) > rel_of(L.out.rr[kw], L.out.bb[kw])) kw = k;
+      fill_info(info + L.idx[0], L.out, kw, mode, ms);
+      for (int k = 0; k < L.sys->nsys; ++k) {
+        info[L.idx[0]].iters = std::max(info[L.idx[0]].iters, L.out.iters[k]);
+        if (L.out.stat[k] != NK_OK) info[L.idx[0]].status = L.out.stat[k];
+      }
+    }
   }
   if (worst != NK_OK)
     return fail(worst, worst == NK_EBREAKDOWN ? "CG breakdown" : "CG did not converge");

@@ -601,6 +601,68 @@ hipError_t cast_copy(const float* src, double* dst, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Internal l2g entries of a one-system system back to the user form it was
+// built from: global DOF + off, orientation sign, Dirichlet flag of the DOF
+// (dirichlet must be zero on entry; entries of one DOF agree, so concurrent
+// writes store the same byte).
+__global__ void k_decode_l2g(int64_t n, const int32_t* __restrict__ l2g_int, int64_t off,
+                             int32_t* __restrict__ l2g_user, int8_t* __restrict__ sign,
+                             uint8_t* __restrict__ dirichlet) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = l2g_int[i];
+    const int64_t g = (int64_t)l2g_dof(v) + off;
+    l2g_user[i] = (int32_t)g;
+    sign[i] = l2g_neg(v) ? int8_t(-1) : int8_t(1);
+    if (v < 0) dirichlet[g] = 1;
+  }
+}
+
+hipError_t decode_l2g(int64_t n, const int32_t* l2g_int, int64_t off, int32_t* l2g_user,
+                      int8_t* sign, uint8_t* dirichlet, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_decode_l2g, dim3((unsigned)nb), dim3(256), 0, s, n, l2g_int, off, l2g_user,
+                     sign, dirichlet);
+  return hipGetLastError();
+}
+
+// One system's padded segment from its own user vector: padded[i] = user[i]
+// for i < n on free DOFs (dinv != 0), 0 on Dirichlet and padding entries.
+template <typename T>
+__global__ void k_seg_in(int64_t n, int64_t npad, const T* __restrict__ user,
+                         const double* __restrict__ dinv, T* __restrict__ padded) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad;
+       i += (int64_t)gridDim.x * blockDim.x)
+    padded[i] = (i < n && dinv[i] != 0.0) ? user[i] : T(0);
+}
+
+hipError_t seg_in(int64_t n, int64_t npad, const double* user, const double* dinv, double* padded,
+                  hipStream_t s) {
+  if (npad == 0) return hipSuccess;
+  int64_t nb = (npad + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_seg_in<double>, dim3((unsigned)nb), dim3(256), 0, s, n, npad, user, dinv,
+                     padded);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_seg_out(int64_t n, const T* __restrict__ padded, T* __restrict__ user) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    user[i] = padded[i];
+}
+
+hipError_t seg_out(int64_t n, const double* padded, double* user, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_seg_out<double>, dim3((unsigned)nb), dim3(256), 0, s, n, padded, user);
+  return hipGetLastError();
+}
+
 template hipError_t cg_update<double>(const VecLayout&, CgState, double*, double*, double*,
                                       double*, double*, double*, const double*, double*,
                                       hipStream_t);

@@ -67,6 +67,14 @@ hipError_t pad_out(int nsys, const int64_t* dof_off, const int64_t* pdof_off, in
 hipError_t build_l2g(int64_t nelem, int nloc, const int32_t* elem_seg, const int64_t* dof_off,
                      const int64_t* pdof_off, const int32_t* l2g_user, const int8_t* sign,
                      const uint8_t* dirichlet, int32_t* l2g_int, int* bad, hipStream_t s);
+// user form (global DOF + off, sign, Dirichlet flags) of a one-system
+// internal l2g; dirichlet must be zeroed first
+hipError_t decode_l2g(int64_t n, const int32_t* l2g_int, int64_t off, int32_t* l2g_user,
+                      int8_t* sign, uint8_t* dirichlet, hipStream_t s);
+// padded segment of one system from / to its own user vector
+hipError_t seg_in(int64_t n, int64_t npad, const double* user, const double* dinv, double* padded,
+                  hipStream_t s);
+hipError_t seg_out(int64_t n, const double* padded, double* user, hipStream_t s);
 hipError_t diag_finish(const VecLayout& L, const double* diag, const double* mark,
                        double* dinv64, float* dinv32, double* diag_out, hipStream_t s);
 hipError_t mark_free(int64_t nelem, int nloc, const int32_t* l2g_int, double* mark, hipStream_t s);

@@ -30,7 +30,8 @@ EXPORTS = [
     "nk_space_create_varp", "nk_space_destroy", "nk_space_sizes", "nk_bwd_trans",
     "nk_iprod_wrt_base", "nk_helmholtz", "nk_helmholtz_weak_rhs", "nk_system_create",
     "nk_system_create_batched", "nk_system_create_signed", "nk_system_destroy", "nk_system_apply",
-    "nk_system_apply_noalloc", "nk_assemble", "nk_gather", "nk_system_diagonal", "nk_cg_solve", "nk_helmholtz_param_grad", "nk_autotune",
+    "nk_system_apply_noalloc", "nk_assemble", "nk_gather", "nk_system_diagonal", "nk_cg_solve",
+    "nk_cg_solve_batched", "nk_helmholtz_param_grad", "nk_autotune",
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
     "nk_tri_points", "nk_space_create_tri", "nk_tet_points", "nk_space_create_tet",
@@ -90,6 +91,7 @@ def lib():
         "nk_gather": (i32, [vp, vp, vp, vp]),
         "nk_system_diagonal": (i32, [vp, vp, vp]),
         "nk_cg_solve": (i32, [vp, i32, vp, vp, dbl, i32, vp, vp]),
+        "nk_cg_solve_batched": (i32, [vp, i32, i32, vp, vp, dbl, i32, vp, vp]),
         "nk_helmholtz_param_grad": (i32, [vp, vp, vp, vp, vp, vp]),
         "nk_autotune": (i32, [vp, i32, vp]),
         "nk_tile_config": (ctypes.c_char_p, [i32, i32, i32, i32]),
@@ -335,6 +337,25 @@ def fwd_trans(space: Space, phys, coeffs=None, dtype=F64):
     _check(lib().nk_fwd_trans(space.handle, dtype, _ptr(phys, td, "phys"),
                               _ptr(coeffs, td, "coeffs"), _stream()))
     return coeffs
+
+
+def solve_batched(systems, bs, xs=None, rtol: float = 1e-10, maxit: int = 20000, mode=SOLVE_F64,
+                  raise_on_fail: bool = True):
+    """nk_cg_solve_batched: separately created systems solved in one call.
+    Returns ([x_k], [SolveInfo dict per system])."""
+    import torch
+    n = len(systems)
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    handles = (ctypes.c_void_p * n)(*[s.handle for s in systems])
+    bp = (ctypes.c_void_p * n)(*[_ptr(b, torch.float64, "b") for b in bs])
+    xp = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64, "x") for x in xs])
+    infos = (SolveInfo * n)()
+    st = lib().nk_cg_solve_batched(handles, n, int(mode), bp, xp, float(rtol), int(maxit), infos,
+                                   _stream())
+    if raise_on_fail:
+        _check(st)
+    return xs, [i.as_dict() for i in infos]
 
 
 def filtered_fwd_trans(space: Space, system, phys, rtol: float = 1e-12, mode=SOLVE_F64):

@@ -471,3 +471,55 @@ def test_system_size_limit_rejected():
     assert "padded system too large" in str(ei.value)
     del dm
     torch.cuda.empty_cache()
+
+
+# ------------------------------------ separately created systems in one call
+
+def test_cg_solve_batched_separate_systems():
+    """nk_cg_solve_batched over systems created separately, each with its own
+    space: two P=3 boxes (one with per-element lambda), two P=5 boxes, one
+    P=7 box and a conforming mixed-order system.  The P=3 and P=5 pairs run
+    as batched unions, the others as lanes of their own.  Every system's
+    solution matches the oracle's direct solve, its true residual meets rtol
+    (library value exactly, oracle value up to rounding), a second call
+    reuses the cached unions, and destroying a member drops them."""
+    m = nk()
+    torch = torch_cuda()
+    specs = [((2, 2, 1), 3, None), ((3, 2, 2), 3, 31), ((2, 2, 2), 5, None), ((1, 2, 2), 5, 32),
+             ((2, 1, 2), 7, None)]
+    cases = []
+    for shape, P, ls in specs:
+        pb = _problem(shape, P, lam_seed=ls)
+        mats = oracle.helmholtz_matrices(pb["ops"])
+        b = _rhs(pb)
+        _, sysm = _gpu_system(pb)
+        cases.append(dict(sys=sysm, mats=mats, l2g=pb["l2g"], ng=pb["ng"], dm=pb["dm"], b=b,
+                          xref=direct_solve(mats, pb["l2g"], pb["ng"], pb["dm"], b)))
+    vc = _varp_case((2, 2, 1), [2, 4, 3, 5])
+    cases.append(dict(sys=vc["sysm"], mats=vc["mats"], l2g=vc["l2g"], ng=vc["ng"], dm=vc["dm"],
+                      b=vc["b"], xref=direct_solve(vc["mats"], vc["l2g"], vc["ng"], vc["dm"], vc["b"])))
+
+    def check(cs, mode, tol, err_tol, what):
+        xs, info = m.solve_batched([c["sys"] for c in cs], [to_dev(c["b"]) for c in cs], rtol=tol,
+                                   mode=mode)
+        assert len(info) == len(cs)
+        for k, c in enumerate(cs):
+            A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"])
+            x = xs[k].cpu().numpy()
+            assert_true_residual(info[k], tol, A, c["mats"], c["l2g"], c["ng"], c["dm"], x, c["b"],
+                                 f"{what} system {k}")
+            assert rel_err(x, c["xref"]) < err_tol, (what, k, rel_err(x, c["xref"]))
+        return xs
+
+    for rep in range(2):
+        check(cases, m.SOLVE_F64, 1e-12, 1e-8, f"f64 call {rep}")
+        check(cases, m.SOLVE_F32_REFINED, 1e-10, 1e-6, f"refined call {rep}")
+    # a single system through the batched call equals nk_cg_solve's contract
+    check(cases[4:5], m.SOLVE_F64, 1e-12, 1e-8, "one system")
+    # destroying a member drops its union; the rest still solve
+    cases[0]["sys"].destroy()
+    check(cases[1:], m.SOLVE_F64, 1e-12, 1e-8, "after destroy")
+    # a system may appear once per call
+    with pytest.raises(m.NkError) as ei:
+        m.solve_batched([cases[1]["sys"], cases[1]["sys"]], [to_dev(cases[1]["b"])] * 2)
+    assert ei.value.status == m.NK_EINVAL
