@@ -123,6 +123,61 @@ def make_space(nk, W, shape, P, amp, torch, kappa=None):
     return sp, lat
 
 
+ROTATE_BYTES = 640e6   # rotation working set per operator: beyond the 256 MB Infinity Cache
+
+
+def rotation_count(bytes_per_launch, floor=3, cap=64):
+    """Buffer sets (or spaces) to rotate over so that the data of one launch
+    is not in the 256 MB Infinity Cache when its set comes round again."""
+    return int(min(cap, max(floor, -(-ROTATE_BYTES // max(bytes_per_launch, 1)))))
+
+
+def time_elementwise_ops(nk, W, torch, spaces_fn, E, nm, npt, nfac, reps):
+    """BwdTrans / IProductWRTBase / Helmholtz of a collapsed-shape space,
+    FP64 and FP32.  Each operator is timed over a rotation of rotation_count
+    launches whose data are all distinct: buffer sets, and for the operators
+    that read the geometric factors, spaces built from the same Jacobians
+    (spaces_fn(k) returns k of them), so the rotation spans at least
+    ROTATE_BYTES.  Algorithmic bytes per element (s bytes per scalar):
+    BwdTrans s(nm + np), IProductWRTBase s(nm + 2 np) (values and w detJ),
+    Helmholtz s(2 nm + nfac np)."""
+    res = {}
+    # the factor-reading operator with the fewest bytes per launch sets the space count
+    nsp = rotation_count(4 * (2 * npt + nm) * E)
+    spaces = spaces_fn(nsp)
+    for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
+        td = torch.float64 if dt == nk.F64 else torch.float32
+        ops = (("bwd_trans", s * (nm + npt)), ("iprod_wrt_base", s * (2 * npt + nm)),
+               ("helmholtz", s * (2 * nm + nfac * npt)))
+        nb = max(rotation_count(b * E) for _, b in ops)
+        cs = [torch.from_numpy(W.uniform(W.seed(1, 0) + k, E * nm)).to(td).cuda() for k in range(nb)]
+        fs = [torch.from_numpy(W.uniform(W.seed(1, 1) + k, E * npt)).to(td).cuda() for k in range(nb)]
+        us = [torch.empty(E * npt, dtype=td, device="cuda") for _ in range(nb)]
+        ys = [torch.empty(E * nm, dtype=td, device="cuda") for _ in range(nb)]
+        fns = {"bwd_trans": lambda k: nk.bwd_trans(spaces[k % nsp], cs[k], us[k], dtype=dt),
+               "iprod_wrt_base": lambda k: nk.iprod_wrt_base(spaces[k % nsp], fs[k], ys[k], dtype=dt),
+               "helmholtz": lambda k: nk.helmholtz(spaces[k % nsp], cs[k], ys[k], lam0=1.0, dtype=dt)}
+        for op, bpe in ops:
+            nrot = rotation_count(bpe * E)
+            fn = fns[op]
+            for k in range(nrot):
+                fn(k)
+            cnt = [0]
+
+            def step():
+                fn(cnt[0] % nrot)
+                cnt[0] += 1
+            ms = time_launches(step, max(reps, nrot), torch)
+            gbs = bpe * E / (ms * 1e-3) / 1e9
+            res[f"{op}_{name}"] = {"ms": round(ms, 5), "gdof_s": round(E * nm / (ms * 1e-3) / 1e9, 3),
+                                   "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "rotation": nrot, "rotation_MB": round(nrot * bpe * E / 1e6, 1)}
+        del cs, fs, us, ys
+    del spaces
+    torch.cuda.empty_cache()
+    return res
+
+
 # ------------------------------------------------------------------ sections
 
 def section_ops(nk, W, torch, space, lat, P, Q, reps):
@@ -236,38 +291,14 @@ def section_tri(nk, W, torch, n=256, orders=(4, 6, 8), reps=40):
         Q = P + 2
         e1, _, e2, _ = nk.tri_points(Q)
         J = torch.from_numpy(W.tri_lattice_jacobians(n, e1, e2, 0.05)).cuda()
-        space = nk.Space.create_tri(P, Q, J)
-        del J
         E = 2 * n * n
         nm, npt = (P + 1) * (P + 2) // 2, Q * (Q - 1)
-        res = {}
-        for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
-            td = torch.float64 if dt == nk.F64 else torch.float32
-            cs = [torch.from_numpy(W.uniform(W.seed(1, 0) + k, E * nm)).to(td).cuda() for k in range(3)]
-            fs = [torch.from_numpy(W.uniform(W.seed(1, 1) + k, E * npt)).to(td).cuda() for k in range(3)]
-            us = [torch.empty(E * npt, dtype=td, device="cuda") for _ in range(3)]
-            ys = [torch.empty(E * nm, dtype=td, device="cuda") for _ in range(3)]
-            for op, bpe, fn in (
-                ("bwd_trans", s * (nm + npt), lambda k: nk.bwd_trans(space, cs[k], us[k], dtype=dt)),
-                ("iprod_wrt_base", s * (2 * npt + nm), lambda k: nk.iprod_wrt_base(space, fs[k], ys[k], dtype=dt)),
-                ("helmholtz", s * (2 * nm + 4 * npt), lambda k: nk.helmholtz(space, cs[k], ys[k], lam0=1.0, dtype=dt)),
-            ):
-                for k in range(3):
-                    fn(k)
-                cnt = [0]
-
-                def step():
-                    fn(cnt[0] % 3)
-                    cnt[0] += 1
-                ms = time_launches(step, reps, torch)
-                gbs = bpe * E / (ms * 1e-3) / 1e9
-                res[f"{op}_{name}"] = {"ms": round(ms, 5), "gdof_s": round(E * nm / (ms * 1e-3) / 1e9, 3),
-                                       "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-            del cs, fs, us, ys
+        res = time_elementwise_ops(nk, W, torch, lambda k: [nk.Space.create_tri(P, Q, J) for _ in range(k)],
+                                   E, nm, npt, 4, reps)
+        del J
         out[f"P{P}"] = res
         log(f"tri P={P}: helmholtz f64 {res['helmholtz_f64']['ms'] * 1e3:.1f} us "
             f"({res['helmholtz_f64']['hbm_frac']:.1%} HBM)")
-        del space
         torch.cuda.empty_cache()
     return out
 
@@ -306,14 +337,20 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
         diff = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
         nel = lat.nelem
         n3, q3 = (P + 1) ** 3, (P + 2) ** 3
-        it_bytes64 = 8 * 7 * q3 * nel + 4 * n3 * nel + 8 * 12 * ng
-        it_bytes32 = 4 * 7 * q3 * nel + 4 * n3 * nel + 4 * 12 * ng
+        # algorithmic bytes of one PCG iteration: factors, the l2g map, and
+        # 9 global vectors (operator in and out, x, r, p read and written,
+        # the diagonal); the implementation streams 12 (its s = A p
+        # recurrence and the reset of w), reported separately
+        it_bytes64 = 8 * 7 * q3 * nel + 4 * n3 * nel + 8 * 9 * ng
+        impl_bytes64 = 8 * 7 * q3 * nel + 4 * n3 * nel + 8 * 12 * ng
         ms_it64 = t64 / max(i64[0]["iters"], 1)
+        gbs64 = it_bytes64 / (ms_it64 * 1e-3) / 1e9
         out[f"P{P}"] = {
             "nglobal": ng, "nelem": nel,
             "f64": {"ms": round(t64, 2), "iters": i64[0]["iters"], "rel_resid": i64[0]["rel_resid"],
                     "ms_per_iter": round(ms_it64, 4),
-                    "GB_s_per_iter": round(it_bytes64 / (ms_it64 * 1e-3) / 1e9, 1)},
+                    "GB_s_per_iter": round(gbs64, 1), "hbm_frac_per_iter": round(gbs64 / HBM_PEAK_GBS, 4),
+                    "impl_GB_s_per_iter": round(impl_bytes64 / (ms_it64 * 1e-3) / 1e9, 1)},
             "f32_refined": {"ms": round(t32, 2), "inner_iters": i32[0]["iters"],
                             "outer_iters": i32[0]["outer_iters"], "rel_resid": i32[0]["rel_resid"],
                             "rel_diff_vs_f64": diff},
@@ -341,51 +378,29 @@ def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30, shape=
         if shape == "tet":
             e1, _, e2, _, e3, _ = nk.tet_points(Q)
             J = torch.from_numpy(W.tet_lattice_jacobians(n, e1, e2, e3)).cuda()
-            space = nk.Space.create_tet(P, Q, J)
+            mk = nk.Space.create_tet
             E = 6 * n ** 3
             nm, npt = (P + 1) * (P + 2) * (P + 3) // 6, Q * (Q - 1) ** 2
         elif shape == "prism":
             e1, _, e2, _ = nk.tri_points(Q)
             J = torch.from_numpy(W.prism_lattice_jacobians(n, e1, e2, e1)).cuda()
-            space = nk.Space.create_prism(P, Q, J)
+            mk = nk.Space.create_prism
             E = 2 * n ** 3
             nm, npt = (P + 1) ** 2 * (P + 2) // 2, Q * Q * (Q - 1)
         else:   # pyramids: 6 per cube
             xg = nk.basis_tables(P, Q)[0]
             J = torch.from_numpy(W.pyr_lattice_jacobians(n, xg, xg, nk.tet_points(Q)[4])).cuda()
-            space = nk.Space.create_pyr(P, Q, J)
+            mk = nk.Space.create_pyr
             E = 6 * n ** 3
             nm, npt = (P + 1) * (P + 2) * (2 * P + 3) // 6, Q * Q * (Q - 1)
-        del J
         res = {"nelem": E}
-        for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
-            td = torch.float64 if dt == nk.F64 else torch.float32
-            cs = [torch.from_numpy(W.uniform(W.seed(1, 0) + k, E * nm)).to(td).cuda() for k in range(3)]
-            fs = [torch.from_numpy(W.uniform(W.seed(1, 1) + k, E * npt)).to(td).cuda() for k in range(3)]
-            us = [torch.empty(E * npt, dtype=td, device="cuda") for _ in range(3)]
-            ys = [torch.empty(E * nm, dtype=td, device="cuda") for _ in range(3)]
-            for op, bpe, fn in (
-                ("bwd_trans", s * (nm + npt), lambda k: nk.bwd_trans(space, cs[k], us[k], dtype=dt)),
-                ("iprod_wrt_base", s * (2 * npt + nm), lambda k: nk.iprod_wrt_base(space, fs[k], ys[k], dtype=dt)),
-                ("helmholtz", s * (2 * nm + 7 * npt), lambda k: nk.helmholtz(space, cs[k], ys[k], lam0=1.0, dtype=dt)),
-            ):
-                for k in range(3):
-                    fn(k)
-                cnt = [0]
-
-                def step():
-                    fn(cnt[0] % 3)
-                    cnt[0] += 1
-                ms = time_launches(step, reps, torch)
-                gbs = bpe * E / (ms * 1e-3) / 1e9
-                res[f"{op}_{name}"] = {"ms": round(ms, 5), "gdof_s": round(E * nm / (ms * 1e-3) / 1e9, 3),
-                                       "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-            del cs, fs, us, ys
+        res.update(time_elementwise_ops(nk, W, torch, lambda k: [mk(P, Q, J) for _ in range(k)],
+                                        E, nm, npt, 7, reps))
+        del J
         out[f"P{P}"] = res
         log(f"{shape} P={P} ({E} elements): helmholtz f64 {res['helmholtz_f64']['ms'] * 1e3:.1f} us "
             f"({res['helmholtz_f64']['hbm_frac']:.1%} HBM), bwd {res['bwd_trans_f64']['hbm_frac']:.1%}, "
             f"iprod {res['iprod_wrt_base_f64']['hbm_frac']:.1%}")
-        del space
         torch.cuda.empty_cache()
     return out
 
@@ -750,6 +765,26 @@ def section_many_solves(nk, W, torch):
                           "speedup_batched": round(ti / out[name]["batched_ms"], 2),
                           "rel_diff_batched_vs_one_by_one": diff})
         log(f"256 solves {name}: one by one {ti:.1f} ms")
+    # the same 256 separately created systems in one nk_cg_solve_batched call
+    # (the library batches them into a cached union on the first call)
+    sys_list = [sy for sp, sy, bk in singles]
+    b_list = [bk for sp, sy, bk in singles]
+    for mode, name in ((nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nk.solve_batched(sys_list, b_list, rtol=1e-2, maxit=50000, mode=mode)
+        tfirst = (time.perf_counter() - t) * 1e3
+        t = time.perf_counter()
+        xs, info = nk.solve_batched(sys_list, b_list, rtol=1e-10, maxit=50000, mode=mode)
+        tsep = (time.perf_counter() - t) * 1e3
+        xb, _ = sysb.solve(b, rtol=1e-10, maxit=50000, mode=mode)
+        diff = float(torch.linalg.norm(torch.cat(xs) - xb) / torch.linalg.norm(xb))
+        out[name].update({"separate_systems_batched_ms": round(tsep, 2),
+                          "separate_systems_first_call_ms": round(tfirst, 2),
+                          "separate_systems_max_rel_resid": max(i["rel_resid"] for i in info),
+                          "rel_diff_separate_vs_batched": diff,
+                          "speedup_separate_batched_vs_one_by_one": round(out[name]["one_by_one_ms"] / tsep, 2)})
+        log(f"256 solves {name}: separate systems batched {tsep:.1f} ms (first call {tfirst:.1f} ms)")
     out["speedup_f32_refined_vs_f64_batched"] = round(out["f64"]["batched_ms"] / out["f32_refined"]["batched_ms"], 3)
     return out
 
@@ -804,20 +839,26 @@ def section_grad(nk, W, torch):
             "fd_rel_diff": abs(fd - an) / abs(an)}
 
 
-def cpu_baseline(W, budget_s=12.0):
-    """The plain FP64 oracle (dense elemental matrices, build + apply) on a
-    bounded sample of the 32^3, P=6 workload's elements."""
-    import oracle
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(W, budget_s=8.0, apply_s=5.0):
+    """The plain FP64 oracle on a bounded sample of the 32^3, P=6 workload:
+    (1) dense elemental matrices built and applied (the headline value);
+    (2) apply only: 256 prebuilt H_e applied as one batched matmul."""
+    import oracle
+    threads = _blas_threads()
     P, Q = 6, 8
+    n3 = (P + 1) ** 3
     lat = W.lattice((32, 32, 32))
     rng = np.random.default_rng(W.seed(1, 6))
     idx = np.sort(rng.choice(lat.nelem, 4096, replace=False))
-    x = W.uniform(W.seed(1, 0), (lat.nelem, (P + 1) ** 3))
+    x = W.uniform(W.seed(1, 0), (lat.nelem, n3))
     done = 0
     t0 = time.perf_counter()
     chunk = 8
@@ -829,10 +870,56 @@ def cpu_baseline(W, budget_s=12.0):
         ops.helmholtz(x[sel])
         done += sel.size
     dt = time.perf_counter() - t0
-    return {"value": round(done * (P + 1) ** 3 / dt / 1e9, 6), "unit": "GDOF/s", "cores": int(threads),
+    # apply only
+    sel = idx[:256]
+    sub = W.Lattice(lat.shape, lat.h, lat.origins[sel])
+    ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], sub, W.WARP_AMPLITUDE), lam=1.0)
+    H = np.stack(oracle.helmholtz_matrices(ops))
+    xs = x[sel][:, :, None]
+    reps = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < apply_s:
+        np.matmul(H, xs)
+        reps += 1
+    da = time.perf_counter() - t1
+    return {"value": round(done * n3 / dt / 1e9, 6), "unit": "GDOF/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{done} of 32768 elements of the 32^3 P=6 workload, dense H_e build + apply, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "apply_only": {"value": round(reps * 256 * n3 / da / 1e9, 6), "unit": "GDOF/s",
+                           "cores": threads,
+                           "sample": f"256 prebuilt H_e (343 x 343) applied as one batched matmul, "
+                                     f"{reps} times in {da:.1f} s"}}
+
+
+def cpu_oracle_pcg(W, P=4, shape=(24, 24, 24), rtol=1e-10):
+    """The oracle's Jacobi PCG on the 24^3 curved-hex problem of the GPU's
+    CG section (same right-hand side construction: weak form of the
+    manufactured sine), as the oracle stands: prebuilt dense H_e applied by
+    its masked operator.  Time to solution on the host's cores; minutes of
+    CPU work, so it runs only when asked for."""
+    import oracle
+    from oracle.assembly import MaskedOperator, jacobi_diagonal
+    threads = _blas_threads()
+    Q = P + 2
+    lat = W.lattice(shape)
+    t0 = time.perf_counter()
+    Jo = W.element_jacobians(oracle.gll(Q)[0], lat, W.WARP_AMPLITUDE)
+    ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0)
+    mats = oracle.helmholtz_matrices(ops)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    U, dU = W.manufactured_ref_gradient(ops.x, lat)
+    b = oracle.assemble_vector(ops.weak_rhs(U, dU), l2g, ng)
+    b[dm.astype(bool)] = 0.0
+    diag = jacobi_diagonal(mats, l2g, ng, dm)
+    A = MaskedOperator(mats, l2g, ng, dm)
+    t_setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    x, its, res = oracle.pcg(A, b, diag, rtol=rtol)
+    t_solve = time.perf_counter() - t1
+    return {"P": P, "nglobal": int(ng), "nelem": int(lat.nelem), "iters": int(its), "rel_resid": float(res),
+            "setup_s": round(t_setup, 2), "solve_s": round(t_solve, 2),
+            "s_per_iter": round(t_solve / max(its, 1), 4), "cores": threads}
 
 
 # --------------------------------------------------------------------- main
@@ -843,7 +930,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sections", default="ops,deriv,tri,tet,cg,batch,grad,cpu",
-                    help="comma list of ops,deriv,tri,tet,cg,batch,grad,cpu (or 'none')")
+                    help="comma list of ops,deriv,tri,tet,cg,batch,grad,cpu,cpu_pcg (or 'none'); "
+                         "cpu_pcg (the oracle's 24^3 P=4 PCG, minutes of CPU) is not in the default")
     ap.add_argument("--cg-orders", default="4,6,8")
     ap.add_argument("--calib", action="store_true",
                     help="after the timed region, one 1 GiB device-to-device copy (counter calibration)")
@@ -970,6 +1058,9 @@ def main():
     if "cpu" in secs:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(W)
+    if "cpu_pcg" in secs:
+        log("cpu oracle PCG, 24^3 P=4 (minutes) ...")
+        result.setdefault("cpu_baseline", {})["pcg_24c_P4"] = cpu_oracle_pcg(W)
     print(json.dumps(result), flush=True)
 
 
