@@ -85,7 +85,7 @@ typedef struct nk_system_s* nk_system;
 typedef struct {
   int iters;             /* CG iterations summed over restarts (FP64 mode) or inner
                             FP32 iterations summed over refinement steps            */
-  int outer_iters;       /* refinement steps (FP32-refined mode), 0 otherwise          */
+  int outer_iters;       /* FP64 residual updates (FP32-refined mode), 0 otherwise     */
   double rel_resid;      /* true ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit    */
   double solve_ms;       /* wall time of the solve on the host clock                   */
   int status;            /* nk_status of this system                                   */
@@ -350,11 +350,15 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
  * system in total.  NK_SOLVE_F64: FP64 throughout; CG stops on its recursive
  * residual, and while the true residual is still above rtol (the two drift
  * apart by rounding) it restarts from the current x, within the budget.
- * NK_SOLVE_F32_REFINED: the operator and CG vectors run in FP32 (dot products
- * accumulated in FP64) inside an FP64 iterative-refinement loop whose
- * residual, dot products and solution update are FP64; the loop ends on the
- * true residual of the returned x, and maxit bounds the inner iterations
- * summed over refinement steps.  Iterations run as captured HIP graphs that
+ * NK_SOLVE_F32_REFINED: one CG whose operator and vectors run in FP32 (dot
+ * products accumulated in FP64), with reliable updates in FP64: whenever the
+ * FP32 residual has fallen tenfold since the last update (or the FP32
+ * iteration stops), its solution increment is added to the FP64 x and its
+ * residual is replaced by the true FP64 residual b - A x, keeping the search
+ * direction; the solve ends on the true residual of the returned x, and maxit
+ * bounds the FP32 iterations.  (Environment NK_REFINE=restart selects plain
+ * iterative refinement instead: FP32 CG solves of the FP64 residual equation,
+ * each reducing its residual by NK_INNER_TOL, default 1e-4.)  Iterations run as captured HIP graphs that
  * do not depend on rtol or maxit.  info (host, may be NULL) receives one
  * entry per system (nsys entries for a batched system).  Returns NK_ENOCONV
  * (budget spent with the true residual above rtol) or NK_EBREAKDOWN if any

@@ -829,6 +829,8 @@ static void system_free(nk_system y) {
     dfree(c->status);
     dfree(c->cnt);
     dfree(c->maxit);
+    dfree(c->rz_prev);
+    dfree(c->alpha_prev);
   }
   dfree(y->bb);
   dfree(y->rr_true);
@@ -851,7 +853,7 @@ static hipError_t alloc_state(CgState& c, int n) {
   if ((e = dmalloc(&c.rz, n)) || (e = dmalloc(&c.rr, n)) || (e = dmalloc(&c.tol2, n)) ||
       (e = dmalloc(&c.alpha, n)) || (e = dmalloc(&c.beta, n)) || (e = dmalloc(&c.done, n)) ||
       (e = dmalloc(&c.iters, n)) || (e = dmalloc(&c.status, n)) || (e = dmalloc(&c.cnt, n)) ||
-      (e = dmalloc(&c.maxit, n)))
+      (e = dmalloc(&c.maxit, n)) || (e = dmalloc(&c.rz_prev, n)) || (e = dmalloc(&c.alpha_prev, n)))
     return e;
   return hipMemset(c.cnt, 0, n * sizeof(int32_t));
 }
@@ -1589,6 +1591,134 @@ static hipError_t solve_refined(nk_system y, double rtol, int maxit, std::vector
   return hipSuccess;
 }
 
+static double reliable_delta() {
+  const char* v = std::getenv("NK_RELIABLE_DELTA");
+  const double d = v ? std::atof(v) : 0.1;
+  return (d > 0.0 && d < 1.0) ? d : 0.1;
+}
+
+static bool refine_by_restart() {
+  const char* v = std::getenv("NK_REFINE");
+  return v && std::strcmp(v, "restart") == 0;
+}
+
+// FP32 CG with reliable updates inside FP64: one FP32 Jacobi-PCG whose
+// recursive residual is replaced by the true FP64 residual b - A x whenever
+// every active system's FP32 residual has fallen by reliable_delta() since
+// the last replacement, or a system's FP32 iteration stopped; the FP32
+// solution increment is then added to the FP64 x and cleared.  The search
+// directions are kept across the replacement (the last step's alpha and beta
+// are recomputed from the new residual), so no Krylov information is lost as
+// it is when the inner solve restarts.  The loop ends on the true FP64
+// residual of the returned x (left in rr); maxit bounds the FP32 iterations.
+static hipError_t solve_reliable(nk_system y, double rtol, int maxit, std::vector<int>& iters,
+                                 std::vector<int>& outer, std::vector<int32_t>& stat,
+                                 std::vector<double>& rr) {
+  const int ns = y->nsys;
+  const int64_t np = y->L.npad;
+  hipStream_t cs = y->cs;
+  CgState outer_st;
+  outer_st.rr = y->outer_rr;
+  outer_st.tol2 = y->outer_tol2;
+  outer_st.done = y->outer_done;
+  outer_st.status = y->outer_status;
+  outer_st.cnt = y->outer_cnt;
+  const double rtol_dev = rtol * (1.0 - 1e-14);
+  const double d2 = reliable_delta() * reliable_delta();
+  std::vector<double> bb, rr_last, rr32;
+  std::vector<int32_t> done, done32, it_dev, st_dev;
+  std::vector<char> fin(ns, 0);
+  stat.assign(ns, NK_OK);
+  hipError_t e;
+  auto true_resid = [&]() -> hipError_t {
+    hipError_t e2;
+    if ((e2 = vec_fill<double>(y->y, np, 0.0, cs))) return e2;
+    if ((e2 = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) return e2;
+    if ((e2 = cg_residual(y->L, outer_st, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs)))
+      return e2;
+    return read_sys(y, y->outer_done, done);
+  };
+  if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol_dev, y->outer_tol2, cs))) return e;
+  if ((e = read_sys(y, y->bb, bb))) return e;
+  if ((e = true_resid())) return e;
+  if ((e = read_sys(y, y->outer_rr, rr_last))) return e;
+  bool all = true;
+  for (int i = 0; i < ns; ++i) all = all && done[i] != 0;
+  const bool began = !all;
+  if (began) {
+    if ((e = set_budgets(y, y->st32, std::vector<int>(ns, maxit)))) return e;
+    if ((e = vec_fill<float>(y->d32, np, 0.f, cs))) return e;
+    if ((e = vec_fill<float>(y->y32, np, 0.f, cs))) return e;
+    // the FP32 iteration stops at half the target residual (tol2 = outer_tol2 / 4)
+    if ((e = cg_begin<float>(y, y->r, 1e-300, y->outer_done))) return e;
+    if ((e = ensure_graph<float>(y))) return e;
+    for (int i = 0; i < ns; ++i)
+      if (!done[i]) outer[i] = 1;
+    const int64_t max_launch = (int64_t)maxit / y->g32_iters + 2;
+    int64_t launches = 0;
+    for (int upd = 0; upd < 10000; ++upd) {
+      // FP32 iterations until a reliable update is due
+      bool due = false;
+      while (!due) {
+        if (launches++ >= max_launch) {
+          due = true;
+          break;
+        }
+        if ((e = hipGraphLaunch(y->g32, cs))) return e;
+        if ((e = read_sys(y, y->st32.done, done32)) || (e = read_sys(y, y->st32.rr, rr32))) return e;
+        bool progressed = true, any_stopped = false, active = false;
+        for (int i = 0; i < ns; ++i) {
+          if (done[i] || fin[i]) continue;
+          active = true;
+          any_stopped = any_stopped || done32[i] != 0;
+          progressed = progressed && rr32[i] <= d2 * rr_last[i];
+        }
+        due = !active || any_stopped || progressed;
+      }
+      // fold the FP32 increment into x and take the true residual
+      if ((e = cg_correct(y->L, y->outer_done, y->d32, y->x, cs))) return e;
+      if ((e = vec_fill<float>(y->d32, np, 0.f, cs))) return e;
+      if ((e = true_resid())) return e;
+      if ((e = read_sys(y, y->outer_rr, rr_last))) return e;
+      if ((e = read_sys(y, y->st32.iters, it_dev)) || (e = read_sys(y, y->st32.status, st_dev)))
+        return e;
+      bool newly_fin = false;
+      all = true;
+      for (int i = 0; i < ns; ++i) {
+        if (done[i] || fin[i]) continue;
+        if (it_dev[i] >= maxit || st_dev[i] != NK_OK || launches > max_launch) {
+          fin[i] = newly_fin = true;   // budget spent or breakdown: x is final
+          stat[i] = st_dev[i] != NK_OK ? st_dev[i] : NK_ENOCONV;
+          continue;
+        }
+        all = false;
+        outer[i] += 1;
+      }
+      if (newly_fin) {
+        // finished systems get an infinite tolerance: skipped from now on
+        for (int i = 0; i < ns; ++i) y->h_d[i] = fin[i] ? HUGE_VAL : rtol_dev * rtol_dev * bb[i];
+        if ((e = hipMemcpyAsync(y->outer_tol2, y->h_d, ns * 8, hipMemcpyHostToDevice, cs)) ||
+            (e = hipStreamSynchronize(cs)))
+          return e;
+      }
+      if (all) break;
+      // the FP32 residual becomes the true one; p and s are kept
+      if ((e = cg_reliable(y->L, y->r, y->r32, y->u32, y->y32, y->dinv32, y->part, cs))) return e;
+      if ((e = sys_op(y, NK_F32, y->u32, y->y32, y->dots, y->outer_done, cs))) return e;
+      if ((e = cg_finish_reliable(ns, y->L, y->Ld, y->part, y->dots, y->st32, y->outer_done, cs)))
+        return e;
+    }
+  }
+  it_dev.assign(ns, 0);
+  if (began && (e = read_sys(y, y->st32.iters, it_dev))) return e;
+  rr = rr_last;
+  for (int i = 0; i < ns; ++i) {
+    iters[i] = it_dev[i];
+    if (stat[i] == NK_OK && !(rel_of(rr[i], bb[i]) <= rtol)) stat[i] = NK_ENOCONV;
+  }
+  return hipSuccess;
+}
+
 // Per-system results of one solve of a (possibly batched) system.
 struct SolveOut {
   std::vector<int> iters, outer;
@@ -1603,7 +1733,9 @@ static hipError_t solve_padded(nk_system y, nk_solve_mode mode, double rtol, int
   o.iters.assign(y->nsys, 0);
   o.outer.assign(y->nsys, 0);
   hipError_t e = mode == NK_SOLVE_F64 ? solve_f64(y, rtol, maxit, o.iters, o.stat, o.rr)
-                                      : solve_refined(y, rtol, maxit, o.iters, o.outer, o.stat, o.rr);
+                 : refine_by_restart()
+                     ? solve_refined(y, rtol, maxit, o.iters, o.outer, o.stat, o.rr)
+                     : solve_reliable(y, rtol, maxit, o.iters, o.outer, o.stat, o.rr);
   if (e) return e;
   return read_sys(y, y->bb, o.bb);
 }

@@ -182,7 +182,10 @@ hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p,
 // One block per system: gamma = sum of (r,u) partials, rr = sum of (r,r)
 // partials, delta = sum of the system's dots.  mode 0: iteration, mode 1:
 // first step of a solve (tol2 is set from rr when tau2 > 0, for the inner
-// solves of the refinement).
+// solves of the refinement), mode 2: the last iteration's step again after
+// its residual was replaced by the true one (reliable update: gamma and
+// delta are new, beta and alpha come from the saved gamma and alpha of the
+// iteration before; the search directions p, s are kept).
 __global__ void __launch_bounds__(kFinThreads)
     k_cg_finish(const int64_t* __restrict__ blk_first, const int64_t* __restrict__ dblk_first,
                 const double* __restrict__ part, const double* __restrict__ dots, CgState st,
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(kFinThreads)
                 const double* __restrict__ outer_tol2, const double* __restrict__ outer_rr) {
   __shared__ double sh[3 * (kFinThreads / 64)];
   const int sg = blockIdx.x;
-  if (!start && st.done[sg]) return;
+  if (start == 0 && st.done[sg]) return;
   // Every thread requests kFinLoads values per round before adding any (the
   // indices are clamped into the range, so every load is in bounds and
   // needs no branch), so a system of up to kFinLoads * kFinThreads elements
@@ -231,8 +234,44 @@ __global__ void __launch_bounds__(kFinThreads)
   rr = v3[1];
   dl = v3[2];
   if (threadIdx.x != 0) return;
+  if (start == 2) {
+    st.rr[sg] = rr;
+    if ((outer_done != nullptr && outer_done[sg] != 0) || rr <= st.tol2[sg] || rr == 0.0 ||
+        st.iters[sg] >= st.maxit[sg]) {
+      st.done[sg] = 1;
+      return;
+    }
+    if (!isfinite(rr) || !isfinite(g) || !isfinite(dl)) {
+      st.done[sg] = 1;
+      st.status[sg] = NK_EBREAKDOWN;
+      return;
+    }
+    // The recurrence for p.Ap assumes the new residual is orthogonal to the
+    // old directions; where rounding has spoilt that (the residual is at the
+    // noise level of the low precision, e.g. a Krylov space that is used up)
+    // the direction restarts from u (beta = 0, p = u, s = A u).
+    const double gp = st.rz_prev[sg];
+    double beta = gp > 0.0 ? g / gp : 0.0;
+    double den = gp > 0.0 ? dl - beta * g / st.alpha_prev[sg] : dl;
+    if (!(den > 0.0) || !isfinite(den)) {
+      beta = 0.0;
+      den = dl;
+    }
+    if (!(den > 0.0)) {
+      st.done[sg] = 1;
+      st.status[sg] = NK_EBREAKDOWN;
+      return;
+    }
+    st.done[sg] = 0;
+    st.beta[sg] = beta;
+    st.alpha[sg] = g / den;
+    st.rz[sg] = g;
+    return;
+  }
   if (start) {
     st.iters[sg] = 0;
+    st.rz_prev[sg] = 0.0;
+    st.alpha_prev[sg] = 0.0;
     st.status[sg] = 0;
     st.rr[sg] = rr;
     if (tau2 > 0.0) {
@@ -260,6 +299,8 @@ __global__ void __launch_bounds__(kFinThreads)
   const int it = st.iters[sg] + 1;
   st.iters[sg] = it;
   st.rr[sg] = rr;
+  st.rz_prev[sg] = st.rz[sg];
+  st.alpha_prev[sg] = st.alpha[sg];
   if (rr <= st.tol2[sg]) {
     st.done[sg] = 1;
     return;
@@ -293,6 +334,47 @@ hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const do
   hipLaunchKernelGGL(k_cg_finish, dim3(nsys), dim3(kFinThreads), 0, stream, L.blk_first,
                      Ld.blk_first, part, dots, st, fatal ? 1 : 0, start ? 1 : 0, tau2,
                      outer_done, outer_tol2, outer_rr);
+  return hipGetLastError();
+}
+
+hipError_t cg_finish_reliable(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
+                              const double* dots, CgState st, const int32_t* outer_done,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_finish, dim3(nsys), dim3(kFinThreads), 0, stream, L.blk_first,
+                     Ld.blk_first, part, dots, st, 0, 2, 0.0, outer_done, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+// Reliable update of the low-precision CG: r = the true residual r64 (FP64,
+// zero off the free DOFs) rounded to T, u = M^{-1} r, w = 0, partial sums of
+// (r, u) and (r, r); p and s are left as they are.
+template <typename T>
+__global__ void __launch_bounds__(kVecBlock)
+    k_cg_reliable(const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ u,
+                  T* __restrict__ w, const T* __restrict__ dinv, double* __restrict__ part) {
+  __shared__ double sh[2 * (kVecBlock / 64)];
+  const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
+  double g = 0.0, rr = 0.0;
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int64_t i = base + c * kVecBlock;
+    const T ri = (T)r64[i];
+    const T ui = ri * dinv[i];
+    r[i] = ri;
+    u[i] = ui;
+    w[i] = T(0);
+    g += (double)ri * (double)ui;
+    rr += (double)ri * (double)ri;
+  }
+  double v[2] = {g, rr};
+  block_sums<kVecBlock, 2>(v, sh);
+  store_parts(v[0], v[1], part);
+}
+
+hipError_t cg_reliable(const VecLayout& L, const double* r64, float* r, float* u, float* w,
+                       const float* dinv, double* part, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_reliable<float>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream, r64,
+                     r, u, w, dinv, part);
   return hipGetLastError();
 }
 

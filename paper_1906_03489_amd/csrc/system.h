@@ -22,6 +22,8 @@ struct CgState {
   int32_t* status = nullptr;
   int32_t* cnt = nullptr;   // finished-block counter of the fused reduction
   int32_t* maxit = nullptr; // iteration budget of the current CG run (device, per system)
+  double* rz_prev = nullptr;     // r.z and alpha of the iteration before the last one
+  double* alpha_prev = nullptr;  // (a reliable update redoes the last step)
 };
 
 // Vector-kernel geometry: DOF ranges of every system are padded to multiples
@@ -45,6 +47,13 @@ hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const do
                      double tau2, const int32_t* outer_done, const double* outer_tol2,
                      const double* outer_rr, hipStream_t stream);
 
+// the last CG step redone after a reliable update (see k_cg_finish, mode 2)
+hipError_t cg_finish_reliable(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
+                              const double* dots, CgState st, const int32_t* outer_done,
+                              hipStream_t stream);
+// r = (float) r64, u = M^{-1} r, w = 0, partial sums of (r, u) and (r, r)
+hipError_t cg_reliable(const VecLayout& L, const double* r64, float* r, float* u, float* w,
+                       const float* dinv, double* part, hipStream_t stream);
 // r = (b - y) on free DOFs (dinv > 0), 0 elsewhere; y is reset to 0; optionally
 // p = 0; per system rz = r.dinv.r, rr = r.r; done = rr <= tol2.
 hipError_t cg_residual(const VecLayout& L, CgState st, const double* b, double* y,
