@@ -914,8 +914,17 @@ def cpu_oracle_pcg(W, P=4, shape=(24, 24, 24), rtol=1e-10):
     diag = jacobi_diagonal(mats, l2g, ng, dm)
     A = MaskedOperator(mats, l2g, ng, dm)
     t_setup = time.perf_counter() - t0
+    log(f"oracle pcg setup {t_setup:.1f} s ({lat.nelem} dense H_e)")
+    calls = [0]
+
+    def apply(v):
+        # the oracle's operator, with a progress line every 100 applications
+        calls[0] += 1
+        if calls[0] % 100 == 0:
+            log(f"oracle pcg: {calls[0]} operator applications, {time.perf_counter() - t1:.0f} s")
+        return A(v)
     t1 = time.perf_counter()
-    x, its, res = oracle.pcg(A, b, diag, rtol=rtol)
+    x, its, res = oracle.pcg(apply, b, diag, rtol=rtol)
     t_solve = time.perf_counter() - t1
     return {"P": P, "nglobal": int(ng), "nelem": int(lat.nelem), "iters": int(its), "rel_resid": float(res),
             "setup_s": round(t_setup, 2), "solve_s": round(t_solve, 2),

@@ -11,8 +11,8 @@
  * Helmholtz operator of the weak problem a(u, v) = l(v) of Eqs. (1)-(2), all
  * by sum-factorisation (the display in section 3.3).  On top of these it
  * assembles the C0 system (section 2.1, assembly operator) and solves it with
- * Jacobi-preconditioned conjugate gradients (FP64, or FP32 inside FP64
- * iterative refinement), batches independent systems and mixed orders, and
+ * Jacobi-preconditioned conjugate gradients (FP64, or FP32 with FP64
+ * residual updates), batches independent systems and mixed orders, and
  * differentiates the solve with respect to kappa and lambda.  Besides
  * quadrilaterals and hexahedra it covers the collapsed-coordinate triangles,
  * tetrahedra, prisms and pyramids of section 2.1 (their elemental operators
@@ -352,7 +352,8 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
  * apart by rounding) it restarts from the current x, within the budget.
  * NK_SOLVE_F32_REFINED: one CG whose operator and vectors run in FP32 (dot
  * products accumulated in FP64), with reliable updates in FP64: whenever the
- * FP32 residual has fallen tenfold since the last update (or the FP32
+ * FP32 residual has fallen by NK_RELIABLE_DELTA (default 0.3) since the last
+ * update (or the FP32
  * iteration stops), its solution increment is added to the FP64 x and its
  * residual is replaced by the true FP64 residual b - A x, keeping the search
  * direction; the solve ends on the true residual of the returned x, and maxit
