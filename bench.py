@@ -79,6 +79,36 @@ def measured_traffic():
         return None
 
 
+FWD_FLOPS_SUMMARY = "profiles/fwd_trans_32c_P6_flops.txt"
+FWD_SOURCES = ["paper_1906_03489_amd/csrc/deriv.hip", "paper_1906_03489_amd/csrc/engine.h"]
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def fwd_trans_flops():
+    """Issued lane-flops per element of FwdTrans (32^3, P=6) per dtype from
+    the committed rocprofv3 flop-counter summary, or {} once the kernel
+    sources changed since those counters were taken."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in FWD_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        vals, digest = {}, None
+        with open(os.path.join(ROOT, FWD_FLOPS_SUMMARY)) as fh:
+            for line in fh:
+                if "kernel sources hash" in line:
+                    digest = line.split(":")[-1].strip()
+                elif line.strip() and not line.startswith("#"):
+                    k, v = line.split()
+                    vals[k] = float(v)
+        if digest != h.hexdigest()[:16]:
+            return {}
+        return {"f64": vals["flops_per_elem_f64"], "f32": vals["flops_per_elem_f32"]}
+    except (OSError, KeyError, ValueError):
+        return {}
+
+
 def time_launches(fn, n, torch):
     """Average ms per call of fn over n back-to-back calls, HIP events on
     the current stream (the stream the kernels are launched on)."""
@@ -243,10 +273,13 @@ def section_deriv(nk, W, torch, space, lat, P, Q, reps):
     (values, gradient, J^{-1}); IProductWRTDerivBase s(3Q^3 + 10Q^3 + n^3)
     (field, J^{-1} and w detJ, coefficients); FwdTrans s(2Q^3 + n^3) (values,
     w detJ, coefficients): its CG iterations run on chip, so it is bound by
-    arithmetic, not HBM, and hbm_frac only says how far.  gdof_s counts the
-    element's n^3 modes per second for all three."""
+    arithmetic, not HBM, and hbm_frac only says how far; its "alu" roofline
+    takes the issued flops per element from the committed counter summary
+    against the vector peak.  gdof_s counts the element's n^3 modes per
+    second for all three."""
     E = lat.nelem
     n3, q3 = (P + 1) ** 3, Q ** 3
+    fwd_flops = fwd_trans_flops() if (P, Q, E) == (6, 8, 32768) else {}
     out = {}
     for dt, name, s in ((nk.F64, "f64", 8), (nk.F32, "f32", 4)):
         td = torch.float64 if dt == nk.F64 else torch.float32
@@ -275,6 +308,13 @@ def section_deriv(nk, W, torch, space, lat, P, Q, reps):
             out[f"{op}_{name}"] = {"ms": round(ms, 5), "gdof_s": round(E * n3 / (ms * 1e-3) / 1e9, 3),
                                    "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                                    "bound": bound}
+            if bound == "alu":
+                fl = fwd_flops.get(name)
+                tf = fl * E / (ms * 1e-3) / 1e12 if fl else None
+                out[f"{op}_{name}"]["alu"] = {
+                    "flops_per_elem": fl, "achieved_TFLOPs": round(tf, 2) if tf else None,
+                    "peak_TFLOPs": VALU_PEAK_TFLOPS[name],
+                    "frac": round(tf / VALU_PEAK_TFLOPS[name], 4) if tf else None}
         del us, fs, dus, cs
         torch.cuda.empty_cache()
     return out

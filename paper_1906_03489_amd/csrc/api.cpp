@@ -793,10 +793,7 @@ static void system_free(nk_system y) {
   dfree(y->d_elem_off);
   dfree(y->d_blk_first);
   dfree(y->d_blk_seg);
-  dfree(y->d_dblk_first);
-  dfree(y->d_dblk_seg);
   dfree(y->dslot);
-  dfree(y->part_d);
   dfree(y->elem_seg);
   dfree(y->l2g);
   dfree(y->lam);
@@ -816,21 +813,23 @@ static void system_free(nk_system y) {
   dfree(y->p32);
   dfree(y->y32);
   dfree(y->d32);
-  dfree(y->dots);
   dfree(y->part);
   for (CgState* c : {&y->st64, &y->st32}) {
     dfree(c->rz);
     dfree(c->rr);
     dfree(c->tol2);
     dfree(c->alpha);
-    dfree(c->beta);
     dfree(c->done);
     dfree(c->iters);
     dfree(c->status);
     dfree(c->cnt);
     dfree(c->maxit);
-    dfree(c->rz_prev);
-    dfree(c->alpha_prev);
+    dfree(c->gsl);
+    dfree(c->dsl);
+    dfree(c->sgam);
+    dfree(c->salp);
+    dfree(c->sit);
+    dfree(c->sdn);
   }
   dfree(y->bb);
   dfree(y->rr_true);
@@ -851,9 +850,11 @@ static void system_free(nk_system y) {
 static hipError_t alloc_state(CgState& c, int n) {
   hipError_t e;
   if ((e = dmalloc(&c.rz, n)) || (e = dmalloc(&c.rr, n)) || (e = dmalloc(&c.tol2, n)) ||
-      (e = dmalloc(&c.alpha, n)) || (e = dmalloc(&c.beta, n)) || (e = dmalloc(&c.done, n)) ||
-      (e = dmalloc(&c.iters, n)) || (e = dmalloc(&c.status, n)) || (e = dmalloc(&c.cnt, n)) ||
-      (e = dmalloc(&c.maxit, n)) || (e = dmalloc(&c.rz_prev, n)) || (e = dmalloc(&c.alpha_prev, n)))
+      (e = dmalloc(&c.alpha, n)) || (e = dmalloc(&c.done, n)) || (e = dmalloc(&c.iters, n)) ||
+      (e = dmalloc(&c.status, n)) || (e = dmalloc(&c.cnt, n)) || (e = dmalloc(&c.maxit, n)) ||
+      (e = dmalloc(&c.gsl, (int64_t)3 * n * 2 * kSlots)) ||
+      (e = dmalloc(&c.dsl, (int64_t)2 * n * kSlots)) || (e = dmalloc(&c.sgam, 2 * n)) ||
+      (e = dmalloc(&c.salp, 2 * n)) || (e = dmalloc(&c.sit, 2 * n)) || (e = dmalloc(&c.sdn, 2 * n)))
     return e;
   return hipMemset(c.cnt, 0, n * sizeof(int32_t));
 }
@@ -906,26 +907,16 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   }
   y->L.npad = y->pdof_off[nsys];
   y->L.nblk = y->L.npad / kSegAlign;
-  y->pdot_off.assign(nsys + 1, 0);
-  y->dblk_first.assign(nsys + 1, 0);
-  for (int k = 0; k < nsys; ++k) {
-    const int64_t ne = std::max<int64_t>(elem_off[k + 1] - elem_off[k], 1);
-    y->pdot_off[k + 1] = y->pdot_off[k] + (ne + kSegAlign - 1) / kSegAlign * kSegAlign;
-    y->dblk_first[k + 1] = y->pdot_off[k + 1] / kSegAlign;
-  }
-  y->Ld.npad = y->pdot_off[nsys];
-  y->Ld.nblk = y->Ld.npad / kSegAlign;
   if (y->L.npad >= (int64_t)kL2gNeg) {   // bit 30 of an internal l2g entry is the sign flag
     system_free(y);
     return fail(NK_EINVAL, "padded system too large");
   }
-  std::vector<int32_t> blk_seg(y->L.nblk), eseg(s->nelem), dblk_seg(y->Ld.nblk), dslot(s->nelem);
+  std::vector<int32_t> blk_seg(y->L.nblk), eseg(s->nelem), dslot(s->nelem);
   for (int k = 0; k < nsys; ++k) {
     for (int64_t b = y->blk_first[k]; b < y->blk_first[k + 1]; ++b) blk_seg[b] = k;
-    for (int64_t b = y->dblk_first[k]; b < y->dblk_first[k + 1]; ++b) dblk_seg[b] = k;
     for (int64_t e = elem_off[k]; e < elem_off[k + 1]; ++e) {
       eseg[e] = k;
-      dslot[e] = (int32_t)(y->pdot_off[k] + (e - elem_off[k]));
+      dslot[e] = (int32_t)(k * kSlots + (e - elem_off[k]) % kSlots);   // CG accumulation slot
     }
   }
   auto cleanup = [&](nk_status stt) {
@@ -960,11 +951,7 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   NK_ALLOC(y->p32, np);
   NK_ALLOC(y->y32, np);
   NK_ALLOC(y->d32, np);
-  NK_ALLOC(y->dots, y->Ld.npad);
   NK_ALLOC(y->part, 2 * y->L.nblk);
-  NK_ALLOC(y->part_d, 2 * y->Ld.nblk);
-  NK_ALLOC(y->d_dblk_first, nsys + 1);
-  NK_ALLOC(y->d_dblk_seg, y->Ld.nblk);
   NK_ALLOC(y->dslot, std::max<int64_t>(s->nelem, 1));
   NK_ALLOC(y->bb, nsys);
   NK_ALLOC(y->rr_true, nsys);
@@ -989,8 +976,6 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
     return cleanup(hip_fail(e, "hipEventCreate"));
   y->L.blk_seg = y->d_blk_seg;
   y->L.blk_first = y->d_blk_first;
-  y->Ld.blk_seg = y->d_dblk_seg;
-  y->Ld.blk_first = y->d_dblk_first;
   // setup runs on the caller's stream, then synchronises it
   int* d_bad = nullptr;
   double *d_B = nullptr, *d_D = nullptr;
@@ -1018,11 +1003,8 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
     if ((e = hipMemcpyAsync(y->d_elem_off, elem_off, (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
     if ((e = hipMemcpyAsync(y->d_blk_first, y->blk_first.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
     if ((e = hipMemcpyAsync(y->d_blk_seg, blk_seg.data(), y->L.nblk * 4, hipMemcpyHostToDevice, st))) break;
-    if ((e = hipMemcpyAsync(y->d_dblk_first, y->dblk_first.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, st))) break;
-    if ((e = hipMemcpyAsync(y->d_dblk_seg, dblk_seg.data(), y->Ld.nblk * 4, hipMemcpyHostToDevice, st))) break;
     if (s->nelem > 0 &&
         (e = hipMemcpyAsync(y->dslot, dslot.data(), s->nelem * 4, hipMemcpyHostToDevice, st))) break;
-    if ((e = vec_fill<double>(y->dots, y->Ld.npad, 0.0, st))) break;
     if (s->nelem > 0 &&
         (e = hipMemcpyAsync(y->elem_seg, eseg.data(), s->nelem * 4, hipMemcpyHostToDevice, st))) break;
     if (lambda && (e = hipMemcpyAsync(y->lam, lambda, s->nelem * 8, hipMemcpyDeviceToDevice, st))) break;
@@ -1126,8 +1108,8 @@ nk_status nk_system_destroy(nk_system sys) {
   return NK_OK;
 }
 
-// y (padded) += A x (padded) over the elements of order group g; dots per
-// element if requested.
+// y (padded) += A x (padded) over the elements of order group g; with dots,
+// each element's energy is added to its CG accumulation slot (dslot).
 static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, void* out,
                                double* dots, const int32_t* seg_done, int tile, hipStream_t st) {
   nk_space s = y->space;
@@ -1322,10 +1304,12 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream) {
 }
 
 // ------------------------------------------------------------------ solve
+// CG iterations per captured graph: a multiple of 6, the period of the
+// rotating reduction sets (cg.hip), so every launch starts on set 0.
 static int graph_iters() {
   const char* v = std::getenv("NK_GRAPH_ITERS");
-  const int k = v ? std::atoi(v) : 16;
-  return std::min(std::max(k, 1), 256);
+  const int k = v ? std::atoi(v) : 18;
+  return std::min(std::max((k + 5) / 6 * 6, 6), 252);
 }
 
 static double inner_tol() {
@@ -1334,12 +1318,16 @@ static double inner_tol() {
   return (t > 0.0 && t < 1.0) ? t : 1e-4;
 }
 
-// One CG iteration of precision T on the system's stream: vector update,
-// assembled operator w = A u with per-element u.Au, per-system finish.  The
-// iteration budget is read from device memory, so captured graphs do not
-// depend on it.
+// Delta slot set q of precision T's state.
+static double* dset(nk_system y, const CgState& st, int q) {
+  return st.dsl + (int64_t)q * y->nsys * kSlots;
+}
+
+// CG iteration j (of a graph launch) in precision T on the system's stream:
+// the update (which forms its step from the slot sums) and the assembled
+// operator w = A u, whose element energies go to delta set j+1.
 template <typename T>
-static hipError_t cg_iteration(nk_system y) {
+static hipError_t cg_iteration(nk_system y, int j) {
   const bool f64 = std::is_same<T, double>::value;
   CgState& st = f64 ? y->st64 : y->st32;
   T* x = f64 ? (T*)y->x : (T*)y->d32;
@@ -1350,16 +1338,14 @@ static hipError_t cg_iteration(nk_system y) {
   T* w = f64 ? (T*)y->y : (T*)y->y32;
   const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
   hipError_t e;
-  if ((e = cg_update<T>(y->L, st, x, r, u, p, s, w, dinv, y->part, y->cs))) return e;
-  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, st.done, y->cs)))
+  if ((e = cg_update<T>(y->L, st, y->nsys, j, f64, nullptr, x, r, u, p, s, w, dinv, y->cs)))
     return e;
-  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, f64, false, 0.0, nullptr,
-                   nullptr, nullptr, y->cs);
+  return sys_op(y, f64 ? NK_F64 : NK_F32, u, w, dset(y, st, (j + 1) & 1), st.done, y->cs);
 }
 
 // First step of a CG solve in precision T: r = b - w (w = A x0 or 0),
-// u = M^{-1} r, w = A u, alpha from (r,u)/(w,u).  Systems whose skip flag is
-// set (or whose residual already meets tol2) are marked done at once.
+// u = M^{-1} r, w = A u, and the scalars the first update reads.  Systems
+// whose skip flag is set (or whose residual already meets tol2) stop at once.
 template <typename T>
 static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int32_t* skip) {
   const bool f64 = std::is_same<T, double>::value;
@@ -1370,12 +1356,14 @@ static hipError_t cg_begin(nk_system y, const double* b, double tau2, const int3
   T* s = f64 ? (T*)y->s : (T*)y->s32;
   T* w = f64 ? (T*)y->y : (T*)y->y32;
   const T* dinv = f64 ? (const T*)y->dinv64 : (const T*)y->dinv32;
+  const int ns = y->nsys;
   hipError_t e;
-  if ((e = cg_start<T>(y->L, b, w, r, u, p, s, dinv, y->part, y->cs))) return e;
-  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, y->dots, nullptr, y->cs)))
+  if ((e = vec_fill<double>(st.gsl, (int64_t)3 * ns * 2 * kSlots, 0.0, y->cs)) ||
+      (e = vec_fill<double>(st.dsl, (int64_t)2 * ns * kSlots, 0.0, y->cs)))
     return e;
-  return cg_finish(y->nsys, y->L, y->Ld, y->part, y->dots, st, f64, true, tau2, skip,
-                   y->outer_tol2, y->outer_rr, y->cs);
+  if ((e = cg_start<T>(y->L, st, ns, b, w, r, u, p, s, dinv, y->cs))) return e;
+  if ((e = sys_op(y, f64 ? NK_F64 : NK_F32, u, w, dset(y, st, 0), nullptr, y->cs))) return e;
+  return cg_begin_scalars(st, ns, tau2, skip, y->outer_tol2, y->outer_rr, y->cs);
 }
 
 template <typename T>
@@ -1393,7 +1381,7 @@ static hipError_t ensure_graph(nk_system y) {
   hipError_t e = hipStreamBeginCapture(y->cs, hipStreamCaptureModeThreadLocal);
   if (e) return e;
   hipError_t e2 = hipSuccess;
-  for (int i = 0; i < k && e2 == hipSuccess; ++i) e2 = cg_iteration<T>(y);
+  for (int i = 0; i < k && e2 == hipSuccess; ++i) e2 = cg_iteration<T>(y, i);
   e = hipStreamEndCapture(y->cs, &g);
   if (e2) {
     if (g) (void)hipGraphDestroy(g);
@@ -1706,11 +1694,15 @@ static hipError_t solve_reliable(nk_system y, double rtol, int maxit, std::vecto
           return e;
       }
       if (all) break;
-      // the FP32 residual becomes the true one; p and s are kept
-      if ((e = cg_reliable(y->L, y->r, y->r32, y->u32, y->y32, y->dinv32, y->part, cs))) return e;
-      if ((e = sys_op(y, NK_F32, y->u32, y->y32, y->dots, y->outer_done, cs))) return e;
-      if ((e = cg_finish_reliable(ns, y->L, y->Ld, y->part, y->dots, y->st32, y->outer_done, cs)))
+      // the FP32 residual becomes the true one; p and s are kept, and the
+      // next update redoes the last step from the new gamma and delta
+      CgState& s32 = y->st32;
+      if ((e = vec_fill<double>(s32.gsl, (int64_t)ns * 2 * kSlots, 0.0, cs)) ||
+          (e = vec_fill<double>(s32.dsl, (int64_t)ns * kSlots, 0.0, cs)))
         return e;
+      if ((e = cg_reliable(y->L, s32, ns, y->r, y->r32, y->u32, y->y32, y->dinv32, cs))) return e;
+      if ((e = sys_op(y, NK_F32, y->u32, y->y32, dset(y, s32, 0), y->outer_done, cs))) return e;
+      if ((e = cg_rearm(s32, ns, y->outer_done, cs))) return e;
     }
   }
   it_dev.assign(ns, 0);

@@ -1,8 +1,8 @@
 // Vector kernels of the Jacobi-preconditioned conjugate-gradient solver and
 // the assembly helpers.  Each block of kVecBlock threads owns kSegAlign
-// consecutive DOFs of one system, so per-system reductions are block sums
-// finished by the last block of that system (fixed summation order, hence
-// deterministic).
+// consecutive DOFs of one system.  The CG iteration's reductions go through
+// per-system accumulation slots (below); the residual and norm kernels finish
+// their per-system sums in the last block of the system.
 #include "system.h"
 
 namespace nk {
@@ -85,71 +85,188 @@ __device__ __forceinline__ void sum_parts(double* part, int64_t b0, int64_t b1, 
 //   gamma = (r, u), delta = (w, u),
 //   beta = gamma / gamma_old,  alpha = gamma / (delta - beta gamma / alpha_old),
 //   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s.
-// One iteration = cg_update (vectors; partial sums of gamma and r.r),
-// the assembled operator w = A u (per-element u_e.(H_e u_e) into dots), and
-// cg_finish (one block per system sums the partials and the dots, tests
-// convergence and forms alpha, beta).  Block partials are plain stores read by
-// the next kernel, so no grid-wide fence is needed.
+// One iteration j is two kernels: cg_update (every block first forms the
+// system's gamma, r.r, delta, alpha and beta itself from kSlots accumulation
+// slots, then updates its vectors and adds its partials of the next gamma and
+// r.r to the slots) and the assembled operator w = A u (each element adds
+// u_e.(H_e u_e) to a slot).  No separate reduction kernel and no grid-wide
+// fence: the slots are filled with atomics by one kernel and read by the next.
+// Slot sets rotate so that no kernel reads a set that is being filled or
+// cleared: gamma / r.r sets by j mod 3 (iteration j reads set j, fills j+1,
+// clears j+2), delta sets by j mod 2 (iteration j's update reads set j and
+// clears j+1, its operator fills j+1), and the carried scalars (gamma, alpha,
+// iterations, stopped) by j mod 2 (read j-1, written j by the system's first
+// block).  Captured graphs hold a multiple of 6 iterations, so iteration j of
+// every launch sees the same sets.
+constexpr int kGS = 2 * kSlots;   // gamma slots then r.r slots, per system and set
 
-// Writes the block's two partial sums; thread 0 holds the block sums.
-__device__ __forceinline__ void store_parts(double a, double b, double* part) {
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = a;
-    part[2 * blockIdx.x + 1] = b;
+__device__ __forceinline__ double* gslot(const CgState& st, int nsys, int q, int s) {
+  return st.gsl + ((int64_t)q * nsys + s) * kGS;
+}
+__device__ __forceinline__ double* dslot_set(const CgState& st, int nsys, int q, int s) {
+  return st.dsl + ((int64_t)q * nsys + s) * kSlots;
+}
+
+// Sums of a system's slots (one per thread: kSlots = kVecBlock), broadcast
+// to every thread of the block.
+__device__ __forceinline__ void slot_sums(const double* g, const double* d, double* sh,
+                                          double& gam, double& rr, double& del) {
+  static_assert(kSlots == kVecBlock, "one slot per thread");
+  const int t = threadIdx.x;
+  double v[3] = {g[t], g[kSlots + t], d[t]};
+  block_sums<kVecBlock, 3>(v, sh);
+  __shared__ double bc[3];
+  if (t == 0) {
+    bc[0] = v[0];
+    bc[1] = v[1];
+    bc[2] = v[2];
   }
+  __syncthreads();
+  gam = bc[0];
+  rr = bc[1];
+  del = bc[2];
+}
+
+// The leader block of a system clears the slot sets it owns this iteration.
+__device__ __forceinline__ void clear_slots(double* g, double* d) {
+  const int t = threadIdx.x;
+  g[t] = 0.0;
+  g[kSlots + t] = 0.0;
+  d[t] = 0.0;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_cg_update(const int32_t* __restrict__ blk_seg, CgState st, T* __restrict__ x,
-                T* __restrict__ r, T* __restrict__ u, T* __restrict__ p, T* __restrict__ s,
-                T* __restrict__ w, const T* __restrict__ dinv, double* __restrict__ part) {
-  __shared__ double sh[2 * (kVecBlock / 64)];
+    k_cg_update(const int32_t* __restrict__ blk_seg, const int64_t* __restrict__ blk_first,
+                CgState st, int nsys, int j, int fatal, const int32_t* __restrict__ skip,
+                T* __restrict__ x, T* __restrict__ r, T* __restrict__ u, T* __restrict__ p,
+                T* __restrict__ s, T* __restrict__ w, const T* __restrict__ dinv) {
+  __shared__ double sh[3 * (kVecBlock / 64)];
   const int sg = blk_seg[blockIdx.x];
-  if (st.done[sg]) return;
-  const T alpha = (T)st.alpha[sg], beta = (T)st.beta[sg];
+  const bool leader = blockIdx.x == blk_first[sg];
+  const int qg = j % 3, qd = j & 1, qp = (j + 1) & 1;   // qp: the set written last iteration
+  const int64_t cur = (int64_t)qd * nsys + sg, prev = (int64_t)qp * nsys + sg;
+  // the block's vectors are requested first, so their loads overlap the
+  // reduction of the slots that decides the step
   const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
-  double g = 0.0, rr = 0.0;
+  T vd[kPer], vr[kPer], vp[kPer], vw[kPer], vs[kPer];
 #pragma unroll
   for (int c = 0; c < kPer; ++c) {
     const int64_t i = base + c * kVecBlock;
-    const T di = dinv[i];
-    const T ri = r[i];
-    const T pi = ri * di + beta * p[i];
-    const T si = w[i] + beta * s[i];
-    x[i] += alpha * pi;
-    const T rn = ri - alpha * si;
-    const T un = rn * di;
+    vd[c] = dinv[i];
+    vr[c] = r[i];
+    vp[c] = p[i];
+    vw[c] = w[i];
+    vs[c] = s[i];
+  }
+  const double gp = st.sgam[prev], ap = st.salp[prev];
+  const int itp = st.sit[prev], dnp = st.sdn[prev];
+  double gam, rr, del;
+  slot_sums(gslot(st, nsys, qg, sg), dslot_set(st, nsys, qd, sg), sh, gam, rr, del);
+  if (leader) clear_slots(gslot(st, nsys, (j + 2) % 3, sg), dslot_set(st, nsys, qp, sg));
+  if (dnp || (skip && skip[sg])) {
+    // stopped: carry the state to this iteration's set
+    if (leader && threadIdx.x == 0) {
+      st.sgam[cur] = gp;
+      st.salp[cur] = ap;
+      st.sit[cur] = itp;
+      st.sdn[cur] = 1;
+      st.done[sg] = 1;
+    }
+    return;
+  }
+  bool stop = false;
+  int status = 0;
+  double beta = 0.0, alpha = 0.0;
+  if (!isfinite(rr) || !isfinite(gam) || !isfinite(del)) {
+    stop = true;
+    status = NK_EBREAKDOWN;
+  } else if (rr <= st.tol2[sg] || rr == 0.0) {
+    stop = true;
+  } else if (itp >= st.maxit[sg]) {
+    stop = true;
+    if (fatal) status = NK_ENOCONV;
+  } else {
+    // After a reliable update the new residual is not orthogonal to the old
+    // directions to working precision; where that spoils p.Ap (or in the low
+    // precision, where rounding does), the direction restarts from u.
+    beta = gp > 0.0 ? gam / gp : 0.0;
+    double den = gp > 0.0 ? del - beta * gam / ap : del;
+    if (!(den > 0.0) || !isfinite(den)) {
+      if (fatal) {
+        stop = true;
+        status = NK_EBREAKDOWN;
+      } else {
+        beta = 0.0;
+        den = del;
+        if (!(den > 0.0)) {
+          stop = true;
+          status = NK_EBREAKDOWN;
+        }
+      }
+    }
+    if (!stop) alpha = gam / den;
+  }
+  if (leader && threadIdx.x == 0) {
+    st.sgam[cur] = stop ? gp : gam;
+    st.salp[cur] = stop ? ap : alpha;
+    st.sit[cur] = stop ? itp : itp + 1;
+    st.sdn[cur] = stop ? 1 : 0;
+    st.done[sg] = stop ? 1 : 0;
+    st.iters[sg] = stop ? itp : itp + 1;
+    st.rr[sg] = rr;
+    st.rz[sg] = gam;
+    st.alpha[sg] = alpha;
+    if (status) st.status[sg] = status;
+  }
+  if (stop) return;
+  const T a = (T)alpha, b = (T)beta;
+  double g = 0.0, r2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int64_t i = base + c * kVecBlock;
+    const T pi = vr[c] * vd[c] + b * vp[c];
+    const T si = vw[c] + b * vs[c];
+    x[i] += a * pi;
+    const T rn = vr[c] - a * si;
+    const T un = rn * vd[c];
     p[i] = pi;
     s[i] = si;
     r[i] = rn;
     u[i] = un;
     w[i] = T(0);
     g += (double)rn * (double)un;
-    rr += (double)rn * (double)rn;
+    r2 += (double)rn * (double)rn;
   }
-  double v[2] = {g, rr};
+  double v[2] = {g, r2};
   block_sums<kVecBlock, 2>(v, sh);
-  store_parts(v[0], v[1], part);
+  if (threadIdx.x == 0) {
+    double* gs = gslot(st, nsys, (j + 1) % 3, sg);
+    const int k = blockIdx.x % kSlots;
+    unsafeAtomicAdd(gs + k, v[0]);
+    unsafeAtomicAdd(gs + kSlots + k, v[1]);
+  }
 }
 
 template <typename T>
-hipError_t cg_update(const VecLayout& L, CgState st, T* x, T* r, T* u, T* p, T* s, T* w,
-                     const T* dinv, double* part, hipStream_t stream) {
+hipError_t cg_update(const VecLayout& L, CgState st, int nsys, int j, bool fatal,
+                     const int32_t* skip, T* x, T* r, T* u, T* p, T* s, T* w, const T* dinv,
+                     hipStream_t stream) {
   hipLaunchKernelGGL(k_cg_update<T>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream,
-                     L.blk_seg, st, x, r, u, p, s, w, dinv, part);
+                     L.blk_seg, L.blk_first, st, nsys, j, fatal ? 1 : 0, skip, x, r, u, p, s, w,
+                     dinv);
   return hipGetLastError();
 }
 
 // Start of a solve: r = (b - w) on free DOFs (w = A x0, or 0), u = M^{-1} r,
-// p = s = w = 0, partial sums of (r, u) and (r, r).
+// p = s = w = 0, partial sums of (r, u) and (r, r) into gamma set 0.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_cg_start(const int32_t* __restrict__ blk_seg, const double* __restrict__ b,
-               T* __restrict__ w, T* __restrict__ r, T* __restrict__ u, T* __restrict__ p,
-               T* __restrict__ s, const T* __restrict__ dinv, double* __restrict__ part) {
+    k_cg_start(const int32_t* __restrict__ blk_seg, CgState st, int nsys,
+               const double* __restrict__ b, T* __restrict__ w, T* __restrict__ r,
+               T* __restrict__ u, T* __restrict__ p, T* __restrict__ s,
+               const T* __restrict__ dinv) {
   __shared__ double sh[2 * (kVecBlock / 64)];
-  (void)blk_seg;
   const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
   double g = 0.0, rr = 0.0;
 #pragma unroll
@@ -168,190 +285,71 @@ __global__ void __launch_bounds__(kVecBlock)
   }
   double v[2] = {g, rr};
   block_sums<kVecBlock, 2>(v, sh);
-  store_parts(v[0], v[1], part);
+  if (threadIdx.x == 0) {
+    double* gs = gslot(st, nsys, 0, blk_seg[blockIdx.x]);
+    const int k = blockIdx.x % kSlots;
+    unsafeAtomicAdd(gs + k, v[0]);
+    unsafeAtomicAdd(gs + kSlots + k, v[1]);
+  }
 }
 
 template <typename T>
-hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p, T* s,
-                    const T* dinv, double* part, hipStream_t stream) {
+hipError_t cg_start(const VecLayout& L, CgState st, int nsys, const double* b, T* w, T* r, T* u,
+                    T* p, T* s, const T* dinv, hipStream_t stream) {
   hipLaunchKernelGGL(k_cg_start<T>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream,
-                     L.blk_seg, b, w, r, u, p, s, dinv, part);
+                     L.blk_seg, st, nsys, b, w, r, u, p, s, dinv);
   return hipGetLastError();
 }
 
-// One block per system: gamma = sum of (r,u) partials, rr = sum of (r,r)
-// partials, delta = sum of the system's dots.  mode 0: iteration, mode 1:
-// first step of a solve (tol2 is set from rr when tau2 > 0, for the inner
-// solves of the refinement), mode 2: the last iteration's step again after
-// its residual was replaced by the true one (reliable update: gamma and
-// delta are new, beta and alpha come from the saved gamma and alpha of the
-// iteration before; the search directions p, s are kept).
-__global__ void __launch_bounds__(kFinThreads)
-    k_cg_finish(const int64_t* __restrict__ blk_first, const int64_t* __restrict__ dblk_first,
-                const double* __restrict__ part, const double* __restrict__ dots, CgState st,
-                int fatal, int start, double tau2, const int32_t* __restrict__ outer_done,
-                const double* __restrict__ outer_tol2, const double* __restrict__ outer_rr) {
-  __shared__ double sh[3 * (kFinThreads / 64)];
+// One block per system after the start kernel and the first operator (which
+// filled gamma set 0 and delta set 0): iteration counters, the starting
+// residual, tol2 for the inner solves of the refinement (tau2 > 0: reduce by
+// tau, or only as far as the outer tolerance still needs, with a factor 1/2
+// of margin), and the carried scalars the first update reads (set 1: no
+// previous gamma, so beta = 0).
+__global__ void __launch_bounds__(kVecBlock)
+    k_cg_begin(CgState st, int nsys, double tau2, const int32_t* __restrict__ skip,
+               const double* __restrict__ outer_tol2, const double* __restrict__ outer_rr) {
+  __shared__ double sh[3 * (kVecBlock / 64)];
   const int sg = blockIdx.x;
-  if (start == 0 && st.done[sg]) return;
-  // Every thread requests kFinLoads values per round before adding any (the
-  // indices are clamped into the range, so every load is in bounds and
-  // needs no branch), so a system of up to kFinLoads * kFinThreads elements
-  // takes one memory round trip instead of one per value.
-  constexpr int kFinLoads = 16;
-  double dl = 0.0, g = 0.0, rr = 0.0;
-  // dots are padded per system to whole kSegAlign blocks (padding is zero)
-  const int64_t d0 = dblk_first[sg] * kSegAlign, d1 = dblk_first[sg + 1] * kSegAlign;
-  for (int64_t i0 = d0 + threadIdx.x; i0 < d1; i0 += (int64_t)kFinLoads * kFinThreads) {
-    double v[kFinLoads];
-#pragma unroll
-    for (int k = 0; k < kFinLoads; ++k) {
-      const int64_t i = i0 + (int64_t)k * kFinThreads;
-      v[k] = dots[i < d1 ? i : d1 - 1];
-    }
-#pragma unroll
-    for (int k = 0; k < kFinLoads; ++k) dl += i0 + (int64_t)k * kFinThreads < d1 ? v[k] : 0.0;
-  }
-  const int64_t b0 = blk_first[sg], b1 = blk_first[sg + 1];
-  for (int64_t j0 = b0 + threadIdx.x; j0 < b1; j0 += (int64_t)kFinLoads * kFinThreads) {
-    double va[kFinLoads], vb[kFinLoads];
-#pragma unroll
-    for (int k = 0; k < kFinLoads; ++k) {
-      const int64_t j = j0 + (int64_t)k * kFinThreads, jc = j < b1 ? j : b1 - 1;
-      va[k] = part[2 * jc];
-      vb[k] = part[2 * jc + 1];
-    }
-#pragma unroll
-    for (int k = 0; k < kFinLoads; ++k) {
-      const bool in = j0 + (int64_t)k * kFinThreads < b1;
-      g += in ? va[k] : 0.0;
-      rr += in ? vb[k] : 0.0;
-    }
-  }
-  double v3[3] = {g, rr, dl};
-  block_sums<kFinThreads, 3>(v3, sh);
-  g = v3[0];
-  rr = v3[1];
-  dl = v3[2];
+  double gam, rr, del;
+  slot_sums(gslot(st, nsys, 0, sg), dslot_set(st, nsys, 0, sg), sh, gam, rr, del);
+  (void)gam;
+  (void)del;
   if (threadIdx.x != 0) return;
-  if (start == 2) {
-    st.rr[sg] = rr;
-    if ((outer_done != nullptr && outer_done[sg] != 0) || rr <= st.tol2[sg] || rr == 0.0 ||
-        st.iters[sg] >= st.maxit[sg]) {
-      st.done[sg] = 1;
-      return;
-    }
-    if (!isfinite(rr) || !isfinite(g) || !isfinite(dl)) {
-      st.done[sg] = 1;
-      st.status[sg] = NK_EBREAKDOWN;
-      return;
-    }
-    // The recurrence for p.Ap assumes the new residual is orthogonal to the
-    // old directions; where rounding has spoilt that (the residual is at the
-    // noise level of the low precision, e.g. a Krylov space that is used up)
-    // the direction restarts from u (beta = 0, p = u, s = A u).
-    const double gp = st.rz_prev[sg];
-    double beta = gp > 0.0 ? g / gp : 0.0;
-    double den = gp > 0.0 ? dl - beta * g / st.alpha_prev[sg] : dl;
-    if (!(den > 0.0) || !isfinite(den)) {
-      beta = 0.0;
-      den = dl;
-    }
-    if (!(den > 0.0)) {
-      st.done[sg] = 1;
-      st.status[sg] = NK_EBREAKDOWN;
-      return;
-    }
-    st.done[sg] = 0;
-    st.beta[sg] = beta;
-    st.alpha[sg] = g / den;
-    st.rz[sg] = g;
-    return;
-  }
-  if (start) {
-    st.iters[sg] = 0;
-    st.rz_prev[sg] = 0.0;
-    st.alpha_prev[sg] = 0.0;
-    st.status[sg] = 0;
-    st.rr[sg] = rr;
-    if (tau2 > 0.0) {
-      // inner solve of the refinement: reduce by tau, or only as far as the
-      // outer tolerance still needs (with a factor 1/2 of margin)
-      const double need = outer_rr[sg] > 0.0 ? 0.25 * outer_tol2[sg] / outer_rr[sg] : 0.0;
-      st.tol2[sg] = (need > tau2 ? need : tau2) * rr;
-    }
-    const bool od = outer_done != nullptr && outer_done[sg] != 0;
-    if (od || rr <= st.tol2[sg] || rr == 0.0) {
-      st.done[sg] = 1;
-      return;
-    }
-    st.done[sg] = 0;
-    if (!(dl > 0.0) || !isfinite(dl) || !isfinite(g)) {
-      st.done[sg] = 1;
-      if (fatal) st.status[sg] = NK_EBREAKDOWN;
-      return;
-    }
-    st.rz[sg] = g;
-    st.alpha[sg] = g / dl;
-    st.beta[sg] = 0.0;
-    return;
-  }
-  const int it = st.iters[sg] + 1;
-  st.iters[sg] = it;
+  st.iters[sg] = 0;
+  st.status[sg] = 0;
   st.rr[sg] = rr;
-  st.rz_prev[sg] = st.rz[sg];
-  st.alpha_prev[sg] = st.alpha[sg];
-  if (rr <= st.tol2[sg]) {
-    st.done[sg] = 1;
-    return;
+  if (tau2 > 0.0) {
+    const double need = outer_rr[sg] > 0.0 ? 0.25 * outer_tol2[sg] / outer_rr[sg] : 0.0;
+    st.tol2[sg] = (need > tau2 ? need : tau2) * rr;
   }
-  if (!isfinite(rr) || !isfinite(g) || !isfinite(dl)) {
-    st.done[sg] = 1;
-    st.status[sg] = NK_EBREAKDOWN;
-    return;
-  }
-  if (it >= st.maxit[sg]) {
-    st.done[sg] = 1;
-    if (fatal) st.status[sg] = NK_ENOCONV;
-    return;
-  }
-  const double beta = g / st.rz[sg];
-  const double den = dl - beta * g / st.alpha[sg];
-  if (!(den > 0.0)) {
-    st.done[sg] = 1;
-    if (fatal) st.status[sg] = NK_EBREAKDOWN;
-    return;
-  }
-  st.beta[sg] = beta;
-  st.alpha[sg] = g / den;
-  st.rz[sg] = g;
+  const bool stop = (skip != nullptr && skip[sg] != 0) || rr <= st.tol2[sg] || rr == 0.0;
+  const int64_t q1 = (int64_t)nsys + sg;
+  st.sgam[q1] = 0.0;
+  st.salp[q1] = 1.0;
+  st.sit[q1] = 0;
+  st.sdn[q1] = stop ? 1 : 0;
+  st.done[sg] = stop ? 1 : 0;
 }
 
-hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
-                     const double* dots, CgState st, bool fatal, bool start,
-                     double tau2, const int32_t* outer_done, const double* outer_tol2,
-                     const double* outer_rr, hipStream_t stream) {
-  hipLaunchKernelGGL(k_cg_finish, dim3(nsys), dim3(kFinThreads), 0, stream, L.blk_first,
-                     Ld.blk_first, part, dots, st, fatal ? 1 : 0, start ? 1 : 0, tau2,
-                     outer_done, outer_tol2, outer_rr);
-  return hipGetLastError();
-}
-
-hipError_t cg_finish_reliable(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
-                              const double* dots, CgState st, const int32_t* outer_done,
-                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_cg_finish, dim3(nsys), dim3(kFinThreads), 0, stream, L.blk_first,
-                     Ld.blk_first, part, dots, st, 0, 2, 0.0, outer_done, nullptr, nullptr);
+hipError_t cg_begin_scalars(CgState st, int nsys, double tau2, const int32_t* skip,
+                            const double* outer_tol2, const double* outer_rr, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_begin, dim3(nsys), dim3(kVecBlock), 0, stream, st, nsys, tau2, skip,
+                     outer_tol2, outer_rr);
   return hipGetLastError();
 }
 
 // Reliable update of the low-precision CG: r = the true residual r64 (FP64,
 // zero off the free DOFs) rounded to T, u = M^{-1} r, w = 0, partial sums of
-// (r, u) and (r, r); p and s are left as they are.
+// (r, u) and (r, r) into gamma set 0 (cleared beforehand with delta set 0);
+// p and s are left as they are.  The next update (iteration 0 of a graph
+// launch) then redoes the last step with the new gamma and delta.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_cg_reliable(const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ u,
-                  T* __restrict__ w, const T* __restrict__ dinv, double* __restrict__ part) {
+    k_cg_reliable(const int32_t* __restrict__ blk_seg, CgState st, int nsys,
+                  const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ u,
+                  T* __restrict__ w, const T* __restrict__ dinv) {
   __shared__ double sh[2 * (kVecBlock / 64)];
   const int64_t base = (int64_t)blockIdx.x * kSegAlign + threadIdx.x;
   double g = 0.0, rr = 0.0;
@@ -368,13 +366,34 @@ __global__ void __launch_bounds__(kVecBlock)
   }
   double v[2] = {g, rr};
   block_sums<kVecBlock, 2>(v, sh);
-  store_parts(v[0], v[1], part);
+  if (threadIdx.x == 0) {
+    double* gs = gslot(st, nsys, 0, blk_seg[blockIdx.x]);
+    const int k = blockIdx.x % kSlots;
+    unsafeAtomicAdd(gs + k, v[0]);
+    unsafeAtomicAdd(gs + kSlots + k, v[1]);
+  }
 }
 
-hipError_t cg_reliable(const VecLayout& L, const double* r64, float* r, float* u, float* w,
-                       const float* dinv, double* part, hipStream_t stream) {
-  hipLaunchKernelGGL(k_cg_reliable<float>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream, r64,
-                     r, u, w, dinv, part);
+hipError_t cg_reliable(const VecLayout& L, CgState st, int nsys, const double* r64, float* r,
+                       float* u, float* w, const float* dinv, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_reliable<float>, dim3((unsigned)L.nblk), dim3(kVecBlock), 0, stream,
+                     L.blk_seg, st, nsys, r64, r, u, w, dinv);
+  return hipGetLastError();
+}
+
+// Re-arm the systems that are still running after a reliable update: the
+// next update (which reads carried set 1) continues them from the new
+// residual; skipped systems stay stopped.
+__global__ void k_cg_rearm(CgState st, int nsys, const int32_t* __restrict__ skip) {
+  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sg >= nsys) return;
+  const int stop = skip != nullptr && skip[sg] != 0;
+  st.sdn[(int64_t)nsys + sg] = stop;
+  st.done[sg] = stop;
+}
+
+hipError_t cg_rearm(CgState st, int nsys, const int32_t* skip, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cg_rearm, dim3((nsys + 255) / 256), dim3(256), 0, stream, st, nsys, skip);
   return hipGetLastError();
 }
 
@@ -406,7 +425,6 @@ __global__ void __launch_bounds__(kVecBlock)
   if (threadIdx.x == 0) {
     if (st.rz) st.rz[s] = rzn;
     st.rr[s] = rrn;
-    if (st.beta) st.beta[s] = 0.0;
     if (st.iters) st.iters[s] = 0;
     if (st.done) st.done[s] = (st.tol2[s] >= 0.0 && rrn <= st.tol2[s]) ? 1 : 0;
     st.cnt[s] = 0;
@@ -745,15 +763,16 @@ hipError_t seg_out(int64_t n, const double* padded, double* user, hipStream_t s)
   return hipGetLastError();
 }
 
-template hipError_t cg_update<double>(const VecLayout&, CgState, double*, double*, double*,
-                                      double*, double*, double*, const double*, double*,
-                                      hipStream_t);
-template hipError_t cg_update<float>(const VecLayout&, CgState, float*, float*, float*, float*,
-                                     float*, float*, const float*, double*, hipStream_t);
-template hipError_t cg_start<double>(const VecLayout&, const double*, double*, double*, double*,
-                                     double*, double*, const double*, double*, hipStream_t);
-template hipError_t cg_start<float>(const VecLayout&, const double*, float*, float*, float*,
-                                    float*, float*, const float*, double*, hipStream_t);
+template hipError_t cg_update<double>(const VecLayout&, CgState, int, int, bool, const int32_t*,
+                                      double*, double*, double*, double*, double*, double*,
+                                      const double*, hipStream_t);
+template hipError_t cg_update<float>(const VecLayout&, CgState, int, int, bool, const int32_t*,
+                                     float*, float*, float*, float*, float*, float*, const float*,
+                                     hipStream_t);
+template hipError_t cg_start<double>(const VecLayout&, CgState, int, const double*, double*,
+                                     double*, double*, double*, double*, const double*, hipStream_t);
+template hipError_t cg_start<float>(const VecLayout&, CgState, int, const double*, float*, float*,
+                                    float*, float*, float*, const float*, hipStream_t);
 template hipError_t pad_in<double>(int, const int64_t*, const int64_t*, const VecLayout&,
                                    const double*, const double*, double*, hipStream_t);
 template hipError_t pad_in<float>(int, const int64_t*, const int64_t*, const VecLayout&,

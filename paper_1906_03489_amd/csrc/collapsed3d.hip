@@ -644,7 +644,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
       if (live && t == 0 && a.dots) {
         double s_ = 0.0;
         for (int k2 = 0; k2 < NS; ++k2) s_ += sred[slot * NS + k2];
-        a.dots[a.dslot ? a.dslot[e] : e] = s_;
+        add_dot(a.dots, a.dslot, e, s_);
       }
     }
     esync();

@@ -91,6 +91,11 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
 
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+// An assembled operator's element energy u_e.(H_e u_e) is added to the CG
+// accumulation slot dslot[e] of its system.
+__device__ __forceinline__ void add_dot(double* dots, const int32_t* dslot, int64_t e, double v) {
+  unsafeAtomicAdd(dots + dslot[e], v);
+}
 
 // Slot synchronisation.  When every slot lies inside one wavefront (NT
 // divides 64) only the owning wavefront touches the slot's LDS, and LDS
@@ -405,7 +410,7 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
       }
     }
     const double s = slot_sum<NT>(dp, red, slot, t);
-    if (live && t == 0 && a.dots) a.dots[a.dslot ? a.dslot[e] : e] = s;
+    if (live && t == 0 && a.dots) add_dot(a.dots, a.dslot, e, s);
   } else {
     if (pq) {
 #pragma unroll

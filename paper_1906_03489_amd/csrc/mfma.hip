@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(EPB * 64)
     if constexpr (ASM) {
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
-      if (l == 0 && a.dots) a.dots[a.dslot ? a.dslot[e] : e] = dp;
+      if (l == 0 && a.dots) add_dot(a.dots, a.dslot, e, dp);
     }
   }
 }

@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(EPB * Q)
         }
       }
       const double s = slot_sum<NT>(dp, red, slot, t);
-      if (live && t == 0 && a.dots) a.dots[a.dslot ? a.dslot[e] : e] = s;
+      if (live && t == 0 && a.dots) add_dot(a.dots, a.dslot, e, s);
     } else {
       if (live && t < N) {
 #pragma unroll

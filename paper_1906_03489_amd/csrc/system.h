@@ -11,19 +11,29 @@
 namespace nk {
 
 // Per-system CG scalars, structure of arrays over the nsys systems.
+// Accumulation slots per system for the CG reductions: one per thread of a
+// vector block, so that the atomics of a system's elements and blocks spread
+// over many addresses (13 824 elements put 54 additions on each).
+constexpr int kSlots = 256;
+
 struct CgState {
-  double* rz = nullptr;     // r . z
-  double* rr = nullptr;     // r . r
+  double* rz = nullptr;     // r . z of the latest update (host-visible)
+  double* rr = nullptr;     // r . r entering the latest update
   double* tol2 = nullptr;   // stop when rr <= tol2
   double* alpha = nullptr;
-  double* beta = nullptr;
   int32_t* done = nullptr;
   int32_t* iters = nullptr;
   int32_t* status = nullptr;
-  int32_t* cnt = nullptr;   // finished-block counter of the fused reduction
+  int32_t* cnt = nullptr;   // finished-block counter of the fused reductions (k_resid, k_norm2)
   int32_t* maxit = nullptr; // iteration budget of the current CG run (device, per system)
-  double* rz_prev = nullptr;     // r.z and alpha of the iteration before the last one
-  double* alpha_prev = nullptr;  // (a reliable update redoes the last step)
+  // rotating sets (see cg.hip): gamma / r.r slots [3][nsys][2][kSlots],
+  // delta slots [2][nsys][kSlots], carried scalars [2][nsys]
+  double* gsl = nullptr;
+  double* dsl = nullptr;
+  double* sgam = nullptr;
+  double* salp = nullptr;
+  int32_t* sit = nullptr;
+  int32_t* sdn = nullptr;
 };
 
 // Vector-kernel geometry: DOF ranges of every system are padded to multiples
@@ -37,23 +47,18 @@ struct VecLayout {
 
 // Kernel launchers (cg.hip).
 template <typename T>
-hipError_t cg_update(const VecLayout& L, CgState st, T* x, T* r, T* u, T* p, T* s, T* w,
-                     const T* dinv, double* part, hipStream_t stream);
+hipError_t cg_update(const VecLayout& L, CgState st, int nsys, int j, bool fatal,
+                     const int32_t* skip, T* x, T* r, T* u, T* p, T* s, T* w, const T* dinv,
+                     hipStream_t stream);
 template <typename T>
-hipError_t cg_start(const VecLayout& L, const double* b, T* w, T* r, T* u, T* p, T* s,
-                    const T* dinv, double* part, hipStream_t stream);
-hipError_t cg_finish(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
-                     const double* dots, CgState st, bool fatal, bool start,
-                     double tau2, const int32_t* outer_done, const double* outer_tol2,
-                     const double* outer_rr, hipStream_t stream);
-
-// the last CG step redone after a reliable update (see k_cg_finish, mode 2)
-hipError_t cg_finish_reliable(int nsys, const VecLayout& L, const VecLayout& Ld, const double* part,
-                              const double* dots, CgState st, const int32_t* outer_done,
-                              hipStream_t stream);
+hipError_t cg_start(const VecLayout& L, CgState st, int nsys, const double* b, T* w, T* r, T* u,
+                    T* p, T* s, const T* dinv, hipStream_t stream);
+hipError_t cg_begin_scalars(CgState st, int nsys, double tau2, const int32_t* skip,
+                            const double* outer_tol2, const double* outer_rr, hipStream_t stream);
 // r = (float) r64, u = M^{-1} r, w = 0, partial sums of (r, u) and (r, r)
-hipError_t cg_reliable(const VecLayout& L, const double* r64, float* r, float* u, float* w,
-                       const float* dinv, double* part, hipStream_t stream);
+hipError_t cg_reliable(const VecLayout& L, CgState st, int nsys, const double* r64, float* r,
+                       float* u, float* w, const float* dinv, hipStream_t stream);
+hipError_t cg_rearm(CgState st, int nsys, const int32_t* skip, hipStream_t stream);
 // r = (b - y) on free DOFs (dinv > 0), 0 elsewhere; y is reset to 0; optionally
 // p = 0; per system rz = r.dinv.r, rr = r.r; done = rr <= tol2.
 hipError_t cg_residual(const VecLayout& L, CgState st, const double* b, double* y,
@@ -106,13 +111,7 @@ struct nk_system_s {
   int64_t nuser = 0;                      // user global length (sum of system DOFs)
   std::vector<int64_t> dof_off, pdof_off, elem_off, blk_first;
   nk::VecLayout L;
-  // per-element p.Ap slots, padded per system like a vector
-  std::vector<int64_t> pdot_off, dblk_first;
-  nk::VecLayout Ld;
-  int64_t* d_dblk_first = nullptr;
-  int32_t* d_dblk_seg = nullptr;
-  int32_t* dslot = nullptr;
-  double* part_d = nullptr;
+  int32_t* dslot = nullptr;               // CG accumulation slot of each element
   int64_t* d_dof_off = nullptr;
   int64_t* d_pdof_off = nullptr;
   int64_t* d_elem_off = nullptr;
@@ -130,7 +129,6 @@ struct nk_system_s {
   double *u = nullptr, *s = nullptr;
   float *r32 = nullptr, *p32 = nullptr, *y32 = nullptr, *d32 = nullptr;
   float *u32 = nullptr, *s32 = nullptr;
-  double* dots = nullptr;                 // per element
   double* part = nullptr;                 // per vector block x 2
   // per-system scalars
   nk::CgState st64, st32;

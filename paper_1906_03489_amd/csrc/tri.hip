@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64) __attribute__((amdgpu_w
           double s = 0.0;
 #pragma unroll
           for (int jj = 0; jj < Q2; ++jj) s += sdot[wave * 64 + lane + jj];
-          a.dots[a.dslot ? a.dslot[e] : e] = s;
+          add_dot(a.dots, a.dslot, e, s);
         }
       }
       for (int k = lane; k < ne * NM; k += 64) {
