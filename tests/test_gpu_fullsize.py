@@ -65,7 +65,49 @@ def test_full_size_20000_mixed_orders_sampled():
             assert off == y.size
 
 
+def _check_256(xs, info, mode, tol, err_tol, ctx):
+    """NK_OK and the library's true residual <= tol for every system; the two
+    smallest systems against the oracle's direct solves; the largest by
+    oracle residuals at sampled free DOFs."""
+    P, Q, cfg, boxes, l2gs, dms, doff, b, small, large = ctx
+    assert len(info) == len(boxes)
+    worst = max(i["rel_resid"] for i in info)
+    assert all(i["status"] == 0 for i in info) and worst <= tol, (mode, worst)
+    for k in small:
+        lat = W.lattice(boxes[k])
+        ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], lat, cfg["warp"]), lam=1.0)
+        bk = b[doff[k]:doff[k + 1]]
+        ref = direct_solve(oracle.helmholtz_matrices(ops), l2gs[k], doff[k + 1] - doff[k], dms[k], bk)
+        assert rel_err(xs[doff[k]:doff[k + 1]], ref) < err_tol, (k, mode)
+    # the largest system: oracle residuals at sampled free DOFs
+    k = large
+    lat = W.lattice(boxes[k])
+    bk, xk, l2g, fixed = b[doff[k]:doff[k + 1]], xs[doff[k]:doff[k + 1]].copy(), l2gs[k], dms[k].astype(bool)
+    xk[fixed] = 0.0
+    sample = np.random.default_rng(44).choice(np.flatnonzero(~fixed), 10, replace=False)
+    hits = {int(g): np.argwhere(l2g == g) for g in sample}
+    elems = np.unique(np.concatenate([h[:, 0] for h in hits.values()]))
+    pos = {int(e): j for j, e in enumerate(elems)}
+    ops = oracle.ElementOps(3, P, Q, W.element_jacobians(
+        oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[elems]), cfg["warp"]), lam=1.0)
+    y = ops.helmholtz_action(xk[l2g[elems]])
+    habs = [np.abs(ops.helmholtz_matrix(j)) for j in range(len(elems))]
+    bn = np.linalg.norm(bk)
+    for g, h in hits.items():
+        Ag = sum(y[pos[int(e)], mm] for e, mm in h)
+        # |r_g| <= ||r||_2 <= tol ||b||_2, plus the rounding of the
+        # oracle's own sum (sqrt(k) u (|A||x|)_g, k = 8 n^3 terms)
+        absAg = sum((habs[pos[int(e)]] @ np.abs(xk[l2g[e]]))[mm] for e, mm in h)
+        allow = 2.0 * np.sqrt(8 * (P + 1) ** 3) * 2.0 ** -53 * absAg
+        assert abs(bk[g] - Ag) <= tol * bn + allow, (mode, g, abs(bk[g] - Ag) / bn)
+
+
 def test_full_size_256_solves_sampled():
+    """The 256 independent P=5 solves of the benchmark (log-uniform 64..4096
+    hexes each) at full size, in both launch configurations it times: one
+    batched system over one space, and the 256 systems created separately
+    (each its own space) passed to nk_cg_solve_batched; FP64 and FP32-refined
+    to 1e-10."""
     torch = torch_cuda()
     m = nk()
     cfg = W.CONFIGS[3]
@@ -85,49 +127,25 @@ def test_full_size_256_solves_sampled():
         eoff.append(eoff[-1] + lat.nelem)
         doff.append(doff[-1] + ng)
     space = m.Space.create(3, P, Q, J)
-    del J
     sysb = m.System.create_batched(space, eoff, doff,
                                    to_dev(np.concatenate([l + o for l, o in zip(l2gs, doff[:-1])]).astype(np.int32)),
                                    to_dev(np.concatenate(dms)), lam0=1.0)
     b = W.uniform(W.seed(3, 1), doff[-1])
     b[np.concatenate(dms).astype(bool)] = 0.0
     order = np.argsort(nel)
-    small, large = [int(k) for k in order[:2]], int(order[-1])
+    ctx = (P, Q, cfg, boxes, l2gs, dms, doff, b, [int(k) for k in order[:2]], int(order[-1]))
     # error <= cond(A) times the residual: 1e-6 leaves room for cond(A) up to 1e4
-    for mode, tol, err_tol in ((m.SOLVE_F64, 1e-10, 1e-6), (m.SOLVE_F32_REFINED, 1e-10, 1e-6)):
-        x, info = sysb.solve(to_dev(b), rtol=tol, maxit=50000, mode=mode)
-        xs = x.cpu().numpy()
-        assert len(info) == len(boxes)
-        # NK_OK: the library's recomputed FP64 true residual meets rtol
-        worst = max(i["rel_resid"] for i in info)
-        assert all(i["status"] == 0 for i in info) and worst <= tol, (mode, worst)
-        for k in small:
-            lat = W.lattice(boxes[k])
-            ops = oracle.ElementOps(3, P, Q, W.element_jacobians(oracle.gll(Q)[0], lat, cfg["warp"]), lam=1.0)
-            bk = b[doff[k]:doff[k + 1]]
-            ref = direct_solve(oracle.helmholtz_matrices(ops), l2gs[k], doff[k + 1] - doff[k], dms[k], bk)
-            assert rel_err(xs[doff[k]:doff[k + 1]], ref) < err_tol, (k, mode)
-        # the largest system: oracle residuals at sampled free DOFs
-        k = large
-        lat = W.lattice(boxes[k])
-        bk, xk, l2g, fixed = b[doff[k]:doff[k + 1]], xs[doff[k]:doff[k + 1]].copy(), l2gs[k], dms[k].astype(bool)
-        xk[fixed] = 0.0
-        sample = np.random.default_rng(44).choice(np.flatnonzero(~fixed), 10, replace=False)
-        hits = {int(g): np.argwhere(l2g == g) for g in sample}
-        elems = np.unique(np.concatenate([h[:, 0] for h in hits.values()]))
-        pos = {int(e): j for j, e in enumerate(elems)}
-        ops = oracle.ElementOps(3, P, Q, W.element_jacobians(
-            oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[elems]), cfg["warp"]), lam=1.0)
-        y = ops.helmholtz_action(xk[l2g[elems]])
-        habs = [np.abs(ops.helmholtz_matrix(j)) for j in range(len(elems))]
-        bn = np.linalg.norm(bk)
-        for g, h in hits.items():
-            Ag = sum(y[pos[int(e)], mm] for e, mm in h)
-            # |r_g| <= ||r||_2 <= tol ||b||_2, plus the rounding of the
-            # oracle's own sum (sqrt(k) u (|A||x|)_g, k = 8 n^3 terms)
-            absAg = sum((habs[pos[int(e)]] @ np.abs(xk[l2g[e]]))[mm] for e, mm in h)
-            allow = 2.0 * np.sqrt(8 * (P + 1) ** 3) * 2.0 ** -53 * absAg
-            assert abs(bk[g] - Ag) <= tol * bn + allow, (mode, g, abs(bk[g] - Ag) / bn)
+    for mode in (m.SOLVE_F64, m.SOLVE_F32_REFINED):
+        x, info = sysb.solve(to_dev(b), rtol=1e-10, maxit=50000, mode=mode)
+        _check_256(x.cpu().numpy(), info, mode, 1e-10, 1e-6, ctx)
+    # separately created systems in one nk_cg_solve_batched call
+    singles = [m.System.create(m.Space.create(3, P, Q, J[eoff[k]:eoff[k + 1]]), doff[k + 1] - doff[k],
+                               to_dev(l2gs[k]), to_dev(dms[k]), lam0=1.0) for k in range(len(boxes))]
+    del J
+    bs = [to_dev(b[doff[k]:doff[k + 1]]) for k in range(len(boxes))]
+    for mode in (m.SOLVE_F64, m.SOLVE_F32_REFINED):
+        xs, info = m.solve_batched(singles, bs, rtol=1e-10, maxit=50000, mode=mode)
+        _check_256(torch.cat(xs).cpu().numpy(), info, mode, 1e-10, 1e-6, ctx)
 
 
 def test_full_size_16c_gradient_kernel_sampled():
