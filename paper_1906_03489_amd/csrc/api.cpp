@@ -84,6 +84,7 @@ static int vector_tile_count(int op, int dim, int P) {
   if (dim == 3 && op_has_lean(op)) {
     c *= kHelmForms;                       // each candidate also lean and deep
     if (packed_epb3(P) > 0) c += 1;        // and the packed slots
+    if (helm_has_pt(P)) c *= 2;            // all again with the point-by-point I stage
   }
   return c;
 }
@@ -104,18 +105,26 @@ const char* tile_name(int op, int dim, int P, int tile) {
     std::snprintf(buf, sizeof buf, "mfma_epb2_thr128");
     return buf;
   }
+  const char* pt = "";
+  if (dim == 3 && op_has_lean(op) && helm_has_pt(P)) {
+    const int half = vector_tile_count(op, dim, P) / 2;
+    if (tile >= half) {
+      tile -= half;
+      pt = "_pt";
+    }
+  }
   const int form = dim == 3 && op_has_lean(op) ? tile / epb3_count(P) : 0;   // 0, lean, deep
   const int q = P + 2;
   const int q2 = q * q;
   if (form == kHelmForms) {
-    std::snprintf(buf, sizeof buf, "epb%d_thr%d_packed", packed_epb3(P), packed_epb3(P) * q2);
+    std::snprintf(buf, sizeof buf, "epb%d_thr%d_packed%s", packed_epb3(P), packed_epb3(P) * q2, pt);
     return buf;
   }
   if (dim == 3) tile %= epb3_count(P);
   const int epb = dim == 3 ? kTileEPB3[P][tile] : kTileEPB2[P][tile];
   const int slot = dim == 3 ? (q2 <= 16 ? 16 : q2 <= 64 ? 64 : q2) : q;
-  std::snprintf(buf, sizeof buf, "epb%d_thr%d%s", epb, epb * slot,
-                form == 1 ? "_lean" : form == 2 ? "_deep" : "");
+  std::snprintf(buf, sizeof buf, "epb%d_thr%d%s%s", epb, epb * slot,
+                form == 1 ? "_lean" : form == 2 ? "_deep" : "", pt);
   return buf;
 }
 

@@ -41,6 +41,168 @@ struct Tab {
   T D[Q * N];  // D[i*N + p] = phi_p'(x_i)
 };
 
+// Even-odd form of the 1-D tables (the even-odd decomposition of a matrix
+// that commutes with the reflection x -> -x, Solomonoff, "A fast algorithm
+// for spectral differentiation", J. Comput. Phys. 98, 1992).  The GLL points
+// are symmetric, x_{Q-1-i} = -x_i.  Of the modified modes, the interior ones
+// phi_p (0 < p < P) are even functions for odd p and odd functions for even
+// p, and the vertex pair splits into the even sum phi_0 + phi_P (= 1) and the
+// odd difference phi_0 - phi_P (= -x).  Coefficients c split into
+//   ce = (c_0 + c_P, c_1, c_3, ...)   (KE = P/2 + 1 entries)
+//   co = (c_0 - c_P, c_2, c_4, ...)   (KO = (P-1)/2 + 1 entries)
+// and for the first H = ceil(Q/2) points the half tables hold the members of
+// each set (vertex columns halved, so that one table serves a contraction
+// and its transpose):
+//   BE[i][0] = 1/2,     BE[i][m] = phi_{2m-1}(x_i),   DE[i][0] = 0,    DE[i][m] = phi'_{2m-1}(x_i)
+//   BO[i][0] = -x_i/2,  BO[i][m] = phi_{2m}(x_i),     DO[i][0] = -1/2, DO[i][m] = phi'_{2m}(x_i)
+// With E = BE.ce, O = BO.co: u(x_i) = E + O, u(x_{Q-1-i}) = E - O; with
+// Ed = DO.co, Od = DE.ce: u'(x_i) = Ed + Od, u'(x_{Q-1-i}) = Ed - Od.  A pair
+// of points costs N products instead of 2N.  The transposed contraction takes
+// v_i + v_{Q-1-i} and v_i - v_{Q-1-i} against the same tables; the middle
+// point of an odd Q (x = 0) meets only the even members and derivatives of
+// the odd ones.
+template <int N>
+struct EO {
+  static constexpr int P = N - 1;
+  static constexpr int KE = P / 2 + 1;
+  static constexpr int KO = (P - 1) / 2 + 1;
+};
+
+template <typename T, int N, int Q>
+struct TabH {
+  static constexpr int H = (Q + 1) / 2, KE = EO<N>::KE, KO = EO<N>::KO;
+  T BE[H * KE];
+  T BO[H * KO];
+  T DE[H * KE];
+  T DO[H * KO];
+};
+
+// Tables passed to the 3-D operator kernels: the half tables, and up to
+// N = kPtMaxN also the full ones, for the Helmholtz candidates that evaluate
+// the I stage point by point (fewer live registers than the paired loop,
+// which matters at low orders, where occupancy decides).
+template <typename T, int N, int Q, bool FULL = (N <= kPtMaxN)>
+struct TabK {
+  TabH<T, N, Q> h;
+  Tab<T, N, Q> f;
+};
+template <typename T, int N, int Q>
+struct TabK<T, N, Q, false> {
+  TabH<T, N, Q> h;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void eo_split(const T (&c)[N], T (&ce)[EO<N>::KE], T (&co)[EO<N>::KO]) {
+  ce[0] = c[0] + c[N - 1];
+  co[0] = c[0] - c[N - 1];
+#pragma unroll
+  for (int m = 1; m < EO<N>::KE; ++m) ce[m] = c[2 * m - 1];
+#pragma unroll
+  for (int m = 1; m < EO<N>::KO; ++m) co[m] = c[2 * m];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void eo_join(const T (&ye)[EO<N>::KE], const T (&yo)[EO<N>::KO], T (&y)[N]) {
+  y[0] = ye[0] + yo[0];
+  y[N - 1] = ye[0] - yo[0];
+#pragma unroll
+  for (int m = 1; m < EO<N>::KE; ++m) y[2 * m - 1] = ye[m];
+#pragma unroll
+  for (int m = 1; m < EO<N>::KO; ++m) y[2 * m] = yo[m];
+}
+
+// values at x_h and x_{Q-1-h}
+template <typename T, int N, int Q>
+__device__ __forceinline__ void eo_val(const TabH<T, N, Q>& tb, int h, const T (&ce)[EO<N>::KE],
+                                       const T (&co)[EO<N>::KO], T& lo, T& hi) {
+  constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
+  const T* be = tb.BE + h * KE;
+  const T* bo = tb.BO + h * KO;
+  T e = 0, o = 0;
+#pragma unroll
+  for (int m = 0; m < KE; ++m) e += be[m] * ce[m];
+#pragma unroll
+  for (int m = 0; m < KO; ++m) o += bo[m] * co[m];
+  lo = e + o;
+  hi = e - o;
+}
+
+// derivatives at x_h and x_{Q-1-h}
+template <typename T, int N, int Q>
+__device__ __forceinline__ void eo_der(const TabH<T, N, Q>& tb, int h, const T (&ce)[EO<N>::KE],
+                                       const T (&co)[EO<N>::KO], T& lo, T& hi) {
+  constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
+  const T* de = tb.DE + h * KE;
+  const T* dd = tb.DO + h * KO;
+  T e = 0, o = 0;
+#pragma unroll
+  for (int m = 0; m < KO; ++m) e += dd[m] * co[m];
+#pragma unroll
+  for (int m = 1; m < KE; ++m) o += de[m] * ce[m];
+  lo = e + o;
+  hi = e - o;
+}
+
+// value and derivative at the middle point of an odd Q
+template <typename T, int N, int Q>
+__device__ __forceinline__ T eo_mid_val(const TabH<T, N, Q>& tb, const T (&ce)[EO<N>::KE]) {
+  const T* be = tb.BE + (Q / 2) * EO<N>::KE;
+  T e = 0;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KE; ++m) e += be[m] * ce[m];
+  return e;
+}
+template <typename T, int N, int Q>
+__device__ __forceinline__ T eo_mid_der(const TabH<T, N, Q>& tb, const T (&co)[EO<N>::KO]) {
+  const T* dd = tb.DO + (Q / 2) * EO<N>::KO;
+  T e = 0;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KO; ++m) e += dd[m] * co[m];
+  return e;
+}
+
+// transposed: ye += BE[h] vp, yo += BO[h] vm (vp = v_h + v_{Q-1-h}, vm = v_h - v_{Q-1-h})
+template <typename T, int N, int Q>
+__device__ __forceinline__ void eo_acc(const TabH<T, N, Q>& tb, int h, T vp, T vm,
+                                       T (&ye)[EO<N>::KE], T (&yo)[EO<N>::KO]) {
+  const T* be = tb.BE + h * EO<N>::KE;
+  const T* bo = tb.BO + h * EO<N>::KO;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KE; ++m) ye[m] += be[m] * vp;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KO; ++m) yo[m] += bo[m] * vm;
+}
+// transposed derivative: ye += DE[h] wm, yo += DO[h] wp
+template <typename T, int N, int Q>
+__device__ __forceinline__ void eo_acc_d(const TabH<T, N, Q>& tb, int h, T wp, T wm,
+                                         T (&ye)[EO<N>::KE], T (&yo)[EO<N>::KO]) {
+  const T* de = tb.DE + h * EO<N>::KE;
+  const T* dd = tb.DO + h * EO<N>::KO;
+#pragma unroll
+  for (int m = 1; m < EO<N>::KE; ++m) ye[m] += de[m] * wm;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KO; ++m) yo[m] += dd[m] * wp;
+}
+// the middle point of an odd Q: value v, derivative weight w
+template <typename T, int N, int Q>
+__device__ __forceinline__ void eo_acc_mid(const TabH<T, N, Q>& tb, T v, T (&ye)[EO<N>::KE]) {
+  const T* be = tb.BE + (Q / 2) * EO<N>::KE;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KE; ++m) ye[m] += be[m] * v;
+}
+template <typename T, int N, int Q>
+__device__ __forceinline__ void eo_acc_mid_d(const TabH<T, N, Q>& tb, T w, T (&yo)[EO<N>::KO]) {
+  const T* dd = tb.DO + (Q / 2) * EO<N>::KO;
+#pragma unroll
+  for (int m = 0; m < EO<N>::KO; ++m) yo[m] += dd[m] * w;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void zero(T (&v)[K]) {
+#pragma unroll
+  for (int m = 0; m < K; ++m) v[m] = T(0);
+}
+
 template <typename T>
 struct DevArgs {
   int64_t nelem;
@@ -277,6 +439,153 @@ __device__ __forceinline__ void stage_kt(const Tab<T, N, Q>& tb, const T* __rest
   }
 }
 
+// The same four stages with the even-odd tables: each output pair (k, Q-1-k)
+// from one pass over the split pencil.  LDS layouts are those above.
+template <typename T, int N, int Q, bool DER>
+__device__ __forceinline__ void stage_k(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t, bool act,
+                                        const T (&xin)[N]) {
+  constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2;
+  if (act && t < NN) {
+    T xe[EO<N>::KE], xo[EO<N>::KO];
+    eo_split<T, N>(xin, xe, xo);
+#pragma unroll 2
+    for (int h = 0; h < HP; ++h) {
+      T lo, hi;
+      eo_val(tb, h, xe, xo, lo, hi);
+      sm[h * NN + t] = lo;
+      sm[(Q - 1 - h) * NN + t] = hi;
+      if constexpr (DER) {
+        eo_der(tb, h, xe, xo, lo, hi);
+        sm[S + h * NN + t] = lo;
+        sm[S + (Q - 1 - h) * NN + t] = hi;
+      }
+    }
+    if constexpr (Q & 1) {
+      sm[HP * NN + t] = eo_mid_val(tb, xe);
+      if constexpr (DER) sm[S + HP * NN + t] = eo_mid_der(tb, xo);
+    }
+  }
+}
+
+template <typename T, int N, int Q, int NT, bool DER>
+__device__ __forceinline__ void stage_j(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t, bool act) {
+  constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
+  const int pj = t % N, kj = t / N;
+  const bool me = act && t < N * Q;
+  T ae[KE], ao[KO], be[KE], bo[KO];
+  if (me) {
+    T av[N], bv[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      av[q] = sm[kj * NN + q * N + pj];
+      if constexpr (DER) bv[q] = sm[S + kj * NN + q * N + pj];
+    }
+    eo_split<T, N>(av, ae, ao);
+    if constexpr (DER) eo_split<T, N>(bv, be, bo);
+  }
+  slot_sync<NT>();
+  if (me) {
+    const int o0 = kj * Q * N + pj;
+#pragma unroll 2
+    for (int h = 0; h < HP; ++h) {
+      const int ol = o0 + h * N, oh = o0 + (Q - 1 - h) * N;
+      T lo, hi;
+      eo_val(tb, h, ae, ao, lo, hi);
+      sm[ol] = lo;
+      sm[oh] = hi;
+      if constexpr (DER) {
+        eo_der(tb, h, ae, ao, lo, hi);
+        sm[S + ol] = lo;
+        sm[S + oh] = hi;
+        eo_val(tb, h, be, bo, lo, hi);
+        sm[2 * S + ol] = lo;
+        sm[2 * S + oh] = hi;
+      }
+    }
+    if constexpr (Q & 1) {
+      const int om = o0 + HP * N;
+      sm[om] = eo_mid_val(tb, ae);
+      if constexpr (DER) {
+        sm[S + om] = eo_mid_der(tb, ao);
+        sm[2 * S + om] = eo_mid_val(tb, be);
+      }
+    }
+  }
+}
+
+template <typename T, int N, int Q, int NT, bool DER>
+__device__ __forceinline__ void stage_jt(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t,
+                                         bool act) {
+  constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
+  const int pj = t % N, kj = t / N;
+  const bool me = act && t < N * Q;
+  T tBe[KE], tBo[KO], tDe[KE], tDo[KO];
+  zero(tBe);
+  zero(tBo);
+  zero(tDe);
+  zero(tDo);
+  if (me) {
+    const int o0 = kj * Q * N + pj;
+#pragma unroll 2
+    for (int h = 0; h < HP; ++h) {
+      const int ol = o0 + h * N, oh = o0 + (Q - 1 - h) * N;
+      const T a1 = sm[ol], a2 = sm[oh];
+      eo_acc(tb, h, a1 + a2, a1 - a2, tBe, tBo);
+      if constexpr (DER) {
+        const T b1 = sm[S + ol], b2 = sm[S + oh], c1 = sm[2 * S + ol], c2 = sm[2 * S + oh];
+        eo_acc_d(tb, h, b1 + b2, b1 - b2, tBe, tBo);
+        eo_acc(tb, h, c1 + c2, c1 - c2, tDe, tDo);
+      }
+    }
+    if constexpr (Q & 1) {
+      const int om = o0 + HP * N;
+      eo_acc_mid(tb, sm[om], tBe);
+      if constexpr (DER) {
+        eo_acc_mid_d(tb, sm[S + om], tBo);
+        eo_acc_mid(tb, sm[2 * S + om], tDe);
+      }
+    }
+  }
+  slot_sync<NT>();
+  if (me) {
+    T tB[N];
+    eo_join<T, N>(tBe, tBo, tB);
+#pragma unroll
+    for (int q = 0; q < N; ++q) sm[kj * NN + q * N + pj] = tB[q];
+    if constexpr (DER) {
+      T tD[N];
+      eo_join<T, N>(tDe, tDo, tD);
+#pragma unroll
+      for (int q = 0; q < N; ++q) sm[S + kj * NN + q * N + pj] = tD[q];
+    }
+  }
+}
+
+template <typename T, int N, int Q, bool DER>
+__device__ __forceinline__ void stage_kt(const TabH<T, N, Q>& tb, const T* __restrict__ sm, int t,
+                                         bool act, T (&yv)[N]) {
+  constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
+  T ye[KE], yo[KO];
+  zero(ye);
+  zero(yo);
+  if (act && t < NN) {
+#pragma unroll 2
+    for (int h = 0; h < HP; ++h) {
+      const T a1 = sm[h * NN + t], a2 = sm[(Q - 1 - h) * NN + t];
+      eo_acc(tb, h, a1 + a2, a1 - a2, ye, yo);
+      if constexpr (DER) {
+        const T b1 = sm[S + h * NN + t], b2 = sm[S + (Q - 1 - h) * NN + t];
+        eo_acc_d(tb, h, b1 + b2, b1 - b2, ye, yo);
+      }
+    }
+    if constexpr (Q & 1) {
+      eo_acc_mid(tb, sm[HP * NN + t], ye);
+      if constexpr (DER) eo_acc_mid_d(tb, sm[S + HP * NN + t], yo);
+    }
+  }
+  eo_join<T, N>(ye, yo, yv);
+}
+
 // Sum of v over the threads of a slot, valid in thread t == 0 of the slot.
 template <int NT>
 __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int t) {
@@ -303,11 +612,12 @@ __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int 
 // i is processed (PF = 1: none, fewest registers).  Local store or (ASM)
 // atomic scatter-add into the global vector with the element's
 // p_e . (H_e p_e).
-template <typename T, int N, int Q, int NT, bool ASM, int PF = 2>
-__device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
+template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true, typename TB>
+__device__ __forceinline__ void helm3_body(const TB& tk, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
                                            const DevArgs<T>& a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q;
+  const TabH<T, N, Q>& tb = tk.h;
   const int64_t ee = live ? e : 0;
   const bool pq = live && t < NN;
   int32_t gidx[N];
@@ -333,52 +643,129 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
   stage_j<T, N, Q, NT, true>(tb, sm, t, live);
   slot_sync<NT>();
   const bool jk = live && t < QQ;
-  T av[N], bv[N], cv[N], sa[N], sb[N], sc[N];
-#pragma unroll
-  for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
-  if (jk) {
-    load_i<T, N, Q, true>(sm, t, av, bv, cv);
-    const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
-    const T* fp = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
-    // one point: forward I contraction, factors, transposed I contraction
-    auto point = [&](int i, const T (&f)[kNF3]) {
-      const T* Bi = tb.B + i * N;
-      const T* Di = tb.D + i * N;
-      T u = 0, u1 = 0, u2 = 0, u3 = 0;
-#pragma unroll
-      for (int p = 0; p < N; ++p) {
-        u += Bi[p] * av[p];
-        u1 += Di[p] * av[p];
-        u2 += Bi[p] * bv[p];
-        u3 += Bi[p] * cv[p];
+  T sa[N], sb[N], sc[N];
+  if constexpr (EOI) {
+    constexpr int HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
+    // accumulators of the transposed I contraction, in split form
+    T sae[KE], sao[KO], sbe[KE], sbo[KO], sce[KE], sco[KO];
+    zero(sae);
+    zero(sao);
+    zero(sbe);
+    zero(sbo);
+    zero(sce);
+    zero(sco);
+    if (jk) {
+      T ae[KE], ao[KO], be[KE], bo[KO], ce[KE], co[KO];
+      {
+        T av[N], bv[N], cv[N];
+        load_i<T, N, Q, true>(sm, t, av, bv, cv);
+        eo_split<T, N>(av, ae, ao);
+        eo_split<T, N>(bv, be, bo);
+        eo_split<T, N>(cv, ce, co);
       }
-      const T m = lam * f[0] * u;
-      const T g1 = f[1] * u1 + f[2] * u2 + f[3] * u3;
-      const T g2 = f[2] * u1 + f[4] * u2 + f[5] * u3;
-      const T g3 = f[3] * u1 + f[5] * u2 + f[6] * u3;
+      const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
+      const T* fp = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
+      // The points are visited in pairs (h, Q-1-h), then the middle one of an
+      // odd Q: sequence position s is point s/2 (even s) or Q-1-s/2 (odd s).
+      auto load = [&](int s, T (&f)[kNF3]) {
+        const int sc = s < Q ? s : Q - 1;
+        const int i = (sc & 1) ? Q - 1 - (sc >> 1) : (sc >> 1);
 #pragma unroll
-      for (int p = 0; p < N; ++p) {
-        sa[p] += Bi[p] * m + Di[p] * g1;
-        sb[p] += Bi[p] * g2;
-        sc[p] += Bi[p] * g3;
-      }
-    };
-    auto load = [&](int i, T (&f)[kNF3]) {
+        for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
+      };
+      // factors with the mass term and the gradient: r = (m, g1, g2, g3)
+      auto pointwise = [&](const T (&f)[kNF3], T u, T u1, T u2, T u3, T (&r)[4]) {
+        r[0] = lam * f[0] * u;
+        r[1] = f[1] * u1 + f[2] * u2 + f[3] * u3;
+        r[2] = f[2] * u1 + f[4] * u2 + f[5] * u3;
+        r[3] = f[3] * u1 + f[5] * u2 + f[6] * u3;
+      };
+      // PF register sets hold the factors of sequence positions s .. s+PF-1;
+      // before position s is computed, the loads of s+PF-1 go into the set
+      // that s-1 has just released.  One loop trip covers L positions, a
+      // multiple of 2 (a pair) and of PF (so every set index is a constant).
+      constexpr int L = (PF % 2 == 0) ? PF : 2 * PF;
+      constexpr int PP = L / 2;
+      T f[PF][kNF3];
 #pragma unroll
-      for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
-    };
-    if constexpr (PF == 1) {
+      for (int s = 0; s + 1 < PF; ++s) load(s, f[s]);
 #pragma unroll 1
-      for (int i = 0; i < Q; ++i) {
-        T f[kNF3];
-        load(i, f);
-        point(i, f);
+      for (int h0 = 0; h0 < HP; h0 += PP) {
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+          const int h = h0 + q;
+          if (HP % PP == 0 || h < HP) {
+            T ul[4], uh[4], rl[4], rh[4];
+            eo_val(tb, h, ae, ao, ul[0], uh[0]);
+            eo_der(tb, h, ae, ao, ul[1], uh[1]);
+            eo_val(tb, h, be, bo, ul[2], uh[2]);
+            eo_val(tb, h, ce, co, ul[3], uh[3]);
+            load(2 * h + PF - 1, f[(2 * q + PF - 1) % PF]);
+            pointwise(f[(2 * q) % PF], ul[0], ul[1], ul[2], ul[3], rl);
+            load(2 * h + PF, f[(2 * q + PF) % PF]);
+            pointwise(f[(2 * q + 1) % PF], uh[0], uh[1], uh[2], uh[3], rh);
+            eo_acc(tb, h, rl[0] + rh[0], rl[0] - rh[0], sae, sao);
+            eo_acc_d(tb, h, rl[1] + rh[1], rl[1] - rh[1], sae, sao);
+            eo_acc(tb, h, rl[2] + rh[2], rl[2] - rh[2], sbe, sbo);
+            eo_acc(tb, h, rl[3] + rh[3], rl[3] - rh[3], sce, sco);
+          }
+        }
       }
-    } else {
-      // set s holds point i+s; before point i+s is computed, the loads of
-      // point i+s+PF-1 go into the set that point i+s-1 has just released.
-      // Loads are unconditional (clamped index) so that the waits for them
-      // can be placed right before their first use.
+      if constexpr (Q & 1) {
+        load(2 * HP + PF - 1, f[(2 * HP + PF - 1) % PF]);
+        T r[4];
+        pointwise(f[(2 * HP) % PF], eo_mid_val(tb, ae), eo_mid_der(tb, ao), eo_mid_val(tb, be),
+                  eo_mid_val(tb, ce), r);
+        eo_acc_mid(tb, r[0], sae);
+        eo_acc_mid_d(tb, r[1], sao);
+        eo_acc_mid(tb, r[2], sbe);
+        eo_acc_mid(tb, r[3], sce);
+      }
+    }
+    eo_join<T, N>(sae, sao, sa);
+    eo_join<T, N>(sbe, sbo, sb);
+    eo_join<T, N>(sce, sco, sc);
+  } else {
+    static_assert(N <= kPtMaxN, "point-by-point I stage needs the full tables");
+#pragma unroll
+    for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
+    if (jk) {
+      const Tab<T, N, Q>& tf = tk.f;
+      T av[N], bv[N], cv[N];
+      load_i<T, N, Q, true>(sm, t, av, bv, cv);
+      const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
+      const T* fp = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
+      // one point: forward I contraction, factors, transposed I contraction
+      auto point = [&](int i, const T (&f)[kNF3]) {
+        const T* Bi = tf.B + i * N;
+        const T* Di = tf.D + i * N;
+        T u = 0, u1 = 0, u2 = 0, u3 = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          u += Bi[p] * av[p];
+          u1 += Di[p] * av[p];
+          u2 += Bi[p] * bv[p];
+          u3 += Bi[p] * cv[p];
+        }
+        const T m = lam * f[0] * u;
+        const T g1 = f[1] * u1 + f[2] * u2 + f[3] * u3;
+        const T g2 = f[2] * u1 + f[4] * u2 + f[5] * u3;
+        const T g3 = f[3] * u1 + f[5] * u2 + f[6] * u3;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          sa[p] += Bi[p] * m + Di[p] * g1;
+          sb[p] += Bi[p] * g2;
+          sc[p] += Bi[p] * g3;
+        }
+      };
+      auto load = [&](int i, T (&f)[kNF3]) {
+#pragma unroll
+        for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
+      };
+      // PF register sets: before point i+s is computed, the loads of point
+      // i+s+PF-1 go into the set that point i+s-1 has just released; loads
+      // are unconditional (clamped index) so that their waits sit right
+      // before their first use
       T f[PF][kNF3];
 #pragma unroll
       for (int s = 0; s + 1 < PF; ++s) load(s < Q ? s : Q - 1, f[s]);
@@ -427,11 +814,13 @@ constexpr int slot_threads() {
 }
 
 // NTX: threads per slot, 0 for slot_threads<Q>(); Q*Q packs slots without
-// idle lanes at the price of block barriers (Q*Q does not divide 64).
-template <typename T, int N, int Q, int EPB, int OP, int PF = 2, int NTX = 0>
+// idle lanes at the price of block barriers (Q*Q does not divide 64).  EOI:
+// the Helmholtz I stage in even-odd pairs (else point by point).
+template <typename T, int N, int Q, int EPB, int OP, int PF = 2, int NTX = 0, bool EOI = true>
 __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
-    k_op3(const Tab<T, N, Q> tb, const DevArgs<T> a) {
+    k_op3(const TabK<T, N, Q> tk, const DevArgs<T> a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q, S = Q * Q * N;
+  const TabH<T, N, Q>& tb = tk.h;
   constexpr int NT = NTX ? NTX : slot_threads<Q>();
   constexpr bool DER = (OP == OP_HELM || OP == OP_HELM_ASM || OP == OP_GRAD || OP == OP_RHS);
   constexpr int NTEN = DER ? 3 : 1;
@@ -461,18 +850,22 @@ __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
     slot_sync<NT>();
     stage_j<T, N, Q, NT, false>(tb, sm, t, live);
     slot_sync<NT>();
-    T av[N], bv[N], cv[N];
-    if (live && t < QQ) load_i<T, N, Q, false>(sm, t, av, bv, cv);
+    T ae[EO<N>::KE], ao[EO<N>::KO];
+    if (live && t < QQ) {
+      T av[N], bv[N], cv[N];
+      load_i<T, N, Q, false>(sm, t, av, bv, cv);
+      eo_split<T, N>(av, ae, ao);
+    }
     slot_sync<NT>();
     if (live && t < QQ) {
 #pragma unroll 2
-      for (int i = 0; i < Q; ++i) {
-        const T* Bi = tb.B + i * N;
-        T u = 0;
-#pragma unroll
-        for (int p = 0; p < N; ++p) u += Bi[p] * av[p];
-        sm[t * Q + i] = u;
+      for (int h = 0; h < Q / 2; ++h) {
+        T lo, hi;
+        eo_val(tb, h, ae, ao, lo, hi);
+        sm[t * Q + h] = lo;
+        sm[t * Q + Q - 1 - h] = hi;
       }
+      if constexpr (Q & 1) sm[t * Q + Q / 2] = eo_mid_val(tb, ae);
     }
     slot_sync<NT>();
     // the slot writes its Q^3 point values contiguously
@@ -486,18 +879,20 @@ __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
       for (int c = t; c < Q3; c += NT) sm[c] = f[c];
     }
     slot_sync<NT>();
-    T sa[N];
-#pragma unroll
-    for (int p = 0; p < N; ++p) sa[p] = T(0);
+    T se[EO<N>::KE], so[EO<N>::KO];
+    zero(se);
+    zero(so);
     if (live && t < QQ) {
 #pragma unroll 2
-      for (int i = 0; i < Q; ++i) {
-        const T m = fe[i * QQ] * sm[t * Q + i];
-        const T* Bi = tb.B + i * N;
-#pragma unroll
-        for (int p = 0; p < N; ++p) sa[p] += Bi[p] * m;
+      for (int h = 0; h < Q / 2; ++h) {
+        const T ml = fe[h * QQ] * sm[t * Q + h];
+        const T mh = fe[(Q - 1 - h) * QQ] * sm[t * Q + Q - 1 - h];
+        eo_acc(tb, h, ml + mh, ml - mh, se, so);
       }
+      if constexpr (Q & 1) eo_acc_mid(tb, fe[(Q / 2) * QQ] * sm[t * Q + Q / 2], se);
     }
+    T sa[N];
+    eo_join<T, N>(se, so, sa);
     slot_sync<NT>();
     if (live && t < QQ) store_i<T, N, Q, false>(sm, t, sa, sa, sa);
     slot_sync<NT>();
@@ -510,32 +905,51 @@ __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
       for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   } else if constexpr (OP == OP_HELM || OP == OP_HELM_ASM) {
-    helm3_body<T, N, Q, NT, ASM, PF>(tb, sm, red, slot, t, live, e, a);
+    helm3_body<T, N, Q, NT, ASM, PF, EOI>(tk, sm, red, slot, t, live, e, a);
   } else if constexpr (OP == OP_RHS) {
     const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
-    T sa[N], sb[N], sc[N];
-#pragma unroll
-    for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
+    constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
+    T sae[KE], sao[KO], sbe[KE], sbo[KO], sce[KE], sco[KO];
+    zero(sae);
+    zero(sao);
+    zero(sbe);
+    zero(sbo);
+    zero(sce);
+    zero(sco);
     if (live && t < QQ) {
       const T* uu = a.in + ee * Q3 + t * Q;
       const double* du = a.in2 + ee * 3 * Q3 + t * Q;
-#pragma unroll 1
-      for (int i = 0; i < Q; ++i) {
+      // (m, g1, g2, g3) at point i
+      auto point = [&](int i, T (&r)[4]) {
         const T* fp = fe + i * QQ;
         const T d1 = du[i], d2 = du[Q3 + i], d3 = du[2 * Q3 + i];
-        const T m = lam * fp[0] * uu[i];
-        const T g1 = fp[Q3] * d1 + fp[2 * Q3] * d2 + fp[3 * Q3] * d3;
-        const T g2 = fp[2 * Q3] * d1 + fp[4 * Q3] * d2 + fp[5 * Q3] * d3;
-        const T g3 = fp[3 * Q3] * d1 + fp[5 * Q3] * d2 + fp[6 * Q3] * d3;
-        const T* Bi = tb.B + i * N;
-        const T* Di = tb.D + i * N;
-#pragma unroll
-        for (int p = 0; p < N; ++p) {
-          sa[p] += Bi[p] * m + Di[p] * g1;
-          sb[p] += Bi[p] * g2;
-          sc[p] += Bi[p] * g3;
-        }
+        r[0] = lam * fp[0] * uu[i];
+        r[1] = fp[Q3] * d1 + fp[2 * Q3] * d2 + fp[3 * Q3] * d3;
+        r[2] = fp[2 * Q3] * d1 + fp[4 * Q3] * d2 + fp[5 * Q3] * d3;
+        r[3] = fp[3 * Q3] * d1 + fp[5 * Q3] * d2 + fp[6 * Q3] * d3;
+      };
+#pragma unroll 1
+      for (int h = 0; h < Q / 2; ++h) {
+        T rl[4], rh[4];
+        point(h, rl);
+        point(Q - 1 - h, rh);
+        eo_acc(tb, h, rl[0] + rh[0], rl[0] - rh[0], sae, sao);
+        eo_acc_d(tb, h, rl[1] + rh[1], rl[1] - rh[1], sae, sao);
+        eo_acc(tb, h, rl[2] + rh[2], rl[2] - rh[2], sbe, sbo);
+        eo_acc(tb, h, rl[3] + rh[3], rl[3] - rh[3], sce, sco);
       }
+      if constexpr (Q & 1) {
+        T r[4];
+        point(Q / 2, r);
+        eo_acc_mid(tb, r[0], sae);
+        eo_acc_mid_d(tb, r[1], sao);
+        eo_acc_mid(tb, r[2], sbe);
+        eo_acc_mid(tb, r[3], sce);
+      }
+      T sa[N], sb[N], sc[N];
+      eo_join<T, N>(sae, sao, sa);
+      eo_join<T, N>(sbe, sbo, sb);
+      eo_join<T, N>(sce, sco, sc);
       store_i<T, N, Q, true>(sm, t, sa, sb, sc);
     }
     slot_sync<NT>();
@@ -572,23 +986,17 @@ __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
     }
     double dl = 0.0;
     if (live && t < QQ) {
-      const double* kap = a.kappa ? a.kappa + ee * Q3 + t * Q : nullptr;
-#pragma unroll 1
-      for (int i = 0; i < Q; ++i) {
-        const T* Bi = tb.B + i * N;
-        const T* Di = tb.D + i * N;
-        T z = 0, z1 = 0, z2 = 0, z3 = 0, u = 0, u1 = 0, u2 = 0, u3 = 0;
+      constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
+      T ze[3][KE], zo[3][KO], ue[3][KE], uo[3][KO];
 #pragma unroll
-        for (int p = 0; p < N; ++p) {
-          z += Bi[p] * zv[0][p];
-          z1 += Di[p] * zv[0][p];
-          z2 += Bi[p] * zv[1][p];
-          z3 += Bi[p] * zv[2][p];
-          u += Bi[p] * uv[0][p];
-          u1 += Di[p] * uv[0][p];
-          u2 += Bi[p] * uv[1][p];
-          u3 += Bi[p] * uv[2][p];
-        }
+      for (int c = 0; c < 3; ++c) {
+        eo_split<T, N>(zv[c], ze[c], zo[c]);
+        eo_split<T, N>(uv[c], ue[c], uo[c]);
+      }
+      const double* kap = a.kappa ? a.kappa + ee * Q3 + t * Q : nullptr;
+      // z, dz (reference gradient), u, du at point i -> dkappa, and the mass
+      // term's share of dlambda
+      auto point = [&](int i, T z, T z1, T z2, T z3, T u, T u1, T u2, T u3) {
         const T* fp = fe + i * QQ;
         const T ik = kap ? T(1) / (T)kap[i] : T(1);
         const T G11 = fp[Q3] * ik, G12 = fp[2 * Q3] * ik, G13 = fp[3 * Q3] * ik,
@@ -598,6 +1006,25 @@ __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
         const T q3 = G13 * u1 + G23 * u2 + G33 * u3;
         if (a.out) a.out[ee * Q3 + t * Q + i] = -(z1 * q1 + z2 * q2 + z3 * q3);
         dl += (double)(fp[0] * z * u);
+      };
+#pragma unroll 1
+      for (int h = 0; h < Q / 2; ++h) {
+        T zl[4], zh[4], ul[4], uh[4];
+        eo_val(tb, h, ze[0], zo[0], zl[0], zh[0]);
+        eo_der(tb, h, ze[0], zo[0], zl[1], zh[1]);
+        eo_val(tb, h, ze[1], zo[1], zl[2], zh[2]);
+        eo_val(tb, h, ze[2], zo[2], zl[3], zh[3]);
+        eo_val(tb, h, ue[0], uo[0], ul[0], uh[0]);
+        eo_der(tb, h, ue[0], uo[0], ul[1], uh[1]);
+        eo_val(tb, h, ue[1], uo[1], ul[2], uh[2]);
+        eo_val(tb, h, ue[2], uo[2], ul[3], uh[3]);
+        point(h, zl[0], zl[1], zl[2], zl[3], ul[0], ul[1], ul[2], ul[3]);
+        point(Q - 1 - h, zh[0], zh[1], zh[2], zh[3], uh[0], uh[1], uh[2], uh[3]);
+      }
+      if constexpr (Q & 1) {
+        point(Q / 2, eo_mid_val(tb, ze[0]), eo_mid_der(tb, zo[0]), eo_mid_val(tb, ze[1]),
+              eo_mid_val(tb, ze[2]), eo_mid_val(tb, ue[0]), eo_mid_der(tb, uo[0]),
+              eo_mid_val(tb, ue[1]), eo_mid_val(tb, ue[2]));
       }
     }
     const double s = slot_sum<NT>(dl, red, slot, t);

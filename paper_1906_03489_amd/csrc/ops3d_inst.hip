@@ -13,17 +13,43 @@
 
 namespace nk {
 
-template <typename T, int P, int EPB, int OP, int PF = 2, int NTX = 0>
+template <typename T, int P, int EPB, int OP, int PF = 2, int NTX = 0, bool EOI = true>
 static hipError_t run3(const OpArgs& a) {
   constexpr int N = P + 1, Q = P + 2;
   static_assert(EPB > 0, "tile");
-  const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
+  const TabK<T, N, Q>& tb = host_tabk<T, N, Q>();
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, PF, NTX>), dim3((unsigned)nblk),
+  hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, PF, NTX, EOI>), dim3((unsigned)nblk),
                      dim3(EPB * (NTX ? NTX : slot_threads<Q>())), 0,
                      a.stream, tb, dev_args<T>(a));
   return hipGetLastError();
+}
+
+// The Helmholtz candidates of one I-stage form (EOI: even-odd pairs, else
+// point by point); tile counts from 0 within the form.
+template <typename T, int P, int OP, bool EOI>
+static hipError_t run3_helm(const OpArgs& a) {
+  constexpr int E0 = kTileEPB3[P][0], E1 = kTileEPB3[P][1], E2 = kTileEPB3[P][2];
+  constexpr int NE = epb3_count(P);
+  constexpr int EPK = packed_epb3(P);
+  if constexpr (EPK > 0) {   // the packed slots, after the three factor-set forms
+    if (a.tile == kHelmForms * NE) return run3<T, P, EPK, OP, 2, (P + 2) * (P + 2), EOI>(a);
+  }
+  if (a.tile >= NE) {   // candidates NE.. : one factor set, then four
+    const int k = (a.tile - NE) % NE;
+    if (a.tile >= 2 * NE) {
+      if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, kDeepPF, 0, EOI>(a);
+      if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, kDeepPF, 0, EOI>(a);
+      return run3<T, P, E0, OP, kDeepPF, 0, EOI>(a);
+    }
+    if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, 1, 0, EOI>(a);
+    if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, 1, 0, EOI>(a);
+    return run3<T, P, E0, OP, 1, 0, EOI>(a);
+  }
+  if (a.tile == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, 2, 0, EOI>(a);
+  if (a.tile == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, 2, 0, EOI>(a);
+  return run3<T, P, E0, OP, 2, 0, EOI>(a);
 }
 
 template <typename T, int P, int OP>
@@ -31,21 +57,15 @@ static hipError_t run3_tiled(const OpArgs& a) {
   constexpr int E0 = kTileEPB3[P][0], E1 = kTileEPB3[P][1], E2 = kTileEPB3[P][2];
   constexpr int NE = epb3_count(P);
   if constexpr (op_has_lean(OP)) {
-    constexpr int EPK = packed_epb3(P);
-    if constexpr (EPK > 0) {   // the packed slots, after the three factor-set forms
-      if (a.tile == kHelmForms * NE) return run3<T, P, EPK, OP, 2, (P + 2) * (P + 2)>(a);
-    }
-    if (a.tile >= NE) {   // candidates NE.. : one factor set, then four
-      const int k = (a.tile - NE) % NE;
-      if (a.tile >= 2 * NE) {
-        if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, kDeepPF>(a);
-        if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, kDeepPF>(a);
-        return run3<T, P, E0, OP, kDeepPF>(a);
+    constexpr int NH = kHelmForms * NE + (packed_epb3(P) > 0 ? 1 : 0);   // candidates per form
+    if constexpr (helm_has_pt(P)) {
+      if (a.tile >= NH) {
+        OpArgs b = a;
+        b.tile -= NH;
+        return run3_helm<T, P, OP, false>(b);
       }
-      if (k == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP, 1>(a);
-      if (k == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP, 1>(a);
-      return run3<T, P, E0, OP, 1>(a);
     }
+    return run3_helm<T, P, OP, true>(a);
   }
   if (a.tile == 1 && E1 > 0) return run3<T, P, (E1 > 0 ? E1 : 1), OP>(a);
   if (a.tile == 2 && E2 > 0) return run3<T, P, (E2 > 0 ? E2 : 1), OP>(a);

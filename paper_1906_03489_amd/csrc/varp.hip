@@ -5,16 +5,22 @@
 // dispatching each item to the sum-factorised body compiled for its order.
 // The 1-D tables of every order live in __constant__ memory so that the
 // uniform table reads go through the scalar cache.
+#include <cstring>
 #include <vector>
 
 #include "engine.h"
+#include "tables.h"
 #include "tiles.h"
 
 namespace nk {
 
+// scalars of the even-odd half tables of order p (TabH<T, p + 1, p + 2>)
+constexpr int varp_tab_len(int p) {
+  return 2 * ((p + 3) / 2) * ((p / 2 + 1) + ((p - 1) / 2 + 1));
+}
 constexpr int varp_tab_off(int P) {
   int off = 0;
-  for (int p = 1; p < P; ++p) off += 2 * (p + 2) * (p + 1);
+  for (int p = 1; p < P; ++p) off += varp_tab_len(p);
   return off;
 }
 constexpr int kVarpTabLen = varp_tab_off(kMaxP + 1);
@@ -62,7 +68,10 @@ __device__ __forceinline__ void varp_body(const VarpDev<T>& a, const VarpGroup& 
   const int t = threadIdx.x - slot * NT;
   const int64_t e = li * EPB + slot;
   const bool live = slot < EPB && e < G.nelem;
-  const Tab<T, N, Q>& tb = *reinterpret_cast<const Tab<T, N, Q>*>(ctab<T>() + varp_tab_off(P));
+  // the half tables only (the paired I stage), TabK's layout without the full tables
+  using TK = TabK<T, N, Q, false>;
+  static_assert(sizeof(TK) == sizeof(T) * varp_tab_len(P), "varp table layout");
+  const TK& tb = *reinterpret_cast<const TK*>(ctab<T>() + varp_tab_off(P));
   DevArgs<T> d{};
   d.nelem = G.nelem;
   d.in = a.x + G.c0;
@@ -108,6 +117,16 @@ int varp_items_per_group(int P, int64_t nelem) {
   return (int)((nelem + epb - 1) / epb);
 }
 
+template <int P>
+static void put_tabs(double* t64, float* t32) {
+  if constexpr (P <= kMaxP) {
+    constexpr int N = P + 1, Q = P + 2;
+    std::memcpy(t64 + varp_tab_off(P), &host_tabh<double, N, Q>(), sizeof(TabH<double, N, Q>));
+    std::memcpy(t32 + varp_tab_off(P), &host_tabh<float, N, Q>(), sizeof(TabH<float, N, Q>));
+    put_tabs<P + 1>(t64, t32);
+  }
+}
+
 // Upload the tables of every order to this device's __constant__ memory once.
 static hipError_t ensure_varp_tables() {
   static thread_local int done_dev_mask = 0;  // per-thread cache; cheap to redo
@@ -117,19 +136,7 @@ static hipError_t ensure_varp_tables() {
   if (dev < 30 && (done_dev_mask >> dev) & 1) return hipSuccess;
   std::vector<double> t64(kVarpTabLen);
   std::vector<float> t32(kVarpTabLen);
-  for (int P = 1; P <= kMaxP; ++P) {
-    const int N = P + 1, Q = P + 2;
-    std::vector<double> x(Q), w(Q), B(Q * N), D(Q * N);
-    gll_points(Q, x.data(), w.data());
-    modified_basis(P, Q, x.data(), B.data(), D.data());
-    const int off = varp_tab_off(P);
-    for (int i = 0; i < Q * N; ++i) {
-      t64[off + i] = B[i];
-      t64[off + Q * N + i] = D[i];
-      t32[off + i] = (float)B[i];
-      t32[off + Q * N + i] = (float)D[i];
-    }
-  }
+  put_tabs<1>(t64.data(), t32.data());
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_tab64), t64.data(), sizeof(double) * kVarpTabLen);
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_tab32), t32.data(), sizeof(float) * kVarpTabLen);

@@ -75,8 +75,14 @@ def test_invalid_arguments_rejected_before_device_work():
     assert L.nk_system_destroy(None) == nk.NK_EINVAL
     assert L.nk_set_tile_config(2, 3, 6, 0, 99) == nk.NK_EINVAL
     assert L.nk_set_tile_config(9, 3, 6, 0, 0) == nk.NK_EINVAL
-    # three vector tiles, each also in its lean and deep forms, + the matrix-core variant
-    assert L.nk_tile_count(2, 3, 6) == 10
+    # three vector tiles, each also in its lean and deep forms, all with the paired and the
+    # point-by-point I stage, + the matrix-core variant
+    assert L.nk_tile_count(2, 3, 6) == 19
+    assert L.nk_set_tile_config(2, 3, 6, 0, 9) == nk.NK_OK
+    assert L.nk_tile_config(2, 3, 6, 0).decode() == "epb1_thr64_pt"
+    assert L.nk_set_tile_config(2, 3, 6, 0, 0) == nk.NK_OK
+    # above P = 6 only the paired I stage: two tiles x three forms + matrix-core (Q = 10 > 8: none)
+    assert L.nk_tile_count(2, 3, 8) == 6
     assert L.nk_tile_count(0, 3, 6) == 3      # BwdTrans: no lean form
     assert L.nk_tile_config(2, 3, 6, 0).decode().startswith("epb")
 
