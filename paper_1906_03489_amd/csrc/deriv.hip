@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
 // I stage with D for g_1 and B for g_2, g_3, then the engine's J' and K'.
 template <typename T, int N, int Q, int EPB>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
-    k_iprod_deriv3(const Tab<T, N, Q> tb, int64_t nelem, const T* __restrict__ in,
+    k_iprod_deriv3(const TabH<T, N, Q> tb, int64_t nelem, const T* __restrict__ in,
                    T* __restrict__ out, const T* __restrict__ dfac) {
   constexpr int NN = N * N, N3 = NN * N, QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
   static_assert(3 * Q3 >= slot_lds<N, Q>(), "LDS slot");
@@ -239,23 +239,36 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
     }
   }
   slot_sync<NT>();
-  T sa[N], sb[N], sc[N];
-#pragma unroll
-  for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
+  // transposed I stage in even-odd pairs: D for g_1, B for g_2, g_3
+  constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
+  T sae[KE], sao[KO], sbe[KE], sbo[KO], sce[KE], sco[KO];
+  zero(sae);
+  zero(sao);
+  zero(sbe);
+  zero(sbo);
+  zero(sce);
+  zero(sco);
   if (act) {
+    const T* g = sm + Q * t;
 #pragma unroll 2
-    for (int i = 0; i < Q; ++i) {
-      const T g1 = sm[i + Q * t], g2 = sm[Q3 + i + Q * t], g3 = sm[2 * Q3 + i + Q * t];
-      const T* Bi = tb.B + i * N;
-      const T* Di = tb.D + i * N;
-#pragma unroll
-      for (int p = 0; p < N; ++p) {
-        sa[p] += Di[p] * g1;
-        sb[p] += Bi[p] * g2;
-        sc[p] += Bi[p] * g3;
-      }
+    for (int h = 0; h < Q / 2; ++h) {
+      const int l = h, u = Q - 1 - h;
+      const T a1 = g[l], a2 = g[u], b1 = g[Q3 + l], b2 = g[Q3 + u], c1 = g[2 * Q3 + l],
+              c2 = g[2 * Q3 + u];
+      eo_acc_d(tb, h, a1 + a2, a1 - a2, sae, sao);
+      eo_acc(tb, h, b1 + b2, b1 - b2, sbe, sbo);
+      eo_acc(tb, h, c1 + c2, c1 - c2, sce, sco);
+    }
+    if constexpr (Q & 1) {
+      eo_acc_mid_d(tb, g[Q / 2], sao);
+      eo_acc_mid(tb, g[Q3 + Q / 2], sbe);
+      eo_acc_mid(tb, g[2 * Q3 + Q / 2], sce);
     }
   }
+  T sa[N], sb[N], sc[N];
+  eo_join<T, N>(sae, sao, sa);
+  eo_join<T, N>(sbe, sbo, sb);
+  eo_join<T, N>(sce, sco, sc);
   slot_sync<NT>();
   if (act) store_i<T, N, Q, true>(sm, t, sa, sb, sc);
   slot_sync<NT>();
@@ -369,29 +382,34 @@ __device__ __forceinline__ void fd_contract(T* __restrict__ X, const T* __restri
 // y = M_e x for the slot's element: BwdTrans stages, w detJ at the points,
 // IProductWRTBase stages.  Vectors are columns over r of thread t = p + N q.
 template <typename T, int N, int Q, int NT>
-__device__ __forceinline__ void fd_mass(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t,
+__device__ __forceinline__ void fd_mass(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t,
                                         bool live, const T (&x)[N], const T (&wj)[Q], T (&y)[N]) {
   stage_k<T, N, Q, false>(tb, sm, t, live, x);
   slot_sync<NT>();
   stage_j<T, N, Q, NT, false>(tb, sm, t, live);
   slot_sync<NT>();
-  T sa[N];
-#pragma unroll
-  for (int p = 0; p < N; ++p) sa[p] = T(0);
+  T se[EO<N>::KE], so[EO<N>::KO];
+  zero(se);
+  zero(so);
   if (live && t < Q * Q) {
-    T av[N], dum[N];
-    load_i<T, N, Q, false>(sm, t, av, dum, dum);
-#pragma unroll 2
-    for (int i = 0; i < Q; ++i) {
-      const T* Bi = tb.B + i * N;
-      T u = 0;
-#pragma unroll
-      for (int p = 0; p < N; ++p) u += Bi[p] * av[p];
-      const T m = wj[i] * u;
-#pragma unroll
-      for (int p = 0; p < N; ++p) sa[p] += Bi[p] * m;
+    T ae[EO<N>::KE], ao[EO<N>::KO];
+    {
+      T av[N], dum[N];
+      load_i<T, N, Q, false>(sm, t, av, dum, dum);
+      eo_split<T, N>(av, ae, ao);
     }
+    // point pairs (h, Q-1-h); wj is indexed by constants only (full unroll)
+#pragma unroll
+    for (int h = 0; h < Q / 2; ++h) {
+      T ul, uh;
+      eo_val(tb, h, ae, ao, ul, uh);
+      const T ml = wj[h] * ul, mh = wj[Q - 1 - h] * uh;
+      eo_acc(tb, h, ml + mh, ml - mh, se, so);
+    }
+    if constexpr (Q & 1) eo_acc_mid(tb, wj[Q / 2] * eo_mid_val(tb, ae), se);
   }
+  T sa[N];
+  eo_join<T, N>(se, so, sa);
   slot_sync<NT>();
   if (live && t < Q * Q) store_i<T, N, Q, false>(sm, t, sa, sa, sa);
   slot_sync<NT>();
@@ -448,7 +466,7 @@ __device__ __forceinline__ double col_dot(const T (&a)[N], const T (&b)[N]) {
 // wavefront's lane groups (no block barriers) or the block itself.
 template <typename T, int N, int Q, int EPB>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
-    k_fwd_trans3(const Tab<T, N, Q> tb, const T* __restrict__ tab, int64_t nelem,
+    k_fwd_trans3(const TabH<T, N, Q> tb, const T* __restrict__ tab, int64_t nelem,
                  const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ dfac,
                  double rtol2, int maxit) {
   constexpr int NN = N * N, N3 = NN * N, QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
@@ -487,18 +505,19 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
       for (int k = 0; k < Q; ++k) sm[t + QQ * k] = fe[t + QQ * k];
     }
     slot_sync<NT>();
-    T sa[N];
-#pragma unroll
-    for (int p = 0; p < N; ++p) sa[p] = T(0);
+    T se[EO<N>::KE], so[EO<N>::KO];
+    zero(se);
+    zero(so);
     if (live && t < QQ) {
-#pragma unroll 2
-      for (int i = 0; i < Q; ++i) {
-        const T* Bi = tb.B + i * N;
-        const T m = wj[i] * sm[i + Q * t];
 #pragma unroll
-        for (int p = 0; p < N; ++p) sa[p] += Bi[p] * m;
+      for (int h = 0; h < Q / 2; ++h) {
+        const T ml = wj[h] * sm[h + Q * t], mh = wj[Q - 1 - h] * sm[Q - 1 - h + Q * t];
+        eo_acc(tb, h, ml + mh, ml - mh, se, so);
       }
+      if constexpr (Q & 1) eo_acc_mid(tb, wj[Q / 2] * sm[Q / 2 + Q * t], se);
     }
+    T sa[N];
+    eo_join<T, N>(se, so, sa);
     slot_sync<NT>();
     if (live && t < QQ) store_i<T, N, Q, false>(sm, t, sa, sa, sa);
     slot_sync<NT>();
@@ -775,10 +794,11 @@ static hipError_t run_deriv(int which, int dim, const DerivArgs& a) {
     return hipGetLastError();
   }
   const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
+  const TabH<T, N, Q>& th = host_tabh<T, N, Q>();
   if (which == DERIV_IPROD) {
     if (dim == 3)
       hipLaunchKernelGGL((k_iprod_deriv3<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
-                         tb, a.nelem, in, out, df);
+                         th, a.nelem, in, out, df);
     else
       hipLaunchKernelGGL((k_iprod_deriv2<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
                          tb, a.nelem, in, out, df);
@@ -804,7 +824,7 @@ static hipError_t run_deriv(int which, int dim, const DerivArgs& a) {
     if (!tab) return hipErrorOutOfMemory;
     const double rtol = sizeof(T) == 8 ? 1e-13 : 2e-6;
     hipLaunchKernelGGL((k_fwd_trans3<T, N, Q, EPBF>), dim3((unsigned)nbf), dim3(EPBF * NT), 0, s,
-                       tb, tab, a.nelem, in, out, df, rtol * rtol, kFwdMaxIt);
+                       th, tab, a.nelem, in, out, df, rtol * rtol, kFwdMaxIt);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

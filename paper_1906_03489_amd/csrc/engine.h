@@ -7,17 +7,18 @@
 // CDNA4 mapping.  One element is handled by one "slot" of NT >= Q*Q threads.
 // Each thread owns a pencil (a line of values along one direction) in
 // registers, so every contraction is a register-local product with a 1-D
-// matrix that is uniform across the wavefront.  The stages loop over the
-// point index (k, j or i) without unrolling and unroll the mode index, so each
-// iteration needs exactly one row of B and of DB, which the scalar unit loads
-// from the kernel arguments; the FP64/FP32 FMAs take it as their scalar
-// operand.  Between directions the pencils are re-oriented through LDS.
+// matrix that is uniform across the wavefront.  The stages loop over pairs of
+// mirrored points (k and Q-1-k, even-odd form below) and unroll the mode
+// index, so each iteration needs one row of each half table, which the
+// scalar unit loads from the kernel arguments; the FP64/FP32 FMAs take it as
+// their scalar operand.  Between directions the pencils are re-oriented
+// through LDS.
 //
 // Forward (coefficients -> values and reference gradient at the points):
 //   K: thread (p,q)  r -> k with B and DB           -> t_B, t_D   [k][q][p]
 //   J: thread (p,k)  q -> j                         -> s_BB, s_DB, s_BD [k][j][p]
 //   I: thread (j,k)  p -> i, fused with the pointwise factors and with the
-//      transposed I stage, one point i per loop iteration
+//      transposed I stage, one pair of points (or one point) per iteration
 // Backward (transpose), summing m and the three flux components:
 //   I': thread (j,k) i -> p                         -> s'_BB, s'_DB, s'_BD
 //   J': thread (p,k) j -> q                         -> t'_B, t'_D
@@ -283,67 +284,6 @@ constexpr int slot_lds() {
 // Every stage is executed by all threads of the block (barriers inside);
 // `act` masks the threads that own a pencil of a live element.
 
-// K: thread t = p + N q (< N^2) holds xin[r]; writes t_B (and t_D) [k][q][p].
-template <typename T, int N, int Q, bool DER>
-__device__ __forceinline__ void stage_k(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool act,
-                                        const T (&xin)[N]) {
-  constexpr int NN = N * N, S = Q * Q * N;
-  if (act && t < NN) {
-#pragma unroll 2
-    for (int k = 0; k < Q; ++k) {
-      const T* Bk = tb.B + k * N;
-      const T* Dk = tb.D + k * N;
-      T sb = 0, sd = 0;
-#pragma unroll
-      for (int r = 0; r < N; ++r) {
-        sb += Bk[r] * xin[r];
-        if constexpr (DER) sd += Dk[r] * xin[r];
-      }
-      sm[k * NN + t] = sb;
-      if constexpr (DER) sm[S + k * NN + t] = sd;
-    }
-  }
-}
-
-// J: thread (p,k) = t < N Q reads t_B, t_D; writes s_BB, s_DB, s_BD [k][j][p].
-template <typename T, int N, int Q, int NT, bool DER>
-__device__ __forceinline__ void stage_j(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool act) {
-  constexpr int NN = N * N, S = Q * Q * N;
-  const int pj = t % N, kj = t / N;
-  const bool me = act && t < N * Q;
-  T av[N], bv[N];
-  if (me) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      av[q] = sm[kj * NN + q * N + pj];
-      if constexpr (DER) bv[q] = sm[S + kj * NN + q * N + pj];
-    }
-  }
-  slot_sync<NT>();
-  if (me) {
-#pragma unroll 2
-    for (int j = 0; j < Q; ++j) {
-      const T* Bj = tb.B + j * N;
-      const T* Dj = tb.D + j * N;
-      T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        s0 += Bj[q] * av[q];
-        if constexpr (DER) {
-          s1 += Dj[q] * av[q];
-          s2 += Bj[q] * bv[q];
-        }
-      }
-      const int o = (kj * Q + j) * N + pj;
-      sm[o] = s0;
-      if constexpr (DER) {
-        sm[S + o] = s1;
-        sm[2 * S + o] = s2;
-      }
-    }
-  }
-}
-
 // I-stage inputs of thread (j,k) = t < Q^2: s_BB, s_DB, s_BD [k][j][p].
 template <typename T, int N, int Q, bool DER>
 __device__ __forceinline__ void load_i(const T* __restrict__ sm, int t, T (&av)[N], T (&bv)[N],
@@ -374,73 +314,9 @@ __device__ __forceinline__ void store_i(T* __restrict__ sm, int t, const T (&sa)
   }
 }
 
-// J': thread (p,k) = t < N Q sums over j; writes t'_B, t'_D [k][q][p].
-template <typename T, int N, int Q, int NT, bool DER>
-__device__ __forceinline__ void stage_jt(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t,
-                                         bool act) {
-  constexpr int NN = N * N, S = Q * Q * N;
-  const int pj = t % N, kj = t / N;
-  const bool me = act && t < N * Q;
-  T tB[N], tD[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) tB[q] = tD[q] = T(0);
-  if (me) {
-#pragma unroll 2
-    for (int j = 0; j < Q; ++j) {
-      const int o = (kj * Q + j) * N + pj;
-      const T a = sm[o];
-      T b = 0, c = 0;
-      if constexpr (DER) {
-        b = sm[S + o];
-        c = sm[2 * S + o];
-      }
-      const T* Bj = tb.B + j * N;
-      const T* Dj = tb.D + j * N;
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        tB[q] += Bj[q] * a;
-        if constexpr (DER) {
-          tB[q] += Dj[q] * b;
-          tD[q] += Bj[q] * c;
-        }
-      }
-    }
-  }
-  slot_sync<NT>();
-  if (me) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      sm[kj * NN + q * N + pj] = tB[q];
-      if constexpr (DER) sm[S + kj * NN + q * N + pj] = tD[q];
-    }
-  }
-}
-
-// K': thread (p,q) = t < N^2 sums over k into y[r].
-template <typename T, int N, int Q, bool DER>
-__device__ __forceinline__ void stage_kt(const Tab<T, N, Q>& tb, const T* __restrict__ sm, int t,
-                                         bool act, T (&yv)[N]) {
-  constexpr int NN = N * N, S = Q * Q * N;
-#pragma unroll
-  for (int r = 0; r < N; ++r) yv[r] = T(0);
-  if (act && t < NN) {
-#pragma unroll 2
-    for (int k = 0; k < Q; ++k) {
-      const T a = sm[k * NN + t];
-      const T b = DER ? sm[S + k * NN + t] : T(0);
-      const T* Bk = tb.B + k * N;
-      const T* Dk = tb.D + k * N;
-#pragma unroll
-      for (int r = 0; r < N; ++r) {
-        yv[r] += Bk[r] * a;
-        if constexpr (DER) yv[r] += Dk[r] * b;
-      }
-    }
-  }
-}
-
-// The same four stages with the even-odd tables: each output pair (k, Q-1-k)
-// from one pass over the split pencil.  LDS layouts are those above.
+// The four contraction stages, each with the even-odd tables: every output
+// pair (k, Q-1-k) from one pass over the split pencil.
+// K: thread t = p + N q (< N^2) holds xin[r]; writes t_B (and t_D) [k][q][p].
 template <typename T, int N, int Q, bool DER>
 __device__ __forceinline__ void stage_k(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t, bool act,
                                         const T (&xin)[N]) {
@@ -467,6 +343,7 @@ __device__ __forceinline__ void stage_k(const TabH<T, N, Q>& tb, T* __restrict__
   }
 }
 
+// J: thread (p,k) = t < N Q reads t_B, t_D; writes s_BB, s_DB, s_BD [k][j][p].
 template <typename T, int N, int Q, int NT, bool DER>
 __device__ __forceinline__ void stage_j(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t, bool act) {
   constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
@@ -513,6 +390,7 @@ __device__ __forceinline__ void stage_j(const TabH<T, N, Q>& tb, T* __restrict__
   }
 }
 
+// J': thread (p,k) = t < N Q sums over j; writes t'_B, t'_D [k][q][p].
 template <typename T, int N, int Q, int NT, bool DER>
 __device__ __forceinline__ void stage_jt(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t,
                                          bool act) {
@@ -561,6 +439,7 @@ __device__ __forceinline__ void stage_jt(const TabH<T, N, Q>& tb, T* __restrict_
   }
 }
 
+// K': thread (p,q) = t < N^2 sums over k into y[r].
 template <typename T, int N, int Q, bool DER>
 __device__ __forceinline__ void stage_kt(const TabH<T, N, Q>& tb, const T* __restrict__ sm, int t,
                                          bool act, T (&yv)[N]) {
