@@ -483,12 +483,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
         // of the element has read them; then the block's contiguous run of
         // point values leaves in one coalesced sweep
         esync();
+        {
+          // eta_1 stage in even-odd point pairs (the GLL points are symmetric)
+          T ve[EO<N>::KE], vo[EO<N>::KO];
+          eo_split<T, N>(V, ve, vo);
 #pragma unroll 1
-        for (int i = 0; i < Q; ++i) {
-          T u = T(0);
-#pragma unroll
-          for (int p = 0; p < N; ++p) u += tb.B[i * N + p] * V[p];
-          if (act) SS[t * RS + i] = u;
+          for (int h = 0; h < Q / 2; ++h) {
+            T lo, hi;
+            eo_val(tb, h, ve, vo, lo, hi);
+            if (act) {
+              SS[t * RS + h] = lo;
+              SS[t * RS + Q - 1 - h] = hi;
+            }
+          }
+          if constexpr (Q & 1) {
+            const T mid = eo_mid_val(tb, ve);
+            if (act) SS[t * RS + Q / 2] = mid;
+          }
         }
         esync();
         // the block's (or, wavefront-aligned, the wavefront's) elements are
@@ -506,53 +517,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
       } else {
         const T lam = (T)(a.lam ? a.lam[live ? e : 0] : a.lam0);
         const T* f = a.fac + (live ? e : 0) * (int64_t)(7 * NPT) + t;
-        // one point i: eta_1 stage, the 7 factors, transposed eta_1 stage
-        auto point = [&](int i, const T (&fv)[7]) {
-          T u = T(0), u1 = T(0), u2 = T(0), u3 = T(0);
+        // eta_1 stage, the 7 factors and the transposed eta_1 stage, point by
+        // point (the paired even-odd form costs these register-bound kernels
+        // up to 80 VGPRs); f points into element 0 for threads without a live
+        // element, so every load is in bounds (their results are never used)
+        plain_helm_row<T, N, Q, (HPF ? 2 : 1)>(
+            tb, lam, V, dV, V3,
+            [&](int i, T (&fv)[kNF3]) {
 #pragma unroll
-          for (int p = 0; p < N; ++p) {
-            u += tb.B[i * N + p] * V[p];
-            u1 += tb.D[i * N + p] * V[p];
-            u2 += tb.B[i * N + p] * dV[p];
-            u3 += tb.B[i * N + p] * V3[p];
-          }
-          const T mq = lam * fv[0] * u;
-          const T g1 = fv[1] * u1 + fv[2] * u2 + fv[3] * u3;
-          const T g2 = fv[2] * u1 + fv[4] * u2 + fv[5] * u3;
-          const T g3 = fv[3] * u1 + fv[5] * u2 + fv[6] * u3;
-#pragma unroll
-          for (int p = 0; p < N; ++p) {
-            SA[p] += tb.B[i * N + p] * mq + tb.D[i * N + p] * g1;
-            SB[p] += tb.B[i * N + p] * g2;
-            SC[p] += tb.B[i * N + p] * g3;
-          }
-        };
-        // f points into element 0 for threads without a live element, so
-        // every load is in bounds (their results are never used)
-        auto load = [&](int i, T (&fv)[7]) {
-#pragma unroll
-          for (int c = 0; c < 7; ++c) fv[c] = f[(c * Q + i) * NS];
-        };
-        if constexpr (HPF) {
-          // two register sets alternate: the factors of point i+1 are in
-          // flight while point i is computed
-          T fA[7], fB[7];
-          load(0, fA);
-#pragma unroll 1
-          for (int i = 0; i < Q; i += 2) {
-            load(i + 1 < Q ? i + 1 : Q - 1, fB);
-            point(i, fA);
-            load(i + 2 < Q ? i + 2 : Q - 1, fA);
-            if (i + 1 < Q) point(i + 1, fB);
-          }
-        } else {
-#pragma unroll 1
-          for (int i = 0; i < Q; ++i) {
-            T fv[7];
-            load(i, fv);
-            point(i, fv);
-          }
-        }
+              for (int c = 0; c < kNF3; ++c) fv[c] = f[(c * Q + i) * NS];
+            },
+            SA, SB, SC);
       }
     } else {   // IProductWRTBase: point values times w detJ, read by rows
                // straight into registers (staging them through LDS measured
@@ -566,12 +541,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tet_mi
         xv[i] = live ? x[i] : T(0);
         wv[i] = live ? f[i * NS] : T(0);
       }
+      T se[EO<N>::KE], so[EO<N>::KO];
+      zero(se);
+      zero(so);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const T mq = wv[i] * xv[i];
-#pragma unroll
-        for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
+      for (int h = 0; h < Q / 2; ++h) {
+        const T ml = wv[h] * xv[h], mh = wv[Q - 1 - h] * xv[Q - 1 - h];
+        eo_acc(tb, h, ml + mh, ml - mh, se, so);
       }
+      if constexpr (Q & 1) eo_acc_mid(tb, wv[Q / 2] * xv[Q / 2], se);
+      eo_join<T, N>(se, so, SA);
     }
     // transposed eta_2 stage, z_t(k') and z'_t(k') for every (k', t) pair,
     // from the transposed eta_1 results SA (with B2), SB (with dB2) and SC

@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
 // I stage with D for g_1 and B for g_2, g_3, then the engine's J' and K'.
 template <typename T, int N, int Q, int EPB>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
-    k_iprod_deriv3(const TabH<T, N, Q> tb, int64_t nelem, const T* __restrict__ in,
+    k_iprod_deriv3(const Tab<T, N, Q> tb, int64_t nelem, const T* __restrict__ in,
                    T* __restrict__ out, const T* __restrict__ dfac) {
   constexpr int NN = N * N, N3 = NN * N, QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
   static_assert(3 * Q3 >= slot_lds<N, Q>(), "LDS slot");
@@ -382,7 +382,7 @@ __device__ __forceinline__ void fd_contract(T* __restrict__ X, const T* __restri
 // y = M_e x for the slot's element: BwdTrans stages, w detJ at the points,
 // IProductWRTBase stages.  Vectors are columns over r of thread t = p + N q.
 template <typename T, int N, int Q, int NT>
-__device__ __forceinline__ void fd_mass(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t,
+__device__ __forceinline__ void fd_mass(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t,
                                         bool live, const T (&x)[N], const T (&wj)[Q], T (&y)[N]) {
   stage_k<T, N, Q, false>(tb, sm, t, live, x);
   slot_sync<NT>();
@@ -466,7 +466,7 @@ __device__ __forceinline__ double col_dot(const T (&a)[N], const T (&b)[N]) {
 // wavefront's lane groups (no block barriers) or the block itself.
 template <typename T, int N, int Q, int EPB>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
-    k_fwd_trans3(const TabH<T, N, Q> tb, const T* __restrict__ tab, int64_t nelem,
+    k_fwd_trans3(const Tab<T, N, Q> tb, const T* __restrict__ tab, int64_t nelem,
                  const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ dfac,
                  double rtol2, int maxit) {
   constexpr int NN = N * N, N3 = NN * N, QQ = Q * Q, Q3 = QQ * Q, NT = slot_threads<Q>();
@@ -794,11 +794,10 @@ static hipError_t run_deriv(int which, int dim, const DerivArgs& a) {
     return hipGetLastError();
   }
   const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
-  const TabH<T, N, Q>& th = host_tabh<T, N, Q>();
   if (which == DERIV_IPROD) {
     if (dim == 3)
       hipLaunchKernelGGL((k_iprod_deriv3<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
-                         th, a.nelem, in, out, df);
+                         tb, a.nelem, in, out, df);
     else
       hipLaunchKernelGGL((k_iprod_deriv2<T, N, Q, EPB>), dim3((unsigned)nblk), dim3(EPB * NT), 0, s,
                          tb, a.nelem, in, out, df);
@@ -824,7 +823,7 @@ static hipError_t run_deriv(int which, int dim, const DerivArgs& a) {
     if (!tab) return hipErrorOutOfMemory;
     const double rtol = sizeof(T) == 8 ? 1e-13 : 2e-6;
     hipLaunchKernelGGL((k_fwd_trans3<T, N, Q, EPBF>), dim3((unsigned)nbf), dim3(EPBF * NT), 0, s,
-                       th, tab, a.nelem, in, out, df, rtol * rtol, kFwdMaxIt);
+                       tb, tab, a.nelem, in, out, df, rtol * rtol, kFwdMaxIt);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

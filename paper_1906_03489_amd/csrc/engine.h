@@ -9,10 +9,10 @@
 // registers, so every contraction is a register-local product with a 1-D
 // matrix that is uniform across the wavefront.  The stages loop over pairs of
 // mirrored points (k and Q-1-k, even-odd form below) and unroll the mode
-// index, so each iteration needs one row of each half table, which the
-// scalar unit loads from the kernel arguments; the FP64/FP32 FMAs take it as
-// their scalar operand.  Between directions the pencils are re-oriented
-// through LDS.
+// index, so each iteration needs one row of B and of DB, which the scalar
+// unit loads from the kernel arguments; the FP64/FP32 FMAs take it as their
+// scalar operand.  Between directions the pencils are re-oriented through
+// LDS.
 //
 // Forward (coefficients -> values and reference gradient at the points):
 //   K: thread (p,q)  r -> k with B and DB           -> t_B, t_D   [k][q][p]
@@ -33,63 +33,43 @@
 #include <cstdint>
 
 #include "nk_internal.h"
+#include "tiles.h"
 
 namespace nk {
 
-template <typename T, int N, int Q>
-struct Tab {
-  T B[Q * N];  // B[i*N + p] = phi_p(x_i)
-  T D[Q * N];  // D[i*N + p] = phi_p'(x_i)
-};
-
-// Even-odd form of the 1-D tables (the even-odd decomposition of a matrix
-// that commutes with the reflection x -> -x, Solomonoff, "A fast algorithm
-// for spectral differentiation", J. Comput. Phys. 98, 1992).  The GLL points
-// are symmetric, x_{Q-1-i} = -x_i.  Of the modified modes, the interior ones
-// phi_p (0 < p < P) are even functions for odd p and odd functions for even
-// p, and the vertex pair splits into the even sum phi_0 + phi_P (= 1) and the
-// odd difference phi_0 - phi_P (= -x).  Coefficients c split into
+// 1-D tables: B and D at the Q GLL points, and X[i] = -x_i/2 for the first
+// H = ceil(Q/2) points.
+//
+// The GLL points are symmetric, x_{Q-1-i} = -x_i, and of the modified modes
+// the interior ones phi_p (0 < p < P) are even functions for odd p and odd
+// functions for even p, while the vertex pair splits into the even sum
+// phi_0 + phi_P (= 1) and the odd difference phi_0 - phi_P (= -x).  The
+// contractions use this as the even-odd decomposition of a matrix that
+// commutes with the reflection (Solomonoff, "A fast algorithm for spectral
+// differentiation", J. Comput. Phys. 98, 1992), reading only the rows of the
+// first H points.  Coefficients c split into
 //   ce = (c_0 + c_P, c_1, c_3, ...)   (KE = P/2 + 1 entries)
 //   co = (c_0 - c_P, c_2, c_4, ...)   (KO = (P-1)/2 + 1 entries)
-// and for the first H = ceil(Q/2) points the half tables hold the members of
-// each set (vertex columns halved, so that one table serves a contraction
-// and its transpose):
-//   BE[i][0] = 1/2,     BE[i][m] = phi_{2m-1}(x_i),   DE[i][0] = 0,    DE[i][m] = phi'_{2m-1}(x_i)
-//   BO[i][0] = -x_i/2,  BO[i][m] = phi_{2m}(x_i),     DO[i][0] = -1/2, DO[i][m] = phi'_{2m}(x_i)
-// With E = BE.ce, O = BO.co: u(x_i) = E + O, u(x_{Q-1-i}) = E - O; with
-// Ed = DO.co, Od = DE.ce: u'(x_i) = Ed + Od, u'(x_{Q-1-i}) = Ed - Od.  A pair
-// of points costs N products instead of 2N.  The transposed contraction takes
-// v_i + v_{Q-1-i} and v_i - v_{Q-1-i} against the same tables; the middle
-// point of an odd Q (x = 0) meets only the even members and derivatives of
-// the odd ones.
+// whose members at x_i are (1/2, phi_1, phi_3, ...) and (-x_i/2, phi_2, ...),
+// with derivatives (0, phi'_1, ...) and (-1/2, phi'_2, ...).  With E, O the
+// even and odd sums: u(x_i) = E + O, u(x_{Q-1-i}) = E - O, and likewise for
+// u' from the derivative sums (Ed from co, Od from ce), so a pair of points
+// costs N products instead of 2N.  The transposed contraction takes
+// v_i + v_{Q-1-i} and v_i - v_{Q-1-i} against the same rows and unpacks the
+// vertex pair; the middle point of an odd Q (x = 0) meets only the even
+// members and the derivatives of the odd ones.
+template <typename T, int N, int Q>
+struct Tab {
+  T B[Q * N];            // B[i*N + p] = phi_p(x_i)
+  T D[Q * N];            // D[i*N + p] = phi_p'(x_i)
+  T X[(Q + 1) / 2];      // X[i] = -x_i / 2
+};
+
 template <int N>
 struct EO {
   static constexpr int P = N - 1;
   static constexpr int KE = P / 2 + 1;
   static constexpr int KO = (P - 1) / 2 + 1;
-};
-
-template <typename T, int N, int Q>
-struct TabH {
-  static constexpr int H = (Q + 1) / 2, KE = EO<N>::KE, KO = EO<N>::KO;
-  T BE[H * KE];
-  T BO[H * KO];
-  T DE[H * KE];
-  T DO[H * KO];
-};
-
-// Tables passed to the 3-D operator kernels: the half tables, and up to
-// N = kPtMaxN also the full ones, for the Helmholtz candidates that evaluate
-// the I stage point by point (fewer live registers than the paired loop,
-// which matters at low orders, where occupancy decides).
-template <typename T, int N, int Q, bool FULL = (N <= kPtMaxN)>
-struct TabK {
-  TabH<T, N, Q> h;
-  Tab<T, N, Q> f;
-};
-template <typename T, int N, int Q>
-struct TabK<T, N, Q, false> {
-  TabH<T, N, Q> h;
 };
 
 template <typename T, int N>
@@ -114,88 +94,88 @@ __device__ __forceinline__ void eo_join(const T (&ye)[EO<N>::KE], const T (&yo)[
 
 // values at x_h and x_{Q-1-h}
 template <typename T, int N, int Q>
-__device__ __forceinline__ void eo_val(const TabH<T, N, Q>& tb, int h, const T (&ce)[EO<N>::KE],
+__device__ __forceinline__ void eo_val(const Tab<T, N, Q>& tb, int h, const T (&ce)[EO<N>::KE],
                                        const T (&co)[EO<N>::KO], T& lo, T& hi) {
-  constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
-  const T* be = tb.BE + h * KE;
-  const T* bo = tb.BO + h * KO;
-  T e = 0, o = 0;
+  const T* b = tb.B + h * N;
+  T e = T(0.5) * ce[0], o = tb.X[h] * co[0];
 #pragma unroll
-  for (int m = 0; m < KE; ++m) e += be[m] * ce[m];
+  for (int m = 1; m < EO<N>::KE; ++m) e += b[2 * m - 1] * ce[m];
 #pragma unroll
-  for (int m = 0; m < KO; ++m) o += bo[m] * co[m];
+  for (int m = 1; m < EO<N>::KO; ++m) o += b[2 * m] * co[m];
   lo = e + o;
   hi = e - o;
 }
 
 // derivatives at x_h and x_{Q-1-h}
 template <typename T, int N, int Q>
-__device__ __forceinline__ void eo_der(const TabH<T, N, Q>& tb, int h, const T (&ce)[EO<N>::KE],
+__device__ __forceinline__ void eo_der(const Tab<T, N, Q>& tb, int h, const T (&ce)[EO<N>::KE],
                                        const T (&co)[EO<N>::KO], T& lo, T& hi) {
-  constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
-  const T* de = tb.DE + h * KE;
-  const T* dd = tb.DO + h * KO;
-  T e = 0, o = 0;
+  const T* d = tb.D + h * N;
+  T e = T(-0.5) * co[0], o = T(0);
 #pragma unroll
-  for (int m = 0; m < KO; ++m) e += dd[m] * co[m];
+  for (int m = 1; m < EO<N>::KO; ++m) e += d[2 * m] * co[m];
 #pragma unroll
-  for (int m = 1; m < KE; ++m) o += de[m] * ce[m];
+  for (int m = 1; m < EO<N>::KE; ++m) o += d[2 * m - 1] * ce[m];
   lo = e + o;
   hi = e - o;
 }
 
 // value and derivative at the middle point of an odd Q
 template <typename T, int N, int Q>
-__device__ __forceinline__ T eo_mid_val(const TabH<T, N, Q>& tb, const T (&ce)[EO<N>::KE]) {
-  const T* be = tb.BE + (Q / 2) * EO<N>::KE;
-  T e = 0;
+__device__ __forceinline__ T eo_mid_val(const Tab<T, N, Q>& tb, const T (&ce)[EO<N>::KE]) {
+  const T* b = tb.B + (Q / 2) * N;
+  T e = T(0.5) * ce[0];
 #pragma unroll
-  for (int m = 0; m < EO<N>::KE; ++m) e += be[m] * ce[m];
+  for (int m = 1; m < EO<N>::KE; ++m) e += b[2 * m - 1] * ce[m];
   return e;
 }
 template <typename T, int N, int Q>
-__device__ __forceinline__ T eo_mid_der(const TabH<T, N, Q>& tb, const T (&co)[EO<N>::KO]) {
-  const T* dd = tb.DO + (Q / 2) * EO<N>::KO;
-  T e = 0;
+__device__ __forceinline__ T eo_mid_der(const Tab<T, N, Q>& tb, const T (&co)[EO<N>::KO]) {
+  const T* d = tb.D + (Q / 2) * N;
+  T e = T(-0.5) * co[0];
 #pragma unroll
-  for (int m = 0; m < EO<N>::KO; ++m) e += dd[m] * co[m];
+  for (int m = 1; m < EO<N>::KO; ++m) e += d[2 * m] * co[m];
   return e;
 }
 
-// transposed: ye += BE[h] vp, yo += BO[h] vm (vp = v_h + v_{Q-1-h}, vm = v_h - v_{Q-1-h})
+// transposed: ye += (even members at x_h) vp, yo += (odd members) vm, with
+// vp = v_h + v_{Q-1-h}, vm = v_h - v_{Q-1-h}
 template <typename T, int N, int Q>
-__device__ __forceinline__ void eo_acc(const TabH<T, N, Q>& tb, int h, T vp, T vm,
+__device__ __forceinline__ void eo_acc(const Tab<T, N, Q>& tb, int h, T vp, T vm,
                                        T (&ye)[EO<N>::KE], T (&yo)[EO<N>::KO]) {
-  const T* be = tb.BE + h * EO<N>::KE;
-  const T* bo = tb.BO + h * EO<N>::KO;
+  const T* b = tb.B + h * N;
+  ye[0] += T(0.5) * vp;
+  yo[0] += tb.X[h] * vm;
 #pragma unroll
-  for (int m = 0; m < EO<N>::KE; ++m) ye[m] += be[m] * vp;
+  for (int m = 1; m < EO<N>::KE; ++m) ye[m] += b[2 * m - 1] * vp;
 #pragma unroll
-  for (int m = 0; m < EO<N>::KO; ++m) yo[m] += bo[m] * vm;
+  for (int m = 1; m < EO<N>::KO; ++m) yo[m] += b[2 * m] * vm;
 }
-// transposed derivative: ye += DE[h] wm, yo += DO[h] wp
+// transposed derivative: ye += (even members)' wm, yo += (odd members)' wp
 template <typename T, int N, int Q>
-__device__ __forceinline__ void eo_acc_d(const TabH<T, N, Q>& tb, int h, T wp, T wm,
+__device__ __forceinline__ void eo_acc_d(const Tab<T, N, Q>& tb, int h, T wp, T wm,
                                          T (&ye)[EO<N>::KE], T (&yo)[EO<N>::KO]) {
-  const T* de = tb.DE + h * EO<N>::KE;
-  const T* dd = tb.DO + h * EO<N>::KO;
+  const T* d = tb.D + h * N;
+  yo[0] += T(-0.5) * wp;
 #pragma unroll
-  for (int m = 1; m < EO<N>::KE; ++m) ye[m] += de[m] * wm;
+  for (int m = 1; m < EO<N>::KE; ++m) ye[m] += d[2 * m - 1] * wm;
 #pragma unroll
-  for (int m = 0; m < EO<N>::KO; ++m) yo[m] += dd[m] * wp;
+  for (int m = 1; m < EO<N>::KO; ++m) yo[m] += d[2 * m] * wp;
 }
 // the middle point of an odd Q: value v, derivative weight w
 template <typename T, int N, int Q>
-__device__ __forceinline__ void eo_acc_mid(const TabH<T, N, Q>& tb, T v, T (&ye)[EO<N>::KE]) {
-  const T* be = tb.BE + (Q / 2) * EO<N>::KE;
+__device__ __forceinline__ void eo_acc_mid(const Tab<T, N, Q>& tb, T v, T (&ye)[EO<N>::KE]) {
+  const T* b = tb.B + (Q / 2) * N;
+  ye[0] += T(0.5) * v;
 #pragma unroll
-  for (int m = 0; m < EO<N>::KE; ++m) ye[m] += be[m] * v;
+  for (int m = 1; m < EO<N>::KE; ++m) ye[m] += b[2 * m - 1] * v;
 }
 template <typename T, int N, int Q>
-__device__ __forceinline__ void eo_acc_mid_d(const TabH<T, N, Q>& tb, T w, T (&yo)[EO<N>::KO]) {
-  const T* dd = tb.DO + (Q / 2) * EO<N>::KO;
+__device__ __forceinline__ void eo_acc_mid_d(const Tab<T, N, Q>& tb, T w, T (&yo)[EO<N>::KO]) {
+  const T* d = tb.D + (Q / 2) * N;
+  yo[0] += T(-0.5) * w;
 #pragma unroll
-  for (int m = 0; m < EO<N>::KO; ++m) yo[m] += dd[m] * w;
+  for (int m = 1; m < EO<N>::KO; ++m) yo[m] += d[2 * m] * w;
 }
 
 template <typename T, int K>
@@ -318,7 +298,7 @@ __device__ __forceinline__ void store_i(T* __restrict__ sm, int t, const T (&sa)
 // pair (k, Q-1-k) from one pass over the split pencil.
 // K: thread t = p + N q (< N^2) holds xin[r]; writes t_B (and t_D) [k][q][p].
 template <typename T, int N, int Q, bool DER>
-__device__ __forceinline__ void stage_k(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t, bool act,
+__device__ __forceinline__ void stage_k(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool act,
                                         const T (&xin)[N]) {
   constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2;
   if (act && t < NN) {
@@ -345,7 +325,7 @@ __device__ __forceinline__ void stage_k(const TabH<T, N, Q>& tb, T* __restrict__
 
 // J: thread (p,k) = t < N Q reads t_B, t_D; writes s_BB, s_DB, s_BD [k][j][p].
 template <typename T, int N, int Q, int NT, bool DER>
-__device__ __forceinline__ void stage_j(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t, bool act) {
+__device__ __forceinline__ void stage_j(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t, bool act) {
   constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
   const int pj = t % N, kj = t / N;
   const bool me = act && t < N * Q;
@@ -392,7 +372,7 @@ __device__ __forceinline__ void stage_j(const TabH<T, N, Q>& tb, T* __restrict__
 
 // J': thread (p,k) = t < N Q sums over j; writes t'_B, t'_D [k][q][p].
 template <typename T, int N, int Q, int NT, bool DER>
-__device__ __forceinline__ void stage_jt(const TabH<T, N, Q>& tb, T* __restrict__ sm, int t,
+__device__ __forceinline__ void stage_jt(const Tab<T, N, Q>& tb, T* __restrict__ sm, int t,
                                          bool act) {
   constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
   const int pj = t % N, kj = t / N;
@@ -441,7 +421,7 @@ __device__ __forceinline__ void stage_jt(const TabH<T, N, Q>& tb, T* __restrict_
 
 // K': thread (p,q) = t < N^2 sums over k into y[r].
 template <typename T, int N, int Q, bool DER>
-__device__ __forceinline__ void stage_kt(const TabH<T, N, Q>& tb, const T* __restrict__ sm, int t,
+__device__ __forceinline__ void stage_kt(const Tab<T, N, Q>& tb, const T* __restrict__ sm, int t,
                                          bool act, T (&yv)[N]) {
   constexpr int NN = N * N, S = Q * Q * N, HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
   T ye[KE], yo[KO];
@@ -484,6 +464,121 @@ __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int 
   }
 }
 
+// The paired I stage of the Helmholtz operator along one pencil: at each
+// pair of points (h, Q-1-h), then the middle one of an odd Q, the forward
+// contraction of the split inputs (a: the pencil, giving the value and the
+// derivative along it; b, c: the tensors of the other two reference
+// derivatives), the 7 factors with the lambda mass term, and the transposed
+// contraction into the split accumulators (sa: mass and first gradient
+// component, sb, sc: the other two).  load(i, f) fetches the factors of point
+// i.  Sequence position s is point s/2 (even s) or Q-1-s/2 (odd s); PF
+// register sets hold positions s .. s+PF-1, and before position s is
+// computed the loads of s+PF-1 go into the set that s-1 has just released.
+// One loop trip covers a multiple of 2 (a pair) and of PF positions, so that
+// every set index is a constant.
+template <typename T, int N, int Q, int PF, typename Load>
+__device__ __forceinline__ void eo_helm_row(
+    const Tab<T, N, Q>& tb, T lam, const T (&ae)[EO<N>::KE], const T (&ao)[EO<N>::KO],
+    const T (&be)[EO<N>::KE], const T (&bo)[EO<N>::KO], const T (&ce)[EO<N>::KE],
+    const T (&co)[EO<N>::KO], Load load, T (&sae)[EO<N>::KE], T (&sao)[EO<N>::KO],
+    T (&sbe)[EO<N>::KE], T (&sbo)[EO<N>::KO], T (&sce)[EO<N>::KE], T (&sco)[EO<N>::KO]) {
+  constexpr int HP = Q / 2;
+  auto ld = [&](int s, T (&f)[kNF3]) {
+    const int sc = s < Q ? s : Q - 1;
+    load((sc & 1) ? Q - 1 - (sc >> 1) : (sc >> 1), f);
+  };
+  // r = (m, g1, g2, g3) at one point
+  auto pointwise = [&](const T (&f)[kNF3], T u, T u1, T u2, T u3, T (&r)[4]) {
+    r[0] = lam * f[0] * u;
+    r[1] = f[1] * u1 + f[2] * u2 + f[3] * u3;
+    r[2] = f[2] * u1 + f[4] * u2 + f[5] * u3;
+    r[3] = f[3] * u1 + f[5] * u2 + f[6] * u3;
+  };
+  constexpr int L = (PF % 2 == 0) ? PF : 2 * PF;
+  constexpr int PP = L / 2;
+  T f[PF][kNF3];
+#pragma unroll
+  for (int s = 0; s + 1 < PF; ++s) ld(s, f[s]);
+#pragma unroll 1
+  for (int h0 = 0; h0 < HP; h0 += PP) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      const int h = h0 + q;
+      if (HP % PP == 0 || h < HP) {
+        T ul[4], uh[4], rl[4], rh[4];
+        eo_val(tb, h, ae, ao, ul[0], uh[0]);
+        eo_der(tb, h, ae, ao, ul[1], uh[1]);
+        eo_val(tb, h, be, bo, ul[2], uh[2]);
+        eo_val(tb, h, ce, co, ul[3], uh[3]);
+        ld(2 * h + PF - 1, f[(2 * q + PF - 1) % PF]);
+        pointwise(f[(2 * q) % PF], ul[0], ul[1], ul[2], ul[3], rl);
+        ld(2 * h + PF, f[(2 * q + PF) % PF]);
+        pointwise(f[(2 * q + 1) % PF], uh[0], uh[1], uh[2], uh[3], rh);
+        eo_acc(tb, h, rl[0] + rh[0], rl[0] - rh[0], sae, sao);
+        eo_acc_d(tb, h, rl[1] + rh[1], rl[1] - rh[1], sae, sao);
+        eo_acc(tb, h, rl[2] + rh[2], rl[2] - rh[2], sbe, sbo);
+        eo_acc(tb, h, rl[3] + rh[3], rl[3] - rh[3], sce, sco);
+      }
+    }
+  }
+  if constexpr (Q & 1) {
+    ld(2 * HP + PF - 1, f[(2 * HP + PF - 1) % PF]);
+    T r[4];
+    pointwise(f[(2 * HP) % PF], eo_mid_val(tb, ae), eo_mid_der(tb, ao), eo_mid_val(tb, be),
+              eo_mid_val(tb, ce), r);
+    eo_acc_mid(tb, r[0], sae);
+    eo_acc_mid_d(tb, r[1], sao);
+    eo_acc_mid(tb, r[2], sbe);
+    eo_acc_mid(tb, r[3], sce);
+  }
+}
+
+// The point-by-point I stage of the Helmholtz operator along one pencil, the
+// unsplit counterpart of eo_helm_row (same inputs, factors and outputs, more
+// products, fewer live registers).  PF register sets hold the factors of
+// points i .. i+PF-1: before point i is computed, the loads of point i+PF-1
+// go into the set that point i-1 has just released.  Loads are unconditional
+// (clamped index) so that their waits sit right before their first use.
+template <typename T, int N, int Q, int PF, typename Load>
+__device__ __forceinline__ void plain_helm_row(const Tab<T, N, Q>& tb, T lam, const T (&a)[N],
+                                               const T (&b)[N], const T (&c)[N], Load load,
+                                               T (&sa)[N], T (&sb)[N], T (&sc)[N]) {
+  auto point = [&](int i, const T (&f)[kNF3]) {
+    const T* Bi = tb.B + i * N;
+    const T* Di = tb.D + i * N;
+    T u = 0, u1 = 0, u2 = 0, u3 = 0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      u += Bi[p] * a[p];
+      u1 += Di[p] * a[p];
+      u2 += Bi[p] * b[p];
+      u3 += Bi[p] * c[p];
+    }
+    const T m = lam * f[0] * u;
+    const T g1 = f[1] * u1 + f[2] * u2 + f[3] * u3;
+    const T g2 = f[2] * u1 + f[4] * u2 + f[5] * u3;
+    const T g3 = f[3] * u1 + f[5] * u2 + f[6] * u3;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      sa[p] += Bi[p] * m + Di[p] * g1;
+      sb[p] += Bi[p] * g2;
+      sc[p] += Bi[p] * g3;
+    }
+  };
+  T f[PF][kNF3];
+#pragma unroll
+  for (int s = 0; s + 1 < PF; ++s) load(s < Q ? s : Q - 1, f[s]);
+#pragma unroll 1
+  for (int i = 0; i < Q; i += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      const int nx = i + s + PF - 1;
+      load(nx < Q ? nx : Q - 1, f[(s + PF - 1) % PF]);
+      if (Q % PF == 0 || i + s < Q) point(i + s, f[s]);
+    }
+  }
+}
+
 // Helmholtz of one element per slot.  The I stage, the pointwise geometric
 // factors with the lambda mass term and the transposed I stage run as one
 // loop over the point index i; PF register sets hold the factors of points
@@ -491,12 +586,11 @@ __device__ __forceinline__ double slot_sum(double v, double* red, int slot, int 
 // i is processed (PF = 1: none, fewest registers).  Local store or (ASM)
 // atomic scatter-add into the global vector with the element's
 // p_e . (H_e p_e).
-template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true, typename TB>
-__device__ __forceinline__ void helm3_body(const TB& tk, T* __restrict__ sm,
+template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true>
+__device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
                                            const DevArgs<T>& a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q;
-  const TabH<T, N, Q>& tb = tk.h;
   const int64_t ee = live ? e : 0;
   const bool pq = live && t < NN;
   int32_t gidx[N];
@@ -524,7 +618,7 @@ __device__ __forceinline__ void helm3_body(const TB& tk, T* __restrict__ sm,
   const bool jk = live && t < QQ;
   T sa[N], sb[N], sc[N];
   if constexpr (EOI) {
-    constexpr int HP = Q / 2, KE = EO<N>::KE, KO = EO<N>::KO;
+    constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
     // accumulators of the transposed I contraction, in split form
     T sae[KE], sao[KO], sbe[KE], sbo[KO], sce[KE], sco[KO];
     zero(sae);
@@ -544,119 +638,32 @@ __device__ __forceinline__ void helm3_body(const TB& tk, T* __restrict__ sm,
       }
       const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
       const T* fp = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
-      // The points are visited in pairs (h, Q-1-h), then the middle one of an
-      // odd Q: sequence position s is point s/2 (even s) or Q-1-s/2 (odd s).
-      auto load = [&](int s, T (&f)[kNF3]) {
-        const int sc = s < Q ? s : Q - 1;
-        const int i = (sc & 1) ? Q - 1 - (sc >> 1) : (sc >> 1);
+      eo_helm_row<T, N, Q, PF>(
+          tb, lam, ae, ao, be, bo, ce, co,
+          [&](int i, T (&f)[kNF3]) {
 #pragma unroll
-        for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
-      };
-      // factors with the mass term and the gradient: r = (m, g1, g2, g3)
-      auto pointwise = [&](const T (&f)[kNF3], T u, T u1, T u2, T u3, T (&r)[4]) {
-        r[0] = lam * f[0] * u;
-        r[1] = f[1] * u1 + f[2] * u2 + f[3] * u3;
-        r[2] = f[2] * u1 + f[4] * u2 + f[5] * u3;
-        r[3] = f[3] * u1 + f[5] * u2 + f[6] * u3;
-      };
-      // PF register sets hold the factors of sequence positions s .. s+PF-1;
-      // before position s is computed, the loads of s+PF-1 go into the set
-      // that s-1 has just released.  One loop trip covers L positions, a
-      // multiple of 2 (a pair) and of PF (so every set index is a constant).
-      constexpr int L = (PF % 2 == 0) ? PF : 2 * PF;
-      constexpr int PP = L / 2;
-      T f[PF][kNF3];
-#pragma unroll
-      for (int s = 0; s + 1 < PF; ++s) load(s, f[s]);
-#pragma unroll 1
-      for (int h0 = 0; h0 < HP; h0 += PP) {
-#pragma unroll
-        for (int q = 0; q < PP; ++q) {
-          const int h = h0 + q;
-          if (HP % PP == 0 || h < HP) {
-            T ul[4], uh[4], rl[4], rh[4];
-            eo_val(tb, h, ae, ao, ul[0], uh[0]);
-            eo_der(tb, h, ae, ao, ul[1], uh[1]);
-            eo_val(tb, h, be, bo, ul[2], uh[2]);
-            eo_val(tb, h, ce, co, ul[3], uh[3]);
-            load(2 * h + PF - 1, f[(2 * q + PF - 1) % PF]);
-            pointwise(f[(2 * q) % PF], ul[0], ul[1], ul[2], ul[3], rl);
-            load(2 * h + PF, f[(2 * q + PF) % PF]);
-            pointwise(f[(2 * q + 1) % PF], uh[0], uh[1], uh[2], uh[3], rh);
-            eo_acc(tb, h, rl[0] + rh[0], rl[0] - rh[0], sae, sao);
-            eo_acc_d(tb, h, rl[1] + rh[1], rl[1] - rh[1], sae, sao);
-            eo_acc(tb, h, rl[2] + rh[2], rl[2] - rh[2], sbe, sbo);
-            eo_acc(tb, h, rl[3] + rh[3], rl[3] - rh[3], sce, sco);
-          }
-        }
-      }
-      if constexpr (Q & 1) {
-        load(2 * HP + PF - 1, f[(2 * HP + PF - 1) % PF]);
-        T r[4];
-        pointwise(f[(2 * HP) % PF], eo_mid_val(tb, ae), eo_mid_der(tb, ao), eo_mid_val(tb, be),
-                  eo_mid_val(tb, ce), r);
-        eo_acc_mid(tb, r[0], sae);
-        eo_acc_mid_d(tb, r[1], sao);
-        eo_acc_mid(tb, r[2], sbe);
-        eo_acc_mid(tb, r[3], sce);
-      }
+            for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
+          },
+          sae, sao, sbe, sbo, sce, sco);
     }
     eo_join<T, N>(sae, sao, sa);
     eo_join<T, N>(sbe, sbo, sb);
     eo_join<T, N>(sce, sco, sc);
   } else {
-    static_assert(N <= kPtMaxN, "point-by-point I stage needs the full tables");
 #pragma unroll
     for (int p = 0; p < N; ++p) sa[p] = sb[p] = sc[p] = T(0);
     if (jk) {
-      const Tab<T, N, Q>& tf = tk.f;
       T av[N], bv[N], cv[N];
       load_i<T, N, Q, true>(sm, t, av, bv, cv);
       const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
       const T* fp = a.fac + ee * (int64_t)(kNF3 * Q3) + t;
-      // one point: forward I contraction, factors, transposed I contraction
-      auto point = [&](int i, const T (&f)[kNF3]) {
-        const T* Bi = tf.B + i * N;
-        const T* Di = tf.D + i * N;
-        T u = 0, u1 = 0, u2 = 0, u3 = 0;
+      plain_helm_row<T, N, Q, PF>(
+          tb, lam, av, bv, cv,
+          [&](int i, T (&f)[kNF3]) {
 #pragma unroll
-        for (int p = 0; p < N; ++p) {
-          u += Bi[p] * av[p];
-          u1 += Di[p] * av[p];
-          u2 += Bi[p] * bv[p];
-          u3 += Bi[p] * cv[p];
-        }
-        const T m = lam * f[0] * u;
-        const T g1 = f[1] * u1 + f[2] * u2 + f[3] * u3;
-        const T g2 = f[2] * u1 + f[4] * u2 + f[5] * u3;
-        const T g3 = f[3] * u1 + f[5] * u2 + f[6] * u3;
-#pragma unroll
-        for (int p = 0; p < N; ++p) {
-          sa[p] += Bi[p] * m + Di[p] * g1;
-          sb[p] += Bi[p] * g2;
-          sc[p] += Bi[p] * g3;
-        }
-      };
-      auto load = [&](int i, T (&f)[kNF3]) {
-#pragma unroll
-        for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
-      };
-      // PF register sets: before point i+s is computed, the loads of point
-      // i+s+PF-1 go into the set that point i+s-1 has just released; loads
-      // are unconditional (clamped index) so that their waits sit right
-      // before their first use
-      T f[PF][kNF3];
-#pragma unroll
-      for (int s = 0; s + 1 < PF; ++s) load(s < Q ? s : Q - 1, f[s]);
-#pragma unroll 1
-      for (int i = 0; i < Q; i += PF) {
-#pragma unroll
-        for (int s = 0; s < PF; ++s) {
-          const int nx = i + s + PF - 1;
-          load(nx < Q ? nx : Q - 1, f[(s + PF - 1) % PF]);
-          if (Q % PF == 0 || i + s < Q) point(i + s, f[s]);
-        }
-      }
+            for (int c = 0; c < kNF3; ++c) f[c] = fp[c * Q3 + i * QQ];
+          },
+          sa, sb, sc);
     }
   }
   slot_sync<NT>();
@@ -697,9 +704,8 @@ constexpr int slot_threads() {
 // the Helmholtz I stage in even-odd pairs (else point by point).
 template <typename T, int N, int Q, int EPB, int OP, int PF = 2, int NTX = 0, bool EOI = true>
 __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
-    k_op3(const TabK<T, N, Q> tk, const DevArgs<T> a) {
+    k_op3(const Tab<T, N, Q> tb, const DevArgs<T> a) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q, S = Q * Q * N;
-  const TabH<T, N, Q>& tb = tk.h;
   constexpr int NT = NTX ? NTX : slot_threads<Q>();
   constexpr bool DER = (OP == OP_HELM || OP == OP_HELM_ASM || OP == OP_GRAD || OP == OP_RHS);
   constexpr int NTEN = DER ? 3 : 1;
@@ -784,7 +790,7 @@ __global__ void __launch_bounds__(EPB * (NTX ? NTX : slot_threads<Q>()))
       for (int r = 0; r < N; ++r) a.out[ee * N3 + r * NN + t] = yv[r];
     }
   } else if constexpr (OP == OP_HELM || OP == OP_HELM_ASM) {
-    helm3_body<T, N, Q, NT, ASM, PF, EOI>(tk, sm, red, slot, t, live, e, a);
+    helm3_body<T, N, Q, NT, ASM, PF, EOI>(tb, sm, red, slot, t, live, e, a);
   } else if constexpr (OP == OP_RHS) {
     const T lam = (T)(a.lam ? a.lam[ee] : a.lam0);
     constexpr int KE = EO<N>::KE, KO = EO<N>::KO;

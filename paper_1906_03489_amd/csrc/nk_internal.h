@@ -15,7 +15,6 @@ namespace nk {
 constexpr int kMinP = 1;
 constexpr int kMaxP = 10;          // n = P+1 <= 11, Q = P+2 <= 12
 constexpr int kNF3 = 7;            // per-point factors in 3-D
-constexpr int kPtMaxN = 7;         // 3-D Helmholtz: point-by-point I stage candidates up to N = P+1
 constexpr int kNF2 = 4;            // per-point factors in 2-D
 constexpr int kVecBlock = 256;     // threads per block of the CG vector kernels
 constexpr int64_t kSegAlign = 2048;  // DOF ranges of each system padded to this (one vector block)

@@ -17,7 +17,7 @@ template <typename T, int P, int EPB, int OP, int PF = 2, int NTX = 0, bool EOI 
 static hipError_t run3(const OpArgs& a) {
   constexpr int N = P + 1, Q = P + 2;
   static_assert(EPB > 0, "tile");
-  const TabK<T, N, Q>& tb = host_tabk<T, N, Q>();
+  const Tab<T, N, Q>& tb = host_tab<T, N, Q>();
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_op3<T, N, Q, EPB, OP, PF, NTX, EOI>), dim3((unsigned)nblk),

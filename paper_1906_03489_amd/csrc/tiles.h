@@ -4,8 +4,6 @@
 // the autotuner picks among them; candidate 0 is the default.
 #pragma once
 
-#include "nk_internal.h"
-
 namespace nk {
 
 constexpr int kMaxTiles = 3;
@@ -63,9 +61,9 @@ constexpr int epb3_count(int P) {
 }
 constexpr bool op_has_lean(int op) { return op == 2 || op == 3; }
 
-// Up to P = kPtMaxN - 1 every 3-D Helmholtz candidate above exists twice:
-// with the I stage in even-odd point pairs (the first half of the list) and
-// point by point on the full tables (the second half, fewer live registers).
-constexpr bool helm_has_pt(int P) { return P + 1 <= kPtMaxN; }
+// Every 3-D Helmholtz candidate above exists twice: with the I stage in
+// even-odd point pairs (the first half of the list: fewer products) and
+// point by point (the second half: fewer live registers).
+constexpr bool helm_has_pt(int) { return true; }
 
 }  // namespace nk

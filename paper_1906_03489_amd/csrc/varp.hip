@@ -14,9 +14,9 @@
 
 namespace nk {
 
-// scalars of the even-odd half tables of order p (TabH<T, p + 1, p + 2>)
+// scalars of the tables of order p (Tab<T, p + 1, p + 2>)
 constexpr int varp_tab_len(int p) {
-  return 2 * ((p + 3) / 2) * ((p / 2 + 1) + ((p - 1) / 2 + 1));
+  return 2 * (p + 2) * (p + 1) + (p + 3) / 2;
 }
 constexpr int varp_tab_off(int P) {
   int off = 0;
@@ -68,10 +68,8 @@ __device__ __forceinline__ void varp_body(const VarpDev<T>& a, const VarpGroup& 
   const int t = threadIdx.x - slot * NT;
   const int64_t e = li * EPB + slot;
   const bool live = slot < EPB && e < G.nelem;
-  // the half tables only (the paired I stage), TabK's layout without the full tables
-  using TK = TabK<T, N, Q, false>;
-  static_assert(sizeof(TK) == sizeof(T) * varp_tab_len(P), "varp table layout");
-  const TK& tb = *reinterpret_cast<const TK*>(ctab<T>() + varp_tab_off(P));
+  static_assert(sizeof(Tab<T, N, Q>) == sizeof(T) * varp_tab_len(P), "varp table layout");
+  const Tab<T, N, Q>& tb = *reinterpret_cast<const Tab<T, N, Q>*>(ctab<T>() + varp_tab_off(P));
   DevArgs<T> d{};
   d.nelem = G.nelem;
   d.in = a.x + G.c0;
@@ -121,8 +119,8 @@ template <int P>
 static void put_tabs(double* t64, float* t32) {
   if constexpr (P <= kMaxP) {
     constexpr int N = P + 1, Q = P + 2;
-    std::memcpy(t64 + varp_tab_off(P), &host_tabh<double, N, Q>(), sizeof(TabH<double, N, Q>));
-    std::memcpy(t32 + varp_tab_off(P), &host_tabh<float, N, Q>(), sizeof(TabH<float, N, Q>));
+    std::memcpy(t64 + varp_tab_off(P), &host_tab<double, N, Q>(), sizeof(Tab<double, N, Q>));
+    std::memcpy(t32 + varp_tab_off(P), &host_tab<float, N, Q>(), sizeof(Tab<float, N, Q>));
     put_tabs<P + 1>(t64, t32);
   }
 }

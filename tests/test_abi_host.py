@@ -81,8 +81,8 @@ def test_invalid_arguments_rejected_before_device_work():
     assert L.nk_set_tile_config(2, 3, 6, 0, 9) == nk.NK_OK
     assert L.nk_tile_config(2, 3, 6, 0).decode() == "epb1_thr64_pt"
     assert L.nk_set_tile_config(2, 3, 6, 0, 0) == nk.NK_OK
-    # above P = 6 only the paired I stage: two tiles x three forms + matrix-core (Q = 10 > 8: none)
-    assert L.nk_tile_count(2, 3, 8) == 6
+    # P = 8: two tiles x three forms x two I-stage forms (Q = 10 > 8: no matrix-core variant)
+    assert L.nk_tile_count(2, 3, 8) == 12
     assert L.nk_tile_count(0, 3, 6) == 3      # BwdTrans: no lean form
     assert L.nk_tile_config(2, 3, 6, 0).decode().startswith("epb")
 
