@@ -50,7 +50,7 @@ def iprod_bytes_per_elem(P, Q, s=8):
 
 
 KERNEL_SOURCES = ["paper_1906_03489_amd/csrc/engine.h", "paper_1906_03489_amd/csrc/ops3d_inst.hip",
-                  "paper_1906_03489_amd/csrc/tiles.h"]
+                  "paper_1906_03489_amd/csrc/tiles.h", "paper_1906_03489_amd/csrc/tables.h"]
 PMC_SUMMARY = "profiles/helmholtz_f64_32c_P6_pmc.txt"
 
 
@@ -80,7 +80,8 @@ def measured_traffic():
 
 
 FWD_FLOPS_SUMMARY = "profiles/fwd_trans_32c_P6_flops.txt"
-FWD_SOURCES = ["paper_1906_03489_amd/csrc/deriv.hip", "paper_1906_03489_amd/csrc/engine.h"]
+FWD_SOURCES = ["paper_1906_03489_amd/csrc/deriv.hip", "paper_1906_03489_amd/csrc/engine.h",
+               "paper_1906_03489_amd/csrc/tables.h", "paper_1906_03489_amd/csrc/tiles.h"]
 VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
 

@@ -244,12 +244,21 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64) __attribute__((amdgpu_w
       if constexpr (OP == OP_BWD) {
         slot_sync<64>();   // every lane has read the coefficients under Xw
         T* x = Xw + ela * XS + j * S::RS;
+        // eta_1 stage in even-odd point pairs (the GLL points are symmetric)
+        T ve[EO<N>::KE], vo[EO<N>::KO];
+        eo_split<T, N>(V, ve, vo);
 #pragma unroll 1
-        for (int i = 0; i < Q; ++i) {
-          T u = T(0);
-#pragma unroll
-          for (int p = 0; p < N; ++p) u += tb.B[i * N + p] * V[p];
-          if (row) x[i] = u;
+        for (int h = 0; h < Q / 2; ++h) {
+          T lo, hi;
+          eo_val(tb, h, ve, vo, lo, hi);
+          if (row) {
+            x[h] = lo;
+            x[Q - 1 - h] = hi;
+          }
+        }
+        if constexpr (Q & 1) {
+          const T mid = eo_mid_val(tb, ve);
+          if (row) x[Q / 2] = mid;
         }
         slot_sync<64>();
         for (int k = lane; k < ne * NP; k += 64) {
@@ -288,16 +297,21 @@ __global__ void __launch_bounds__(TriShape<P>::WPB * 64) __attribute__((amdgpu_w
     } else {   // IProductWRTBase: staged point values times w detJ
       const T* x = Xw + ela * XS + j * S::RS;
       const T* f = a.fac + g * (int64_t)(4 * Q * LANES) + lane;
-      T fa = row ? f[0] : T(0), fb = row ? f[LANES] : T(0);
+      // transposed eta_1 stage in even-odd point pairs
+      T se[EO<N>::KE], so[EO<N>::KO];
+      zero(se);
+      zero(so);
 #pragma unroll 1
-      for (int i = 0; i < Q; ++i) {
-        const T fc = (row && i + 2 < Q) ? f[(i + 2) * LANES] : T(0);
-        const T mq = row ? fa * x[i] : T(0);
-#pragma unroll
-        for (int p = 0; p < N; ++p) SA[p] += tb.B[i * N + p] * mq;
-        fa = fb;
-        fb = fc;
+      for (int h = 0; h < Q / 2; ++h) {
+        const T fl = row ? f[h * LANES] : T(0), fh = row ? f[(Q - 1 - h) * LANES] : T(0);
+        const T ml = row ? fl * x[h] : T(0), mh = row ? fh * x[Q - 1 - h] : T(0);
+        eo_acc(tb, h, ml + mh, ml - mh, se, so);
       }
+      if constexpr (Q & 1) {
+        const T fm = row ? f[(Q / 2) * LANES] : T(0);
+        eo_acc_mid(tb, row ? fm * x[Q / 2] : T(0), se);
+      }
+      eo_join<T, N>(se, so, SA);
       slot_sync<64>();
     }
     // transposed eta_2 stage
