@@ -16,13 +16,15 @@
 //                         Jacobian determinant (fast diagonalisation: the 1-D
 //                         reference mass M1 = V diag(lam) V^T gives
 //                         (M1 x M1 x M1)^{-1} = (V x V x V) diag(1/(lam lam lam))
-//                         (V x V x V)^T).  The whole iteration stays on chip;
+//                         (V x V x V)^T, V block diagonal in the even and odd
+//                         modes).  The whole iteration stays on chip;
 //                         HBM sees the point values, w detJ and the result.
 //
 // Element data layouts as for the other operators: points [E][Q^d] with
 // q = i + Q(j + Q k), coefficients [E][n^d] with m = p + n(q + n r); vector
 // fields [E][d][Q^d].  Derivative factors [E][d*d+1][Q^d] (J^{-1} entry
 // (a,c) at a*d + c, then w detJ) in point order.
+#include <cmath>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -68,9 +70,20 @@ static const T* colloc_table(int Q) {
   });
 }
 
-// Fast-diagonalisation tables of order P: VT [N][N] (VT[o][m] = V[m][o]),
-// V [N][N], then S [N^3] with S[p + N(q + N r)] = 1 / (lam_p lam_q lam_r)
-// (3-D) or S[p + N q] = 1 / (lam_p lam_q) (2-D).
+// Fast-diagonalisation tables of order P.  2-D: VT [N][N] (VT[o][m] =
+// V[m][o]), V [N][N], then S [N^2] with S[p + N q] = 1 / (lam_p lam_q), from
+// the 1-D modal mass M1 = V diag(lam) V^T.  3-D: M1 commutes with the
+// reflection of the modes (the vertex swap and the sign of the odd interior
+// modes; see the even-odd tables of engine.h), so in the orthonormal basis of
+// even members ((d_0 + d_P)/sqrt 2, d_1, d_3, ...) and odd members
+// ((d_0 - d_P)/sqrt 2, d_2, ...) it is block diagonal, M_e = V_e L_e V_e^T and
+// M_o = V_o L_o V_o^T, and the eigenvector transforms act on the split
+// coefficients of eo_split / eo_join: FE [KE][KE] and FO [KO][KO] with
+// F[a][k] = V[k][a] (column k = 0 divided by sqrt 2, which maps the split's
+// c_0 +- c_P onto the orthonormal vertex members), GE and GO their
+// transposes (the same scaling on row 0), then S [N^3] with
+// S[a + N(b + N c)] = 1 / (lam_a lam_b lam_c) in the eigen ordering (the KE
+// even eigenvalues, then the KO odd ones).
 template <typename T>
 static const T* fastdiag_table(int P, int Q, int dim) {
   return cached_table<T>(1000L * dim + 32L * P + Q, [P, Q, dim] {
@@ -81,17 +94,57 @@ static const T* fastdiag_table(int P, int Q, int dim) {
     for (int p = 0; p < N; ++p)
       for (int pp = 0; pp < N; ++pp)
         for (int i = 0; i < Q; ++i) M[p * N + pp] += w[i] * B[i * N + p] * B[i * N + pp];
-    symmetric_eigen(N, M.data(), V.data(), lam.data());
-    const int nd = dim == 3 ? N * N * N : N * N;
-    std::vector<double> t(2 * N * N + nd);
-    for (int o = 0; o < N; ++o)
-      for (int m = 0; m < N; ++m) {
-        t[o * N + m] = V[m * N + o];
-        t[N * N + o * N + m] = V[o * N + m];
+    if (dim == 2) {
+      symmetric_eigen(N, M.data(), V.data(), lam.data());
+      std::vector<double> t(2 * N * N + N * N);
+      for (int o = 0; o < N; ++o)
+        for (int m = 0; m < N; ++m) {
+          t[o * N + m] = V[m * N + o];
+          t[N * N + o * N + m] = V[o * N + m];
+        }
+      for (int id = 0; id < N * N; ++id) {
+        const int p = id % N, q = id / N;
+        t[2 * N * N + id] = 1.0 / (lam[p] * lam[q]);
       }
-    for (int id = 0; id < nd; ++id) {
-      const int p = id % N, q = (id / N) % N, r = id / (N * N);
-      t[2 * N * N + id] = 1.0 / (lam[p] * lam[q] * (dim == 3 ? lam[r] : 1.0));
+      return t;
+    }
+    const int KE = P / 2 + 1, KO = (P - 1) / 2 + 1;
+    const double r2 = std::sqrt(0.5);
+    // orthonormal basis vectors (columns), even members then odd members
+    auto basis = [&](int col, int k) {   // component k of basis vector col
+      if (col == 0) return (k == 0 || k == P) ? r2 : 0.0;
+      if (col < KE) return k == 2 * col - 1 ? 1.0 : 0.0;
+      const int m = col - KE;
+      if (m == 0) return k == 0 ? r2 : (k == P ? -r2 : 0.0);
+      return k == 2 * m ? 1.0 : 0.0;
+    };
+    auto block = [&](int c0, int n, std::vector<double>& Vb, std::vector<double>& lb) {
+      std::vector<double> Mb(n * n, 0.0);
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+          for (int k = 0; k < N; ++k)
+            for (int l = 0; l < N; ++l)
+              Mb[a * n + b] += basis(c0 + a, k) * M[k * N + l] * basis(c0 + b, l);
+      Vb.assign(n * n, 0.0);
+      lb.assign(n, 0.0);
+      symmetric_eigen(n, Mb.data(), Vb.data(), lb.data());
+    };
+    std::vector<double> Ve, le, Vo, lo;
+    block(0, KE, Ve, le);
+    block(KE, KO, Vo, lo);
+    std::vector<double> t;
+    for (int a = 0; a < KE; ++a)        // FE[a][k] = Ve[k][a] (k = 0 scaled)
+      for (int k = 0; k < KE; ++k) t.push_back(Ve[k * KE + a] * (k == 0 ? r2 : 1.0));
+    for (int a = 0; a < KO; ++a)        // FO
+      for (int k = 0; k < KO; ++k) t.push_back(Vo[k * KO + a] * (k == 0 ? r2 : 1.0));
+    for (int k = 0; k < KE; ++k)        // GE[k][a] = Ve[k][a] (k = 0 scaled)
+      for (int a = 0; a < KE; ++a) t.push_back(Ve[k * KE + a] * (k == 0 ? r2 : 1.0));
+    for (int k = 0; k < KO; ++k)        // GO
+      for (int a = 0; a < KO; ++a) t.push_back(Vo[k * KO + a] * (k == 0 ? r2 : 1.0));
+    auto ev = [&](int i) { return i < KE ? le[i] : lo[i - KE]; };
+    for (int id = 0; id < N * N * N; ++id) {
+      const int a = id % N, b = (id / N) % N, c = id / (N * N);
+      t.push_back(1.0 / (ev(a) * ev(b) * ev(c)));
     }
     return t;
   });
@@ -348,37 +401,6 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
 
 // ----------------------------------------------------------------- FwdTrans
 
-// Contract direction DIR (0: p, 1: q, 2: r) of the n^3 array X in LDS
-// (layout [r][q][p]) with the N x N table A (row o at A + o*N):
-// X'[.., o, ..] = sum_m A[o][m] X[.., m, ..].  Thread t < N^2 owns the pencil
-// along DIR indexed by the other two directions.
-template <typename T, int N, int NT, int DIR>
-__device__ __forceinline__ void fd_contract(T* __restrict__ X, const T* __restrict__ A, int t,
-                                            bool act) {
-  constexpr int NN = N * N;
-  constexpr int stride = DIR == 0 ? 1 : DIR == 1 ? N : NN;
-  const int a = t % N, b = t / N;
-  const int base = DIR == 0 ? a * N + b * NN : DIR == 1 ? a + b * NN : a + b * N;
-  const bool me = act && t < NN;
-  T x[N];
-  if (me) {
-#pragma unroll
-    for (int m = 0; m < N; ++m) x[m] = X[base + m * stride];
-  }
-  slot_sync<NT>();
-  if (me) {
-#pragma unroll 2
-    for (int o = 0; o < N; ++o) {
-      const T* Ao = A + o * N;
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += Ao[m] * x[m];
-      X[base + o * stride] = s;
-    }
-  }
-  slot_sync<NT>();
-}
-
 // y = M_e x for the slot's element: BwdTrans stages, w detJ at the points,
 // IProductWRTBase stages.  Vectors are columns over r of thread t = p + N q.
 template <typename T, int N, int Q, int NT>
@@ -419,34 +441,135 @@ __device__ __forceinline__ void fd_mass(const Tab<T, N, Q>& tb, T* __restrict__ 
   slot_sync<NT>();
 }
 
-// z = P^{-1} r = (1/c) (V x V x V) S (V x V x V)^T r.
+// The even or odd block transform of one split pencil: FWD applies FE / FO
+// to the split coefficients, else GE / GO to eigen-coordinates.
+template <typename T, int N, bool FWD>
+__device__ __forceinline__ void fd_eo_apply(const T* __restrict__ tab, const T (&ie)[EO<N>::KE],
+                                            const T (&io)[EO<N>::KO], T (&oe)[EO<N>::KE],
+                                            T (&oo)[EO<N>::KO]) {
+  constexpr int KE = EO<N>::KE, KO = EO<N>::KO;
+  const T* Ae = tab + (FWD ? 0 : KE * KE + KO * KO);
+  const T* Ao = Ae + KE * KE;
+#pragma unroll
+  for (int o = 0; o < KE; ++o) {
+    T v = 0;
+#pragma unroll
+    for (int m = 0; m < KE; ++m) v += Ae[o * KE + m] * ie[m];
+    oe[o] = v;
+  }
+#pragma unroll
+  for (int o = 0; o < KO; ++o) {
+    T v = 0;
+#pragma unroll
+    for (int m = 0; m < KO; ++m) v += Ao[o * KO + m] * io[m];
+    oo[o] = v;
+  }
+}
+
+// One direction of the even-odd fast diagonalisation on the n^3 array X in
+// LDS (layout [r][q][p]); thread t < N^2 owns the pencil along DIR.  FWD:
+// split the pencil, apply FE / FO, store the KE even then the KO odd
+// eigen-coordinates; else read those, apply GE / GO and join.
+template <typename T, int N, int NT, int DIR, bool FWD>
+__device__ __forceinline__ void fd_eo_contract(T* __restrict__ X, const T* __restrict__ tab, int t,
+                                               bool act) {
+  constexpr int NN = N * N, KE = EO<N>::KE, KO = EO<N>::KO;
+  constexpr int stride = DIR == 0 ? 1 : DIR == 1 ? N : NN;
+  const int a = t % N, b = t / N;
+  const int base = DIR == 0 ? a * N + b * NN : DIR == 1 ? a + b * NN : a + b * N;
+  const bool me = act && t < NN;
+  T x[N];
+  if (me) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = X[base + m * stride];
+  }
+  slot_sync<NT>();
+  if (me) {
+    T ie[KE], io[KO];
+    if constexpr (FWD) {
+      eo_split<T, N>(x, ie, io);
+    } else {
+#pragma unroll
+      for (int m = 0; m < KE; ++m) ie[m] = x[m];
+#pragma unroll
+      for (int m = 0; m < KO; ++m) io[m] = x[KE + m];
+    }
+    T oe[KE], oo[KO];
+    fd_eo_apply<T, N, FWD>(tab, ie, io, oe, oo);
+    if constexpr (FWD) {
+#pragma unroll
+      for (int m = 0; m < KE; ++m) X[base + m * stride] = oe[m];
+#pragma unroll
+      for (int m = 0; m < KO; ++m) X[base + (KE + m) * stride] = oo[m];
+    } else {
+      T y[N];
+      eo_join<T, N>(oe, oo, y);
+#pragma unroll
+      for (int m = 0; m < N; ++m) X[base + m * stride] = y[m];
+    }
+  }
+  slot_sync<NT>();
+}
+
+// Direction p of the preconditioner: forward transform, the diagonal
+// scaling, backward transform, all in the registers of the thread that owns
+// the pencil (t = q + N r).
+template <typename T, int N, int NT>
+__device__ __forceinline__ void fd_eo_middle(T* __restrict__ X, const T* __restrict__ tab,
+                                             const T* __restrict__ S, T inv_c, int t, bool act) {
+  constexpr int NN = N * N, KE = EO<N>::KE, KO = EO<N>::KO;
+  const int base = (t % N) * N + (t / N) * NN;
+  const bool me = act && t < NN;
+  if (me) {
+    T x[N], ie[KE], io[KO], ye[KE], yo[KO];
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = X[base + m];
+    eo_split<T, N>(x, ie, io);
+    fd_eo_apply<T, N, true>(tab, ie, io, ye, yo);
+#pragma unroll
+    for (int m = 0; m < KE; ++m) ye[m] *= inv_c * S[base + m];
+#pragma unroll
+    for (int m = 0; m < KO; ++m) yo[m] *= inv_c * S[base + KE + m];
+    fd_eo_apply<T, N, false>(tab, ye, yo, ie, io);
+    eo_join<T, N>(ie, io, x);
+#pragma unroll
+    for (int m = 0; m < N; ++m) X[base + m] = x[m];
+  }
+  slot_sync<NT>();
+}
+
+// z = P^{-1} r = (1/c) (V x V x V) S (V x V x V)^T r, each 1-D transform in
+// its even and odd blocks (half the products of a dense N x N one).  The
+// thread t = p + N q holding r along direction r transforms it in registers;
+// direction q goes through LDS both ways, direction p does forward, scaling
+// and backward in one pass.
 template <typename T, int N, int NT>
 __device__ __forceinline__ void fd_precond(const T* __restrict__ tab, T* __restrict__ X, int t,
                                            bool live, T inv_c, const T (&r)[N], T (&z)[N]) {
-  constexpr int NN = N * N;
+  constexpr int NN = N * N, KE = EO<N>::KE, KO = EO<N>::KO;
   const bool me = live && t < NN;
-  const T* VT = tab;
-  const T* V = tab + NN;
-  const T* S = tab + 2 * NN;
+  const T* S = tab + 2 * (KE * KE + KO * KO);
   if (me) {
+    T ie[KE], io[KO], ye[KE], yo[KO];
+    eo_split<T, N>(r, ie, io);
+    fd_eo_apply<T, N, true>(tab, ie, io, ye, yo);
 #pragma unroll
-    for (int k = 0; k < N; ++k) X[k * NN + t] = r[k];
+    for (int m = 0; m < KE; ++m) X[m * NN + t] = ye[m];
+#pragma unroll
+    for (int m = 0; m < KO; ++m) X[(KE + m) * NN + t] = yo[m];
   }
   slot_sync<NT>();
-  fd_contract<T, N, NT, 2>(X, VT, t, live);
-  fd_contract<T, N, NT, 1>(X, VT, t, live);
-  fd_contract<T, N, NT, 0>(X, VT, t, live);
+  fd_eo_contract<T, N, NT, 1, true>(X, tab, t, live);
+  fd_eo_middle<T, N, NT>(X, tab, S, inv_c, t, live);
+  fd_eo_contract<T, N, NT, 1, false>(X, tab, t, live);
   if (me) {
+    T ye[KE], yo[KO], oe[KE], oo[KO];
 #pragma unroll
-    for (int k = 0; k < N; ++k) X[k * NN + t] *= inv_c * S[k * NN + t];
-  }
-  slot_sync<NT>();
-  fd_contract<T, N, NT, 0>(X, V, t, live);
-  fd_contract<T, N, NT, 1>(X, V, t, live);
-  fd_contract<T, N, NT, 2>(X, V, t, live);
-  if (me) {
+    for (int m = 0; m < KE; ++m) ye[m] = X[m * NN + t];
 #pragma unroll
-    for (int k = 0; k < N; ++k) z[k] = X[k * NN + t];
+    for (int m = 0; m < KO; ++m) yo[m] = X[(KE + m) * NN + t];
+    fd_eo_apply<T, N, false>(tab, ye, yo, oe, oo);
+    eo_join<T, N>(oe, oo, z);
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) z[k] = T(0);
