@@ -53,6 +53,38 @@ def test_library_basis_tables_match_oracle(P):
     np.testing.assert_allclose(D, Do, atol=1e-13)
 
 
+@pytest.mark.parametrize("P", list(range(1, 11)))
+def test_library_tables_have_the_reflection_symmetry_of_the_even_odd_kernels(P):
+    """The hexahedral kernels read only the rows of the first ceil(Q/2) points
+    and rebuild the others from the reflection x -> -x: the GLL points are
+    symmetric, phi_p(-x) = s_p phi_{p*}(x) with p* swapping the vertex modes and
+    s_p = -1 for even interior modes, and phi_p'(-x) = -s_p phi_{p*}'(x).  Then
+    the even-odd split c -> (c_0 + c_P, c_1, c_3, ...), (c_0 - c_P, c_2, ...) with
+    the members (1/2, phi_1, ...) and (-x/2, phi_2, ...) gives u(x_i) = E + O and
+    u(x_{Q-1-i}) = E - O (derivatives likewise), which is checked here against
+    the full tables on random coefficients."""
+    nk, _ = _lib()
+    Q, N = P + 2, P + 1
+    x, _, B, D = nk.basis_tables(P, Q)
+    np.testing.assert_allclose(x[::-1], -x, atol=1e-15)
+    star = [N - 1] + list(range(1, N - 1)) + [0]
+    sgn = np.array([1.0] + [(-1.0 if p % 2 == 0 else 1.0) for p in range(1, N - 1)] + [1.0])
+    np.testing.assert_allclose(B[::-1], B[:, star] * sgn, atol=1e-14)
+    np.testing.assert_allclose(D[::-1], -D[:, star] * sgn, atol=1e-12)
+    c = np.random.default_rng(P).uniform(-1, 1, N)
+    ce = np.r_[c[0] + c[P], c[1:P:2]]
+    co = np.r_[c[0] - c[P], c[2:P:2]]
+    H = (Q + 1) // 2
+    for i in range(H):
+        e = 0.5 * ce[0] + B[i, 1:P:2] @ ce[1:]
+        o = -0.5 * x[i] * co[0] + B[i, 2:P:2] @ co[1:]
+        ed = -0.5 * co[0] + D[i, 2:P:2] @ co[1:]
+        od = D[i, 1:P:2] @ ce[1:]
+        u, du = B @ c, D @ c
+        assert abs(e + o - u[i]) < 1e-13 and abs(e - o - u[Q - 1 - i]) < 1e-13
+        assert abs(ed + od - du[i]) < 1e-12 and abs(ed - od - du[Q - 1 - i]) < 1e-12
+
+
 def test_invalid_arguments_rejected_before_device_work():
     nk, L = _lib()
     h = ctypes.c_void_p()
