@@ -25,6 +25,9 @@ methods" (arXiv 1906.03489):
   assembly   C0 gather/scatter (section 2.1, assembly operator), Dirichlet
              restriction, Jacobi-preconditioned CG and a sparse direct solve of
              the weak problem of Eqs. (1)-(2).
+  condense   static condensation of the assembled system onto the elemental
+             boundary DOFs and the element-by-element interior recovery
+             (section 2.1).
   grad       gradients of a solve's loss with respect to the per-element
              Helmholtz coefficient and the per-point diffusion coefficient.
 
@@ -37,6 +40,7 @@ from .element import (tensor_bases, geometry, inverse_jacobian, collocation_deri
                       helmholtz_apply, helmholtz_matrices, mass_matrices, weak_rhs)
 from .assembly import (assemble_vector, gather, assembled_matrix, pcg, direct_solve,
                        jacobi_diagonal)
+from .condense import Condensed, condensed_solve, interior_modes, schur_complement
 from .grad import param_grad, loss_and_solution
 
 __all__ = [
@@ -46,4 +50,5 @@ __all__ = [
     "helmholtz_apply", "helmholtz_matrices", "mass_matrices", "weak_rhs",
     "assemble_vector", "gather", "assembled_matrix", "pcg", "direct_solve",
     "jacobi_diagonal", "param_grad", "loss_and_solution",
+    "Condensed", "condensed_solve", "interior_modes", "schur_complement",
 ]

@@ -829,3 +829,12 @@ def solve_boxes(seed_: int, nsolves: int, smin: int = 64, smax: int = 4096):
         c = max(1, int(math.ceil(si / (a * b))))
         boxes.append((a, b, c))
     return boxes
+
+
+def dof_signs(seed_: int, l2g: np.ndarray, nglobal: int) -> np.ndarray:
+    """A consistent orientation-sign array for a map: each global DOF draws
+    sigma_g = +-1 with equal odds and every local mode referencing it gets
+    sign sigma_g (the same global functions, some negated).  int8, shape of
+    l2g."""
+    sig = np.where(np.random.default_rng(seed_).random(int(nglobal)) < 0.5, -1, 1).astype(np.int8)
+    return sig[np.asarray(l2g, np.int64)]
