@@ -77,7 +77,7 @@ typedef enum {
 
 typedef enum { NK_F64 = 0, NK_F32 = 1 } nk_dtype;
 
-typedef enum { NK_SOLVE_F64 = 0, NK_SOLVE_F32_REFINED = 1 } nk_solve_mode;
+typedef enum { NK_SOLVE_F64 = 0, NK_SOLVE_F32_REFINED = 1, NK_SOLVE_CONDENSED = 2 } nk_solve_mode;
 
 typedef struct nk_space_s* nk_space;
 typedef struct nk_system_s* nk_system;
@@ -85,7 +85,8 @@ typedef struct nk_system_s* nk_system;
 typedef struct {
   int iters;             /* CG iterations summed over restarts (FP64 mode) or inner
                             FP32 iterations summed over refinement steps            */
-  int outer_iters;       /* FP64 residual updates (FP32-refined mode), 0 otherwise     */
+  int outer_iters;       /* FP64 residual updates (FP32-refined mode), condensation
+                            passes (condensed mode), 0 otherwise                       */
   double rel_resid;      /* true ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit    */
   double solve_ms;       /* wall time of the solve on the host clock                   */
   int status;            /* nk_status of this system                                   */
@@ -359,13 +360,42 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
  * direction; the solve ends on the true residual of the returned x, and maxit
  * bounds the FP32 iterations.  (Environment NK_REFINE=restart selects plain
  * iterative refinement instead: FP32 CG solves of the FP64 residual equation,
- * each reducing its residual by NK_INNER_TOL, default 1e-4.)  Iterations run as captured HIP graphs that
+ * each reducing its residual by NK_INNER_TOL, default 1e-4.)
+ * NK_SOLVE_CONDENSED (section 2.1, static condensation): FP64 CG on the
+ * system condensed onto the elemental boundary DOFs (nk_system_condense,
+ * built on first use), preconditioned by the diagonal of its boundary block;
+ * the interiors follow element by element, and the pass repeats on the full
+ * residual b - A x until it meets rtol (iters: boundary CG iterations summed
+ * over passes).  One-system hexahedral systems with 2 <= P <= 6 only
+ * (NK_EUNSUPPORTED otherwise).  Iterations run as captured HIP graphs that
  * do not depend on rtol or maxit.  info (host, may be NULL) receives one
  * entry per system (nsys entries for a batched system).  Returns NK_ENOCONV
  * (budget spent with the true residual above rtol) or NK_EBREAKDOWN if any
  * system did not converge. */
 nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double* x,
                       double rtol, int maxit, nk_solve_info* info, void* stream);
+
+/* Static condensation (section 2.1): the modified basis splits each
+ * hexahedron's modes into boundary modes (index 0 or P in some direction,
+ * shared with neighbours) and (P-1)^3 interior modes owned by the element, so
+ * the system condenses onto the boundary DOFs with the elemental Schur
+ * complements S_e = H_bb - H_bi H_ii^{-1} H_ib.  Builds (once per system;
+ * later calls reuse it) the boundary system and the dense inverses H_ii^{-1}
+ * of every element (E (P-1)^6 doubles of device memory), and returns the
+ * number of boundary DOFs in *nboundary (host).  bmap (device int32
+ * [nboundary], may be NULL) receives the global DOF of each boundary DOF, in
+ * increasing order.  Requires a one-system system on a uniform-order
+ * hexahedral space, 2 <= P <= 6, Q = P + 2 (else NK_EUNSUPPORTED), and a map
+ * whose interior modes each reference a DOF no other mode references and that
+ * is not Dirichlet (else NK_EUNSUPPORTED).  Synchronises the stream. */
+nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, void* stream);
+
+/* yb = S xb, the assembled condensed operator over the boundary numbering of
+ * nk_system_condense (Dirichlet entries of xb read as zero, Dirichlet entries
+ * of yb zero).  Device FP64 [nboundary].  Matrix-free: two sum-factorised
+ * Helmholtz passes and one dense H_ii^{-1} product per element.  Requires a
+ * prior nk_system_condense.  Synchronises the stream. */
+nk_status nk_condensed_apply(nk_system sys, const double* xb, double* yb, void* stream);
 
 /* Several separately created systems (their own spaces, orders and maps)
  * solved in one call, as nk_cg_solve solves each: sys, b, x are host arrays
@@ -382,7 +412,8 @@ nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double
  * members' factors: device memory comparable to their spaces) and kept for
  * later calls with the same list, at most four lists, until a member is
  * destroyed.  A system may appear once per call; all must live on the
- * current device.  Synchronises like nk_cg_solve. */
+ * current device.  NK_SOLVE_CONDENSED is not taken here (NK_EUNSUPPORTED).
+ * Synchronises like nk_cg_solve. */
 nk_status nk_cg_solve_batched(nk_system* sys, int nsys, nk_solve_mode mode,
                               const double* const* b, double* const* x, double rtol, int maxit,
                               nk_solve_info* info, void* stream);

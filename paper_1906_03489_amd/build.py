@@ -27,7 +27,7 @@ DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 SOURCES = [("api.cpp", []), ("basis.cpp", []), ("geom.hip", []), ("cg.hip", []),
            ("varp.hip", []), ("ops2d.hip", []), ("mfma.hip", []), ("deriv.hip", []), ("tri.hip", []),
-           ("collapsed3d.hip", [])] + \
+           ("collapsed3d.hip", []), ("condense.hip", [])] + \
           [("ops3d_inst.hip", [f"-DNK_PSET={k}"]) for k in range(7)]
 
 

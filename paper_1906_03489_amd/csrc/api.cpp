@@ -792,9 +792,12 @@ nk_status nk_helmholtz_param_grad(nk_space s, const double* z_loc, const double*
 }
 
 // ================================================================ systems
+static void cond_free(CondData*& c);
+
 static void system_free(nk_system y) {
   if (!y) return;
   if (y->cs) (void)hipStreamSynchronize(y->cs);
+  cond_free(y->cond);
   if (y->g64) (void)hipGraphExecDestroy(y->g64);
   if (y->g32) (void)hipGraphExecDestroy(y->g32);
   dfree(y->d_dof_off);
@@ -873,7 +876,7 @@ static int tune_asm_tile(nk_system y, nk_dtype t, int g, hipStream_t st);
 static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64_t* elem_off,
                                const int64_t* dof_off, const int32_t* l2g, const int8_t* sign,
                                const uint8_t* dirichlet, const double* lambda, double lambda0,
-                               void* stream) {
+                               void* stream, bool tune = true) {
   if (!out) return fail(NK_EINVAL, "out is NULL");
   *out = nullptr;
   if (!s) return fail(NK_EINVAL, "space is NULL");
@@ -1070,8 +1073,8 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
   if (e != hipSuccess) return cleanup(hip_fail(e, "system setup"));
   if (bad) return cleanup(fail(NK_EINVAL, "l2g index outside its system's DOF range, or a sign other than +-1"));
   for (size_t g = 0; g < s->groups.size(); ++g) {
-    y->tiles64.push_back(tune_asm_tile(y, NK_F64, (int)g, st));
-    y->tiles32.push_back(tune_asm_tile(y, NK_F32, (int)g, st));
+    y->tiles64.push_back(tune ? tune_asm_tile(y, NK_F64, (int)g, st) : 0);
+    y->tiles32.push_back(tune ? tune_asm_tile(y, NK_F32, (int)g, st) : 0);
   }
   // the timing runs wrote into the work vectors: clear them again
   if ((e = vec_fill<double>(y->y, np, 0.0, st)) || (e = vec_fill<float>(y->y32, np, 0.f, st)) ||
@@ -1122,6 +1125,15 @@ nk_status nk_system_destroy(nk_system sys) {
 static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, void* out,
                                double* dots, const int32_t* seg_done, int tile, hipStream_t st) {
   nk_space s = y->space;
+  if (y->sc) {   // boundary system of a static condensation (FP64, one hexahedral group)
+    if (t != NK_F64 || g != 0) return hipErrorInvalidValue;
+    const int32_t* ds = dots ? y->dslot : nullptr;
+    hipError_t e;
+    if ((e = sc_pass(*y->sc, 1, (const double*)x, nullptr, nullptr, nullptr, seg_done, st)) ||
+        (e = sc_ainv(*y->sc, nullptr, nullptr, 1.0, 0.0, -1.0, nullptr, seg_done, st)))
+      return e;
+    return sc_pass(*y->sc, 2, (const double*)x, (double*)out, dots, ds, seg_done, st);
+  }
   const Group& G = s->groups[g];
   OpArgs a;
   a.op = OP_HELM_ASM;
@@ -1746,7 +1758,8 @@ static hipError_t solve_padded(nk_system y, nk_solve_mode mode, double rtol, int
 }
 
 static nk_status check_solve_args(nk_solve_mode mode, double rtol, int maxit) {
-  if (mode != NK_SOLVE_F64 && mode != NK_SOLVE_F32_REFINED) return fail(NK_EINVAL, "bad mode");
+  if (mode != NK_SOLVE_F64 && mode != NK_SOLVE_F32_REFINED && mode != NK_SOLVE_CONDENSED)
+    return fail(NK_EINVAL, "bad mode");
   if (!(rtol > 0.0) || rtol >= 1.0) return fail(NK_EINVAL, "rtol must be in (0, 1)");
   if (maxit < 1) return fail(NK_EINVAL, "maxit must be >= 1");
   return NK_OK;
@@ -1760,12 +1773,303 @@ static void fill_info(nk_solve_info* info, const SolveOut& o, int i, nk_solve_mo
   info->status = o.stat[i];
 }
 
+// ---------------------------------------------------- static condensation
+// Section 2.1: the assembled hexahedral system condensed onto the elemental
+// boundary DOFs.  The boundary system is an ordinary assembled system over
+// the boundary DOFs plus one dummy Dirichlet DOF that every interior mode
+// maps to (so the assembled kernels gather 0 there and scatter nothing); its
+// operator is the three-launch condensed one of condense.hip, its Jacobi
+// preconditioner the diagonal of the boundary-boundary block.
+
+static void cond_free(CondData*& c) {
+  if (!c) return;
+  if (c->bsys) system_free(c->bsys);
+  dfree(c->bmap);
+  dfree(c->iidx);
+  dfree(c->ainv);
+  dfree(c->t);
+  dfree(c->zero);
+  delete c;
+  c = nullptr;
+}
+
+static nk_status cond_check(nk_system y) {
+  nk_space s = y->space;
+  if (y->nsys != 1) return fail(NK_EUNSUPPORTED, "static condensation takes a one-system (not batched) system");
+  if (s->shape != 0 || s->dim != 3 || s->groups.size() != 1)
+    return fail(NK_EUNSUPPORTED, "static condensation is built for uniform-order hexahedral spaces");
+  const Group& G = s->groups[0];
+  if (G.P < kCondMinP || G.P > kCondMaxP || G.Q != G.P + 2)
+    return fail(NK_EUNSUPPORTED, "static condensation is built for 2 <= P <= 6 with Q = P + 2");
+  return NK_OK;
+}
+
+// Build the boundary system and the interior inverses of y (once).
+static nk_status cond_build(nk_system y, hipStream_t st) {
+  if (y->cond) return NK_OK;
+  NK_CHECK(cond_check(y));
+  nk_space s = y->space;
+  const Group& G = s->groups[0];
+  const int P = G.P, n = P + 1, n3 = n * n * n, ni = (P - 1) * (P - 1) * (P - 1);
+  const int64_t E = s->nelem, nloc = E * n3, nu = y->nuser;
+  hipError_t e;
+  // the internal map of a one-system system numbers DOFs as the caller does
+  std::vector<int32_t> m(nloc);
+  if ((e = hipMemcpyAsync(m.data(), y->l2g, nloc * 4, hipMemcpyDeviceToHost, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "condensation setup");
+  std::vector<uint8_t> inner(n3);
+  for (int r = 0; r < n; ++r)
+    for (int hi = 0; hi < n; ++hi)
+      for (int lo = 0; lo < n; ++lo)
+        inner[(r * n + hi) * n + lo] = r > 0 && r < P && hi > 0 && hi < P && lo > 0 && lo < P;
+  std::vector<int32_t> count(nu, 0);
+  std::vector<uint8_t> dir(nu, 0), isb(nu, 0);
+  for (int64_t i = 0; i < nloc; ++i) {
+    const int32_t d = l2g_dof(m[i]);
+    ++count[d];
+    if (m[i] < 0) dir[d] = 1;
+    if (!inner[i % n3]) isb[d] = 1;
+  }
+  for (int64_t i = 0; i < nloc; ++i)
+    if (inner[i % n3] && (m[i] < 0 || count[l2g_dof(m[i])] != 1))
+      return fail(NK_EUNSUPPORTED, "an interior mode's DOF is shared or Dirichlet: the map is not condensable");
+  std::vector<int32_t> cpos(nu, -1), bmap;
+  for (int64_t d = 0; d < nu; ++d)
+    if (isb[d]) {
+      cpos[d] = (int32_t)bmap.size();
+      bmap.push_back((int32_t)d);
+    }
+  const int64_t nb = (int64_t)bmap.size();
+  std::vector<int32_t> l2gc(nloc), iidx(E * (int64_t)ni);
+  std::vector<int8_t> sgn(nloc, 1);
+  std::vector<uint8_t> dirc(nb + 1, 0);
+  for (int64_t c = 0; c < nb; ++c) dirc[c] = dir[bmap[c]];
+  dirc[nb] = 1;
+  for (int64_t el = 0; el < E; ++el) {
+    int k = 0;
+    for (int md = 0; md < n3; ++md) {
+      const int64_t i = el * n3 + md;
+      const int32_t d = l2g_dof(m[i]);
+      if (inner[md]) {
+        l2gc[i] = (int32_t)nb;
+        iidx[el * ni + k++] = d | (l2g_neg(m[i]) ? kL2gNeg : 0);
+      } else {
+        l2gc[i] = cpos[d];
+        sgn[i] = l2g_neg(m[i]) ? -1 : 1;
+      }
+    }
+  }
+  CondData* c = new CondData();
+  auto bail = [&](nk_status stt) {
+    cond_free(c);
+    return stt;
+  };
+  c->nb = nb;
+  int32_t* d_l2g = nullptr;
+  int8_t* d_sgn = nullptr;
+  uint8_t* d_dir = nullptr;
+  if ((e = dmalloc(&d_l2g, nloc)) || (e = dmalloc(&d_sgn, nloc)) || (e = dmalloc(&d_dir, nb + 1)) ||
+      (e = hipMemcpyAsync(d_l2g, l2gc.data(), nloc * 4, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(d_sgn, sgn.data(), nloc, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(d_dir, dirc.data(), nb + 1, hipMemcpyHostToDevice, st))) {
+    dfree(d_l2g);
+    dfree(d_sgn);
+    dfree(d_dir);
+    return bail(hip_fail(e, "condensation setup"));
+  }
+  const int64_t eo[2] = {0, E}, dofo[2] = {0, nb + 1};
+  const nk_status cs = system_create(&c->bsys, s, 1, eo, dofo, d_l2g, d_sgn, d_dir, y->lam, y->lam0,
+                                     st, /*tune=*/false);
+  dfree(d_l2g);
+  dfree(d_sgn);
+  dfree(d_dir);
+  if (cs != NK_OK) return bail(cs);
+  double *cu = nullptr, *yl = nullptr;
+  int* d_bad = nullptr;
+  auto bail_tmp = [&](hipError_t err) {
+    dfree(cu);
+    dfree(yl);
+    dfree(d_bad);
+    return bail(hip_fail(err, "condensation setup"));
+  };
+  if ((e = dmalloc(&c->bmap, std::max<int64_t>(nb, 1))) ||
+      (e = dmalloc(&c->iidx, std::max<int64_t>(E * ni, 1))) ||
+      (e = dmalloc(&c->ainv, std::max<int64_t>(E * ni * (int64_t)ni, 1))) ||
+      (e = dmalloc(&c->t, std::max<int64_t>(E * ni, 1))) ||
+      (e = dmalloc(&c->zero, c->bsys->L.npad)) || (e = dmalloc(&cu, std::max<int64_t>(nloc, 1))) ||
+      (e = dmalloc(&yl, std::max<int64_t>(nloc, 1))) || (e = dmalloc(&d_bad, 1)))
+    return bail_tmp(e);
+  if ((e = hipMemcpyAsync(c->bmap, bmap.data(), nb * 4, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(c->iidx, iidx.data(), E * ni * 4, hipMemcpyHostToDevice, st)) ||
+      (e = vec_fill<double>(c->zero, c->bsys->L.npad, 0.0, st)) ||
+      (e = vec_fill<double>(cu, nloc, 0.0, st)) || (e = vec_fill<int32_t>(d_bad, 1, 0, st)))
+    return bail_tmp(e);
+  // H_ii row by row: the local Helmholtz operator on each interior unit vector
+  OpArgs a;
+  a.op = OP_HELM;
+  a.dim = 3;
+  a.P = P;
+  a.Q = G.Q;
+  a.nelem = E;
+  a.in = cu;
+  a.out = yl;
+  a.fac = s->fac64 + G.f0;
+  a.lam = y->lam;
+  a.lam0 = y->lam0;
+  a.tile = cur_tile(OP_HELM, 3, P, NK_F64);
+  a.stream = st;
+  for (int k = 0; k < ni; ++k) {
+    if ((e = sc_unit(P, E, cu, k, st)) || (e = launch_op(3, NK_F64, a)) ||
+        (e = sc_column(P, E, yl, c->ainv, k, st)))
+      return bail_tmp(e);
+  }
+  if ((e = sc_invert(P, E, c->ainv, d_bad, st))) return bail_tmp(e);
+  int bad = 0;
+  if ((e = hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return bail_tmp(e);
+  dfree(cu);
+  dfree(yl);
+  dfree(d_bad);
+  if (bad) return bail(fail(NK_EINVAL, "an element's interior block is not positive definite"));
+  c->op.P = P;
+  c->op.nelem = E;
+  c->op.ainv = c->ainv;
+  c->op.t = c->t;
+  c->op.fac = s->fac64 + G.f0;
+  c->op.lam = c->bsys->lam;
+  c->op.lam0 = y->lam0;
+  c->op.l2g = c->bsys->l2g;
+  c->bsys->sc = &c->op;
+  y->cond = c;
+  return NK_OK;
+}
+
+nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  if (!nboundary) return fail(NK_EINVAL, "nboundary is NULL");
+  NK_CHECK(check_device());
+  hipStream_t st = (hipStream_t)stream;
+  NK_CHECK(cond_build(sys, st));
+  *nboundary = sys->cond->nb;
+  if (bmap) {
+    NK_CHECK(check_buf(bmap, (size_t)sys->cond->nb * 4, "bmap"));
+    const hipError_t e = hipMemcpyAsync(bmap, sys->cond->bmap, sys->cond->nb * 4,
+                                        hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "nk_system_condense");
+  }
+  return NK_OK;
+}
+
+nk_status nk_condensed_apply(nk_system sys, const double* xb, double* yb, void* stream) {
+  if (!sys) return fail(NK_EINVAL, "system is NULL");
+  if (!sys->cond) return fail(NK_EINVAL, "system has no condensed form (call nk_system_condense)");
+  CondData* c = sys->cond;
+  nk_system z = c->bsys;
+  NK_CHECK(check_buf(xb, (size_t)c->nb * 8, "xb"));
+  NK_CHECK(check_buf(yb, (size_t)c->nb * 8, "yb"));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = z->L.npad;
+  hipError_t e;
+  if ((e = seg_in(c->nb, np, xb, z->dinv64, z->p, st)) || (e = vec_fill<double>(z->y, np, 0.0, st)) ||
+      (e = sys_op(z, NK_F64, z->p, z->y, nullptr, nullptr, st)) ||
+      (e = seg_out(c->nb, z->y, yb, st)) || (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "condensed apply");
+  return NK_OK;
+}
+
+// FP64 solve by static condensation with iterative refinement on the full
+// system: r = b - A x; the boundary system solves for the correction of r
+// (right-hand side g = r_B - sum_e R_e^T H_bi H_ii^{-1} r_i(e)), the interiors
+// follow element by element, x is updated and the full true residual
+// recomputed; passes repeat until it meets rtol (one pass as a rule).
+static nk_status cg_solve_condensed(nk_system y, const double* b, double* x, double rtol, int maxit,
+                                    nk_solve_info* info, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t us = (hipStream_t)stream;
+  hipStream_t cs = y->cs;
+  hipError_t e = hipSuccess;
+  if ((e = hipEventRecord(y->ev, us)) || (e = hipStreamWaitEvent(cs, y->ev, 0)))
+    return hip_fail(e, "stream ordering");
+  NK_CHECK(cond_build(y, cs));
+  CondData* c = y->cond;
+  nk_system z = c->bsys;
+  const int kMaxPasses = 4;
+  int iters = 0, passes = 0;
+  int32_t status = NK_ENOCONV;
+  std::vector<double> bb, rr, gg;
+  do {
+    if ((e = pad_in<double>(1, y->d_dof_off, y->d_pdof_off, y->L, b, y->dinv64, y->b, cs))) break;
+    if ((e = pad_in<double>(1, y->d_dof_off, y->d_pdof_off, y->L, x, y->dinv64, y->x, cs))) break;
+    if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol, nullptr, cs)) ||
+        (e = read_sys(y, y->bb, bb)))
+      break;
+    if ((e = true_residual(y)) || (e = read_sys(y, y->rr_true, rr))) break;
+    while (true) {
+      if (rel_of(rr[0], bb[0]) <= rtol) {
+        status = NK_OK;
+        break;
+      }
+      if (passes == kMaxPasses || iters >= maxit) break;
+      ++passes;
+      // g: the boundary right-hand side of the residual (the boundary
+      // system's work runs on its own stream; y's stream is idle here, as
+      // read_sys synchronised it)
+      hipStream_t zs = z->cs;
+      if ((e = sc_restrict(c->nb, z->L.npad, c->bmap, y->r, z->dinv64, z->b, zs)) ||
+          (e = sc_ainv(c->op, y->r, c->iidx, 0.0, 1.0, -1.0, nullptr, nullptr, zs)) ||
+          (e = sc_pass(c->op, 2, c->zero, z->b, nullptr, nullptr, nullptr, zs)) ||
+          (e = vec_fill<double>(z->x, z->L.npad, 0.0, zs)) ||
+          (e = vec_norm2(z->L, z->b, z->part, z->cnt_aux, z->bb, rtol, nullptr, zs)) ||
+          (e = read_sys(z, z->bb, gg)))
+        break;
+      // the boundary residual that makes the full one meet rtol
+      double rc = gg[0] > 0.0 ? 0.9 * rtol * std::sqrt(bb[0] / gg[0]) : 0.5;
+      rc = std::min(rc, 0.5);
+      std::vector<int> it(1, 0);
+      std::vector<int32_t> st;
+      std::vector<double> rrc;
+      if ((e = solve_f64(z, rc, maxit - iters, it, st, rrc))) break;
+      iters += it[0];
+      if (st[0] == NK_EBREAKDOWN) {
+        status = NK_EBREAKDOWN;
+        break;
+      }
+      // interiors: x_i += H_ii^{-1} (r_i - H_ib dx_B); boundary: x_B += dx_B
+      if ((e = sc_pass(c->op, 1, z->x, nullptr, nullptr, nullptr, nullptr, zs)) ||
+          (e = sc_ainv(c->op, y->r, c->iidx, -1.0, 1.0, 1.0, y->x, nullptr, zs)) ||
+          (e = sc_expand_add(c->nb, c->bmap, z->x, y->x, zs)) || (e = hipStreamSynchronize(zs)))
+        break;
+      if ((e = true_residual(y)) || (e = read_sys(y, y->rr_true, rr))) break;
+    }
+    if (e) break;
+    if ((e = pad_out<double>(1, y->d_dof_off, y->d_pdof_off, y->nuser, y->x, x, cs))) break;
+    if ((e = hipEventRecord(y->ev, cs)) || (e = hipStreamWaitEvent(us, y->ev, 0))) break;
+    e = hipStreamSynchronize(cs);
+  } while (0);
+  if (e != hipSuccess) return hip_fail(e, "condensed solve");
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->iters = iters;
+    info->outer_iters = passes;
+    info->rel_resid = rel_of(rr[0], bb[0]);
+    info->solve_ms = ms;
+    info->status = status;
+  }
+  if (status != NK_OK)
+    return fail((nk_status)status, status == NK_EBREAKDOWN ? "CG breakdown" : "CG did not converge");
+  return NK_OK;
+}
+
 nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* x, double rtol,
                       int maxit, nk_solve_info* info, void* stream) {
   if (!y) return fail(NK_EINVAL, "system is NULL");
   NK_CHECK(check_solve_args(mode, rtol, maxit));
   NK_CHECK(check_buf(b, y->nuser * 8, "b"));
   NK_CHECK(check_buf(x, y->nuser * 8, "x"));
+  if (mode == NK_SOLVE_CONDENSED) return cg_solve_condensed(y, b, x, rtol, maxit, info, stream);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t us = (hipStream_t)stream;
   hipStream_t cs = y->cs;
@@ -1999,6 +2303,8 @@ nk_status nk_cg_solve_batched(nk_system* sys, int nsys, nk_solve_mode mode, cons
   if (!sys || !b || !x) return fail(NK_EINVAL, "sys, b and x must be non-NULL");
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
   NK_CHECK(check_solve_args(mode, rtol, maxit));
+  if (mode == NK_SOLVE_CONDENSED)
+    return fail(NK_EUNSUPPORTED, "NK_SOLVE_CONDENSED solves one system per nk_cg_solve call");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -579,6 +579,21 @@ __device__ __forceinline__ void plain_helm_row(const Tab<T, N, Q>& tb, T lam, co
   }
 }
 
+// Interior modes of the statically condensed operator: a slot thread t holds
+// the modes (r, t / N, t % N), r = 0..N-1, and the element's (N-2)^3 interior
+// modes (every index in 1..N-2) are numbered with r slowest, then t / N, then
+// t % N (increasing local mode index).
+template <int N>
+__device__ __forceinline__ bool sc_inner(int t) {
+  const int hi = t / N, lo = t - hi * N;
+  return hi >= 1 && hi <= N - 2 && lo >= 1 && lo <= N - 2;
+}
+template <int N>
+__device__ __forceinline__ int sc_k(int t) {
+  const int hi = t / N, lo = t - hi * N;
+  return (hi - 1) * (N - 2) + (lo - 1);
+}
+
 // Helmholtz of one element per slot.  The I stage, the pointwise geometric
 // factors with the lambda mass term and the transposed I stage run as one
 // loop over the point index i; PF register sets hold the factors of points
@@ -586,7 +601,13 @@ __device__ __forceinline__ void plain_helm_row(const Tab<T, N, Q>& tb, T lam, co
 // i is processed (PF = 1: none, fewest registers).  Local store or (ASM)
 // atomic scatter-add into the global vector with the element's
 // p_e . (H_e p_e).
-template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true>
+// SC selects a pass of the statically condensed operator (assembled maps
+// whose interior modes are Dirichlet entries, so their gathered values are
+// 0 and their scatter is skipped): 1 stores the element's interior outputs
+// into out2[e][k] and scatters nothing; 2 takes the interior inputs from
+// in2[e][k], scatters the boundary outputs and sums the energy over the free
+// boundary modes only.
+template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true, int SC = 0>
 __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
                                            const DevArgs<T>& a) {
@@ -609,6 +630,15 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
     if constexpr (ASM) {
 #pragma unroll
       for (int r = 0; r < N; ++r) xin[r] = l2g_value(gidx[r], xin[r]);
+    }
+    if constexpr (SC == 2) {
+      static_assert(ASM && N >= 3, "condensed pass");
+      constexpr int NI2 = (N - 2) * (N - 2);
+      if (sc_inner<N>(t)) {
+        const double* ti = a.in2 + ee * (int64_t)(NI2 * (N - 2)) + sc_k<N>(t);
+#pragma unroll
+        for (int r = 1; r < N - 1; ++r) xin[r] = (T)ti[(r - 1) * NI2];
+      }
     }
   }
   stage_k<T, N, Q, true>(tb, sm, t, live, xin);
@@ -673,13 +703,21 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
   slot_sync<NT>();
   T yv[N];
   stage_kt<T, N, Q, true>(tb, sm, t, live, yv);
-  if constexpr (ASM) {
+  if constexpr (SC == 1) {
+    static_assert(ASM && N >= 3, "condensed pass");
+    constexpr int NI2 = (N - 2) * (N - 2);
+    if (pq && sc_inner<N>(t)) {
+      double* to = a.out2 + ee * (int64_t)(NI2 * (N - 2)) + sc_k<N>(t);
+#pragma unroll
+      for (int r = 1; r < N - 1; ++r) to[(r - 1) * NI2] = (double)yv[r];
+    }
+  } else if constexpr (ASM) {
     double dp = 0.0;
     if (pq) {
 #pragma unroll
       for (int r = 0; r < N; ++r) {
         if (gidx[r] >= 0) atomic_add(a.out + l2g_dof(gidx[r]), l2g_sign(gidx[r], yv[r]));
-        dp += (double)xin[r] * (double)yv[r];
+        if (SC != 2 || gidx[r] >= 0) dp += (double)xin[r] * (double)yv[r];
       }
     }
     const double s = slot_sum<NT>(dp, red, slot, t);

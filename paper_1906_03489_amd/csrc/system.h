@@ -102,6 +102,48 @@ hipError_t launch_diag(int dim, int P, int Q, int64_t nelem, const double* Bt, c
                        const double* fac, const double* lam, double lam0, const int32_t* l2g,
                        double* diag, hipStream_t s);
 
+// Statically condensed operator of a hexahedral system (condense.hip).
+constexpr int kCondMinP = 2;
+constexpr int kCondMaxP = 6;
+struct CondOp {
+  int P = 0;
+  int64_t nelem = 0;
+  const double* ainv = nullptr;   // [E][NI][NI] interior inverses, NI = (P-1)^3
+  double* t = nullptr;            // [E][NI] interior values between the passes
+  const double* fac = nullptr;    // FP64 geometric factors
+  const double* lam = nullptr;
+  double lam0 = 0.0;
+  const int32_t* l2g = nullptr;   // internal map of the boundary system
+};
+// pass 1: t = interior part of H [x_b; 0]; pass 2: y += boundary part of
+// H [x_b; t], element energies into dots
+hipError_t sc_pass(const CondOp& c, int pass, const double* x, double* y, double* dots,
+                   const int32_t* dslot, const int32_t* seg_done, hipStream_t s);
+// z = gamma H_ii^{-1} (alpha t + beta b_i) into t, or added into xadd at the
+// interior DOFs (iidx: DOF | sign bit per interior mode)
+hipError_t sc_ainv(const CondOp& c, const double* b, const int32_t* iidx, double alpha, double beta,
+                   double gamma, double* xadd, const int32_t* seg_done, hipStream_t s);
+hipError_t sc_unit(int P, int64_t nelem, double* c, int k, hipStream_t s);
+hipError_t sc_column(int P, int64_t nelem, const double* y, double* A, int k, hipStream_t s);
+hipError_t sc_invert(int P, int64_t nelem, double* A, int* bad, hipStream_t s);
+hipError_t sc_restrict(int64_t nb, int64_t npad, const int32_t* bmap, const double* full,
+                       const double* dinv_c, double* cond, hipStream_t s);
+hipError_t sc_expand_add(int64_t nb, const int32_t* bmap, const double* cond, double* full,
+                         hipStream_t s);
+
+// What a system keeps of its condensed form: the boundary system and the
+// arrays that connect it to the full one.
+struct CondData {
+  nk_system bsys = nullptr;       // boundary system (its operator is op)
+  CondOp op;
+  int64_t nb = 0;                 // boundary DOFs (the boundary system has nb + 1: a dummy)
+  int32_t* bmap = nullptr;        // [nb] full DOF of each boundary DOF
+  int32_t* iidx = nullptr;        // [E][NI] full DOF | sign bit of each interior mode
+  double* ainv = nullptr;
+  double* t = nullptr;
+  double* zero = nullptr;         // boundary-length zeros
+};
+
 }  // namespace nk
 
 struct nk_system_s {
@@ -149,4 +191,6 @@ struct nk_system_s {
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
   int g64_iters = 0, g32_iters = 0;
   std::vector<int> tiles64, tiles32;   // assembled-operator tile per order group
+  nk::CondData* cond = nullptr;           // statically condensed form (built on first use)
+  const nk::CondOp* sc = nullptr;         // set on a boundary system: its operator is condensed
 };

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnk.so")
 
 NK_OK, NK_EINVAL, NK_ENOMEM, NK_EDEVICE, NK_EHIP, NK_ENOCONV, NK_EBREAKDOWN, NK_EUNSUPPORTED = range(8)
 F64, F32 = 0, 1
-SOLVE_F64, SOLVE_F32_REFINED = 0, 1
+SOLVE_F64, SOLVE_F32_REFINED, SOLVE_CONDENSED = 0, 1, 2
 OP_BWD, OP_IPROD, OP_HELM, OP_HELM_ASM = 0, 1, 2, 3
 STATUS_NAMES = {0: "NK_OK", 1: "NK_EINVAL", 2: "NK_ENOMEM", 3: "NK_EDEVICE", 4: "NK_EHIP",
                 5: "NK_ENOCONV", 6: "NK_EBREAKDOWN", 7: "NK_EUNSUPPORTED"}
@@ -35,7 +35,7 @@ EXPORTS = [
     "nk_tile_config", "nk_tile_count", "nk_set_tile_config", "nk_space_set_strategy",
     "nk_space_get_strategy", "nk_phys_deriv", "nk_iprod_wrt_deriv_base", "nk_fwd_trans",
     "nk_tri_points", "nk_space_create_tri", "nk_tet_points", "nk_space_create_tet",
-    "nk_space_create_prism", "nk_space_create_pyr",
+    "nk_space_create_prism", "nk_space_create_pyr", "nk_system_condense", "nk_condensed_apply",
 ]
 
 
@@ -108,6 +108,8 @@ def lib():
         "nk_space_create_tet": (i32, [pp, i64, i32, i32, vp, vp, vp]),
         "nk_space_create_prism": (i32, [pp, i64, i32, i32, vp, vp, vp]),
         "nk_space_create_pyr": (i32, [pp, i64, i32, i32, vp, vp, vp]),
+        "nk_system_condense": (i32, [vp, ctypes.POINTER(i64), vp, vp]),
+        "nk_condensed_apply": (i32, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -504,6 +506,27 @@ class System:
         if raise_on_fail:
             _check(st)
         return x, [i.as_dict() for i in infos]
+
+    def condense(self, with_map: bool = True):
+        """nk_system_condense: builds the statically condensed boundary system
+        (once); returns (nboundary, bmap int32 device tensor or None)."""
+        import torch
+        nb = ctypes.c_int64(0)
+        _check(lib().nk_system_condense(self.handle, ctypes.byref(nb), None, _stream()))
+        if not with_map:
+            return nb.value, None
+        bmap = torch.empty(max(nb.value, 1), dtype=torch.int32, device="cuda")
+        _check(lib().nk_system_condense(self.handle, ctypes.byref(nb), _ptr(bmap, torch.int32, "bmap"),
+                                        _stream()))
+        return nb.value, bmap[:nb.value]
+
+    def condensed_apply(self, xb, yb=None):
+        """nk_condensed_apply: yb = S xb over the boundary numbering."""
+        import torch
+        yb = _out(yb, xb.numel(), torch.float64, xb.device)
+        _check(lib().nk_condensed_apply(self.handle, _ptr(xb, torch.float64, "xb"),
+                                        _ptr(yb, torch.float64, "yb"), _stream()))
+        return yb
 
     def destroy(self):
         if self.handle:

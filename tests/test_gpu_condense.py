@@ -1,0 +1,179 @@
+"""GPU parity of static condensation (section 2.1): the boundary numbering,
+the condensed operator S x_B against the oracle's assembled elemental Schur
+complements (FP64 <= 1e-12: the interior blocks have condition numbers below
+40 up to P = 6, so the dense inverse adds no more than the assembled
+operator's rounding), the condensed solve against the oracle's direct solve
+(true residual <= rtol recomputed by the oracle), fewer CG iterations than
+the full system, and the error paths."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.assembly import MaskedOperator, direct_solve
+from oracle.condense import Condensed
+from gpu_common import (FP64_RTOL, assert_close, assert_true_residual, jacobians, lib_points, nk,
+                        rel_err, to_dev, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(shape, P, signed=False, lam_seed=None):
+    Q = P + 2
+    Jg, Jo, lat = jacobians(shape, P, W.WARP_AMPLITUDE)
+    E = lat.nelem
+    lam = None if lam_seed is None else np.random.default_rng(lam_seed).uniform(0.5, 2.0, E)
+    ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0 if lam is None else lam)
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    sign = W.dof_signs(W.seed(0, 70) + P, l2g, ng) if signed else None
+    m = nk()
+    space = m.Space.create(3, P, Q, to_dev(Jg))
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm),
+                           lam=to_dev(lam) if lam is not None else None, lam0=1.0,
+                           sign=to_dev(sign) if signed else None)
+    mats = oracle.helmholtz_matrices(ops)
+    return dict(P=P, l2g=l2g, ng=ng, dm=dm, sign=sign, mats=mats, space=space, sysm=sysm, ops=ops)
+
+
+@pytest.mark.parametrize("P,shape,signed,lam", [(2, (3, 2, 2), False, None), (3, (3, 2, 2), True, 4),
+                                                (4, (2, 3, 2), False, 5), (5, (2, 2, 2), True, None),
+                                                (6, (2, 2, 2), False, 6)])
+def test_condensed_operator_matches_oracle(P, shape, signed, lam):
+    torch = torch_cuda()
+    c = _case(shape, P, signed, lam)
+    ref = Condensed(c["mats"], c["l2g"], c["ng"], c["dm"], 3, P, c["sign"])
+    nb, bmap = c["sysm"].condense()
+    assert nb == ref.bdofs.size
+    np.testing.assert_array_equal(bmap.cpu().numpy(), ref.bdofs)
+    # a second call reuses the built form
+    assert c["sysm"].condense(with_map=False)[0] == nb
+    for k in range(2):
+        xb = W.uniform(W.seed(0, 71) + 10 * P + k, nb)
+        y = c["sysm"].condensed_apply(to_dev(xb)).cpu().numpy()
+        assert_close(y, ref.apply(xb), FP64_RTOL, f"condensed apply P={P} call {k}")
+    del torch
+
+
+@pytest.mark.parametrize("P,shape,signed", [(2, (3, 3, 2), False), (4, (3, 2, 2), True),
+                                            (6, (2, 2, 2), False)])
+def test_condensed_solve_matches_direct_solve(P, shape, signed):
+    """NK_SOLVE_CONDENSED to 1e-12: the oracle's residual of the returned x,
+    and x against the oracle's sparse direct solve (error <= cond(A) rtol)."""
+    torch_cuda()
+    m = nk()
+    c = _case(shape, P, signed, lam_seed=7)
+    b = W.uniform(W.seed(0, 72) + P, c["ng"])
+    b[c["dm"].astype(bool)] = 0.0
+    x, info = c["sysm"].solve(to_dev(b), rtol=1e-12, maxit=20000, mode=m.SOLVE_CONDENSED)
+    xs = x.cpu().numpy()
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"], c["sign"])
+    assert_true_residual(info[0], 1e-12, A, c["mats"], c["l2g"], c["ng"], c["dm"], xs, b, f"P={P}")
+    assert info[0]["outer_iters"] >= 1 and info[0]["iters"] >= 1
+    xref = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b, c["sign"])
+    assert rel_err(xs, xref) < 1e-8
+    # the condensed oracle agrees with the direct one (same x)
+    xo = oracle.condensed_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b, 3, P, c["sign"])
+    assert rel_err(xs, xo) < 1e-8
+
+
+def test_condensed_solve_takes_fewer_iterations():
+    """On a 4^3 curved lattice at P = 4 the boundary system needs fewer
+    Jacobi-PCG iterations than the full one to the same full residual."""
+    torch_cuda()
+    m = nk()
+    c = _case((4, 4, 4), 4)
+    b = W.uniform(W.seed(0, 73), c["ng"])
+    b[c["dm"].astype(bool)] = 0.0
+    xf, inf_f = c["sysm"].solve(to_dev(b), rtol=1e-10, maxit=20000)
+    xc, inf_c = c["sysm"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_CONDENSED)
+    assert inf_c[0]["status"] == 0 and inf_c[0]["rel_resid"] <= 1e-10
+    assert inf_c[0]["iters"] < inf_f[0]["iters"], (inf_c[0]["iters"], inf_f[0]["iters"])
+    assert rel_err(xc.cpu().numpy(), xf.cpu().numpy()) < 1e-6
+
+
+def test_condensed_solve_initial_guess_and_zero_rhs():
+    """An exact initial guess returns at once (no boundary solve); a zero
+    right-hand side gives x = 0."""
+    torch = torch_cuda()
+    m = nk()
+    c = _case((3, 2, 2), 3)
+    b = W.uniform(W.seed(0, 74), c["ng"])
+    b[c["dm"].astype(bool)] = 0.0
+    x, info = c["sysm"].solve(to_dev(b), rtol=1e-12, maxit=20000, mode=m.SOLVE_CONDENSED)
+    x2, info2 = c["sysm"].solve(to_dev(b), x=x.clone(), rtol=1e-10, maxit=20000, mode=m.SOLVE_CONDENSED)
+    assert info2[0]["status"] == 0 and info2[0]["iters"] == 0 and info2[0]["outer_iters"] == 0
+    z = torch.zeros(c["ng"], dtype=torch.float64, device="cuda")
+    x0, info0 = c["sysm"].solve(z, rtol=1e-10, maxit=100, mode=m.SOLVE_CONDENSED)
+    assert info0[0]["status"] == 0 and float(x0.abs().max()) == 0.0
+
+
+def test_condensed_error_paths():
+    torch = torch_cuda()
+    m = nk()
+    # P = 1: no interior modes
+    c1 = _case((2, 2, 2), 1)
+    with pytest.raises(m.NkError) as ei:
+        c1["sysm"].condense()
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    # condensed apply before the condensed form exists
+    c = _case((2, 2, 1), 2)
+    with pytest.raises(m.NkError) as ei:
+        c["sysm"].condensed_apply(torch.zeros(8, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == m.NK_EINVAL
+    # an interior mode sharing its DOF with another element
+    l2g = c["l2g"].copy()
+    inner = np.flatnonzero(oracle.interior_modes(3, 2))[0]
+    l2g[1, inner] = l2g[0, inner]
+    bad = m.System.create(c["space"], c["ng"], to_dev(l2g), to_dev(c["dm"]), lam0=1.0)
+    with pytest.raises(m.NkError) as ei:
+        bad.condense()
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    # the batched solve does not take the condensed mode
+    b = torch.zeros(c["ng"], dtype=torch.float64, device="cuda")
+    with pytest.raises(m.NkError) as ei:
+        m.solve_batched([c["sysm"]], [b], mode=m.SOLVE_CONDENSED)
+    assert ei.value.status == m.NK_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("P", [4, 6])
+def test_full_size_24c_condensed_solve_sampled_residuals(P):
+    """The 24^3 curved-hex problem of the benchmark solved by condensation to
+    1e-10: the library's true residual, the oracle's residual rows at a
+    seeded sample of free DOFs (lattice vertices shared by eight elements,
+    and random DOFs, interior ones included) each <= 1e-10 ||b||_2, and
+    agreement with the full FP64 CG solution."""
+    m = nk()
+    torch_cuda()
+    shape, Q = (24, 24, 24), P + 2
+    lat = W.lattice(shape)
+    space = m.Space.create(3, P, Q, to_dev(W.element_jacobians(lib_points(P, Q), lat, W.WARP_AMPLITUDE)))
+    l2g, ng, dm = W.lattice_l2g(shape, P)
+    sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm), lam0=1.0)
+    fixed = dm.astype(bool)
+    b = W.uniform(W.seed(2, 1) + P, ng)
+    b[fixed] = 0.0
+    xc, info = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000, mode=m.SOLVE_CONDENSED)
+    assert info[0]["status"] == 0 and info[0]["rel_resid"] <= 1e-10
+    xf, infof = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000)
+    assert info[0]["iters"] < infof[0]["iters"]
+    xs = xc.cpu().numpy().copy()
+    xs[fixed] = 0.0
+    assert rel_err(xs, xf.cpu().numpy()) < 1e-5
+    G = [s * P + 1 for s in shape]
+    free = np.flatnonzero(~fixed)
+    gx, gy, gz = free % G[0], (free // G[0]) % G[1], free // (G[0] * G[1])
+    verts = free[(gx % P == 0) & (gy % P == 0) & (gz % P == 0)]
+    inner = free[(gx % P != 0) & (gy % P != 0) & (gz % P != 0)]
+    rng = np.random.default_rng(50 + P)
+    sample = np.unique(np.concatenate([rng.choice(verts, 4, replace=False), rng.choice(inner, 4, replace=False),
+                                       rng.choice(free, 6, replace=False)]))
+    hits = {int(g): np.argwhere(l2g == g) for g in sample}
+    elems = np.unique(np.concatenate([h[:, 0] for h in hits.values()]))
+    pos = {int(e): k for k, e in enumerate(elems)}
+    Jo = W.element_jacobians(oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[elems]), W.WARP_AMPLITUDE)
+    ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0)
+    y = ops.helmholtz_action(xs[l2g[elems]])
+    bn = np.linalg.norm(b)
+    for g, h in hits.items():
+        Ag = sum(y[pos[int(e)], mm] for e, mm in h)
+        assert abs(b[g] - Ag) <= 1e-10 * bn, (g, abs(b[g] - Ag) / bn)
