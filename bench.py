@@ -404,6 +404,51 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
     return out
 
 
+def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
+    """Static condensation (section 2.1) against the full FP64 PCG on the 24^3
+    problem: setup of the boundary system and interior inverses, boundary CG
+    iterations, time per iteration and per solve."""
+    out = {}
+    for P in orders:
+        space, sysm, b, ng, lat = build_cg_problem(nk, W, torch, shape, P, W.WARP_AMPLITUDE)
+        sysm.solve(b, rtol=1e-2, maxit=64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nb, _ = sysm.condense(with_map=False)
+        setup_ms = (time.perf_counter() - t) * 1e3
+        sysm.solve(b, rtol=1e-2, maxit=64, mode=nk.SOLVE_CONDENSED)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xf, inf_f = sysm.solve(b, rtol=1e-10, maxit=50000)
+        tf = (time.perf_counter() - t) * 1e3
+        t = time.perf_counter()
+        xc, inf_c = sysm.solve(b, rtol=1e-10, maxit=50000, mode=nk.SOLVE_CONDENSED)
+        tc = (time.perf_counter() - t) * 1e3
+        nel, n3, q3, ni = lat.nelem, (P + 1) ** 3, (P + 2) ** 3, (P - 1) ** 3
+        # algorithmic bytes of one boundary iteration: two Helmholtz passes
+        # (factors and map each), the interior inverses, the interior values
+        # between the passes (written, read, written, read), 9 boundary vectors
+        it_bytes = nel * (2 * (8 * 7 * q3 + 4 * n3) + 8 * ni * ni + 4 * 8 * ni) + 8 * 9 * nb
+        ms_it = tc / max(inf_c[0]["iters"], 1)
+        gbs = it_bytes / (ms_it * 1e-3) / 1e9
+        out[f"P{P}"] = {
+            "nglobal": ng, "nboundary": nb, "nelem": nel, "setup_ms": round(setup_ms, 1),
+            "full_f64": {"ms": round(tf, 2), "iters": inf_f[0]["iters"],
+                         "ms_per_iter": round(tf / max(inf_f[0]["iters"], 1), 4)},
+            "condensed": {"ms": round(tc, 2), "iters": inf_c[0]["iters"], "passes": inf_c[0]["outer_iters"],
+                          "rel_resid": inf_c[0]["rel_resid"], "ms_per_iter": round(ms_it, 4),
+                          "GB_s_per_iter": round(gbs, 1), "hbm_frac_per_iter": round(gbs / HBM_PEAK_GBS, 4)},
+            "speedup_condensed_vs_full": round(tf / tc, 3),
+            "rel_diff": float(torch.linalg.norm(xc - xf) / torch.linalg.norm(xf)),
+        }
+        log(f"condensed P={P}: setup {setup_ms:.1f} ms, full {tf:.1f} ms ({inf_f[0]['iters']} it), "
+            f"condensed {tc:.1f} ms ({inf_c[0]['iters']} it, {inf_c[0]['outer_iters']} passes, "
+            f"{ms_it * 1e3:.1f} us/it)")
+        del space, sysm, b, xf, xc
+        torch.cuda.empty_cache()
+    return out
+
+
 def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30, shape="tet"):
     """Collapsed-coordinate tetrahedra (the unit cube split into n^3 cubes of
     six curved tetrahedra each), prisms (the triangle mesh of the unit
@@ -1090,6 +1135,9 @@ def main():
         torch.cuda.empty_cache()
         log("section cg (filter equation) ...")
         sections["filter_24c_P6"] = section_filter(nk, W, torch)
+        torch.cuda.empty_cache()
+        log("section cg (static condensation) ...")
+        sections["condensed_24c"] = section_condensed(nk, W, torch)
         torch.cuda.empty_cache()
     if "batch" in secs:
         log("section batch (mixed order) ...")
