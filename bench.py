@@ -425,10 +425,11 @@ def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
         xc, inf_c = sysm.solve(b, rtol=1e-10, maxit=50000, mode=nk.SOLVE_CONDENSED)
         tc = (time.perf_counter() - t) * 1e3
         nel, n3, q3, ni = lat.nelem, (P + 1) ** 3, (P + 2) ** 3, (P - 1) ** 3
-        # algorithmic bytes of one boundary iteration: two Helmholtz passes
-        # (factors and map each), the interior inverses, the interior values
-        # between the passes (written, read, written, read), 9 boundary vectors
-        it_bytes = nel * (2 * (8 * 7 * q3 + 4 * n3) + 8 * ni * ni + 4 * 8 * ni) + 8 * 9 * nb
+        # algorithmic bytes of one boundary iteration: one read of the factors
+        # and the map (the fused kernel's second pass re-reads them from
+        # cache), the interior inverses in their diagonal storage, 9 boundary
+        # vectors
+        it_bytes = nel * (8 * 7 * q3 + 4 * n3 + 8 * (ni // 2 + 1) * ni) + 8 * 9 * nb
         ms_it = tc / max(inf_c[0]["iters"], 1)
         gbs = it_bytes / (ms_it * 1e-3) / 1e9
         out[f"P{P}"] = {

@@ -363,7 +363,7 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
  * each reducing its residual by NK_INNER_TOL, default 1e-4.)
  * NK_SOLVE_CONDENSED (section 2.1, static condensation): FP64 CG on the
  * system condensed onto the elemental boundary DOFs (nk_system_condense,
- * built on first use), preconditioned by the diagonal of its boundary block;
+ * built on first use), preconditioned by the diagonal of S;
  * the interiors follow element by element, and the pass repeats on the full
  * residual b - A x until it meets rtol (iters: boundary CG iterations summed
  * over passes).  One-system hexahedral systems with 2 <= P <= 6 only
@@ -381,14 +381,18 @@ nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double
  * the system condenses onto the boundary DOFs with the elemental Schur
  * complements S_e = H_bb - H_bi H_ii^{-1} H_ib.  Builds (once per system;
  * later calls reuse it) the boundary system and the dense inverses H_ii^{-1}
- * of every element (E (P-1)^6 doubles of device memory), and returns the
+ * of every element (symmetric, stored by diagonals: E (NI/2 + 1) NI doubles
+ * of device memory, NI = (P-1)^3), and returns the
  * number of boundary DOFs in *nboundary (host).  bmap (device int32
  * [nboundary], may be NULL) receives the global DOF of each boundary DOF, in
- * increasing order.  Requires a one-system system on a uniform-order
+ * increasing order; bdiag (device FP64 [nboundary], may be NULL) the
+ * diagonal of S that preconditions the condensed solve (1 on Dirichlet
+ * DOFs).  Requires a one-system system on a uniform-order
  * hexahedral space, 2 <= P <= 6, Q = P + 2 (else NK_EUNSUPPORTED), and a map
  * whose interior modes each reference a DOF no other mode references and that
  * is not Dirichlet (else NK_EUNSUPPORTED).  Synchronises the stream. */
-nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, void* stream);
+nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, double* bdiag,
+                             void* stream);
 
 /* yb = S xb, the assembled condensed operator over the boundary numbering of
  * nk_system_condense (Dirichlet entries of xb read as zero, Dirichlet entries

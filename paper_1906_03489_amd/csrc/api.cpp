@@ -1127,12 +1127,8 @@ static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, vo
   nk_space s = y->space;
   if (y->sc) {   // boundary system of a static condensation (FP64, one hexahedral group)
     if (t != NK_F64 || g != 0) return hipErrorInvalidValue;
-    const int32_t* ds = dots ? y->dslot : nullptr;
-    hipError_t e;
-    if ((e = sc_pass(*y->sc, 1, (const double*)x, nullptr, nullptr, nullptr, seg_done, st)) ||
-        (e = sc_ainv(*y->sc, nullptr, nullptr, 1.0, 0.0, -1.0, nullptr, seg_done, st)))
-      return e;
-    return sc_pass(*y->sc, 2, (const double*)x, (double*)out, dots, ds, seg_done, st);
+    return sc_apply(*y->sc, (const double*)x, (double*)out, dots, dots ? y->dslot : nullptr,
+                    seg_done, st);
   }
   const Group& G = s->groups[g];
   OpArgs a;
@@ -1778,8 +1774,8 @@ static void fill_info(nk_solve_info* info, const SolveOut& o, int i, nk_solve_mo
 // boundary DOFs.  The boundary system is an ordinary assembled system over
 // the boundary DOFs plus one dummy Dirichlet DOF that every interior mode
 // maps to (so the assembled kernels gather 0 there and scatter nothing); its
-// operator is the three-launch condensed one of condense.hip, its Jacobi
-// preconditioner the diagonal of the boundary-boundary block.
+// operator is the fused condensed one of condense.hip, its Jacobi
+// preconditioner the diagonal of S.
 
 static void cond_free(CondData*& c) {
   if (!c) return;
@@ -1885,17 +1881,19 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   dfree(d_sgn);
   dfree(d_dir);
   if (cs != NK_OK) return bail(cs);
-  double *cu = nullptr, *yl = nullptr;
+  double *cu = nullptr, *yl = nullptr, *afull = nullptr;
   int* d_bad = nullptr;
   auto bail_tmp = [&](hipError_t err) {
     dfree(cu);
     dfree(yl);
+    dfree(afull);
     dfree(d_bad);
     return bail(hip_fail(err, "condensation setup"));
   };
   if ((e = dmalloc(&c->bmap, std::max<int64_t>(nb, 1))) ||
       (e = dmalloc(&c->iidx, std::max<int64_t>(E * ni, 1))) ||
-      (e = dmalloc(&c->ainv, std::max<int64_t>(E * ni * (int64_t)ni, 1))) ||
+      (e = dmalloc(&afull, std::max<int64_t>(E * ni * (int64_t)ni, 1))) ||
+      (e = dmalloc(&c->ainv, std::max<int64_t>(E * sc_packed(ni), 1))) ||
       (e = dmalloc(&c->t, std::max<int64_t>(E * ni, 1))) ||
       (e = dmalloc(&c->zero, c->bsys->L.npad)) || (e = dmalloc(&cu, std::max<int64_t>(nloc, 1))) ||
       (e = dmalloc(&yl, std::max<int64_t>(nloc, 1))) || (e = dmalloc(&d_bad, 1)))
@@ -1921,18 +1919,22 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   a.stream = st;
   for (int k = 0; k < ni; ++k) {
     if ((e = sc_unit(P, E, cu, k, st)) || (e = launch_op(3, NK_F64, a)) ||
-        (e = sc_column(P, E, yl, c->ainv, k, st)))
+        (e = sc_column(P, E, yl, afull, k, st)))
       return bail_tmp(e);
   }
-  if ((e = sc_invert(P, E, c->ainv, d_bad, st))) return bail_tmp(e);
+  if ((e = sc_invert(P, E, afull, d_bad, st)) || (e = sc_pack(P, E, afull, c->ainv, st)))
+    return bail_tmp(e);
   int bad = 0;
   if ((e = hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, st)) ||
       (e = hipStreamSynchronize(st)))
     return bail_tmp(e);
-  dfree(cu);
-  dfree(yl);
-  dfree(d_bad);
-  if (bad) return bail(fail(NK_EINVAL, "an element's interior block is not positive definite"));
+  dfree(afull);
+  if (bad) {
+    dfree(cu);
+    dfree(yl);
+    dfree(d_bad);
+    return bail(fail(NK_EINVAL, "an element's interior block is not positive definite"));
+  }
   c->op.P = P;
   c->op.nelem = E;
   c->op.ainv = c->ainv;
@@ -1941,12 +1943,77 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   c->op.lam = c->bsys->lam;
   c->op.lam0 = y->lam0;
   c->op.l2g = c->bsys->l2g;
+  // Jacobi preconditioner of the boundary system: diag(S) = sum_e diag(S_e),
+  // each elemental diagonal probed by the local condensed operator on the
+  // boundary unit vectors (all elements at once), replacing the diagonal of
+  // the boundary block that the system was created with
+  {
+    nk_system z = c->bsys;
+    const int64_t npc = z->L.npad;
+    double* dS = c->t;   // borrowed when large enough, else a temporary
+    double* dS_own = nullptr;
+    if (E * (int64_t)ni < npc) {
+      if ((e = dmalloc(&dS_own, npc))) return bail_tmp(e);
+      dS = dS_own;
+    }
+    int prev = -1;
+    e = vec_fill<double>(cu, nloc, 0.0, st);
+    if (e == hipSuccess) e = vec_fill<double>(dS, npc, 0.0, st);
+    for (int md = 0; md < n3 && e == hipSuccess; ++md) {
+      if (inner[md]) continue;
+      if ((e = sc_unit_mode(P, E, cu, md, prev, st)) || (e = sc_local(c->op, cu, yl, st)) ||
+          (e = sc_diag_add(P, E, yl, md, z->l2g, dS, st)))
+        break;
+      prev = md;
+    }
+    if (e == hipSuccess) e = sc_dinv(npc, dS, z->dinv64, z->dinv32, z->diag, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(dS_own);
+    if (e != hipSuccess) return bail_tmp(e);
+  }
+  dfree(cu);
+  dfree(yl);
+  dfree(d_bad);
   c->bsys->sc = &c->op;
+  // the faster of the two fused-kernel variants on this system
+  {
+    nk_system z = c->bsys;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best = 0.f;
+    int pick = 0;
+    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+      if (e0) (void)hipEventDestroy(e0);
+      return bail(hip_fail(e, "hipEventCreate"));
+    }
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+      c->op.variant = v;
+      e = sc_apply(c->op, c->zero, z->y, nullptr, nullptr, nullptr, st);   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < 5 && e == hipSuccess; ++r)
+        e = sc_apply(c->op, c->zero, z->y, nullptr, nullptr, nullptr, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (v == 0 || ms < best)) {
+        best = ms;
+        pick = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->op.variant = pick;
+    // the timing runs accumulated into the boundary system's output vector
+    if (e == hipSuccess) e = vec_fill<double>(z->y, z->L.npad, 0.0, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(hip_fail(e, "condensation setup"));
+  }
   y->cond = c;
   return NK_OK;
 }
 
-nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, void* stream) {
+nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, double* bdiag,
+                             void* stream) {
   if (!sys) return fail(NK_EINVAL, "system is NULL");
   if (!nboundary) return fail(NK_EINVAL, "nboundary is NULL");
   NK_CHECK(check_device());
@@ -1957,6 +2024,16 @@ nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, v
     NK_CHECK(check_buf(bmap, (size_t)sys->cond->nb * 4, "bmap"));
     const hipError_t e = hipMemcpyAsync(bmap, sys->cond->bmap, sys->cond->nb * 4,
                                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "nk_system_condense");
+  }
+  if (bdiag) {
+    NK_CHECK(check_buf(bdiag, (size_t)sys->cond->nb * 8, "bdiag"));
+    const hipError_t e = hipMemcpyAsync(bdiag, sys->cond->bsys->diag, sys->cond->nb * 8,
+                                        hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "nk_system_condense");
+  }
+  if (bmap || bdiag) {
+    const hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "nk_system_condense");
   }
   return NK_OK;

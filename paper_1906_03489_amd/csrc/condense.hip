@@ -4,7 +4,9 @@
 // neighbours, and interior bubbles owned by the element alone).
 //
 // The condensed operator S = sum_e R_e^T (H_bb - H_bi H_ii^{-1} H_ib) R_e is
-// applied matrix-free in three launches:
+// applied matrix-free, per element (one fused launch; the three steps are
+// also separate launches, used for the right-hand side and the interior
+// recovery):
 //   pass 1  gather the boundary values (interior modes are Dirichlet entries
 //           of the condensed map, so they read 0), sum-factorised Helmholtz,
 //           store the interior outputs (H_ib x_b) per element;
@@ -26,6 +28,43 @@ namespace nk {
 constexpr int sc_ni(int P) { return (P - 1) * (P - 1) * (P - 1); }
 constexpr int sc_threads(int ni) { return ni <= 64 ? 64 : (ni + 63) / 64 * 64; }
 
+// The symmetric interior inverse A of an element is stored by diagonals:
+// D[s][k] = A[k][(k + s) mod NI] for s = 0 .. NI/2, (NI/2 + 1) NI values,
+// about half of NI^2.  Row k of A y is the sum over s of D[s][k] y[k + s]
+// and, for 0 < s < NI - s, of D[s][k - s] y[k - s] (indices mod NI; the
+// second term is the transposed half, read from the same diagonal).  Both
+// reads of a diagonal are contiguous across k, so a slot's loads coalesce
+// and the second one hits the cache lines of the first.
+// Rows k = t, t + NT, .. (R of them) of one thread, in one pass over the
+// diagonals so that the loads of all its rows are in flight together; rows
+// past NI read row NI - 1 and their result is not used.
+template <int NI, int NT, int R>
+__device__ __forceinline__ void sc_symv_rows(const double* __restrict__ D, const double* y, int t,
+                                             double (&z)[R]) {
+  constexpr int H = NI / 2;
+  int k[R], kp[R], km[R];   // row, (k + s) mod NI, (k - s) mod NI
+  double zt[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    k[i] = t + i * NT < NI ? t + i * NT : NI - 1;
+    kp[i] = km[i] = k[i];
+    z[i] = zt[i] = 0.0;
+  }
+#pragma unroll 16
+  for (int s = 0; s <= H; ++s) {
+    const double* Ds = D + s * NI;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      z[i] += Ds[k[i]] * y[kp[i]];
+      if (s > 0 && s < NI - s) zt[i] += Ds[km[i]] * y[km[i]];
+      kp[i] = kp[i] + 1 == NI ? 0 : kp[i] + 1;
+      km[i] = km[i] == 0 ? NI - 1 : km[i] - 1;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) z[i] += zt[i];
+}
+
 // ------------------------------------------------------------ operator passes
 
 template <int N, int Q, int EPB, int PASS>
@@ -40,8 +79,51 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
   const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
   bool live = e < a.nelem;
   if (live && seg_converged(a.elem_seg, a.seg_done, e)) live = false;
+  constexpr int NI = (N - 2) * (N - 2) * (N - 2);
+  double* scb = a.out2 + (live ? e : 0) * (int64_t)NI;
   helm3_body<double, N, Q, NT, true, 2, true, PASS>(tb, smem + slot * 3 * S, red, slot, t, live,
-                                                     e, a);
+                                                     e, a, scb);
+}
+
+// The whole condensed operator of one element per slot in one launch:
+// pass 1 into the slot's LDS block y, z = -H_ii^{-1} y (the slot's threads
+// take the rows k = t, t + NT, ...; the inverse in its diagonal storage),
+// pass 2 from z.  The interior values never
+// leave LDS, and pass 2 re-reads the element's factors and map right after
+// pass 1, from cache.
+// PF / EOI: the Helmholtz body's factor prefetch depth and I-stage form
+// (two variants per order are compiled; setup times both).  ASM = false is
+// the elemental form S_e x_e on local vectors (local input with zero
+// interior entries, every local output stored), used to probe diag(S_e).
+template <int N, int Q, int EPB, int PF, bool EOI, bool ASM = true>
+__global__ void __launch_bounds__(EPB * slot_threads<Q>())
+    k_sc_fused(const Tab<double, N, Q> tb, const DevArgs<double> a, const double* __restrict__ A) {
+  constexpr int NT = slot_threads<Q>(), S = Q * Q * N, NI = (N - 2) * (N - 2) * (N - 2);
+  __shared__ double smem[EPB * 3 * S];
+  __shared__ double red[NT != 64 ? EPB * NT : 1];
+  __shared__ double ib[EPB][2][NI];
+  const int slot = threadIdx.x / NT;
+  const int t = threadIdx.x - slot * NT;
+  const int64_t nblk = (a.nelem + EPB - 1) / EPB;
+  const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
+  bool live = e < a.nelem;
+  if (live && seg_converged(a.elem_seg, a.seg_done, e)) live = false;
+  double* y = ib[slot][0];
+  double* z = ib[slot][1];
+  helm3_body<double, N, Q, NT, ASM, PF, EOI, 1>(tb, smem + slot * 3 * S, red, slot, t, live, e, a,
+                                                y);
+  slot_sync<NT>();
+  if (live) {
+    constexpr int R = (NI + NT - 1) / NT;
+    double zr[R];
+    sc_symv_rows<NI, NT, R>(A + e * (int64_t)sc_packed(NI), y, t, zr);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (t + i * NT < NI) z[t + i * NT] = -zr[i];
+  }
+  slot_sync<NT>();
+  helm3_body<double, N, Q, NT, ASM, PF, EOI, 2>(tb, smem + slot * 3 * S, red, slot, t, live, e, a,
+                                                z);
 }
 
 template <int P, int PASS>
@@ -69,6 +151,57 @@ static hipError_t run_pass(const CondOp& c, const double* x, double* y, double* 
   return hipGetLastError();
 }
 
+template <int P, int PF, bool EOI, bool ASM = true>
+static hipError_t run_fused(const CondOp& c, const double* x, double* y, double* dots,
+                            const int32_t* dslot, const int32_t* seg_done, hipStream_t s) {
+  constexpr int N = P + 1, Q = P + 2, EPB = kTileEPB3[P][0];
+  DevArgs<double> d{};
+  d.nelem = c.nelem;
+  d.in = x;
+  d.out = y;
+  d.fac = c.fac;
+  d.lam = c.lam;
+  d.lam0 = c.lam0;
+  d.l2g = c.l2g;
+  d.dots = dots;
+  d.dslot = dslot;
+  d.seg_done = seg_done;
+  const int64_t nblk = (c.nelem + EPB - 1) / EPB;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  if (nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sc_fused<N, Q, EPB, PF, EOI, ASM>), dim3((unsigned)nblk),
+                     dim3(EPB * slot_threads<Q>()), 0, s, host_tab<double, N, Q>(), d, c.ainv);
+  return hipGetLastError();
+}
+
+hipError_t sc_apply(const CondOp& c, const double* x, double* y, double* dots,
+                    const int32_t* dslot, const int32_t* seg_done, hipStream_t s) {
+#define NK_SC_FUSED(P)                                                      \
+  case P:                                                                   \
+    return c.variant == 0 ? run_fused<P, 2, true>(c, x, y, dots, dslot, seg_done, s) \
+                          : run_fused<P, 1, false>(c, x, y, dots, dslot, seg_done, s);
+  switch (c.P) {
+    NK_SC_FUSED(2)
+    NK_SC_FUSED(3)
+    NK_SC_FUSED(4)
+    NK_SC_FUSED(5)
+    NK_SC_FUSED(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef NK_SC_FUSED
+}
+
+hipError_t sc_local(const CondOp& c, const double* x, double* y, hipStream_t s) {
+  switch (c.P) {
+    case 2: return run_fused<2, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 3: return run_fused<3, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 4: return run_fused<4, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 5: return run_fused<5, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 6: return run_fused<6, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t sc_pass(const CondOp& c, int pass, const double* x, double* y, double* dots,
                    const int32_t* dslot, const int32_t* seg_done, hipStream_t s) {
   if (pass != 1 && pass != 2) return hipErrorInvalidValue;
@@ -89,10 +222,9 @@ hipError_t sc_pass(const CondOp& c, int pass, const double* x, double* y, double
 
 // --------------------------------------------------------- interior inverse
 // One block per element.  y_k = alpha T[e][k] + beta sign_k b[dof_k] (terms
-// with a zero coefficient are not read), z = gamma H_ii^{-1} y; z goes back
-// to T[e] or, with xadd, is added to xadd at the interior DOFs (sign
-// applied).  The inverse is symmetric, so thread k reads column k of row j:
-// for each j the block reads one contiguous row.
+// with a zero coefficient are not read), z = gamma H_ii^{-1} y (the inverse
+// in its diagonal storage); z goes back to T[e] or, with xadd, is added to
+// xadd at the interior DOFs (sign applied).
 template <int NI>
 __global__ void __launch_bounds__(sc_threads(NI))
     k_sc_ainv(const double* __restrict__ A, double* __restrict__ T, const double* __restrict__ b,
@@ -112,18 +244,9 @@ __global__ void __launch_bounds__(sc_threads(NI))
   }
   __syncthreads();
   if (k < NI) {
-    const double* Ak = A + e * (int64_t)(NI * NI) + k;
-    double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-    int j = 0;
-#pragma unroll 4
-    for (; j + 4 <= NI; j += 4) {
-      z0 += Ak[(j + 0) * NI] * ys[j + 0];
-      z1 += Ak[(j + 1) * NI] * ys[j + 1];
-      z2 += Ak[(j + 2) * NI] * ys[j + 2];
-      z3 += Ak[(j + 3) * NI] * ys[j + 3];
-    }
-    for (; j < NI; ++j) z0 += Ak[j * NI] * ys[j];
-    const double z = gamma * ((z0 + z1) + (z2 + z3));
+    double zr[1];
+    sc_symv_rows<NI, sc_threads(NI), 1>(A + e * (int64_t)sc_packed(NI), ys, k, zr);
+    const double z = gamma * zr[0];
     if (xadd != nullptr)
       xadd[l2g_dof(ik)] += l2g_sign(ik, z);
     else
@@ -176,6 +299,40 @@ __global__ void k_sc_unit(int P, int64_t nelem, double* __restrict__ c, int k) {
   }
 }
 
+// c[e][m_new] = 1 and c[e][m_old] = 0 (m_old < 0: none) for every element.
+__global__ void k_sc_unit_mode(int n3, int64_t nelem, double* __restrict__ c, int m_new, int m_old) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nelem;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (m_old >= 0) c[e * n3 + m_old] = 0.0;
+    c[e * n3 + m_new] = 1.0;
+  }
+}
+
+// diag[g] += y[e][m] where local mode m of element e is the free DOF g of
+// the boundary map (its sign squares away).
+__global__ void k_sc_diag_add(int n3, int64_t nelem, const double* __restrict__ y, int m,
+                              const int32_t* __restrict__ l2g, double* __restrict__ diag) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nelem;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = l2g[e * n3 + m];
+    if (g >= 0) atomicAdd(diag + l2g_dof(g), y[e * n3 + m]);
+  }
+}
+
+// Jacobi preconditioner from diag: on the free DOFs (dinv64 != 0) dinv =
+// 1/diag and diag_out = diag.
+__global__ void k_sc_dinv(int64_t n, const double* __restrict__ diag, double* __restrict__ dinv64,
+                          float* __restrict__ dinv32, double* __restrict__ diag_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (dinv64[i] != 0.0) {
+      dinv64[i] = 1.0 / diag[i];
+      dinv32[i] = (float)(1.0 / diag[i]);
+      diag_out[i] = diag[i];
+    }
+  }
+}
+
 // Row k of H_ii (= column k, H is symmetric) from y = H e_k.
 __global__ void k_sc_column(int P, int64_t nelem, const double* __restrict__ y,
                             double* __restrict__ A, int k) {
@@ -222,6 +379,19 @@ __global__ void __launch_bounds__(256) k_sc_invert(double* __restrict__ A, int* 
   }
 }
 
+// Diagonal storage of each element's inverse (see sc_symv_row).
+__global__ void k_sc_pack(int ni, int64_t nelem, const double* __restrict__ A,
+                          double* __restrict__ D) {
+  const int64_t per = (int64_t)(ni / 2 + 1) * ni, total = nelem * per;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx / per;
+    const int r = (int)(idx - e * per), sd = r / ni, k = r - sd * ni;
+    const int j = k + sd < ni ? k + sd : k + sd - ni;
+    D[idx] = A[(e * ni + k) * ni + j];
+  }
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t nb = (n + 255) / 256;
   if (nb > 65536) nb = 65536;
@@ -233,9 +403,35 @@ hipError_t sc_unit(int P, int64_t nelem, double* c, int k, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t sc_unit_mode(int P, int64_t nelem, double* c, int m_new, int m_old, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_unit_mode, dim3(grid_for(nelem)), dim3(256), 0, s, (P + 1) * (P + 1) * (P + 1),
+                     nelem, c, m_new, m_old);
+  return hipGetLastError();
+}
+
+hipError_t sc_diag_add(int P, int64_t nelem, const double* y, int m, const int32_t* l2g,
+                       double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_diag_add, dim3(grid_for(nelem)), dim3(256), 0, s, (P + 1) * (P + 1) * (P + 1),
+                     nelem, y, m, l2g, diag);
+  return hipGetLastError();
+}
+
+hipError_t sc_dinv(int64_t n, const double* diag, double* dinv64, float* dinv32, double* diag_out,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_dinv, dim3(grid_for(n)), dim3(256), 0, s, n, diag, dinv64, dinv32,
+                     diag_out);
+  return hipGetLastError();
+}
+
 hipError_t sc_column(int P, int64_t nelem, const double* y, double* A, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_sc_column, dim3(grid_for(nelem * sc_ni(P))), dim3(256), 0, s, P, nelem, y,
                      A, k);
+  return hipGetLastError();
+}
+
+hipError_t sc_pack(int P, int64_t nelem, const double* A, double* D, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_pack, dim3(grid_for(nelem * sc_packed(sc_ni(P)))), dim3(256), 0, s,
+                     sc_ni(P), nelem, A, D);
   return hipGetLastError();
 }
 

@@ -603,14 +603,16 @@ __device__ __forceinline__ int sc_k(int t) {
 // p_e . (H_e p_e).
 // SC selects a pass of the statically condensed operator (assembled maps
 // whose interior modes are Dirichlet entries, so their gathered values are
-// 0 and their scatter is skipped): 1 stores the element's interior outputs
-// into out2[e][k] and scatters nothing; 2 takes the interior inputs from
-// in2[e][k], scatters the boundary outputs and sums the energy over the free
-// boundary modes only.
+// 0 and their scatter is skipped; local inputs whose interior entries are
+// 0): 1 stores the element's interior outputs into scb[k] and writes nothing
+// else; 2 takes the interior inputs from scb[k], then scatters the boundary
+// outputs and sums the energy over the free boundary modes only (ASM) or
+// stores every output locally.  scb is the element's block of (N-2)^3
+// interior values (global or LDS memory).
 template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true, int SC = 0>
 __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
-                                           const DevArgs<T>& a) {
+                                           const DevArgs<T>& a, double* scb = nullptr) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q;
   const int64_t ee = live ? e : 0;
   const bool pq = live && t < NN;
@@ -632,10 +634,10 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
       for (int r = 0; r < N; ++r) xin[r] = l2g_value(gidx[r], xin[r]);
     }
     if constexpr (SC == 2) {
-      static_assert(ASM && N >= 3, "condensed pass");
+      static_assert(N >= 3, "condensed pass");
       constexpr int NI2 = (N - 2) * (N - 2);
       if (sc_inner<N>(t)) {
-        const double* ti = a.in2 + ee * (int64_t)(NI2 * (N - 2)) + sc_k<N>(t);
+        const double* ti = scb + sc_k<N>(t);
 #pragma unroll
         for (int r = 1; r < N - 1; ++r) xin[r] = (T)ti[(r - 1) * NI2];
       }
@@ -704,10 +706,10 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
   T yv[N];
   stage_kt<T, N, Q, true>(tb, sm, t, live, yv);
   if constexpr (SC == 1) {
-    static_assert(ASM && N >= 3, "condensed pass");
+    static_assert(N >= 3, "condensed pass");
     constexpr int NI2 = (N - 2) * (N - 2);
     if (pq && sc_inner<N>(t)) {
-      double* to = a.out2 + ee * (int64_t)(NI2 * (N - 2)) + sc_k<N>(t);
+      double* to = scb + sc_k<N>(t);
 #pragma unroll
       for (int r = 1; r < N - 1; ++r) to[(r - 1) * NI2] = (double)yv[r];
     }

@@ -105,16 +105,23 @@ hipError_t launch_diag(int dim, int P, int Q, int64_t nelem, const double* Bt, c
 // Statically condensed operator of a hexahedral system (condense.hip).
 constexpr int kCondMinP = 2;
 constexpr int kCondMaxP = 6;
+// scalars of one element's interior inverse in its diagonal storage
+constexpr int sc_packed(int ni) { return (ni / 2 + 1) * ni; }
 struct CondOp {
   int P = 0;
   int64_t nelem = 0;
-  const double* ainv = nullptr;   // [E][NI][NI] interior inverses, NI = (P-1)^3
+  const double* ainv = nullptr;   // [E][NI/2 + 1][NI] interior inverses by diagonals, NI = (P-1)^3
   double* t = nullptr;            // [E][NI] interior values between the passes
   const double* fac = nullptr;    // FP64 geometric factors
   const double* lam = nullptr;
   double lam0 = 0.0;
   const int32_t* l2g = nullptr;   // internal map of the boundary system
+  int variant = 0;                // fused kernel: 0 paired I stage, two factor sets; 1 point by
+                                  // point, one set (fewer registers)
 };
+// y += S x (boundary numbering) in one fused launch, element energies into dots
+hipError_t sc_apply(const CondOp& c, const double* x, double* y, double* dots,
+                    const int32_t* dslot, const int32_t* seg_done, hipStream_t s);
 // pass 1: t = interior part of H [x_b; 0]; pass 2: y += boundary part of
 // H [x_b; t], element energies into dots
 hipError_t sc_pass(const CondOp& c, int pass, const double* x, double* y, double* dots,
@@ -123,9 +130,18 @@ hipError_t sc_pass(const CondOp& c, int pass, const double* x, double* y, double
 // interior DOFs (iidx: DOF | sign bit per interior mode)
 hipError_t sc_ainv(const CondOp& c, const double* b, const int32_t* iidx, double alpha, double beta,
                    double gamma, double* xadd, const int32_t* seg_done, hipStream_t s);
+// y_e = S_e x_e on local vectors (x_e with zero interior entries)
+hipError_t sc_local(const CondOp& c, const double* x, double* y, hipStream_t s);
 hipError_t sc_unit(int P, int64_t nelem, double* c, int k, hipStream_t s);
+hipError_t sc_unit_mode(int P, int64_t nelem, double* c, int m_new, int m_old, hipStream_t s);
+hipError_t sc_diag_add(int P, int64_t nelem, const double* y, int m, const int32_t* l2g,
+                       double* diag, hipStream_t s);
+hipError_t sc_dinv(int64_t n, const double* diag, double* dinv64, float* dinv32, double* diag_out,
+                   hipStream_t s);
 hipError_t sc_column(int P, int64_t nelem, const double* y, double* A, int k, hipStream_t s);
 hipError_t sc_invert(int P, int64_t nelem, double* A, int* bad, hipStream_t s);
+// D = diagonal storage of the full inverses A ([E][NI][NI])
+hipError_t sc_pack(int P, int64_t nelem, const double* A, double* D, hipStream_t s);
 hipError_t sc_restrict(int64_t nb, int64_t npad, const int32_t* bmap, const double* full,
                        const double* dinv_c, double* cond, hipStream_t s);
 hipError_t sc_expand_add(int64_t nb, const int32_t* bmap, const double* cond, double* full,

@@ -108,7 +108,7 @@ def lib():
         "nk_space_create_tet": (i32, [pp, i64, i32, i32, vp, vp, vp]),
         "nk_space_create_prism": (i32, [pp, i64, i32, i32, vp, vp, vp]),
         "nk_space_create_pyr": (i32, [pp, i64, i32, i32, vp, vp, vp]),
-        "nk_system_condense": (i32, [vp, ctypes.POINTER(i64), vp, vp]),
+        "nk_system_condense": (i32, [vp, ctypes.POINTER(i64), vp, vp, vp]),
         "nk_condensed_apply": (i32, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -507,18 +507,23 @@ class System:
             _check(st)
         return x, [i.as_dict() for i in infos]
 
-    def condense(self, with_map: bool = True):
+    def condense(self, with_map: bool = True, with_diag: bool = False):
         """nk_system_condense: builds the statically condensed boundary system
-        (once); returns (nboundary, bmap int32 device tensor or None)."""
+        (once); returns (nboundary, bmap int32 device tensor or None), plus
+        diag(S) (FP64 device tensor) with with_diag."""
         import torch
         nb = ctypes.c_int64(0)
-        _check(lib().nk_system_condense(self.handle, ctypes.byref(nb), None, _stream()))
-        if not with_map:
-            return nb.value, None
-        bmap = torch.empty(max(nb.value, 1), dtype=torch.int32, device="cuda")
-        _check(lib().nk_system_condense(self.handle, ctypes.byref(nb), _ptr(bmap, torch.int32, "bmap"),
-                                        _stream()))
-        return nb.value, bmap[:nb.value]
+        _check(lib().nk_system_condense(self.handle, ctypes.byref(nb), None, None, _stream()))
+        bmap = diag = None
+        if with_map or with_diag:
+            n = max(nb.value, 1)
+            bmap = torch.empty(n, dtype=torch.int32, device="cuda") if with_map else None
+            diag = torch.empty(n, dtype=torch.float64, device="cuda") if with_diag else None
+            _check(lib().nk_system_condense(self.handle, ctypes.byref(nb), _ptr(bmap, torch.int32, "bmap"),
+                                            _ptr(diag, torch.float64, "bdiag"), _stream()))
+            bmap = bmap[:nb.value] if bmap is not None else None
+            diag = diag[:nb.value] if diag is not None else None
+        return (nb.value, bmap, diag) if with_diag else (nb.value, bmap)
 
     def condensed_apply(self, xb, yb=None):
         """nk_condensed_apply: yb = S xb over the boundary numbering."""

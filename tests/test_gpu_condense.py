@@ -1,5 +1,5 @@
 """GPU parity of static condensation (section 2.1): the boundary numbering,
-the condensed operator S x_B against the oracle's assembled elemental Schur
+the Jacobi preconditioner diag(S), the condensed operator S x_B against the oracle's assembled elemental Schur
 complements (FP64 <= 1e-12: the interior blocks have condition numbers below
 40 up to P = 6, so the dense inverse adds no more than the assembled
 operator's rounding), the condensed solve against the oracle's direct solve
@@ -45,8 +45,11 @@ def test_condensed_operator_matches_oracle(P, shape, signed, lam):
     nb, bmap = c["sysm"].condense()
     assert nb == ref.bdofs.size
     np.testing.assert_array_equal(bmap.cpu().numpy(), ref.bdofs)
-    # a second call reuses the built form
-    assert c["sysm"].condense(with_map=False)[0] == nb
+    # a second call reuses the built form; the preconditioner is diag(S)
+    nb2, _, dS = c["sysm"].condense(with_map=False, with_diag=True)
+    assert nb2 == nb
+    dref = np.where(ref.bfree, ref.S.diagonal(), 1.0)
+    assert_close(dS.cpu().numpy(), dref, FP64_RTOL, f"diag(S) P={P}")
     for k in range(2):
         xb = W.uniform(W.seed(0, 71) + 10 * P + k, nb)
         y = c["sysm"].condensed_apply(to_dev(xb)).cpu().numpy()
