@@ -50,7 +50,7 @@ __device__ __forceinline__ void sc_symv_rows(const double* __restrict__ D, const
     kp[i] = km[i] = k[i];
     z[i] = zt[i] = 0.0;
   }
-#pragma unroll 16
+#pragma unroll 32
   for (int s = 0; s <= H; ++s) {
     const double* Ds = D + s * NI;
 #pragma unroll
