@@ -11,8 +11,9 @@
  * Helmholtz operator of the weak problem a(u, v) = l(v) of Eqs. (1)-(2), all
  * by sum-factorisation (the display in section 3.3).  On top of these it
  * assembles the C0 system (section 2.1, assembly operator) and solves it with
- * Jacobi-preconditioned conjugate gradients (FP64, or FP32 with FP64
- * residual updates), batches independent systems and mixed orders, and
+ * Jacobi-preconditioned conjugate gradients (FP64, FP32 with FP64 residual
+ * updates, or FP64 on the system statically condensed onto the elemental
+ * boundary DOFs), batches independent systems and mixed orders, and
  * differentiates the solve with respect to kappa and lambda.  Besides
  * quadrilaterals and hexahedra it covers the collapsed-coordinate triangles,
  * tetrahedra, prisms and pyramids of section 2.1 (their elemental operators
