@@ -424,6 +424,11 @@ def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
         t = time.perf_counter()
         xc, inf_c = sysm.solve(b, rtol=1e-10, maxit=50000, mode=nk.SOLVE_CONDENSED)
         tc = (time.perf_counter() - t) * 1e3
+        sysm.solve(b, rtol=1e-2, maxit=64, mode=nk.SOLVE_CONDENSED_F32_REFINED)   # FP32 copy, graphs
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xr, inf_r = sysm.solve(b, rtol=1e-10, maxit=50000, mode=nk.SOLVE_CONDENSED_F32_REFINED)
+        tr = (time.perf_counter() - t) * 1e3
         nel, n3, q3, ni = lat.nelem, (P + 1) ** 3, (P + 2) ** 3, (P - 1) ** 3
         # algorithmic bytes of one boundary iteration: one read of the factors
         # and the map (the fused kernel's second pass re-reads them from
@@ -439,13 +444,18 @@ def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
             "condensed": {"ms": round(tc, 2), "iters": inf_c[0]["iters"], "passes": inf_c[0]["outer_iters"],
                           "rel_resid": inf_c[0]["rel_resid"], "ms_per_iter": round(ms_it, 4),
                           "GB_s_per_iter": round(gbs, 1), "hbm_frac_per_iter": round(gbs / HBM_PEAK_GBS, 4)},
+            "condensed_f32_refined": {"ms": round(tr, 2), "iters": inf_r[0]["iters"],
+                                      "passes": inf_r[0]["outer_iters"], "rel_resid": inf_r[0]["rel_resid"],
+                                      "rel_diff": float(torch.linalg.norm(xr - xf) / torch.linalg.norm(xf))},
             "speedup_condensed_vs_full": round(tf / tc, 3),
+            "speedup_condensed_f32_refined_vs_full": round(tf / tr, 3),
             "rel_diff": float(torch.linalg.norm(xc - xf) / torch.linalg.norm(xf)),
         }
         log(f"condensed P={P}: setup {setup_ms:.1f} ms, full {tf:.1f} ms ({inf_f[0]['iters']} it), "
             f"condensed {tc:.1f} ms ({inf_c[0]['iters']} it, {inf_c[0]['outer_iters']} passes, "
-            f"{ms_it * 1e3:.1f} us/it)")
-        del space, sysm, b, xf, xc
+            f"{ms_it * 1e3:.1f} us/it), condensed f32-refined {tr:.1f} ms ({inf_r[0]['iters']} it, "
+            f"{inf_r[0]['outer_iters']} passes)")
+        del space, sysm, b, xf, xc, xr
         torch.cuda.empty_cache()
     return out
 

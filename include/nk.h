@@ -78,7 +78,12 @@ typedef enum {
 
 typedef enum { NK_F64 = 0, NK_F32 = 1 } nk_dtype;
 
-typedef enum { NK_SOLVE_F64 = 0, NK_SOLVE_F32_REFINED = 1, NK_SOLVE_CONDENSED = 2 } nk_solve_mode;
+typedef enum {
+  NK_SOLVE_F64 = 0,
+  NK_SOLVE_F32_REFINED = 1,
+  NK_SOLVE_CONDENSED = 2,
+  NK_SOLVE_CONDENSED_F32_REFINED = 3
+} nk_solve_mode;
 
 typedef struct nk_space_s* nk_space;
 typedef struct nk_system_s* nk_system;
@@ -87,7 +92,7 @@ typedef struct {
   int iters;             /* CG iterations summed over restarts (FP64 mode) or inner
                             FP32 iterations summed over refinement steps            */
   int outer_iters;       /* FP64 residual updates (FP32-refined mode), condensation
-                            passes (condensed mode), 0 otherwise                       */
+                            passes (condensed modes), 0 otherwise                      */
   double rel_resid;      /* true ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit    */
   double solve_ms;       /* wall time of the solve on the host clock                   */
   int status;            /* nk_status of this system                                   */
@@ -367,8 +372,11 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
  * built on first use), preconditioned by the diagonal of S;
  * the interiors follow element by element, and the pass repeats on the full
  * residual b - A x until it meets rtol (iters: boundary CG iterations summed
- * over passes).  One-system hexahedral systems with 2 <= P <= 6 only
- * (NK_EUNSUPPORTED otherwise).  Iterations run as captured HIP graphs that
+ * over passes).  NK_SOLVE_CONDENSED_F32_REFINED: the same, with the boundary
+ * system solved as NK_SOLVE_F32_REFINED solves (FP32 condensed operator from
+ * an FP32 copy of the interior inverses, made on first use, with FP64
+ * reliable updates; iters: FP32 boundary iterations).  Both: one-system
+ * hexahedral systems with 2 <= P <= 6 only (NK_EUNSUPPORTED otherwise).  Iterations run as captured HIP graphs that
  * do not depend on rtol or maxit.  info (host, may be NULL) receives one
  * entry per system (nsys entries for a batched system).  Returns NK_ENOCONV
  * (budget spent with the true residual above rtol) or NK_EBREAKDOWN if any

@@ -1125,10 +1125,9 @@ nk_status nk_system_destroy(nk_system sys) {
 static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, void* out,
                                double* dots, const int32_t* seg_done, int tile, hipStream_t st) {
   nk_space s = y->space;
-  if (y->sc) {   // boundary system of a static condensation (FP64, one hexahedral group)
-    if (t != NK_F64 || g != 0) return hipErrorInvalidValue;
-    return sc_apply(*y->sc, (const double*)x, (double*)out, dots, dots ? y->dslot : nullptr,
-                    seg_done, st);
+  if (y->sc) {   // boundary system of a static condensation (one hexahedral group)
+    if (g != 0) return hipErrorInvalidValue;
+    return sc_apply(*y->sc, t, x, out, dots, dots ? y->dslot : nullptr, seg_done, st);
   }
   const Group& G = s->groups[g];
   OpArgs a;
@@ -1754,7 +1753,8 @@ static hipError_t solve_padded(nk_system y, nk_solve_mode mode, double rtol, int
 }
 
 static nk_status check_solve_args(nk_solve_mode mode, double rtol, int maxit) {
-  if (mode != NK_SOLVE_F64 && mode != NK_SOLVE_F32_REFINED && mode != NK_SOLVE_CONDENSED)
+  if (mode != NK_SOLVE_F64 && mode != NK_SOLVE_F32_REFINED && mode != NK_SOLVE_CONDENSED &&
+      mode != NK_SOLVE_CONDENSED_F32_REFINED)
     return fail(NK_EINVAL, "bad mode");
   if (!(rtol > 0.0) || rtol >= 1.0) return fail(NK_EINVAL, "rtol must be in (0, 1)");
   if (maxit < 1) return fail(NK_EINVAL, "maxit must be >= 1");
@@ -1783,6 +1783,7 @@ static void cond_free(CondData*& c) {
   dfree(c->bmap);
   dfree(c->iidx);
   dfree(c->ainv);
+  dfree(c->ainv32);
   dfree(c->t);
   dfree(c->zero);
   delete c;
@@ -1797,6 +1798,66 @@ static nk_status cond_check(nk_system y) {
   const Group& G = s->groups[0];
   if (G.P < kCondMinP || G.P > kCondMaxP || G.Q != G.P + 2)
     return fail(NK_EUNSUPPORTED, "static condensation is built for 2 <= P <= 6 with Q = P + 2");
+  return NK_OK;
+}
+
+// Time the two fused-kernel variants of one precision on the boundary
+// system (five launches each, after a warm-up) and keep the faster.  The
+// timing runs write into the boundary system's work vectors, cleared after.
+static hipError_t cond_pick_variant(CondData* c, nk_dtype t, hipStream_t st) {
+  nk_system z = c->bsys;
+  const int64_t np = z->L.npad;
+  void* in = t == NK_F64 ? (void*)c->zero : (void*)z->s32;
+  void* out = t == NK_F64 ? (void*)z->y : (void*)z->y32;
+  int& var = t == NK_F64 ? c->op.variant : c->op.variant32;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if (t == NK_F32 && (e = vec_fill<float>(z->s32, np, 0.f, st))) return e;
+  if ((e = hipEventCreate(&e0))) return e;
+  if ((e = hipEventCreate(&e1))) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  float best = 0.f;
+  int pick = 0;
+  for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+    var = v;
+    e = sc_apply(c->op, t, in, out, nullptr, nullptr, nullptr, st);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < 5 && e == hipSuccess; ++r)
+      e = sc_apply(c->op, t, in, out, nullptr, nullptr, nullptr, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (v == 0 || ms < best)) {
+      best = ms;
+      pick = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  var = pick;
+  if (e == hipSuccess)
+    e = t == NK_F64 ? vec_fill<double>(z->y, np, 0.0, st) : vec_fill<float>(z->y32, np, 0.f, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+// The FP32 copy of the inverses and the FP32 kernel choice (first refined
+// condensed solve of a system).
+static nk_status cond_build_f32(CondData* c, hipStream_t st) {
+  if (c->ainv32) return NK_OK;
+  const int ni = (c->op.P - 1) * (c->op.P - 1) * (c->op.P - 1);
+  const int64_t n = std::max<int64_t>(c->op.nelem * sc_packed(ni), 1);
+  hipError_t e;
+  if ((e = dmalloc(&c->ainv32, n))) return hip_fail(e, "hipMalloc");
+  if ((e = cast_copy(c->ainv, c->ainv32, n, st)) || (e = hipStreamSynchronize(st))) {
+    dfree(c->ainv32);
+    return hip_fail(e, "condensation setup");
+  }
+  c->op.ainv32 = c->ainv32;
+  if ((e = cond_pick_variant(c, NK_F32, st))) return hip_fail(e, "condensation setup");
   return NK_OK;
 }
 
@@ -1940,6 +2001,7 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   c->op.ainv = c->ainv;
   c->op.t = c->t;
   c->op.fac = s->fac64 + G.f0;
+  c->op.fac32 = s->fac32 + G.f0;
   c->op.lam = c->bsys->lam;
   c->op.lam0 = y->lam0;
   c->op.l2g = c->bsys->l2g;
@@ -1976,38 +2038,7 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   dfree(d_bad);
   c->bsys->sc = &c->op;
   // the faster of the two fused-kernel variants on this system
-  {
-    nk_system z = c->bsys;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    float best = 0.f;
-    int pick = 0;
-    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
-      if (e0) (void)hipEventDestroy(e0);
-      return bail(hip_fail(e, "hipEventCreate"));
-    }
-    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
-      c->op.variant = v;
-      e = sc_apply(c->op, c->zero, z->y, nullptr, nullptr, nullptr, st);   // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int r = 0; r < 5 && e == hipSuccess; ++r)
-        e = sc_apply(c->op, c->zero, z->y, nullptr, nullptr, nullptr, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess && (v == 0 || ms < best)) {
-        best = ms;
-        pick = v;
-      }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->op.variant = pick;
-    // the timing runs accumulated into the boundary system's output vector
-    if (e == hipSuccess) e = vec_fill<double>(z->y, z->L.npad, 0.0, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return bail(hip_fail(e, "condensation setup"));
-  }
+  if ((e = cond_pick_variant(c, NK_F64, st))) return bail(hip_fail(e, "condensation setup"));
   y->cond = c;
   return NK_OK;
 }
@@ -2061,8 +2092,8 @@ nk_status nk_condensed_apply(nk_system sys, const double* xb, double* yb, void* 
 // (right-hand side g = r_B - sum_e R_e^T H_bi H_ii^{-1} r_i(e)), the interiors
 // follow element by element, x is updated and the full true residual
 // recomputed; passes repeat until it meets rtol (one pass as a rule).
-static nk_status cg_solve_condensed(nk_system y, const double* b, double* x, double rtol, int maxit,
-                                    nk_solve_info* info, void* stream) {
+static nk_status cg_solve_condensed(nk_system y, bool refined, const double* b, double* x,
+                                    double rtol, int maxit, nk_solve_info* info, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t us = (hipStream_t)stream;
   hipStream_t cs = y->cs;
@@ -2072,6 +2103,7 @@ static nk_status cg_solve_condensed(nk_system y, const double* b, double* x, dou
   NK_CHECK(cond_build(y, cs));
   CondData* c = y->cond;
   nk_system z = c->bsys;
+  if (refined) NK_CHECK(cond_build_f32(c, cs));
   const int kMaxPasses = 4;
   int iters = 0, passes = 0;
   int32_t status = NK_ENOCONV;
@@ -2104,12 +2136,11 @@ static nk_status cg_solve_condensed(nk_system y, const double* b, double* x, dou
       // the boundary residual that makes the full one meet rtol
       double rc = gg[0] > 0.0 ? 0.9 * rtol * std::sqrt(bb[0] / gg[0]) : 0.5;
       rc = std::min(rc, 0.5);
-      std::vector<int> it(1, 0);
-      std::vector<int32_t> st;
-      std::vector<double> rrc;
-      if ((e = solve_f64(z, rc, maxit - iters, it, st, rrc))) break;
-      iters += it[0];
-      if (st[0] == NK_EBREAKDOWN) {
+      SolveOut so;
+      if ((e = solve_padded(z, refined ? NK_SOLVE_F32_REFINED : NK_SOLVE_F64, rc, maxit - iters, so)))
+        break;
+      iters += so.iters[0];
+      if (so.stat[0] == NK_EBREAKDOWN) {
         status = NK_EBREAKDOWN;
         break;
       }
@@ -2146,7 +2177,9 @@ nk_status nk_cg_solve(nk_system y, nk_solve_mode mode, const double* b, double* 
   NK_CHECK(check_solve_args(mode, rtol, maxit));
   NK_CHECK(check_buf(b, y->nuser * 8, "b"));
   NK_CHECK(check_buf(x, y->nuser * 8, "x"));
-  if (mode == NK_SOLVE_CONDENSED) return cg_solve_condensed(y, b, x, rtol, maxit, info, stream);
+  if (mode == NK_SOLVE_CONDENSED || mode == NK_SOLVE_CONDENSED_F32_REFINED)
+    return cg_solve_condensed(y, mode == NK_SOLVE_CONDENSED_F32_REFINED, b, x, rtol, maxit, info,
+                              stream);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t us = (hipStream_t)stream;
   hipStream_t cs = y->cs;
@@ -2380,8 +2413,8 @@ nk_status nk_cg_solve_batched(nk_system* sys, int nsys, nk_solve_mode mode, cons
   if (!sys || !b || !x) return fail(NK_EINVAL, "sys, b and x must be non-NULL");
   if (nsys < 1) return fail(NK_EINVAL, "nsys must be >= 1");
   NK_CHECK(check_solve_args(mode, rtol, maxit));
-  if (mode == NK_SOLVE_CONDENSED)
-    return fail(NK_EUNSUPPORTED, "NK_SOLVE_CONDENSED solves one system per nk_cg_solve call");
+  if (mode == NK_SOLVE_CONDENSED || mode == NK_SOLVE_CONDENSED_F32_REFINED)
+    return fail(NK_EUNSUPPORTED, "the condensed modes solve one system per nk_cg_solve call");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -38,21 +38,20 @@ constexpr int sc_threads(int ni) { return ni <= 64 ? 64 : (ni + 63) / 64 * 64; }
 // Rows k = t, t + NT, .. (R of them) of one thread, in one pass over the
 // diagonals so that the loads of all its rows are in flight together; rows
 // past NI read row NI - 1 and their result is not used.
-template <int NI, int NT, int R>
-__device__ __forceinline__ void sc_symv_rows(const double* __restrict__ D, const double* y, int t,
-                                             double (&z)[R]) {
+template <typename T, int NI, int NT, int R>
+__device__ __forceinline__ void sc_symv_rows(const T* __restrict__ D, const T* y, int t, T (&z)[R]) {
   constexpr int H = NI / 2;
   int k[R], kp[R], km[R];   // row, (k + s) mod NI, (k - s) mod NI
-  double zt[R];
+  T zt[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     k[i] = t + i * NT < NI ? t + i * NT : NI - 1;
     kp[i] = km[i] = k[i];
-    z[i] = zt[i] = 0.0;
+    z[i] = zt[i] = T(0);
   }
 #pragma unroll 32
   for (int s = 0; s <= H; ++s) {
-    const double* Ds = D + s * NI;
+    const T* Ds = D + s * NI;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       z[i] += Ds[k[i]] * y[kp[i]];
@@ -91,39 +90,39 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
 // pass 2 from z.  The interior values never
 // leave LDS, and pass 2 re-reads the element's factors and map right after
 // pass 1, from cache.
-// PF / EOI: the Helmholtz body's factor prefetch depth and I-stage form
-// (two variants per order are compiled; setup times both).  ASM = false is
+// T: FP64, or FP32 (factors and an FP32 copy of the inverses) for the inner
+// iterations of the refined condensed solve.  PF / EOI: the Helmholtz
+// body's factor prefetch depth and I-stage form (two variants per order and
+// precision are compiled; setup times both).  ASM = false is
 // the elemental form S_e x_e on local vectors (local input with zero
 // interior entries, every local output stored), used to probe diag(S_e).
-template <int N, int Q, int EPB, int PF, bool EOI, bool ASM = true>
+template <typename T, int N, int Q, int EPB, int PF, bool EOI, bool ASM = true>
 __global__ void __launch_bounds__(EPB * slot_threads<Q>())
-    k_sc_fused(const Tab<double, N, Q> tb, const DevArgs<double> a, const double* __restrict__ A) {
+    k_sc_fused(const Tab<T, N, Q> tb, const DevArgs<T> a, const T* __restrict__ A) {
   constexpr int NT = slot_threads<Q>(), S = Q * Q * N, NI = (N - 2) * (N - 2) * (N - 2);
-  __shared__ double smem[EPB * 3 * S];
+  __shared__ T smem[EPB * 3 * S];
   __shared__ double red[NT != 64 ? EPB * NT : 1];
-  __shared__ double ib[EPB][2][NI];
+  __shared__ T ib[EPB][2][NI];
   const int slot = threadIdx.x / NT;
   const int t = threadIdx.x - slot * NT;
   const int64_t nblk = (a.nelem + EPB - 1) / EPB;
   const int64_t e = xcd_remap(blockIdx.x, nblk) * EPB + slot;
   bool live = e < a.nelem;
   if (live && seg_converged(a.elem_seg, a.seg_done, e)) live = false;
-  double* y = ib[slot][0];
-  double* z = ib[slot][1];
-  helm3_body<double, N, Q, NT, ASM, PF, EOI, 1>(tb, smem + slot * 3 * S, red, slot, t, live, e, a,
-                                                y);
+  T* y = ib[slot][0];
+  T* z = ib[slot][1];
+  helm3_body<T, N, Q, NT, ASM, PF, EOI, 1>(tb, smem + slot * 3 * S, red, slot, t, live, e, a, y);
   slot_sync<NT>();
   if (live) {
     constexpr int R = (NI + NT - 1) / NT;
-    double zr[R];
-    sc_symv_rows<NI, NT, R>(A + e * (int64_t)sc_packed(NI), y, t, zr);
+    T zr[R];
+    sc_symv_rows<T, NI, NT, R>(A + e * (int64_t)sc_packed(NI), y, t, zr);
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if (t + i * NT < NI) z[t + i * NT] = -zr[i];
   }
   slot_sync<NT>();
-  helm3_body<double, N, Q, NT, ASM, PF, EOI, 2>(tb, smem + slot * 3 * S, red, slot, t, live, e, a,
-                                                z);
+  helm3_body<T, N, Q, NT, ASM, PF, EOI, 2>(tb, smem + slot * 3 * S, red, slot, t, live, e, a, z);
 }
 
 template <int P, int PASS>
@@ -151,15 +150,15 @@ static hipError_t run_pass(const CondOp& c, const double* x, double* y, double* 
   return hipGetLastError();
 }
 
-template <int P, int PF, bool EOI, bool ASM = true>
-static hipError_t run_fused(const CondOp& c, const double* x, double* y, double* dots,
-                            const int32_t* dslot, const int32_t* seg_done, hipStream_t s) {
+template <typename T, int P, int PF, bool EOI, bool ASM = true>
+static hipError_t run_fused(const CondOp& c, const T* x, T* y, double* dots, const int32_t* dslot,
+                            const int32_t* seg_done, hipStream_t s) {
   constexpr int N = P + 1, Q = P + 2, EPB = kTileEPB3[P][0];
-  DevArgs<double> d{};
+  DevArgs<T> d{};
   d.nelem = c.nelem;
   d.in = x;
   d.out = y;
-  d.fac = c.fac;
+  d.fac = sizeof(T) == 8 ? (const T*)c.fac : (const T*)c.fac32;
   d.lam = c.lam;
   d.lam0 = c.lam0;
   d.l2g = c.l2g;
@@ -169,17 +168,20 @@ static hipError_t run_fused(const CondOp& c, const double* x, double* y, double*
   const int64_t nblk = (c.nelem + EPB - 1) / EPB;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   if (nblk == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_sc_fused<N, Q, EPB, PF, EOI, ASM>), dim3((unsigned)nblk),
-                     dim3(EPB * slot_threads<Q>()), 0, s, host_tab<double, N, Q>(), d, c.ainv);
+  const T* A = sizeof(T) == 8 ? (const T*)c.ainv : (const T*)c.ainv32;
+  hipLaunchKernelGGL((k_sc_fused<T, N, Q, EPB, PF, EOI, ASM>), dim3((unsigned)nblk),
+                     dim3(EPB * slot_threads<Q>()), 0, s, host_tab<T, N, Q>(), d, A);
   return hipGetLastError();
 }
 
-hipError_t sc_apply(const CondOp& c, const double* x, double* y, double* dots,
-                    const int32_t* dslot, const int32_t* seg_done, hipStream_t s) {
-#define NK_SC_FUSED(P)                                                      \
-  case P:                                                                   \
-    return c.variant == 0 ? run_fused<P, 2, true>(c, x, y, dots, dslot, seg_done, s) \
-                          : run_fused<P, 1, false>(c, x, y, dots, dslot, seg_done, s);
+template <typename T>
+static hipError_t sc_apply_t(const CondOp& c, const T* x, T* y, double* dots, const int32_t* dslot,
+                             const int32_t* seg_done, hipStream_t s) {
+  const int v = sizeof(T) == 8 ? c.variant : c.variant32;
+#define NK_SC_FUSED(P)                                                                  \
+  case P:                                                                               \
+    return v == 0 ? run_fused<T, P, 2, true>(c, x, y, dots, dslot, seg_done, s)         \
+                  : run_fused<T, P, 1, false>(c, x, y, dots, dslot, seg_done, s);
   switch (c.P) {
     NK_SC_FUSED(2)
     NK_SC_FUSED(3)
@@ -191,13 +193,21 @@ hipError_t sc_apply(const CondOp& c, const double* x, double* y, double* dots,
 #undef NK_SC_FUSED
 }
 
+hipError_t sc_apply(const CondOp& c, nk_dtype t, const void* x, void* y, double* dots,
+                    const int32_t* dslot, const int32_t* seg_done, hipStream_t s) {
+  if (t == NK_F64)
+    return sc_apply_t<double>(c, (const double*)x, (double*)y, dots, dslot, seg_done, s);
+  if (c.ainv32 == nullptr) return hipErrorInvalidValue;
+  return sc_apply_t<float>(c, (const float*)x, (float*)y, dots, dslot, seg_done, s);
+}
+
 hipError_t sc_local(const CondOp& c, const double* x, double* y, hipStream_t s) {
   switch (c.P) {
-    case 2: return run_fused<2, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
-    case 3: return run_fused<3, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
-    case 4: return run_fused<4, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
-    case 5: return run_fused<5, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
-    case 6: return run_fused<6, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 2: return run_fused<double, 2, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 3: return run_fused<double, 3, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 4: return run_fused<double, 4, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 5: return run_fused<double, 5, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
+    case 6: return run_fused<double, 6, 1, false, false>(c, x, y, nullptr, nullptr, nullptr, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -245,7 +255,7 @@ __global__ void __launch_bounds__(sc_threads(NI))
   __syncthreads();
   if (k < NI) {
     double zr[1];
-    sc_symv_rows<NI, sc_threads(NI), 1>(A + e * (int64_t)sc_packed(NI), ys, k, zr);
+    sc_symv_rows<double, NI, sc_threads(NI), 1>(A + e * (int64_t)sc_packed(NI), ys, k, zr);
     const double z = gamma * zr[0];
     if (xadd != nullptr)
       xadd[l2g_dof(ik)] += l2g_sign(ik, z);

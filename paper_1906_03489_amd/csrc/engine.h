@@ -612,7 +612,7 @@ __device__ __forceinline__ int sc_k(int t) {
 template <typename T, int N, int Q, int NT, bool ASM, int PF = 2, bool EOI = true, int SC = 0>
 __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict__ sm,
                                            double* red, int slot, int t, bool live, int64_t e,
-                                           const DevArgs<T>& a, double* scb = nullptr) {
+                                           const DevArgs<T>& a, T* scb = nullptr) {
   constexpr int NN = N * N, N3 = N * N * N, Q3 = Q * Q * Q, QQ = Q * Q;
   const int64_t ee = live ? e : 0;
   const bool pq = live && t < NN;
@@ -637,9 +637,9 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
       static_assert(N >= 3, "condensed pass");
       constexpr int NI2 = (N - 2) * (N - 2);
       if (sc_inner<N>(t)) {
-        const double* ti = scb + sc_k<N>(t);
+        const T* ti = scb + sc_k<N>(t);
 #pragma unroll
-        for (int r = 1; r < N - 1; ++r) xin[r] = (T)ti[(r - 1) * NI2];
+        for (int r = 1; r < N - 1; ++r) xin[r] = ti[(r - 1) * NI2];
       }
     }
   }
@@ -709,9 +709,9 @@ __device__ __forceinline__ void helm3_body(const Tab<T, N, Q>& tb, T* __restrict
     static_assert(N >= 3, "condensed pass");
     constexpr int NI2 = (N - 2) * (N - 2);
     if (pq && sc_inner<N>(t)) {
-      double* to = scb + sc_k<N>(t);
+      T* to = scb + sc_k<N>(t);
 #pragma unroll
-      for (int r = 1; r < N - 1; ++r) to[(r - 1) * NI2] = (double)yv[r];
+      for (int r = 1; r < N - 1; ++r) to[(r - 1) * NI2] = yv[r];
     }
   } else if constexpr (ASM) {
     double dp = 0.0;

@@ -113,14 +113,18 @@ struct CondOp {
   const double* ainv = nullptr;   // [E][NI/2 + 1][NI] interior inverses by diagonals, NI = (P-1)^3
   double* t = nullptr;            // [E][NI] interior values between the passes
   const double* fac = nullptr;    // FP64 geometric factors
+  const float* fac32 = nullptr;   // FP32 geometric factors
+  const float* ainv32 = nullptr;  // FP32 copy of ainv (null until a refined condensed solve needs it)
   const double* lam = nullptr;
   double lam0 = 0.0;
   const int32_t* l2g = nullptr;   // internal map of the boundary system
   int variant = 0;                // fused kernel: 0 paired I stage, two factor sets; 1 point by
                                   // point, one set (fewer registers)
+  int variant32 = 0;              // the same for the FP32 kernel
 };
 // y += S x (boundary numbering) in one fused launch, element energies into dots
-hipError_t sc_apply(const CondOp& c, const double* x, double* y, double* dots,
+// (FP32 needs ainv32)
+hipError_t sc_apply(const CondOp& c, nk_dtype t, const void* x, void* y, double* dots,
                     const int32_t* dslot, const int32_t* seg_done, hipStream_t s);
 // pass 1: t = interior part of H [x_b; 0]; pass 2: y += boundary part of
 // H [x_b; t], element energies into dots
@@ -156,6 +160,7 @@ struct CondData {
   int32_t* bmap = nullptr;        // [nb] full DOF of each boundary DOF
   int32_t* iidx = nullptr;        // [E][NI] full DOF | sign bit of each interior mode
   double* ainv = nullptr;
+  float* ainv32 = nullptr;
   double* t = nullptr;
   double* zero = nullptr;         // boundary-length zeros
 };

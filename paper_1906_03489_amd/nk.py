@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnk.so")
 
 NK_OK, NK_EINVAL, NK_ENOMEM, NK_EDEVICE, NK_EHIP, NK_ENOCONV, NK_EBREAKDOWN, NK_EUNSUPPORTED = range(8)
 F64, F32 = 0, 1
-SOLVE_F64, SOLVE_F32_REFINED, SOLVE_CONDENSED = 0, 1, 2
+SOLVE_F64, SOLVE_F32_REFINED, SOLVE_CONDENSED, SOLVE_CONDENSED_F32_REFINED = 0, 1, 2, 3
 OP_BWD, OP_IPROD, OP_HELM, OP_HELM_ASM = 0, 1, 2, 3
 STATUS_NAMES = {0: "NK_OK", 1: "NK_EINVAL", 2: "NK_ENOMEM", 3: "NK_EDEVICE", 4: "NK_EHIP",
                 5: "NK_ENOCONV", 6: "NK_EBREAKDOWN", 7: "NK_EUNSUPPORTED"}

@@ -3,8 +3,9 @@ the Jacobi preconditioner diag(S), the condensed operator S x_B against the orac
 complements (FP64 <= 1e-12: the interior blocks have condition numbers below
 40 up to P = 6, so the dense inverse adds no more than the assembled
 operator's rounding), the condensed solve against the oracle's direct solve
-(true residual <= rtol recomputed by the oracle), fewer CG iterations than
-the full system, and the error paths."""
+(true residual <= rtol recomputed by the oracle), the FP32-refined condensed
+solve to an FP64 residual <= 1e-10, fewer CG iterations than the full
+system, and the error paths."""
 import numpy as np
 import pytest
 
@@ -77,6 +78,28 @@ def test_condensed_solve_matches_direct_solve(P, shape, signed):
     # the condensed oracle agrees with the direct one (same x)
     xo = oracle.condensed_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b, 3, P, c["sign"])
     assert rel_err(xs, xo) < 1e-8
+
+
+@pytest.mark.parametrize("P,shape,signed", [(3, (3, 3, 2), True), (6, (2, 2, 3), False)])
+def test_condensed_f32_refined_true_residual(P, shape, signed):
+    """NK_SOLVE_CONDENSED_F32_REFINED: the boundary system in FP32 (FP32
+    factors and inverses) with FP64 reliable updates; the FP64 residual of the
+    returned x, recomputed by the oracle, is <= 1e-10, and x agrees with the
+    direct solve to cond(A) 1e-10."""
+    torch_cuda()
+    m = nk()
+    c = _case(shape, P, signed, lam_seed=8)
+    b = W.uniform(W.seed(0, 75) + P, c["ng"])
+    b[c["dm"].astype(bool)] = 0.0
+    x, info = c["sysm"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_CONDENSED_F32_REFINED)
+    xs = x.cpu().numpy()
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"], c["sign"])
+    assert_true_residual(info[0], 1e-10, A, c["mats"], c["l2g"], c["ng"], c["dm"], xs, b, f"P={P}")
+    xref = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b, c["sign"])
+    assert rel_err(xs, xref) < 1e-5
+    # the FP64 condensed solve of the same system after the FP32 one
+    x64, info64 = c["sysm"].solve(to_dev(b), rtol=1e-10, maxit=20000, mode=m.SOLVE_CONDENSED)
+    assert info64[0]["status"] == 0 and rel_err(x64.cpu().numpy(), xref) < 1e-5
 
 
 def test_condensed_solve_takes_fewer_iterations():
@@ -157,11 +180,14 @@ def test_full_size_24c_condensed_solve_sampled_residuals(P):
     b[fixed] = 0.0
     xc, info = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000, mode=m.SOLVE_CONDENSED)
     assert info[0]["status"] == 0 and info[0]["rel_resid"] <= 1e-10
+    xr, infor = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000, mode=m.SOLVE_CONDENSED_F32_REFINED)
+    assert infor[0]["status"] == 0 and infor[0]["rel_resid"] <= 1e-10
     xf, infof = sysm.solve(to_dev(b), rtol=1e-10, maxit=50000)
     assert info[0]["iters"] < infof[0]["iters"]
     xs = xc.cpu().numpy().copy()
     xs[fixed] = 0.0
     assert rel_err(xs, xf.cpu().numpy()) < 1e-5
+    assert rel_err(xr.cpu().numpy(), xf.cpu().numpy()) < 1e-5
     G = [s * P + 1 for s in shape]
     free = np.flatnonzero(~fixed)
     gx, gy, gz = free % G[0], (free // G[0]) % G[1], free // (G[0] * G[1])
@@ -175,8 +201,11 @@ def test_full_size_24c_condensed_solve_sampled_residuals(P):
     pos = {int(e): k for k, e in enumerate(elems)}
     Jo = W.element_jacobians(oracle.gll(Q)[0], W.Lattice(lat.shape, lat.h, lat.origins[elems]), W.WARP_AMPLITUDE)
     ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0)
-    y = ops.helmholtz_action(xs[l2g[elems]])
     bn = np.linalg.norm(b)
-    for g, h in hits.items():
-        Ag = sum(y[pos[int(e)], mm] for e, mm in h)
-        assert abs(b[g] - Ag) <= 1e-10 * bn, (g, abs(b[g] - Ag) / bn)
+    for xv, tag in ((xs, "condensed"), (xr.cpu().numpy(), "condensed f32-refined")):
+        xv = xv.copy()
+        xv[fixed] = 0.0
+        y = ops.helmholtz_action(xv[l2g[elems]])
+        for g, h in hits.items():
+            Ag = sum(y[pos[int(e)], mm] for e, mm in h)
+            assert abs(b[g] - Ag) <= 1e-10 * bn, (tag, g, abs(b[g] - Ag) / bn)
