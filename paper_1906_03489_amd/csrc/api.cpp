@@ -1983,8 +1983,7 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
         (e = sc_column(P, E, yl, afull, k, st)))
       return bail_tmp(e);
   }
-  if ((e = sc_invert(P, E, afull, d_bad, st)) || (e = sc_pack(P, E, afull, c->ainv, st)))
-    return bail_tmp(e);
+  if ((e = sc_invert(P, E, afull, c->ainv, d_bad, st))) return bail_tmp(e);
   int bad = 0;
   if ((e = hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, st)) ||
       (e = hipStreamSynchronize(st)))

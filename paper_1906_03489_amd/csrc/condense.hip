@@ -14,9 +14,9 @@
 //   pass 2  gather the boundary values again with the interior inputs taken
 //           from z, Helmholtz, scatter-add the boundary outputs
 //           (H_bb x_b + H_bi z = S_e x_b) and the element energies.
-// The dense inverses are formed once: H_ii column by column from the local
-// Helmholtz kernel applied to interior unit vectors, then inverted in place
-// by Gauss-Jordan elimination (H_ii is symmetric positive definite, so no
+// The dense inverses are formed once: H_ii row by row from the local
+// Helmholtz kernel applied to interior unit vectors, then inverted by
+// Gauss-Jordan elimination in LDS (H_ii is symmetric positive definite, so no
 // pivoting is needed).
 #include "engine.h"
 #include "system.h"
@@ -356,18 +356,27 @@ __global__ void k_sc_column(int P, int64_t nelem, const double* __restrict__ y,
   }
 }
 
-// In-place Gauss-Jordan inversion of each element's NI x NI block (one block
-// of threads per element, the matrix in global memory).  A pivot that is not
-// positive sets *bad.
+// Gauss-Jordan inversion of each element's NI x NI block H_ii (one block of
+// sc_inv_threads threads per element, the matrix in LDS: at most 125 x 125 doubles, within
+// gfx950's 160 KB per workgroup), written out in the diagonal storage of
+// sc_symv_rows.  H_ii is symmetric positive definite, so no pivoting is
+// needed; a pivot that is not positive sets *bad.
+// Threads per element: the elimination steps are latency-bound, and with
+// the largest blocks one workgroup fills the CU's LDS, so it brings its own
+// waves.
+constexpr int sc_inv_threads(int ni) { return ni >= 64 ? 1024 : 256; }
+
 template <int NI>
-__global__ void __launch_bounds__(256) k_sc_invert(double* __restrict__ A, int* __restrict__ bad) {
+__global__ void __launch_bounds__(sc_inv_threads(NI))
+    k_sc_invert(const double* __restrict__ A, double* __restrict__ D, int* __restrict__ bad) {
+  __shared__ double M[NI * NI];
   __shared__ double rowk[NI], colk[NI];
-  double* M = A + (int64_t)blockIdx.x * (NI * NI);
+  const double* Ae = A + (int64_t)blockIdx.x * (NI * NI);
+  for (int i = threadIdx.x; i < NI * NI; i += blockDim.x) M[i] = Ae[i];
+  __syncthreads();
   for (int kk = 0; kk < NI; ++kk) {
     const double piv = M[kk * NI + kk];
-    if (!(piv > 0.0)) {
-      if (threadIdx.x == 0) atomicOr(bad, 1);
-    }
+    if (!(piv > 0.0) && threadIdx.x == 0) atomicOr(bad, 1);
     const double ip = 1.0 / piv;
     for (int j = threadIdx.x; j < NI; j += blockDim.x) {
       rowk[j] = j == kk ? ip : M[kk * NI + j] * ip;
@@ -376,29 +385,15 @@ __global__ void __launch_bounds__(256) k_sc_invert(double* __restrict__ A, int* 
     __syncthreads();
     for (int idx = threadIdx.x; idx < NI * NI; idx += blockDim.x) {
       const int i = idx / NI, j = idx - i * NI;
-      double v;
-      if (i == kk)
-        v = rowk[j];
-      else if (j == kk)
-        v = -colk[i] * ip;
-      else
-        v = M[idx] - colk[i] * rowk[j];
-      M[idx] = v;
+      M[idx] = i == kk ? rowk[j] : j == kk ? -colk[i] * ip : M[idx] - colk[i] * rowk[j];
     }
     __syncthreads();
   }
-}
-
-// Diagonal storage of each element's inverse (see sc_symv_row).
-__global__ void k_sc_pack(int ni, int64_t nelem, const double* __restrict__ A,
-                          double* __restrict__ D) {
-  const int64_t per = (int64_t)(ni / 2 + 1) * ni, total = nelem * per;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = idx / per;
-    const int r = (int)(idx - e * per), sd = r / ni, k = r - sd * ni;
-    const int j = k + sd < ni ? k + sd : k + sd - ni;
-    D[idx] = A[(e * ni + k) * ni + j];
+  double* De = D + (int64_t)blockIdx.x * sc_packed(NI);
+  for (int idx = threadIdx.x; idx < sc_packed(NI); idx += blockDim.x) {
+    const int sd = idx / NI, k = idx - sd * NI;
+    const int j = k + sd < NI ? k + sd : k + sd - NI;
+    De[idx] = M[k * NI + j];
   }
 }
 
@@ -439,24 +434,23 @@ hipError_t sc_column(int P, int64_t nelem, const double* y, double* A, int k, hi
   return hipGetLastError();
 }
 
-hipError_t sc_pack(int P, int64_t nelem, const double* A, double* D, hipStream_t s) {
-  hipLaunchKernelGGL(k_sc_pack, dim3(grid_for(nelem * sc_packed(sc_ni(P)))), dim3(256), 0, s,
-                     sc_ni(P), nelem, A, D);
-  return hipGetLastError();
-}
-
-hipError_t sc_invert(int P, int64_t nelem, double* A, int* bad, hipStream_t s) {
+hipError_t sc_invert(int P, int64_t nelem, const double* A, double* D, int* bad, hipStream_t s) {
   if (nelem > 0x7fffffff) return hipErrorInvalidValue;
   if (nelem == 0) return hipSuccess;
-  const dim3 g((unsigned)nelem), b(256);
+  const dim3 g((unsigned)nelem);
+#define NK_SC_INV(P)                                                                    \
+  case P:                                                                               \
+    hipLaunchKernelGGL(k_sc_invert<sc_ni(P)>, g, dim3(sc_inv_threads(sc_ni(P))), 0, s, A, D, bad); \
+    break;
   switch (P) {
-    case 2: hipLaunchKernelGGL(k_sc_invert<sc_ni(2)>, g, b, 0, s, A, bad); break;
-    case 3: hipLaunchKernelGGL(k_sc_invert<sc_ni(3)>, g, b, 0, s, A, bad); break;
-    case 4: hipLaunchKernelGGL(k_sc_invert<sc_ni(4)>, g, b, 0, s, A, bad); break;
-    case 5: hipLaunchKernelGGL(k_sc_invert<sc_ni(5)>, g, b, 0, s, A, bad); break;
-    case 6: hipLaunchKernelGGL(k_sc_invert<sc_ni(6)>, g, b, 0, s, A, bad); break;
+    NK_SC_INV(2)
+    NK_SC_INV(3)
+    NK_SC_INV(4)
+    NK_SC_INV(5)
+    NK_SC_INV(6)
     default: return hipErrorInvalidValue;
   }
+#undef NK_SC_INV
   return hipGetLastError();
 }
 

@@ -143,9 +143,8 @@ hipError_t sc_diag_add(int P, int64_t nelem, const double* y, int m, const int32
 hipError_t sc_dinv(int64_t n, const double* diag, double* dinv64, float* dinv32, double* diag_out,
                    hipStream_t s);
 hipError_t sc_column(int P, int64_t nelem, const double* y, double* A, int k, hipStream_t s);
-hipError_t sc_invert(int P, int64_t nelem, double* A, int* bad, hipStream_t s);
-// D = diagonal storage of the full inverses A ([E][NI][NI])
-hipError_t sc_pack(int P, int64_t nelem, const double* A, double* D, hipStream_t s);
+// D = diagonal storage of the inverses of the blocks A ([E][NI][NI])
+hipError_t sc_invert(int P, int64_t nelem, const double* A, double* D, int* bad, hipStream_t s);
 hipError_t sc_restrict(int64_t nb, int64_t npad, const int32_t* bmap, const double* full,
                        const double* dinv_c, double* cond, hipStream_t s);
 hipError_t sc_expand_add(int64_t nb, const int32_t* bmap, const double* cond, double* full,
