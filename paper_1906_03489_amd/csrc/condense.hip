@@ -88,8 +88,8 @@ __global__ void __launch_bounds__(EPB * slot_threads<Q>())
 // pass 1 into the slot's LDS block y, z = -H_ii^{-1} y (the slot's threads
 // take the rows k = t, t + NT, ...; the inverse in its diagonal storage),
 // pass 2 from z.  The interior values never
-// leave LDS, and pass 2 re-reads the element's factors and map right after
-// pass 1, from cache.
+// leave LDS; pass 2 re-reads the element's factors and map right after
+// pass 1.
 // T: FP64, or FP32 (factors and an FP32 copy of the inverses) for the inner
 // iterations of the refined condensed solve.  PF / EOI: the Helmholtz
 // body's factor prefetch depth and I-stage form (two variants per order and
