@@ -19,16 +19,17 @@ from gpu_common import (FP64_RTOL, assert_close, assert_true_residual, jacobians
 pytestmark = pytest.mark.gpu
 
 
-def _case(shape, P, signed=False, lam_seed=None):
+def _case(shape, P, signed=False, lam_seed=None, kappa_seed=None):
     Q = P + 2
     Jg, Jo, lat = jacobians(shape, P, W.WARP_AMPLITUDE)
     E = lat.nelem
     lam = None if lam_seed is None else np.random.default_rng(lam_seed).uniform(0.5, 2.0, E)
-    ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0 if lam is None else lam)
+    kap = None if kappa_seed is None else W.uniform(kappa_seed, (E, Q ** 3), 0.5, 2.0)
+    ops = oracle.ElementOps(3, P, Q, Jo, kappa=kap, lam=1.0 if lam is None else lam)
     l2g, ng, dm = W.lattice_l2g(shape, P)
     sign = W.dof_signs(W.seed(0, 70) + P, l2g, ng) if signed else None
     m = nk()
-    space = m.Space.create(3, P, Q, to_dev(Jg))
+    space = m.Space.create(3, P, Q, to_dev(Jg), kappa=to_dev(kap) if kap is not None else None)
     sysm = m.System.create(space, ng, to_dev(l2g), to_dev(dm),
                            lam=to_dev(lam) if lam is not None else None, lam0=1.0,
                            sign=to_dev(sign) if signed else None)
@@ -58,14 +59,15 @@ def test_condensed_operator_matches_oracle(P, shape, signed, lam):
     del torch
 
 
-@pytest.mark.parametrize("P,shape,signed", [(2, (3, 3, 2), False), (4, (3, 2, 2), True),
-                                            (6, (2, 2, 2), False)])
-def test_condensed_solve_matches_direct_solve(P, shape, signed):
+@pytest.mark.parametrize("P,shape,signed,kappa", [(2, (3, 3, 2), False, None), (4, (3, 2, 2), True, None),
+                                                  (6, (2, 2, 2), False, None), (5, (2, 3, 2), True, 12)])
+def test_condensed_solve_matches_direct_solve(P, shape, signed, kappa):
     """NK_SOLVE_CONDENSED to 1e-12: the oracle's residual of the returned x,
-    and x against the oracle's sparse direct solve (error <= cond(A) rtol)."""
+    and x against the oracle's sparse direct solve (error <= cond(A) rtol);
+    the last case has a per-point diffusion coefficient kappa in [0.5, 2]."""
     torch_cuda()
     m = nk()
-    c = _case(shape, P, signed, lam_seed=7)
+    c = _case(shape, P, signed, lam_seed=7, kappa_seed=kappa)
     b = W.uniform(W.seed(0, 72) + P, c["ng"])
     b[c["dm"].astype(bool)] = 0.0
     x, info = c["sysm"].solve(to_dev(b), rtol=1e-12, maxit=20000, mode=m.SOLVE_CONDENSED)
