@@ -944,7 +944,7 @@ def _blas_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(W, budget_s=8.0, apply_s=5.0):
+def cpu_baseline(W, budget_s=5.0, apply_s=3.0):
     """The plain FP64 oracle on a bounded sample of the 32^3, P=6 workload:
     (1) dense elemental matrices built and applied (the headline value);
     (2) apply only: 256 prebuilt H_e applied as one batched matmul."""
@@ -989,12 +989,15 @@ def cpu_baseline(W, budget_s=8.0, apply_s=5.0):
                                      f"{reps} times in {da:.1f} s"}}
 
 
-def cpu_oracle_pcg(W, P=4, shape=(24, 24, 24), rtol=1e-10):
+def cpu_oracle_pcg(W, P=4, shape=(24, 24, 24), rtol=1e-10, maxit=None, iters_ref=None):
     """The oracle's Jacobi PCG on the 24^3 curved-hex problem of the GPU's
     CG section (same right-hand side construction: weak form of the
     manufactured sine), as the oracle stands: prebuilt dense H_e applied by
-    its masked operator.  Time to solution on the host's cores; minutes of
-    CPU work, so it runs only when asked for."""
+    its masked operator.  Time to solution on the host's cores (about a
+    minute of CPU work).  With maxit, a bounded sample: the setup and maxit
+    iterations are timed, and the time to solution is the setup plus
+    iters_ref (the iteration count of the same textbook PCG to rtol, e.g. the
+    GPU's FP64 count for this problem) times the measured iteration."""
     import oracle
     from oracle.assembly import MaskedOperator, jacobi_diagonal
     threads = _blas_threads()
@@ -1021,11 +1024,19 @@ def cpu_oracle_pcg(W, P=4, shape=(24, 24, 24), rtol=1e-10):
             log(f"oracle pcg: {calls[0]} operator applications, {time.perf_counter() - t1:.0f} s")
         return A(v)
     t1 = time.perf_counter()
-    x, its, res = oracle.pcg(apply, b, diag, rtol=rtol)
+    x, its, res = oracle.pcg(apply, b, diag, rtol=rtol, maxit=maxit if maxit else 100000)
     t_solve = time.perf_counter() - t1
-    return {"P": P, "nglobal": int(ng), "nelem": int(lat.nelem), "iters": int(its), "rel_resid": float(res),
-            "setup_s": round(t_setup, 2), "solve_s": round(t_solve, 2),
-            "s_per_iter": round(t_solve / max(its, 1), 4), "cores": threads}
+    out = {"P": P, "nglobal": int(ng), "nelem": int(lat.nelem), "iters": int(its), "rel_resid": float(res),
+           "setup_s": round(t_setup, 2), "solve_s": round(t_solve, 2),
+           "s_per_iter": round(t_solve / max(its, 1), 4), "cores": threads}
+    if maxit:
+        out["sample"] = f"setup and the first {its} of the PCG iterations timed"
+        if iters_ref:
+            out["time_to_solution_s"] = round(t_setup + iters_ref * t_solve / max(its, 1), 1)
+            out["iters_to_solution"] = int(iters_ref)
+            out["sample"] += (f"; time to solution = setup + {iters_ref} iterations (the GPU FP64 "
+                              f"PCG's count for the same problem and rtol)")
+    return out
 
 
 # --------------------------------------------------------------------- main
@@ -1167,6 +1178,11 @@ def main():
     if "cpu" in secs:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(W)
+        if "cpu_pcg" not in secs:
+            # bounded sample of the oracle's PCG on the 24^3 P=4 problem
+            ref = sections.get("cg_24c", {}).get("P4", {}).get("f64", {}).get("iters")
+            log("cpu oracle PCG, 24^3 P=4 (setup and 30 iterations) ...")
+            result["cpu_baseline"]["pcg_24c_P4"] = cpu_oracle_pcg(W, maxit=30, iters_ref=ref)
     if "cpu_pcg" in secs:
         log("cpu oracle PCG, 24^3 P=4 (minutes) ...")
         result.setdefault("cpu_baseline", {})["pcg_24c_P4"] = cpu_oracle_pcg(W)
