@@ -5,7 +5,8 @@ element's modes split into boundary modes (a vertex mode 0 or P in at least
 one direction) and interior modes (a bubble in every direction); the interior
 modes of an element belong to that element alone, so the assembled system can
 be condensed onto the elemental boundary degrees of freedom and the interior
-unknowns recovered element by element afterwards.
+unknowns recovered element by element afterwards.  With spatially variable
+order (section 4.2) each element has its own (P_e - 1)^dim interior modes.
 
 With the elemental matrix partitioned into boundary (b) and interior (i)
 blocks,
@@ -60,39 +61,45 @@ def schur_complement(H, interior):
 
 class Condensed:
     """The condensed boundary system of an assembled hexahedral (dim = 3) or
-    quadrilateral (dim = 2) C0 system at one order P.
+    quadrilateral (dim = 2) C0 system, at one order P or with per-element
+    orders (l2g a list of per-element maps of lengths (P_e + 1)^dim; P is
+    then ignored and each element's order follows from its map).
 
     bdofs: sorted global DOFs referenced by boundary modes; S (sparse, over
     bdofs, Dirichlet rows and columns kept); the per-element blocks and maps."""
 
     def __init__(self, mats, l2g, nglobal, dirichlet, dim, P, sign=None):
-        l2g = np.asarray(l2g, np.int64)
-        E = l2g.shape[0]
-        self.dim, self.P, self.nglobal = dim, P, int(nglobal)
-        self.interior = interior_modes(dim, P)
-        sgn = np.ones(l2g.shape) if sign is None else np.asarray(sign, np.float64)
+        E = len(l2g)
+        maps = [np.asarray(l2g[e], np.int64).ravel() for e in range(E)]
+        signs = [np.ones(m.size) if sign is None else np.asarray(sign[e], np.float64).ravel()
+                 for e, m in enumerate(maps)]
+        self.dim, self.nglobal = dim, int(nglobal)
+        orders = [int(round(m.size ** (1.0 / dim))) - 1 for m in maps]
+        self.P = P if len(set(orders)) > 1 else orders[0]
+        masks = {q: interior_modes(dim, q) for q in set(orders)}
+        self.inner = [masks[q] for q in orders]
         self.dirichlet = np.asarray(dirichlet, bool)
-        ig = l2g[:, self.interior]
-        bg = l2g[:, ~self.interior]
-        counts = np.bincount(l2g.ravel(), minlength=self.nglobal)
-        if ig.size and (np.any(counts[ig.ravel()] != 1) or np.any(self.dirichlet[ig.ravel()])):
+        allg = np.concatenate(maps)
+        counts = np.bincount(allg, minlength=self.nglobal)
+        ig = np.concatenate([m[k] for m, k in zip(maps, self.inner)])
+        if ig.size and (np.any(counts[ig] != 1) or np.any(self.dirichlet[ig])):
             raise ValueError("an interior mode's DOF is shared or Dirichlet: not condensable")
-        self.bdofs = np.unique(bg.ravel())
+        self.bdofs = np.unique(np.concatenate([m[~k] for m, k in zip(maps, self.inner)]))
         pos = -np.ones(self.nglobal, np.int64)
         pos[self.bdofs] = np.arange(self.bdofs.size)
-        self.bpos = pos[bg]                       # [E, nb_loc] boundary index of each mode
-        self.bsign = sgn[:, ~self.interior]
-        self.isign = sgn[:, self.interior]
-        self.idofs = ig                           # [E, ni] global DOF of each interior mode
-        self.blocks = [element_blocks(H, self.interior) for H in mats]
+        self.bpos = [pos[m[~k]] for m, k in zip(maps, self.inner)]
+        self.bsign = [sg[~k] for sg, k in zip(signs, self.inner)]
+        self.isign = [sg[k] for sg, k in zip(signs, self.inner)]
+        self.idofs = [m[k] for m, k in zip(maps, self.inner)]
+        self.blocks = [element_blocks(H, k) for H, k in zip(mats, self.inner)]
         nb = self.bdofs.size
         rows, cols, vals = [], [], []
         for e in range(E):
-            Se = schur_complement(mats[e], self.interior)
-            s = self.bsign[e]
-            rows.append(np.repeat(self.bpos[e], s.size))
-            cols.append(np.tile(self.bpos[e], s.size))
-            vals.append((s[:, None] * Se * s[None, :]).ravel())
+            Se = schur_complement(mats[e], self.inner[e])
+            sg = self.bsign[e]
+            rows.append(np.repeat(self.bpos[e], sg.size))
+            cols.append(np.tile(self.bpos[e], sg.size))
+            vals.append((sg[:, None] * Se * sg[None, :]).ravel())
         self.S = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                                shape=(nb, nb))
         self.bfree = ~self.dirichlet[self.bdofs]
@@ -121,6 +128,7 @@ class Condensed:
         xb = np.where(self.bfree, np.asarray(xb, np.float64), 0.0)
         x = np.zeros(self.nglobal)
         x[self.bdofs] = xb
+        x[self.dirichlet] = 0.0
         for e, (Hbb, Hbi, Hib, Hii) in enumerate(self.blocks):
             if Hii.shape[0] == 0:
                 continue

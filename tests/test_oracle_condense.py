@@ -110,3 +110,25 @@ def test_shared_interior_dof_is_rejected():
     bad[1, m] = bad[0, m]
     with pytest.raises(ValueError):
         Condensed(mats, bad, ng, dm, 3, 2)
+
+
+def test_variable_order_condensation_equals_direct_solve_and_global_schur():
+    """Section 4.2's spatially variable order (minimum-rule map, orders 2..6):
+    the per-element condensation reproduces the direct solve, and its S is
+    the assembled matrix's Schur complement onto the boundary DOFs."""
+    from test_oracle import _varp_problem
+    shape = (3, 2, 2)
+    orders = [2, 5, 3, 4, 2, 6, 3, 3, 5, 2, 4, 6]
+    perm, l2g, ng, dm, groups, mats = _varp_problem(shape, orders)
+    c = Condensed(mats, l2g, ng, dm, 3, None)
+    inner = np.concatenate([np.asarray(g)[interior_modes(3, int(round(len(g) ** (1 / 3))) - 1)]
+                            for g in l2g])
+    assert c.bdofs.size == ng - inner.size
+    B, Sg = global_schur(mats, l2g, ng, inner)
+    np.testing.assert_array_equal(B, c.bdofs)
+    assert np.abs(c.S.toarray() - Sg).max() <= 1e-12 * np.abs(Sg).max()
+    b = W.uniform(21, ng)
+    b[dm.astype(bool)] = 0
+    xd = direct_solve(mats, l2g, ng, dm, b)
+    xc = c.solve(b)
+    assert np.abs(xc - xd).max() <= 1e-11 * np.abs(xd).max()
