@@ -376,7 +376,8 @@ nk_status nk_system_diagonal(nk_system sys, double* diag, void* stream);
  * system solved as NK_SOLVE_F32_REFINED solves (FP32 condensed operator from
  * an FP32 copy of the interior inverses, made on first use, with FP64
  * reliable updates; iters: FP32 boundary iterations).  Both: one-system
- * hexahedral systems with 2 <= P <= 6 only (NK_EUNSUPPORTED otherwise).  Iterations run as captured HIP graphs that
+ * hexahedral systems (uniform or variable order) with every 2 <= P <= 6 only
+ * (NK_EUNSUPPORTED otherwise).  Iterations run as captured HIP graphs that
  * do not depend on rtol or maxit.  info (host, may be NULL) receives one
  * entry per system (nsys entries for a batched system).  Returns NK_ENOCONV
  * (budget spent with the true residual above rtol) or NK_EBREAKDOWN if any
@@ -396,8 +397,10 @@ nk_status nk_cg_solve(nk_system sys, nk_solve_mode mode, const double* b, double
  * [nboundary], may be NULL) receives the global DOF of each boundary DOF, in
  * increasing order; bdiag (device FP64 [nboundary], may be NULL) the
  * diagonal of S that preconditions the condensed solve (1 on Dirichlet
- * DOFs).  Requires a one-system system on a uniform-order
- * hexahedral space, 2 <= P <= 6, Q = P + 2 (else NK_EUNSUPPORTED), and a map
+ * DOFs).  Requires a one-system system on a hexahedral space, uniform or
+ * variable order (section 4.2: each order group has its own interior modes
+ * and inverses), every order 2 <= P <= 6 with Q = P + 2 (else
+ * NK_EUNSUPPORTED), and a map
  * whose interior modes each reference a DOF no other mode references and that
  * is not Dirichlet (else NK_EUNSUPPORTED).  Synchronises the stream. */
 nk_status nk_system_condense(nk_system sys, int64_t* nboundary, int32_t* bmap, double* bdiag,

@@ -1125,10 +1125,9 @@ nk_status nk_system_destroy(nk_system sys) {
 static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, void* out,
                                double* dots, const int32_t* seg_done, int tile, hipStream_t st) {
   nk_space s = y->space;
-  if (y->sc) {   // boundary system of a static condensation (one hexahedral group)
-    if (g != 0) return hipErrorInvalidValue;
-    return sc_apply(*y->sc, t, x, out, dots, dots ? y->dslot : nullptr, seg_done, st);
-  }
+  if (y->sc)   // boundary system of a static condensation (hexahedral order groups)
+    return sc_apply(y->sc[g], t, x, out, dots, dots ? y->dslot + s->groups[g].e0 : nullptr,
+                    seg_done, st);
   const Group& G = s->groups[g];
   OpArgs a;
   a.op = OP_HELM_ASM;
@@ -1793,23 +1792,24 @@ static void cond_free(CondData*& c) {
 static nk_status cond_check(nk_system y) {
   nk_space s = y->space;
   if (y->nsys != 1) return fail(NK_EUNSUPPORTED, "static condensation takes a one-system (not batched) system");
-  if (s->shape != 0 || s->dim != 3 || s->groups.size() != 1)
-    return fail(NK_EUNSUPPORTED, "static condensation is built for uniform-order hexahedral spaces");
-  const Group& G = s->groups[0];
-  if (G.P < kCondMinP || G.P > kCondMaxP || G.Q != G.P + 2)
-    return fail(NK_EUNSUPPORTED, "static condensation is built for 2 <= P <= 6 with Q = P + 2");
+  if (s->shape != 0 || s->dim != 3)
+    return fail(NK_EUNSUPPORTED, "static condensation is built for hexahedral spaces");
+  for (const Group& G : s->groups)
+    if (G.P < kCondMinP || G.P > kCondMaxP || G.Q != G.P + 2)
+      return fail(NK_EUNSUPPORTED, "static condensation is built for 2 <= P <= 6 with Q = P + 2");
   return NK_OK;
 }
 
 // Time the two fused-kernel variants of one precision on the boundary
 // system (five launches each, after a warm-up) and keep the faster.  The
 // timing runs write into the boundary system's work vectors, cleared after.
-static hipError_t cond_pick_variant(CondData* c, nk_dtype t, hipStream_t st) {
+static hipError_t cond_pick_variant(CondData* c, int g, nk_dtype t, hipStream_t st) {
   nk_system z = c->bsys;
+  CondOp& op = c->ops[g];
   const int64_t np = z->L.npad;
   void* in = t == NK_F64 ? (void*)c->zero : (void*)z->s32;
   void* out = t == NK_F64 ? (void*)z->y : (void*)z->y32;
-  int& var = t == NK_F64 ? c->op.variant : c->op.variant32;
+  int& var = t == NK_F64 ? op.variant : op.variant32;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
   if (t == NK_F32 && (e = vec_fill<float>(z->s32, np, 0.f, st))) return e;
@@ -1822,10 +1822,10 @@ static hipError_t cond_pick_variant(CondData* c, nk_dtype t, hipStream_t st) {
   int pick = 0;
   for (int v = 0; v < 2 && e == hipSuccess; ++v) {
     var = v;
-    e = sc_apply(c->op, t, in, out, nullptr, nullptr, nullptr, st);   // warm-up
+    e = sc_apply(op, t, in, out, nullptr, nullptr, nullptr, st);   // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     for (int r = 0; r < 5 && e == hipSuccess; ++r)
-      e = sc_apply(c->op, t, in, out, nullptr, nullptr, nullptr, st);
+      e = sc_apply(op, t, in, out, nullptr, nullptr, nullptr, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1848,49 +1848,76 @@ static hipError_t cond_pick_variant(CondData* c, nk_dtype t, hipStream_t st) {
 // condensed solve of a system).
 static nk_status cond_build_f32(CondData* c, hipStream_t st) {
   if (c->ainv32) return NK_OK;
-  const int ni = (c->op.P - 1) * (c->op.P - 1) * (c->op.P - 1);
-  const int64_t n = std::max<int64_t>(c->op.nelem * sc_packed(ni), 1);
+  int64_t n = 0;
+  for (const CondOp& op : c->ops) {
+    const int ni = (op.P - 1) * (op.P - 1) * (op.P - 1);
+    n += op.nelem * sc_packed(ni);
+  }
+  n = std::max<int64_t>(n, 1);
   hipError_t e;
   if ((e = dmalloc(&c->ainv32, n))) return hip_fail(e, "hipMalloc");
   if ((e = cast_copy(c->ainv, c->ainv32, n, st)) || (e = hipStreamSynchronize(st))) {
     dfree(c->ainv32);
     return hip_fail(e, "condensation setup");
   }
-  c->op.ainv32 = c->ainv32;
-  if ((e = cond_pick_variant(c, NK_F32, st))) return hip_fail(e, "condensation setup");
+  for (CondOp& op : c->ops) op.ainv32 = c->ainv32 + (op.ainv - c->ainv);
+  for (size_t g = 0; g < c->ops.size(); ++g)
+    if ((e = cond_pick_variant(c, (int)g, NK_F32, st))) return hip_fail(e, "condensation setup");
   return NK_OK;
 }
 
-// Build the boundary system and the interior inverses of y (once).
+// Build the boundary system and the interior inverses of y (once).  Each
+// order group of the space has its own interior modes, inverses and fused
+// kernel; the boundary numbering is global.
 static nk_status cond_build(nk_system y, hipStream_t st) {
   if (y->cond) return NK_OK;
   NK_CHECK(cond_check(y));
   nk_space s = y->space;
-  const Group& G = s->groups[0];
-  const int P = G.P, n = P + 1, n3 = n * n * n, ni = (P - 1) * (P - 1) * (P - 1);
-  const int64_t E = s->nelem, nloc = E * n3, nu = y->nuser;
+  const int ng = (int)s->groups.size();
+  const int64_t E = s->nelem, nloc = s->ncoeff, nu = y->nuser;
   hipError_t e;
   // the internal map of a one-system system numbers DOFs as the caller does
   std::vector<int32_t> m(nloc);
   if ((e = hipMemcpyAsync(m.data(), y->l2g, nloc * 4, hipMemcpyDeviceToHost, st)) ||
       (e = hipStreamSynchronize(st)))
     return hip_fail(e, "condensation setup");
-  std::vector<uint8_t> inner(n3);
-  for (int r = 0; r < n; ++r)
-    for (int hi = 0; hi < n; ++hi)
-      for (int lo = 0; lo < n; ++lo)
-        inner[(r * n + hi) * n + lo] = r > 0 && r < P && hi > 0 && hi < P && lo > 0 && lo < P;
+  std::vector<std::vector<uint8_t>> inner(ng);
+  std::vector<int64_t> ioff(ng + 1, 0), aoff(ng + 1, 0);
+  int64_t max_loc = 1, max_full = 1;
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = s->groups[g];
+    const int P = G.P, n = P + 1, ni = (P - 1) * (P - 1) * (P - 1);
+    inner[g].assign(n * n * n, 0);
+    for (int r = 0; r < n; ++r)
+      for (int hi = 0; hi < n; ++hi)
+        for (int lo = 0; lo < n; ++lo)
+          inner[g][(r * n + hi) * n + lo] = r > 0 && r < P && hi > 0 && hi < P && lo > 0 && lo < P;
+    ioff[g + 1] = ioff[g] + G.nelem * ni;
+    aoff[g + 1] = aoff[g] + G.nelem * sc_packed(ni);
+    max_loc = std::max<int64_t>(max_loc, G.nelem * n * n * n);
+    max_full = std::max<int64_t>(max_full, G.nelem * ni * (int64_t)ni);
+  }
   std::vector<int32_t> count(nu, 0);
   std::vector<uint8_t> dir(nu, 0), isb(nu, 0);
-  for (int64_t i = 0; i < nloc; ++i) {
-    const int32_t d = l2g_dof(m[i]);
-    ++count[d];
-    if (m[i] < 0) dir[d] = 1;
-    if (!inner[i % n3]) isb[d] = 1;
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = s->groups[g];
+    const int n3 = (int)inner[g].size();
+    for (int64_t i = 0; i < G.nelem * n3; ++i) {
+      const int32_t v = m[G.c0 + i], d = l2g_dof(v);
+      ++count[d];
+      if (v < 0) dir[d] = 1;
+      if (!inner[g][i % n3]) isb[d] = 1;
+    }
   }
-  for (int64_t i = 0; i < nloc; ++i)
-    if (inner[i % n3] && (m[i] < 0 || count[l2g_dof(m[i])] != 1))
-      return fail(NK_EUNSUPPORTED, "an interior mode's DOF is shared or Dirichlet: the map is not condensable");
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = s->groups[g];
+    const int n3 = (int)inner[g].size();
+    for (int64_t i = 0; i < G.nelem * n3; ++i) {
+      const int32_t v = m[G.c0 + i];
+      if (inner[g][i % n3] && (v < 0 || count[l2g_dof(v)] != 1))
+        return fail(NK_EUNSUPPORTED, "an interior mode's DOF is shared or Dirichlet: the map is not condensable");
+    }
+  }
   std::vector<int32_t> cpos(nu, -1), bmap;
   for (int64_t d = 0; d < nu; ++d)
     if (isb[d]) {
@@ -1898,19 +1925,20 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
       bmap.push_back((int32_t)d);
     }
   const int64_t nb = (int64_t)bmap.size();
-  std::vector<int32_t> l2gc(nloc), iidx(E * (int64_t)ni);
+  std::vector<int32_t> l2gc(nloc), iidx(std::max<int64_t>(ioff[ng], 1));
   std::vector<int8_t> sgn(nloc, 1);
   std::vector<uint8_t> dirc(nb + 1, 0);
   for (int64_t c = 0; c < nb; ++c) dirc[c] = dir[bmap[c]];
   dirc[nb] = 1;
-  for (int64_t el = 0; el < E; ++el) {
-    int k = 0;
-    for (int md = 0; md < n3; ++md) {
-      const int64_t i = el * n3 + md;
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = s->groups[g];
+    const int n3 = (int)inner[g].size();
+    int64_t k = ioff[g];
+    for (int64_t i = G.c0; i < G.c0 + G.nelem * n3; ++i) {
       const int32_t d = l2g_dof(m[i]);
-      if (inner[md]) {
+      if (inner[g][(i - G.c0) % n3]) {
         l2gc[i] = (int32_t)nb;
-        iidx[el * ni + k++] = d | (l2g_neg(m[i]) ? kL2gNeg : 0);
+        iidx[k++] = d | (l2g_neg(m[i]) ? kL2gNeg : 0);
       } else {
         l2gc[i] = cpos[d];
         sgn[i] = l2g_neg(m[i]) ? -1 : 1;
@@ -1923,6 +1951,7 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
     return stt;
   };
   c->nb = nb;
+  c->ioff.assign(ioff.begin(), ioff.end());
   int32_t* d_l2g = nullptr;
   int8_t* d_sgn = nullptr;
   uint8_t* d_dir = nullptr;
@@ -1942,6 +1971,7 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   dfree(d_sgn);
   dfree(d_dir);
   if (cs != NK_OK) return bail(cs);
+  nk_system z = c->bsys;
   double *cu = nullptr, *yl = nullptr, *afull = nullptr;
   int* d_bad = nullptr;
   auto bail_tmp = [&](hipError_t err) {
@@ -1952,38 +1982,52 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
     return bail(hip_fail(err, "condensation setup"));
   };
   if ((e = dmalloc(&c->bmap, std::max<int64_t>(nb, 1))) ||
-      (e = dmalloc(&c->iidx, std::max<int64_t>(E * ni, 1))) ||
-      (e = dmalloc(&afull, std::max<int64_t>(E * ni * (int64_t)ni, 1))) ||
-      (e = dmalloc(&c->ainv, std::max<int64_t>(E * sc_packed(ni), 1))) ||
-      (e = dmalloc(&c->t, std::max<int64_t>(E * ni, 1))) ||
-      (e = dmalloc(&c->zero, c->bsys->L.npad)) || (e = dmalloc(&cu, std::max<int64_t>(nloc, 1))) ||
-      (e = dmalloc(&yl, std::max<int64_t>(nloc, 1))) || (e = dmalloc(&d_bad, 1)))
+      (e = dmalloc(&c->iidx, std::max<int64_t>(ioff[ng], 1))) ||
+      (e = dmalloc(&afull, max_full)) || (e = dmalloc(&c->ainv, std::max<int64_t>(aoff[ng], 1))) ||
+      (e = dmalloc(&c->t, std::max<int64_t>(ioff[ng], 1))) || (e = dmalloc(&c->zero, z->L.npad)) ||
+      (e = dmalloc(&cu, max_loc)) || (e = dmalloc(&yl, max_loc)) || (e = dmalloc(&d_bad, 1)))
     return bail_tmp(e);
   if ((e = hipMemcpyAsync(c->bmap, bmap.data(), nb * 4, hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(c->iidx, iidx.data(), E * ni * 4, hipMemcpyHostToDevice, st)) ||
-      (e = vec_fill<double>(c->zero, c->bsys->L.npad, 0.0, st)) ||
-      (e = vec_fill<double>(cu, nloc, 0.0, st)) || (e = vec_fill<int32_t>(d_bad, 1, 0, st)))
+      (e = hipMemcpyAsync(c->iidx, iidx.data(), ioff[ng] * 4, hipMemcpyHostToDevice, st)) ||
+      (e = vec_fill<double>(c->zero, z->L.npad, 0.0, st)) || (e = vec_fill<int32_t>(d_bad, 1, 0, st)))
     return bail_tmp(e);
-  // H_ii row by row: the local Helmholtz operator on each interior unit vector
-  OpArgs a;
-  a.op = OP_HELM;
-  a.dim = 3;
-  a.P = P;
-  a.Q = G.Q;
-  a.nelem = E;
-  a.in = cu;
-  a.out = yl;
-  a.fac = s->fac64 + G.f0;
-  a.lam = y->lam;
-  a.lam0 = y->lam0;
-  a.tile = cur_tile(OP_HELM, 3, P, NK_F64);
-  a.stream = st;
-  for (int k = 0; k < ni; ++k) {
-    if ((e = sc_unit(P, E, cu, k, st)) || (e = launch_op(3, NK_F64, a)) ||
-        (e = sc_column(P, E, yl, afull, k, st)))
-      return bail_tmp(e);
+  c->ops.resize(ng);
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = s->groups[g];
+    const int P = G.P, n3 = (int)inner[g].size(), ni = (P - 1) * (P - 1) * (P - 1);
+    const int64_t Eg = G.nelem;
+    // H_ii row by row: the local Helmholtz operator on each interior unit vector
+    OpArgs a;
+    a.op = OP_HELM;
+    a.dim = 3;
+    a.P = P;
+    a.Q = G.Q;
+    a.nelem = Eg;
+    a.in = cu;
+    a.out = yl;
+    a.fac = s->fac64 + G.f0;
+    a.lam = y->lam ? y->lam + G.e0 : nullptr;
+    a.lam0 = y->lam0;
+    a.tile = cur_tile(OP_HELM, 3, P, NK_F64);
+    a.stream = st;
+    if ((e = vec_fill<double>(cu, Eg * n3, 0.0, st))) return bail_tmp(e);
+    for (int k = 0; k < ni; ++k) {
+      if ((e = sc_unit(P, Eg, cu, k, st)) || (e = launch_op(3, NK_F64, a)) ||
+          (e = sc_column(P, Eg, yl, afull, k, st)))
+        return bail_tmp(e);
+    }
+    if ((e = sc_invert(P, Eg, afull, c->ainv + aoff[g], d_bad, st))) return bail_tmp(e);
+    CondOp& op = c->ops[g];
+    op.P = P;
+    op.nelem = Eg;
+    op.ainv = c->ainv + aoff[g];
+    op.t = c->t + ioff[g];
+    op.fac = s->fac64 + G.f0;
+    op.fac32 = s->fac32 + G.f0;
+    op.lam = z->lam ? z->lam + G.e0 : nullptr;
+    op.lam0 = y->lam0;
+    op.l2g = z->l2g + G.c0;
   }
-  if ((e = sc_invert(P, E, afull, c->ainv, d_bad, st))) return bail_tmp(e);
   int bad = 0;
   if ((e = hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, st)) ||
       (e = hipStreamSynchronize(st)))
@@ -1995,37 +2039,32 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
     dfree(d_bad);
     return bail(fail(NK_EINVAL, "an element's interior block is not positive definite"));
   }
-  c->op.P = P;
-  c->op.nelem = E;
-  c->op.ainv = c->ainv;
-  c->op.t = c->t;
-  c->op.fac = s->fac64 + G.f0;
-  c->op.fac32 = s->fac32 + G.f0;
-  c->op.lam = c->bsys->lam;
-  c->op.lam0 = y->lam0;
-  c->op.l2g = c->bsys->l2g;
   // Jacobi preconditioner of the boundary system: diag(S) = sum_e diag(S_e),
   // each elemental diagonal probed by the local condensed operator on the
-  // boundary unit vectors (all elements at once), replacing the diagonal of
-  // the boundary block that the system was created with
+  // boundary unit vectors (all elements of a group at once), replacing the
+  // diagonal of the boundary block that the system was created with
   {
-    nk_system z = c->bsys;
     const int64_t npc = z->L.npad;
     double* dS = c->t;   // borrowed when large enough, else a temporary
     double* dS_own = nullptr;
-    if (E * (int64_t)ni < npc) {
+    if (ioff[ng] < npc) {
       if ((e = dmalloc(&dS_own, npc))) return bail_tmp(e);
       dS = dS_own;
     }
-    int prev = -1;
-    e = vec_fill<double>(cu, nloc, 0.0, st);
-    if (e == hipSuccess) e = vec_fill<double>(dS, npc, 0.0, st);
-    for (int md = 0; md < n3 && e == hipSuccess; ++md) {
-      if (inner[md]) continue;
-      if ((e = sc_unit_mode(P, E, cu, md, prev, st)) || (e = sc_local(c->op, cu, yl, st)) ||
-          (e = sc_diag_add(P, E, yl, md, z->l2g, dS, st)))
-        break;
-      prev = md;
+    e = vec_fill<double>(dS, npc, 0.0, st);
+    for (int g = 0; g < ng && e == hipSuccess; ++g) {
+      const Group& G = s->groups[g];
+      const int n3 = (int)inner[g].size();
+      int prev = -1;
+      e = vec_fill<double>(cu, G.nelem * n3, 0.0, st);
+      for (int md = 0; md < n3 && e == hipSuccess; ++md) {
+        if (inner[g][md]) continue;
+        if ((e = sc_unit_mode(G.P, G.nelem, cu, md, prev, st)) ||
+            (e = sc_local(c->ops[g], cu, yl, st)) ||
+            (e = sc_diag_add(G.P, G.nelem, yl, md, c->ops[g].l2g, dS, st)))
+          break;
+        prev = md;
+      }
     }
     if (e == hipSuccess) e = sc_dinv(npc, dS, z->dinv64, z->dinv32, z->diag, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -2035,9 +2074,10 @@ static nk_status cond_build(nk_system y, hipStream_t st) {
   dfree(cu);
   dfree(yl);
   dfree(d_bad);
-  c->bsys->sc = &c->op;
-  // the faster of the two fused-kernel variants on this system
-  if ((e = cond_pick_variant(c, NK_F64, st))) return bail(hip_fail(e, "condensation setup"));
+  z->sc = c->ops.data();
+  // the faster of the two fused-kernel variants of each group on this system
+  for (int g = 0; g < ng; ++g)
+    if ((e = cond_pick_variant(c, g, NK_F64, st))) return bail(hip_fail(e, "condensation setup"));
   y->cond = c;
   return NK_OK;
 }
@@ -2125,10 +2165,12 @@ static nk_status cg_solve_condensed(nk_system y, bool refined, const double* b, 
       // system's work runs on its own stream; y's stream is idle here, as
       // read_sys synchronised it)
       hipStream_t zs = z->cs;
-      if ((e = sc_restrict(c->nb, z->L.npad, c->bmap, y->r, z->dinv64, z->b, zs)) ||
-          (e = sc_ainv(c->op, y->r, c->iidx, 0.0, 1.0, -1.0, nullptr, nullptr, zs)) ||
-          (e = sc_pass(c->op, 2, c->zero, z->b, nullptr, nullptr, nullptr, zs)) ||
-          (e = vec_fill<double>(z->x, z->L.npad, 0.0, zs)) ||
+      if ((e = sc_restrict(c->nb, z->L.npad, c->bmap, y->r, z->dinv64, z->b, zs))) break;
+      for (size_t g = 0; g < c->ops.size() && e == hipSuccess; ++g)
+        if (!(e = sc_ainv(c->ops[g], y->r, c->iidx + c->ioff[g], 0.0, 1.0, -1.0, nullptr, nullptr, zs)))
+          e = sc_pass(c->ops[g], 2, c->zero, z->b, nullptr, nullptr, nullptr, zs);
+      if (e) break;
+      if ((e = vec_fill<double>(z->x, z->L.npad, 0.0, zs)) ||
           (e = vec_norm2(z->L, z->b, z->part, z->cnt_aux, z->bb, rtol, nullptr, zs)) ||
           (e = read_sys(z, z->bb, gg)))
         break;
@@ -2144,9 +2186,10 @@ static nk_status cg_solve_condensed(nk_system y, bool refined, const double* b, 
         break;
       }
       // interiors: x_i += H_ii^{-1} (r_i - H_ib dx_B); boundary: x_B += dx_B
-      if ((e = sc_pass(c->op, 1, z->x, nullptr, nullptr, nullptr, nullptr, zs)) ||
-          (e = sc_ainv(c->op, y->r, c->iidx, -1.0, 1.0, 1.0, y->x, nullptr, zs)) ||
-          (e = sc_expand_add(c->nb, c->bmap, z->x, y->x, zs)) || (e = hipStreamSynchronize(zs)))
+      for (size_t g = 0; g < c->ops.size() && e == hipSuccess; ++g)
+        if (!(e = sc_pass(c->ops[g], 1, z->x, nullptr, nullptr, nullptr, nullptr, zs)))
+          e = sc_ainv(c->ops[g], y->r, c->iidx + c->ioff[g], -1.0, 1.0, 1.0, y->x, nullptr, zs);
+      if (e || (e = sc_expand_add(c->nb, c->bmap, z->x, y->x, zs)) || (e = hipStreamSynchronize(zs)))
         break;
       if ((e = true_residual(y)) || (e = read_sys(y, y->rr_true, rr))) break;
     }

@@ -153,11 +153,12 @@ hipError_t sc_expand_add(int64_t nb, const int32_t* bmap, const double* cond, do
 // What a system keeps of its condensed form: the boundary system and the
 // arrays that connect it to the full one.
 struct CondData {
-  nk_system bsys = nullptr;       // boundary system (its operator is op)
-  CondOp op;
+  nk_system bsys = nullptr;       // boundary system (its operator is ops)
+  std::vector<CondOp> ops;        // per order group
+  std::vector<int64_t> ioff;      // per order group: first entry in iidx and t
   int64_t nb = 0;                 // boundary DOFs (the boundary system has nb + 1: a dummy)
   int32_t* bmap = nullptr;        // [nb] full DOF of each boundary DOF
-  int32_t* iidx = nullptr;        // [E][NI] full DOF | sign bit of each interior mode
+  int32_t* iidx = nullptr;        // per group [E_g][NI_g]: full DOF | sign bit of each interior mode
   double* ainv = nullptr;
   float* ainv32 = nullptr;
   double* t = nullptr;
@@ -213,4 +214,5 @@ struct nk_system_s {
   std::vector<int> tiles64, tiles32;   // assembled-operator tile per order group
   nk::CondData* cond = nullptr;           // statically condensed form (built on first use)
   const nk::CondOp* sc = nullptr;         // set on a boundary system: its operator is condensed
+                                          // (one CondOp per order group)
 };

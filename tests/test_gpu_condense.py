@@ -104,6 +104,36 @@ def test_condensed_f32_refined_true_residual(P, shape, signed):
     assert info64[0]["status"] == 0 and rel_err(x64.cpu().numpy(), xref) < 1e-5
 
 
+@pytest.mark.parametrize("shape,orders", [((3, 2, 2), [2, 5, 3, 4, 2, 6, 3, 3, 5, 2, 4, 6]),
+                                          ((4, 3, 2), [3, 6, 2, 4, 5, 6, 2, 3, 4, 5, 6, 2,
+                                                       3, 3, 4, 4, 5, 5, 6, 6, 2, 2, 4, 6])])
+def test_variable_order_condensation(shape, orders):
+    """Section 4.2's spatially variable order (minimum-rule map, orders 2..6):
+    the boundary numbering, diag(S) and S x against the oracle's per-element
+    condensation, and both condensed solves against the direct solve."""
+    torch_cuda()
+    m = nk()
+    from test_gpu_solve import _varp_case
+    c = _varp_case(shape, orders)
+    ref = Condensed(c["mats"], c["l2g"], c["ng"], c["dm"], 3, None)
+    nb, bmap, dS = c["sysm"].condense(with_diag=True)
+    assert nb == ref.bdofs.size
+    np.testing.assert_array_equal(bmap.cpu().numpy(), ref.bdofs)
+    assert_close(dS.cpu().numpy(), np.where(ref.bfree, ref.S.diagonal(), 1.0), FP64_RTOL, "varp diag(S)")
+    xb = W.uniform(W.seed(0, 76), nb)
+    assert_close(c["sysm"].condensed_apply(to_dev(xb)).cpu().numpy(), ref.apply(xb), FP64_RTOL,
+                 "varp condensed apply")
+    b = c["b"]
+    A = MaskedOperator(c["mats"], c["l2g"], c["ng"], c["dm"])
+    xd = direct_solve(c["mats"], c["l2g"], c["ng"], c["dm"], b)
+    for mode, rtol, tag in ((m.SOLVE_CONDENSED, 1e-12, "condensed"),
+                            (m.SOLVE_CONDENSED_F32_REFINED, 1e-10, "condensed f32-refined")):
+        x, info = c["sysm"].solve(to_dev(b), rtol=rtol, maxit=20000, mode=mode)
+        xs = x.cpu().numpy()
+        assert_true_residual(info[0], rtol, A, c["mats"], c["l2g"], c["ng"], c["dm"], xs, b, tag)
+        assert rel_err(xs, xd) < (1e-8 if rtol < 1e-11 else 1e-5), tag
+
+
 def test_condensed_solve_takes_fewer_iterations():
     """On a 4^3 curved lattice at P = 4 the boundary system needs fewer
     Jacobi-PCG iterations than the full one to the same full residual."""
@@ -138,10 +168,15 @@ def test_condensed_solve_initial_guess_and_zero_rhs():
 def test_condensed_error_paths():
     torch = torch_cuda()
     m = nk()
-    # P = 1: no interior modes
+    # P = 1: no interior modes; a variable-order space with an order-1 group
     c1 = _case((2, 2, 2), 1)
     with pytest.raises(m.NkError) as ei:
         c1["sysm"].condense()
+    assert ei.value.status == m.NK_EUNSUPPORTED
+    from test_gpu_solve import _varp_case
+    cv = _varp_case((2, 2, 1), [1, 3, 2, 4])
+    with pytest.raises(m.NkError) as ei:
+        cv["sysm"].condense()
     assert ei.value.status == m.NK_EUNSUPPORTED
     # condensed apply before the condensed form exists
     c = _case((2, 2, 1), 2)
