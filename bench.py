@@ -729,8 +729,10 @@ def section_varp(nk, W, torch, reps=20):
 
 def section_varp_solve(nk, W, torch, shape=(12, 12, 12), orders=(2, 8)):
     """A conforming variable-order solve: curved lattice with per-element
-    order drawn from {2..8}, C0 map by the minimum rule, manufactured-sine
-    weak right-hand side, FP64 CG and the FP32-refined solve to 1e-10."""
+    order drawn from {orders[0]..orders[1]}, C0 map by the minimum rule,
+    manufactured-sine weak right-hand side, FP64 CG and the FP32-refined
+    solve to 1e-10; with every order at most 6 also both condensed solves
+    (setup timed on its own)."""
     cfg = W.CONFIGS[3]
     lat = W.lattice(shape)
     Pe = W.varp_orders(W.seed(3, 4) + 1, lat.nelem, *orders)
@@ -753,7 +755,14 @@ def section_varp_solve(nk, W, torch, shape=(12, 12, 12), orders=(2, 8)):
     b = sysm.assemble(yl)
     out = {"shape": list(shape), "orders": Ps, "nelem": int(lat.nelem), "nglobal": int(ng),
            "local_dof": int(sum((P + 1) ** 3 for P in ords))}
-    for mode, name in ((nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")):
+    modes = [(nk.SOLVE_F64, "f64"), (nk.SOLVE_F32_REFINED, "f32_refined")]
+    if max(Ps) <= 6:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sysm.condense(with_map=False)
+        out["condense_setup_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        modes += [(nk.SOLVE_CONDENSED, "condensed"), (nk.SOLVE_CONDENSED_F32_REFINED, "condensed_f32_refined")]
+    for mode, name in modes:
         sysm.solve(b, rtol=1e-10, mode=mode)         # graphs and tiles warmed
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -1167,6 +1176,9 @@ def main():
         torch.cuda.empty_cache()
         log("section batch (mixed-order solve) ...")
         sections["varp_solve_12c"] = section_varp_solve(nk, W, torch)
+        torch.cuda.empty_cache()
+        log("section batch (mixed-order solve, orders 2..6, condensed) ...")
+        sections["varp_solve_16c_P2_6"] = section_varp_solve(nk, W, torch, shape=(16, 16, 16), orders=(2, 6))
         torch.cuda.empty_cache()
         log("section batch (256 solves) ...")
         sections["batch_256_solves"] = section_many_solves(nk, W, torch)
