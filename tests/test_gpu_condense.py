@@ -196,6 +196,14 @@ def test_condensed_error_paths():
     with pytest.raises(m.NkError) as ei:
         m.solve_batched([c["sysm"]], [b], mode=m.SOLVE_CONDENSED)
     assert ei.value.status == m.NK_EUNSUPPORTED
+    # an iteration budget too small for the tolerance: NK_ENOCONV, budget respected
+    c3 = _case((3, 3, 2), 4)
+    b3 = W.uniform(W.seed(0, 77), c3["ng"])
+    b3[c3["dm"].astype(bool)] = 0.0
+    for mode in (m.SOLVE_CONDENSED, m.SOLVE_CONDENSED_F32_REFINED):
+        x, info = c3["sysm"].solve(to_dev(b3), rtol=1e-12, maxit=3, mode=mode, raise_on_fail=False)
+        assert info[0]["status"] == m.NK_ENOCONV and info[0]["iters"] <= 3
+        assert info[0]["rel_resid"] > 1e-12
 
 
 @pytest.mark.parametrize("P", [4, 6])
