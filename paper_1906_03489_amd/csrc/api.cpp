@@ -855,6 +855,11 @@ static void system_free(nk_system y) {
   if (y->h_budget) (void)hipHostFree(y->h_budget);
   if (y->h_d) (void)hipHostFree(y->h_d);
   if (y->ev) (void)hipEventDestroy(y->ev);
+  for (hipStream_t gs : y->ostreams)
+    if (gs) (void)hipStreamDestroy(gs);
+  for (hipEvent_t ge : y->oevents)
+    if (ge) (void)hipEventDestroy(ge);
+  if (y->ofork) (void)hipEventDestroy(y->ofork);
   if (y->cs) (void)hipStreamDestroy(y->cs);
   delete y;
 }
@@ -986,6 +991,20 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
     return cleanup(hip_fail(e, "hipStreamCreate"));
   if ((e = hipEventCreateWithFlags(&y->ev, hipEventDisableTiming)) != hipSuccess)
     return cleanup(hip_fail(e, "hipEventCreate"));
+  if (s->groups.size() > 1 && s->shape == 0) {   // side streams of the order groups (sys_op)
+    for (size_t g = 1; g < s->groups.size(); ++g) {
+      hipStream_t gs = nullptr;
+      hipEvent_t ge = nullptr;
+      if ((e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking)) != hipSuccess)
+        return cleanup(hip_fail(e, "hipStreamCreate"));
+      y->ostreams.push_back(gs);
+      if ((e = hipEventCreateWithFlags(&ge, hipEventDisableTiming)) != hipSuccess)
+        return cleanup(hip_fail(e, "hipEventCreate"));
+      y->oevents.push_back(ge);
+    }
+    if ((e = hipEventCreateWithFlags(&y->ofork, hipEventDisableTiming)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipEventCreate"));
+  }
   y->L.blk_seg = y->d_blk_seg;
   y->L.blk_first = y->d_blk_first;
   // setup runs on the caller's stream, then synchronises it
@@ -1157,12 +1176,32 @@ static hipError_t sys_op_group(nk_system y, nk_dtype t, int g, const void* x, vo
 
 // y (padded) += A x (padded) over all elements, each order group with its
 // own tuned tile.
+// With several order groups the groups' launches are independent (they
+// only add into out and the energy slots, atomically), so groups 1.. run on
+// the system's own side streams (made at creation), forked from and joined
+// back into st by events: each group alone is often too small to fill the
+// GPU.  Under graph capture the fork and join become graph dependencies.
 static hipError_t sys_op(nk_system y, nk_dtype t, const void* x, void* out, double* dots,
                          const int32_t* seg_done, hipStream_t st) {
   const std::vector<int>& tiles = t == NK_F64 ? y->tiles64 : y->tiles32;
-  for (size_t g = 0; g < y->space->groups.size(); ++g) {
-    const hipError_t e = sys_op_group(y, t, (int)g, x, out, dots, seg_done,
-                                      g < tiles.size() ? tiles[g] : 0, st);
+  const size_t ng = y->space->groups.size();
+  hipError_t e = hipSuccess;
+  if (ng > 1 && y->ostreams.size() + 1 == ng) {
+    if ((e = hipEventRecord(y->ofork, st))) return e;
+    for (size_t g = 1; g < ng; ++g) {
+      hipStream_t gs = y->ostreams[g - 1];
+      if ((e = hipStreamWaitEvent(gs, y->ofork, 0)) ||
+          (e = sys_op_group(y, t, (int)g, x, out, dots, seg_done, g < tiles.size() ? tiles[g] : 0, gs)) ||
+          (e = hipEventRecord(y->oevents[g - 1], gs)))
+        return e;
+    }
+    if ((e = sys_op_group(y, t, 0, x, out, dots, seg_done, tiles.empty() ? 0 : tiles[0], st))) return e;
+    for (size_t g = 1; g < ng; ++g)
+      if ((e = hipStreamWaitEvent(st, y->oevents[g - 1], 0))) return e;
+    return hipSuccess;
+  }
+  for (size_t g = 0; g < ng; ++g) {
+    e = sys_op_group(y, t, (int)g, x, out, dots, seg_done, g < tiles.size() ? tiles[g] : 0, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -208,6 +208,9 @@ struct nk_system_s {
   int32_t* h_budget = nullptr;            // nsys: iteration budgets on their way to the device
   double* h_d = nullptr;                  // nsys
   hipStream_t cs = nullptr;               // private stream (graphs are captured here)
+  std::vector<hipStream_t> ostreams;      // side streams of order groups 1.. (made on first use)
+  std::vector<hipEvent_t> oevents;        // their join events
+  hipEvent_t ofork = nullptr;             // fork event of the order groups
   hipEvent_t ev = nullptr;
   hipGraphExec_t g64 = nullptr, g32 = nullptr;
   int g64_iters = 0, g32_iters = 0;
