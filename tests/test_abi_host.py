@@ -103,6 +103,10 @@ def test_invalid_arguments_rejected_before_device_work():
     assert L.nk_helmholtz(None, 0, None, 1.0, None, None, None) == nk.NK_EINVAL
     assert L.nk_system_create(ctypes.byref(h), None, 5, None, None, None, 1.0, None) == nk.NK_EINVAL
     assert L.nk_cg_solve(None, 0, None, None, 1e-10, 10, None, None) == nk.NK_EINVAL
+    assert L.nk_cg_solve(None, nk.SOLVE_CONDENSED, None, None, 1e-10, 10, None, None) == nk.NK_EINVAL
+    nb = ctypes.c_int64(0)
+    assert L.nk_system_condense(None, ctypes.byref(nb), None, None, None) == nk.NK_EINVAL
+    assert L.nk_condensed_apply(None, None, None, None) == nk.NK_EINVAL
     assert L.nk_space_destroy(None) == nk.NK_EINVAL
     assert L.nk_system_destroy(None) == nk.NK_EINVAL
     assert L.nk_set_tile_config(2, 3, 6, 0, 99) == nk.NK_EINVAL
