@@ -406,8 +406,9 @@ def section_cg(nk, W, torch, orders, shape=(24, 24, 24)):
 
 def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
     """Static condensation (section 2.1) against the full FP64 PCG on the 24^3
-    problem: setup of the boundary system and interior inverses, boundary CG
-    iterations, time per iteration and per solve."""
+    problem: setup of the boundary system and interior inverses, the
+    condensed operator S x_B alone, boundary CG iterations, time per iteration
+    and per solve."""
     out = {}
     for P in orders:
         space, sysm, b, ng, lat = build_cg_problem(nk, W, torch, shape, P, W.WARP_AMPLITUDE)
@@ -431,14 +432,31 @@ def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
         tr = (time.perf_counter() - t) * 1e3
         nel, n3, q3, ni = lat.nelem, (P + 1) ** 3, (P + 2) ** 3, (P - 1) ** 3
         # algorithmic bytes of one boundary iteration: one read of the factors
-        # and the map (the fused kernel's second pass re-reads them from
-        # cache), the interior inverses in their diagonal storage, 9 boundary
-        # vectors
-        it_bytes = nel * (8 * 7 * q3 + 4 * n3 + 8 * (ni // 2 + 1) * ni) + 8 * 9 * nb
+        # and the map (the fused kernel's second pass reads them again; the
+        # counters show that re-read reaching memory), the interior inverses
+        # in their diagonal storage, 9 boundary vectors
+        el_bytes = nel * (8 * 7 * q3 + 4 * n3 + 8 * (ni // 2 + 1) * ni)
+        it_bytes = el_bytes + 8 * 9 * nb
+        # S x_B alone: nk_condensed_apply calls (each pads x_B, launches the
+        # fused kernel and synchronises), HIP events over 20 calls
+        xb = torch.from_numpy(W.uniform(3, nb)).cuda()
+        yb = torch.empty_like(xb)
+        for _ in range(3):
+            sysm.condensed_apply(xb, yb)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            sysm.condensed_apply(xb, yb)
+        e1.record()
+        torch.cuda.synchronize()
+        ap_ms = e0.elapsed_time(e1) / 20
+        ap_gbs = (el_bytes + 16 * nb) / (ap_ms * 1e-3) / 1e9
+        del xb, yb
         ms_it = tc / max(inf_c[0]["iters"], 1)
         gbs = it_bytes / (ms_it * 1e-3) / 1e9
         out[f"P{P}"] = {
             "nglobal": ng, "nboundary": nb, "nelem": nel, "setup_ms": round(setup_ms, 1),
+            "apply_f64_per_call": {"ms": round(ap_ms, 4), "GB_s": round(ap_gbs, 1)},
             "full_f64": {"ms": round(tf, 2), "iters": inf_f[0]["iters"],
                          "ms_per_iter": round(tf / max(inf_f[0]["iters"], 1), 4)},
             "condensed": {"ms": round(tc, 2), "iters": inf_c[0]["iters"], "passes": inf_c[0]["outer_iters"],
@@ -454,13 +472,13 @@ def section_condensed(nk, W, torch, orders=(4, 6), shape=(24, 24, 24)):
         log(f"condensed P={P}: setup {setup_ms:.1f} ms, full {tf:.1f} ms ({inf_f[0]['iters']} it), "
             f"condensed {tc:.1f} ms ({inf_c[0]['iters']} it, {inf_c[0]['outer_iters']} passes, "
             f"{ms_it * 1e3:.1f} us/it), condensed f32-refined {tr:.1f} ms ({inf_r[0]['iters']} it, "
-            f"{inf_r[0]['outer_iters']} passes)")
+            f"{inf_r[0]['outer_iters']} passes); S x_B {ap_ms * 1e3:.1f} us per call")
         del space, sysm, b, xf, xc, xr
         torch.cuda.empty_cache()
     return out
 
 
-def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (14, 8)), reps=30, shape="tet"):
+def section_tet(nk, W, torch, cases=((20, 4), (20, 6), (20, 8)), reps=30, shape="tet"):
     """Collapsed-coordinate tetrahedra (the unit cube split into n^3 cubes of
     six curved tetrahedra each), prisms (the triangle mesh of the unit
     square extruded into n layers, 2 n^3 curved prisms) or pyramids (six per
@@ -1056,7 +1074,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sections", default="ops,deriv,tri,tet,cg,batch,grad,cpu",
-                    help="comma list of ops,deriv,tri,tet,cg,batch,grad,cpu,cpu_pcg (or 'none'); "
+                    help="comma list of ops,deriv,tri,tet,cg,cond,batch,grad,cpu,cpu_pcg (or 'none'; "
+                         "cond: the static-condensation comparison alone, also part of cg); "
                          "cpu_pcg (the oracle's 24^3 P=4 PCG, minutes of CPU) is not in the default")
     ap.add_argument("--cg-orders", default="4,6,8")
     ap.add_argument("--calib", action="store_true",
@@ -1149,9 +1168,9 @@ def main():
         log("section tet ...")
         sections["tet"] = section_tet(nk, W, torch)
         log("section prism ...")
-        sections["prism"] = section_tet(nk, W, torch, cases=((24, 4), (24, 6), (16, 8)), shape="prism")
+        sections["prism"] = section_tet(nk, W, torch, cases=((24, 4), (24, 6), (24, 8)), shape="prism")
         log("section pyramid ...")
-        sections["pyramid"] = section_tet(nk, W, torch, cases=((20, 4), (16, 6), (10, 8)), shape="pyramid")
+        sections["pyramid"] = section_tet(nk, W, torch, cases=((20, 4), (20, 6), (20, 8)), shape="pyramid")
         log("section tet solve ...")
         sections["tet_solve_10368"] = section_tet_solve(nk, W, torch)
         log("section prism solve ...")
@@ -1167,6 +1186,7 @@ def main():
         log("section cg (filter equation) ...")
         sections["filter_24c_P6"] = section_filter(nk, W, torch)
         torch.cuda.empty_cache()
+    if "cg" in secs or "cond" in secs:
         log("section cg (static condensation) ...")
         sections["condensed_24c"] = section_condensed(nk, W, torch)
         torch.cuda.empty_cache()
