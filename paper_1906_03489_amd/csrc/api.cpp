@@ -981,7 +981,7 @@ static nk_status system_create(nk_system* out, nk_space s, int nsys, const int64
 #undef NK_ALLOC
   if ((e = alloc_state(y->st64, nsys)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = alloc_state(y->st32, nsys)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
-  if ((e = hipHostMalloc((void**)&y->h_flags, nsys * sizeof(int32_t), 0)) != hipSuccess)
+  if ((e = hipHostMalloc((void**)&y->h_flags, 2 * nsys * sizeof(int32_t), 0)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc"));
   if ((e = hipHostMalloc((void**)&y->h_budget, nsys * sizeof(int32_t), 0)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc"));
@@ -1505,6 +1505,25 @@ static hipError_t read_sys(nk_system y, const V* dev, std::vector<V>& out) {
   return hipSuccess;
 }
 
+// Read an int32 and an FP64 nsys-long device array (or, with dd null, two
+// int32 arrays) through the pinned staging buffers with one synchronisation:
+// the solve loops check flags and residuals after every graph launch, and
+// each synchronisation leaves the GPU idle while the host looks.
+static hipError_t read_sys2(nk_system y, const int32_t* di, std::vector<int32_t>& oi,
+                            const double* dd, std::vector<double>& od,
+                            const int32_t* di2 = nullptr, std::vector<int32_t>* oi2 = nullptr) {
+  const int ns = y->nsys;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(y->h_flags, di, ns * 4, hipMemcpyDeviceToHost, y->cs))) return e;
+  if (dd && (e = hipMemcpyAsync(y->h_d, dd, ns * 8, hipMemcpyDeviceToHost, y->cs))) return e;
+  if (di2 && (e = hipMemcpyAsync(y->h_flags + ns, di2, ns * 4, hipMemcpyDeviceToHost, y->cs))) return e;
+  if ((e = hipStreamSynchronize(y->cs))) return e;
+  oi.assign(y->h_flags, y->h_flags + ns);
+  if (dd) od.assign(y->h_d, y->h_d + ns);
+  if (di2) oi2->assign(y->h_flags + ns, y->h_flags + 2 * ns);
+  return hipSuccess;
+}
+
 // FP64 CG restarted from the current x while the true residual of a system
 // is above rtol and its budget lasts: the recursive residual the iteration
 // stops on drifts from b - A x by rounding, so one restart (a few
@@ -1534,8 +1553,8 @@ static hipError_t solve_f64(nk_system y, double rtol, int maxit, std::vector<int
     if ((e = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, y->cs))) return e;
     if ((e = cg_begin<double>(y, y->b, 0.0, y->outer_done))) return e;
     if ((e = cg_loop<double>(y, maxb, y->st64.done))) return e;
-    if ((e = read_sys(y, y->st64.iters, it_dev)) || (e = read_sys(y, y->st64.status, st_dev)))
-      return e;
+    std::vector<double> unused;
+    if ((e = read_sys2(y, y->st64.iters, it_dev, nullptr, unused, y->st64.status, &st_dev))) return e;
     if ((e = true_residual(y)) || (e = read_sys(y, y->rr_true, rr))) return e;
     bool again = false;
     for (int i = 0; i < ns; ++i) {
@@ -1682,12 +1701,11 @@ static hipError_t solve_reliable(nk_system y, double rtol, int maxit, std::vecto
     if ((e2 = sys_op(y, NK_F64, y->x, y->y, nullptr, nullptr, cs))) return e2;
     if ((e2 = cg_residual(y->L, outer_st, y->b, y->y, y->dinv64, y->r, nullptr, y->part, cs)))
       return e2;
-    return read_sys(y, y->outer_done, done);
+    return read_sys2(y, y->outer_done, done, y->outer_rr, rr_last);
   };
   if ((e = vec_norm2(y->L, y->b, y->part, y->cnt_aux, y->bb, rtol_dev, y->outer_tol2, cs))) return e;
   if ((e = read_sys(y, y->bb, bb))) return e;
   if ((e = true_resid())) return e;
-  if ((e = read_sys(y, y->outer_rr, rr_last))) return e;
   bool all = true;
   for (int i = 0; i < ns; ++i) all = all && done[i] != 0;
   const bool began = !all;
@@ -1711,7 +1729,7 @@ static hipError_t solve_reliable(nk_system y, double rtol, int maxit, std::vecto
           break;
         }
         if ((e = hipGraphLaunch(y->g32, cs))) return e;
-        if ((e = read_sys(y, y->st32.done, done32)) || (e = read_sys(y, y->st32.rr, rr32))) return e;
+        if ((e = read_sys2(y, y->st32.done, done32, y->st32.rr, rr32))) return e;
         bool progressed = true, any_stopped = false, active = false;
         for (int i = 0; i < ns; ++i) {
           if (done[i] || fin[i]) continue;
@@ -1725,9 +1743,8 @@ static hipError_t solve_reliable(nk_system y, double rtol, int maxit, std::vecto
       if ((e = cg_correct(y->L, y->outer_done, y->d32, y->x, cs))) return e;
       if ((e = vec_fill<float>(y->d32, np, 0.f, cs))) return e;
       if ((e = true_resid())) return e;
-      if ((e = read_sys(y, y->outer_rr, rr_last))) return e;
-      if ((e = read_sys(y, y->st32.iters, it_dev)) || (e = read_sys(y, y->st32.status, st_dev)))
-        return e;
+      std::vector<double> unused;
+      if ((e = read_sys2(y, y->st32.iters, it_dev, nullptr, unused, y->st32.status, &st_dev))) return e;
       bool newly_fin = false;
       all = true;
       for (int i = 0; i < ns; ++i) {

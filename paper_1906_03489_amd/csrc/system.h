@@ -204,7 +204,7 @@ struct nk_system_s {
   int32_t* outer_cnt = nullptr;
   int32_t* outer_status = nullptr;
   // host staging (pinned)
-  int32_t* h_flags = nullptr;             // nsys
+  int32_t* h_flags = nullptr;             // 2 nsys (two int32 arrays read together)
   int32_t* h_budget = nullptr;            // nsys: iteration budgets on their way to the device
   double* h_d = nullptr;                  // nsys
   hipStream_t cs = nullptr;               // private stream (graphs are captured here)
