@@ -1033,7 +1033,13 @@ def cpu_oracle_pcg(W, P=4, shape=(24, 24, 24), rtol=1e-10, maxit=None, iters_ref
     t0 = time.perf_counter()
     Jo = W.element_jacobians(oracle.gll(Q)[0], lat, W.WARP_AMPLITUDE)
     ops = oracle.ElementOps(3, P, Q, Jo, lam=1.0)
-    mats = oracle.helmholtz_matrices(ops)
+    # the oracle's dense H_e element by element (what helmholtz_matrices
+    # does), with a progress line every 1000 elements
+    mats = []
+    for e in range(ops.nelem):
+        mats.append(ops.helmholtz_matrix(e))
+        if (e + 1) % 1000 == 0:
+            log(f"oracle pcg setup: {e + 1} of {ops.nelem} H_e, {time.perf_counter() - t0:.0f} s")
     l2g, ng, dm = W.lattice_l2g(shape, P)
     U, dU = W.manufactured_ref_gradient(ops.x, lat)
     b = oracle.assemble_vector(ops.weak_rhs(U, dU), l2g, ng)
@@ -1076,7 +1082,8 @@ def main():
     ap.add_argument("--sections", default="ops,deriv,tri,tet,cg,batch,grad,cpu",
                     help="comma list of ops,deriv,tri,tet,cg,cond,batch,grad,cpu,cpu_pcg (or 'none'; "
                          "cond: the static-condensation comparison alone, also part of cg); "
-                         "cpu_pcg (the oracle's 24^3 P=4 PCG, minutes of CPU) is not in the default")
+                         "cpu_pcg (the oracle's 24^3 P=4 PCG, minutes of CPU) and cpu_pcg6 (a sample of "
+                         "its P=6 PCG, 13 GB of host memory) are not in the default")
     ap.add_argument("--cg-orders", default="4,6,8")
     ap.add_argument("--calib", action="store_true",
                     help="after the timed region, one 1 GiB device-to-device copy (counter calibration)")
@@ -1218,6 +1225,12 @@ def main():
     if "cpu_pcg" in secs:
         log("cpu oracle PCG, 24^3 P=4 (minutes) ...")
         result.setdefault("cpu_baseline", {})["pcg_24c_P4"] = cpu_oracle_pcg(W)
+    if "cpu_pcg6" in secs:
+        # bounded sample at P=6: 13 824 dense 343 x 343 H_e (13 GB), setup and
+        # 10 iterations, the time to solution extrapolated with the GPU's count
+        ref = sections.get("cg_24c", {}).get("P6", {}).get("f64", {}).get("iters")
+        log("cpu oracle PCG, 24^3 P=6 (setup and 10 iterations, minutes) ...")
+        result.setdefault("cpu_baseline", {})["pcg_24c_P6"] = cpu_oracle_pcg(W, P=6, maxit=10, iters_ref=ref)
     print(json.dumps(result), flush=True)
 
 
